@@ -1,0 +1,317 @@
+"""Python front end of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+The oracle is a plain FP64 brute-force implementation of what one frame of the
+dynamic EM ray tracer computes (paper Sec. III: ray sphere, specular bounces,
+per-depth visited-path tables, image-method refinement, path validation, and
+per-path distance / attenuation / phase).  Only the test-suite, the smoke check
+and the benchmark's CPU-baseline leg may import this module.  It never imports
+the GPU library and shares no code with it.
+
+Scene objects are taken by duck typing (attributes ``vertices``, ``tris``,
+``tri_face``, ``face_material``, ``face_object``, ``materials``,
+``object_vertex_range``, ``tx``, ``rx``, ``rx_radius``, ...), so this module
+does not import the package either.
+
+Functions and the passages they follow:
+  fibonacci          ray sphere (step 1 of the frame algorithm)
+  trace              bounces + capture spheres (steps 1-2, forward direction)
+  candidates         de-duplicated (tx, rx, order, faces) keys (step 2's tables)
+  refine             image method, validity, field per path (steps 3, 4, 6;
+                     Eq. (3) with n = 2 for the free-space magnitude)
+  received_power     phase-coherent sum per receiver ("phase calculation")
+  frame              all of the above for one frame
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dcem_oracle.cpp")
+_LIB = os.environ.get("DCEM_ORACLE_LIB") or os.path.join(_HERE, "libdcem_oracle.so")
+
+SEG_TIE, SEG_EDGE, SEG_TRI = 1, 2, 4
+CAP_HIT, CAP_MARGINAL, CAP_UNCERTAIN = 1, 2, 4
+
+T_MIN = 1e-4          # metres; hits closer than this to a segment start are ignored
+EPS_TRACE = 4e-6      # relative position tolerance of an FP32 tracer (see flags)
+EPS_REFINE = 1e-9     # relative tolerance of an FP64 validation
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain -O2, no fast-math)."""
+    if os.environ.get("DCEM_ORACLE_LIB"):
+        return _LIB
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        lib.oracle_scene_new.restype = P
+        lib.oracle_scene_new.argtypes = [P, I64, P, P, I64, P, P, I32, P, I32, P, I32, P]
+        lib.oracle_scene_free.argtypes = [P]
+        lib.oracle_scene_radius.argtypes = [P, P]
+        lib.oracle_fibonacci.argtypes = [I64, P]
+        lib.oracle_trace.restype = I64
+        lib.oracle_trace.argtypes = [P, P, I32, P, I32, F64, P, P, I64, I32, F64, F64, I32,
+                                     P, P, P, P, P, P, P, I64]
+        lib.oracle_refine.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32,
+                                      P, P, P, P, P, P, P]
+        lib.oracle_fresnel.argtypes = [F64, F64, F64, F64, F64, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+class OracleScene:
+    """FP64 copy of a scene at one frame (object transforms applied)."""
+
+    def __init__(self, scene, xf: Optional[np.ndarray] = None):
+        lib = _load()
+        self._keep = [
+            np.ascontiguousarray(scene.vertices, dtype=np.float32),
+            np.ascontiguousarray(scene.tris, dtype=np.int32),
+            np.ascontiguousarray(scene.tri_face, dtype=np.int32),
+            np.ascontiguousarray(scene.face_material, dtype=np.int32),
+            np.ascontiguousarray(scene.face_object, dtype=np.int32),
+            np.ascontiguousarray(scene.materials, dtype=np.float64),
+            np.ascontiguousarray(scene.object_vertex_range, dtype=np.int64),
+        ]
+        V, T, TF, FM, FO, M, OR = self._keep
+        xfa = None if xf is None else np.ascontiguousarray(xf, dtype=np.float32)
+        self.n_faces = FM.shape[0]
+        self.handle = lib.oracle_scene_new(
+            _ptr(V), V.shape[0], _ptr(T), _ptr(TF), T.shape[0], _ptr(FM), _ptr(FO), FM.shape[0],
+            _ptr(M), M.shape[0], _ptr(OR), OR.shape[0], _ptr(xfa))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.oracle_scene_free(self.handle)
+            self.handle = None
+
+
+def fibonacci(n: int) -> np.ndarray:
+    out = np.empty((n, 3), dtype=np.float32)
+    _load().oracle_fibonacci(n, _ptr(out))
+    return out
+
+
+def fresnel(eps_r: float, sigma: float, freq: float, cos_theta: float,
+            const_gamma: float = float("nan")):
+    out = np.empty(4, dtype=np.float64)
+    _load().oracle_fresnel(eps_r, sigma, const_gamma, freq, cos_theta, _ptr(out))
+    return complex(out[0], out[1]), complex(out[2], out[3])
+
+
+@dataclass
+class TraceResult:
+    tri: np.ndarray        # i32 [ntx, nsel, K+1]  (-1 miss, -2 not traced)
+    face: np.ndarray       # i32 [ntx, nsel, K+1]
+    t: np.ndarray          # f64 [ntx, nsel, K+1]
+    length: np.ndarray     # f64 [ntx, nsel, K+1]
+    flags: np.ndarray      # i32 [ntx, nsel, K+1]  SEG_*
+    caps: np.ndarray       # i32 [ncap, 4 + K]     (ray, tx, rx, order, faces...)
+    cap_flags: np.ndarray  # i32 [ncap]            CAP_*
+
+
+def trace(osc: OracleScene, tx, rx, radius: float, dirs: np.ndarray, K: int,
+          ray_ids: Optional[np.ndarray] = None, t_min: float = T_MIN,
+          eps_rel: float = EPS_TRACE, nthreads: Optional[int] = None) -> TraceResult:
+    lib = _load()
+    tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
+    rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
+    dirs = np.ascontiguousarray(dirs, dtype=np.float32).reshape(-1, 3)
+    ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, dtype=np.int64)
+    nsel = dirs.shape[0] if ids is None else ids.shape[0]
+    ntx = tx.shape[0]
+    shp = (ntx, nsel, K + 1)
+    tri = np.empty(shp, np.int32)
+    face = np.empty(shp, np.int32)
+    t = np.empty(shp, np.float64)
+    length = np.empty(shp, np.float64)
+    flags = np.empty(shp, np.int32)
+    cap = max(1024, 4 * ntx * nsel)
+    nthreads = nthreads or default_threads()
+    while True:
+        rows = np.empty((cap, 4 + K), np.int32)
+        cflags = np.empty(cap, np.int32)
+        n = lib.oracle_trace(osc.handle, _ptr(tx), ntx, _ptr(rx), rx.shape[0], float(radius),
+                             _ptr(dirs), _ptr(ids), nsel, K, t_min, eps_rel, nthreads,
+                             _ptr(tri), _ptr(face), _ptr(t), _ptr(length), _ptr(flags),
+                             _ptr(rows), _ptr(cflags), cap)
+        if n <= cap:
+            return TraceResult(tri, face, t, length, flags, rows[:n].copy(), cflags[:n].copy())
+        cap = int(n)
+
+
+def los_keys(ntx: int, nrx: int, K: int) -> np.ndarray:
+    """Direct-path keys (tx, rx, 0, -1...) for every pair: direct rays are their own mechanism."""
+    keys = np.full((ntx * nrx, 3 + K), -1, dtype=np.int32)
+    keys[:, 0] = np.repeat(np.arange(ntx), nrx)
+    keys[:, 1] = np.tile(np.arange(nrx), ntx)
+    keys[:, 2] = 0
+    return keys
+
+
+def candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = True):
+    """Unique keys from exact captures, sorted by (tx, rx, order, f1..fK).
+
+    Returns (keys, certain, possible):
+      keys      the oracle's own candidate set (captures with distance <= r)
+      certain   bool per key: produced by at least one capture that no FP32
+                tracer can decide differently
+      possible  every key seen by any capture within r + eps (marginal and
+                uncertain ones included); an FP32 tracer can only find keys
+                outside this set on rays whose path the oracle marks uncertain
+    """
+    rows = tr.caps[:, 1:]
+    hit = (tr.cap_flags & CAP_HIT) != 0
+    sure = tr.cap_flags == CAP_HIT
+    parts = [rows[hit]]
+    if los_always:
+        parts.append(los_keys(ntx, nrx, K))
+    allk = np.concatenate(parts) if parts else np.zeros((0, 3 + K), np.int32)
+    keys = np.unique(allk, axis=0) if len(allk) else allk
+    sure_rows = rows[sure]
+    if los_always:
+        sure_rows = np.concatenate([sure_rows, los_keys(ntx, nrx, K)])
+    certain = _member(keys, sure_rows)
+    poss = [rows] + parts[1:]
+    possible = np.unique(np.concatenate(poss), axis=0) if sum(len(x) for x in poss) \
+        else np.zeros((0, 3 + K), np.int32)
+    return keys, certain, possible
+
+
+def _member(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    if len(a) == 0:
+        return np.zeros(0, bool)
+    if len(b) == 0:
+        return np.zeros(len(a), bool)
+    sb = {tuple(r) for r in b.tolist()}
+    return np.array([tuple(r) in sb for r in a.tolist()], dtype=bool)
+
+
+@dataclass
+class Paths:
+    keys: np.ndarray      # i32 [n, 3 + K]
+    valid: np.ndarray     # bool [n]
+    marginal: np.ndarray  # bool [n]
+    length: np.ndarray    # f64 [n]
+    tau: np.ndarray       # f64 [n]
+    aod: np.ndarray       # f64 [n, 3]
+    aoa: np.ndarray       # f64 [n, 3]
+    amp: np.ndarray       # c128 [n, nfreq, 3]
+
+
+def refine(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w: float,
+           atten_db_per_km: float = 0.0, t_min: float = T_MIN, eps_rel: float = EPS_REFINE,
+           nthreads: Optional[int] = None) -> Paths:
+    lib = _load()
+    tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
+    rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
+    keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3 + K)
+    freqs = np.ascontiguousarray(freqs, dtype=np.float64).reshape(-1)
+    n = keys.shape[0]
+    nf = freqs.shape[0]
+    valid = np.zeros(n, np.uint8)
+    marginal = np.zeros(n, np.uint8)
+    length = np.zeros(n)
+    tau = np.zeros(n)
+    aod = np.zeros((n, 3))
+    aoa = np.zeros((n, 3))
+    amp = np.zeros((n, nf, 3, 2))
+    if n:
+        lib.oracle_refine(osc.handle, _ptr(tx), _ptr(rx), _ptr(keys), n, K, _ptr(freqs), nf,
+                          float(tx_power_w), float(atten_db_per_km), t_min, eps_rel,
+                          nthreads or default_threads(), _ptr(valid), _ptr(marginal),
+                          _ptr(length), _ptr(tau), _ptr(aod), _ptr(aoa), _ptr(amp))
+    return Paths(keys, valid.astype(bool), marginal.astype(bool), length, tau, aod, aoa,
+                 amp[..., 0] + 1j * amp[..., 1])
+
+
+def received_power(paths: Paths, ntx: int, nrx: int, nfreq: int):
+    """Per (freq, tx, rx): coherent P = sum_c |sum_p a_pc|^2 and incoherent sum_p |a_p|^2.
+
+    Paths are summed in key order (keys are sorted)."""
+    p_coh = np.zeros((nfreq, ntx, nrx))
+    p_inc = np.zeros((nfreq, ntx, nrx))
+    for i in range(len(paths.keys)):
+        if not paths.valid[i]:
+            continue
+        t, r = int(paths.keys[i, 0]), int(paths.keys[i, 1])
+        p_inc[:, t, r] += np.sum(np.abs(paths.amp[i]) ** 2, axis=-1)
+    acc = np.zeros((nfreq, ntx, nrx, 3), dtype=np.complex128)
+    for i in range(len(paths.keys)):
+        if paths.valid[i]:
+            acc[:, int(paths.keys[i, 0]), int(paths.keys[i, 1])] += paths.amp[i]
+    p_coh[:] = np.sum(np.abs(acc) ** 2, axis=-1)
+    return p_coh, p_inc
+
+
+@dataclass
+class FrameResult:
+    trace: TraceResult
+    keys: np.ndarray
+    certain: np.ndarray
+    possible: np.ndarray
+    paths: Paths
+    p_coh: np.ndarray
+    p_inc: np.ndarray
+
+
+def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Optional[int] = None,
+          freqs=None, tx_power_w: Optional[float] = None, atten_db_per_km: float = 0.0,
+          los_always: bool = True, nthreads: Optional[int] = None) -> FrameResult:
+    """One frame, from scratch: the oracle keeps nothing between frames."""
+    K = scene.max_reflections if K is None else K
+    freqs = scene.freqs_hz if freqs is None else freqs
+    tx_power_w = scene.tx_power_w if tx_power_w is None else tx_power_w
+    if dirs is None:
+        dirs = fibonacci(scene.n_rays)
+    xf = scene.transforms(frame_index) if scene.object_vertex_range.shape[0] else None
+    osc = OracleScene(scene, xf)
+    tr = trace(osc, scene.tx, scene.rx, scene.rx_radius, dirs, K, nthreads=nthreads)
+    ntx, nrx = scene.tx.shape[0], scene.rx.shape[0]
+    keys, certain, possible = candidates(tr, ntx, nrx, K, los_always)
+    paths = refine(osc, scene.tx, scene.rx, keys, K, freqs, tx_power_w, atten_db_per_km,
+                   nthreads=nthreads)
+    p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))
+    return FrameResult(tr, keys, certain, possible, paths, p_coh, p_inc)
+
+
+def enumerate_keys(n_faces: int, ntx: int, nrx: int, K: int) -> np.ndarray:
+    """Every face sequence of length 0..K without immediate repeats, for every (tx, rx)."""
+    seqs = [[]]
+    out = []
+    for order in range(K + 1):
+        for s in seqs:
+            for t in range(ntx):
+                for r in range(nrx):
+                    out.append([t, r, order] + s + [-1] * (K - order))
+        seqs = [s + [f] for s in seqs for f in range(n_faces) if not s or s[-1] != f]
+    return np.array(out, dtype=np.int32).reshape(-1, 3 + K)

@@ -1,0 +1,390 @@
+"""Seeded synthetic scenes for the dynamic vehicular ray tracer.
+
+This module only builds inputs: triangle geometry, materials, transmitter and
+receiver positions, per-frame rigid transforms of the moving vehicles and
+(optionally) random ray directions.  It holds none of the propagation
+arithmetic, so both the HIP library and the CPU oracle can be fed from it.
+
+The paper evaluates on a commercial European-town model and an indoor office
+(Sec. III, Sec. IV) that are not available here; the scenes below stand in for
+its "typical vehicular communication scenario" (Sec. IV-A): an urban street grid
+with box buildings on a ground plane and box-shaped vehicles moving along lanes.
+The material table follows the paper's choice of one reflection property per
+object class (Table II), expressed as relative permittivity and conductivity.
+
+Arrays use float32 for geometry (the library traces in FP32) and float64 for
+material constants.  Every scene is a pure function of its seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+# material rows: (eps_r, sigma [S/m], const_gamma); const_gamma = NaN selects Fresnel
+CONCRETE = (5.31, 0.48, float("nan"))
+GROUND = (15.0, 0.035, float("nan"))
+METAL = (1.0, 1.0e7, float("nan"))
+
+
+@dataclass
+class Scene:
+    name: str
+    vertices: np.ndarray            # f32 [Nv, 3], upload (reference) pose
+    tris: np.ndarray                # i32 [Nt, 3]
+    tri_face: np.ndarray            # i32 [Nt]
+    face_material: np.ndarray       # i32 [Nf]
+    face_object: np.ndarray         # i32 [Nf], -1 = static
+    materials: np.ndarray           # f64 [Nm, 3] (eps_r, sigma, const_gamma)
+    object_vertex_range: np.ndarray  # i64 [No, 2], half-open vertex ranges
+    tx: np.ndarray                  # f32 [Ntx, 3]
+    rx: np.ndarray                  # f32 [Nrx, 3]
+    rx_radius: float = 0.5
+    n_rays: int = 4096
+    max_reflections: int = 2
+    freqs_hz: List[float] = field(default_factory=lambda: [28e9])
+    tx_power_w: float = 5.0
+    n_frames: int = 1
+    dt: float = 0.1
+    # frame -> f32 [No, 3, 4] object-to-world transforms relative to the upload pose
+    transforms_fn: Optional[Callable[[int], np.ndarray]] = None
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.tris.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.face_material.shape[0])
+
+    @property
+    def n_objects(self) -> int:
+        return int(self.object_vertex_range.shape[0])
+
+    def transforms(self, frame: int) -> np.ndarray:
+        if self.transforms_fn is None or self.n_objects == 0:
+            return identity_transforms(self.n_objects)
+        return self.transforms_fn(frame)
+
+
+def identity_transforms(n: int) -> np.ndarray:
+    xf = np.zeros((n, 3, 4), dtype=np.float32)
+    xf[:, 0, 0] = 1.0
+    xf[:, 1, 1] = 1.0
+    xf[:, 2, 2] = 1.0
+    return xf
+
+
+class _MeshBuilder:
+    """Accumulates shared-vertex meshes whose triangles are grouped in planar faces."""
+
+    def __init__(self):
+        self.verts: List[np.ndarray] = []
+        self.tris: List[np.ndarray] = []
+        self.tri_face: List[np.ndarray] = []
+        self.face_material: List[int] = []
+        self.face_object: List[int] = []
+        self.nv = 0
+        self.object_ranges: List[tuple] = []
+
+    def add_box(self, lo, hi, cells, material: int, obj: int = -1) -> None:
+        """Axis-aligned box [lo, hi] tessellated into cells=(nx, ny, nz) lattice quads.
+
+        The six sides are six faces (-x, +x, -y, +y, -z, +z); lattice points are
+        shared between sides so the mesh is closed.
+        """
+        nx, ny, nz = cells
+        lo = np.asarray(lo, dtype=np.float64)
+        hi = np.asarray(hi, dtype=np.float64)
+        index = {}
+        pts = []
+
+        def vid(i, j, k):
+            key = (i, j, k)
+            if key not in index:
+                index[key] = len(pts)
+                pts.append((lo[0] + (hi[0] - lo[0]) * i / nx,
+                            lo[1] + (hi[1] - lo[1]) * j / ny,
+                            lo[2] + (hi[2] - lo[2]) * k / nz))
+            return index[key]
+
+        tris = []
+        fids = []
+        base_face = len(self.face_material)
+        # (fixed axis, fixed value index, axis a, count a, axis b, count b)
+        sides = [
+            (0, 0, 1, ny, 2, nz), (0, nx, 1, ny, 2, nz),
+            (1, 0, 0, nx, 2, nz), (1, ny, 0, nx, 2, nz),
+            (2, 0, 0, nx, 1, ny), (2, nz, 0, nx, 1, ny),
+        ]
+        for f, (ax, fixed, a, na, b, nb) in enumerate(sides):
+            for ia in range(na):
+                for ib in range(nb):
+                    quad = []
+                    for (da, db) in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        c = [0, 0, 0]
+                        c[ax] = fixed
+                        c[a] = ia + da
+                        c[b] = ib + db
+                        quad.append(vid(*c))
+                    tris.append((quad[0], quad[1], quad[2]))
+                    tris.append((quad[0], quad[2], quad[3]))
+                    fids += [base_face + f, base_face + f]
+            self.face_material.append(material)
+            self.face_object.append(obj)
+        v0 = self.nv
+        self.verts.append(np.asarray(pts, dtype=np.float64).astype(np.float32))
+        self.tris.append(np.asarray(tris, dtype=np.int64) + v0)
+        self.tri_face.append(np.asarray(fids, dtype=np.int64))
+        self.nv += len(pts)
+        if obj >= 0:
+            self.object_ranges.append((v0, self.nv))
+
+    def add_ground(self, half: float, material: int) -> None:
+        pts = np.array([[-half, -half, 0.0], [half, -half, 0.0],
+                        [half, half, 0.0], [-half, half, 0.0]], dtype=np.float32)
+        f = len(self.face_material)
+        v0 = self.nv
+        self.verts.append(pts)
+        self.tris.append(np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int64) + v0)
+        self.tri_face.append(np.array([f, f], dtype=np.int64))
+        self.face_material.append(material)
+        self.face_object.append(-1)
+        self.nv += 4
+
+    def add_polygon_face(self, pts, tris, material: int) -> None:
+        """One planar face given explicitly (used by the small closed-form scenes)."""
+        pts = np.asarray(pts, dtype=np.float32)
+        f = len(self.face_material)
+        v0 = self.nv
+        self.verts.append(pts)
+        self.tris.append(np.asarray(tris, dtype=np.int64) + v0)
+        self.tri_face.append(np.full(len(tris), f, dtype=np.int64))
+        self.face_material.append(material)
+        self.face_object.append(-1)
+        self.nv += len(pts)
+
+    def finish(self, name, materials, tx, rx, **kw) -> Scene:
+        return Scene(
+            name=name,
+            vertices=np.concatenate(self.verts).astype(np.float32) if self.verts
+            else np.zeros((0, 3), np.float32),
+            tris=np.concatenate(self.tris).astype(np.int32) if self.tris
+            else np.zeros((0, 3), np.int32),
+            tri_face=np.concatenate(self.tri_face).astype(np.int32) if self.tri_face
+            else np.zeros((0,), np.int32),
+            face_material=np.asarray(self.face_material, dtype=np.int32),
+            face_object=np.asarray(self.face_object, dtype=np.int32),
+            materials=np.asarray(materials, dtype=np.float64).reshape(-1, 3),
+            object_vertex_range=np.asarray(self.object_ranges, dtype=np.int64).reshape(-1, 2),
+            tx=np.asarray(tx, dtype=np.float32).reshape(-1, 3),
+            rx=np.asarray(rx, dtype=np.float32).reshape(-1, 3),
+            **kw,
+        )
+
+
+def static_toy(seed: int = 1) -> Scene:
+    """Static toy scene, one frame: 200 m ground, 4 random boxes, 16 receivers.
+
+    Ground [-100, 100]^2 (2 triangles, ground material); four axis-aligned
+    concrete boxes with footprints U(20, 40) m per side, heights U(10, 30) m and
+    centres U(-80, 80)^2, rejection-sampled to keep 1 m clear of each other, of
+    the transmitter and of every receiver.  Tx at (0, 0, 5); receivers on the
+    grid {-75, -25, 25, 75}^2 at 1.5 m with 0.5 m capture spheres; 4096 rays,
+    2 reflections, 28 GHz, 5 W (the paper's outdoor transmit power, Sec. III).
+    """
+    rng = np.random.default_rng(seed)
+    tx = np.array([[0.0, 0.0, 5.0]])
+    g = np.array([-75.0, -25.0, 25.0, 75.0])
+    rx = np.array([[x, y, 1.5] for x in g for y in g])
+    boxes = []
+    while len(boxes) < 4:
+        sx, sy = rng.uniform(20.0, 40.0, size=2)
+        h = rng.uniform(10.0, 30.0)
+        cx, cy = rng.uniform(-80.0, 80.0, size=2)
+        lo = np.array([cx - sx / 2, cy - sy / 2])
+        hi = np.array([cx + sx / 2, cy + sy / 2])
+        ok = True
+        for (blo, bhi, _) in boxes:
+            if np.all(lo - 1.0 < bhi) and np.all(blo < hi + 1.0):
+                ok = False
+        for p in np.concatenate([tx[:, :2], rx[:, :2]]):
+            if np.all(p > lo - 1.0) and np.all(p < hi + 1.0):
+                ok = False
+        if ok:
+            boxes.append((lo, hi, h))
+    mb = _MeshBuilder()
+    mb.add_ground(100.0, material=1)
+    for (lo, hi, h) in boxes:
+        mb.add_box((lo[0], lo[1], 0.0), (hi[0], hi[1], h), (1, 1, 1), material=0)
+    return mb.finish("static_toy", [CONCRETE, GROUND], tx, rx,
+                     rx_radius=0.5, n_rays=4096, max_reflections=2,
+                     freqs_hz=[28e9], tx_power_w=5.0, n_frames=1)
+
+
+# ---- dynamic urban grid -------------------------------------------------------
+
+GRID_BLOCKS = 8
+BLOCK = 40.0
+STREET = 15.0
+EXTENT = GRID_BLOCKS * BLOCK + (GRID_BLOCKS + 1) * STREET   # 455 m
+HALF = EXTENT / 2.0                                          # 227.5 m
+LANE_OFFSET = 2.25
+VEHICLE = (4.5, 1.8, 1.5)
+VEHICLE_CLEARANCE = 0.3
+
+
+def _block_origin(i: int) -> float:
+    return -HALF + STREET + i * (BLOCK + STREET)
+
+
+def _street_centre(k: int) -> float:
+    return -HALF + STREET / 2.0 + k * (BLOCK + STREET)
+
+
+def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
+                  n_rays: int = 1 << 20, max_reflections: int = 4,
+                  n_frames: int = 60) -> Scene:
+    """Dynamic urban scene: 8x8 Manhattan grid, moving metal vehicles, 60 frames at 10 Hz.
+
+    Blocks of 40 m separated by 15 m streets (border streets included, 455 m
+    across, centred on the origin) on a [-260, 260]^2 ground plane.  One
+    concrete box building per block, footprint 40x40 m, height U(10, 60) m,
+    tessellated 3x3x6.  Each vehicle is a 4.5x1.8x1.5 m metal box 0.3 m above
+    the ground, tessellated 12x5x4 (512 triangles), placed on one of 18 streets
+    and one of its two lanes (+-2.25 m from the centre line) at a uniform
+    position, moving at U(10, 20) m/s in the lane direction, wrapping
+    periodically at the grid edge and passing through intersections.  The
+    transmitter sits 2 m above the roof centre of block (3, 3); receivers are
+    uniform on the sidewalks (4.5-7.0 m from a street centre line, away from
+    intersections) at 1.5 m.
+    """
+    rng = np.random.default_rng(seed)
+    heights = rng.uniform(10.0, 60.0, size=(GRID_BLOCKS, GRID_BLOCKS))
+    mb = _MeshBuilder()
+    mb.add_ground(260.0, material=1)
+    for i in range(GRID_BLOCKS):
+        for j in range(GRID_BLOCKS):
+            x0, y0 = _block_origin(i), _block_origin(j)
+            mb.add_box((x0, y0, 0.0), (x0 + BLOCK, y0 + BLOCK, heights[i, j]),
+                       (3, 3, 6), material=0)
+    tx = np.array([[_block_origin(3) + BLOCK / 2, _block_origin(3) + BLOCK / 2,
+                    heights[3, 3] + 2.0]])
+
+    # vehicles: (axis along which it moves, lane coordinate, direction, start, speed)
+    veh = []
+    for v in range(n_vehicles):
+        street = int(rng.integers(0, 2 * (GRID_BLOCKS + 1)))
+        lane = int(rng.integers(0, 2))
+        u = rng.uniform(-HALF, HALF)
+        speed = rng.uniform(10.0, 20.0)
+        k = street % (GRID_BLOCKS + 1)
+        c = _street_centre(k)
+        if street <= GRID_BLOCKS:      # street running along x at y = c
+            axis = 0
+            lane_c = c - LANE_OFFSET if lane == 0 else c + LANE_OFFSET
+            direction = 1.0 if lane == 0 else -1.0
+        else:                          # street running along y at x = c
+            axis = 1
+            lane_c = c + LANE_OFFSET if lane == 0 else c - LANE_OFFSET
+            direction = 1.0 if lane == 0 else -1.0
+        veh.append((axis, lane_c, direction, u, speed))
+        L, W, H = VEHICLE
+        if axis == 0:
+            lo = (u - L / 2, lane_c - W / 2, VEHICLE_CLEARANCE)
+            hi = (u + L / 2, lane_c + W / 2, VEHICLE_CLEARANCE + H)
+            cells = (12, 5, 4)
+        else:
+            lo = (lane_c - W / 2, u - L / 2, VEHICLE_CLEARANCE)
+            hi = (lane_c + W / 2, u + L / 2, VEHICLE_CLEARANCE + H)
+            cells = (5, 12, 4)
+        mb.add_box(lo, hi, cells, material=2, obj=v)
+
+    centres = np.array([_street_centre(k) for k in range(GRID_BLOCKS + 1)])
+    rx = []
+    while len(rx) < n_rx:
+        street = int(rng.integers(0, 2 * (GRID_BLOCKS + 1)))
+        side = 1.0 if rng.integers(0, 2) == 1 else -1.0
+        off = rng.uniform(4.5, 7.0)
+        along = rng.uniform(-HALF + 2.5, HALF - 2.5)
+        if np.any(np.abs(along - centres) < STREET / 2 + 0.5):
+            continue   # keep receivers out of intersections, where cross traffic passes
+        c = centres[street % (GRID_BLOCKS + 1)]
+        if street <= GRID_BLOCKS:
+            rx.append((along, c + side * off, 1.5))
+        else:
+            rx.append((c + side * off, along, 1.5))
+
+    dt = 0.1
+    veh_arr = veh
+
+    def transforms(frame: int) -> np.ndarray:
+        xf = identity_transforms(len(veh_arr))
+        for v, (axis, _lane_c, direction, u, speed) in enumerate(veh_arr):
+            p = u + direction * speed * frame * dt
+            p = -HALF + np.mod(p + HALF, EXTENT)
+            xf[v, axis, 3] = np.float32(p - u)
+        return xf
+
+    return mb.finish("dynamic_urban", [CONCRETE, GROUND, METAL], tx, np.array(rx),
+                     rx_radius=0.5, n_rays=n_rays, max_reflections=max_reflections,
+                     freqs_hz=[28e9], tx_power_w=5.0, n_frames=n_frames, dt=dt,
+                     transforms_fn=transforms)
+
+
+# ---- small scenes with closed-form answers -------------------------------------
+
+def free_space(tx, rx, **kw) -> Scene:
+    """No geometry at all: only the direct path exists."""
+    mb = _MeshBuilder()
+    return mb.finish("free_space", [CONCRETE], tx, rx, **kw)
+
+
+def ground_only(tx, rx, material=GROUND, half: float = 2000.0, **kw) -> Scene:
+    """A single ground plane z = 0 (two triangles)."""
+    mb = _MeshBuilder()
+    mb.add_ground(half, material=0)
+    return mb.finish("ground_only", [material], tx, rx, **kw)
+
+
+def single_wall(tx, rx, x: float = 10.0, half: float = 500.0, material=CONCRETE, **kw) -> Scene:
+    """One vertical wall in the plane x = const, spanning |y|, |z| <= half."""
+    mb = _MeshBuilder()
+    pts = [[x, -half, -half], [x, half, -half], [x, half, half], [x, -half, half]]
+    mb.add_polygon_face(pts, [[0, 1, 2], [0, 2, 3]], material=0)
+    return mb.finish("single_wall", [material], tx, rx, **kw)
+
+
+def corner(tx, rx, half: float = 200.0, material=CONCRETE, **kw) -> Scene:
+    """Two perpendicular walls x = 0 (y >= 0) and y = 0 (x >= 0), both |z| <= half."""
+    mb = _MeshBuilder()
+    mb.add_polygon_face([[0, 0, -half], [0, half, -half], [0, half, half], [0, 0, half]],
+                        [[0, 1, 2], [0, 2, 3]], material=0)
+    mb.add_polygon_face([[0, 0, -half], [half, 0, -half], [half, 0, half], [0, 0, half]],
+                        [[0, 1, 2], [0, 2, 3]], material=0)
+    return mb.finish("corner", [material], tx, rx, **kw)
+
+
+def parallel_walls(tx, rx, x0: float = -10.0, x1: float = 10.0, half: float = 500.0,
+                   material=CONCRETE, **kw) -> Scene:
+    """Two facing walls x = x0 and x = x1 (a street canyon without ground)."""
+    mb = _MeshBuilder()
+    for x in (x0, x1):
+        mb.add_polygon_face([[x, -half, -half], [x, half, -half], [x, half, half], [x, -half, half]],
+                            [[0, 1, 2], [0, 2, 3]], material=0)
+    return mb.finish("parallel_walls", [material], tx, rx, **kw)
+
+
+def random_sphere_dirs(n: int, seed: int) -> np.ndarray:
+    """n random directions, uniform on the unit sphere (the paper's 'random sphere of rays')."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v.astype(np.float32)
+
+
+CONFIGS = {
+    "static_toy": static_toy,
+    "dynamic_urban": dynamic_urban,
+}

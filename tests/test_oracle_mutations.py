@@ -1,0 +1,57 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a flipped sign, a wrong operand
+order) in a private copy of the oracle source, builds it, and runs the pin
+suite against that copy: the suite has to fail.  The real oracle is untouched.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dcem_oracle.cpp")
+
+MUTATIONS = {
+    "gamma_te_sign": ("g_te = (cos_t - root) / (cos_t + root);",
+                      "g_te = (root - cos_t) / (cos_t + root);"),
+    "gamma_tm_operands": ("g_tm = (eps_c * cos_t - root) / (eps_c * cos_t + root);",
+                          "g_tm = (cos_t - eps_c * root) / (cos_t + eps_c * root);"),
+    "conductivity_sign": ("cplx eps_c(m.eps_r, -m.sigma", "cplx eps_c(m.eps_r, m.sigma"),
+    "dropped_4pi": ("lam / (4.0 * kPi * length)", "lam / (kPi * length)"),
+    "phase_sign": ("std::polar(mag, -k0 * length)", "std::polar(mag, k0 * length)"),
+    "basis_order": ("V3 p_out = cross(sv, kr);", "V3 p_out = cross(kr, sv);"),
+    "reflect_factor": ("d = d - (2.0 * dot(d, n)) * n;", "d = d - dot(d, n) * n;"),
+    "image_factor": ("img[j] = img[j - 1] - (2.0 *", "img[j] = img[j - 1] - (1.0 *"),
+    "tie_break": ("if (t < tb) { tb = t;", "if (t <= tb) { tb = t;"),
+    "capture_clamp": ("s = std::max(0.0, std::min(s, tb));", "s = std::max(0.0, s);"),
+    "theta_hat_sign": ("V3{u.z * u.x / rho, u.z * u.y / rho, -rho}",
+                       "V3{u.z * u.x / rho, u.z * u.y / rho, rho}"),
+    "attenuation_sign": ("std::pow(10.0, -atten_db_per_km", "std::pow(10.0, atten_db_per_km"),
+    "golden_angle": ("kPi * (3.0 - std::sqrt(5.0))", "kPi * (3.0 + std::sqrt(5.0))"),
+    "no_in_face_check": ("if (!inside) return out;", "(void)inside;"),
+    "no_occlusion": ("if (m >= 0 && inside_t) hit = true;", "(void)inside_t;"),
+    "no_side_check": ("if (!(s > 0.0 && s < 1.0)) return out;", ""),
+    "xform_order": ("r = r + (double)row[3];", "r = r - (double)row[3];"),
+    "tie_flag_dropped": ("flags |= SEG_TIE;", "(void)0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation anchor not found: %s" % name
+    mutated = src.replace(old, new)
+    cpp = tmp_path / "mut.cpp"
+    lib = tmp_path / "libmut.so"
+    cpp.write_text(mutated)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-pthread",
+                           str(cpp), "-o", str(lib)])
+    env = dict(os.environ, DCEM_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])

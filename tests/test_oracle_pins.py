@@ -1,0 +1,530 @@
+"""Pins of the CPU oracle against closed forms, invariants and brute force.
+
+Nothing here re-types the oracle's formulas: each expected value comes from a
+different route (Eq. (3) in dB form, the textbook two-ray model, image theory
+for perfect conductors, Maxwell boundary conditions solved numerically, the
+paper's Table II coefficient, exact hit distances of simple rays, brute-force
+enumeration of face sequences).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2112_07115_amd import scenes
+
+C0 = 299792458.0
+EPS0 = 8.8541878128e-12
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def sim_params():
+    return {r[0]: float(r[1]) for r in _golden("sim_parameters.txt")}
+
+
+def table2():
+    return {r[0]: (float(r[1]), float(r[2]), float(r[3])) for r in _golden("table2_materials.txt")}
+
+
+def eq3_received_dbm(pt_w, f_hz, d, n=2.0, at_db=0.0):
+    """Eq. (3): PL = FSPL(f, 1 m) + 10 n log10(d) + AT, with n = 2 in free space."""
+    fspl_1m = 20.0 * math.log10(4.0 * math.pi * f_hz / C0)
+    return 10.0 * math.log10(pt_w * 1e3) - (fspl_1m + 10.0 * n * math.log10(d) + at_db)
+
+
+def eps_c(eps_r, sigma, f):
+    return complex(eps_r, -sigma / (2 * math.pi * f * EPS0))
+
+
+def bc_reflection(ec, cos_t, pol):
+    """Reflection coefficient from Maxwell's boundary conditions, solved numerically.
+
+    Vacuum z > 0, medium of relative permittivity ec at z < 0, plane waves
+    ~ exp(j(wt - k.r)), H ~ k x E.  The incident field is along s (TE) or
+    p = s x k_i (TM), with s = k_i x n / |k_i x n|; the reflected field is
+    expressed along s (TE) or p' = s x k_r (TM).  Tangential E and H are
+    continuous at z = 0; the 2x2 system is solved for (R, T) by least squares.
+    """
+    sin_t = math.sqrt(max(0.0, 1.0 - cos_t * cos_t))
+    ki = np.array([sin_t, 0.0, -cos_t], dtype=complex)
+    kr = np.array([sin_t, 0.0, cos_t], dtype=complex)
+    ktz = -np.sqrt(ec - sin_t ** 2 + 0j)
+    kt = np.array([sin_t, 0.0, ktz], dtype=complex)
+    n = np.array([0.0, 0.0, 1.0])
+    s = np.cross(ki.real, n)
+    s = s / np.linalg.norm(s)
+    if pol == "TE":
+        ei, er, et = s.astype(complex), s.astype(complex), s.astype(complex)
+    else:
+        ei, er, et = np.cross(s, ki), np.cross(s, kr), np.cross(s, kt)
+    hi, hr, ht = np.cross(ki, ei), np.cross(kr, er), np.cross(kt, et)
+    # rows: E_x, E_y, H_x, H_y ; unknowns R, T ; rhs = -incident
+    A = np.array([[er[0], -et[0]], [er[1], -et[1]], [hr[0], -ht[0]], [hr[1], -ht[1]]])
+    b = -np.array([ei[0], ei[1], hi[0], hi[1]])
+    sol, *_ = np.linalg.lstsq(A, b, rcond=None)
+    assert np.linalg.norm(A @ sol - b) < 1e-10
+    return sol[0]
+
+
+def refine_keys(O, sc, keys, K, freqs=None, xf=None):
+    osc = O.OracleScene(sc, xf)
+    return O.refine(osc, sc.tx, sc.rx, np.asarray(keys, np.int32), K,
+                    freqs or sc.freqs_hz, sc.tx_power_w)
+
+
+# ---------------------------------------------------------------- Fresnel ----
+
+@pytest.mark.parametrize("eps_r,sigma", [(5.31, 0.48), (15.0, 0.035), (1.0, 1e7), (4.0, 0.0),
+                                         (80.0, 4.0), (2.0, 1e-3)])
+@pytest.mark.parametrize("cos_t", [1.0, 0.9, 0.5, 0.2, 0.01])
+def test_fresnel_matches_boundary_conditions(oracle_mod, eps_r, sigma, cos_t):
+    f = 28e9
+    te, tm = oracle_mod.fresnel(eps_r, sigma, f, cos_t)
+    ec = eps_c(eps_r, sigma, f)
+    if cos_t < 1.0:
+        assert abs(te - bc_reflection(ec, cos_t, "TE")) < 1e-9
+        assert abs(tm - bc_reflection(ec, cos_t, "TM")) < 1e-9
+    else:
+        # normal incidence, textbook: (1 - sqrt(eps)) / (1 + sqrt(eps)); TM = -TE
+        r = (1 - np.sqrt(ec)) / (1 + np.sqrt(ec))
+        assert abs(te - r) < 1e-12
+        assert abs(tm + r) < 1e-12
+
+
+def test_fresnel_pec_limit(oracle_mod):
+    prev = None
+    for sigma in [1e7, 1e9, 1e11, 1e13, 1e15]:
+        for cos_t in [1.0, 0.7, 0.3]:
+            te, tm = oracle_mod.fresnel(1.0, sigma, 28e9, cos_t)
+            bound = 2.5 / (cos_t * math.sqrt(abs(eps_c(1.0, sigma, 28e9))))
+            assert abs(te + 1) <= bound and abs(tm - 1) <= bound
+        dev = abs(oracle_mod.fresnel(1.0, sigma, 28e9, 0.7)[0] + 1)
+        if prev is not None:
+            assert dev < prev
+        prev = dev
+    assert prev < 1e-7
+
+
+def test_fresnel_brewster_zero(oracle_mod):
+    for eps_r in [2.0, 4.0, 9.0, 15.0]:
+        th = math.atan(math.sqrt(eps_r))
+        _, tm = oracle_mod.fresnel(eps_r, 0.0, 28e9, math.cos(th))
+        assert abs(tm) < 1e-12
+
+
+def test_fresnel_passivity_and_grazing(oracle_mod):
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        er = rng.uniform(1.0, 80.0)
+        sg = 10 ** rng.uniform(-4, 3)
+        c = rng.uniform(1e-6, 1.0)
+        te, tm = oracle_mod.fresnel(er, sg, 28e9, c)
+        assert abs(te) <= 1 + 1e-12 and abs(tm) <= 1 + 1e-12
+    for er, sg in [(5.31, 0.48), (15.0, 0.035)]:
+        te, tm = oracle_mod.fresnel(er, sg, 28e9, 0.0)
+        assert abs(te + 1) < 1e-12 and abs(tm + 1) < 1e-12
+
+
+def test_fresnel_constant_gamma_table2(oracle_mod):
+    g = table2()["wall_outdoor"][1]
+    te, tm = oracle_mod.fresnel(5.0, 0.1, 28e9, 0.3, const_gamma=g)
+    assert te == -g and tm == g
+
+
+# ----------------------------------------------------------- direct path ----
+
+def test_friis_eq3(oracle_mod):
+    p = sim_params()
+    f, pt, h = p["frequency"], p["tx_power_outdoor"], p["tx_height"]
+    d = np.array([1.0, 7.5, 30.0, 100.0, 1234.5])
+    sc = scenes.free_space([[0, 0, h]], [[x, 0, h] for x in d], freqs_hz=[f], tx_power_w=pt)
+    keys = oracle_mod.los_keys(1, len(d), 0)
+    paths = refine_keys(oracle_mod, sc, keys, 0)
+    assert paths.valid.all()
+    pc, pi = oracle_mod.received_power(paths, 1, len(d), 1)
+    got = 10 * np.log10(pc[0, 0] * 1e3)
+    want = np.array([eq3_received_dbm(pt, f, x) for x in d])
+    np.testing.assert_allclose(got, want, atol=1e-9)
+    np.testing.assert_allclose(pc, pi, rtol=1e-12)
+    np.testing.assert_allclose(paths.length, d, rtol=1e-12)
+    np.testing.assert_allclose(paths.tau, d / C0, rtol=1e-12)
+
+
+def test_atmospheric_term_eq3(oracle_mod):
+    # Eq. (3)'s AT term: a specific attenuation gamma [dB/km] adds gamma * d / 1000 dB
+    d = np.array([10.0, 250.0, 900.0])
+    sc = scenes.free_space([[0, 0, 2]], [[0, x, 2] for x in d], freqs_hz=[60e9])
+    osc = oracle_mod.OracleScene(sc)
+    paths = oracle_mod.refine(osc, sc.tx, sc.rx, oracle_mod.los_keys(1, 3, 0), 0, [60e9], 5.0,
+                              atten_db_per_km=15.0)
+    pc, _ = oracle_mod.received_power(paths, 1, 3, 1)
+    want = [eq3_received_dbm(5.0, 60e9, x, at_db=15.0 * x / 1000.0) for x in d]
+    np.testing.assert_allclose(10 * np.log10(pc[0, 0] * 1e3), want, atol=1e-9)
+
+
+def test_friis_28ghz_100m_value(oracle_mod):
+    # 5 W = 36.99 dBm; FSPL(28 GHz, 1 m) = 61.39 dB; 100 m adds 40 dB
+    assert abs(eq3_received_dbm(5.0, 28e9, 100.0) - (-64.40)) < 0.005
+    sc = scenes.free_space([[0, 0, 5]], [[100, 0, 5]])
+    paths = refine_keys(oracle_mod, sc, oracle_mod.los_keys(1, 1, 0), 0)
+    pc, _ = oracle_mod.received_power(paths, 1, 1, 1)
+    assert abs(10 * np.log10(pc[0, 0, 0] * 1e3) - (-64.40)) < 0.005
+
+
+def test_receding_receiver_trend(oracle_mod):
+    # paper, Fig. 13: as the car moves away, direct-path power falls and delay grows
+    xs = np.linspace(80.0, 100.0, 11)
+    sc = scenes.ground_only([[0, 0, 2.0]], [[x, 3.0, 1.5] for x in xs])
+    paths = refine_keys(oracle_mod, sc, oracle_mod.los_keys(1, len(xs), 0), 0)
+    p = np.sum(np.abs(paths.amp[:, 0]) ** 2, axis=-1)
+    assert np.all(np.diff(paths.tau) > 0) and np.all(np.diff(p) < 0)
+
+
+# ------------------------------------------------------- reflected paths ----
+
+def test_two_ray_ground(oracle_mod):
+    f, pt, ht, hr = 28e9, 5.0, 5.0, 1.5
+    ds = np.linspace(300.0, 1500.0, 97)
+    sc = scenes.ground_only([[0, 0, ht]], [[x, 0, hr] for x in ds])
+    keys = []
+    for r in range(len(ds)):
+        keys.append([0, r, 0, -1])
+        keys.append([0, r, 1, 0])
+    paths = refine_keys(oracle_mod, sc, keys, 1)
+    assert paths.valid.all()
+    pc, _ = oracle_mod.received_power(paths, 1, len(ds), 1)
+    lam = C0 / f
+    k = 2 * math.pi / lam
+    ec = eps_c(*scenes.GROUND[:2], f)
+    d1 = np.sqrt(ds ** 2 + (ht - hr) ** 2)
+    d2 = np.sqrt(ds ** 2 + (ht + hr) ** 2)
+    gam = np.array([bc_reflection(ec, (ht + hr) / x, "TM") for x in d2])
+    field = np.exp(-1j * k * d1) / d1 + gam * np.exp(-1j * k * d2) / d2
+    scalar = pt * (lam / (4 * math.pi)) ** 2 * np.abs(field) ** 2
+    away = np.abs(field) > 0.3 * (1 / d1 + np.abs(gam) / d2)
+    assert away.sum() > 40
+    err_db = np.abs(10 * np.log10(pc[0, 0][away] / scalar[away]))
+    assert err_db.max() < 0.01
+    # reflected path length = distance to the image transmitter (closed form)
+    np.testing.assert_allclose(paths.length[1::2], d2, rtol=1e-12)
+
+
+@pytest.mark.parametrize("geom", ["ground", "wall"])
+def test_pec_reflection_is_image_source_field(oracle_mod, geom):
+    """A perfect conductor reflects like an image source (image theory).
+
+    Ground z = 0: the image of the theta-polarised source radiates theta-hat
+    of its own direction.  Vertical wall x = 10: the image is reversed.
+    """
+    pec = (1.0, 1e17, float("nan"))
+    tx = np.array([0.0, 0.0, 5.0])
+    rx = np.array([[40.0, 7.0, 1.5], [25.0, -3.0, 9.0], [3.0, 1.0, 2.0]])
+    if geom == "ground":
+        sc = scenes.ground_only([tx], rx, material=pec)
+        img, sign = tx * np.array([1, 1, -1]), 1.0
+    else:
+        sc = scenes.single_wall([tx], rx * np.array([0.2, 1, 1]), x=10.0, material=pec)
+        img, sign = np.array([20.0 - tx[0], tx[1], tx[2]]), -1.0
+    keys = [[0, r, 1, 0] for r in range(3)]
+    paths = refine_keys(oracle_mod, sc, keys, 1)
+    assert paths.valid.all()
+    f = 28e9
+    lam, k = C0 / f, 2 * math.pi * f / C0
+    for r in range(3):
+        v = sc.rx[r].astype(np.float64) - img
+        d = np.linalg.norm(v)
+        u = v / d
+        th, ph = math.acos(u[2]), math.atan2(u[1], u[0])
+        theta_hat = np.array([math.cos(th) * math.cos(ph), math.cos(th) * math.sin(ph), -math.sin(th)])
+        want = sign * math.sqrt(5.0) * lam / (4 * math.pi * d) * np.exp(-1j * k * d) * theta_hat
+        assert np.linalg.norm(paths.amp[r, 0] - want) < 1e-6 * np.linalg.norm(want)
+
+
+def test_validation_occlusion_and_sides(oracle_mod):
+    sc = scenes.single_wall([[0, 0, 1.5]], [[20.0, 0.0, 1.5], [5.0, 0.0, 1.5], [15.0, 5.0, 1.5]], x=10.0)
+    keys = [[0, 0, 0, -1], [0, 1, 0, -1], [0, 1, 1, 0], [0, 2, 1, 0]]
+    paths = refine_keys(oracle_mod, sc, keys, 1)
+    # direct path through the wall is blocked; in front of it, it is clear;
+    # a reflection towards a receiver behind the wall does not exist
+    assert list(paths.valid) == [False, True, True, False]
+
+
+def test_single_wall_te(oracle_mod):
+    sc = scenes.single_wall([[0, 0, 1.5]], [[0, 20, 1.5]], x=10.0)
+    paths = refine_keys(oracle_mod, sc, [[0, 0, 1, 0]], 1)
+    assert paths.valid[0]
+    d = 2 * math.hypot(10.0, 10.0)      # reflection point at the midpoint, by symmetry
+    assert abs(paths.length[0] - d) < 1e-12 * d
+    f = 28e9
+    lam = C0 / f
+    g = bc_reflection(eps_c(*scenes.CONCRETE[:2], f), math.cos(math.radians(45.0)), "TE")
+    p = np.sum(np.abs(paths.amp[0, 0]) ** 2)
+    assert abs(p - 5.0 * (lam / (4 * math.pi * d)) ** 2 * abs(g) ** 2) < 1e-9 * p
+    # vertical polarisation at grazing-free horizontal incidence stays vertical
+    assert np.linalg.norm(paths.amp[0, 0, :2]) < 1e-12 * np.linalg.norm(paths.amp[0, 0])
+    np.testing.assert_allclose(paths.aod[0], [math.sqrt(0.5), math.sqrt(0.5), 0.0], atol=1e-12)
+    np.testing.assert_allclose(paths.aoa[0], [math.sqrt(0.5), -math.sqrt(0.5), 0.0], atol=1e-12)
+
+
+def test_brewster_path_vanishes(oracle_mod):
+    mat = (4.0, 0.0, float("nan"))
+    # tan(theta) = (x / 2) / h = sqrt(eps_r) at x = 4 h for equal heights
+    sc = scenes.ground_only([[0, 0, 5.0]], [[20.0, 0, 5.0]], material=mat)
+    paths = refine_keys(oracle_mod, sc, [[0, 0, 0, -1], [0, 0, 1, 0]], 1)
+    assert paths.valid.all()
+    assert np.linalg.norm(paths.amp[1, 0]) < 1e-12 * np.linalg.norm(paths.amp[0, 0])
+
+
+def test_normal_incidence_branch_is_continuous(oracle_mod):
+    sc = scenes.ground_only([[0, 0, 5.0]], [[0, 0, 1.5], [1e-5, 0, 1.5], [0, 1e-5, 1.5]])
+    paths = refine_keys(oracle_mod, sc, [[0, r, 1, 0] for r in range(3)], 1)
+    assert paths.valid.all()
+    ec = eps_c(*scenes.GROUND[:2], 28e9)
+    r0 = (1 - np.sqrt(ec)) / (1 + np.sqrt(ec))
+    lam = C0 / 28e9
+    mag = math.sqrt(5.0) * lam / (4 * math.pi * 6.5)
+    # exactly normal: E0 = theta-hat of straight down = -x, reflected with Gamma_TE(0)
+    e = paths.amp[0, 0] * np.exp(1j * 2 * math.pi / lam * 6.5) / mag
+    np.testing.assert_allclose(e, [-r0, 0, 0], atol=1e-9)
+    # off-normal by 1e-5 m: the generic branch converges to the normal-incidence one
+    # (the second point departs at azimuth 90 deg, where theta-hat points along -y)
+    a0 = paths.amp[0, 0]
+    assert np.linalg.norm(paths.amp[1, 0] - a0) < 1e-5 * np.linalg.norm(a0)
+    assert np.linalg.norm(paths.amp[2, 0] - a0[[1, 0, 2]]) < 1e-5 * np.linalg.norm(a0)
+
+
+def test_constant_gamma_orders(oracle_mod):
+    g = table2()["wall_outdoor"][1]     # 0.8 (Table II)
+    mat = (5.0, 0.0, g)
+    f, pt = 28e9, 5.0
+    lam = C0 / f
+    sc = scenes.parallel_walls([[0, 0, 1.5]], [[3.0, 40.0, 1.5]], material=mat)
+    keys = [[0, 0, 1, 1, -1], [0, 0, 1, 0, -1], [0, 0, 2, 0, 1], [0, 0, 2, 1, 0]]
+    paths = refine_keys(oracle_mod, sc, keys, 2)
+    assert paths.valid.all()
+    for i, kk in enumerate(keys):
+        order = kk[2]
+        d = paths.length[i]
+        p = np.sum(np.abs(paths.amp[i, 0]) ** 2)
+        assert abs(p - (g ** 2) ** order * pt * (lam / (4 * math.pi * d)) ** 2) < 1e-10 * p
+    # closed-form lengths: unfold the canyon (walls x = -10 and x = +10); the
+    # transmitter's x after reflections [1], [0], [0, 1], [1, 0] is 20, -20, 40, -40
+    def unfolded(xi):
+        return math.hypot(xi - 3.0, 40.0)
+    np.testing.assert_allclose(paths.length, [unfolded(20.0), unfolded(-20.0),
+                                              unfolded(40.0), unfolded(-40.0)], rtol=1e-12)
+
+
+def test_corner_reflector_double_bounce(oracle_mod):
+    """Two reflections in perpendicular walls = point reflection through the corner axis.
+
+    Walls x = 0 (y >= 0, face 0) and y = 0 (x >= 0, face 1).  The straight line
+    from the receiver to the doubly-mirrored transmitter crosses exactly one of
+    the two half-walls first; that wall is the last one hit, which fixes the
+    only valid order of the two faces."""
+    for tx, rx in [([3.0, 5.0, 1.0], [8.0, 2.0, 1.5]), ([6.0, 1.0, 2.0], [1.0, 9.0, 1.0]),
+                   ([4.0, 4.0, 1.0], [2.0, 7.0, 3.0])]:
+        sc = scenes.corner([tx], [rx])
+        paths = refine_keys(oracle_mod, sc, [[0, 0, 2, 0, 1], [0, 0, 2, 1, 0]], 2)
+        img = np.array([-tx[0], -tx[1], tx[2]])
+        r = np.array(rx)
+        # parameter where the segment r -> img meets y = 0, and the x there
+        s_y = r[1] / (r[1] - img[1])
+        x_at = r[0] + s_y * (img[0] - r[0])
+        last_is_y_wall = x_at >= 0
+        assert list(paths.valid) == [last_is_y_wall, not last_is_y_wall]
+        d = np.linalg.norm(r - img)
+        assert abs(paths.length[paths.valid][0] - d) < 1e-12 * d
+
+
+def test_reciprocity_static_toy(oracle_mod):
+    s = scenes.static_toy()
+    K = 2
+    a, b = s.tx[0], s.rx[5]
+    fwd = scenes.Scene(**{**s.__dict__, "tx": a[None], "rx": b[None]})
+    bwd = scenes.Scene(**{**s.__dict__, "tx": b[None], "rx": a[None]})
+    keys = oracle_mod.enumerate_keys(s.n_faces, 1, 1, K)
+    pf = refine_keys(oracle_mod, fwd, keys, K)
+    pb = refine_keys(oracle_mod, bwd, keys, K)
+    def as_set(p):
+        out = {}
+        for kk, v, l in zip(p.keys.tolist(), p.valid, p.length):
+            if v:
+                out[tuple(kk[3:3 + kk[2]])] = l
+        return out
+    sf, sb = as_set(pf), as_set(pb)
+    assert len(sf) >= 3
+    assert set(sf) == {tuple(reversed(k)) for k in sb}
+    for k, l in sf.items():
+        assert abs(l - sb[tuple(reversed(k))]) < 1e-9 * l
+
+
+# ------------------------------------------------------------------ trace ----
+
+def _trace(O, sc, dirs, K, xf=None):
+    osc = O.OracleScene(sc, xf)
+    return O.trace(osc, sc.tx, sc.rx, sc.rx_radius, np.asarray(dirs, np.float32), K)
+
+
+def test_trace_straight_down_and_back(oracle_mod):
+    sc = scenes.ground_only([[0, 0, 5.0]], [[50, 50, 1.5]])
+    tr = _trace(oracle_mod, sc, [[0, 0, -1]], 2)
+    assert tr.tri[0, 0, 0] in (0, 1) and tr.t[0, 0, 0] == 5.0
+    assert tr.tri[0, 0, 1] == -1          # reflected straight up: nothing above
+    assert tr.tri[0, 0, 2] == -2          # terminated
+    assert tr.length[0, 0, 0] == 5.0
+
+
+def test_trace_canyon_bounces(oracle_mod):
+    a = math.radians(70.0)
+    sc = scenes.parallel_walls([[0, 0, 0.0]], [[0, 900, 0]])
+    d = np.array([[math.cos(a), math.sin(a), 0.0]], np.float32)
+    K = 4
+    tr = _trace(oracle_mod, sc, d, K)
+    dx = float(d[0, 0])
+    assert list(tr.face[0, 0]) == [1, 0, 1, 0, 1]
+    want = [10.0 / dx] + [20.0 / dx] * K
+    np.testing.assert_allclose(tr.t[0, 0], want, rtol=1e-12)
+    dl = float(np.linalg.norm(d[0].astype(np.float64)))
+    np.testing.assert_allclose(tr.length[0, 0], np.cumsum(want) * dl, rtol=1e-12)
+
+
+def test_trace_capture_radius(oracle_mod):
+    sc = scenes.free_space([[0, 0, 0.0]], [[50, 0.49, 0], [50, 0.51, 0], [-50, 0.1, 0]])
+    tr = _trace(oracle_mod, sc, [[1, 0, 0]], 1)
+    hit = tr.caps[(tr.cap_flags & oracle_mod.CAP_HIT) != 0]
+    assert hit[:, 2].tolist() == [0]        # only rx 0; rx 2 lies behind the ray origin
+    assert hit[0, 3] == 0 and tr.tri[0, 0, 0] == -1
+
+
+def test_trace_capture_stops_at_hit(oracle_mod):
+    # a segment ends at its hit: a receiver behind the wall is not captured by it
+    sc = scenes.single_wall([[0, 0, 0.0]], [[20.0, 0.1, 0.0], [5.0, 0.1, 0.0]], x=10.0)
+    tr = _trace(oracle_mod, sc, [[1, 0, 0]], 0)
+    hit = tr.caps[(tr.cap_flags & oracle_mod.CAP_HIT) != 0]
+    assert hit[:, 2].tolist() == [1]
+    assert tr.t[0, 0, 0] == 10.0
+
+
+def test_trace_tie_break_and_flags(oracle_mod):
+    # two coplanar overlapping squares in z = 0 on different faces
+    mb = scenes._MeshBuilder()
+    sq = [[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0]]
+    mb.add_polygon_face(sq, [[0, 1, 2], [0, 2, 3]], material=0)
+    mb.add_polygon_face(sq, [[0, 1, 2], [0, 2, 3]], material=0)
+    sc = mb.finish("tie", [scenes.CONCRETE], [[0.3, -0.5, 2.0]], [[5, 5, 5]])
+    tr = _trace(oracle_mod, sc, [[0, 0, -1]], 0)
+    assert tr.tri[0, 0, 0] == 0                      # lower id wins the exact tie
+    assert tr.flags[0, 0, 0] & oracle_mod.SEG_TIE
+
+
+def test_trace_edge_flags(oracle_mod):
+    mb = scenes._MeshBuilder()
+    mb.add_polygon_face([[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0]],
+                        [[0, 1, 2], [0, 2, 3]], material=0)
+    sc = mb.finish("edge", [scenes.CONCRETE], [[0.25, 0.25, 2.0], [1.0, 0.3, 2.0], [0.2, -0.4, 2.0]],
+                   [[5, 5, 5]])
+    tr = _trace(oracle_mod, sc, [[0, 0, -1]], 0)
+    assert tr.flags[0, 0, 0] == oracle_mod.SEG_TRI      # on the internal diagonal
+    assert tr.flags[1, 0, 0] & oracle_mod.SEG_EDGE      # on the silhouette x = 1
+    assert tr.flags[2, 0, 0] == 0                       # well inside one triangle
+
+
+def test_trace_t_min(oracle_mod):
+    sc = scenes.ground_only([[0, 0, 0.5e-4]], [[50, 50, 1.5]])
+    tr = _trace(oracle_mod, sc, [[0, 0, -1]], 0)
+    assert tr.tri[0, 0, 0] == -1                      # the ground is closer than t_min
+
+
+def test_object_transform_moves_geometry(oracle_mod):
+    s = scenes.dynamic_urban(n_rays=16, n_frames=31)
+    xf = s.transforms(30)
+    v = s.object_vertex_range[0]
+    lo = s.vertices[v[0]:v[1]].min(axis=0).astype(np.float64)
+    hi = s.vertices[v[0]:v[1]].max(axis=0).astype(np.float64)
+    # a ray straight down over vehicle 0's moved roof hits that roof (z = 1.8)
+    c = (lo + hi) / 2 + xf[0, :, 3]
+    sc = scenes.Scene(**{**s.__dict__, "tx": np.array([[c[0] + 0.01, c[1] + 0.013, 10.0]], np.float32)})
+    tr = _trace(oracle_mod, sc, [[0, 0, -1]], 0, xf=xf)
+    assert s.face_object[tr.face[0, 0, 0]] == 0
+    assert abs(tr.t[0, 0, 0] - (10.0 - 1.8)) < 1e-5
+    # in the upload pose the vehicle is elsewhere (it moved 30 m or more)
+    tr0 = _trace(oracle_mod, sc, [[0, 0, -1]], 0, xf=None)
+    assert s.face_object[tr0.face[0, 0, 0]] != 0
+
+
+# --------------------------------------------------- discovery vs images ----
+
+def test_fibonacci_sphere(oracle_mod):
+    n = 1000
+    d = oracle_mod.fibonacci(n).astype(np.float64)
+    i = np.arange(n)
+    np.testing.assert_allclose(d[:, 2], 1 - (2 * i + 1) / n, atol=1e-7)
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, atol=3e-7)
+    assert np.abs(d.mean(axis=0)).max() < 2e-3
+    az = np.arctan2(d[:, 1], d[:, 0])
+    step = np.mod(np.diff(az), 2 * np.pi)
+    ga = np.pi * (3 - np.sqrt(5))
+    np.testing.assert_allclose(step[10:-10], ga, atol=1e-5)
+
+
+def test_ray_along_exact_path_follows_it(oracle_mod):
+    """Shooting along an image-method path's departure direction retraces its faces."""
+    s = scenes.static_toy()
+    K = 2
+    keys = oracle_mod.enumerate_keys(s.n_faces, 1, len(s.rx), K)
+    paths = refine_keys(oracle_mod, s, keys, K)
+    ok = paths.valid & ~paths.marginal
+    assert ok.sum() > 20
+    sel = np.nonzero(ok)[0]
+    dirs = paths.aod[sel].astype(np.float32)
+    osc = oracle_mod.OracleScene(s)
+    checked = 0
+    for j, i in enumerate(sel):
+        tr = oracle_mod.trace(osc, s.tx, s.rx, s.rx_radius, dirs[j:j + 1], K)
+        if tr.flags[0, 0].any():
+            continue
+        order = keys[i, 2]
+        assert list(tr.face[0, 0, :order]) == list(keys[i, 3:3 + order])
+        hit = tr.caps[(tr.cap_flags & oracle_mod.CAP_HIT) != 0]
+        rows = {(int(r[2]), int(r[3])) for r in hit}
+        assert (int(keys[i, 1]), int(order)) in rows
+        checked += 1
+    assert checked > 20
+
+
+def test_dense_rays_find_every_short_range_path(oracle_mod):
+    sc = scenes.single_wall([[0, 0, 1.5]], [[2.0, 12.0, 1.5], [-4.0, 8.0, 3.0]], x=10.0,
+                            n_rays=200000, max_reflections=1)
+    fr = oracle_mod.frame(sc, los_always=False)
+    found = {tuple(k) for k, v in zip(fr.keys.tolist(), fr.paths.valid) if v}
+    keys = oracle_mod.enumerate_keys(1, 1, 2, 1)
+    paths = refine_keys(oracle_mod, sc, keys, 1)
+    want = {tuple(k) for k, v in zip(keys.tolist(), paths.valid) if v}
+    assert len(want) == 4 and found == want
+
+
+def test_enumeration_contains_discovered_paths(oracle_mod):
+    s = scenes.static_toy()
+    K = 2
+    dirs = scenes.random_sphere_dirs(200000, seed=11)
+    fr = oracle_mod.frame(s, dirs=dirs, K=K)
+    keys = oracle_mod.enumerate_keys(s.n_faces, 1, len(s.rx), K)
+    paths = refine_keys(oracle_mod, s, keys, K)
+    enum_valid = {tuple(k) for k, v in zip(keys.tolist(), paths.valid) if v}
+    disc_valid = {tuple(k) for k, v in zip(fr.keys.tolist(), fr.paths.valid) if v}
+    assert len(disc_valid) > 20
+    assert disc_valid <= enum_valid
