@@ -1,0 +1,254 @@
+/*
+ * dcem.h - C ABI of the MI355X dynamic coherence-based EM ray tracer.
+ *
+ * Implements the per-frame loop of Wang & Manocha, "Dynamic Coherence-Based
+ * EM Ray Tracing Simulations in Vehicular Environments" (Sec. III): a BVH
+ * kept up to date while vehicles move ("Efficient BVH updating"), a sphere of
+ * rays bounced by specular reflection up to K times (the frame algorithm's
+ * steps 1-2 and the "Reflected and transmitted rays" item), receiver capture
+ * spheres, de-duplicated face-sequence candidates (the per-depth visited-path
+ * tables), image-method refinement and validation (steps 3-4), per-path
+ * distance, direction, Fresnel attenuation and phase (step 6), and per-receiver
+ * received power (Eq. (3) with path-loss exponent 2 for the free-space
+ * magnitude, plus the phase calculation).  Paths found in the previous frame
+ * are revalidated and only invalidated rays are traced again ("Propagation
+ * path caching").
+ *
+ * Rays are shot forward from the transmitters and captured at receiver
+ * spheres (the paper traces backward from the receiver; the set of geometric
+ * paths is the same by reciprocity).
+ *
+ * Units: metres, hertz, watts, siemens per metre.  Right-handed, z up.
+ * Geometry is FP32; path lengths, phases and fields are FP64.
+ *
+ * Conventions for every call:
+ *  - A dcem_ctx owns one HIP device and one HIP stream; all work is enqueued
+ *    on that stream in call order.  A context is not thread-safe.
+ *  - Input arrays are owned by the caller.  Host inputs (mem_kind
+ *    DCEM_MEM_HOST) are copied before the call returns and may be freed at
+ *    once.  Device inputs (DCEM_MEM_DEVICE) are read on the context's stream
+ *    and must stay valid and unchanged until that stream has passed the call.
+ *  - No exception or abort crosses this interface.  Every call returns a
+ *    dcem_status; on failure dcem_last_error() describes it.  Faults detected
+ *    inside kernels (traversal stack overflow, candidate buffer overflow,
+ *    non-finite input) set a device error word that is reported by the next
+ *    call that synchronises (dcem_received_power, dcem_get_*); that frame's
+ *    outputs are then undefined.
+ *  - Call order: dcem_scene_upload, then per frame optionally
+ *    dcem_set_object_transforms and dcem_refit_bvh, then dcem_trace_frame,
+ *    then dcem_received_power / dcem_get_*.  Other orders return
+ *    DCEM_E_STATE.
+ */
+#ifndef DCEM_H
+#define DCEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dcem_ctx dcem_ctx;
+typedef int32_t dcem_status;
+
+#define DCEM_OK 0
+#define DCEM_E_INVALID_ARG (-1)   /* bad pointer, size, index or non-finite value */
+#define DCEM_E_OUT_OF_MEMORY (-2) /* device allocation failed */
+#define DCEM_E_DEVICE (-3)        /* HIP runtime error */
+#define DCEM_E_STATE (-4)         /* call made out of order */
+#define DCEM_E_CAPACITY (-5)      /* a device buffer or the traversal stack overflowed */
+#define DCEM_E_UNSUPPORTED (-6)   /* sizes beyond what this build supports */
+
+#define DCEM_MEM_HOST 0
+#define DCEM_MEM_DEVICE 1
+
+#define DCEM_MODE_FULL 0      /* trace every ray */
+#define DCEM_MODE_COHERENT 1  /* reuse the previous frame's rays; retrace invalidated ones */
+
+#define DCEM_FORCE_REBUILD 1  /* dcem_refit_bvh flag: rebuild instead of refitting */
+
+#define DCEM_MAX_REFLECTIONS 10  /* paper, Sec. III: at most 10 reflections */
+
+/* bits of the device error word (reported as DCEM_E_CAPACITY / DCEM_E_INVALID_ARG) */
+#define DCEM_ERR_STACK 1u      /* traversal stack overflow */
+#define DCEM_ERR_CAPTURES 2u   /* more captures than the candidate capacity */
+#define DCEM_ERR_NONFINITE 4u  /* non-finite vertex after a transform */
+
+/* Scene geometry and materials (paper Sec. III: the environment description
+ * and Table II's per-material reflection properties).
+ *  vertices             [n_vertices][3] FP32, the upload (reference) pose
+ *  tris                 [n_tris][3] vertex indices
+ *  tri_face             [n_tris] face index of each triangle.  A face is a
+ *                       planar group of triangles; paths are identified by
+ *                       face sequences, so a tessellated wall is one face.
+ *  face_material        [n_faces] material index
+ *  face_object          [n_faces] moving-object index, -1 for static faces
+ *  materials            [n_materials][3] FP64: eps_r, sigma [S/m],
+ *                       const_gamma.  const_gamma = NaN selects Fresnel
+ *                       coefficients from (eps_r, sigma); any other value g
+ *                       is a polarisation-independent coefficient of
+ *                       magnitude g (Table II's scalar reflection
+ *                       coefficient): Gamma_TE = -g, Gamma_TM = +g.
+ *  object_vertex_range  [n_objects][2] half-open vertex range of each moving
+ *                       object; ranges must not overlap
+ *  mem_kind             DCEM_MEM_HOST or DCEM_MEM_DEVICE for all arrays
+ * Limits: n_tris < 2^31 - 1, n_faces < 2^20, n_objects < 2^16. */
+typedef struct dcem_scene_desc {
+  const float* vertices;
+  int64_t n_vertices;
+  const int32_t* tris;
+  const int32_t* tri_face;
+  int64_t n_tris;
+  const int32_t* face_material;
+  const int32_t* face_object;
+  int32_t n_faces;
+  const double* materials;
+  int32_t n_materials;
+  const int64_t* object_vertex_range;
+  int32_t n_objects;
+  int32_t mem_kind;
+} dcem_scene_desc;
+
+/* One frame of tracing.
+ *  tx_pos [n_tx][3], rx_pos [n_rx][3] FP32 (mem_kind); rx_radius: capture
+ *  sphere radius (closed ball, transparent).
+ *  n_rays: rays per transmitter; ray_dirs [n_rays][3] FP32 (mem_kind) or NULL
+ *  for a Fibonacci sphere: z_i = 1 - (2i+1)/n, phi_i = i * pi * (3 - sqrt 5),
+ *  evaluated in FP64 and rounded to FP32 (paper: "a sphere of sampled rays").
+ *  max_reflections: 0..DCEM_MAX_REFLECTIONS.
+ *  freqs_hz [n_freqs] FP64, host memory.  tx_power_w: transmit power;
+ *  atten_db_per_km: Eq. (3)'s atmospheric term as a specific attenuation.
+ *  mode: DCEM_MODE_FULL or DCEM_MODE_COHERENT.  COHERENT reuses the cached
+ *  rays of the previous frame traced with the same transmitters, receivers,
+ *  rays and max_reflections (falls back to FULL otherwise).
+ *  los_always: 1 adds the direct path of every (tx, rx) pair as a candidate
+ *  (direct rays are their own mechanism, Sec. III); 0 keeps only captured ones.
+ *  keep_cache: 1 stores the per-ray segments needed by the next COHERENT
+ *  frame (COHERENT implies it).
+ *  record_trace_log: 1 stores per (tx, ray, bounce) the hit triangle, its
+ *  distance and the cumulative path length (see dcem_get_trace_log).
+ *  Antennas are ideal and omnidirectional (Sec. III); the transmitter is
+ *  vertically polarised (theta-hat of the departure direction) and the
+ *  receiver is polarisation-agnostic. */
+typedef struct dcem_trace_params {
+  const float* tx_pos;
+  int32_t n_tx;
+  const float* rx_pos;
+  int32_t n_rx;
+  float rx_radius;
+  int64_t n_rays;
+  const float* ray_dirs;
+  int32_t max_reflections;
+  const double* freqs_hz;
+  int32_t n_freqs;
+  double tx_power_w;
+  double atten_db_per_km;
+  int32_t mode;
+  int32_t los_always;
+  int32_t keep_cache;
+  int32_t record_trace_log;
+  int32_t mem_kind;
+} dcem_trace_params;
+
+/* Counters and timings of the last dcem_refit_bvh + dcem_trace_frame. */
+typedef struct dcem_frame_stats {
+  int64_t rays_total;        /* n_tx * n_rays */
+  int64_t rays_traced;       /* rays actually traced this frame */
+  int64_t rays_reused;       /* rays whose cached result was reused */
+  int64_t segments;          /* closest-hit queries executed */
+  int64_t captures;          /* capture records (reused + new) */
+  int64_t unique_candidates; /* unique (tx, rx, order, faces) keys */
+  int64_t valid_paths;
+  int32_t rebuilt;           /* last dcem_refit_bvh rebuilt the tree */
+  int32_t coherent;          /* this frame reused the cache */
+  double sah_ratio;          /* SAH cost of the tree relative to its last build */
+  float ms_refit, ms_coherence, ms_trace, ms_candidates, ms_refine, ms_reduce;
+} dcem_frame_stats;
+
+/* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream). */
+dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream);
+void dcem_destroy(dcem_ctx* ctx);
+/* Human-readable description of the last failure on ctx ("" if none). */
+const char* dcem_last_error(const dcem_ctx* ctx);
+/* Capacity of the capture buffer (default 1<<22 records).  Overflow sets
+ * DCEM_ERR_CAPTURES. */
+dcem_status dcem_set_capture_capacity(dcem_ctx* ctx, int64_t max_captures);
+/* Enable per-stage HIP event timings in dcem_frame_stats (default off). */
+dcem_status dcem_set_timing(dcem_ctx* ctx, int32_t enabled);
+
+/* Copy the scene to the device and build its LBVH (paper Sec. III: the BVH
+ * over the environment's triangles).  Replaces any previous scene and drops
+ * the ray cache.  Validates indices and finiteness on the host (host inputs)
+ * and returns DCEM_E_INVALID_ARG on a violation. */
+dcem_status dcem_scene_upload(dcem_ctx* ctx, const dcem_scene_desc* scene);
+
+/* Place the moving objects for the next frame (paper Sec. III: objects move
+ * between frames).  xf [n_objects][3][4] row-major FP32 object-to-world
+ * transforms applied to the upload pose: x' = R x + t, evaluated with exact
+ * FP32 products summed left to right in FP64 and rounded to FP32. */
+dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n_objects,
+                                       int32_t mem_kind);
+
+/* Bring the BVH up to date with the current vertices (paper Sec. III,
+ * "Efficient BVH updating"): refit the node boxes bottom-up over the fixed
+ * topology, measure quality as the SAH surface-area sum relative to the last
+ * build, and rebuild when it exceeds rebuild_threshold (<= 0 selects 1.5;
+ * +inf never rebuilds) or when flags has DCEM_FORCE_REBUILD.
+ * rebuilt / sah_ratio (nullable, host) receive the decision and the ratio
+ * (1.0 right after a rebuild).  Synchronises the stream. */
+dcem_status dcem_refit_bvh(dcem_ctx* ctx, int32_t flags, double rebuild_threshold,
+                           int32_t* rebuilt, double* sah_ratio);
+
+/* Trace one frame (asynchronous on the context stream). */
+dcem_status dcem_trace_frame(dcem_ctx* ctx, const dcem_trace_params* params);
+
+/* Received power of the last frame, [n_freqs][n_tx][n_rx] FP64 watts:
+ * p_coh = sum over field components of |sum over valid paths of a_p|^2
+ * (phase-coherent), p_incoh (nullable) = sum over paths of |a_p|^2.  Paths
+ * are summed in key order, so results are bitwise reproducible.  Waits for
+ * the frame and reports any device error. */
+dcem_status dcem_received_power(dcem_ctx* ctx, double* p_coh, double* p_incoh, int32_t mem_kind);
+
+/* Paths of the last frame in key order (tx, rx, order, faces), host memory.
+ * keys [cap][3 + K] int32 (faces padded with -1, K = max_reflections),
+ * valid [cap], length [cap] (m), tau [cap] (s), aod/aoa [cap][3] unit vectors
+ * (departure direction at the transmitter; direction from the receiver
+ * towards the last path point), amp [cap][n_freqs][3][2] complex field vector
+ * (re, im) whose squared norm is the path's received power, first_ray [cap]
+ * (lowest ray index tx * n_rays + i that captured it, -1 for a direct path
+ * added by los_always).  Any output pointer may be NULL.  n_out receives the
+ * number of paths; at most cap are written. */
+dcem_status dcem_get_paths(dcem_ctx* ctx, int64_t cap, int32_t* keys, uint8_t* valid, double* length,
+                           double* tau, double* aod, double* aoa, double* amp, int32_t* first_ray,
+                           int64_t* n_out);
+
+/* Per (tx, ray, bounce) log of the last frame ([n_tx][n_rays][K+1], host):
+ * tri = hit triangle (-1 miss, -2 not reached), t = hit distance along the
+ * (unnormalised) direction, length = cumulative path length at the hit.
+ * Requires record_trace_log = 1.  Any pointer may be NULL. */
+dcem_status dcem_get_trace_log(dcem_ctx* ctx, int32_t* tri, float* t, float* length);
+
+/* Raw capture records of the last frame (host): rows [cap][4 + K] =
+ * (ray, tx, rx, order, faces... padded -1), in key order then ray order. */
+dcem_status dcem_get_captures(dcem_ctx* ctx, int64_t cap, int32_t* rows, int64_t* n_out);
+
+/* Current BVH (host): n_internal nodes; child [n][2] (>= 0 internal node,
+ * < 0 leaf ~child); box [n][2][6] child boxes (lo xyz, hi xyz); leaf_tri
+ * [n_tris] triangle index of each leaf.  Pointers may be NULL to query
+ * n_internal. */
+dcem_status dcem_get_bvh(dcem_ctx* ctx, int64_t cap_internal, int32_t* n_internal, int32_t* child,
+                         float* box, int32_t* leaf_tri);
+
+/* Current world-space vertices [n_vertices][3] (host). */
+dcem_status dcem_get_vertices(dcem_ctx* ctx, float* out);
+
+/* Ray directions of the last frame [n_rays][3] (host). */
+dcem_status dcem_get_ray_dirs(dcem_ctx* ctx, float* out);
+
+dcem_status dcem_get_stats(dcem_ctx* ctx, dcem_frame_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCEM_H */

@@ -1,0 +1,683 @@
+// Host side of the C ABI: argument checks, device buffers, call order and the
+// per-frame schedule of kernels on the context's stream.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+
+#include "dcem_internal.h"
+
+using namespace dcem;
+
+namespace dcem {
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes && b.p) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.bytes = want;
+  return hipSuccess;
+}
+
+void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+}  // namespace dcem
+
+namespace {
+
+dcem_status fail(dcem_ctx* c, dcem_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+dcem_status fail(dcem_ctx* c, dcem_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+dcem_status hip_fail(dcem_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? DCEM_E_OUT_OF_MEMORY : DCEM_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(c, e_, what); \
+  } while (0)
+
+// Copy n elements of T from caller memory (host or device) into a host vector.
+template <class T>
+hipError_t fetch(std::vector<T>& out, const T* src, size_t n, int mem_kind, hipStream_t s) {
+  out.resize(n);
+  if (n == 0) return hipSuccess;
+  if (mem_kind == DCEM_MEM_DEVICE) {
+    hipError_t e = hipMemcpyAsync(out.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  }
+  std::memcpy(out.data(), src, n * sizeof(T));
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  hipError_t e = ensure(b, std::max<size_t>(v.size() * sizeof(T), 16));
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+bool mem_kind_ok(int k) { return k == DCEM_MEM_HOST || k == DCEM_MEM_DEVICE; }
+
+void ev_record(dcem_ctx* c, int i) {
+  if (c->timing) (void)hipEventRecord(c->ev[i], c->stream);
+}
+
+float ev_ms(dcem_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (c->timing && hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) == hipSuccess) return ms;
+  return 0.f;
+}
+
+dcem_status check_device_error(dcem_ctx* c) {
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, c->err_word.p, 4, hipMemcpyDeviceToHost, c->stream), "read error word");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  if (err) {
+    HIP_TRY(hipMemsetAsync(c->err_word.p, 0, 4, c->stream), "clear error word");
+    if (err & DCEM_ERR_NONFINITE) return fail(c, DCEM_E_INVALID_ARG, "non-finite vertex after a transform");
+    return fail(c, DCEM_E_CAPACITY, "device capacity exceeded (%s%s)",
+                (err & DCEM_ERR_STACK) ? "traversal stack " : "", (err & DCEM_ERR_CAPTURES) ? "capture buffer" : "");
+  }
+  return DCEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return DCEM_E_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DCEM_E_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return DCEM_E_DEVICE;
+  dcem_ctx* c = new dcem_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (ensure(c->counters, sizeof(uint32_t) * 64) != hipSuccess || ensure(c->err_word, 256) != hipSuccess) {
+    delete c;
+    return DCEM_E_OUT_OF_MEMORY;
+  }
+  if (hipMemsetAsync(c->counters.p, 0, sizeof(uint32_t) * 64, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->err_word.p, 0, 256, c->stream) != hipSuccess) {
+    delete c;
+    return DCEM_E_DEVICE;
+  }
+  for (auto& e : c->ev) (void)hipEventCreate(&e);
+  *out = c;
+  return DCEM_OK;
+}
+
+void dcem_destroy(dcem_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
+                    &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
+                    &c->obj_box, &c->face_plane, &c->nodes, &c->leaves, &c->leaf_tri, &c->leaf_parent,
+                    &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
+                    &c->rx_pos, &c->freqs, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
+                    &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
+                    &c->counters, &c->err_word, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
+                    &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
+                    &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist};
+  for (DevBuf* b : bufs) release(*b);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* dcem_last_error(const dcem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+dcem_status dcem_set_capture_capacity(dcem_ctx* c, int64_t max_captures) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  if (max_captures < 1 || max_captures > (int64_t(1) << 31))
+    return fail(c, DCEM_E_INVALID_ARG, "capture capacity must be in [1, 2^31]");
+  c->cap_capacity = max_captures;
+  c->cache_valid = false;
+  return DCEM_OK;
+}
+
+dcem_status dcem_set_timing(dcem_ctx* c, int32_t enabled) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->timing = enabled != 0;
+  return DCEM_OK;
+}
+
+dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!s) return fail(c, DCEM_E_INVALID_ARG, "null scene");
+  if (!mem_kind_ok(s->mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad mem_kind");
+  if (s->n_vertices < 0 || s->n_tris < 0 || s->n_faces < 0 || s->n_materials < 0 || s->n_objects < 0)
+    return fail(c, DCEM_E_INVALID_ARG, "negative size");
+  if (s->n_tris >= (int64_t(1) << 31) - 1 || s->n_vertices >= (int64_t(1) << 31))
+    return fail(c, DCEM_E_UNSUPPORTED, "too many triangles or vertices");
+  if (s->n_faces >= (1 << 20)) return fail(c, DCEM_E_UNSUPPORTED, "at most 2^20 - 1 faces");
+  if (s->n_objects >= (1 << 16)) return fail(c, DCEM_E_UNSUPPORTED, "at most 2^16 - 1 objects");
+  if (s->n_tris > 0 && s->n_faces == 0) return fail(c, DCEM_E_INVALID_ARG, "triangles without faces");
+  if (s->n_faces > 0 && s->n_materials == 0) return fail(c, DCEM_E_INVALID_ARG, "faces without materials");
+  if ((s->n_vertices && !s->vertices) || (s->n_tris && (!s->tris || !s->tri_face)) ||
+      (s->n_faces && (!s->face_material || !s->face_object)) || (s->n_materials && !s->materials) ||
+      (s->n_objects && !s->object_vertex_range))
+    return fail(c, DCEM_E_INVALID_ARG, "null array with nonzero size");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  std::vector<float> V;
+  std::vector<int32_t> T, TF, FM, FO;
+  std::vector<double> M;
+  std::vector<int64_t> OR;
+  HIP_TRY(fetch(V, s->vertices, 3 * (size_t)s->n_vertices, s->mem_kind, c->stream), "read vertices");
+  HIP_TRY(fetch(T, s->tris, 3 * (size_t)s->n_tris, s->mem_kind, c->stream), "read tris");
+  HIP_TRY(fetch(TF, s->tri_face, (size_t)s->n_tris, s->mem_kind, c->stream), "read tri_face");
+  HIP_TRY(fetch(FM, s->face_material, (size_t)s->n_faces, s->mem_kind, c->stream), "read face_material");
+  HIP_TRY(fetch(FO, s->face_object, (size_t)s->n_faces, s->mem_kind, c->stream), "read face_object");
+  HIP_TRY(fetch(M, s->materials, 3 * (size_t)s->n_materials, s->mem_kind, c->stream), "read materials");
+  HIP_TRY(fetch(OR, s->object_vertex_range, 2 * (size_t)s->n_objects, s->mem_kind, c->stream), "read objects");
+  double R = 0.0;
+  for (size_t i = 0; i < V.size(); ++i) {
+    if (!std::isfinite(V[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite vertex coordinate %zu", i / 3);
+    R = std::max(R, (double)std::fabs(V[i]));
+  }
+  for (size_t i = 0; i < T.size(); ++i)
+    if (T[i] < 0 || T[i] >= s->n_vertices) return fail(c, DCEM_E_INVALID_ARG, "triangle %zu: vertex index out of range", i / 3);
+  for (size_t i = 0; i < TF.size(); ++i)
+    if (TF[i] < 0 || TF[i] >= s->n_faces) return fail(c, DCEM_E_INVALID_ARG, "triangle %zu: face out of range", i);
+  for (int32_t f = 0; f < s->n_faces; ++f) {
+    if (FM[f] < 0 || FM[f] >= s->n_materials) return fail(c, DCEM_E_INVALID_ARG, "face %d: material out of range", f);
+    if (FO[f] < -1 || FO[f] >= s->n_objects) return fail(c, DCEM_E_INVALID_ARG, "face %d: object out of range", f);
+  }
+  for (int32_t m = 0; m < s->n_materials; ++m) {
+    const double er = M[3 * m], sg = M[3 * m + 1], g = M[3 * m + 2];
+    if (!std::isfinite(er) || !std::isfinite(sg) || er < 1.0 || sg < 0.0 || (!std::isnan(g) && !(g >= 0.0 && g <= 1.0)))
+      return fail(c, DCEM_E_INVALID_ARG, "material %d: need eps_r >= 1, sigma >= 0, const_gamma in [0,1] or NaN", m);
+  }
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  for (int32_t o = 0; o < s->n_objects; ++o) {
+    const int64_t b = OR[2 * o], e = OR[2 * o + 1];
+    if (b < 0 || e < b || e > s->n_vertices) return fail(c, DCEM_E_INVALID_ARG, "object %d: bad vertex range", o);
+    ranges.push_back({b, e});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second) return fail(c, DCEM_E_INVALID_ARG, "object vertex ranges overlap");
+  // faces: triangle lists (CSR) and the largest triangle (plane reference)
+  const int nf = s->n_faces;
+  std::vector<int32_t> off(nf + 1, 0), ftris(T.size() / 3), ref(nf, -1);
+  std::vector<double> best(nf, -1.0);
+  for (size_t t = 0; t < TF.size(); ++t) off[TF[t] + 1]++;
+  for (int f = 0; f < nf; ++f) off[f + 1] += off[f];
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (size_t t = 0; t < TF.size(); ++t) {
+      const int f = TF[t];
+      ftris[fill[f]++] = (int32_t)t;
+      const float* a = &V[3 * T[3 * t]];
+      const float* b = &V[3 * T[3 * t + 1]];
+      const float* cc = &V[3 * T[3 * t + 2]];
+      const double ux = b[0] - (double)a[0], uy = b[1] - (double)a[1], uz = b[2] - (double)a[2];
+      const double vx = cc[0] - (double)a[0], vy = cc[1] - (double)a[1], vz = cc[2] - (double)a[2];
+      const double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+      const double ar = std::sqrt(nx * nx + ny * ny + nz * nz);
+      if (ar > best[f]) {
+        best[f] = ar;
+        ref[f] = (int32_t)t;
+      }
+    }
+  }
+  for (int f = 0; f < nf; ++f) {
+    if (ref[f] < 0) return fail(c, DCEM_E_INVALID_ARG, "face %d has no triangle", f);
+    if (!(best[f] > 0.0)) return fail(c, DCEM_E_INVALID_ARG, "face %d has only degenerate triangles", f);
+  }
+  c->nv = s->n_vertices;
+  c->nt = s->n_tris;
+  c->nf = nf;
+  c->nm = s->n_materials;
+  c->no = s->n_objects;
+  c->pad = (float)(4e-6 * (2.0 * R + 1.0));
+  c->h_face_object = FO;
+  HIP_TRY(upload(c->ref_vertices, V, c->stream), "upload vertices");
+  HIP_TRY(upload(c->vertices, V, c->stream), "upload vertices");
+  HIP_TRY(upload(c->tris, T, c->stream), "upload tris");
+  HIP_TRY(upload(c->tri_face, TF, c->stream), "upload tri_face");
+  HIP_TRY(upload(c->face_material, FM, c->stream), "upload face_material");
+  HIP_TRY(upload(c->face_object, FO, c->stream), "upload face_object");
+  HIP_TRY(upload(c->materials, M, c->stream), "upload materials");
+  HIP_TRY(upload(c->obj_range, OR, c->stream), "upload objects");
+  HIP_TRY(upload(c->face_tri_off, off, c->stream), "upload faces");
+  HIP_TRY(upload(c->face_tris, ftris, c->stream), "upload faces");
+  HIP_TRY(upload(c->face_ref_tri, ref, c->stream), "upload faces");
+  HIP_TRY(ensure(c->face_plane, sizeof(double) * 4 * std::max(nf, 1)), "alloc planes");
+  std::vector<float> ident(12 * (size_t)c->no, 0.f);
+  for (int o = 0; o < c->no; ++o) ident[12 * o] = ident[12 * o + 5] = ident[12 * o + 10] = 1.f;
+  HIP_TRY(upload(c->xf, ident, c->stream), "upload transforms");
+  HIP_TRY(ensure(c->obj_box, sizeof(float) * 6 * std::max(c->no, 1)), "alloc object boxes");
+  launch_xform(c);
+  HIP_TRY(hipGetLastError(), "transform kernel");
+  HIP_TRY(build_lbvh(c), "build BVH");
+  c->has_scene = true;
+  c->cache_valid = false;
+  c->has_frame = false;
+  c->bvh_stale = false;
+  c->sah_last = 1.0;
+  c->last_rebuilt = 1;
+  return check_device_error(c);
+}
+
+dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_objects, int32_t mem_kind) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  if (n_objects != c->no) return fail(c, DCEM_E_INVALID_ARG, "scene has %d objects, got %d", c->no, n_objects);
+  if (!mem_kind_ok(mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad mem_kind");
+  if (n_objects == 0) return DCEM_OK;
+  if (!xf) return fail(c, DCEM_E_INVALID_ARG, "null transforms");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (mem_kind == DCEM_MEM_HOST) {
+    for (int i = 0; i < 12 * n_objects; ++i)
+      if (!std::isfinite(xf[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite transform entry %d", i);
+    HIP_TRY(hipMemcpyAsync(c->xf.p, xf, sizeof(float) * 12 * n_objects, hipMemcpyHostToDevice, c->stream), "copy xf");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  } else {
+    HIP_TRY(hipMemcpyAsync(c->xf.p, xf, sizeof(float) * 12 * n_objects, hipMemcpyDeviceToDevice, c->stream), "copy xf");
+  }
+  launch_xform(c);
+  HIP_TRY(hipGetLastError(), "transform kernel");
+  c->bvh_stale = true;
+  return DCEM_OK;
+}
+
+dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t* rebuilt, double* sah_ratio) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  if (std::isnan(threshold)) return fail(c, DCEM_E_INVALID_ARG, "threshold is NaN");
+  if (threshold <= 0.0) threshold = 1.5;
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  ev_record(c, 6);
+  int32_t rb = 0;
+  double ratio = 1.0;
+  if (flags & DCEM_FORCE_REBUILD) {
+    HIP_TRY(build_lbvh(c), "rebuild BVH");
+    rb = 1;
+  } else {
+    launch_refit(c);
+    HIP_TRY(hipGetLastError(), "refit kernel");
+    double sah = 1.0;
+    HIP_TRY(compute_sah(c, &sah), "SAH");
+    ratio = c->sah_build > 0 ? sah / c->sah_build : 1.0;
+    if (ratio > threshold) {
+      HIP_TRY(build_lbvh(c), "rebuild BVH");
+      rb = 1;
+      ratio = 1.0;
+    }
+  }
+  ev_record(c, 7);
+  c->bvh_stale = false;
+  c->last_rebuilt = rb;
+  c->sah_last = ratio;
+  if (rebuilt) *rebuilt = rb;
+  if (sah_ratio) *sah_ratio = ratio;
+  dcem_status st = check_device_error(c);
+  c->stats.ms_refit = ev_ms(c, 6, 7);
+  return st;
+}
+
+dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  if (c->bvh_stale) return fail(c, DCEM_E_STATE, "objects moved: call dcem_refit_bvh before tracing");
+  if (!p) return fail(c, DCEM_E_INVALID_ARG, "null params");
+  if (!mem_kind_ok(p->mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad mem_kind");
+  if (p->n_tx < 1 || p->n_rx < 1 || !p->tx_pos || !p->rx_pos) return fail(c, DCEM_E_INVALID_ARG, "need >= 1 tx and rx");
+  if (p->n_rays < 0) return fail(c, DCEM_E_INVALID_ARG, "negative ray count");
+  if (p->max_reflections < 0 || p->max_reflections > DCEM_MAX_REFLECTIONS)
+    return fail(c, DCEM_E_INVALID_ARG, "max_reflections must be in [0, %d]", DCEM_MAX_REFLECTIONS);
+  if (p->n_freqs < 1 || p->n_freqs > 64 || !p->freqs_hz) return fail(c, DCEM_E_INVALID_ARG, "need 1..64 frequencies");
+  for (int i = 0; i < p->n_freqs; ++i)
+    if (!(p->freqs_hz[i] > 0.0) || !std::isfinite(p->freqs_hz[i])) return fail(c, DCEM_E_INVALID_ARG, "bad frequency");
+  if (!(p->rx_radius >= 0.0f) || !std::isfinite(p->rx_radius)) return fail(c, DCEM_E_INVALID_ARG, "bad rx_radius");
+  if (!(p->tx_power_w >= 0.0) || !std::isfinite(p->tx_power_w)) return fail(c, DCEM_E_INVALID_ARG, "bad tx_power_w");
+  if (!std::isfinite(p->atten_db_per_km)) return fail(c, DCEM_E_INVALID_ARG, "bad atten_db_per_km");
+  if (p->mode != DCEM_MODE_FULL && p->mode != DCEM_MODE_COHERENT) return fail(c, DCEM_E_INVALID_ARG, "bad mode");
+  const int64_t n_work = (int64_t)p->n_tx * p->n_rays;
+  if (n_work >= (int64_t(1) << 31) - 1) return fail(c, DCEM_E_UNSUPPORTED, "n_tx * n_rays must be < 2^31 - 1");
+  if ((int64_t)p->n_tx * p->n_rx >= (int64_t(1) << 27)) return fail(c, DCEM_E_UNSUPPORTED, "too many tx x rx pairs");
+  {
+    int bt = 0, br = 0, bf = 0;
+    while ((int64_t(1) << bt) < p->n_tx) ++bt;
+    while ((int64_t(1) << br) < p->n_rx) ++br;
+    while ((int64_t(1) << bf) < c->nf) ++bf;
+    if (bt + br + 4 + p->max_reflections * std::max(bf, 1) > 256)
+      return fail(c, DCEM_E_UNSUPPORTED, "candidate key exceeds 256 bits");
+  }
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  // -- configuration and cache applicability
+  std::vector<float> txh, rxh;
+  HIP_TRY(fetch(txh, p->tx_pos, 3 * (size_t)p->n_tx, p->mem_kind, c->stream), "read tx");
+  HIP_TRY(fetch(rxh, p->rx_pos, 3 * (size_t)p->n_rx, p->mem_kind, c->stream), "read rx");
+  for (float v : txh) if (!std::isfinite(v)) return fail(c, DCEM_E_INVALID_ARG, "non-finite tx position");
+  for (float v : rxh) if (!std::isfinite(v)) return fail(c, DCEM_E_INVALID_ARG, "non-finite rx position");
+  const bool fib = p->ray_dirs == nullptr;
+  std::vector<float> dirh;
+  if (!fib && p->mem_kind == DCEM_MEM_HOST) {
+    dirh.assign(p->ray_dirs, p->ray_dirs + 3 * (size_t)p->n_rays);
+    for (float v : dirh) if (!std::isfinite(v)) return fail(c, DCEM_E_INVALID_ARG, "non-finite ray direction");
+  }
+  TraceConfig& cfg = c->cfg;
+  const bool same = cfg.n_tx == p->n_tx && cfg.n_rx == p->n_rx && cfg.K == p->max_reflections &&
+                    cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius && cfg.tx == txh && cfg.rx == rxh &&
+                    cfg.dirs_fib == fib &&
+                    (fib || (p->mem_kind == DCEM_MEM_HOST ? cfg.dirs_host == dirh : cfg.dirs_ptr == p->ray_dirs));
+  const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same;
+  const bool keep_cache = p->keep_cache != 0 || p->mode == DCEM_MODE_COHERENT;
+  // -- device inputs
+  const bool need_dirs = !same || !c->has_frame;
+  cfg.n_tx = p->n_tx;
+  cfg.n_rx = p->n_rx;
+  cfg.K = p->max_reflections;
+  cfg.n_rays = p->n_rays;
+  cfg.rx_radius = p->rx_radius;
+  cfg.tx = txh;
+  cfg.rx = rxh;
+  cfg.dirs_fib = fib;
+  cfg.dirs_ptr = p->ray_dirs;
+  cfg.dirs_host = dirh;
+  c->n_tx = p->n_tx;
+  c->n_rx = p->n_rx;
+  c->n_rays = p->n_rays;
+  c->K = p->max_reflections;
+  c->n_freqs = p->n_freqs;
+  c->sqrt_pt = std::sqrt(p->tx_power_w);
+  c->atten_db_per_km = p->atten_db_per_km;
+  c->record_log = p->record_trace_log != 0;
+  HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
+  HIP_TRY(upload(c->rx_pos, rxh, c->stream), "upload rx");
+  HIP_TRY(upload(c->freqs, std::vector<double>(p->freqs_hz, p->freqs_hz + p->n_freqs), c->stream), "upload freqs");
+  if (need_dirs) {
+    HIP_TRY(ensure(c->dirs, sizeof(float) * 3 * std::max<int64_t>(p->n_rays, 1)), "alloc dirs");
+    if (fib) {
+      if (p->n_rays > 0) launch_fibonacci(c);
+    } else if (p->mem_kind == DCEM_MEM_HOST) {
+      HIP_TRY(upload(c->dirs, dirh, c->stream), "upload dirs");
+    } else if (p->n_rays > 0) {
+      HIP_TRY(hipMemcpyAsync(c->dirs.p, p->ray_dirs, sizeof(float) * 3 * p->n_rays, hipMemcpyDeviceToDevice, c->stream),
+              "copy dirs");
+    }
+  }
+  const size_t nw = (size_t)std::max<int64_t>(n_work, 1), K1 = (size_t)p->max_reflections + 1;
+  HIP_TRY(ensure(c->face_log, sizeof(int32_t) * K1 * nw), "alloc face log");
+  HIP_TRY(ensure(c->ray_state, nw), "alloc ray state");
+  if (keep_cache) {
+    HIP_TRY(ensure(c->seg_o, sizeof(float4) * K1 * nw), "alloc segment log");
+    HIP_TRY(ensure(c->seg_d, sizeof(float4) * K1 * nw), "alloc segment log");
+  }
+  if (c->record_log) {
+    HIP_TRY(ensure(c->log_tri, sizeof(int32_t) * K1 * nw), "alloc trace log");
+    HIP_TRY(ensure(c->log_t, sizeof(float) * K1 * nw), "alloc trace log");
+    HIP_TRY(ensure(c->log_len, sizeof(float) * K1 * nw), "alloc trace log");
+  }
+  HIP_TRY(ensure(c->caps[0], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
+  HIP_TRY(ensure(c->caps[1], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
+  HIP_TRY(ensure(c->work_list, sizeof(uint32_t) * nw), "alloc work list");
+  HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
+  HIP_TRY(ensure(c->p_coh, sizeof(double) * p->n_freqs * p->n_tx * p->n_rx), "alloc power");
+  HIP_TRY(ensure(c->p_inc, sizeof(double) * p->n_freqs * p->n_tx * p->n_rx), "alloc power");
+  // -- schedule
+  ev_record(c, 0);
+  const uint32_t n_prev = (uint32_t)c->n_caps_host;
+  launch_reset_counters(c);
+  c->cur_caps ^= 1;
+  if (coherent) {
+    launch_coherence(c, n_prev);
+  }
+  ev_record(c, 1);
+  if (n_work > 0) launch_trace(c, !coherent, keep_cache, n_work);
+  if (p->los_always) launch_los(c);
+  HIP_TRY(hipGetLastError(), "trace kernels");
+  ev_record(c, 2);
+  launch_face_planes(c);
+  HIP_TRY(build_candidates(c), "candidates");
+  ev_record(c, 3);
+  HIP_TRY(ensure_paths(c, c->n_caps_host), "alloc paths");
+  launch_refine(c);
+  ev_record(c, 4);
+  launch_reduce(c);
+  ev_record(c, 5);
+  HIP_TRY(hipGetLastError(), "refine kernels");
+  c->cache_valid = keep_cache;
+  c->has_frame = true;
+  c->stats.coherent = coherent ? 1 : 0;
+  c->stats.rays_total = n_work;
+  return DCEM_OK;
+}
+
+dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32_t mem_kind) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  if (!p_coh || !mem_kind_ok(mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad output");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  const size_t bytes = sizeof(double) * c->n_freqs * c->n_tx * c->n_rx;
+  const hipMemcpyKind kind = mem_kind == DCEM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HIP_TRY(hipMemcpyAsync(p_coh, c->p_coh.p, bytes, kind, c->stream), "copy power");
+  if (p_inc) HIP_TRY(hipMemcpyAsync(p_inc, c->p_inc.p, bytes, kind, c->stream), "copy power");
+  return check_device_error(c);
+}
+
+dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
+  if (!c || !out) return DCEM_E_INVALID_ARG;
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  uint32_t cnt[kCntSlots];
+  HIP_TRY(hipMemcpyAsync(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost, c->stream), "read counters");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  dcem_frame_stats& s = c->stats;
+  s.rays_traced = s.coherent ? (int64_t)cnt[kCntWork] : s.rays_total;
+  s.rays_reused = s.rays_total - s.rays_traced;
+  s.segments = cnt[kCntSegments];
+  s.captures = c->n_caps_host;
+  s.unique_candidates = cnt[kCntUnique];
+  s.valid_paths = cnt[kCntValid];
+  s.rebuilt = c->last_rebuilt;
+  s.sah_ratio = c->sah_last;
+  s.ms_coherence = ev_ms(c, 0, 1);
+  s.ms_trace = ev_ms(c, 1, 2);
+  s.ms_candidates = ev_ms(c, 2, 3);
+  s.ms_refine = ev_ms(c, 3, 4);
+  s.ms_reduce = ev_ms(c, 4, 5);
+  *out = s;
+  return check_device_error(c);
+}
+
+dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* valid, double* length, double* tau,
+                           double* aod, double* aoa, double* amp, int32_t* first_ray, int64_t* n_out) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  dcem_status st = check_device_error(c);
+  if (st != DCEM_OK) return st;
+  uint32_t nu = 0;
+  if (c->n_caps_host > 0) {
+    HIP_TRY(hipMemcpy(&nu, ptr<uint32_t>(c->counters) + kCntUnique, 4, hipMemcpyDeviceToHost), "read count");
+  }
+  if (n_out) *n_out = nu;
+  const int64_t n = std::min<int64_t>(nu, cap);
+  if (n == 0) return DCEM_OK;
+  auto get = [&](void* dst, DevBuf& b, size_t bytes) -> hipError_t {
+    if (!dst) return hipSuccess;
+    return hipMemcpy(dst, b.p, bytes, hipMemcpyDeviceToHost);
+  };
+  HIP_TRY(get(valid, c->path_valid, n), "copy valid");
+  HIP_TRY(get(length, c->path_len, 8 * n), "copy length");
+  HIP_TRY(get(tau, c->path_tau, 8 * n), "copy tau");
+  HIP_TRY(get(aod, c->path_aod, 24 * n), "copy aod");
+  HIP_TRY(get(aoa, c->path_aoa, 24 * n), "copy aoa");
+  HIP_TRY(get(amp, c->path_amp, 48 * n * (size_t)c->n_freqs), "copy amp");
+  HIP_TRY(get(first_ray, c->first_ray, 4 * n), "copy first ray");
+  if (keys) {
+    const int64_t nc = c->n_caps_host;
+    const int W = c->key_words;
+    std::vector<uint32_t> kw((size_t)W * nc), perm(nc), pos(nu + 1);
+    HIP_TRY(hipMemcpy(kw.data(), c->cand_keys.p, 4 * kw.size(), hipMemcpyDeviceToHost), "copy keys");
+    HIP_TRY(hipMemcpy(perm.data(), c->cand_perm.p, 4 * perm.size(), hipMemcpyDeviceToHost), "copy perm");
+    HIP_TRY(hipMemcpy(pos.data(), c->uniq_idx.p, 4 * pos.size(), hipMemcpyDeviceToHost), "copy heads");
+    auto bits = [&](uint32_t idx, int at, int nb) {
+      uint32_t v = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int q = at + b;
+        const uint32_t word = kw[(size_t)(W - 1 - q / 32) * nc + idx];
+        v |= ((word >> (q % 32)) & 1u) << b;
+      }
+      return v;
+    };
+    const int K = c->K, bf = c->bits_face;
+    for (int64_t u = 0; u < n; ++u) {
+      const uint32_t idx = perm[pos[u]];
+      int32_t* row = keys + u * (3 + K);
+      int at = K * bf;
+      const int order = (int)bits(idx, at, 4);
+      at += 4;
+      row[1] = (int32_t)bits(idx, at, c->bits_rx);
+      at += c->bits_rx;
+      row[0] = (int32_t)bits(idx, at, c->bits_tx);
+      row[2] = order;
+      for (int j = 0; j < K; ++j) row[3 + j] = j < order ? (int32_t)bits(idx, (K - 1 - j) * bf, bf) : -1;
+    }
+  }
+  return DCEM_OK;
+}
+
+dcem_status dcem_get_trace_log(dcem_ctx* c, int32_t* tri, float* t, float* length) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  if (!c->record_log) return fail(c, DCEM_E_STATE, "trace log not recorded (record_trace_log = 0)");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  dcem_status st = check_device_error(c);
+  if (st != DCEM_OK) return st;
+  const size_t n = (size_t)c->n_tx * c->n_rays * (c->K + 1);
+  if (tri) HIP_TRY(hipMemcpy(tri, c->log_tri.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
+  if (t) HIP_TRY(hipMemcpy(t, c->log_t.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
+  if (length) HIP_TRY(hipMemcpy(length, c->log_len.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
+  return DCEM_OK;
+}
+
+dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* n_out) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  dcem_status st = check_device_error(c);
+  if (st != DCEM_OK) return st;
+  const int64_t nc = c->n_caps_host;
+  if (n_out) *n_out = nc;
+  if (!rows || nc == 0) return DCEM_OK;
+  std::vector<Capture> cp(nc);
+  HIP_TRY(hipMemcpy(cp.data(), c->caps[c->cur_caps].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
+  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int K = c->K;
+  std::vector<int32_t> flog((size_t)(K + 1) * std::max<int64_t>(n_work, 1));
+  if (n_work > 0)
+    HIP_TRY(hipMemcpy(flog.data(), c->face_log.p, 4 * flog.size(), hipMemcpyDeviceToHost), "copy face log");
+  std::vector<std::vector<int32_t>> out;
+  out.reserve(nc);
+  for (const Capture& x : cp) {
+    std::vector<int32_t> r(4 + K, -1);
+    const uint32_t pair = x.pair_order >> 4, order = x.pair_order & 15u;
+    r[0] = x.work == kNoRay ? -1 : (int32_t)x.work;
+    r[1] = (int32_t)(pair / c->n_rx);
+    r[2] = (int32_t)(pair % c->n_rx);
+    r[3] = (int32_t)order;
+    for (uint32_t j = 0; j < order; ++j) r[4 + j] = flog[(size_t)j * n_work + x.work];
+    out.push_back(std::move(r));
+  }
+  std::sort(out.begin(), out.end(), [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+    if (a[1] != b[1]) return a[1] < b[1];
+    if (a[2] != b[2]) return a[2] < b[2];
+    if (a[3] != b[3]) return a[3] < b[3];
+    for (size_t j = 4; j < a.size(); ++j)
+      if (a[j] != b[j]) return a[j] < b[j];
+    return a[0] < b[0];
+  });
+  const int64_t n = std::min<int64_t>(nc, cap);
+  for (int64_t i = 0; i < n; ++i) std::memcpy(rows + i * (4 + K), out[i].data(), sizeof(int32_t) * (4 + K));
+  return DCEM_OK;
+}
+
+dcem_status dcem_get_bvh(dcem_ctx* c, int64_t cap_internal, int32_t* n_internal, int32_t* child, float* box,
+                         int32_t* leaf_tri) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  const int32_t ni = c->nt > 0 ? c->n_internal : 0;
+  if (n_internal) *n_internal = ni;
+  if (ni == 0) return DCEM_OK;
+  if ((child || box) && cap_internal < ni) return fail(c, DCEM_E_INVALID_ARG, "capacity below node count");
+  std::vector<Node> nodes(ni);
+  HIP_TRY(hipMemcpy(nodes.data(), c->nodes.p, sizeof(Node) * ni, hipMemcpyDeviceToHost), "copy nodes");
+  for (int32_t i = 0; i < ni; ++i) {
+    if (child) {
+      child[2 * i] = nodes[i].c.x;
+      child[2 * i + 1] = nodes[i].c.y;
+    }
+    if (box) std::memcpy(box + 12 * i, &nodes[i], 12 * sizeof(float));
+  }
+  if (leaf_tri) HIP_TRY(hipMemcpy(leaf_tri, c->leaf_tri.p, 4 * c->nt, hipMemcpyDeviceToHost), "copy leaves");
+  return DCEM_OK;
+}
+
+dcem_status dcem_get_vertices(dcem_ctx* c, float* out) {
+  if (!c || !out) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  if (c->nv) HIP_TRY(hipMemcpy(out, c->vertices.p, sizeof(float) * 3 * c->nv, hipMemcpyDeviceToHost), "copy vertices");
+  return check_device_error(c);
+}
+
+dcem_status dcem_get_ray_dirs(dcem_ctx* c, float* out) {
+  if (!c || !out) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  if (c->n_rays) HIP_TRY(hipMemcpy(out, c->dirs.p, sizeof(float) * 3 * c->n_rays, hipMemcpyDeviceToHost), "copy dirs");
+  return DCEM_OK;
+}
+
+}  // extern "C"

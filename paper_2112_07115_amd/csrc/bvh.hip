@@ -1,0 +1,372 @@
+// Moving-object transforms, LBVH construction and bottom-up refit.
+//
+// The paper keeps a BVH over the scene and updates it every frame, rebuilding
+// only when its quality has degraded (Sec. III, "Efficient BVH updating").
+// Here the tree is a linear BVH (Morton-ordered triangles, hierarchy from the
+// longest common prefixes of the sorted codes, one thread per internal node),
+// refit bottom-up with arrival counters, and scored by the SAH surface-area
+// sum relative to the last build.
+#include "dcem_internal.h"
+
+#include <cfloat>
+
+namespace dcem {
+namespace {
+
+__device__ inline uint32_t ordered_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float from_ordered(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// x' = R x + t for one row: the FP32 x FP32 products are exact in FP64 and are
+// summed left to right, then rounded once to FP32.
+__device__ inline float xform_row(const float* m, float x, float y, float z) {
+  double r = (double)m[0] * (double)x;
+  r = r + (double)m[1] * (double)y;
+  r = r + (double)m[2] * (double)z;
+  r = r + (double)m[3];
+  return (float)r;
+}
+
+// One block per moving object: transform its vertex range and reduce its
+// world-space box (padded by `pad`, used by the coherence test).
+__global__ void k_xform(const float* __restrict__ ref, float* __restrict__ out,
+                        const int64_t* __restrict__ range, const float* __restrict__ xf,
+                        float* __restrict__ obj_box, float pad, uint32_t* err) {
+  const int o = blockIdx.x;
+  const int64_t b = range[2 * o], e = range[2 * o + 1];
+  const float* m = xf + 12 * o;
+  float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  bool bad = false;
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    float x = ref[3 * i], y = ref[3 * i + 1], z = ref[3 * i + 2];
+    float w[3] = {xform_row(m, x, y, z), xform_row(m + 4, x, y, z), xform_row(m + 8, x, y, z)};
+    for (int a = 0; a < 3; ++a) {
+      out[3 * i + a] = w[a];
+      lo[a] = fminf(lo[a], w[a]);
+      hi[a] = fmaxf(hi[a], w[a]);
+      bad |= !isfinite(w[a]);
+    }
+  }
+  if (bad) atomicOr(err, DCEM_ERR_NONFINITE);
+  __shared__ float red[6][256];
+  for (int a = 0; a < 3; ++a) {
+    red[a][threadIdx.x] = lo[a];
+    red[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) {
+    float v = red[threadIdx.x][0];
+    obj_box[6 * o + threadIdx.x] = threadIdx.x < 3 ? v - pad : v + pad;
+  }
+}
+
+__global__ void k_box_init(uint32_t* box) {
+  if (threadIdx.x < 3) box[threadIdx.x] = 0xffffffffu;
+  else if (threadIdx.x < 6) box[threadIdx.x] = 0u;
+}
+
+__device__ inline float3 load_v(const float* v, int i) { return make_float3(v[3 * i], v[3 * i + 1], v[3 * i + 2]); }
+
+// Bounds of the triangle centroids (exact min/max through order-preserving bits).
+__global__ void k_centroid_bounds(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
+                                  uint32_t* box) {
+  float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
+    float3 a = load_v(V, T[3 * i]), b = load_v(V, T[3 * i + 1]), c = load_v(V, T[3 * i + 2]);
+    float cx = (a.x + b.x + c.x) * (1.0f / 3.0f), cy = (a.y + b.y + c.y) * (1.0f / 3.0f),
+          cz = (a.z + b.z + c.z) * (1.0f / 3.0f);
+    lo[0] = fminf(lo[0], cx); lo[1] = fminf(lo[1], cy); lo[2] = fminf(lo[2], cz);
+    hi[0] = fmaxf(hi[0], cx); hi[1] = fmaxf(hi[1], cy); hi[2] = fmaxf(hi[2], cz);
+  }
+  // wave reduction, then one atomic per wave
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&box[a], ordered_bits(lo[a]));
+      atomicMax(&box[3 + a], ordered_bits(hi[a]));
+    }
+  }
+}
+
+__device__ inline uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 30-bit Morton code of each centroid inside the centroid bounds.
+__global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
+                         const uint32_t* __restrict__ box, uint32_t* __restrict__ code) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  float lo[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = from_ordered(box[a]);
+    float h = from_ordered(box[3 + a]);
+    ext[a] = h > lo[a] ? h - lo[a] : 1.0f;
+  }
+  float3 a = load_v(V, T[3 * i]), b = load_v(V, T[3 * i + 1]), c = load_v(V, T[3 * i + 2]);
+  float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
+                (a.z + b.z + c.z) * (1.0f / 3.0f)};
+  uint32_t q[3];
+  for (int k = 0; k < 3; ++k) {
+    float u = (p[k] - lo[k]) / ext[k];
+    u = fminf(fmaxf(u, 0.0f), 1.0f);
+    q[k] = (uint32_t)fminf(u * 1024.0f, 1023.0f);
+  }
+  code[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+}
+
+// Longest common prefix of sorted codes i and j (ties broken by index).
+__device__ inline int lcp(const uint32_t* __restrict__ code, const uint32_t* __restrict__ perm, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  uint32_t a = code[perm[i]], b = code[perm[j]];
+  if (a != b) return __clz(a ^ b);
+  return 32 + __clz((uint32_t)(i ^ j));
+}
+
+// Hierarchy from the sorted Morton codes, one thread per internal node
+// (Karras, "Maximizing parallelism in the construction of BVHs", 2012).
+__global__ void k_karras(const uint32_t* __restrict__ code, const uint32_t* __restrict__ perm, int n,
+                         Node* __restrict__ nodes, int32_t* __restrict__ leaf_parent,
+                         int32_t* __restrict__ leaf_tri) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) leaf_tri[i] = (int32_t)perm[i];
+  if (i >= n - 1) return;
+  int d = (lcp(code, perm, n, i, i + 1) - lcp(code, perm, n, i, i - 1)) >= 0 ? 1 : -1;
+  int dmin = lcp(code, perm, n, i, i - d);
+  int lmax = 2;
+  while (lcp(code, perm, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (lcp(code, perm, n, i, i + (l + t) * d) > dmin) l += t;
+  int j = i + l * d;
+  int dnode = lcp(code, perm, n, i, j);
+  int s = 0;
+  int t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (lcp(code, perm, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  int gamma = i + s * d + min(d, 0);
+  int lo = min(i, j), hi = max(i, j);
+  int left = (lo == gamma) ? ~gamma : gamma;
+  int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+  nodes[i].c.x = left;
+  nodes[i].c.y = right;
+  nodes[i].c.w = 0;
+  if (left < 0) leaf_parent[~left] = 2 * i;
+  else nodes[left].c.z = 2 * i;
+  if (right < 0) leaf_parent[~right] = 2 * i + 1;
+  else nodes[right].c.z = 2 * i + 1;
+  if (i == 0) nodes[0].c.z = -1;
+}
+
+__device__ inline void store_slot(Node* nd, int slot, const float* lo, const float* hi) {
+  float* f = reinterpret_cast<float*>(nd);
+  const int base = slot * 6;
+  f[base + 0] = lo[0]; f[base + 1] = lo[1]; f[base + 2] = lo[2];
+  f[base + 3] = hi[0]; f[base + 4] = hi[1]; f[base + 5] = hi[2];
+}
+
+__device__ inline void load_slot_coherent(Node* nd, int slot, float* lo, float* hi) {
+  float* f = reinterpret_cast<float*>(nd);
+  const int base = slot * 6;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Bottom-up refit over a fixed topology.  One thread per leaf writes the leaf
+// triangle record and its padded box into its parent's slot; the second thread
+// to arrive at a node (arrival counter) forms the union and climbs on.  The
+// counter is reset by that second thread, so the next refit needs no clearing.
+// Boxes are min/max of FP32 values: the result does not depend on the order.
+__global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__ T,
+                        const int32_t* __restrict__ tri_face, const int32_t* __restrict__ leaf_tri,
+                        const int32_t* __restrict__ leaf_parent, Node* __restrict__ nodes,
+                        Leaf* __restrict__ leaves, uint32_t* __restrict__ cnt, float* __restrict__ root_box,
+                        int n, float pad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int tri = leaf_tri[i];
+  float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
+  Leaf L;
+  L.v0 = make_float4(a.x, a.y, a.z, __int_as_float(tri));
+  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(tri_face[tri]));
+  L.v2 = make_float4(c.x, c.y, c.z, 0.0f);
+  leaves[i] = L;
+  float lo[3] = {fminf(a.x, fminf(b.x, c.x)) - pad, fminf(a.y, fminf(b.y, c.y)) - pad,
+                 fminf(a.z, fminf(b.z, c.z)) - pad};
+  float hi[3] = {fmaxf(a.x, fmaxf(b.x, c.x)) + pad, fmaxf(a.y, fmaxf(b.y, c.y)) + pad,
+                 fmaxf(a.z, fmaxf(b.z, c.z)) + pad};
+  if (n == 1) {
+    store_slot(&nodes[0], 0, lo, hi);
+    store_slot(&nodes[0], 1, lo, hi);
+    for (int k = 0; k < 3; ++k) { root_box[k] = lo[k]; root_box[3 + k] = hi[k]; }
+    return;
+  }
+  int p2 = leaf_parent[i];
+  for (int guard = n; guard > 0; --guard) {   // depth < n in a sound tree
+    const int node = p2 >> 1, slot = p2 & 1;
+    store_slot(&nodes[node], slot, lo, hi);
+    uint32_t old = __hip_atomic_fetch_add(&cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) return;
+    cnt[node] = 0;
+    float slo[3], shi[3];
+    load_slot_coherent(&nodes[node], slot ^ 1, slo, shi);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], slo[k]);
+      hi[k] = fmaxf(hi[k], shi[k]);
+    }
+    p2 = nodes[node].c.z;
+    if (p2 < 0) {
+      for (int k = 0; k < 3; ++k) { root_box[k] = lo[k]; root_box[3 + k] = hi[k]; }
+      return;
+    }
+  }
+}
+
+__device__ inline double box_area(const float* lo, const float* hi) {
+  double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+  return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+// Surface-area sum of the internal nodes below the root (each stored in its
+// parent's slot).  Per-block partial sums, combined in a fixed order.
+__global__ void k_sah_partial(const Node* __restrict__ nodes, int n_internal, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_internal; i += gridDim.x * blockDim.x) {
+    const float* f = reinterpret_cast<const float*>(&nodes[i]);
+    const int c0 = nodes[i].c.x, c1 = nodes[i].c.y;
+    if (c0 >= 0) s += box_area(f, f + 3);
+    if (c1 >= 0) s += box_area(f + 6, f + 9);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sah_final(const double* __restrict__ part, int nb, const float* __restrict__ root,
+                            double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += part[i];
+  double ar = box_area(root, root + 3);
+  out[0] = ar > 0 ? (s + ar) / ar : 1.0;
+}
+
+constexpr int kSahBlocks = 64;
+
+}  // namespace
+
+void launch_xform(dcem_ctx* c) {
+  if (c->no == 0) return;
+  hipLaunchKernelGGL(k_xform, dim3(c->no), dim3(256), 0, c->stream, ptr<float>(c->ref_vertices),
+                     ptr<float>(c->vertices), ptr<int64_t>(c->obj_range), ptr<float>(c->xf),
+                     ptr<float>(c->obj_box), c->pad, ptr<uint32_t>(c->err_word));
+}
+
+hipError_t build_lbvh(dcem_ctx* c) {
+  const int64_t nt = c->nt;
+  hipError_t e;
+  c->n_internal = nt > 1 ? (int32_t)(nt - 1) : (nt == 1 ? 1 : 0);
+  if (nt == 0) {
+    c->has_bvh = true;
+    c->sah_build = 1.0;
+    return hipSuccess;
+  }
+  if ((e = ensure(c->nodes, sizeof(Node) * c->n_internal)) != hipSuccess) return e;
+  if ((e = ensure(c->leaves, sizeof(Leaf) * nt)) != hipSuccess) return e;
+  if ((e = ensure(c->leaf_tri, sizeof(int32_t) * nt)) != hipSuccess) return e;
+  if ((e = ensure(c->leaf_parent, sizeof(int32_t) * nt)) != hipSuccess) return e;
+  if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * c->n_internal)) != hipSuccess) return e;
+  if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
+  uint32_t* code = ptr<uint32_t>(c->morton);
+  uint32_t* perm = code + nt;
+  uint32_t* perm_tmp = perm + nt;
+  uint32_t* nbox = perm_tmp + nt;   // 6 ordered-bit words + n
+  hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox);
+  const int nb = (int)std::min<int64_t>((nt + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_centroid_bounds, dim3(nb), dim3(256), 0, c->stream, ptr<float>(c->vertices),
+                     ptr<int32_t>(c->tris), nt, nbox);
+  hipLaunchKernelGGL(k_morton, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
+                     ptr<int32_t>(c->tris), nt, nbox, code);
+  uint32_t n32 = (uint32_t)nt;
+  if ((e = hipMemcpyAsync(nbox + 6, &n32, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return e;
+  if ((e = radix_sort_perm(c, code, 1, 30, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * c->n_internal, c->stream)) != hipSuccess) return e;
+  if (nt == 1) {
+    Node root{};
+    root.c = make_int4(~0, ~0, -1, 0);
+    if ((e = hipMemcpyAsync(c->nodes.p, &root, sizeof(Node), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return e;
+    int32_t zero = 0, lp = 0;
+    if ((e = hipMemcpyAsync(c->leaf_tri.p, &zero, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(c->leaf_parent.p, &lp, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, code, perm, (int)nt,
+                       ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri));
+  }
+  launch_refit(c);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  double sah = 1.0;
+  if ((e = compute_sah(c, &sah)) != hipSuccess) return e;
+  c->sah_build = sah;
+  c->has_bvh = true;
+  return hipSuccess;
+}
+
+void launch_refit(dcem_ctx* c) {
+  if (c->nt == 0) return;
+  hipLaunchKernelGGL(k_refit, dim3((c->nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
+                     ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face), ptr<int32_t>(c->leaf_tri),
+                     ptr<int32_t>(c->leaf_parent), ptr<Node>(c->nodes), ptr<Leaf>(c->leaves),
+                     ptr<uint32_t>(c->refit_cnt), ptr<float>(c->scene_box), (int)c->nt, c->pad);
+}
+
+hipError_t compute_sah(dcem_ctx* c, double* sah) {
+  if (c->nt == 0) {
+    *sah = 1.0;
+    return hipSuccess;
+  }
+  double* part = reinterpret_cast<double*>(ptr<char>(c->scene_box) + 8 * sizeof(float));
+  hipLaunchKernelGGL(k_sah_partial, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
+                     c->n_internal, part);
+  hipLaunchKernelGGL(k_sah_final, dim3(1), dim3(64), 0, c->stream, part, kSahBlocks, ptr<float>(c->scene_box),
+                     part + kSahBlocks);
+  hipError_t e = hipMemcpyAsync(sah, part + kSahBlocks, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+}  // namespace dcem

@@ -1,0 +1,164 @@
+// Internal declarations shared by the HIP translation units of libdcem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dcem.h"
+
+namespace dcem {
+
+constexpr int kWave = 64;
+constexpr float kTMin = 1e-4f;           // hits closer than this to a segment start are ignored
+constexpr double kTMinD = 1e-4;
+constexpr int kStackSize = 64;           // traversal stack entries per lane (LDS)
+constexpr int kTraceBlock = 128;         // threads per trace block
+constexpr uint32_t kNoRay = 0xffffffffu;
+
+// BVH2 internal node, 64 bytes: both child boxes plus links.
+//   b0 = (lo0.x, lo0.y, lo0.z, hi0.x)   b1 = (hi0.y, hi0.z, lo1.x, lo1.y)
+//   b2 = (lo1.z, hi1.x, hi1.y, hi1.z)   c  = (child0, child1, parent*2+slot, 0)
+// child >= 0 is an internal node, child < 0 is leaf ~child; parent -1 at the root.
+struct __align__(16) Node {
+  float4 b0, b1, b2;
+  int4 c;
+};
+
+// Leaf triangle in BVH order, 48 bytes: vertices with the triangle id and its
+// face id in the w components (as integer bits).
+struct __align__(16) Leaf {
+  float4 v0, v1, v2;
+};
+
+// Packed capture record: ray work item (tx * n_rays + ray) and
+// (tx * n_rx + rx) << 4 | order.
+struct Capture {
+  uint32_t work;
+  uint32_t pair_order;
+};
+
+// Frame-invariant description of the current trace configuration, used to
+// decide whether the coherence cache still applies.
+struct TraceConfig {
+  int32_t n_tx = 0, n_rx = 0, K = -1;
+  int64_t n_rays = 0;
+  float rx_radius = 0.f;
+  std::vector<float> tx, rx;
+  bool dirs_fib = true;
+  const void* dirs_ptr = nullptr;
+  std::vector<float> dirs_host;
+};
+
+// Growable device allocation owned by the context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace dcem
+
+struct dcem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool timing = false;
+  int64_t cap_capacity = int64_t(1) << 22;
+
+  // -- scene
+  bool has_scene = false;
+  int64_t nv = 0, nt = 0;
+  int32_t nf = 0, nm = 0, no = 0;
+  float pad = 0.f;          // absolute padding of leaf boxes (conservative traversal)
+  dcem::DevBuf ref_vertices, vertices, tris, tri_face, face_material, face_object, materials,
+      obj_range, face_tri_off, face_tris, face_ref_tri, xf, obj_box, face_plane;
+  std::vector<int32_t> h_face_object;
+
+  // -- BVH
+  bool has_bvh = false;
+  int32_t n_internal = 0;
+  double sah_build = 0.0, sah_last = 1.0;
+  int32_t last_rebuilt = 0;
+  dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box;
+
+  // -- rays and cache
+  dcem::TraceConfig cfg;
+  bool cache_valid = false;
+  bool geometry_moved = true;   // transforms changed since the cached frame
+  dcem::DevBuf dirs, tx_pos, rx_pos, freqs;
+  dcem::DevBuf face_log;     // [K+1][n_work] int32 face hit per bounce (-1 miss)
+  dcem::DevBuf ray_state;    // [n_work] uint8: segments (low 4 bits), bit 7 = hit a moving face
+  dcem::DevBuf seg_o, seg_d; // [K+1][n_work] float4: origin + t_end, direction
+  dcem::DevBuf log_tri, log_t, log_len;  // parity log [n_work][K+1]
+  dcem::DevBuf caps[2];      // double-buffered capture lists
+  int cur_caps = 0;
+  dcem::DevBuf work_list, invalid_flag;
+  dcem::DevBuf counters;     // uint32 device counters (see kCnt*)
+  dcem::DevBuf err_word;
+
+  // -- candidates / paths
+  int32_t key_words = 0, K = 0, n_freqs = 0, n_tx = 0, n_rx = 0;
+  int64_t n_rays = 0;
+  int bits_tx = 0, bits_rx = 0, bits_face = 0;
+  dcem::DevBuf cand_keys, cand_perm, cand_tmp, uniq_idx, first_ray;
+  dcem::DevBuf path_valid, path_len, path_tau, path_aod, path_aoa, path_amp;
+  dcem::DevBuf p_coh, p_inc, pair_range;
+  dcem::DevBuf sort_hist;
+  int64_t n_caps_host = 0;
+  double sqrt_pt = 0.0, atten_db_per_km = 0.0;
+  bool bvh_stale = false;     // transforms changed since the last refit
+  bool has_frame = false;
+  int32_t record_log = 0;
+  dcem_frame_stats stats{};
+  hipEvent_t ev[8] = {};
+};
+
+namespace dcem {
+
+// counters in ctx->counters
+enum : int {
+  kCntCaptures = 0,   // capture records in the current list
+  kCntWork = 1,       // work items to trace
+  kCntQueue = 2,      // persistent-thread queue head
+  kCntUnique = 3,     // unique candidates
+  kCntSegments = 4,   // closest-hit queries executed
+  kCntValid = 5,      // valid paths
+  kCntSlots = 8,      // number of counters
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes);
+void release(DevBuf& b);
+
+template <class T>
+T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
+
+// ---- launchers (bvh.hip)
+void launch_xform(dcem_ctx* c);
+hipError_t build_lbvh(dcem_ctx* c);
+void launch_refit(dcem_ctx* c);
+hipError_t compute_sah(dcem_ctx* c, double* sah);
+
+// ---- radix sort (sort.hip)
+// Stable LSD sort of n items by `bits` low bits of a multi-word key stored
+// word-major ([W][n], word W-1 least significant), producing a permutation.
+// The item count is min(*n_dev, n_max), read on the device.
+hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, const uint32_t* n_dev,
+                           int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s);
+
+// ---- trace (trace.hip)
+void launch_fibonacci(dcem_ctx* c);
+void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_max);
+void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps);
+void launch_los(dcem_ctx* c);
+void launch_reset_counters(dcem_ctx* c);
+
+// ---- candidates, refinement and accumulation (refine.hip)
+hipError_t build_candidates(dcem_ctx* c);
+void launch_face_planes(dcem_ctx* c);
+hipError_t ensure_paths(dcem_ctx* c, int64_t n);
+void launch_refine(dcem_ctx* c);
+void launch_reduce(dcem_ctx* c);
+
+}  // namespace dcem

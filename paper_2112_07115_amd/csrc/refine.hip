@@ -1,0 +1,631 @@
+// Candidate de-duplication, image-method refinement in FP64 and per-receiver
+// accumulation.
+//
+// Paper, Sec. III: visited propagation paths are kept in one table per
+// reflection depth (step 2); each new sequence of faces yields images of the
+// source through the face planes (step 3) and is validated (step 4); every
+// valid path gets its total length, direction, attenuation and phase (step 6).
+// Candidates here are keys (tx, rx, order, face sequence) sorted
+// lexicographically, so the per-receiver sums are taken in a fixed order.
+#include "dcem_internal.h"
+
+#include <cfloat>
+
+namespace dcem {
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxK = DCEM_MAX_REFLECTIONS;
+
+struct KeyLayout {
+  int W;       // 32-bit words per key
+  int bits;    // significant bits
+  int bt, br, bf, K;
+  int n_rx;
+};
+
+// Place `nbits` of `v` at bit offset `pos` (from the least significant end of
+// the W-word key, word W-1 holding bits 0..31).
+__device__ inline void put_bits(uint32_t* w, int W, int pos, int nbits, uint32_t v) {
+  while (nbits > 0) {
+    const int word = W - 1 - pos / 32, off = pos % 32;
+    const int take = min(nbits, 32 - off);
+    const uint32_t mask = take == 32 ? 0xffffffffu : ((1u << take) - 1u);
+    w[word] |= (v & mask) << off;
+    v = take == 32 ? 0 : (v >> take);
+    nbits -= take;
+    pos += take;
+  }
+}
+
+__device__ inline uint32_t get_bits(const uint32_t* __restrict__ keys, int64_t stride, uint32_t idx, int W, int pos,
+                                    int nbits) {
+  uint32_t v = 0;
+  int got = 0;
+  while (got < nbits) {
+    const int word = W - 1 - pos / 32, off = pos % 32;
+    const int take = min(nbits - got, 32 - off);
+    const uint32_t mask = take == 32 ? 0xffffffffu : ((1u << take) - 1u);
+    v |= ((keys[word * stride + idx] >> off) & mask) << got;
+    got += take;
+    pos += take;
+  }
+  return v;
+}
+
+// Sort key of every capture: (tx, rx, order, f1..fK) packed most significant
+// first, faces read from the per-bounce face log of the capturing ray.
+__global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log,
+                       int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys, int64_t stride) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Capture c = caps[i];
+  const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
+  const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
+  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < L.K; ++j) {
+    uint32_t f = 0;
+    if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
+    put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
+  }
+  int pos = L.K * L.bf;
+  put_bits(w, L.W, pos, 4, order);
+  pos += 4;
+  put_bits(w, L.W, pos, L.br, rx);
+  pos += L.br;
+  put_bits(w, L.W, pos, L.bt, tx);
+  for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
+}
+
+__global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
+                                               const uint32_t* __restrict__ perm, uint32_t n,
+                                               uint8_t* __restrict__ head, uint32_t* __restrict__ block_cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool h = false;
+  if (i < n) {
+    h = i == 0;
+    if (!h) {
+      const uint32_t a = perm[i], b = perm[i - 1];
+      for (int k = 0; k < W && !h; ++k) h = keys[k * stride + a] != keys[k * stride + b];
+    }
+    head[i] = h ? 1 : 0;
+  }
+  const uint64_t m = __ballot(h);
+  __shared__ uint32_t wc[4];
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t* __restrict__ v, int n, uint32_t* __restrict__ total) {
+  __shared__ uint32_t part[1024];
+  const int per = (n + 1023) / 1024;
+  const int b = threadIdx.x * per, e = min(n, b + per);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t x = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ head,
+                                                 const uint32_t* __restrict__ block_off, uint32_t n,
+                                                 const uint32_t* __restrict__ n_unique,
+                                                 uint32_t* __restrict__ uniq_pos) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool h = i < n && head[i];
+  const uint64_t m = __ballot(h);
+  __shared__ uint32_t wc[4];
+  if (lane == 0) wc[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t off = block_off[blockIdx.x];
+  for (int w = 0; w < wave; ++w) off += wc[w];
+  if (h) uniq_pos[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  if (i == 0) uniq_pos[*n_unique] = n;
+}
+
+__global__ void k_face_planes(const float* __restrict__ V, const int32_t* __restrict__ T,
+                              const int32_t* __restrict__ ref_tri, int nf, double4* __restrict__ plane) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int t = ref_tri[f];
+  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
+  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
+  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
+  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
+  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+  const double l = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= l; ny /= l; nz /= l;
+  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
+}
+
+struct D3 {
+  double x, y, z;
+};
+__device__ inline D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 operator*(double s, D3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline D3 cross(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline double len(D3 a) { return sqrt(dot(a, a)); }
+__device__ inline D3 normed(D3 a) { return (1.0 / len(a)) * a; }
+__device__ inline D3 fvec(const float* v, int i) { return {(double)v[3 * i], (double)v[3 * i + 1], (double)v[3 * i + 2]}; }
+
+struct Cx {
+  double re, im;
+};
+__device__ inline Cx cadd(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline Cx csub(Cx a, Cx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline Cx cmul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cx cscl(double s, Cx a) { return {s * a.re, s * a.im}; }
+__device__ inline Cx cdiv(Cx a, Cx b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+// principal square root for Re z >= 0 (the case eps_c - sin^2 with eps_r >= 1)
+__device__ inline Cx csqrt_p(Cx z) {
+  const double r = hypot(z.re, z.im);
+  double re = sqrt(0.5 * (r + z.re));
+  if (re == 0.0) return {0.0, sqrt(0.5 * (r - z.re)) * (z.im < 0 ? -1.0 : 1.0)};
+  return {re, z.im / (2.0 * re)};
+}
+
+// Reflection coefficients of a plane interface with relative permittivity
+// eps_c = eps_r - j sigma / (2 pi f eps0) (time factor e^{+j w t}); TE with
+// E normal to the plane of incidence, TM with E in it.  const_gamma g (not
+// NaN) is a polarisation-independent mirror: TE = -g, TM = +g.
+__device__ inline void fresnel_coeffs(const double* mat, double freq, double cos_t, Cx& te, Cx& tm) {
+  const double g = mat[2];
+  if (!isnan(g)) {
+    te = {-g, 0.0};
+    tm = {g, 0.0};
+    return;
+  }
+  const Cx ec = {mat[0], -mat[1] / (2.0 * kPi * freq * kEps0)};
+  const Cx root = csqrt_p({ec.re - (1.0 - cos_t * cos_t), ec.im});
+  const Cx ct = {cos_t, 0.0};
+  te = cdiv(csub(ct, root), cadd(ct, root));
+  const Cx ecc = cscl(cos_t, ec);
+  tm = cdiv(csub(ecc, root), cadd(ecc, root));
+}
+
+__device__ inline double vol(D3 a, D3 b, D3 c, D3 d) { return dot(b - a, cross(c - a, d - a)); }
+
+struct RefineArgs {
+  const uint32_t* keys;
+  int64_t stride;
+  KeyLayout L;
+  const uint32_t* perm;
+  const uint32_t* uniq_pos;
+  const uint32_t* n_unique;
+  const Capture* caps;
+  const float* tx;
+  const float* rx;
+  const double4* plane;
+  const int32_t* face_tri_off;
+  const int32_t* face_tris;
+  const int32_t* tris;
+  const float* V;
+  const int32_t* face_material;
+  const double* materials;
+  const Node* nodes;
+  const Leaf* leaves;
+  int n_internal;
+  const double* freqs;
+  int n_freqs;
+  double sqrt_pt;
+  double atten_db_per_km;
+  int64_t n_rays;
+  uint8_t* valid;
+  double* length;
+  double* tau;
+  double* aod;
+  double* aoa;
+  double* amp;       // [n][n_freqs][3][2]
+  int32_t* first_ray;
+  int32_t* pair;
+  uint32_t* counters;
+  uint32_t* err;
+};
+
+// Is point p inside face f (inclusive)?  2D edge functions on the plane
+// projection that drops the normal's dominant axis.
+__device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
+  const double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
+  const int drop = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  auto pr = [drop](D3 v, double& u, double& w) {
+    if (drop == 0) { u = v.y; w = v.z; }
+    else if (drop == 1) { u = v.z; w = v.x; }
+    else { u = v.x; w = v.y; }
+  };
+  double pu, pw;
+  pr(p, pu, pw);
+  for (int k = a.face_tri_off[f]; k < a.face_tri_off[f + 1]; ++k) {
+    const int t = a.face_tris[k];
+    D3 A = fvec(a.V, a.tris[3 * t]), B = fvec(a.V, a.tris[3 * t + 1]), C = fvec(a.V, a.tris[3 * t + 2]);
+    double au, aw, bu, bw, cu, cw;
+    pr(A, au, aw);
+    pr(B, bu, bw);
+    pr(C, cu, cw);
+    const double e0 = (bu - au) * (pw - aw) - (bw - aw) * (pu - au);
+    const double e1 = (cu - bu) * (pw - bw) - (cw - bw) * (pu - bu);
+    const double e2 = (au - cu) * (pw - cw) - (aw - cw) * (pu - cu);
+    if ((e0 >= 0 && e1 >= 0 && e2 >= 0) || (e0 <= 0 && e1 <= 0 && e2 <= 0)) return true;
+  }
+  return false;
+}
+
+// Any triangle (outside faces fa, fb) crossed by the open segment p -> q,
+// keeping t_min away from both ends?  FP64 orientation tests at the leaves;
+// BVH boxes (FP32, padded) tested in FP64.
+__device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* stack, int stride, bool& fault) {
+  if (a.n_internal == 0) return false;
+  const D3 dv = q - p;
+  const double L = len(dv);
+  const double tlo = kTMinD / L, thi = 1.0 - kTMinD / L;
+  if (!(tlo < thi)) return false;
+  const double big = 1e300;
+  const double ix = dv.x != 0 ? 1.0 / dv.x : big, iy = dv.y != 0 ? 1.0 / dv.y : big,
+               iz = dv.z != 0 ? 1.0 / dv.z : big;
+  int node = 0, sp = 0;
+  auto box = [&](const float* f) {
+    const double ax = (f[0] - p.x) * ix, bx = (f[3] - p.x) * ix;
+    const double ay = (f[1] - p.y) * iy, by = (f[4] - p.y) * iy;
+    const double az = (f[2] - p.z) * iz, bz = (f[5] - p.z) * iz;
+    const double tn = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmax(fmin(az, bz), 0.0));
+    const double tf = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmin(fmax(az, bz), 1.0));
+    return tn <= tf * (1.0 + 1e-12);
+  };
+  auto leaf = [&](int li) {
+    const Leaf& lf = a.leaves[li];
+    const int face = __float_as_int(lf.v1.w);
+    if (face == fa || face == fb) return false;
+    const D3 A = {lf.v0.x, lf.v0.y, lf.v0.z}, B = {lf.v1.x, lf.v1.y, lf.v1.z}, C = {lf.v2.x, lf.v2.y, lf.v2.z};
+    const double op = vol(A, B, C, p), oq = vol(A, B, C, q);
+    if (op == oq) return false;
+    const double t = op / (op - oq);
+    if (!(t > tlo && t < thi)) return false;
+    const double s0 = vol(p, q, A, B), s1 = vol(p, q, B, C), s2 = vol(p, q, C, A);
+    return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+  };
+  // a sound tree visits each node at most once per query; the bound only
+  // guarantees termination
+  for (int64_t guard = 2 * (int64_t)a.n_internal + 2; guard > 0; --guard) {
+    const Node& nd = a.nodes[node];
+    const float* f = reinterpret_cast<const float*>(&nd);
+    bool h0 = box(f), h1 = box(f + 6);
+    const int c0 = nd.c.x, c1 = nd.c.y;
+    if (h0 && c0 < 0) { if (leaf(~c0)) return true; h0 = false; }
+    if (h1 && c1 < 0) { if (leaf(~c1)) return true; h1 = false; }
+    if (h0 && h1) {
+      if (sp < kStackSize) stack[(sp++) * stride] = c1;
+      else fault = true;
+      node = c0;
+    } else if (h0) {
+      node = c0;
+    } else if (h1) {
+      node = c1;
+    } else {
+      if (sp == 0) return false;
+      node = stack[(--sp) * stride];
+    }
+  }
+  fault = true;
+  return false;
+}
+
+constexpr int kRefineBlock = 64;
+
+__global__ __launch_bounds__(kRefineBlock) void k_refine(RefineArgs a) {
+  __shared__ int stack_mem[kStackSize * kRefineBlock];
+  int* stack = stack_mem + threadIdx.x;
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nu = *a.n_unique;
+  const int lane = threadIdx.x & 63;
+  bool ok = false, fault = false;
+  if (u < nu) {
+    const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
+    const uint32_t idx = a.perm[h];
+    const KeyLayout& L = a.L;
+    // decode (tx, rx, order, faces)
+    int faces[kMaxK];
+    for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
+    int pos = L.K * L.bf;
+    const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
+    pos += 4;
+    const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
+    pos += L.br;
+    const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
+    a.pair[u] = tx * L.n_rx + rx;
+    uint32_t fr = kNoRay;
+    for (uint32_t j = h; j < e; ++j) fr = min(fr, a.caps[a.perm[j]].work);
+    a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
+
+    const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
+    // images of the transmitter through the face planes
+    D3 img[kMaxK + 1];
+    img[0] = T;
+    for (int j = 1; j <= order; ++j) {
+      const double4 pl = a.plane[faces[j - 1]];
+      const D3 n = {pl.x, pl.y, pl.z};
+      img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
+    }
+    // reflection points, from the receiver back towards the transmitter
+    D3 pts[kMaxK + 2];
+    pts[0] = T;
+    pts[order + 1] = R;
+    ok = true;
+    D3 Q = R;
+    for (int j = order; j >= 1 && ok; --j) {
+      const double4 pl = a.plane[faces[j - 1]];
+      const D3 n = {pl.x, pl.y, pl.z};
+      const D3 D = img[j] - Q;
+      const double den = dot(D, n);
+      if (den == 0.0) { ok = false; break; }
+      const double s = (pl.w - dot(Q, n)) / den;
+      if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
+      const D3 P = Q + s * D;
+      if (!in_face(a, faces[j - 1], P, n)) { ok = false; break; }
+      pts[j] = P;
+      Q = P;
+    }
+    for (int j = 0; j <= order && ok; ++j) {
+      const int fa = j >= 1 ? faces[j - 1] : -1;
+      const int fb = j + 1 <= order ? faces[j] : -1;
+      if (occluded(a, pts[j], pts[j + 1], fa, fb, stack, kRefineBlock, fault)) ok = false;
+    }
+    a.valid[u] = ok ? 1 : 0;
+    const double d = len(R - img[order]);
+    a.length[u] = ok ? d : 0.0;
+    a.tau[u] = ok ? d / kC0 : 0.0;
+    D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
+    if (ok) {
+      aod = normed(pts[1] - pts[0]);
+      aoa = normed(pts[order] - R);
+    }
+    a.aod[3 * u] = aod.x; a.aod[3 * u + 1] = aod.y; a.aod[3 * u + 2] = aod.z;
+    a.aoa[3 * u] = aoa.x; a.aoa[3 * u + 1] = aoa.y; a.aoa[3 * u + 2] = aoa.z;
+    // field: theta-hat of the departure direction, carried through each reflection
+    const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
+    const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+    for (int fi = 0; fi < a.n_freqs; ++fi) {
+      const double f = a.freqs[fi];
+      double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
+      if (!ok) {
+        for (int k = 0; k < 6; ++k) out[k] = 0.0;
+        continue;
+      }
+      Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
+      for (int j = 1; j <= order; ++j) {
+        const double4 pl = a.plane[faces[j - 1]];
+        const D3 n = {pl.x, pl.y, pl.z};
+        const D3 ki = normed(pts[j] - pts[j - 1]);
+        const D3 kr = normed(pts[j + 1] - pts[j]);
+        const double cos_t = fabs(dot(ki, n));
+        D3 s = cross(ki, n);
+        const double sl = len(s);
+        if (sl < 1e-12) {
+          const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
+          s = normed(cross(ki, ax));
+        } else {
+          s = (1.0 / sl) * s;
+        }
+        const D3 pin = cross(s, ki), pout = cross(s, kr);
+        Cx te, tm;
+        fresnel_coeffs(a.materials + 3 * a.face_material[faces[j - 1]], f, cos_t, te, tm);
+        const Cx es = cadd(cadd(cscl(s.x, E[0]), cscl(s.y, E[1])), cscl(s.z, E[2]));
+        const Cx ep = cadd(cadd(cscl(pin.x, E[0]), cscl(pin.y, E[1])), cscl(pin.z, E[2]));
+        const Cx cs = cmul(te, es), cp = cmul(tm, ep);
+        E[0] = cadd(cscl(s.x, cs), cscl(pout.x, cp));
+        E[1] = cadd(cscl(s.y, cs), cscl(pout.y, cp));
+        E[2] = cadd(cscl(s.z, cs), cscl(pout.z, cp));
+      }
+      const double lam = kC0 / f;
+      const double k0 = 2.0 * kPi * f / kC0;
+      const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
+      double sn, cs;
+      sincos(k0 * d, &sn, &cs);
+      const Cx ph = {mag * cs, -mag * sn};
+      for (int c = 0; c < 3; ++c) {
+        const Cx v = cmul(ph, E[c]);
+        out[2 * c] = v.re;
+        out[2 * c + 1] = v.im;
+      }
+    }
+  }
+  const uint64_t m = __ballot(ok);
+  if (lane == 0 && m) atomicAdd(&a.counters[kCntValid], (uint32_t)__popcll(m));
+  if (fault) atomicOr(a.err, DCEM_ERR_STACK);
+}
+
+// One wavefront per (tx, rx): sum the valid paths of that pair (contiguous in
+// key order) with a fixed lane assignment and butterfly, so the result is
+// bitwise reproducible.
+__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair, const uint8_t* __restrict__ valid,
+                                                const double* __restrict__ amp, const uint32_t* __restrict__ n_unique,
+                                                int n_pairs, int n_freqs, double* __restrict__ p_coh,
+                                                double* __restrict__ p_inc) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= n_pairs) return;
+  const int n = (int)*n_unique;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pair[mid] < wave) lo = mid + 1; else hi = mid;
+  }
+  const int start = lo;
+  hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
+  }
+  const int end = lo;
+  for (int fi = 0; fi < n_freqs; ++fi) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double inc = 0.0;
+    for (int u = start + lane; u < end; u += 64) {
+      if (!valid[u]) continue;
+      const double* v = amp + ((size_t)u * n_freqs + fi) * 6;
+      for (int k = 0; k < 6; ++k) {
+        acc[k] += v[k];
+        inc += v[k] * v[k];
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      for (int k = 0; k < 6; ++k) acc[k] += __shfl_xor(acc[k], off);
+      inc += __shfl_xor(inc, off);
+    }
+    if (lane == 0) {
+      double pc = 0.0;
+      for (int k = 0; k < 6; ++k) pc += acc[k] * acc[k];
+      p_coh[(size_t)fi * n_pairs + wave] = pc;
+      p_inc[(size_t)fi * n_pairs + wave] = inc;
+    }
+  }
+}
+
+int bits_for(int64_t n_values) {
+  int b = 0;
+  while (((int64_t)1 << b) < n_values) ++b;
+  return b;
+}
+
+}  // namespace
+
+hipError_t build_candidates(dcem_ctx* c) {
+  hipError_t e;
+  uint32_t* cnt = ptr<uint32_t>(c->counters);
+  uint32_t n_caps = 0;
+  if ((e = hipMemcpyAsync(&n_caps, cnt + kCntCaptures, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (n_caps > c->cap_capacity) n_caps = (uint32_t)c->cap_capacity;
+  c->n_caps_host = n_caps;
+  KeyLayout L;
+  L.bt = bits_for(c->n_tx);
+  L.br = bits_for(c->n_rx);
+  L.bf = std::max(1, bits_for(c->nf));
+  L.K = c->K;
+  L.n_rx = c->n_rx;
+  L.bits = L.bt + L.br + 4 + L.K * L.bf;
+  L.W = (L.bits + 31) / 32;
+  c->key_words = L.W;
+  c->bits_tx = L.bt;
+  c->bits_rx = L.br;
+  c->bits_face = L.bf;
+  const int64_t n = std::max<int64_t>(n_caps, 1);
+  if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * n)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_perm, sizeof(uint32_t) * 2 * n)) != hipSuccess) return e;
+  const int nb = (int)((n + 255) / 256);
+  if ((e = ensure(c->cand_tmp, n + 16 + sizeof(uint32_t) * (nb + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (n + 1))) != hipSuccess) return e;
+  uint32_t* keys = ptr<uint32_t>(c->cand_keys);
+  uint32_t* perm = ptr<uint32_t>(c->cand_perm);
+  uint8_t* head = ptr<uint8_t>(c->cand_tmp);
+  uint32_t* bcnt = reinterpret_cast<uint32_t*>(ptr<uint8_t>(c->cand_tmp) + ((n + 15) / 16) * 16);
+  if (n_caps == 0) return hipSuccess;   // the unique counter was cleared at frame start
+  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_caps,
+                     ptr<int32_t>(c->face_log), (int64_t)c->n_tx * c->n_rays, L, keys, (int64_t)n);
+  if ((e = radix_sort_perm(c, keys, L.W, L.bits, cnt + kCntCaptures, n, perm, perm + n, c->stream)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_caps, head, bcnt);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nb, cnt + kCntUnique);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_caps, cnt + kCntUnique,
+                     ptr<uint32_t>(c->uniq_idx));
+  return hipGetLastError();
+}
+
+void launch_face_planes(dcem_ctx* c) {
+  if (c->nf == 0) return;
+  hipLaunchKernelGGL(k_face_planes, dim3((c->nf + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
+                     ptr<int32_t>(c->tris), ptr<int32_t>(c->face_ref_tri), c->nf, ptr<double4>(c->face_plane));
+}
+
+hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
+  hipError_t e;
+  n = std::max<int64_t>(n, 1);
+  if ((e = ensure(c->path_valid, n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_len, 8 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_tau, 8 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_aod, 24 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_aoa, 24 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_amp, 48 * n * (size_t)c->n_freqs)) != hipSuccess) return e;
+  if ((e = ensure(c->first_ray, 4 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->pair_range, 4 * n)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void launch_refine(dcem_ctx* c) {
+  const int64_t n = c->n_caps_host;
+  if (n == 0) return;
+  KeyLayout L;
+  L.bt = c->bits_tx;
+  L.br = c->bits_rx;
+  L.bf = c->bits_face;
+  L.K = c->K;
+  L.n_rx = c->n_rx;
+  L.bits = L.bt + L.br + 4 + L.K * L.bf;
+  L.W = c->key_words;
+  RefineArgs a;
+  a.keys = ptr<uint32_t>(c->cand_keys);
+  a.stride = std::max<int64_t>(n, 1);
+  a.L = L;
+  a.perm = ptr<uint32_t>(c->cand_perm);
+  a.uniq_pos = ptr<uint32_t>(c->uniq_idx);
+  a.n_unique = ptr<uint32_t>(c->counters) + kCntUnique;
+  a.caps = ptr<Capture>(c->caps[c->cur_caps]);
+  a.tx = ptr<float>(c->tx_pos);
+  a.rx = ptr<float>(c->rx_pos);
+  a.plane = ptr<double4>(c->face_plane);
+  a.face_tri_off = ptr<int32_t>(c->face_tri_off);
+  a.face_tris = ptr<int32_t>(c->face_tris);
+  a.tris = ptr<int32_t>(c->tris);
+  a.V = ptr<float>(c->vertices);
+  a.face_material = ptr<int32_t>(c->face_material);
+  a.materials = ptr<double>(c->materials);
+  a.nodes = ptr<Node>(c->nodes);
+  a.leaves = ptr<Leaf>(c->leaves);
+  a.n_internal = c->nt > 0 ? c->n_internal : 0;
+  a.freqs = ptr<double>(c->freqs);
+  a.n_freqs = c->n_freqs;
+  a.sqrt_pt = c->sqrt_pt;
+  a.atten_db_per_km = c->atten_db_per_km;
+  a.n_rays = c->n_rays;
+  a.valid = ptr<uint8_t>(c->path_valid);
+  a.length = ptr<double>(c->path_len);
+  a.tau = ptr<double>(c->path_tau);
+  a.aod = ptr<double>(c->path_aod);
+  a.aoa = ptr<double>(c->path_aoa);
+  a.amp = ptr<double>(c->path_amp);
+  a.first_ray = ptr<int32_t>(c->first_ray);
+  a.pair = ptr<int32_t>(c->pair_range);
+  a.counters = ptr<uint32_t>(c->counters);
+  a.err = ptr<uint32_t>(c->err_word);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)((n + kRefineBlock - 1) / kRefineBlock)), dim3(kRefineBlock), 0,
+                     c->stream, a);
+}
+
+void launch_reduce(dcem_ctx* c) {
+  const int n_pairs = c->n_tx * c->n_rx;
+  hipLaunchKernelGGL(k_reduce, dim3((n_pairs * 64 + 255) / 256), dim3(256), 0, c->stream,
+                     ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
+                     ptr<uint32_t>(c->counters) + kCntUnique, n_pairs, c->n_freqs, ptr<double>(c->p_coh),
+                     ptr<double>(c->p_inc));
+}
+
+}  // namespace dcem

@@ -1,0 +1,450 @@
+// Ray shooting: Fibonacci ray sphere, closest-hit BVH traversal with a
+// watertight ray-triangle test, receiver-sphere capture and specular
+// reflection, plus the frame-to-frame coherence pass.
+//
+// Paper, Sec. III: the frame algorithm casts a sphere of sampled rays (step 1)
+// and records their reflections up to a bounce limit (step 2; at most 10);
+// propagation-path caching re-checks the previous frame's paths at the start
+// of each frame so that fewer rays are cast.  Here a ray is reused unchanged
+// when none of its segments can meet moved geometry; only the others are
+// traced again, which reproduces the full re-trace exactly.
+#include "dcem_internal.h"
+
+#include <cfloat>
+
+namespace dcem {
+namespace {
+
+__device__ inline float comp(const float3& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+struct Ray {
+  float3 o, d, inv;   // origin, direction (not normalised), 1 / direction (zeros replaced)
+  float sx, sy, sz;   // shear constants of the watertight test
+  int kx, ky, kz;     // axis permutation of the watertight test
+};
+
+__device__ inline void setup_ray(Ray& r) {
+  const float ax = fabsf(r.d.x), ay = fabsf(r.d.y), az = fabsf(r.d.z);
+  int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  if (comp(r.d, kz) < 0.0f) { int t = kx; kx = ky; ky = t; }
+  r.kx = kx; r.ky = ky; r.kz = kz;
+  const float dz = comp(r.d, kz);
+  r.sx = __fdiv_rn(comp(r.d, kx), dz);
+  r.sy = __fdiv_rn(comp(r.d, ky), dz);
+  r.sz = __fdiv_rn(1.0f, dz);
+  const float tiny = 1e-30f;
+  r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny), __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
+                      __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
+}
+
+// Watertight ray-triangle intersection (Woop, Benthin and Wald, JCGT 2013):
+// vertices are translated to the ray origin and sheared so the ray runs along
+// +z; the 2D edge functions decide the hit, with an FP64 re-evaluation when
+// one is exactly zero.  Edge functions are evaluated without FMA contraction
+// so that two triangles sharing an edge compute exactly opposite values.
+// Returns the hit distance t (IEEE division) or -1.
+__device__ inline float watertight(const Ray& r, const float4& p0, const float4& p1, const float4& p2) {
+#pragma clang fp contract(off)
+  const float3 A = make_float3(p0.x - r.o.x, p0.y - r.o.y, p0.z - r.o.z);
+  const float3 B = make_float3(p1.x - r.o.x, p1.y - r.o.y, p1.z - r.o.z);
+  const float3 C = make_float3(p2.x - r.o.x, p2.y - r.o.y, p2.z - r.o.z);
+  const float Az = comp(A, r.kz), Bz = comp(B, r.kz), Cz = comp(C, r.kz);
+  const float Ax = comp(A, r.kx) - r.sx * Az, Ay = comp(A, r.ky) - r.sy * Az;
+  const float Bx = comp(B, r.kx) - r.sx * Bz, By = comp(B, r.ky) - r.sy * Bz;
+  const float Cx = comp(C, r.kx) - r.sx * Cz, Cy = comp(C, r.ky) - r.sy * Cz;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+  }
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return -1.0f;
+  const float det = U + V + W;
+  if (det == 0.0f) return -1.0f;
+  const float T = U * (r.sz * Az) + V * (r.sz * Bz) + W * (r.sz * Cz);
+  return __fdiv_rn(T, det);
+}
+
+// Conservative slab test against a box given as (lo, hi) over (t0, tmax].
+__device__ inline bool slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz, float tmax,
+                            float& tnear) {
+  const float ox = r.o.x * r.inv.x, oy = r.o.y * r.inv.y, oz = r.o.z * r.inv.z;
+  const float ax = fmaf(lx, r.inv.x, -ox), bx = fmaf(hx, r.inv.x, -ox);
+  const float ay = fmaf(ly, r.inv.y, -oy), by = fmaf(hy, r.inv.y, -oy);
+  const float az = fmaf(lz, r.inv.z, -oz), bz = fmaf(hz, r.inv.z, -oz);
+  const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+  const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax));
+  tnear = tn;
+  return tn <= tf * 1.0000004f;
+}
+
+struct Hit {
+  float t;
+  int tri;    // original triangle id, -1 none
+  int leaf;   // leaf index, -1 none
+  int face;
+};
+
+__device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ leaves, int li, int excl, Hit& h) {
+  const float4 p0 = leaves[li].v0, p1 = leaves[li].v1, p2 = leaves[li].v2;
+  const int face = __float_as_int(p1.w);
+  if (face == excl) return;
+  const float t = watertight(r, p0, p1, p2);
+  if (!(t > kTMin)) return;
+  const int tri = __float_as_int(p0.w);
+  if (t < h.t || (t == h.t && tri < h.tri)) {
+    h.t = t;
+    h.tri = tri;
+    h.leaf = li;
+    h.face = face;
+  }
+}
+
+// Closest hit: lexicographic minimum of (t, triangle id) over all triangles
+// with t > t_min outside face `excl`.  The result does not depend on the tree
+// shape: boxes are conservative and nodes are pruned only when their entry
+// distance exceeds the current best (ties are still visited).
+__device__ Hit closest_hit(const Ray& r, const Node* __restrict__ nodes, const Leaf* __restrict__ leaves,
+                           int n_internal, int excl, int* stack, int stride, bool& overflow) {
+  Hit h{FLT_MAX, -1, -1, -1};
+  if (n_internal == 0) return h;
+  int node = 0, sp = 0;
+  // a sound tree visits each node at most once per query; the bound only
+  // guarantees termination
+  for (int64_t guard = 2 * (int64_t)n_internal + 2;; --guard) {
+    if (guard == 0) { overflow = true; break; }
+    const Node nd = nodes[node];
+    float t0, t1;
+    bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, h.t, t0);
+    bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, h.t, t1);
+    const int c0 = nd.c.x, c1 = nd.c.y;
+    if (h0 && c0 < 0) { test_leaf(r, leaves, ~c0, excl, h); h0 = false; }
+    if (h1 && c1 < 0) { test_leaf(r, leaves, ~c1, excl, h); h1 = false; }
+    if (h0 && h1) {
+      int nearc = c0, farc = c1;
+      if (t1 < t0) { nearc = c1; farc = c0; }
+      if (sp < kStackSize) stack[(sp++) * stride] = farc;
+      else overflow = true;
+      node = nearc;
+    } else if (h0) {
+      node = c0;
+    } else if (h1) {
+      node = c1;
+    } else {
+      if (sp == 0) break;
+      node = stack[(--sp) * stride];
+    }
+  }
+  return h;
+}
+
+// Fibonacci sphere in FP64, plain evaluation (no fused multiply-add), rounded to FP32.
+__global__ void k_fibonacci(float* __restrict__ dirs, int64_t n) {
+#pragma clang fp contract(off)
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+  const double z = 1.0 - (2.0 * (double)i + 1.0) / (double)n;
+  const double rho = sqrt(1.0 - z * z);
+  const double phi = (double)i * golden;
+  double s, c;
+  sincos(phi, &s, &c);
+  dirs[3 * i] = (float)(rho * c);
+  dirs[3 * i + 1] = (float)(rho * s);
+  dirs[3 * i + 2] = (float)z;
+}
+
+struct TraceArgs {
+  const Node* nodes;
+  const Leaf* leaves;
+  int n_internal;
+  const float* dirs;
+  const float* tx;
+  const float* rx;      // [n_rx][3]
+  int n_rx;
+  float r2;
+  float rx_zlo, rx_zhi; // z range of all capture spheres
+  int64_t n_rays;
+  int n_work;
+  const uint32_t* work_list;  // null: all work items
+  int K;
+  const int32_t* face_object;
+  uint32_t* counters;
+  int32_t* face_log;          // [K+1][n_work]
+  uint8_t* ray_state;         // [n_work]
+  float4* seg_o;              // [K+1][n_work] or null
+  float4* seg_d;
+  int32_t* log_tri;           // [n_work][K+1] or null
+  float* log_t;
+  float* log_len;
+  Capture* caps;
+  int64_t cap_capacity;
+  uint32_t* err;
+};
+
+// Persistent trace kernel: each wavefront takes 64 consecutive work items from
+// a global queue and traces them through all bounces.
+__global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
+  __shared__ int stack_mem[kStackSize * kTraceBlock];
+  int* stack = stack_mem + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t n_work = a.work_list ? a.counters[kCntWork] : (uint32_t)a.n_work;
+  uint32_t seg_count = 0;
+  bool overflow = false, cap_over = false;
+  while (true) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&a.counters[kCntQueue], (uint32_t)kWave);
+    base = __shfl(base, 0);
+    if (base >= n_work) break;
+    const uint32_t wi = base + lane;
+    if (wi < n_work) {
+      const uint32_t work = a.work_list ? a.work_list[wi] : wi;
+      const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
+      const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
+      Ray r;
+      r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
+      r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
+      setup_ray(r);
+      int excl = -1;
+      float L = 0.0f;
+      uint32_t state = 0;
+      int k = 0;
+      for (; k <= a.K; ++k) {
+        Hit h = closest_hit(r, a.nodes, a.leaves, a.n_internal, excl, stack, kTraceBlock, overflow);
+        ++seg_count;
+        const bool hit = h.tri >= 0;
+        const float tend = hit ? h.t : INFINITY;
+        a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
+        if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
+        if (a.seg_o) {
+          a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
+          a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, 0.0f);
+        }
+        const float dl = __fsqrt_rn(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+        if (a.log_tri) {
+          const size_t li = (size_t)work * (a.K + 1) + k;
+          a.log_tri[li] = h.tri;
+          a.log_t[li] = hit ? h.t : INFINITY;
+          a.log_len[li] = hit ? L + h.t * dl : INFINITY;
+        }
+        // capture: closest approach of the segment to each sphere centre
+        const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
+        float za = r.o.z, zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+        if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+          for (int c = 0; c < a.n_rx; ++c) {
+            const float wx = a.rx[3 * c] - r.o.x, wy = a.rx[3 * c + 1] - r.o.y, wz = a.rx[3 * c + 2] - r.o.z;
+            float s = __fdiv_rn(wx * r.d.x + wy * r.d.y + wz * r.d.z, dd);
+            s = fminf(fmaxf(s, 0.0f), tend);
+            const float px = fmaf(s, r.d.x, -wx), py = fmaf(s, r.d.y, -wy), pz = fmaf(s, r.d.z, -wz);
+            if (px * px + py * py + pz * pz <= a.r2) {
+              const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
+              if (slot < a.cap_capacity) {
+                Capture cp;
+                cp.work = work;
+                cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+                a.caps[slot] = cp;
+              } else {
+                cap_over = true;
+              }
+            }
+          }
+        }
+        if (!hit || k == a.K) { ++k; break; }
+        // specular reflection off the hit triangle's plane
+        L += h.t * dl;
+        const float4 p0 = a.leaves[h.leaf].v0, p1 = a.leaves[h.leaf].v1, p2 = a.leaves[h.leaf].v2;
+        const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
+        const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
+        float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+        const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
+        nx = __fdiv_rn(nx, nl); ny = __fdiv_rn(ny, nl); nz = __fdiv_rn(nz, nl);
+        const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
+        r.o = make_float3(fmaf(h.t, r.d.x, r.o.x), fmaf(h.t, r.d.y, r.o.y), fmaf(h.t, r.d.z, r.o.z));
+        r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
+        setup_ray(r);
+        excl = h.face;
+      }
+      // mark the remaining bounces as not reached
+      for (int j = k; j <= a.K; ++j) {
+        a.face_log[(size_t)j * a.n_work + work] = -2;
+        if (a.log_tri) {
+          const size_t li = (size_t)work * (a.K + 1) + j;
+          a.log_tri[li] = -2;
+          a.log_t[li] = INFINITY;
+          a.log_len[li] = INFINITY;
+        }
+      }
+      a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
+    }
+  }
+  // one atomic per wavefront for the segment counter
+  for (int off = 32; off > 0; off >>= 1) seg_count += __shfl_xor(seg_count, off);
+  if (lane == 0) atomicAdd(&a.counters[kCntSegments], seg_count);
+  if (overflow) atomicOr(a.err, DCEM_ERR_STACK);
+  if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
+}
+
+__global__ void k_reset_counters(uint32_t* counters) {
+  if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
+}
+
+// Coherence pass.  A cached ray stays valid iff none of its hits in the cached
+// frame was on a moving face and none of its segments (the last one unbounded
+// on a miss) meets the padded box of any moving object now.  Valid rays would
+// be traced to exactly the same hits and captures, so they are reused; the
+// others are listed for re-tracing (wavefront-aggregated append).
+__global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o,
+                            const float4* __restrict__ seg_d, const float* __restrict__ obj_box, int n_obj,
+                            int n_work, uint8_t* __restrict__ invalid, uint32_t* __restrict__ list,
+                            uint32_t* counters) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  bool bad = false;
+  if (w < n_work) {
+    const uint32_t st = ray_state[w];
+    bad = (st & 0x80u) != 0;
+    const int nseg = (int)(st & 0x0fu);
+    for (int k = 0; k < nseg && !bad; ++k) {
+      const float4 o = seg_o[(size_t)k * n_work + w];
+      const float4 d = seg_d[(size_t)k * n_work + w];
+      Ray r;
+      r.o = make_float3(o.x, o.y, o.z);
+      r.d = make_float3(d.x, d.y, d.z);
+      const float tiny = 1e-30f;
+      r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny),
+                          __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
+                          __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
+      for (int b = 0; b < n_obj; ++b) {
+        const float* bx = obj_box + 6 * b;
+        float tn;
+        if (slab(r, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o.w, tn)) { bad = true; break; }
+      }
+    }
+    invalid[w] = bad ? 1 : 0;
+  }
+  const uint64_t m = __ballot(bad);
+  uint32_t base = 0;
+  if (lane == 0 && m) base = atomicAdd(&counters[kCntWork], (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)w;
+}
+
+// Keep the cached captures of valid rays (direct-path records are re-added).
+__global__ void k_filter_caps(const Capture* __restrict__ prev, uint32_t n_prev,
+                              const uint8_t* __restrict__ invalid, Capture* __restrict__ cur, uint32_t* counters) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  bool keep = false;
+  Capture c{};
+  if (i < n_prev) {
+    c = prev[i];
+    keep = c.work != kNoRay && !invalid[c.work];
+  }
+  const uint64_t m = __ballot(keep);
+  uint32_t base = 0;
+  if (lane == 0 && m) base = atomicAdd(&counters[kCntCaptures], (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (keep) cur[base + __popcll(m & ((1ull << lane) - 1ull))] = c;
+}
+
+__global__ void k_los(Capture* __restrict__ caps, uint32_t* counters, int n_pairs, int64_t cap_capacity,
+                      uint32_t* err) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const uint32_t slot = atomicAdd(&counters[kCntCaptures], 1u);
+  if (slot < cap_capacity) {
+    Capture c;
+    c.work = kNoRay;
+    c.pair_order = (uint32_t)p << 4;
+    caps[slot] = c;
+  } else {
+    atomicOr(err, DCEM_ERR_CAPTURES);
+  }
+}
+
+int trace_grid(int device) {
+  static int cus = 0;
+  if (cus == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus * 5;   // 32 KB of LDS stack per block: five blocks per CU
+}
+
+}  // namespace
+
+void launch_fibonacci(dcem_ctx* c) {
+  const int64_t n = c->n_rays;
+  hipLaunchKernelGGL(k_fibonacci, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, ptr<float>(c->dirs), n);
+}
+
+// Trace all work items (all_rays) or those listed by the coherence pass.
+void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_max) {
+  (void)n_work_max;
+  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  TraceArgs a;
+  a.nodes = ptr<Node>(c->nodes);
+  a.leaves = ptr<Leaf>(c->leaves);
+  a.n_internal = c->nt > 0 ? c->n_internal : 0;
+  a.dirs = ptr<float>(c->dirs);
+  a.tx = ptr<float>(c->tx_pos);
+  a.rx = ptr<float>(c->rx_pos);
+  a.n_rx = c->n_rx;
+  a.r2 = c->cfg.rx_radius * c->cfg.rx_radius;
+  float zlo = FLT_MAX, zhi = -FLT_MAX;
+  for (int i = 0; i < c->n_rx; ++i) {
+    zlo = fminf(zlo, c->cfg.rx[3 * i + 2]);
+    zhi = fmaxf(zhi, c->cfg.rx[3 * i + 2]);
+  }
+  // widen the culling slab well beyond rounding so it never changes a decision
+  const float rr = c->cfg.rx_radius * 1.001f + 1e-3f;
+  a.rx_zlo = zlo - rr;
+  a.rx_zhi = zhi + rr;
+  a.n_rays = c->n_rays;
+  a.n_work = (int)n_work;
+  a.work_list = all_rays ? nullptr : ptr<uint32_t>(c->work_list);
+  a.K = c->K;
+  a.face_object = ptr<int32_t>(c->face_object);
+  a.counters = ptr<uint32_t>(c->counters);
+  a.face_log = ptr<int32_t>(c->face_log);
+  a.ray_state = ptr<uint8_t>(c->ray_state);
+  a.seg_o = keep_cache ? ptr<float4>(c->seg_o) : nullptr;
+  a.seg_d = keep_cache ? ptr<float4>(c->seg_d) : nullptr;
+  a.log_tri = c->record_log ? ptr<int32_t>(c->log_tri) : nullptr;
+  a.log_t = c->record_log ? ptr<float>(c->log_t) : nullptr;
+  a.log_len = c->record_log ? ptr<float>(c->log_len) : nullptr;
+  a.caps = ptr<Capture>(c->caps[c->cur_caps]);
+  a.cap_capacity = c->cap_capacity;
+  a.err = ptr<uint32_t>(c->err_word);
+  hipLaunchKernelGGL(k_trace, dim3(trace_grid(c->device)), dim3(kTraceBlock), 0, c->stream, a);
+}
+
+void launch_reset_counters(dcem_ctx* c) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, ptr<uint32_t>(c->counters));
+}
+
+void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
+  const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
+  uint32_t* cnt = ptr<uint32_t>(c->counters);
+  hipLaunchKernelGGL(k_coherence, dim3((n_work + 255) / 256), dim3(256), 0, c->stream, ptr<uint8_t>(c->ray_state),
+                     ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<float>(c->obj_box), c->no, n_work,
+                     ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
+  const int prev = c->cur_caps ^ 1;
+  if (n_prev_caps == 0) return;
+  hipLaunchKernelGGL(k_filter_caps, dim3((n_prev_caps + 255) / 256), dim3(256), 0, c->stream,
+                     ptr<Capture>(c->caps[prev]), n_prev_caps, ptr<uint8_t>(c->invalid_flag),
+                     ptr<Capture>(c->caps[c->cur_caps]), cnt);
+}
+
+void launch_los(dcem_ctx* c) {
+  const int n_pairs = c->n_tx * c->n_rx;
+  hipLaunchKernelGGL(k_los, dim3((n_pairs + 255) / 256), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
+                     ptr<uint32_t>(c->counters), n_pairs, c->cap_capacity, ptr<uint32_t>(c->err_word));
+}
+
+}  // namespace dcem

@@ -1,0 +1,305 @@
+"""Python binding of libdcem (ctypes): argument marshalling only.
+
+Every step of a frame runs in the HIP kernels behind include/dcem.h; this
+module converts NumPy arrays or torch tensors to pointers, passes the caller's
+HIP stream, and turns status codes into exceptions.  It raises at import of a
+context if the shared library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcem.so")
+
+OK = 0
+E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+MODE_FULL, MODE_COHERENT = 0, 1
+FORCE_REBUILD = 1
+MAX_REFLECTIONS = 10
+
+_P = ctypes.c_void_p
+_I32, _I64, _F32, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("vertices", _P), ("n_vertices", _I64), ("tris", _P), ("tri_face", _P), ("n_tris", _I64),
+                ("face_material", _P), ("face_object", _P), ("n_faces", _I32), ("materials", _P),
+                ("n_materials", _I32), ("object_vertex_range", _P), ("n_objects", _I32), ("mem_kind", _I32)]
+
+
+class TraceParams(ctypes.Structure):
+    _fields_ = [("tx_pos", _P), ("n_tx", _I32), ("rx_pos", _P), ("n_rx", _I32), ("rx_radius", _F32),
+                ("n_rays", _I64), ("ray_dirs", _P), ("max_reflections", _I32), ("freqs_hz", _P),
+                ("n_freqs", _I32), ("tx_power_w", _F64), ("atten_db_per_km", _F64), ("mode", _I32),
+                ("los_always", _I32), ("keep_cache", _I32), ("record_trace_log", _I32), ("mem_kind", _I32)]
+
+
+class FrameStats(ctypes.Structure):
+    _fields_ = [("rays_total", _I64), ("rays_traced", _I64), ("rays_reused", _I64), ("segments", _I64),
+                ("captures", _I64), ("unique_candidates", _I64), ("valid_paths", _I64), ("rebuilt", _I32),
+                ("coherent", _I32), ("sah_ratio", _F64), ("ms_refit", _F32), ("ms_coherence", _F32),
+                ("ms_trace", _F32), ("ms_candidates", _F32), ("ms_refine", _F32), ("ms_reduce", _F32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# (name, restype, argtypes) of every exported entry point of include/dcem.h
+SIGNATURES = [
+    ("dcem_create", _I32, [ctypes.POINTER(_P), _I32, _P]),
+    ("dcem_destroy", None, [_P]),
+    ("dcem_last_error", ctypes.c_char_p, [_P]),
+    ("dcem_set_capture_capacity", _I32, [_P, _I64]),
+    ("dcem_set_timing", _I32, [_P, _I32]),
+    ("dcem_scene_upload", _I32, [_P, ctypes.POINTER(SceneDesc)]),
+    ("dcem_set_object_transforms", _I32, [_P, _P, _I32, _I32]),
+    ("dcem_refit_bvh", _I32, [_P, _I32, _F64, ctypes.POINTER(_I32), ctypes.POINTER(_F64)]),
+    ("dcem_trace_frame", _I32, [_P, ctypes.POINTER(TraceParams)]),
+    ("dcem_received_power", _I32, [_P, _P, _P, _I32]),
+    ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
+    ("dcem_get_trace_log", _I32, [_P, _P, _P, _P]),
+    ("dcem_get_captures", _I32, [_P, _I64, _P, ctypes.POINTER(_I64)]),
+    ("dcem_get_bvh", _I32, [_P, _I64, ctypes.POINTER(_I32), _P, _P, _P]),
+    ("dcem_get_vertices", _I32, [_P, _P]),
+    ("dcem_get_ray_dirs", _I32, [_P, _P]),
+    ("dcem_get_stats", _I32, [_P, ctypes.POINTER(FrameStats)]),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdcem.so; raises if it is missing (build it with paper_2112_07115_amd.build)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libdcem.so not built (%s); run `python -m paper_2112_07115_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+class DcemError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("dcem status %d: %s" % (status, message))
+        self.status = status
+
+
+def _addr(a) -> Optional[int]:
+    """Address of a contiguous NumPy array or torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+def _kind(a) -> int:
+    if a is None or isinstance(a, np.ndarray):
+        return MEM_HOST
+    return MEM_DEVICE if a.is_cuda else MEM_HOST
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Context:
+    """One dcem context: a device, a HIP stream and the scene, BVH and ray cache on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load_library()
+        if stream is None:
+            # follow torch's current stream when torch is in use; else the null stream
+            torch = sys.modules.get("torch")
+            stream = torch.cuda.current_stream(device).cuda_stream if torch is not None else 0
+        self.handle = _P()
+        st = self.lib.dcem_create(ctypes.byref(self.handle), device, _P(stream or None))
+        if st != OK:
+            raise DcemError(st, "dcem_create failed (device %d)" % device)
+        self._keep = []
+        self.K = 0
+        self.n_freqs = 1
+        self.n_tx = self.n_rx = 0
+        self.n_rays = 0
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.dcem_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            raise DcemError(st, self.lib.dcem_last_error(self.handle).decode())
+
+    def set_capture_capacity(self, n: int):
+        self._check(self.lib.dcem_set_capture_capacity(self.handle, int(n)))
+
+    def set_timing(self, on: bool = True):
+        self._check(self.lib.dcem_set_timing(self.handle, 1 if on else 0))
+
+    def scene_upload(self, scene):
+        """Upload a scene (object with the arrays of paper_2112_07115_amd.scenes.Scene)."""
+        arrs = [_host(scene.vertices, np.float32), _host(scene.tris, np.int32),
+                _host(scene.tri_face, np.int32), _host(scene.face_material, np.int32),
+                _host(scene.face_object, np.int32), _host(scene.materials, np.float64),
+                _host(scene.object_vertex_range, np.int64)]
+        V, T, TF, FM, FO, M, OR = arrs
+        d = SceneDesc(_addr(V), V.shape[0], _addr(T), _addr(TF), T.shape[0], _addr(FM), _addr(FO),
+                      FM.shape[0], _addr(M), M.shape[0], _addr(OR), OR.shape[0], MEM_HOST)
+        self._check(self.lib.dcem_scene_upload(self.handle, ctypes.byref(d)))
+        self.n_vertices = V.shape[0]
+        self.n_tris = T.shape[0]
+        self.n_objects = OR.shape[0]
+
+    def set_object_transforms(self, xf):
+        a = xf if not isinstance(xf, np.ndarray) else _host(xf, np.float32)
+        n = int(a.shape[0])
+        self._check(self.lib.dcem_set_object_transforms(self.handle, _addr(a), n, _kind(a)))
+
+    def refit_bvh(self, force_rebuild: bool = False, threshold: float = 1.5):
+        rb = _I32(0)
+        ratio = _F64(0.0)
+        self._check(self.lib.dcem_refit_bvh(self.handle, FORCE_REBUILD if force_rebuild else 0,
+                                            float(threshold), ctypes.byref(rb), ctypes.byref(ratio)))
+        return bool(rb.value), float(ratio.value)
+
+    def trace_frame(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None,
+                    max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
+                    tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
+                    los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False):
+        dev = ray_dirs is not None and not isinstance(ray_dirs, np.ndarray) and ray_dirs.is_cuda
+        if dev:
+            txa, rxa, dirs = tx, rx, ray_dirs
+        else:
+            txa, rxa = _host(tx, np.float32).reshape(-1, 3), _host(rx, np.float32).reshape(-1, 3)
+            dirs = None if ray_dirs is None else _host(ray_dirs, np.float32).reshape(-1, 3)
+        fr = _host(freqs_hz, np.float64).reshape(-1)
+        self._keep = [txa, rxa, dirs, fr]
+        p = TraceParams(_addr(txa), int(txa.shape[0]), _addr(rxa), int(rxa.shape[0]), float(rx_radius),
+                        int(n_rays), _addr(dirs), int(max_reflections), _addr(fr), int(fr.shape[0]),
+                        float(tx_power_w), float(atten_db_per_km), int(mode), int(bool(los_always)),
+                        int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST)
+        self._check(self.lib.dcem_trace_frame(self.handle, ctypes.byref(p)))
+        self.K = int(max_reflections)
+        self.n_freqs = int(fr.shape[0])
+        self.n_tx, self.n_rx = int(txa.shape[0]), int(rxa.shape[0])
+        self.n_rays = int(n_rays)
+
+    def received_power(self, out=None):
+        """(p_coh, p_inc) [n_freqs, n_tx, n_rx] FP64; host arrays unless `out` tensors are given."""
+        shape = (self.n_freqs, self.n_tx, self.n_rx)
+        if out is None:
+            pc = np.empty(shape, np.float64)
+            pi = np.empty(shape, np.float64)
+        else:
+            pc, pi = out
+        self._check(self.lib.dcem_received_power(self.handle, _addr(pc), _addr(pi), _kind(pc)))
+        return pc, pi
+
+    def stats(self) -> dict:
+        s = FrameStats()
+        self._check(self.lib.dcem_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def paths(self) -> dict:
+        n = _I64(0)
+        self._check(self.lib.dcem_get_paths(self.handle, 0, None, None, None, None, None, None, None, None,
+                                            ctypes.byref(n)))
+        m = int(n.value)
+        K, nf = self.K, self.n_freqs
+        out = {"keys": np.zeros((m, 3 + K), np.int32), "valid": np.zeros(m, np.uint8),
+               "length": np.zeros(m), "tau": np.zeros(m), "aod": np.zeros((m, 3)), "aoa": np.zeros((m, 3)),
+               "amp": np.zeros((m, nf, 3, 2)), "first_ray": np.zeros(m, np.int32)}
+        if m:
+            self._check(self.lib.dcem_get_paths(self.handle, m, _addr(out["keys"]), _addr(out["valid"]),
+                                                _addr(out["length"]), _addr(out["tau"]), _addr(out["aod"]),
+                                                _addr(out["aoa"]), _addr(out["amp"]), _addr(out["first_ray"]),
+                                                ctypes.byref(n)))
+        out["valid"] = out["valid"].astype(bool)
+        out["amp"] = out["amp"][..., 0] + 1j * out["amp"][..., 1]
+        return out
+
+    def trace_log(self):
+        shp = (self.n_tx, self.n_rays, self.K + 1)
+        tri = np.empty(shp, np.int32)
+        t = np.empty(shp, np.float32)
+        length = np.empty(shp, np.float32)
+        self._check(self.lib.dcem_get_trace_log(self.handle, _addr(tri), _addr(t), _addr(length)))
+        return tri, t, length
+
+    def captures(self) -> np.ndarray:
+        n = _I64(0)
+        self._check(self.lib.dcem_get_captures(self.handle, 0, None, ctypes.byref(n)))
+        rows = np.zeros((int(n.value), 4 + self.K), np.int32)
+        if n.value:
+            self._check(self.lib.dcem_get_captures(self.handle, rows.shape[0], _addr(rows), ctypes.byref(n)))
+        return rows
+
+    def bvh(self):
+        ni = _I32(0)
+        self._check(self.lib.dcem_get_bvh(self.handle, 0, ctypes.byref(ni), None, None, None))
+        n = int(ni.value)
+        child = np.zeros((n, 2), np.int32)
+        box = np.zeros((n, 2, 6), np.float32)
+        leaf_tri = np.zeros(self.n_tris, np.int32)
+        self._check(self.lib.dcem_get_bvh(self.handle, n, ctypes.byref(ni), _addr(child), _addr(box),
+                                          _addr(leaf_tri)))
+        return child, box, leaf_tri
+
+    def vertices(self) -> np.ndarray:
+        out = np.empty((self.n_vertices, 3), np.float32)
+        self._check(self.lib.dcem_get_vertices(self.handle, _addr(out)))
+        return out
+
+    def ray_dirs(self) -> np.ndarray:
+        out = np.empty((self.n_rays, 3), np.float32)
+        self._check(self.lib.dcem_get_ray_dirs(self.handle, _addr(out)))
+        return out
+
+
+@dataclass
+class FrameOutput:
+    p_coh: np.ndarray
+    p_inc: np.ndarray
+
+
+def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL, ray_dirs=None,
+                      n_rays: Optional[int] = None, K: Optional[int] = None, rebuild: bool = False,
+                      keep_cache: bool = False, record_trace_log: bool = False, los_always: bool = True,
+                      threshold: float = 1.5) -> FrameOutput:
+    """Convenience: place the scene's objects for `frame`, update the BVH, trace, read power."""
+    if scene.object_vertex_range.shape[0]:
+        ctx.set_object_transforms(scene.transforms(frame))
+        ctx.refit_bvh(force_rebuild=rebuild, threshold=threshold)
+    n = scene.n_rays if n_rays is None else n_rays
+    if ray_dirs is not None:
+        n = ray_dirs.shape[0]
+    ctx.trace_frame(scene.tx, scene.rx, scene.rx_radius, n, ray_dirs=ray_dirs,
+                    max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
+                    tx_power_w=scene.tx_power_w, mode=mode, los_always=los_always, keep_cache=keep_cache,
+                    record_trace_log=record_trace_log)
+    pc, pi = ctx.received_power()
+    return FrameOutput(pc, pi)

@@ -1,0 +1,182 @@
+"""Comparison of the GPU library's outputs with the CPU oracle.
+
+The oracle marks, per ray segment, the decisions an FP32 tracer may take
+differently (hits within eps of a face silhouette, near misses before the hit,
+ties within 1e-6 relative, hits near t_min, capture distances within eps of the
+radius).  Everything else must agree exactly:
+  - hit triangle ids and reflection orders bit-exact on every segment before
+    the first uncertain one (only the face is compared where the oracle marks
+    the triangle id alone as uncertain);
+  - hit distances and cumulative lengths within the FP32 tolerance;
+  - per-ray captures: every certain oracle capture is found, nothing outside
+    the oracle's possible set before an uncertain segment;
+  - candidate keys: every certain key found; every extra key traced back to a
+    ray whose path is uncertain;
+  - refined paths (FP64 on both sides): validity, length within 1e-9
+    relative, field amplitude within 1e-6 relative;
+  - received power within 0.01 dB for every receiver whose path set is
+    certain on both sides.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEG_TIE, SEG_EDGE, SEG_TRI = 1, 2, 4
+CAP_HIT, CAP_MARGINAL, CAP_UNCERTAIN = 1, 2, 4
+
+
+def first_uncertain(flags: np.ndarray) -> np.ndarray:
+    """Index of the first segment with SEG_TIE/SEG_EDGE (K+1 if none); flags [..., K+1]."""
+    unc = (flags & (SEG_TIE | SEG_EDGE)) != 0
+    K1 = flags.shape[-1]
+    idx = np.where(unc.any(axis=-1), unc.argmax(axis=-1), K1)
+    return idx
+
+
+def compare_trace(g_tri, g_t, g_len, o, tri_face, eps_rel=4e-6, radius=1.0):
+    """g_*: GPU log rows for the same rays as the oracle TraceResult `o` ([ntx, n, K+1]).
+
+    Returns a dict of counts; raises AssertionError listing the first mismatches."""
+    K1 = o.tri.shape[-1]
+    fu = first_uncertain(o.flags)
+    ks = np.arange(K1)
+    check = ks[None, None, :] < fu[..., None]
+    o_tri, g_tri = o.tri, g_tri
+    same_tri = o_tri == g_tri
+    tri_only = (o.flags & SEG_TRI) != 0
+    o_face = np.where(o_tri >= 0, tri_face[np.maximum(o_tri, 0)], o_tri)
+    g_face = np.where(g_tri >= 0, tri_face[np.maximum(g_tri, 0)], g_tri)
+    ok = np.where(tri_only, o_face == g_face, same_tri)
+    bad = check & ~ok
+    msgs = []
+    if bad.any():
+        for (t, r, k) in np.argwhere(bad)[:10]:
+            msgs.append("tx %d ray %d bounce %d: oracle tri %d (flags %d) gpu tri %d" %
+                        (t, r, k, o_tri[t, r, k], o.flags[t, r, k], g_tri[t, r, k]))
+    hit = check & (o_tri >= 0) & ok
+    # FP32 distances against FP64: positions agree to eps_rel * (k+1) * (R + L)
+    tol = eps_rel * (ks[None, None, :] + 1) * (radius + np.where(np.isfinite(o.length), o.length, 0.0))
+    dt = np.abs(g_t.astype(np.float64) - o.t)
+    dl = np.abs(g_len.astype(np.float64) - o.length)
+    bad_t = hit & ((dt > tol) | (dl > tol))
+    if bad_t.any():
+        for (t, r, k) in np.argwhere(bad_t)[:10]:
+            msgs.append("tx %d ray %d bounce %d: t %.9g vs %.9g, len %.9g vs %.9g" %
+                        (t, r, k, g_t[t, r, k], o.t[t, r, k], g_len[t, r, k], o.length[t, r, k]))
+    rel_len = np.where(hit, dl / np.maximum(o.length, 1e-30), 0.0)
+    stats = {
+        "rays": int(np.prod(fu.shape)),
+        "rays_fully_certain": int((fu == K1).sum()),
+        "segments_checked": int(check.sum()),
+        "segments_hit_checked": int(hit.sum()),
+        "tri_only": int((check & tri_only).sum()),
+        "max_rel_len_err": float(rel_len.max()) if hit.any() else 0.0,
+        "max_abs_t_err": float(np.where(hit, dt, 0).max()) if hit.any() else 0.0,
+    }
+    assert not msgs, "\n".join(msgs)
+    return stats
+
+
+def _cap_tuples(rows, ray_col, n_rays_total=None):
+    return {tuple(int(x) for x in r) for r in rows}
+
+
+def compare_captures(g_rows, o, ray_index, n_rays):
+    """g_rows: GPU captures (ray=work, tx, rx, order, faces...) restricted to the
+    compared rays; o: oracle TraceResult over those rays (caps' ray column holds the
+    ray index); ray_index: mapping oracle ray id -> row position in o's arrays."""
+    fu = first_uncertain(o.flags)
+    K = o.tri.shape[-1] - 1
+    # normalise GPU rows to (tx, ray, rx, order, faces...)
+    g = set()
+    for r in g_rows:
+        work, tx = int(r[0]), int(r[1])
+        ray = work - tx * n_rays
+        g.add((tx, ray, int(r[2]), int(r[3])) + tuple(int(x) for x in r[4:4 + K]))
+    certain, possible, late = set(), set(), set()
+    for row, fl in zip(o.caps, o.cap_flags):
+        ray, tx, rx, order = int(row[0]), int(row[1]), int(row[2]), int(row[3])
+        key = (tx, ray, rx, order) + tuple(int(x) for x in row[4:4 + K])
+        possible.add(key)
+        if fl == CAP_HIT:
+            certain.add(key)
+    missing = certain - g
+    extra = set()
+    for key in g - possible:
+        tx, ray, order = key[0], key[1], key[3]
+        if order < fu[tx, ray_index[ray]]:
+            extra.add(key)
+    assert not missing, "certain oracle captures not found on the GPU: %s" % sorted(missing)[:10]
+    assert not extra, "GPU captures outside the oracle's possible set: %s" % sorted(extra)[:10]
+    return {"gpu_captures": len(g), "oracle_certain": len(certain), "oracle_possible": len(possible)}
+
+
+def compare_paths(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6, tol_db=0.01,
+                  min_comparable=0.9):
+    """Candidate keys, refined paths and per-receiver power of one frame."""
+    K = ofr.keys.shape[1] - 3
+    gk = {tuple(int(x) for x in k): i for i, k in enumerate(gp["keys"])}
+    ok_ = {tuple(int(x) for x in k): i for i, k in enumerate(ofr.keys)}
+    cert = {k for k, i in ok_.items() if ofr.certain[i]}
+    poss = {tuple(int(x) for x in k) for k in ofr.possible}
+    missing = cert - set(gk)
+    assert not missing, "certain keys missing on the GPU: %s" % sorted(missing)[:10]
+    fu = first_uncertain(ofr.trace.flags)
+    unexplained = []
+    for k, i in gk.items():
+        if k in poss:
+            continue
+        fr = int(gp["first_ray"][i])
+        if fr < 0:
+            unexplained.append(k)
+            continue
+        tx, ray = fr // n_rays, fr % n_rays
+        if k[2] < fu[tx, ray]:
+            unexplained.append(k)
+    assert not unexplained, "GPU keys the oracle cannot explain: %s" % unexplained[:10]
+    # path attributes for common keys
+    n_common = 0
+    bad = []
+    for k, i in gk.items():
+        j = ok_.get(k)
+        if j is None:
+            continue
+        n_common += 1
+        if ofr.paths.marginal[j]:
+            continue
+        if bool(gp["valid"][i]) != bool(ofr.paths.valid[j]):
+            bad.append((k, "valid", bool(gp["valid"][i]), bool(ofr.paths.valid[j])))
+            continue
+        if not ofr.paths.valid[j]:
+            continue
+        lo = ofr.paths.length[j]
+        if abs(gp["length"][i] - lo) > eps_len * lo:
+            bad.append((k, "length", gp["length"][i], lo))
+        ao = ofr.paths.amp[j]
+        if np.linalg.norm(gp["amp"][i] - ao) > eps_amp * np.linalg.norm(ao) + 1e-300:
+            bad.append((k, "amp", gp["amp"][i].tolist(), ao.tolist()))
+    assert not bad, "path mismatches: %s" % bad[:5]
+    # per-receiver power
+    ntx, nrx = ofr.p_coh.shape[1], ofr.p_coh.shape[2]
+    comparable = np.ones((ntx, nrx), bool)
+    for k, i in ok_.items():
+        if (not ofr.certain[i]) or ofr.paths.marginal[i]:
+            comparable[k[0], k[1]] = False
+    for k in gk:
+        if k not in cert:
+            comparable[k[0], k[1]] = False
+    for k in poss:
+        if k not in cert:
+            comparable[k[0], k[1]] = False
+    return comparable, n_common
+
+
+def compare_power(g_pc, o_pc, comparable, tol_db=0.01):
+    both0 = (g_pc == 0) & (o_pc == 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        db = np.abs(10 * np.log10(g_pc / o_pc))
+    db = np.where(both0, 0.0, db)
+    sel = np.broadcast_to(comparable, db.shape)
+    worst = float(np.max(db[sel])) if sel.any() else 0.0
+    assert worst <= tol_db, "power differs by %.4g dB on a comparable receiver" % worst
+    return worst

@@ -1,0 +1,91 @@
+"""GPU: frame-to-frame coherence reproduces the full re-trace exactly, refit and
+rebuild give the same hits, and repeated runs are bitwise identical."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2112_07115_amd import dcem, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def frame_outputs(ctx):
+    pc, pi = ctx.received_power()
+    p = ctx.paths()
+    tri, t, length = ctx.trace_log()
+    return pc, pi, p, tri, t, length
+
+
+def assert_same(a, b):
+    pc0, pi0, p0, tri0, t0, l0 = a
+    pc1, pi1, p1, tri1, t1, l1 = b
+    assert np.array_equal(tri0, tri1)
+    assert np.array_equal(t0, t1, equal_nan=True) and np.array_equal(l0, l1, equal_nan=True)
+    for k in ["keys", "valid", "length", "tau", "aod", "aoa", "amp", "first_ray"]:
+        assert np.array_equal(p0[k], p1[k]), k
+    assert np.array_equal(pc0, pc1) and np.array_equal(pi0, pi1)
+
+
+def test_coherent_equals_full_retrace():
+    s = scenes.dynamic_urban()
+    n = 1 << 17
+    full, coh = dcem.Context(0), dcem.Context(0)
+    full.scene_upload(s)
+    coh.scene_upload(s)
+    traced = []
+    for frame in range(0, 12):
+        log("frame", frame)
+        xf = s.transforms(frame)
+        full.set_object_transforms(xf)
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=s.freqs_hz,
+                         tx_power_w=s.tx_power_w, mode=dcem.MODE_FULL, record_trace_log=True)
+        coh.set_object_transforms(xf)
+        coh.refit_bvh()
+        coh.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=s.freqs_hz,
+                        tx_power_w=s.tx_power_w, mode=dcem.MODE_COHERENT, record_trace_log=True)
+        assert_same(frame_outputs(full), frame_outputs(coh))
+        st = coh.stats()
+        traced.append(st["rays_traced"])
+        log("  coherent: traced", st["rays_traced"], "reused", st["rays_reused"], "paths", st["valid_paths"])
+        if frame > 0:
+            assert st["coherent"] == 1 and st["rays_traced"] < n
+    full.close()
+    coh.close()
+
+
+def test_refit_equals_rebuild():
+    s = scenes.dynamic_urban()
+    a, b = dcem.Context(0), dcem.Context(0)
+    a.scene_upload(s)
+    b.scene_upload(s)
+    xf = s.transforms(40)
+    a.set_object_transforms(xf)
+    a.refit_bvh(threshold=float("inf"))
+    b.set_object_transforms(xf)
+    b.refit_bvh(force_rebuild=True)
+    for c in (a, b):
+        c.trace_frame(s.tx, s.rx, s.rx_radius, 1 << 16, max_reflections=4, freqs_hz=s.freqs_hz,
+                      record_trace_log=True)
+    assert_same(frame_outputs(a), frame_outputs(b))
+    a.close()
+    b.close()
+
+
+def test_repeat_runs_bitwise_identical():
+    s = scenes.dynamic_urban()
+    c = dcem.Context(0)
+    c.scene_upload(s)
+    outs = []
+    for _ in range(2):
+        c.trace_frame(s.tx, s.rx, s.rx_radius, 1 << 18, max_reflections=4, freqs_hz=s.freqs_hz,
+                      record_trace_log=True)
+        outs.append(frame_outputs(c))
+    assert_same(outs[0], outs[1])
+    c.close()

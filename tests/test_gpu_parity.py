@@ -1,0 +1,213 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Workloads: the static toy scene (4096 Fibonacci rays, K = 2, 50 triangles),
+the same scene with 200k random rays, the dynamic urban grid (32k triangles,
+K = 4) at several frames with random-ray subsets, and the full-size urban frame
+(2^20 Fibonacci rays) compared on sampled rays and oracle-derived paths.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2112_07115_amd import dcem, scenes
+from tests import parity
+from tests.bvh_check import check_bvh
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.build()
+    return oracle
+
+
+@pytest.fixture()
+def ctx():
+    c = dcem.Context(0)
+    yield c
+    c.close()
+
+
+def radius_of(scene):
+    pts = np.concatenate([scene.vertices, scene.tx, scene.rx]).astype(np.float64)
+    return float(np.linalg.norm(pts, axis=1).max())
+
+
+def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True):
+    """Trace one frame on both sides and compare everything; returns stats."""
+    K = scene.max_reflections if K is None else K
+    log("case", scene.name, "frame", frame, "K", K, "rays", n_rays if dirs is None else len(dirs))
+    ctx.scene_upload(scene)
+    out = dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=dirs, n_rays=n_rays, K=K,
+                                 record_trace_log=True)
+    g_tri, g_t, g_len = ctx.trace_log()
+    if dirs is None:
+        g_dirs = ctx.ray_dirs()
+        o_dirs = O.fibonacci(n_rays or scene.n_rays)
+        assert np.array_equal(g_dirs, o_dirs), "Fibonacci directions differ"
+    else:
+        o_dirs = dirs
+    ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K)
+    st = parity.compare_trace(g_tri, g_t, g_len, ofr.trace, scene.tri_face, radius=radius_of(scene))
+    log("  trace", st)
+    n = o_dirs.shape[0]
+    if check_captures:
+        g_caps = ctx.captures()
+        g_caps = g_caps[g_caps[:, 0] >= 0]
+        cs = parity.compare_captures(g_caps, ofr.trace, np.arange(n), n)
+        log("  captures", cs)
+    if check_paths:
+        gp = ctx.paths()
+        comparable, n_common = parity.compare_paths(gp, ofr, n)
+        worst = parity.compare_power(out.p_coh, ofr.p_coh, comparable)
+        log("  paths: gpu %d oracle %d common %d; comparable rx %d/%d; worst %.2e dB" %
+            (len(gp["keys"]), len(ofr.keys), n_common, comparable.sum(), comparable.size, worst))
+        st["comparable"] = float(comparable.mean())
+    return st, out, ofr
+
+
+def test_static_toy_full(ctx, O):
+    s = scenes.static_toy()
+    st, out, ofr = run_pair(ctx, O, s)
+    assert st["rays_fully_certain"] > 0.98 * st["rays"]
+    assert st["comparable"] >= 0.8
+
+
+def test_static_toy_dense_random_rays(ctx, O):
+    s = scenes.static_toy()
+    dirs = scenes.random_sphere_dirs(200_000, seed=5)
+    st, out, ofr = run_pair(ctx, O, s, dirs=dirs)
+    assert st["rays_fully_certain"] > 0.98 * st["rays"]
+    assert len(ofr.keys) > 30
+
+
+def test_ragged_ray_counts_and_orders(ctx, O):
+    s = scenes.static_toy()
+    for n, K in [(1, 2), (63, 0), (65, 3), (1000, 10)]:
+        dirs = scenes.random_sphere_dirs(n, seed=100 + n)
+        run_pair(ctx, O, s, dirs=dirs, K=K)
+
+
+def test_urban_frames_random_subset(ctx, O):
+    s = scenes.dynamic_urban()
+    dirs = scenes.random_sphere_dirs(8192, seed=7)
+    for frame in [0, 1, 30, 59]:
+        st, out, ofr = run_pair(ctx, O, s, frame=frame, dirs=dirs)
+        assert st["rays_fully_certain"] > 0.95 * st["rays"]
+
+
+def test_urban_full_size_sampled(ctx, O):
+    """Full 2^20-ray frame as the benchmark launches it; oracle on every 512th ray."""
+    s = scenes.dynamic_urban()
+    log("case urban full size, frame 0")
+    ctx.scene_upload(s)
+    dcem.trace_scene_frame(ctx, s, frame=0, record_trace_log=True)
+    g_tri, g_t, g_len = ctx.trace_log()
+    g_dirs = ctx.ray_dirs()
+    o_dirs = O.fibonacci(s.n_rays)
+    assert np.array_equal(g_dirs, o_dirs)
+    ids = np.arange(0, s.n_rays, 512, dtype=np.int64)
+    osc = O.OracleScene(s, s.transforms(0))
+    otr = O.trace(osc, s.tx, s.rx, s.rx_radius, o_dirs, s.max_reflections, ray_ids=ids)
+    st = parity.compare_trace(g_tri[:, ids], g_t[:, ids], g_len[:, ids], otr, s.tri_face, radius=radius_of(s))
+    log("  sampled trace", st)
+    g_caps = ctx.captures()
+    sel = np.isin(g_caps[:, 0], ids)
+    pos = {int(r): i for i, r in enumerate(ids)}
+    parity.compare_captures(g_caps[sel], otr, pos, s.n_rays)
+    # oracle-derived keys: certain captures of the sampled rays, refined by the oracle
+    hit = otr.caps[otr.cap_flags == parity.CAP_HIT][:, 1:]
+    keys = np.unique(hit, axis=0)
+    gp = ctx.paths()
+    gk = {tuple(int(x) for x in k): i for i, k in enumerate(gp["keys"])}
+    op = O.refine(osc, s.tx, s.rx, keys, s.max_reflections, s.freqs_hz, s.tx_power_w)
+    checked = 0
+    for j, k in enumerate(keys):
+        i = gk.get(tuple(int(x) for x in k))
+        assert i is not None, "oracle key %s not found on the GPU" % (k,)
+        if op.marginal[j]:
+            continue
+        assert bool(gp["valid"][i]) == bool(op.valid[j])
+        if op.valid[j]:
+            assert abs(gp["length"][i] - op.length[j]) <= 1e-9 * op.length[j]
+            assert np.linalg.norm(gp["amp"][i] - op.amp[j]) <= 1e-6 * np.linalg.norm(op.amp[j])
+            checked += 1
+    log("  oracle-derived paths checked", checked, "of", len(keys))
+    assert checked > 20
+    # power is the coherent sum of the GPU's own valid paths (key order)
+    pc, pi = ctx.received_power()
+    acc = np.zeros((1, 1, s.rx.shape[0], 3), complex)
+    for i, k in enumerate(gp["keys"]):
+        if gp["valid"][i]:
+            acc[:, k[0], k[1]] += gp["amp"][i]
+    np.testing.assert_allclose(pc, np.sum(np.abs(acc) ** 2, axis=-1), rtol=1e-9, atol=0)
+
+
+def test_multi_tx_multi_freq(ctx, O):
+    s = scenes.static_toy()
+    s2 = scenes.Scene(**{**s.__dict__, "tx": np.array([[0, 0, 5], [-60, 10, 3]], np.float32),
+                         "freqs_hz": [28e9, 60e9]})
+    dirs = scenes.random_sphere_dirs(50_000, seed=9)
+    st, out, ofr = run_pair(ctx, O, s2, dirs=dirs)
+    assert out.p_coh.shape == (2, 2, 16)
+
+
+def test_free_space_and_single_triangle(ctx, O):
+    fs = scenes.free_space([[0, 0, 5]], [[10, 0, 5], [0, 30, 1]], n_rays=512, max_reflections=2)
+    st, out, ofr = run_pair(ctx, O, fs)
+    mb = scenes._MeshBuilder()
+    mb.add_polygon_face([[-5, -5, 0], [5, -5, 0], [0, 5, 0]], [[0, 1, 2]], material=0)
+    one = mb.finish("one_triangle", [scenes.GROUND], [[0, 0, 3]], [[1, 1, 1.5], [2, -1, 2.0]],
+                    n_rays=4096, max_reflections=2)
+    run_pair(ctx, O, one)
+
+
+def test_bvh_invariants_build_refit_rebuild(ctx):
+    s = scenes.dynamic_urban(n_rays=4096)
+    ctx.scene_upload(s)
+    pad = 4e-6 * (2.0 * float(np.abs(s.vertices).max()) + 1.0)
+    child, box, leaf = ctx.bvh()
+    V = ctx.vertices()
+    assert check_bvh(child, box, leaf, V, s.tris, pad=np.float32(pad), exact=True) == []
+    for frame in [1, 30, 59]:
+        ctx.set_object_transforms(s.transforms(frame))
+        rebuilt, ratio = ctx.refit_bvh(threshold=float("inf"))
+        assert not rebuilt and ratio >= 1.0
+        child, box, leaf = ctx.bvh()
+        V = ctx.vertices()
+        assert check_bvh(child, box, leaf, V, s.tris, pad=np.float32(pad), exact=True) == []
+        log("frame", frame, "sah ratio", ratio)
+    rebuilt, ratio = ctx.refit_bvh(force_rebuild=True)
+    assert rebuilt and ratio == 1.0
+    child, box, leaf = ctx.bvh()
+    assert check_bvh(child, box, leaf, ctx.vertices(), s.tris, pad=np.float32(pad), exact=True) == []
+
+
+def test_transform_matches_oracle_geometry(ctx, O):
+    s = scenes.dynamic_urban(n_rays=4096)
+    ctx.scene_upload(s)
+    xf = s.transforms(45)
+    ctx.set_object_transforms(xf)
+    ctx.refit_bvh()
+    V = ctx.vertices()
+    want = s.vertices.copy()
+    for o, (b, e) in enumerate(s.object_vertex_range):
+        v = s.vertices[b:e].astype(np.float64)
+        m = xf[o].astype(np.float64)
+        w = np.zeros_like(v)
+        for r in range(3):
+            acc = m[r, 0] * v[:, 0]
+            acc = acc + m[r, 1] * v[:, 1]
+            acc = acc + m[r, 2] * v[:, 2]
+            acc = acc + m[r, 3]
+            w[:, r] = acc
+        want[b:e] = w.astype(np.float32)
+    assert np.array_equal(V, want)
