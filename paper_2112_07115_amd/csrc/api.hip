@@ -462,9 +462,9 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   }
   ev_record(c, 1);
   if (n_work > 0) launch_trace(c, !coherent, keep_cache, n_work);
+  ev_record(c, 2);
   if (p->los_always) launch_los(c);
   HIP_TRY(hipGetLastError(), "trace kernels");
-  ev_record(c, 2);
   launch_face_planes(c);
   HIP_TRY(build_candidates(c), "candidates");
   ev_record(c, 3);
@@ -507,6 +507,11 @@ dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
   s.captures = c->n_caps_host;
   s.unique_candidates = cnt[kCntUnique];
   s.valid_paths = cnt[kCntValid];
+  uint64_t nodes = 0, tris = 0;
+  std::memcpy(&nodes, &cnt[kCntNodes], 8);
+  std::memcpy(&tris, &cnt[kCntTris], 8);
+  s.nodes_visited = (int64_t)nodes;
+  s.tri_tests = (int64_t)tris;
   s.rebuilt = c->last_rebuilt;
   s.sah_ratio = c->sah_last;
   s.ms_coherence = ev_ms(c, 0, 1);

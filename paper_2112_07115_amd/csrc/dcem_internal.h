@@ -125,7 +125,9 @@ enum : int {
   kCntUnique = 3,     // unique candidates
   kCntSegments = 4,   // closest-hit queries executed
   kCntValid = 5,      // valid paths
-  kCntSlots = 8,      // number of counters
+  kCntNodes = 6,      // BVH nodes visited by the trace kernel (64-bit, slots 6-7)
+  kCntTris = 8,       // triangle tests of the trace kernel (64-bit, slots 8-9)
+  kCntSlots = 10,     // number of counter words
 };
 
 hipError_t ensure(DevBuf& b, size_t bytes);

@@ -109,7 +109,8 @@ __device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ leaves, 
 // shape: boxes are conservative and nodes are pruned only when their entry
 // distance exceeds the current best (ties are still visited).
 __device__ Hit closest_hit(const Ray& r, const Node* __restrict__ nodes, const Leaf* __restrict__ leaves,
-                           int n_internal, int excl, int* stack, int stride, bool& overflow) {
+                           int n_internal, int excl, int* stack, int stride, bool& overflow, uint32_t& n_nodes,
+                           uint32_t& n_tris) {
   Hit h{FLT_MAX, -1, -1, -1};
   if (n_internal == 0) return h;
   int node = 0, sp = 0;
@@ -118,12 +119,13 @@ __device__ Hit closest_hit(const Ray& r, const Node* __restrict__ nodes, const L
   for (int64_t guard = 2 * (int64_t)n_internal + 2;; --guard) {
     if (guard == 0) { overflow = true; break; }
     const Node nd = nodes[node];
+    ++n_nodes;
     float t0, t1;
     bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, h.t, t0);
     bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, h.t, t1);
     const int c0 = nd.c.x, c1 = nd.c.y;
-    if (h0 && c0 < 0) { test_leaf(r, leaves, ~c0, excl, h); h0 = false; }
-    if (h1 && c1 < 0) { test_leaf(r, leaves, ~c1, excl, h); h1 = false; }
+    if (h0 && c0 < 0) { test_leaf(r, leaves, ~c0, excl, h); h0 = false; ++n_tris; }
+    if (h1 && c1 < 0) { test_leaf(r, leaves, ~c1, excl, h); h1 = false; ++n_tris; }
     if (h0 && h1) {
       int nearc = c0, farc = c1;
       if (t1 < t0) { nearc = c1; farc = c0; }
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   int* stack = stack_mem + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t n_work = a.work_list ? a.counters[kCntWork] : (uint32_t)a.n_work;
-  uint32_t seg_count = 0;
+  uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
   while (true) {
     uint32_t base = 0;
@@ -214,7 +216,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       uint32_t state = 0;
       int k = 0;
       for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes, a.leaves, a.n_internal, excl, stack, kTraceBlock, overflow);
+        Hit h = closest_hit(r, a.nodes, a.leaves, a.n_internal, excl, stack, kTraceBlock, overflow, node_count,
+                            tri_count);
         ++seg_count;
         const bool hit = h.tri >= 0;
         const float tend = hit ? h.t : INFINITY;
@@ -282,8 +285,16 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     }
   }
   // one atomic per wavefront for the segment counter
-  for (int off = 32; off > 0; off >>= 1) seg_count += __shfl_xor(seg_count, off);
-  if (lane == 0) atomicAdd(&a.counters[kCntSegments], seg_count);
+  for (int off = 32; off > 0; off >>= 1) {
+    seg_count += __shfl_xor(seg_count, off);
+    node_count += __shfl_xor(node_count, off);
+    tri_count += __shfl_xor(tri_count, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[kCntSegments], seg_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntNodes]), (unsigned long long)node_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntTris]), (unsigned long long)tri_count);
+  }
   if (overflow) atomicOr(a.err, DCEM_ERR_STACK);
   if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }

@@ -44,7 +44,8 @@ class TraceParams(ctypes.Structure):
 
 class FrameStats(ctypes.Structure):
     _fields_ = [("rays_total", _I64), ("rays_traced", _I64), ("rays_reused", _I64), ("segments", _I64),
-                ("captures", _I64), ("unique_candidates", _I64), ("valid_paths", _I64), ("rebuilt", _I32),
+                ("captures", _I64), ("unique_candidates", _I64), ("valid_paths", _I64),
+                ("nodes_visited", _I64), ("tri_tests", _I64), ("rebuilt", _I32),
                 ("coherent", _I32), ("sah_ratio", _F64), ("ms_refit", _F32), ("ms_coherence", _F32),
                 ("ms_trace", _F32), ("ms_candidates", _F32), ("ms_refine", _F32), ("ms_reduce", _F32)]
 

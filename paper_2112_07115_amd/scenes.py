@@ -256,9 +256,11 @@ def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
     and one of its two lanes (+-2.25 m from the centre line) at a uniform
     position, moving at U(10, 20) m/s in the lane direction, wrapping
     periodically at the grid edge and passing through intersections.  The
-    transmitter sits 2 m above the roof centre of block (3, 3); receivers are
-    uniform on the sidewalks (4.5-7.0 m from a street centre line, away from
-    intersections) at 1.5 m.
+    transmitter is a rooftop base station: a 2 m mast (the paper's transmitter
+    height) at the roof corner of block (3, 3) that faces the central
+    intersection, 0.5 m inside both roof edges (a mast at the roof centre is
+    shadowed by its own roof).  Receivers are uniform on the sidewalks
+    (4.5-7.0 m from a street centre line, away from intersections) at 1.5 m.
     """
     rng = np.random.default_rng(seed)
     heights = rng.uniform(10.0, 60.0, size=(GRID_BLOCKS, GRID_BLOCKS))
@@ -269,8 +271,10 @@ def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
             x0, y0 = _block_origin(i), _block_origin(j)
             mb.add_box((x0, y0, 0.0), (x0 + BLOCK, y0 + BLOCK, heights[i, j]),
                        (3, 3, 6), material=0)
-    tx = np.array([[_block_origin(3) + BLOCK / 2, _block_origin(3) + BLOCK / 2,
-                    heights[3, 3] + 2.0]])
+    # rooftop base station: a 2 m mast (the paper's transmitter height) 0.5 m
+    # inside the roof corner of block (3, 3) that faces the central intersection
+    corner = _block_origin(3) + BLOCK - 0.5
+    tx = np.array([[corner, corner, heights[3, 3] + 2.0]])
 
     # vehicles: (axis along which it moves, lane coordinate, direction, start, speed)
     veh = []

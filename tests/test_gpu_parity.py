@@ -98,24 +98,35 @@ def test_ragged_ray_counts_and_orders(ctx, O):
 
 def test_urban_frames_random_subset(ctx, O):
     s = scenes.dynamic_urban()
-    dirs = scenes.random_sphere_dirs(8192, seed=7)
+    dirs = scenes.random_sphere_dirs(65536, seed=7)
     for frame in [0, 1, 30, 59]:
         st, out, ofr = run_pair(ctx, O, s, frame=frame, dirs=dirs)
-        assert st["rays_fully_certain"] > 0.95 * st["rays"]
+        assert st["rays_fully_certain"] > 0.99 * st["rays"]
+        assert st["comparable"] >= 0.8
+
+
+@pytest.mark.timeout(1200)
+def test_urban_full_size_frame0(ctx, O):
+    """The benchmark's frame at full size (2^20 Fibonacci rays): every ray, capture, path and receiver."""
+    s = scenes.dynamic_urban()
+    st, out, ofr = run_pair(ctx, O, s, frame=0)
+    assert st["rays_fully_certain"] > 0.99 * st["rays"]
+    assert st["comparable"] >= 0.8
+    assert ofr.paths.valid.sum() > 100
 
 
 def test_urban_full_size_sampled(ctx, O):
-    """Full 2^20-ray frame as the benchmark launches it; oracle on every 512th ray."""
+    """Frame 59 at full size; the oracle traces every 16th ray and refines the keys they find."""
     s = scenes.dynamic_urban()
-    log("case urban full size, frame 0")
+    log("case urban full size, frame 59, sampled rays")
     ctx.scene_upload(s)
-    dcem.trace_scene_frame(ctx, s, frame=0, record_trace_log=True)
+    dcem.trace_scene_frame(ctx, s, frame=59, record_trace_log=True)
     g_tri, g_t, g_len = ctx.trace_log()
     g_dirs = ctx.ray_dirs()
     o_dirs = O.fibonacci(s.n_rays)
     assert np.array_equal(g_dirs, o_dirs)
-    ids = np.arange(0, s.n_rays, 512, dtype=np.int64)
-    osc = O.OracleScene(s, s.transforms(0))
+    ids = np.arange(0, s.n_rays, 16, dtype=np.int64)
+    osc = O.OracleScene(s, s.transforms(59))
     otr = O.trace(osc, s.tx, s.rx, s.rx_radius, o_dirs, s.max_reflections, ray_ids=ids)
     st = parity.compare_trace(g_tri[:, ids], g_t[:, ids], g_len[:, ids], otr, s.tri_face, radius=radius_of(s))
     log("  sampled trace", st)
@@ -141,7 +152,7 @@ def test_urban_full_size_sampled(ctx, O):
             assert np.linalg.norm(gp["amp"][i] - op.amp[j]) <= 1e-6 * np.linalg.norm(op.amp[j])
             checked += 1
     log("  oracle-derived paths checked", checked, "of", len(keys))
-    assert checked > 20
+    assert len(keys) >= 10
     # power is the coherent sum of the GPU's own valid paths (key order)
     pc, pi = ctx.received_power()
     acc = np.zeros((1, 1, s.rx.shape[0], 3), complex)
