@@ -44,8 +44,9 @@ def compare_trace(g_tri, g_t, g_len, o, tri_face, eps_rel=4e-6, radius=1.0):
     o_tri, g_tri = o.tri, g_tri
     same_tri = o_tri == g_tri
     tri_only = (o.flags & SEG_TRI) != 0
-    o_face = np.where(o_tri >= 0, tri_face[np.maximum(o_tri, 0)], o_tri)
-    g_face = np.where(g_tri >= 0, tri_face[np.maximum(g_tri, 0)], g_tri)
+    tf = np.concatenate([np.asarray(tri_face, np.int64), [-3]])   # index -> face, sentinel for empty scenes
+    o_face = np.where(o_tri >= 0, tf[np.clip(o_tri, 0, len(tf) - 1)], o_tri)
+    g_face = np.where(g_tri >= 0, tf[np.clip(g_tri, 0, len(tf) - 1)], g_tri)
     ok = np.where(tri_only, o_face == g_face, same_tri)
     bad = check & ~ok
     msgs = []
