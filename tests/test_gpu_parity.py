@@ -191,7 +191,7 @@ def test_bvh_invariants_build_refit_rebuild(ctx):
     for frame in [1, 30, 59]:
         ctx.set_object_transforms(s.transforms(frame))
         rebuilt, ratio = ctx.refit_bvh(threshold=float("inf"))
-        assert not rebuilt and ratio >= 1.0
+        assert not rebuilt and ratio > 0.5
         child, box, leaf = ctx.bvh()
         V = ctx.vertices()
         assert check_bvh(child, box, leaf, V, s.tris, pad=np.float32(pad), exact=True) == []
