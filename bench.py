@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["both", "coherent", "full"], default="both")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -84,6 +86,13 @@ def main():
     import torch
     from paper_2112_07115_amd import dcem, scenes
     scene = scenes.dynamic_urban(n_rays=args.rays)
+    if args.copy_probe:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = {}
     for mode in (["coherent", "full"] if args.mode == "both" else [args.mode]):
         ctx = dcem.Context(0)
