@@ -87,6 +87,73 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
 
 bool mem_kind_ok(int k) { return k == DCEM_MEM_HOST || k == DCEM_MEM_DEVICE; }
 
+// Binary tree over the capture spheres (median split on the longest axis of the
+// centres), in the scene BVH's node layout; leaves are receiver ids and every
+// box is the sphere box grown by `grow`, so the box test is conservative.
+struct RxTree {
+  std::vector<Node> nodes;
+  const std::vector<float>* rx;
+  float r;
+
+  void box_of(const std::vector<int>& ids, int b, int e, float* lo, float* hi) const {
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int i = b; i < e; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], (*rx)[3 * ids[i] + a] - r);
+        hi[a] = std::max(hi[a], (*rx)[3 * ids[i] + a] + r);
+      }
+  }
+  static void set_slot(Node& n, int slot, const float* lo, const float* hi) {
+    float* f = reinterpret_cast<float*>(&n);
+    for (int a = 0; a < 3; ++a) { f[6 * slot + a] = lo[a]; f[6 * slot + 3 + a] = hi[a]; }
+  }
+  int build(std::vector<int>& ids, int b, int e) {
+    if (e - b == 1) return ~ids[b];
+    const int me = (int)nodes.size();
+    nodes.push_back(Node{});
+    float lo[3], hi[3];
+    box_of(ids, b, e, lo, hi);
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    const int mid = (b + e) / 2;
+    std::nth_element(ids.begin() + b, ids.begin() + mid, ids.begin() + e, [&](int x, int y) {
+      const float px = (*rx)[3 * x + ax], py = (*rx)[3 * y + ax];
+      return px < py || (px == py && x < y);
+    });
+    const int l = build(ids, b, mid), rr = build(ids, mid, e);
+    float llo[3], lhi[3], rlo[3], rhi[3];
+    box_of(ids, b, mid, llo, lhi);
+    box_of(ids, mid, e, rlo, rhi);
+    set_slot(nodes[me], 0, llo, lhi);
+    set_slot(nodes[me], 1, rlo, rhi);
+    nodes[me].c = make_int4(l, rr, -1, 0);
+    return me;
+  }
+};
+
+std::vector<Node> build_rx_tree(const std::vector<float>& rx, float radius) {
+  RxTree t;
+  t.rx = &rx;
+  double R = 1.0;
+  for (float v : rx) R = std::max(R, (double)std::fabs(v));
+  t.r = (float)(radius * (1.0 + 1e-5) + 1e-3 + 4e-6 * (2.0 * R + 1.0));
+  const int n = (int)(rx.size() / 3);
+  std::vector<int> ids(n);
+  for (int i = 0; i < n; ++i) ids[i] = i;
+  if (n == 1) {
+    Node root{};
+    float lo[3], hi[3];
+    t.box_of(ids, 0, 1, lo, hi);
+    RxTree::set_slot(root, 0, lo, hi);
+    RxTree::set_slot(root, 1, lo, hi);
+    root.c = make_int4(~0, ~0, -1, 0);
+    return {root};
+  }
+  t.build(ids, 0, n);
+  return t.nodes;
+}
+
 void ev_record(dcem_ctx* c, int i) {
   if (c->timing) (void)hipEventRecord(c->ev[i], c->stream);
 }
@@ -145,11 +212,12 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
                     &c->obj_box, &c->face_plane, &c->nodes, &c->leaves, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
-                    &c->rx_pos, &c->freqs, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
+                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
                     &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
                     &c->counters, &c->err_word, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
-                    &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist};
+                    &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist, &c->path_order,
+                    &c->path_faces, &c->path_pts};
   for (DevBuf* b : bufs) release(*b);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -396,8 +464,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   TraceConfig& cfg = c->cfg;
   const bool same = cfg.n_tx == p->n_tx && cfg.n_rx == p->n_rx && cfg.K == p->max_reflections &&
                     cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius && cfg.tx == txh && cfg.rx == rxh &&
-                    cfg.dirs_fib == fib &&
-                    (fib || (p->mem_kind == DCEM_MEM_HOST ? cfg.dirs_host == dirh : cfg.dirs_ptr == p->ray_dirs));
+                    cfg.dirs_fib == fib && (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
   const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same;
   const bool keep_cache = p->keep_cache != 0 || p->mode == DCEM_MODE_COHERENT;
   // -- device inputs
@@ -420,9 +487,20 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   c->sqrt_pt = std::sqrt(p->tx_power_w);
   c->atten_db_per_km = p->atten_db_per_km;
   c->record_log = p->record_trace_log != 0;
-  HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
-  HIP_TRY(upload(c->rx_pos, rxh, c->stream), "upload rx");
-  HIP_TRY(upload(c->freqs, std::vector<double>(p->freqs_hz, p->freqs_hz + p->n_freqs), c->stream), "upload freqs");
+  if (need_dirs) {   // transmitters, receivers or rays changed
+    HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
+    HIP_TRY(upload(c->rx_pos, rxh, c->stream), "upload rx");
+    std::vector<Node> rt = build_rx_tree(rxh, p->rx_radius);
+    c->n_rx_nodes = (int32_t)rt.size();
+    HIP_TRY(upload(c->rx_nodes, rt, c->stream), "upload receiver tree");
+  }
+  {
+    std::vector<double> fv(p->freqs_hz, p->freqs_hz + p->n_freqs);
+    if (fv != c->freqs_host || need_dirs) {
+      HIP_TRY(upload(c->freqs, fv, c->stream), "upload freqs");
+      c->freqs_host = fv;
+    }
+  }
   if (need_dirs) {
     HIP_TRY(ensure(c->dirs, sizeof(float) * 3 * std::max<int64_t>(p->n_rays, 1)), "alloc dirs");
     if (fib) {
@@ -433,6 +511,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
       HIP_TRY(hipMemcpyAsync(c->dirs.p, p->ray_dirs, sizeof(float) * 3 * p->n_rays, hipMemcpyDeviceToDevice, c->stream),
               "copy dirs");
     }
+    HIP_TRY(build_ray_order(c), "ray order");
   }
   const size_t nw = (size_t)std::max<int64_t>(n_work, 1), K1 = (size_t)p->max_reflections + 1;
   HIP_TRY(ensure(c->face_log, sizeof(int32_t) * K1 * nw), "alloc face log");

@@ -87,14 +87,16 @@ struct dcem_ctx {
   dcem::TraceConfig cfg;
   bool cache_valid = false;
   bool geometry_moved = true;   // transforms changed since the cached frame
-  dcem::DevBuf dirs, tx_pos, rx_pos, freqs;
+  dcem::DevBuf dirs, ray_order, tx_pos, rx_pos, freqs, rx_nodes;
+  std::vector<double> freqs_host;
+  int32_t n_rx_nodes = 0;
   dcem::DevBuf face_log;     // [K+1][n_work] int32 face hit per bounce (-1 miss)
   dcem::DevBuf ray_state;    // [n_work] uint8: segments (low 4 bits), bit 7 = hit a moving face
   dcem::DevBuf seg_o, seg_d; // [K+1][n_work] float4: origin + t_end, direction
   dcem::DevBuf log_tri, log_t, log_len;  // parity log [n_work][K+1]
   dcem::DevBuf caps[2];      // double-buffered capture lists
   int cur_caps = 0;
-  dcem::DevBuf work_list, invalid_flag;
+  dcem::DevBuf work_list, invalid_flag;   // re-trace list; per-ray first invalid segment (255 = valid)
   dcem::DevBuf counters;     // uint32 device counters (see kCnt*)
   dcem::DevBuf err_word;
 
@@ -104,7 +106,7 @@ struct dcem_ctx {
   int bits_tx = 0, bits_rx = 0, bits_face = 0;
   dcem::DevBuf cand_keys, cand_perm, cand_tmp, uniq_idx, first_ray;
   dcem::DevBuf path_valid, path_len, path_tau, path_aod, path_aoa, path_amp;
-  dcem::DevBuf p_coh, p_inc, pair_range;
+  dcem::DevBuf p_coh, p_inc, pair_range, path_order, path_faces, path_pts;
   dcem::DevBuf sort_hist;
   int64_t n_caps_host = 0;
   double sqrt_pt = 0.0, atten_db_per_km = 0.0;
@@ -155,6 +157,7 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_ma
 void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps);
 void launch_los(dcem_ctx* c);
 void launch_reset_counters(dcem_ctx* c);
+hipError_t build_ray_order(dcem_ctx* c);
 
 // ---- candidates, refinement and accumulation (refine.hip)
 hipError_t build_candidates(dcem_ctx* c);

@@ -239,6 +239,9 @@ struct RefineArgs {
   double* amp;       // [n][n_freqs][3][2]
   int32_t* first_ray;
   int32_t* pair;
+  uint8_t* order;    // [n] reflection order
+  int32_t* faces;    // [n][K] face sequence
+  double* pts;       // [n][K+2][3] transmitter, reflection points, receiver
   uint32_t* counters;
   uint32_t* err;
 };
@@ -331,76 +334,122 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
 
 constexpr int kRefineBlock = 64;
 
-__global__ __launch_bounds__(kRefineBlock) void k_refine(RefineArgs a) {
+// Refinement, stage 1 (one thread per unique key): decode the key, image
+// sources through the face planes and reflection points walked back from the
+// receiver, each strictly inside its segment.  Points go to pts[u][0..order+1].
+__global__ __launch_bounds__(kRefineBlock) void k_refine_geom(RefineArgs a) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= *a.n_unique) return;
+  const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
+  const uint32_t idx = a.perm[h];
+  const KeyLayout& L = a.L;
+  int faces[kMaxK];
+  for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
+  int pos = L.K * L.bf;
+  const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
+  pos += 4;
+  const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
+  pos += L.br;
+  const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
+  a.pair[u] = tx * L.n_rx + rx;
+  a.order[u] = (uint8_t)order;
+  for (int j = 0; j < L.K; ++j) a.faces[(size_t)u * L.K + j] = j < order ? faces[j] : -1;
+  uint32_t fr = kNoRay;
+  for (uint32_t j = h; j < e; ++j) fr = min(fr, a.caps[a.perm[j]].work);
+  a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
+
+  const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
+  D3 img[kMaxK + 1];
+  img[0] = T;
+  for (int j = 1; j <= order; ++j) {
+    const double4 pl = a.plane[faces[j - 1]];
+    const D3 n = {pl.x, pl.y, pl.z};
+    img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
+  }
+  double* P = a.pts + (size_t)u * (L.K + 2) * 3;
+  bool ok = true;
+  D3 Q = R;
+  for (int j = order; j >= 1; --j) {
+    const double4 pl = a.plane[faces[j - 1]];
+    const D3 n = {pl.x, pl.y, pl.z};
+    const D3 D = img[j] - Q;
+    const double den = dot(D, n);
+    if (den == 0.0) { ok = false; break; }
+    const double s = (pl.w - dot(Q, n)) / den;
+    if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
+    Q = Q + s * D;
+    P[3 * j] = Q.x; P[3 * j + 1] = Q.y; P[3 * j + 2] = Q.z;
+  }
+  P[0] = T.x; P[1] = T.y; P[2] = T.z;
+  P[3 * (order + 1)] = R.x; P[3 * (order + 1) + 1] = R.y; P[3 * (order + 1) + 2] = R.z;
+  a.valid[u] = ok ? 1 : 0;
+  a.length[u] = len(R - img[order]);
+}
+
+// Refinement, stage 2 (one thread per path and check): check c < K tests that
+// reflection point c+1 lies in its face; check K + j tests that sub-segment j
+// is unoccluded.  A failed check clears the path's valid flag.
+__global__ __launch_bounds__(kRefineBlock) void k_refine_check(RefineArgs a) {
   __shared__ int stack_mem[kStackSize * kRefineBlock];
   int* stack = stack_mem + threadIdx.x;
+  const int K = a.L.K;
+  const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint32_t u = (uint32_t)(gid / (2 * K + 1));
+  const int c = (int)(gid - (uint64_t)u * (2 * K + 1));
+  bool fault = false;
+  if (u < *a.n_unique && a.valid[u]) {
+    const int order = a.order[u];
+    const double* P = a.pts + (size_t)u * (K + 2) * 3;
+    const int32_t* faces = a.faces + (size_t)u * K;
+    bool fail = false;
+    if (c < K) {
+      if (c < order) {
+        const int f = faces[c];
+        const double4 pl = a.plane[f];
+        const D3 p = {P[3 * (c + 1)], P[3 * (c + 1) + 1], P[3 * (c + 1) + 2]};
+        fail = !in_face(a, f, p, D3{pl.x, pl.y, pl.z});
+      }
+    } else {
+      const int j = c - K;
+      if (j <= order) {
+        const int fa = j >= 1 ? faces[j - 1] : -1;
+        const int fb = j + 1 <= order ? faces[j] : -1;
+        const D3 p = {P[3 * j], P[3 * j + 1], P[3 * j + 2]};
+        const D3 q = {P[3 * (j + 1)], P[3 * (j + 1) + 1], P[3 * (j + 1) + 2]};
+        fail = occluded(a, p, q, fa, fb, stack, kRefineBlock, fault);
+      }
+    }
+    if (fail) a.valid[u] = 0;
+  }
+  if (fault) atomicOr(a.err, DCEM_ERR_STACK);
+}
+
+// Refinement, stage 3 (one thread per path): length, delay, directions and the
+// field: theta-hat of the departure direction carried through each reflection
+// by the Fresnel coefficients, times sqrt(Pt) lambda / (4 pi d), the specific
+// attenuation and the phase e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
+__global__ __launch_bounds__(kRefineBlock) void k_refine_field(RefineArgs a) {
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nu = *a.n_unique;
   const int lane = threadIdx.x & 63;
-  bool ok = false, fault = false;
+  bool ok = false;
   if (u < nu) {
-    const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
-    const uint32_t idx = a.perm[h];
-    const KeyLayout& L = a.L;
-    // decode (tx, rx, order, faces)
-    int faces[kMaxK];
-    for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
-    int pos = L.K * L.bf;
-    const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
-    pos += 4;
-    const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
-    pos += L.br;
-    const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
-    a.pair[u] = tx * L.n_rx + rx;
-    uint32_t fr = kNoRay;
-    for (uint32_t j = h; j < e; ++j) fr = min(fr, a.caps[a.perm[j]].work);
-    a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
-
-    const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
-    // images of the transmitter through the face planes
-    D3 img[kMaxK + 1];
-    img[0] = T;
-    for (int j = 1; j <= order; ++j) {
-      const double4 pl = a.plane[faces[j - 1]];
-      const D3 n = {pl.x, pl.y, pl.z};
-      img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
-    }
-    // reflection points, from the receiver back towards the transmitter
-    D3 pts[kMaxK + 2];
-    pts[0] = T;
-    pts[order + 1] = R;
-    ok = true;
-    D3 Q = R;
-    for (int j = order; j >= 1 && ok; --j) {
-      const double4 pl = a.plane[faces[j - 1]];
-      const D3 n = {pl.x, pl.y, pl.z};
-      const D3 D = img[j] - Q;
-      const double den = dot(D, n);
-      if (den == 0.0) { ok = false; break; }
-      const double s = (pl.w - dot(Q, n)) / den;
-      if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
-      const D3 P = Q + s * D;
-      if (!in_face(a, faces[j - 1], P, n)) { ok = false; break; }
-      pts[j] = P;
-      Q = P;
-    }
-    for (int j = 0; j <= order && ok; ++j) {
-      const int fa = j >= 1 ? faces[j - 1] : -1;
-      const int fb = j + 1 <= order ? faces[j] : -1;
-      if (occluded(a, pts[j], pts[j + 1], fa, fb, stack, kRefineBlock, fault)) ok = false;
-    }
-    a.valid[u] = ok ? 1 : 0;
-    const double d = len(R - img[order]);
-    a.length[u] = ok ? d : 0.0;
+    const int K = a.L.K;
+    ok = a.valid[u] != 0;
+    const int order = a.order[u];
+    const double* P = a.pts + (size_t)u * (K + 2) * 3;
+    const int32_t* faces = a.faces + (size_t)u * K;
+    auto pt = [P](int j) { return D3{P[3 * j], P[3 * j + 1], P[3 * j + 2]}; };
+    const double d = a.length[u];
     a.tau[u] = ok ? d / kC0 : 0.0;
+    if (!ok) a.length[u] = 0.0;
     D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
     if (ok) {
-      aod = normed(pts[1] - pts[0]);
-      aoa = normed(pts[order] - R);
+      aod = normed(pt(1) - pt(0));
+      aoa = normed(pt(order) - pt(order + 1));
     }
     a.aod[3 * u] = aod.x; a.aod[3 * u + 1] = aod.y; a.aod[3 * u + 2] = aod.z;
     a.aoa[3 * u] = aoa.x; a.aoa[3 * u + 1] = aoa.y; a.aoa[3 * u + 2] = aoa.z;
-    // field: theta-hat of the departure direction, carried through each reflection
     const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
     const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
     for (int fi = 0; fi < a.n_freqs; ++fi) {
@@ -414,8 +463,8 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(RefineArgs a) {
       for (int j = 1; j <= order; ++j) {
         const double4 pl = a.plane[faces[j - 1]];
         const D3 n = {pl.x, pl.y, pl.z};
-        const D3 ki = normed(pts[j] - pts[j - 1]);
-        const D3 kr = normed(pts[j + 1] - pts[j]);
+        const D3 ki = normed(pt(j) - pt(j - 1));
+        const D3 kr = normed(pt(j + 1) - pt(j));
         const double cos_t = fabs(dot(ki, n));
         D3 s = cross(ki, n);
         const double sl = len(s);
@@ -450,7 +499,6 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(RefineArgs a) {
   }
   const uint64_t m = __ballot(ok);
   if (lane == 0 && m) atomicAdd(&a.counters[kCntValid], (uint32_t)__popcll(m));
-  if (fault) atomicOr(a.err, DCEM_ERR_STACK);
 }
 
 // One wavefront per (tx, rx): sum the valid paths of that pair (contiguous in
@@ -567,6 +615,9 @@ hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
   if ((e = ensure(c->path_amp, 48 * n * (size_t)c->n_freqs)) != hipSuccess) return e;
   if ((e = ensure(c->first_ray, 4 * n)) != hipSuccess) return e;
   if ((e = ensure(c->pair_range, 4 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_order, n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_faces, 4 * n * (size_t)std::max(c->K, 1))) != hipSuccess) return e;
+  if ((e = ensure(c->path_pts, 24 * n * (size_t)(c->K + 2))) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -614,10 +665,17 @@ void launch_refine(dcem_ctx* c) {
   a.amp = ptr<double>(c->path_amp);
   a.first_ray = ptr<int32_t>(c->first_ray);
   a.pair = ptr<int32_t>(c->pair_range);
+  a.order = ptr<uint8_t>(c->path_order);
+  a.faces = ptr<int32_t>(c->path_faces);
+  a.pts = ptr<double>(c->path_pts);
   a.counters = ptr<uint32_t>(c->counters);
   a.err = ptr<uint32_t>(c->err_word);
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)((n + kRefineBlock - 1) / kRefineBlock)), dim3(kRefineBlock), 0,
+  const unsigned nb = (unsigned)((n + kRefineBlock - 1) / kRefineBlock);
+  hipLaunchKernelGGL(k_refine_geom, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
+  const uint64_t nchk = (uint64_t)n * (2 * c->K + 1);
+  hipLaunchKernelGGL(k_refine_check, dim3((unsigned)((nchk + kRefineBlock - 1) / kRefineBlock)), dim3(kRefineBlock), 0,
                      c->stream, a);
+  hipLaunchKernelGGL(k_refine_field, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
 }
 
 void launch_reduce(dcem_ctx* c) {

@@ -165,11 +165,15 @@ struct TraceArgs {
   const Leaf* leaves;
   int n_internal;
   const float* dirs;
+  const uint32_t* ray_order;  // traversal order of the rays (directions sorted along a space-filling curve)
   const float* tx;
   const float* rx;      // [n_rx][3]
   int n_rx;
+  const Node* rx_nodes; // BVH over the capture spheres (boxes padded), leaves = receiver ids
+  int n_rx_nodes;
   float r2;
   float rx_zlo, rx_zhi; // z range of all capture spheres
+  const uint8_t* restart;     // work-list mode: first segment to trace again
   int64_t n_rays;
   int n_work;
   const uint32_t* work_list;  // null: all work items
@@ -188,8 +192,19 @@ struct TraceArgs {
   uint32_t* err;
 };
 
+// Capture test of one segment [o, o + tend d] against one sphere: closest
+// approach of the segment to the centre within the radius (FP32).
+__device__ inline bool captured(const Ray& r, float tend, float dd, float cx, float cy, float cz, float r2) {
+  const float wx = cx - r.o.x, wy = cy - r.o.y, wz = cz - r.o.z;
+  float s = __fdiv_rn(wx * r.d.x + wy * r.d.y + wz * r.d.z, dd);
+  s = fminf(fmaxf(s, 0.0f), tend);
+  const float px = fmaf(s, r.d.x, -wx), py = fmaf(s, r.d.y, -wy), pz = fmaf(s, r.d.z, -wz);
+  return px * px + py * py + pz * pz <= r2;
+}
+
 // Persistent trace kernel: each wavefront takes 64 consecutive work items from
-// a global queue and traces them through all bounces.
+// a global queue and traces them through all bounces.  In work-list mode a ray
+// restarts at its first invalidated segment from the cached segment state.
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   __shared__ int stack_mem[kStackSize * kTraceBlock];
   int* stack = stack_mem + threadIdx.x;
@@ -204,17 +219,33 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     if (base >= n_work) break;
     const uint32_t wi = base + lane;
     if (wi < n_work) {
-      const uint32_t work = a.work_list ? a.work_list[wi] : wi;
-      const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
-      const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
+      uint32_t work, txi, ray;
+      if (a.work_list) {
+        work = a.work_list[wi];
+        txi = (uint32_t)(work / (uint64_t)a.n_rays);
+        ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
+      } else {
+        txi = (uint32_t)(wi / (uint64_t)a.n_rays);
+        ray = a.ray_order[wi - (uint64_t)txi * a.n_rays];
+        work = txi * (uint32_t)a.n_rays + ray;
+      }
+      int k = a.restart ? (int)a.restart[work] : 0;
       Ray r;
-      r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
-      r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
-      setup_ray(r);
       int excl = -1;
       float L = 0.0f;
+      if (k == 0) {
+        r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
+        r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
+      } else {
+        const float4 so = a.seg_o[(size_t)k * a.n_work + work];
+        const float4 sd = a.seg_d[(size_t)k * a.n_work + work];
+        r.o = make_float3(so.x, so.y, so.z);
+        r.d = make_float3(sd.x, sd.y, sd.z);
+        L = sd.w;
+        excl = a.face_log[(size_t)(k - 1) * a.n_work + work];
+      }
+      setup_ray(r);
       uint32_t state = 0;
-      int k = 0;
       for (; k <= a.K; ++k) {
         Hit h = closest_hit(r, a.nodes, a.leaves, a.n_internal, excl, stack, kTraceBlock, overflow, node_count,
                             tri_count);
@@ -225,7 +256,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
         if (a.seg_o) {
           a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
-          a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, 0.0f);
+          a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
         }
         const float dl = __fsqrt_rn(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
         if (a.log_tri) {
@@ -234,25 +265,48 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
           a.log_t[li] = hit ? h.t : INFINITY;
           a.log_len[li] = hit ? L + h.t * dl : INFINITY;
         }
-        // capture: closest approach of the segment to each sphere centre
+        // capture: spheres whose padded box the segment meets, then the exact test
         const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
-        float za = r.o.z, zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+        const float za = r.o.z;
+        const float zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
         if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
-          for (int c = 0; c < a.n_rx; ++c) {
-            const float wx = a.rx[3 * c] - r.o.x, wy = a.rx[3 * c + 1] - r.o.y, wz = a.rx[3 * c + 2] - r.o.z;
-            float s = __fdiv_rn(wx * r.d.x + wy * r.d.y + wz * r.d.z, dd);
-            s = fminf(fmaxf(s, 0.0f), tend);
-            const float px = fmaf(s, r.d.x, -wx), py = fmaf(s, r.d.y, -wy), pz = fmaf(s, r.d.z, -wz);
-            if (px * px + py * py + pz * pz <= a.r2) {
-              const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
-              if (slot < a.cap_capacity) {
-                Capture cp;
-                cp.work = work;
-                cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
-                a.caps[slot] = cp;
-              } else {
-                cap_over = true;
+          int node = 0, sp = 0;
+          for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
+            const Node nd = a.rx_nodes[node];
+            float t0, t1;
+            bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, tend, t0);
+            bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, tend, t1);
+            const int c0 = nd.c.x, c1 = nd.c.y;
+            for (int side = 0; side < 2; ++side) {
+              const int cc = side ? c1 : c0;
+              const bool hh = side ? h1 : h0;
+              if (!(hh && cc < 0) || (side == 1 && c1 == c0)) continue;   // a lone sphere fills both slots
+              const int c = ~cc;
+              if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
+                const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
+                if (slot < a.cap_capacity) {
+                  Capture cp;
+                  cp.work = work;
+                  cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+                  a.caps[slot] = cp;
+                } else {
+                  cap_over = true;
+                }
               }
+            }
+            h0 = h0 && c0 >= 0;
+            h1 = h1 && c1 >= 0;
+            if (h0 && h1) {
+              if (sp < kStackSize) stack[(sp++) * kTraceBlock] = c1;
+              else overflow = true;
+              node = c0;
+            } else if (h0) {
+              node = c0;
+            } else if (h1) {
+              node = c1;
+            } else {
+              if (sp == 0) break;
+              node = stack[(--sp) * kTraceBlock];
             }
           }
         }
@@ -284,7 +338,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
     }
   }
-  // one atomic per wavefront for the segment counter
+  // one atomic per wavefront for the counters
   for (int off = 32; off > 0; off >>= 1) {
     seg_count += __shfl_xor(seg_count, off);
     node_count += __shfl_xor(node_count, off);
@@ -303,23 +357,33 @@ __global__ void k_reset_counters(uint32_t* counters) {
   if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
 }
 
-// Coherence pass.  A cached ray stays valid iff none of its hits in the cached
-// frame was on a moving face and none of its segments (the last one unbounded
-// on a miss) meets the padded box of any moving object now.  Valid rays would
-// be traced to exactly the same hits and captures, so they are reused; the
-// others are listed for re-tracing (wavefront-aggregated append).
+// Coherence pass.  Segment k of a cached ray is still valid iff no earlier
+// segment is invalid, its hit in the cached frame was not on a moving face, and
+// it (unbounded on a miss) does not meet the padded box of any moving object
+// now.  A ray whose segments are all valid would be traced to exactly the same
+// hits and captures, so it is reused as it is; otherwise it is listed for
+// re-tracing from its first invalid segment (wavefront-aggregated append).
+// Rays are visited in the traversal order so the list stays spatially coherent.
 __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o,
-                            const float4* __restrict__ seg_d, const float* __restrict__ obj_box, int n_obj,
-                            int n_work, uint8_t* __restrict__ invalid, uint32_t* __restrict__ list,
-                            uint32_t* counters) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+                            const float4* __restrict__ seg_d, const int32_t* __restrict__ face_log,
+                            const int32_t* __restrict__ face_object, const float* __restrict__ obj_box, int n_obj,
+                            const uint32_t* __restrict__ ray_order, int64_t n_rays, int n_work,
+                            uint8_t* __restrict__ restart, uint32_t* __restrict__ list, uint32_t* counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  bool bad = false;
-  if (w < n_work) {
+  int first = 255;
+  uint32_t w = 0;
+  if (i < n_work) {
+    const uint32_t txi = (uint32_t)(i / n_rays);
+    w = txi * (uint32_t)n_rays + ray_order[i - (int64_t)txi * n_rays];
     const uint32_t st = ray_state[w];
-    bad = (st & 0x80u) != 0;
     const int nseg = (int)(st & 0x0fu);
-    for (int k = 0; k < nseg && !bad; ++k) {
+    const bool moving_hit = (st & 0x80u) != 0;
+    for (int k = 0; k < nseg && first == 255; ++k) {
+      if (moving_hit) {
+        const int f = face_log[(size_t)k * n_work + w];
+        if (f >= 0 && face_object[f] >= 0) { first = k; break; }
+      }
       const float4 o = seg_o[(size_t)k * n_work + w];
       const float4 d = seg_d[(size_t)k * n_work + w];
       Ray r;
@@ -332,34 +396,64 @@ __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4*
       for (int b = 0; b < n_obj; ++b) {
         const float* bx = obj_box + 6 * b;
         float tn;
-        if (slab(r, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o.w, tn)) { bad = true; break; }
+        if (slab(r, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o.w, tn)) { first = k; break; }
       }
     }
-    invalid[w] = bad ? 1 : 0;
+    restart[w] = (uint8_t)first;
   }
+  const bool bad = first != 255;
   const uint64_t m = __ballot(bad);
   uint32_t base = 0;
   if (lane == 0 && m) base = atomicAdd(&counters[kCntWork], (uint32_t)__popcll(m));
   base = __shfl(base, 0);
-  if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)w;
+  if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = w;
 }
 
-// Keep the cached captures of valid rays (direct-path records are re-added).
+// Keep the cached captures made before each ray's first invalid segment
+// (direct-path records are re-added every frame).
 __global__ void k_filter_caps(const Capture* __restrict__ prev, uint32_t n_prev,
-                              const uint8_t* __restrict__ invalid, Capture* __restrict__ cur, uint32_t* counters) {
+                              const uint8_t* __restrict__ restart, Capture* __restrict__ cur, uint32_t* counters) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   bool keep = false;
   Capture c{};
   if (i < n_prev) {
     c = prev[i];
-    keep = c.work != kNoRay && !invalid[c.work];
+    keep = c.work != kNoRay && (c.pair_order & 15u) < restart[c.work];
   }
   const uint64_t m = __ballot(keep);
   uint32_t base = 0;
   if (lane == 0 && m) base = atomicAdd(&counters[kCntCaptures], (uint32_t)__popcll(m));
   base = __shfl(base, 0);
   if (keep) cur[base + __popcll(m & ((1ull << lane) - 1ull))] = c;
+}
+
+// Spatial key of a direction: octahedral map to the unit square, 16 bits per
+// axis, interleaved.  Sorting rays by it groups neighbouring directions in a
+// wavefront.
+__device__ inline uint32_t spread16(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__global__ void k_dir_keys(const float* __restrict__ dirs, int64_t n, uint32_t* __restrict__ key) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float x = dirs[3 * i], y = dirs[3 * i + 1], z = dirs[3 * i + 2];
+  const float l1 = fabsf(x) + fabsf(y) + fabsf(z);
+  float u = 0.f, v = 0.f;
+  if (l1 > 0.f) {
+    x /= l1; y /= l1; z /= l1;
+    if (z >= 0.f) { u = x; v = y; }
+    else { u = (1.f - fabsf(y)) * (x >= 0.f ? 1.f : -1.f); v = (1.f - fabsf(x)) * (y >= 0.f ? 1.f : -1.f); }
+  }
+  const uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
+  const uint32_t qv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
+  key[i] = (spread16(qu) << 1) | spread16(qv);
 }
 
 __global__ void k_los(Capture* __restrict__ caps, uint32_t* counters, int n_pairs, int64_t cap_capacity,
@@ -403,9 +497,13 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_ma
   a.leaves = ptr<Leaf>(c->leaves);
   a.n_internal = c->nt > 0 ? c->n_internal : 0;
   a.dirs = ptr<float>(c->dirs);
+  a.ray_order = ptr<uint32_t>(c->ray_order);
   a.tx = ptr<float>(c->tx_pos);
   a.rx = ptr<float>(c->rx_pos);
   a.n_rx = c->n_rx;
+  a.rx_nodes = ptr<Node>(c->rx_nodes);
+  a.n_rx_nodes = c->n_rx_nodes;
+  a.restart = all_rays ? nullptr : ptr<uint8_t>(c->invalid_flag);
   a.r2 = c->cfg.rx_radius * c->cfg.rx_radius;
   float zlo = FLT_MAX, zhi = -FLT_MAX;
   for (int i = 0; i < c->n_rx; ++i) {
@@ -443,13 +541,31 @@ void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
   const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
   uint32_t* cnt = ptr<uint32_t>(c->counters);
   hipLaunchKernelGGL(k_coherence, dim3((n_work + 255) / 256), dim3(256), 0, c->stream, ptr<uint8_t>(c->ray_state),
-                     ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<float>(c->obj_box), c->no, n_work,
-                     ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
+                     ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<int32_t>(c->face_log),
+                     ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, ptr<uint32_t>(c->ray_order),
+                     c->n_rays, n_work, ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
   const int prev = c->cur_caps ^ 1;
   if (n_prev_caps == 0) return;
   hipLaunchKernelGGL(k_filter_caps, dim3((n_prev_caps + 255) / 256), dim3(256), 0, c->stream,
                      ptr<Capture>(c->caps[prev]), n_prev_caps, ptr<uint8_t>(c->invalid_flag),
                      ptr<Capture>(c->caps[c->cur_caps]), cnt);
+}
+
+hipError_t build_ray_order(dcem_ctx* c) {
+  const int64_t n = c->n_rays;
+  hipError_t e;
+  if ((e = ensure(c->ray_order, sizeof(uint32_t) * 3 * std::max<int64_t>(n, 1) + 16)) != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  uint32_t* order = ptr<uint32_t>(c->ray_order);
+  uint32_t* tmp = order + n;
+  uint32_t* key = tmp + n;
+  uint32_t* n_dev = key + n;
+  hipLaunchKernelGGL(k_dir_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, ptr<float>(c->dirs), n,
+                     key);
+  const uint32_t n32 = (uint32_t)n;
+  if ((e = hipMemcpyAsync(n_dev, &n32, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+  if ((e = radix_sort_perm(c, key, 1, 32, n_dev, n, order, tmp, c->stream)) != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
 }
 
 void launch_los(dcem_ctx* c) {
