@@ -217,7 +217,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->counters, &c->err_word, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist, &c->path_order,
-                    &c->path_faces, &c->path_pts};
+                    &c->path_faces, &c->path_pts, &c->node_range};
   for (DevBuf* b : bufs) release(*b);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);

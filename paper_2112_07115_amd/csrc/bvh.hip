@@ -150,7 +150,7 @@ __device__ inline int lcp(const uint32_t* __restrict__ code, const uint32_t* __r
 // (Karras, "Maximizing parallelism in the construction of BVHs", 2012).
 __global__ void k_karras(const uint32_t* __restrict__ code, const uint32_t* __restrict__ perm, int n,
                          Node* __restrict__ nodes, int32_t* __restrict__ leaf_parent,
-                         int32_t* __restrict__ leaf_tri) {
+                         int32_t* __restrict__ leaf_tri, int2* __restrict__ range) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) leaf_tri[i] = (int32_t)perm[i];
   if (i >= n - 1) return;
@@ -171,6 +171,7 @@ __global__ void k_karras(const uint32_t* __restrict__ code, const uint32_t* __re
   } while (t > 1);
   int gamma = i + s * d + min(d, 0);
   int lo = min(i, j), hi = max(i, j);
+  range[i] = make_int2(lo, hi);
   int left = (lo == gamma) ? ~gamma : gamma;
   int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
   nodes[i].c.x = left;
@@ -199,17 +200,36 @@ __device__ inline void load_slot_coherent(Node* nd, int slot, float* lo, float* 
   }
 }
 
+constexpr int kRefitBlock = 1024;
+
+__device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
+  float* f = reinterpret_cast<float*>(nd);
+  const int base = slot * 6;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 // Bottom-up refit over a fixed topology.  One thread per leaf writes the leaf
 // triangle record and its padded box into its parent's slot; the second thread
-// to arrive at a node (arrival counter) forms the union and climbs on.  The
-// counter is reset by that second thread, so the next refit needs no clearing.
-// Boxes are min/max of FP32 values: the result does not depend on the order.
-__global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__ T,
-                        const int32_t* __restrict__ tri_face, const int32_t* __restrict__ leaf_tri,
-                        const int32_t* __restrict__ leaf_parent, Node* __restrict__ nodes,
-                        Leaf* __restrict__ leaves, uint32_t* __restrict__ cnt, float* __restrict__ root_box,
-                        int n, float pad) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// to arrive at a node forms the union and climbs on.  An internal node covers a
+// contiguous range of sorted leaves and is one end of it, so a node whose range
+// lies inside this block's 1024 leaves has both children here: its arrival
+// counter lives in LDS and the hand-off needs only workgroup-scope ordering.
+// Only nodes spanning several blocks use device-wide counters (reset by their
+// second arrival, so the next refit needs no clearing).  Boxes are min/max of
+// FP32 values: the result does not depend on the order of arrival.
+__global__ __launch_bounds__(kRefitBlock) void k_refit(
+    const float* __restrict__ V, const int32_t* __restrict__ T, const int32_t* __restrict__ tri_face,
+    const int32_t* __restrict__ leaf_tri, const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range,
+    Node* __restrict__ nodes, Leaf* __restrict__ leaves, uint32_t* __restrict__ cnt, float* __restrict__ root_box,
+    int n, float pad) {
+  __shared__ uint32_t lcnt[kRefitBlock];
+  lcnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int b0 = blockIdx.x * kRefitBlock;
+  const int i = b0 + threadIdx.x;
   if (i >= n) return;
   const int tri = leaf_tri[i];
   float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
@@ -232,11 +252,19 @@ __global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__
   for (int guard = n; guard > 0; --guard) {   // depth < n in a sound tree
     const int node = p2 >> 1, slot = p2 & 1;
     store_slot(&nodes[node], slot, lo, hi);
-    uint32_t old = __hip_atomic_fetch_add(&cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0) return;
-    cnt[node] = 0;
+    const int2 rg = range[node];
     float slo[3], shi[3];
-    load_slot_coherent(&nodes[node], slot ^ 1, slo, shi);
+    if (rg.x >= b0 && rg.y < b0 + kRefitBlock) {
+      const uint32_t old = __hip_atomic_fetch_add(&lcnt[node - b0], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) return;
+      load_slot_wg(&nodes[node], slot ^ 1, slo, shi);
+    } else {
+      const uint32_t old = __hip_atomic_fetch_add(&cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == 0) return;
+      cnt[node] = 0;
+      load_slot_coherent(&nodes[node], slot ^ 1, slo, shi);
+    }
     for (int k = 0; k < 3; ++k) {
       lo[k] = fminf(lo[k], slo[k]);
       hi[k] = fmaxf(hi[k], shi[k]);
@@ -308,6 +336,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->leaf_tri, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_parent, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * c->n_internal)) != hipSuccess) return e;
+  if ((e = ensure(c->node_range, sizeof(int2) * c->n_internal)) != hipSuccess) return e;
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
   uint32_t* code = ptr<uint32_t>(c->morton);
@@ -335,7 +364,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
     if ((e = hipMemcpyAsync(c->leaf_parent.p, &lp, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, code, perm, (int)nt,
-                       ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri));
+                       ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri),
+                       ptr<int2>(c->node_range));
   }
   launch_refit(c);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -348,10 +378,11 @@ hipError_t build_lbvh(dcem_ctx* c) {
 
 void launch_refit(dcem_ctx* c) {
   if (c->nt == 0) return;
-  hipLaunchKernelGGL(k_refit, dim3((c->nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
-                     ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face), ptr<int32_t>(c->leaf_tri),
-                     ptr<int32_t>(c->leaf_parent), ptr<Node>(c->nodes), ptr<Leaf>(c->leaves),
-                     ptr<uint32_t>(c->refit_cnt), ptr<float>(c->scene_box), (int)c->nt, c->pad);
+  hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
+                     c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face),
+                     ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->leaf_parent), ptr<int2>(c->node_range),
+                     ptr<Node>(c->nodes), ptr<Leaf>(c->leaves), ptr<uint32_t>(c->refit_cnt),
+                     ptr<float>(c->scene_box), (int)c->nt, c->pad);
 }
 
 hipError_t compute_sah(dcem_ctx* c, double* sah) {

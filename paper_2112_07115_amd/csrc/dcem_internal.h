@@ -81,7 +81,8 @@ struct dcem_ctx {
   int32_t n_internal = 0;
   double sah_build = 0.0, sah_last = 1.0;
   int32_t last_rebuilt = 0;
-  dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box;
+  dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
+      node_range;
 
   // -- rays and cache
   dcem::TraceConfig cfg;
