@@ -152,7 +152,7 @@ def main():
     rays = np.array([s["rays_traced"] for s in src], float)
     caps = np.array([s["captures"] for s in src], float)
     cache = 0 if "full" in res else 32
-    alg_bytes = 64 * nodes + 48 * tris + (12 + 1) * rays + (4 + cache) * segs + 8 * caps
+    alg_bytes = 128 * nodes + 48 * tris + (12 + 1) * rays + (4 + cache) * segs + 8 * caps
     achieved = float(np.mean(alg_bytes) / (np.mean(ms) * 1e-3) / 1e9)
     out["roofline"] = {"bound": "hbm", "kernel": "k_trace (full re-trace frame)", "achieved": achieved,
                        "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,

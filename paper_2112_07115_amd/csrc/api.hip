@@ -217,7 +217,8 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->counters, &c->err_word, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist, &c->path_order,
-                    &c->path_faces, &c->path_pts, &c->node_range};
+                    &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
+                    &c->bvh2_of4, &c->map4, &c->depth_key};
   for (DevBuf* b : bufs) release(*b);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -398,6 +399,7 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
     rb = 1;
   } else {
     launch_refit(c);
+    launch_collapse(c);
     HIP_TRY(hipGetLastError(), "refit kernel");
     double sah = 1.0;
     HIP_TRY(compute_sah(c, &sah), "SAH");

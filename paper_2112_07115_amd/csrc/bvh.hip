@@ -313,6 +313,75 @@ __global__ void k_sah_final(const double* __restrict__ part, int nb, const float
 
 constexpr int kSahBlocks = 64;
 
+// Depth of each binary internal node (steps to the root) as a sort key: nodes
+// at even depth become 4-wide nodes and are ordered by (depth, index), i.e.
+// breadth-first; odd-depth nodes sort to the end.
+__global__ void k_depth_keys(const Node* __restrict__ nodes, int n_internal, uint32_t* __restrict__ key,
+                             uint32_t* __restrict__ n_even) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_internal) return;
+  int d = 0, p2 = nodes[i].c.z;
+  while (p2 >= 0 && d < n_internal) {
+    ++d;
+    p2 = nodes[p2 >> 1].c.z;
+  }
+  const bool even = (d & 1) == 0;
+  key[i] = even ? ((uint32_t)d << 26) | (uint32_t)i : 0xffffffffu;
+  if (even) atomicAdd(n_even, 1u);
+}
+
+__global__ void k_map4(const uint32_t* __restrict__ perm, int n4, int32_t* __restrict__ bvh2_of,
+                       int32_t* __restrict__ map4) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n4) return;
+  const int p = (int)perm[q];
+  bvh2_of[q] = p;
+  map4[p] = q;
+}
+
+// Fill every 4-wide node from its binary node p: a leaf child of p is one
+// entry (box from p's slot); an internal child c of p contributes its two
+// children (boxes from c's slots).  Run after every build and refit.
+__global__ void k_collapse(const Node* __restrict__ nodes, const int32_t* __restrict__ bvh2_of,
+                           const int32_t* __restrict__ map4, int n4, Node4* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n4) return;
+  const int p = bvh2_of[q];
+  float lo[4][3], hi[4][3];
+  int ch[4];
+  int m = 0;
+  const float* fp = reinterpret_cast<const float*>(&nodes[p]);
+  const int cp[2] = {nodes[p].c.x, nodes[p].c.y};
+  for (int s = 0; s < 2; ++s) {
+    const int c = cp[s];
+    if (c < 0) {
+      for (int a = 0; a < 3; ++a) { lo[m][a] = fp[6 * s + a]; hi[m][a] = fp[6 * s + 3 + a]; }
+      ch[m++] = c;
+    } else {
+      const float* fc = reinterpret_cast<const float*>(&nodes[c]);
+      const int cc[2] = {nodes[c].c.x, nodes[c].c.y};
+      for (int t = 0; t < 2; ++t) {
+        for (int a = 0; a < 3; ++a) { lo[m][a] = fc[6 * t + a]; hi[m][a] = fc[6 * t + 3 + a]; }
+        ch[m++] = cc[t] < 0 ? cc[t] : map4[cc[t]];
+      }
+    }
+  }
+  for (; m < 4; ++m) {
+    for (int a = 0; a < 3; ++a) { lo[m][a] = 0.0f; hi[m][a] = 0.0f; }
+    ch[m] = kEmpty;
+  }
+  Node4 n;
+  n.lox = make_float4(lo[0][0], lo[1][0], lo[2][0], lo[3][0]);
+  n.loy = make_float4(lo[0][1], lo[1][1], lo[2][1], lo[3][1]);
+  n.loz = make_float4(lo[0][2], lo[1][2], lo[2][2], lo[3][2]);
+  n.hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
+  n.hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
+  n.hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
+  n.child = make_int4(ch[0], ch[1], ch[2], ch[3]);
+  n.pad = make_int4(0, 0, 0, 0);
+  out[q] = n;
+}
+
 }  // namespace
 
 void launch_xform(dcem_ctx* c) {
@@ -369,11 +438,40 @@ hipError_t build_lbvh(dcem_ctx* c) {
   }
   launch_refit(c);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 4-wide tree: binary nodes at even depth, breadth-first
+  const int ni = c->n_internal;
+  if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
+  uint32_t* dkey = ptr<uint32_t>(c->depth_key);
+  uint32_t* dperm = dkey + ni;
+  uint32_t* dtmp = dperm + ni;
+  uint32_t* dcount = dtmp + ni;   // [0] = even count, [1] = n
+  const uint32_t init[2] = {0u, (uint32_t)ni};
+  if ((e = hipMemcpyAsync(dcount, init, sizeof init, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_depth_keys, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), ni, dkey,
+                     dcount);
+  if ((e = radix_sort_perm(c, dkey, 1, 32, dcount + 1, ni, dperm, dtmp, c->stream)) != hipSuccess) return e;
+  uint32_t n4 = 0;
+  if ((e = hipMemcpyAsync(&n4, dcount, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  c->n4 = (int32_t)n4;
+  if ((e = ensure(c->nodes4, sizeof(Node4) * std::max<int32_t>(c->n4, 1))) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_map4, dim3((n4 + 255) / 256), dim3(256), 0, c->stream, dperm, (int)n4,
+                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4));
+  launch_collapse(c);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   double sah = 1.0;
   if ((e = compute_sah(c, &sah)) != hipSuccess) return e;
   c->sah_build = sah;
   c->has_bvh = true;
   return hipSuccess;
+}
+
+void launch_collapse(dcem_ctx* c) {
+  if (c->nt == 0 || c->n4 == 0) return;
+  hipLaunchKernelGGL(k_collapse, dim3((c->n4 + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
+                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), c->n4, ptr<Node4>(c->nodes4));
 }
 
 void launch_refit(dcem_ctx* c) {

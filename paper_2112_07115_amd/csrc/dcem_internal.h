@@ -14,7 +14,8 @@ namespace dcem {
 constexpr int kWave = 64;
 constexpr float kTMin = 1e-4f;           // hits closer than this to a segment start are ignored
 constexpr double kTMinD = 1e-4;
-constexpr int kStackSize = 64;           // traversal stack entries per lane (LDS)
+constexpr int kStackSize = 48;           // traversal stack entries per lane (LDS)
+constexpr int kTopNodes = 21;            // 4-wide nodes of the top three levels, kept in LDS
 constexpr int kTraceBlock = 128;         // threads per trace block
 constexpr uint32_t kNoRay = 0xffffffffu;
 
@@ -26,6 +27,17 @@ struct __align__(16) Node {
   float4 b0, b1, b2;
   int4 c;
 };
+
+// 4-wide node used by the traversals, 128 bytes: child boxes as SoA lanes,
+// child entries (>= 0 node, < 0 leaf ~entry, kEmpty unused).  Built by
+// collapsing every other level of the binary tree; nodes are stored in
+// breadth-first order so the top of the tree is a prefix of the array.
+struct __align__(16) Node4 {
+  float4 lox, loy, loz, hix, hiy, hiz;
+  int4 child;
+  int4 pad;
+};
+constexpr int kEmpty = (int)0x80000000;
 
 // Leaf triangle in BVH order, 48 bytes: vertices with the triangle id and its
 // face id in the w components (as integer bits).
@@ -83,6 +95,8 @@ struct dcem_ctx {
   int32_t last_rebuilt = 0;
   dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
       node_range;
+  dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
+  int32_t n4 = 0;
 
   // -- rays and cache
   dcem::TraceConfig cfg;
@@ -143,6 +157,7 @@ T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
 void launch_xform(dcem_ctx* c);
 hipError_t build_lbvh(dcem_ctx* c);
 void launch_refit(dcem_ctx* c);
+void launch_collapse(dcem_ctx* c);
 hipError_t compute_sah(dcem_ctx* c, double* sah);
 
 // ---- radix sort (sort.hip)

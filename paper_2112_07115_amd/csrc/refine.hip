@@ -79,6 +79,141 @@ __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32
   for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
 }
 
+// Whole de-duplication of a small capture list in one workgroup: keys, stable
+// LSD radix sort (8-bit digits, wavefront-ballot ranking), unique heads and
+// their compaction, all in LDS.  Used when n <= kSmallN and W <= kSmallW.
+constexpr int kSmallN = 2048;
+constexpr int kSmallW = 3;
+constexpr int kSmallThreads = 1024;
+
+__global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
+    const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos,
+    uint32_t* __restrict__ n_unique) {
+  __shared__ uint32_t key[kSmallW][kSmallN];
+  __shared__ uint32_t pa[kSmallN], pb[kSmallN];
+  __shared__ uint32_t wcnt[kSmallThreads / kWave][256];
+  __shared__ uint32_t hist[256], running[256];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr int kW = kSmallThreads / kWave;
+  for (uint32_t i = tid; i < n; i += kSmallThreads) {
+    const Capture c = caps[i];
+    const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
+    const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
+    uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < L.K; ++j) {
+      uint32_t f = 0;
+      if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
+      put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
+    }
+    int pos = L.K * L.bf;
+    put_bits(w, L.W, pos, 4, order);
+    pos += 4;
+    put_bits(w, L.W, pos, L.br, rx);
+    pos += L.br;
+    put_bits(w, L.W, pos, L.bt, tx);
+    for (int k = 0; k < L.W; ++k) {
+      key[k][i] = w[k];
+      keys_out[k * (int64_t)n + i] = w[k];
+    }
+    pa[i] = i;
+  }
+  __syncthreads();
+  uint32_t* src = pa;
+  uint32_t* dst = pb;
+  const int passes = (L.bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int word = L.W - 1 - (8 * p) / 32, shift = (8 * p) % 32;
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(key[word][src[i]] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int d = 0; d < 256; ++d) {
+        running[d] = run;
+        run += hist[d];
+      }
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += kSmallThreads) {
+      for (int w = 0; w < kW; ++w)
+        if (tid < 256) wcnt[w][tid] = 0;
+      __syncthreads();
+      const uint32_t i = base + tid;
+      const bool valid = i < n;
+      uint32_t idx = 0, d = 0;
+      if (valid) {
+        idx = src[i];
+        d = (key[word][idx] >> shift) & 0xffu;
+      }
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint64_t below = peers & ((1ull << lane) - 1ull);
+      if (valid && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = running[d] + (uint32_t)__popcll(below);
+        for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+        dst[pos] = idx;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t add = 0;
+        for (int w = 0; w < kW; ++w) add += wcnt[w][tid];
+        running[tid] += add;
+      }
+      __syncthreads();
+    }
+    uint32_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  // unique heads of the sorted keys, compacted in order (chunks of 2 per thread)
+  constexpr int kPer = kSmallN / kSmallThreads;
+  uint32_t flags = 0, cnt = 0;
+  for (int q = 0; q < kPer; ++q) {
+    const uint32_t i = tid * kPer + q;
+    bool h = false;
+    if (i < n) {
+      h = i == 0;
+      for (int k = 0; k < L.W && !h; ++k) h = key[k][src[i]] != key[k][src[i - 1]];
+    }
+    flags |= (h ? 1u : 0u) << q;
+    cnt += h ? 1u : 0u;
+  }
+  // exclusive scan of cnt over the block (hist/running reused as scratch per wave)
+  uint32_t incl = cnt;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == kWave - 1) hist[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < kW; ++w) {
+      const uint32_t v = hist[w];
+      hist[w] = run;
+      run += v;
+    }
+    hist[kW] = run;
+  }
+  __syncthreads();
+  uint32_t off = hist[wave] + incl - cnt;
+  for (int q = 0; q < kPer; ++q)
+    if ((flags >> q) & 1u) uniq_pos[off++] = tid * kPer + q;
+  for (uint32_t i = tid; i < n; i += kSmallThreads) perm_out[i] = src[i];
+  if (tid == 0) {
+    *n_unique = hist[kW];
+    uniq_pos[hist[kW]] = n;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
                                                const uint32_t* __restrict__ perm, uint32_t n,
                                                uint8_t* __restrict__ head, uint32_t* __restrict__ block_cnt) {
@@ -223,9 +358,9 @@ struct RefineArgs {
   const float* V;
   const int32_t* face_material;
   const double* materials;
-  const Node* nodes;
+  const Node4* nodes4;
   const Leaf* leaves;
-  int n_internal;
+  int n4;
   const double* freqs;
   int n_freqs;
   double sqrt_pt;
@@ -275,9 +410,9 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
 
 // Any triangle (outside faces fa, fb) crossed by the open segment p -> q,
 // keeping t_min away from both ends?  FP64 orientation tests at the leaves;
-// BVH boxes (FP32, padded) tested in FP64.
+// 4-wide tree boxes (FP32, padded) tested in FP64.
 __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* stack, int stride, bool& fault) {
-  if (a.n_internal == 0) return false;
+  if (a.n4 == 0) return false;
   const D3 dv = q - p;
   const double L = len(dv);
   const double tlo = kTMinD / L, thi = 1.0 - kTMinD / L;
@@ -285,11 +420,10 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
   const double big = 1e300;
   const double ix = dv.x != 0 ? 1.0 / dv.x : big, iy = dv.y != 0 ? 1.0 / dv.y : big,
                iz = dv.z != 0 ? 1.0 / dv.z : big;
-  int node = 0, sp = 0;
-  auto box = [&](const float* f) {
-    const double ax = (f[0] - p.x) * ix, bx = (f[3] - p.x) * ix;
-    const double ay = (f[1] - p.y) * iy, by = (f[4] - p.y) * iy;
-    const double az = (f[2] - p.z) * iz, bz = (f[5] - p.z) * iz;
+  auto box = [&](double lx, double ly, double lz, double hx, double hy, double hz) {
+    const double ax = (lx - p.x) * ix, bx = (hx - p.x) * ix;
+    const double ay = (ly - p.y) * iy, by = (hy - p.y) * iy;
+    const double az = (lz - p.z) * iz, bz = (hz - p.z) * iz;
     const double tn = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmax(fmin(az, bz), 0.0));
     const double tf = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmin(fmax(az, bz), 1.0));
     return tn <= tf * (1.0 + 1e-12);
@@ -306,27 +440,28 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
     const double s0 = vol(p, q, A, B), s1 = vol(p, q, B, C), s2 = vol(p, q, C, A);
     return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
   };
+  int node = 0, sp = 0;
   // a sound tree visits each node at most once per query; the bound only
   // guarantees termination
-  for (int64_t guard = 2 * (int64_t)a.n_internal + 2; guard > 0; --guard) {
-    const Node& nd = a.nodes[node];
-    const float* f = reinterpret_cast<const float*>(&nd);
-    bool h0 = box(f), h1 = box(f + 6);
-    const int c0 = nd.c.x, c1 = nd.c.y;
-    if (h0 && c0 < 0) { if (leaf(~c0)) return true; h0 = false; }
-    if (h1 && c1 < 0) { if (leaf(~c1)) return true; h1 = false; }
-    if (h0 && h1) {
-      if (sp < kStackSize) stack[(sp++) * stride] = c1;
-      else fault = true;
-      node = c0;
-    } else if (h0) {
-      node = c0;
-    } else if (h1) {
-      node = c1;
-    } else {
-      if (sp == 0) return false;
-      node = stack[(--sp) * stride];
+  for (int64_t guard = (int64_t)a.n4 + 2; guard > 0; --guard) {
+    const Node4 nd = a.nodes4[node];
+    const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
+    const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}, hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
+    const float hy[4] = {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w}, hz[4] = {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w};
+    const int ch[4] = {nd.child.x, nd.child.y, nd.child.z, nd.child.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (ch[e] == kEmpty || !box(lx[e], ly[e], lz[e], hx[e], hy[e], hz[e])) continue;
+      if (ch[e] < 0) {
+        if (leaf(~ch[e])) return true;
+      } else if (sp < kStackSize) {
+        stack[(sp++) * stride] = ch[e];
+      } else {
+        fault = true;
+      }
     }
+    if (sp == 0) return false;
+    node = stack[(--sp) * stride];
   }
   fault = true;
   return false;
@@ -587,6 +722,12 @@ hipError_t build_candidates(dcem_ctx* c) {
   uint8_t* head = ptr<uint8_t>(c->cand_tmp);
   uint32_t* bcnt = reinterpret_cast<uint32_t*>(ptr<uint8_t>(c->cand_tmp) + ((n + 15) / 16) * 16);
   if (n_caps == 0) return hipSuccess;   // the unique counter was cleared at frame start
+  if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
+    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
+                       n_caps, ptr<int32_t>(c->face_log), (int64_t)c->n_tx * c->n_rays, L, keys, perm,
+                       ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_caps,
                      ptr<int32_t>(c->face_log), (int64_t)c->n_tx * c->n_rays, L, keys, (int64_t)n);
   if ((e = radix_sort_perm(c, keys, L.W, L.bits, cnt + kCntCaptures, n, perm, perm + n, c->stream)) != hipSuccess)
@@ -649,9 +790,9 @@ void launch_refine(dcem_ctx* c) {
   a.V = ptr<float>(c->vertices);
   a.face_material = ptr<int32_t>(c->face_material);
   a.materials = ptr<double>(c->materials);
-  a.nodes = ptr<Node>(c->nodes);
+  a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n_internal = c->nt > 0 ? c->n_internal : 0;
+  a.n4 = c->nt > 0 ? c->n4 : 0;
   a.freqs = ptr<double>(c->freqs);
   a.n_freqs = c->n_freqs;
   a.sqrt_pt = c->sqrt_pt;

@@ -17,6 +17,14 @@ namespace {
 
 __device__ inline float comp(const float3& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
+__device__ inline uint32_t ordered_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float from_ordered(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
 struct Ray {
   float3 o, d, inv;   // origin, direction (not normalised), 1 / direction (zeros replaced)
   float sx, sy, sz;   // shear constants of the watertight test
@@ -104,42 +112,70 @@ __device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ leaves, 
   }
 }
 
+__device__ inline float lane4(const float4& v, int e) { return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)); }
+__device__ inline int lane4(const int4& v, int e) { return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)); }
+
+__device__ inline void cswap(float& ta, int& ca, float& tb, int& cb) {
+  if (tb < ta) {
+    const float t = ta; ta = tb; tb = t;
+    const int c = ca; ca = cb; cb = c;
+  }
+}
+
 // Closest hit: lexicographic minimum of (t, triangle id) over all triangles
-// with t > t_min outside face `excl`.  The result does not depend on the tree
-// shape: boxes are conservative and nodes are pruned only when their entry
-// distance exceeds the current best (ties are still visited).
-__device__ Hit closest_hit(const Ray& r, const Node* __restrict__ nodes, const Leaf* __restrict__ leaves,
-                           int n_internal, int excl, int* stack, int stride, bool& overflow, uint32_t& n_nodes,
-                           uint32_t& n_tris) {
+// with t > t_min outside face `excl`, by a stack traversal of the 4-wide tree
+// (nearest child first; the top levels are read from LDS).  The result does
+// not depend on the tree shape: boxes are conservative and nodes are pruned
+// only when their entry distance exceeds the current best (ties are visited).
+__device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const Node4* top, int n_top, int n4,
+                           const Leaf* __restrict__ leaves, int excl, int* stack, int stride, bool& overflow,
+                           uint32_t& n_nodes, uint32_t& n_tris) {
   Hit h{FLT_MAX, -1, -1, -1};
-  if (n_internal == 0) return h;
+  if (n4 == 0) return h;
   int node = 0, sp = 0;
   // a sound tree visits each node at most once per query; the bound only
   // guarantees termination
-  for (int64_t guard = 2 * (int64_t)n_internal + 2;; --guard) {
+  for (int64_t guard = (int64_t)n4 + 2;; --guard) {
     if (guard == 0) { overflow = true; break; }
-    const Node nd = nodes[node];
+    const Node4 nd = node < n_top ? top[node] : nodes[node];
     ++n_nodes;
-    float t0, t1;
-    bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, h.t, t0);
-    bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, h.t, t1);
-    const int c0 = nd.c.x, c1 = nd.c.y;
-    if (h0 && c0 < 0) { test_leaf(r, leaves, ~c0, excl, h); h0 = false; ++n_tris; }
-    if (h1 && c1 < 0) { test_leaf(r, leaves, ~c1, excl, h); h1 = false; ++n_tris; }
-    if (h0 && h1) {
-      int nearc = c0, farc = c1;
-      if (t1 < t0) { nearc = c1; farc = c0; }
-      if (sp < kStackSize) stack[(sp++) * stride] = farc;
-      else overflow = true;
-      node = nearc;
-    } else if (h0) {
-      node = c0;
-    } else if (h1) {
-      node = c1;
-    } else {
+    float t[4];
+    int c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      t[e] = INFINITY;
+      c[e] = kEmpty;
+      const int ch = lane4(nd.child, e);
+      if (ch == kEmpty) continue;
+      float tn;
+      if (!slab(r, lane4(nd.lox, e), lane4(nd.loy, e), lane4(nd.loz, e), lane4(nd.hix, e), lane4(nd.hiy, e),
+                lane4(nd.hiz, e), h.t, tn))
+        continue;
+      if (ch < 0) {
+        test_leaf(r, leaves, ~ch, excl, h);
+        ++n_tris;
+      } else {
+        t[e] = tn;
+        c[e] = ch;
+      }
+    }
+    cswap(t[0], c[0], t[1], c[1]);
+    cswap(t[2], c[2], t[3], c[3]);
+    cswap(t[0], c[0], t[2], c[2]);
+    cswap(t[1], c[1], t[3], c[3]);
+    cswap(t[1], c[1], t[2], c[2]);
+    if (c[0] == kEmpty) {
       if (sp == 0) break;
       node = stack[(--sp) * stride];
+      continue;
     }
+#pragma unroll
+    for (int e = 3; e >= 1; --e) {
+      if (c[e] == kEmpty) continue;
+      if (sp < kStackSize) stack[(sp++) * stride] = c[e];
+      else overflow = true;
+    }
+    node = c[0];
   }
   return h;
 }
@@ -161,9 +197,9 @@ __global__ void k_fibonacci(float* __restrict__ dirs, int64_t n) {
 }
 
 struct TraceArgs {
-  const Node* nodes;
+  const Node4* nodes4;
   const Leaf* leaves;
-  int n_internal;
+  int n4;
   const float* dirs;
   const uint32_t* ray_order;  // traversal order of the rays (directions sorted along a space-filling curve)
   const float* tx;
@@ -207,7 +243,11 @@ __device__ inline bool captured(const Ray& r, float tend, float dd, float cx, fl
 // restarts at its first invalidated segment from the cached segment state.
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   __shared__ int stack_mem[kStackSize * kTraceBlock];
+  __shared__ Node4 top[kTopNodes];
   int* stack = stack_mem + threadIdx.x;
+  const int n_top = min(kTopNodes, a.n4);
+  for (int i = threadIdx.x; i < n_top; i += blockDim.x) top[i] = a.nodes4[i];
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t n_work = a.work_list ? a.counters[kCntWork] : (uint32_t)a.n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
@@ -247,8 +287,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       setup_ray(r);
       uint32_t state = 0;
       for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes, a.leaves, a.n_internal, excl, stack, kTraceBlock, overflow, node_count,
-                            tri_count);
+        Hit h = closest_hit(r, a.nodes4, top, n_top, a.n4, a.leaves, excl, stack, kTraceBlock, overflow,
+                            node_count, tri_count);
         ++seg_count;
         const bool hit = h.tri >= 0;
         const float tend = hit ? h.t : INFINITY;
@@ -367,8 +407,22 @@ __global__ void k_reset_counters(uint32_t* counters) {
 __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o,
                             const float4* __restrict__ seg_d, const int32_t* __restrict__ face_log,
                             const int32_t* __restrict__ face_object, const float* __restrict__ obj_box, int n_obj,
-                            const uint32_t* __restrict__ ray_order, int64_t n_rays, int n_work,
+                            const uint32_t* __restrict__ ray_order, int64_t n_rays, int n_work, float margin,
                             uint8_t* __restrict__ restart, uint32_t* __restrict__ list, uint32_t* counters) {
+  // z range of all moving-object boxes (exact min/max through order-preserving bits)
+  __shared__ uint32_t zr[2];
+  if (threadIdx.x == 0) {
+    zr[0] = 0xffffffffu;
+    zr[1] = 0u;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_obj; b += blockDim.x) {
+    atomicMin(&zr[0], ordered_bits(obj_box[6 * b + 2]));
+    atomicMax(&zr[1], ordered_bits(obj_box[6 * b + 5]));
+  }
+  __syncthreads();
+  const float zlo = n_obj ? from_ordered(zr[0]) - margin : INFINITY;
+  const float zhi = n_obj ? from_ordered(zr[1]) + margin : -INFINITY;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   int first = 255;
@@ -386,6 +440,22 @@ __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4*
       }
       const float4 o = seg_o[(size_t)k * n_work + w];
       const float4 d = seg_d[(size_t)k * n_work + w];
+      // cull: the part of the segment inside the moving objects' z range, and
+      // its xy bounds (widened by `margin` so the cull never rejects a box the
+      // exact slab test below would accept)
+      float s0 = 0.0f, s1 = o.w;
+      if (d.z != 0.0f) {
+        const float a0 = (zlo - o.z) / d.z, a1 = (zhi - o.z) / d.z;
+        s0 = fmaxf(s0, fminf(a0, a1));
+        s1 = fminf(s1, fmaxf(a0, a1));
+      } else if (o.z < zlo || o.z > zhi) {
+        continue;
+      }
+      if (!(s0 <= s1)) continue;
+      const float xa = fmaf(s0, d.x, o.x), xb = fmaf(s1, d.x, o.x);
+      const float ya = fmaf(s0, d.y, o.y), yb = fmaf(s1, d.y, o.y);
+      const float bx0 = fminf(xa, xb) - margin, bx1 = fmaxf(xa, xb) + margin;
+      const float by0 = fminf(ya, yb) - margin, by1 = fmaxf(ya, yb) + margin;
       Ray r;
       r.o = make_float3(o.x, o.y, o.z);
       r.d = make_float3(d.x, d.y, d.z);
@@ -395,6 +465,7 @@ __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4*
                           __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
       for (int b = 0; b < n_obj; ++b) {
         const float* bx = obj_box + 6 * b;
+        if (bx[3] < bx0 || bx[0] > bx1 || bx[4] < by0 || bx[1] > by1) continue;
         float tn;
         if (slab(r, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o.w, tn)) { first = k; break; }
       }
@@ -493,9 +564,9 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_ma
   (void)n_work_max;
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
-  a.nodes = ptr<Node>(c->nodes);
+  a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n_internal = c->nt > 0 ? c->n_internal : 0;
+  a.n4 = c->nt > 0 ? c->n4 : 0;
   a.dirs = ptr<float>(c->dirs);
   a.ray_order = ptr<uint32_t>(c->ray_order);
   a.tx = ptr<float>(c->tx_pos);
@@ -543,7 +614,8 @@ void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
   hipLaunchKernelGGL(k_coherence, dim3((n_work + 255) / 256), dim3(256), 0, c->stream, ptr<uint8_t>(c->ray_state),
                      ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<int32_t>(c->face_log),
                      ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, ptr<uint32_t>(c->ray_order),
-                     c->n_rays, n_work, ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
+                     c->n_rays, n_work, 1e-3f + c->pad, ptr<uint8_t>(c->invalid_flag),
+                     ptr<uint32_t>(c->work_list), cnt);
   const int prev = c->cur_caps ^ 1;
   if (n_prev_caps == 0) return;
   hipLaunchKernelGGL(k_filter_caps, dim3((n_prev_caps + 255) / 256), dim3(256), 0, c->stream,

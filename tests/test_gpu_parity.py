@@ -89,6 +89,15 @@ def test_static_toy_dense_random_rays(ctx, O):
     assert len(ofr.keys) > 30
 
 
+def test_large_capture_list(ctx, O):
+    """More than 2048 captures: the multi-kernel sort and de-duplication path."""
+    s = scenes.static_toy()
+    s2 = scenes.Scene(**{**s.__dict__, "rx_radius": 2.0})
+    dirs = scenes.random_sphere_dirs(1_000_000, seed=13)
+    st, out, ofr = run_pair(ctx, O, s2, dirs=dirs)
+    assert ofr.trace.caps.shape[0] > 4096
+
+
 def test_ragged_ray_counts_and_orders(ctx, O):
     s = scenes.static_toy()
     for n, K in [(1, 2), (63, 0), (65, 3), (1000, 10)]:
