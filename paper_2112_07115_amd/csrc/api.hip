@@ -164,16 +164,83 @@ float ev_ms(dcem_ctx* c, int a, int b) {
   return 0.f;
 }
 
-dcem_status check_device_error(dcem_ctx* c) {
-  uint32_t err = 0;
-  HIP_TRY(hipMemcpyAsync(&err, c->err_word.p, 4, hipMemcpyDeviceToHost, c->stream), "read error word");
+// Frame block layout (bytes): counters [0, 128), error word [128, 256),
+// SAH values [256, 512), p_coh and p_inc from 512.
+constexpr size_t kBlockHead = 512;
+
+hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
+  n_pow = std::max<int64_t>(n_pow, 1);
+  if (n_pow <= c->n_pow_cap && c->frame_block.p) return hipSuccess;
+  const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
+  hipError_t e = ensure(c->frame_block, bytes);
+  if (e != hipSuccess) return e;
+  if (c->host_block) (void)hipHostFree(c->host_block);
+  c->host_block = nullptr;
+  if ((e = hipHostMalloc(&c->host_block, c->frame_block.bytes, hipHostMallocDefault)) != hipSuccess) return e;
+  c->host_block_bytes = c->frame_block.bytes;
+  char* b = ptr<char>(c->frame_block);
+  c->cnt_dev = reinterpret_cast<uint32_t*>(b);
+  c->err_dev = reinterpret_cast<uint32_t*>(b + 128);
+  c->sah_dev = reinterpret_cast<double*>(b + 256);
+  c->pcoh_dev = reinterpret_cast<double*>(b + kBlockHead);
+  c->pinc_dev = c->pcoh_dev + n_pow;
+  c->n_pow_cap = n_pow;
+  e = hipMemsetAsync(b, 0, c->frame_block.bytes, c->stream);
+  if (e != hipSuccess) return e;
+  const double one[2] = {1.0, 1.0};
+  e = hipMemcpyAsync(c->sah_dev, one, sizeof one, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+dcem_status finish_candidates(dcem_ctx* c);
+
+// Wait for the stream and read the frame block in one transfer: counters,
+// device error word, SAH values and powers.  Redoes a frame's candidates when
+// the small de-duplication path overflowed.  Reports device errors.
+dcem_status sync_frame(dcem_ctx* c) {
+  const size_t n_pow = (size_t)std::max<int64_t>(c->n_pow_cap, 1);
+  const size_t bytes = kBlockHead + 2 * sizeof(double) * n_pow;
+  HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, bytes, hipMemcpyDeviceToHost, c->stream), "read results");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  const char* hb = static_cast<const char*>(c->host_block);
+  std::memcpy(c->last_cnt, hb, sizeof(uint32_t) * kCntSlots);
+  uint32_t err = 0;
+  std::memcpy(&err, hb + 128, 4);
+  double sah[2];
+  std::memcpy(sah, hb + 256, sizeof sah);
+  if (c->refit_since_build && sah[0] > 0) c->pending_ratio = sah[1] / sah[0];
+  c->sah_last = c->pending_ratio;
+  if (c->has_frame) {
+    c->n_caps_host = std::min<int64_t>(c->last_cnt[kCntCaptures], c->cap_capacity);
+    c->counts_current = true;
+    if (c->last_cnt[kCntFallback] && !err) {
+      // more captures than the small path holds: redo the candidates exactly
+      const uint32_t zero = 0;
+      HIP_TRY(hipMemcpyAsync(c->cnt_dev + kCntFallback, &zero, 4, hipMemcpyHostToDevice, c->stream), "reset");
+      dcem_status st = finish_candidates(c);
+      if (st != DCEM_OK) return st;
+      return sync_frame(c);
+    }
+  }
   if (err) {
-    HIP_TRY(hipMemsetAsync(c->err_word.p, 0, 4, c->stream), "clear error word");
+    HIP_TRY(hipMemsetAsync(c->err_dev, 0, 4, c->stream), "clear error word");
     if (err & DCEM_ERR_NONFINITE) return fail(c, DCEM_E_INVALID_ARG, "non-finite vertex after a transform");
     return fail(c, DCEM_E_CAPACITY, "device capacity exceeded (%s%s)",
                 (err & DCEM_ERR_STACK) ? "traversal stack " : "", (err & DCEM_ERR_CAPTURES) ? "capture buffer" : "");
   }
+  return DCEM_OK;
+}
+
+dcem_status check_device_error(dcem_ctx* c) { return sync_frame(c); }
+
+// Candidates (exact count), refinement and accumulation of the current frame.
+dcem_status finish_candidates(dcem_ctx* c) {
+  HIP_TRY(build_candidates(c, false), "candidates");
+  HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");
+  launch_refine(c);
+  launch_reduce(c);
+  HIP_TRY(hipGetLastError(), "refine kernels");
   return DCEM_OK;
 }
 
@@ -190,14 +257,11 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
   dcem_ctx* c = new dcem_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (ensure(c->counters, sizeof(uint32_t) * 64) != hipSuccess || ensure(c->err_word, 256) != hipSuccess) {
+  if (ensure_frame_block(c, 1) != hipSuccess) {
+    release(c->frame_block);
+    if (c->host_block) (void)hipHostFree(c->host_block);
     delete c;
     return DCEM_E_OUT_OF_MEMORY;
-  }
-  if (hipMemsetAsync(c->counters.p, 0, sizeof(uint32_t) * 64, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->err_word.p, 0, 256, c->stream) != hipSuccess) {
-    delete c;
-    return DCEM_E_DEVICE;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
   *out = c;
@@ -214,12 +278,13 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
                     &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
                     &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
-                    &c->counters, &c->err_word, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
+                    &c->frame_block, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
-                    &c->path_amp, &c->p_coh, &c->p_inc, &c->pair_range, &c->sort_hist, &c->path_order,
+                    &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
                     &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
                     &c->bvh2_of4, &c->map4, &c->depth_key};
   for (DevBuf* b : bufs) release(*b);
+  if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -392,33 +457,27 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   if (threshold <= 0.0) threshold = 1.5;
   HIP_TRY(hipSetDevice(c->device), "set device");
   ev_record(c, 6);
+  // the decision uses the quality measured after the previous refit (read at
+  // the last synchronisation), so no host round trip is needed here
+  const double measured = c->pending_ratio;
   int32_t rb = 0;
-  double ratio = 1.0;
-  if (flags & DCEM_FORCE_REBUILD) {
+  if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
     HIP_TRY(build_lbvh(c), "rebuild BVH");
     rb = 1;
   } else {
     launch_refit(c);
     launch_collapse(c);
+    launch_sah(c, c->sah_dev + 1);
     HIP_TRY(hipGetLastError(), "refit kernel");
-    double sah = 1.0;
-    HIP_TRY(compute_sah(c, &sah), "SAH");
-    ratio = c->sah_build > 0 ? sah / c->sah_build : 1.0;
-    if (ratio > threshold) {
-      HIP_TRY(build_lbvh(c), "rebuild BVH");
-      rb = 1;
-      ratio = 1.0;
-    }
+    c->refit_since_build = true;
   }
   ev_record(c, 7);
   c->bvh_stale = false;
   c->last_rebuilt = rb;
-  c->sah_last = ratio;
+  c->refit_pending_timing = true;
   if (rebuilt) *rebuilt = rb;
-  if (sah_ratio) *sah_ratio = ratio;
-  dcem_status st = check_device_error(c);
-  c->stats.ms_refit = ev_ms(c, 6, 7);
-  return st;
+  if (sah_ratio) *sah_ratio = rb ? 1.0 : measured;
+  return DCEM_OK;
 }
 
 dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
@@ -531,25 +590,31 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   HIP_TRY(ensure(c->caps[1], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
   HIP_TRY(ensure(c->work_list, sizeof(uint32_t) * nw), "alloc work list");
   HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
-  HIP_TRY(ensure(c->p_coh, sizeof(double) * p->n_freqs * p->n_tx * p->n_rx), "alloc power");
-  HIP_TRY(ensure(c->p_inc, sizeof(double) * p->n_freqs * p->n_tx * p->n_rx), "alloc power");
-  // -- schedule
-  ev_record(c, 0);
+  HIP_TRY(ensure_frame_block(c, (int64_t)p->n_freqs * p->n_tx * p->n_rx), "alloc results");
+  // counts of the previous frame: its capture list (reused by a coherent frame),
+  // its re-trace count (sizes the persistent grid) and its capture count (picks
+  // the de-duplication path)
+  if (c->has_frame && !c->counts_current) {
+    dcem_status st = sync_frame(c);
+    if (st != DCEM_OK) return st;
+  }
   const uint32_t n_prev = (uint32_t)c->n_caps_host;
+  const int64_t expected_work = (c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work;
+  const bool small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
+  // -- schedule (no host round trip on the small path)
+  ev_record(c, 0);
   launch_reset_counters(c);
   c->cur_caps ^= 1;
-  if (coherent) {
-    launch_coherence(c, n_prev);
-  }
+  if (coherent) launch_coherence(c, n_prev);
   ev_record(c, 1);
-  if (n_work > 0) launch_trace(c, !coherent, keep_cache, n_work);
+  if (n_work > 0) launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work);
   ev_record(c, 2);
   if (p->los_always) launch_los(c);
   HIP_TRY(hipGetLastError(), "trace kernels");
   launch_face_planes(c);
-  HIP_TRY(build_candidates(c), "candidates");
+  HIP_TRY(build_candidates(c, small), "candidates");
   ev_record(c, 3);
-  HIP_TRY(ensure_paths(c, c->n_caps_host), "alloc paths");
+  HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");
   launch_refine(c);
   ev_record(c, 4);
   launch_reduce(c);
@@ -557,6 +622,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   HIP_TRY(hipGetLastError(), "refine kernels");
   c->cache_valid = keep_cache;
   c->has_frame = true;
+  c->counts_current = false;
   c->stats.coherent = coherent ? 1 : 0;
   c->stats.rays_total = n_work;
   return DCEM_OK;
@@ -568,19 +634,28 @@ dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (!p_coh || !mem_kind_ok(mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad output");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  const size_t bytes = sizeof(double) * c->n_freqs * c->n_tx * c->n_rx;
-  const hipMemcpyKind kind = mem_kind == DCEM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  HIP_TRY(hipMemcpyAsync(p_coh, c->p_coh.p, bytes, kind, c->stream), "copy power");
-  if (p_inc) HIP_TRY(hipMemcpyAsync(p_inc, c->p_inc.p, bytes, kind, c->stream), "copy power");
-  return check_device_error(c);
+  dcem_status st = sync_frame(c);
+  if (st != DCEM_OK) return st;
+  const size_t n = (size_t)c->n_freqs * c->n_tx * c->n_rx;
+  const double* hp = reinterpret_cast<const double*>(static_cast<const char*>(c->host_block) + kBlockHead);
+  if (mem_kind == DCEM_MEM_HOST) {
+    std::memcpy(p_coh, hp, sizeof(double) * n);
+    if (p_inc) std::memcpy(p_inc, hp + c->n_pow_cap, sizeof(double) * n);
+  } else {
+    HIP_TRY(hipMemcpyAsync(p_coh, c->pcoh_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream), "copy power");
+    if (p_inc)
+      HIP_TRY(hipMemcpyAsync(p_inc, c->pinc_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream), "copy power");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  }
+  return DCEM_OK;
 }
 
 dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
   if (!c || !out) return DCEM_E_INVALID_ARG;
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
-  uint32_t cnt[kCntSlots];
-  HIP_TRY(hipMemcpyAsync(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost, c->stream), "read counters");
-  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  dcem_status st = sync_frame(c);
+  if (st != DCEM_OK) return st;
+  const uint32_t* cnt = c->last_cnt;
   dcem_frame_stats& s = c->stats;
   s.rays_traced = s.coherent ? (int64_t)cnt[kCntWork] : s.rays_total;
   s.rays_reused = s.rays_total - s.rays_traced;
@@ -595,13 +670,17 @@ dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
   s.tri_tests = (int64_t)tris;
   s.rebuilt = c->last_rebuilt;
   s.sah_ratio = c->sah_last;
+  if (c->refit_pending_timing) {
+    s.ms_refit = ev_ms(c, 6, 7);
+    c->refit_pending_timing = false;
+  }
   s.ms_coherence = ev_ms(c, 0, 1);
   s.ms_trace = ev_ms(c, 1, 2);
   s.ms_candidates = ev_ms(c, 2, 3);
   s.ms_refine = ev_ms(c, 3, 4);
   s.ms_reduce = ev_ms(c, 4, 5);
   *out = s;
-  return check_device_error(c);
+  return DCEM_OK;
 }
 
 dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* valid, double* length, double* tau,
@@ -613,10 +692,7 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   HIP_TRY(hipSetDevice(c->device), "set device");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
-  uint32_t nu = 0;
-  if (c->n_caps_host > 0) {
-    HIP_TRY(hipMemcpy(&nu, ptr<uint32_t>(c->counters) + kCntUnique, 4, hipMemcpyDeviceToHost), "read count");
-  }
+  const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
   if (n_out) *n_out = nu;
   const int64_t n = std::min<int64_t>(nu, cap);
   if (n == 0) return DCEM_OK;
@@ -632,9 +708,9 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   HIP_TRY(get(amp, c->path_amp, 48 * n * (size_t)c->n_freqs), "copy amp");
   HIP_TRY(get(first_ray, c->first_ray, 4 * n), "copy first ray");
   if (keys) {
-    const int64_t nc = c->n_caps_host;
+    const int64_t nc = c->n_caps_host, ks = c->key_stride;
     const int W = c->key_words;
-    std::vector<uint32_t> kw((size_t)W * nc), perm(nc), pos(nu + 1);
+    std::vector<uint32_t> kw((size_t)W * ks), perm(nc), pos(nu + 1);
     HIP_TRY(hipMemcpy(kw.data(), c->cand_keys.p, 4 * kw.size(), hipMemcpyDeviceToHost), "copy keys");
     HIP_TRY(hipMemcpy(perm.data(), c->cand_perm.p, 4 * perm.size(), hipMemcpyDeviceToHost), "copy perm");
     HIP_TRY(hipMemcpy(pos.data(), c->uniq_idx.p, 4 * pos.size(), hipMemcpyDeviceToHost), "copy heads");
@@ -642,7 +718,7 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
       uint32_t v = 0;
       for (int b = 0; b < nb; ++b) {
         const int q = at + b;
-        const uint32_t word = kw[(size_t)(W - 1 - q / 32) * nc + idx];
+        const uint32_t word = kw[(size_t)(W - 1 - q / 32) * ks + idx];
         v |= ((word >> (q % 32)) & 1u) << b;
       }
       return v;

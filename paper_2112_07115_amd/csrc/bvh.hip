@@ -73,9 +73,18 @@ __global__ void k_xform(const float* __restrict__ ref, float* __restrict__ out,
   }
 }
 
-__global__ void k_box_init(uint32_t* box) {
+// Clear the centroid bounds (ordered bits) and store the item count next to them.
+__global__ void k_box_init(uint32_t* box, uint32_t n) {
   if (threadIdx.x < 3) box[threadIdx.x] = 0xffffffffu;
   else if (threadIdx.x < 6) box[threadIdx.x] = 0u;
+  else if (threadIdx.x == 6) box[6] = n;
+}
+
+__global__ void k_set2(uint32_t* p, uint32_t a, uint32_t* q, uint32_t b) {
+  if (threadIdx.x == 0) {
+    *p = a;
+    *q = b;
+  }
 }
 
 __device__ inline float3 load_v(const float* v, int i) { return make_float3(v[3 * i], v[3 * i + 1], v[3 * i + 2]); }
@@ -304,6 +313,7 @@ __global__ void k_sah_partial(const Node* __restrict__ nodes, int n_internal, do
 
 __global__ void k_sah_final(const double* __restrict__ part, int nb, const float* __restrict__ root,
                             double* __restrict__ out) {
+  // out: the SAH sum ratio of the current tree
   if (threadIdx.x != 0) return;
   double s = 0.0;
   for (int i = 0; i < nb; ++i) s += part[i];
@@ -330,10 +340,10 @@ __global__ void k_depth_keys(const Node* __restrict__ nodes, int n_internal, uin
   if (even) atomicAdd(n_even, 1u);
 }
 
-__global__ void k_map4(const uint32_t* __restrict__ perm, int n4, int32_t* __restrict__ bvh2_of,
-                       int32_t* __restrict__ map4) {
+__global__ void k_map4(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ n4_dev,
+                       int32_t* __restrict__ bvh2_of, int32_t* __restrict__ map4) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n4) return;
+  if (q >= (int)*n4_dev) return;
   const int p = (int)perm[q];
   bvh2_of[q] = p;
   map4[p] = q;
@@ -343,9 +353,10 @@ __global__ void k_map4(const uint32_t* __restrict__ perm, int n4, int32_t* __res
 // entry (box from p's slot); an internal child c of p contributes its two
 // children (boxes from c's slots).  Run after every build and refit.
 __global__ void k_collapse(const Node* __restrict__ nodes, const int32_t* __restrict__ bvh2_of,
-                           const int32_t* __restrict__ map4, int n4, Node4* __restrict__ out) {
+                           const int32_t* __restrict__ map4, const uint32_t* __restrict__ n4_dev,
+                           Node4* __restrict__ out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n4) return;
+  if (q >= (int)*n4_dev) return;
   const int p = bvh2_of[q];
   float lo[4][3], hi[4][3];
   int ch[4];
@@ -388,41 +399,46 @@ void launch_xform(dcem_ctx* c) {
   if (c->no == 0) return;
   hipLaunchKernelGGL(k_xform, dim3(c->no), dim3(256), 0, c->stream, ptr<float>(c->ref_vertices),
                      ptr<float>(c->vertices), ptr<int64_t>(c->obj_range), ptr<float>(c->xf),
-                     ptr<float>(c->obj_box), c->pad, ptr<uint32_t>(c->err_word));
+                     ptr<float>(c->obj_box), c->pad, c->err_dev);
 }
 
+// Build the binary LBVH and its 4-wide collapse, entirely on the stream (no
+// host round trip).  The SAH sum ratio of the new tree goes to sah_dev[0].
 hipError_t build_lbvh(dcem_ctx* c) {
   const int64_t nt = c->nt;
   hipError_t e;
   c->n_internal = nt > 1 ? (int32_t)(nt - 1) : (nt == 1 ? 1 : 0);
+  c->refit_since_build = false;
+  c->pending_ratio = 1.0;
   if (nt == 0) {
     c->has_bvh = true;
-    c->sah_build = 1.0;
     return hipSuccess;
   }
-  if ((e = ensure(c->nodes, sizeof(Node) * c->n_internal)) != hipSuccess) return e;
+  const int ni = c->n_internal;
+  if ((e = ensure(c->nodes, sizeof(Node) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->leaves, sizeof(Leaf) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_tri, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_parent, sizeof(int32_t) * nt)) != hipSuccess) return e;
-  if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * c->n_internal)) != hipSuccess) return e;
-  if ((e = ensure(c->node_range, sizeof(int2) * c->n_internal)) != hipSuccess) return e;
+  if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
+  if ((e = ensure(c->nodes4, sizeof(Node4) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
   uint32_t* code = ptr<uint32_t>(c->morton);
   uint32_t* perm = code + nt;
   uint32_t* perm_tmp = perm + nt;
-  uint32_t* nbox = perm_tmp + nt;   // 6 ordered-bit words + n
-  hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox);
+  uint32_t* nbox = perm_tmp + nt;   // 6 ordered-bit words, then n
+  hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox, (uint32_t)nt);
   const int nb = (int)std::min<int64_t>((nt + 255) / 256, 1024);
   hipLaunchKernelGGL(k_centroid_bounds, dim3(nb), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox);
   hipLaunchKernelGGL(k_morton, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox, code);
-  uint32_t n32 = (uint32_t)nt;
-  if ((e = hipMemcpyAsync(nbox + 6, &n32, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-    return e;
   if ((e = radix_sort_perm(c, code, 1, 30, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * c->n_internal, c->stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
   if (nt == 1) {
     Node root{};
     root.c = make_int4(~0, ~0, -1, 0);
@@ -431,47 +447,35 @@ hipError_t build_lbvh(dcem_ctx* c) {
     int32_t zero = 0, lp = 0;
     if ((e = hipMemcpyAsync(c->leaf_tri.p, &zero, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(c->leaf_parent.p, &lp, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, code, perm, (int)nt,
                        ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri),
                        ptr<int2>(c->node_range));
   }
   launch_refit(c);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   // 4-wide tree: binary nodes at even depth, breadth-first
-  const int ni = c->n_internal;
-  if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
-  if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
-  if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
   uint32_t* dperm = dkey + ni;
   uint32_t* dtmp = dperm + ni;
-  uint32_t* dcount = dtmp + ni;   // [0] = even count, [1] = n
-  const uint32_t init[2] = {0u, (uint32_t)ni};
-  if ((e = hipMemcpyAsync(dcount, init, sizeof init, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_depth_keys, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), ni, dkey,
-                     dcount);
-  if ((e = radix_sort_perm(c, dkey, 1, 32, dcount + 1, ni, dperm, dtmp, c->stream)) != hipSuccess) return e;
-  uint32_t n4 = 0;
-  if ((e = hipMemcpyAsync(&n4, dcount, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-  c->n4 = (int32_t)n4;
-  if ((e = ensure(c->nodes4, sizeof(Node4) * std::max<int32_t>(c->n4, 1))) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_map4, dim3((n4 + 255) / 256), dim3(256), 0, c->stream, dperm, (int)n4,
-                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4));
+  uint32_t* dn = dtmp + ni;   // item count for the sort
+  uint32_t* n4 = c->cnt_dev + kCntN4;
+  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, n4, 0u, dn, (uint32_t)ni);
+  hipLaunchKernelGGL(k_depth_keys, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), ni, dkey, n4);
+  if ((e = radix_sort_perm(c, dkey, 1, 32, dn, ni, dperm, dtmp, c->stream)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_map4, dim3((ni + 255) / 256), dim3(256), 0, c->stream, dperm, n4, ptr<int32_t>(c->bvh2_of4),
+                     ptr<int32_t>(c->map4));
   launch_collapse(c);
+  launch_sah(c, c->sah_dev + 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  double sah = 1.0;
-  if ((e = compute_sah(c, &sah)) != hipSuccess) return e;
-  c->sah_build = sah;
   c->has_bvh = true;
   return hipSuccess;
 }
 
 void launch_collapse(dcem_ctx* c) {
-  if (c->nt == 0 || c->n4 == 0) return;
-  hipLaunchKernelGGL(k_collapse, dim3((c->n4 + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
-                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), c->n4, ptr<Node4>(c->nodes4));
+  if (c->nt == 0) return;
+  hipLaunchKernelGGL(k_collapse, dim3((c->n_internal + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
+                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), c->cnt_dev + kCntN4, ptr<Node4>(c->nodes4));
 }
 
 void launch_refit(dcem_ctx* c) {
@@ -483,19 +487,12 @@ void launch_refit(dcem_ctx* c) {
                      ptr<float>(c->scene_box), (int)c->nt, c->pad);
 }
 
-hipError_t compute_sah(dcem_ctx* c, double* sah) {
-  if (c->nt == 0) {
-    *sah = 1.0;
-    return hipSuccess;
-  }
+void launch_sah(dcem_ctx* c, double* out) {
+  if (c->nt == 0) return;
   double* part = reinterpret_cast<double*>(ptr<char>(c->scene_box) + 8 * sizeof(float));
   hipLaunchKernelGGL(k_sah_partial, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
                      c->n_internal, part);
-  hipLaunchKernelGGL(k_sah_final, dim3(1), dim3(64), 0, c->stream, part, kSahBlocks, ptr<float>(c->scene_box),
-                     part + kSahBlocks);
-  hipError_t e = hipMemcpyAsync(sah, part + kSahBlocks, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(c->stream);
+  hipLaunchKernelGGL(k_sah_final, dim3(1), dim3(64), 0, c->stream, part, kSahBlocks, ptr<float>(c->scene_box), out);
 }
 
 }  // namespace dcem

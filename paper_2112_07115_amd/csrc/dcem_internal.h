@@ -96,7 +96,6 @@ struct dcem_ctx {
   dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
       node_range;
   dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
-  int32_t n4 = 0;
 
   // -- rays and cache
   dcem::TraceConfig cfg;
@@ -112,8 +111,23 @@ struct dcem_ctx {
   dcem::DevBuf caps[2];      // double-buffered capture lists
   int cur_caps = 0;
   dcem::DevBuf work_list, invalid_flag;   // re-trace list; per-ray first invalid segment (255 = valid)
-  dcem::DevBuf counters;     // uint32 device counters (see kCnt*)
-  dcem::DevBuf err_word;
+  // One device block holding everything the host reads after a frame, copied
+  // in one transfer to pinned host memory: counters (128 B), error word
+  // (128 B), SAH values (256 B), then p_coh and p_inc.
+  dcem::DevBuf frame_block;
+  void* host_block = nullptr;
+  size_t host_block_bytes = 0;
+  int64_t n_pow_cap = 0;
+  uint32_t* cnt_dev = nullptr;
+  uint32_t* err_dev = nullptr;
+  double* sah_dev = nullptr;     // [0] SAH sum ratio of the last build, [1] of the last refit
+  double* pcoh_dev = nullptr;
+  double* pinc_dev = nullptr;
+  uint32_t last_cnt[32] = {};    // counters as of the last synchronisation
+  bool counts_current = false;   // last_cnt reflects the last traced frame
+  bool refit_since_build = false;
+  double pending_ratio = 1.0;    // quality ratio measured after the last refit
+  bool refit_pending_timing = false;
 
   // -- candidates / paths
   int32_t key_words = 0, K = 0, n_freqs = 0, n_tx = 0, n_rx = 0;
@@ -121,7 +135,10 @@ struct dcem_ctx {
   int bits_tx = 0, bits_rx = 0, bits_face = 0;
   dcem::DevBuf cand_keys, cand_perm, cand_tmp, uniq_idx, first_ray;
   dcem::DevBuf path_valid, path_len, path_tau, path_aod, path_aoa, path_amp;
-  dcem::DevBuf p_coh, p_inc, pair_range, path_order, path_faces, path_pts;
+  dcem::DevBuf pair_range, path_order, path_faces, path_pts;
+  int64_t key_stride = 1;        // stride of the candidate key words
+  int64_t path_cap = 0;          // bound on the number of unique paths of the frame
+  bool small_path = false;       // candidates de-duplicated without a host round trip
   dcem::DevBuf sort_hist;
   int64_t n_caps_host = 0;
   double sqrt_pt = 0.0, atten_db_per_km = 0.0;
@@ -144,7 +161,9 @@ enum : int {
   kCntValid = 5,      // valid paths
   kCntNodes = 6,      // BVH nodes visited by the trace kernel (64-bit, slots 6-7)
   kCntTris = 8,       // triangle tests of the trace kernel (64-bit, slots 8-9)
-  kCntSlots = 10,     // number of counter words
+  kCntFallback = 10,  // the small de-duplication path saw more captures than it holds
+  kCntN4 = 11,        // 4-wide nodes of the current tree
+  kCntSlots = 12,     // number of counter words cleared per frame (kCntN4 is kept)
 };
 
 hipError_t ensure(DevBuf& b, size_t bytes);
@@ -158,7 +177,7 @@ void launch_xform(dcem_ctx* c);
 hipError_t build_lbvh(dcem_ctx* c);
 void launch_refit(dcem_ctx* c);
 void launch_collapse(dcem_ctx* c);
-hipError_t compute_sah(dcem_ctx* c, double* sah);
+void launch_sah(dcem_ctx* c, double* out);
 
 // ---- radix sort (sort.hip)
 // Stable LSD sort of n items by `bits` low bits of a multi-word key stored
@@ -169,14 +188,16 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
 
 // ---- trace (trace.hip)
 void launch_fibonacci(dcem_ctx* c);
-void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_max);
+void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected);
 void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps);
 void launch_los(dcem_ctx* c);
 void launch_reset_counters(dcem_ctx* c);
 hipError_t build_ray_order(dcem_ctx* c);
 
 // ---- candidates, refinement and accumulation (refine.hip)
-hipError_t build_candidates(dcem_ctx* c);
+hipError_t build_candidates(dcem_ctx* c, bool small);
+bool small_path_fits(const dcem_ctx* c);
+int64_t small_path_capacity();
 void launch_face_planes(dcem_ctx* c);
 hipError_t ensure_paths(dcem_ctx* c, int64_t n);
 void launch_refine(dcem_ctx* c);

@@ -87,10 +87,18 @@ constexpr int kSmallW = 3;
 constexpr int kSmallThreads = 1024;
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
-    const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos,
-    uint32_t* __restrict__ n_unique) {
+    const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, const int32_t* __restrict__ face_log,
+    int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out,
+    uint32_t* __restrict__ uniq_pos, uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
   __shared__ uint32_t key[kSmallW][kSmallN];
+  const uint32_t n = *n_dev;
+  if (n > (uint32_t)kSmallN) {   // uniform: the host redoes this frame's candidates the exact way
+    if (threadIdx.x == 0) {
+      *fallback = 1;
+      *n_unique = 0;
+    }
+    return;
+  }
   __shared__ uint32_t pa[kSmallN], pb[kSmallN];
   __shared__ uint32_t wcnt[kSmallThreads / kWave][256];
   __shared__ uint32_t hist[256], running[256];
@@ -114,7 +122,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
     put_bits(w, L.W, pos, L.bt, tx);
     for (int k = 0; k < L.W; ++k) {
       key[k][i] = w[k];
-      keys_out[k * (int64_t)n + i] = w[k];
+      keys_out[k * (int64_t)kSmallN + i] = w[k];
     }
     pa[i] = i;
   }
@@ -360,7 +368,7 @@ struct RefineArgs {
   const double* materials;
   const Node4* nodes4;
   const Leaf* leaves;
-  int n4;
+  const uint32_t* n4_dev;   // null: empty scene
   const double* freqs;
   int n_freqs;
   double sqrt_pt;
@@ -412,7 +420,8 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
 // keeping t_min away from both ends?  FP64 orientation tests at the leaves;
 // 4-wide tree boxes (FP32, padded) tested in FP64.
 __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* stack, int stride, bool& fault) {
-  if (a.n4 == 0) return false;
+  const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+  if (n4 == 0) return false;
   const D3 dv = q - p;
   const double L = len(dv);
   const double tlo = kTMinD / L, thi = 1.0 - kTMinD / L;
@@ -443,7 +452,7 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
   int node = 0, sp = 0;
   // a sound tree visits each node at most once per query; the bound only
   // guarantees termination
-  for (int64_t guard = (int64_t)a.n4 + 2; guard > 0; --guard) {
+  for (int64_t guard = (int64_t)n4 + 2; guard > 0; --guard) {
     const Node4 nd = a.nodes4[node];
     const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
     const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}, hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
@@ -689,16 +698,7 @@ int bits_for(int64_t n_values) {
   return b;
 }
 
-}  // namespace
-
-hipError_t build_candidates(dcem_ctx* c) {
-  hipError_t e;
-  uint32_t* cnt = ptr<uint32_t>(c->counters);
-  uint32_t n_caps = 0;
-  if ((e = hipMemcpyAsync(&n_caps, cnt + kCntCaptures, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-  if (n_caps > c->cap_capacity) n_caps = (uint32_t)c->cap_capacity;
-  c->n_caps_host = n_caps;
+KeyLayout key_layout(const dcem_ctx* c) {
   KeyLayout L;
   L.bt = bits_for(c->n_tx);
   L.br = bits_for(c->n_rx);
@@ -707,11 +707,60 @@ hipError_t build_candidates(dcem_ctx* c) {
   L.n_rx = c->n_rx;
   L.bits = L.bt + L.br + 4 + L.K * L.bf;
   L.W = (L.bits + 31) / 32;
+  return L;
+}
+
+}  // namespace
+
+bool small_path_fits(const dcem_ctx* c) { return key_layout(c).W <= kSmallW; }
+int64_t small_path_capacity() { return kSmallN; }
+
+// Candidate keys, sort and unique.  `small`: one workgroup de-duplicates up to
+// kSmallN captures whose count it reads on the device (no host round trip; a
+// larger count raises the fallback counter and the host redoes the frame's
+// candidates exactly).  Otherwise the capture count is read back first.
+hipError_t build_candidates(dcem_ctx* c, bool small) {
+  hipError_t e;
+  uint32_t* cnt = c->cnt_dev;
+  const KeyLayout L = key_layout(c);
   c->key_words = L.W;
   c->bits_tx = L.bt;
   c->bits_rx = L.br;
   c->bits_face = L.bf;
+  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  if (small) {
+    if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
+    if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
+    if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+    c->key_stride = kSmallN;
+    c->path_cap = kSmallN;
+    c->small_path = true;
+    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
+                       cnt + kCntCaptures, ptr<int32_t>(c->face_log), n_work, L, ptr<uint32_t>(c->cand_keys),
+                       ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
+                       cnt + kCntFallback);
+    return hipGetLastError();
+  }
+  c->small_path = false;
+  uint32_t n_caps = 0;
+  if ((e = hipMemcpyAsync(&n_caps, cnt + kCntCaptures, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (n_caps > c->cap_capacity) n_caps = (uint32_t)c->cap_capacity;
+  c->n_caps_host = n_caps;
   const int64_t n = std::max<int64_t>(n_caps, 1);
+  c->path_cap = n_caps;
+  if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
+    if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
+    if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
+    if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+    c->key_stride = kSmallN;
+    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
+                       cnt + kCntCaptures, ptr<int32_t>(c->face_log), n_work, L, ptr<uint32_t>(c->cand_keys),
+                       ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
+                       cnt + kCntFallback);
+    return hipGetLastError();
+  }
+  c->key_stride = n;
   if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * n)) != hipSuccess) return e;
   if ((e = ensure(c->cand_perm, sizeof(uint32_t) * 2 * n)) != hipSuccess) return e;
   const int nb = (int)((n + 255) / 256);
@@ -722,14 +771,8 @@ hipError_t build_candidates(dcem_ctx* c) {
   uint8_t* head = ptr<uint8_t>(c->cand_tmp);
   uint32_t* bcnt = reinterpret_cast<uint32_t*>(ptr<uint8_t>(c->cand_tmp) + ((n + 15) / 16) * 16);
   if (n_caps == 0) return hipSuccess;   // the unique counter was cleared at frame start
-  if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
-    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                       n_caps, ptr<int32_t>(c->face_log), (int64_t)c->n_tx * c->n_rays, L, keys, perm,
-                       ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_caps,
-                     ptr<int32_t>(c->face_log), (int64_t)c->n_tx * c->n_rays, L, keys, (int64_t)n);
+                     ptr<int32_t>(c->face_log), n_work, L, keys, (int64_t)n);
   if ((e = radix_sort_perm(c, keys, L.W, L.bits, cnt + kCntCaptures, n, perm, perm + n, c->stream)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_caps, head, bcnt);
@@ -763,7 +806,7 @@ hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
 }
 
 void launch_refine(dcem_ctx* c) {
-  const int64_t n = c->n_caps_host;
+  const int64_t n = c->path_cap;
   if (n == 0) return;
   KeyLayout L;
   L.bt = c->bits_tx;
@@ -775,11 +818,11 @@ void launch_refine(dcem_ctx* c) {
   L.W = c->key_words;
   RefineArgs a;
   a.keys = ptr<uint32_t>(c->cand_keys);
-  a.stride = std::max<int64_t>(n, 1);
+  a.stride = c->key_stride;
   a.L = L;
   a.perm = ptr<uint32_t>(c->cand_perm);
   a.uniq_pos = ptr<uint32_t>(c->uniq_idx);
-  a.n_unique = ptr<uint32_t>(c->counters) + kCntUnique;
+  a.n_unique = c->cnt_dev + kCntUnique;
   a.caps = ptr<Capture>(c->caps[c->cur_caps]);
   a.tx = ptr<float>(c->tx_pos);
   a.rx = ptr<float>(c->rx_pos);
@@ -792,7 +835,7 @@ void launch_refine(dcem_ctx* c) {
   a.materials = ptr<double>(c->materials);
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n4 = c->nt > 0 ? c->n4 : 0;
+  a.n4_dev = c->nt > 0 ? c->cnt_dev + kCntN4 : nullptr;
   a.freqs = ptr<double>(c->freqs);
   a.n_freqs = c->n_freqs;
   a.sqrt_pt = c->sqrt_pt;
@@ -809,8 +852,8 @@ void launch_refine(dcem_ctx* c) {
   a.order = ptr<uint8_t>(c->path_order);
   a.faces = ptr<int32_t>(c->path_faces);
   a.pts = ptr<double>(c->path_pts);
-  a.counters = ptr<uint32_t>(c->counters);
-  a.err = ptr<uint32_t>(c->err_word);
+  a.counters = c->cnt_dev;
+  a.err = c->err_dev;
   const unsigned nb = (unsigned)((n + kRefineBlock - 1) / kRefineBlock);
   hipLaunchKernelGGL(k_refine_geom, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
   const uint64_t nchk = (uint64_t)n * (2 * c->K + 1);
@@ -823,8 +866,8 @@ void launch_reduce(dcem_ctx* c) {
   const int n_pairs = c->n_tx * c->n_rx;
   hipLaunchKernelGGL(k_reduce, dim3((n_pairs * 64 + 255) / 256), dim3(256), 0, c->stream,
                      ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
-                     ptr<uint32_t>(c->counters) + kCntUnique, n_pairs, c->n_freqs, ptr<double>(c->p_coh),
-                     ptr<double>(c->p_inc));
+                     c->cnt_dev + kCntUnique, n_pairs, c->n_freqs, c->pcoh_dev,
+                     c->pinc_dev);
 }
 
 }  // namespace dcem

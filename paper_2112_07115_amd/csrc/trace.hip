@@ -199,7 +199,7 @@ __global__ void k_fibonacci(float* __restrict__ dirs, int64_t n) {
 struct TraceArgs {
   const Node4* nodes4;
   const Leaf* leaves;
-  int n4;
+  const uint32_t* n4_dev;     // number of 4-wide nodes (null: empty scene)
   const float* dirs;
   const uint32_t* ray_order;  // traversal order of the rays (directions sorted along a space-filling curve)
   const float* tx;
@@ -245,7 +245,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   __shared__ int stack_mem[kStackSize * kTraceBlock];
   __shared__ Node4 top[kTopNodes];
   int* stack = stack_mem + threadIdx.x;
-  const int n_top = min(kTopNodes, a.n4);
+  const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+  const int n_top = min(kTopNodes, n4);
   for (int i = threadIdx.x; i < n_top; i += blockDim.x) top[i] = a.nodes4[i];
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       setup_ray(r);
       uint32_t state = 0;
       for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes4, top, n_top, a.n4, a.leaves, excl, stack, kTraceBlock, overflow,
+        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.leaves, excl, stack, kTraceBlock, overflow,
                             node_count, tri_count);
         ++seg_count;
         const bool hit = h.tri >= 0;
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 }
 
 __global__ void k_reset_counters(uint32_t* counters) {
-  if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
+  if (threadIdx.x < kCntSlots && threadIdx.x != kCntN4) counters[threadIdx.x] = 0;
 }
 
 // Coherence pass.  Segment k of a cached ray is still valid iff no earlier
@@ -559,14 +560,15 @@ void launch_fibonacci(dcem_ctx* c) {
   hipLaunchKernelGGL(k_fibonacci, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, ptr<float>(c->dirs), n);
 }
 
-// Trace all work items (all_rays) or those listed by the coherence pass.
-void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_max) {
-  (void)n_work_max;
+// Trace all work items (all_rays) or those listed by the coherence pass.  The
+// persistent grid is sized for `expected` work items (any size is correct:
+// blocks drain a shared queue).
+void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) {
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n4 = c->nt > 0 ? c->n4 : 0;
+  a.n4_dev = c->nt > 0 ? c->cnt_dev + kCntN4 : nullptr;
   a.dirs = ptr<float>(c->dirs);
   a.ray_order = ptr<uint32_t>(c->ray_order);
   a.tx = ptr<float>(c->tx_pos);
@@ -590,7 +592,7 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_ma
   a.work_list = all_rays ? nullptr : ptr<uint32_t>(c->work_list);
   a.K = c->K;
   a.face_object = ptr<int32_t>(c->face_object);
-  a.counters = ptr<uint32_t>(c->counters);
+  a.counters = c->cnt_dev;
   a.face_log = ptr<int32_t>(c->face_log);
   a.ray_state = ptr<uint8_t>(c->ray_state);
   a.seg_o = keep_cache ? ptr<float4>(c->seg_o) : nullptr;
@@ -600,17 +602,19 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t n_work_ma
   a.log_len = c->record_log ? ptr<float>(c->log_len) : nullptr;
   a.caps = ptr<Capture>(c->caps[c->cur_caps]);
   a.cap_capacity = c->cap_capacity;
-  a.err = ptr<uint32_t>(c->err_word);
-  hipLaunchKernelGGL(k_trace, dim3(trace_grid(c->device)), dim3(kTraceBlock), 0, c->stream, a);
+  a.err = c->err_dev;
+  const int64_t want = (expected + expected / 4 + kTraceBlock - 1) / kTraceBlock;
+  const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(trace_grid(c->device), want));
+  hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
 }
 
 void launch_reset_counters(dcem_ctx* c) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, ptr<uint32_t>(c->counters));
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, c->cnt_dev);
 }
 
 void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
   const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
-  uint32_t* cnt = ptr<uint32_t>(c->counters);
+  uint32_t* cnt = c->cnt_dev;
   hipLaunchKernelGGL(k_coherence, dim3((n_work + 255) / 256), dim3(256), 0, c->stream, ptr<uint8_t>(c->ray_state),
                      ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<int32_t>(c->face_log),
                      ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, ptr<uint32_t>(c->ray_order),
@@ -643,7 +647,7 @@ hipError_t build_ray_order(dcem_ctx* c) {
 void launch_los(dcem_ctx* c) {
   const int n_pairs = c->n_tx * c->n_rx;
   hipLaunchKernelGGL(k_los, dim3((n_pairs + 255) / 256), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                     ptr<uint32_t>(c->counters), n_pairs, c->cap_capacity, ptr<uint32_t>(c->err_word));
+                     c->cnt_dev, n_pairs, c->cap_capacity, c->err_dev);
 }
 
 }  // namespace dcem
