@@ -427,6 +427,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->tree_info, 64)) != hipSuccess) return e;
   uint32_t* code = ptr<uint32_t>(c->morton);
   uint32_t* perm = code + nt;
   uint32_t* perm_tmp = perm + nt;
@@ -459,7 +460,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   uint32_t* dperm = dkey + ni;
   uint32_t* dtmp = dperm + ni;
   uint32_t* dn = dtmp + ni;   // item count for the sort
-  uint32_t* n4 = c->cnt_dev + kCntN4;
+  uint32_t* n4 = ptr<uint32_t>(c->tree_info);   // [0] = 4-wide node count
   hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, n4, 0u, dn, (uint32_t)ni);
   hipLaunchKernelGGL(k_depth_keys, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), ni, dkey, n4);
   if ((e = radix_sort_perm(c, dkey, 1, 32, dn, ni, dperm, dtmp, c->stream)) != hipSuccess) return e;
@@ -475,7 +476,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
 void launch_collapse(dcem_ctx* c) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_collapse, dim3((c->n_internal + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
-                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), c->cnt_dev + kCntN4, ptr<Node4>(c->nodes4));
+                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), ptr<uint32_t>(c->tree_info), ptr<Node4>(c->nodes4));
 }
 
 void launch_refit(dcem_ctx* c) {

@@ -96,6 +96,7 @@ struct dcem_ctx {
   dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
       node_range;
   dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
+  dcem::DevBuf tree_info;                            // uint32 [0]: number of 4-wide nodes
 
   // -- rays and cache
   dcem::TraceConfig cfg;
@@ -162,8 +163,7 @@ enum : int {
   kCntNodes = 6,      // BVH nodes visited by the trace kernel (64-bit, slots 6-7)
   kCntTris = 8,       // triangle tests of the trace kernel (64-bit, slots 8-9)
   kCntFallback = 10,  // the small de-duplication path saw more captures than it holds
-  kCntN4 = 11,        // 4-wide nodes of the current tree
-  kCntSlots = 12,     // number of counter words cleared per frame (kCntN4 is kept)
+  kCntSlots = 12,     // number of counter words cleared per frame
 };
 
 hipError_t ensure(DevBuf& b, size_t bytes);

@@ -835,7 +835,7 @@ void launch_refine(dcem_ctx* c) {
   a.materials = ptr<double>(c->materials);
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n4_dev = c->nt > 0 ? c->cnt_dev + kCntN4 : nullptr;
+  a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.freqs = ptr<double>(c->freqs);
   a.n_freqs = c->n_freqs;
   a.sqrt_pt = c->sqrt_pt;

@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 }
 
 __global__ void k_reset_counters(uint32_t* counters) {
-  if (threadIdx.x < kCntSlots && threadIdx.x != kCntN4) counters[threadIdx.x] = 0;
+  if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
 }
 
 // Coherence pass.  Segment k of a cached ray is still valid iff no earlier
@@ -568,7 +568,7 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected)
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
-  a.n4_dev = c->nt > 0 ? c->cnt_dev + kCntN4 : nullptr;
+  a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.dirs = ptr<float>(c->dirs);
   a.ray_order = ptr<uint32_t>(c->ray_order);
   a.tx = ptr<float>(c->tx_pos);
