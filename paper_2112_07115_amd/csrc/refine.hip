@@ -87,11 +87,14 @@ constexpr int kSmallW = 3;
 constexpr int kSmallThreads = 1024;
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
-    const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, const int32_t* __restrict__ face_log,
-    int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out,
-    uint32_t* __restrict__ uniq_pos, uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
+    const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, uint32_t capacity,
+    const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos, uint32_t* __restrict__ n_unique,
+    uint32_t* __restrict__ fallback) {
   __shared__ uint32_t key[kSmallW][kSmallN];
-  const uint32_t n = *n_dev;
+  // the counter keeps counting past the buffer when captures overflow (the
+  // trace kernel flags that); only the stored records are read
+  const uint32_t n = min(*n_dev, capacity);
   if (n > (uint32_t)kSmallN) {   // uniform: the host redoes this frame's candidates the exact way
     if (threadIdx.x == 0) {
       *fallback = 1;
@@ -736,7 +739,8 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     c->path_cap = kSmallN;
     c->small_path = true;
     hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                       cnt + kCntCaptures, ptr<int32_t>(c->face_log), n_work, L, ptr<uint32_t>(c->cand_keys),
+                       cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
+                       ptr<uint32_t>(c->cand_keys),
                        ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
                        cnt + kCntFallback);
     return hipGetLastError();
@@ -755,7 +759,8 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
     c->key_stride = kSmallN;
     hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                       cnt + kCntCaptures, ptr<int32_t>(c->face_log), n_work, L, ptr<uint32_t>(c->cand_keys),
+                       cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
+                       ptr<uint32_t>(c->cand_keys),
                        ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
                        cnt + kCntFallback);
     return hipGetLastError();
