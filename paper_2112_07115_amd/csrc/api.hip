@@ -172,7 +172,16 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   n_pow = std::max<int64_t>(n_pow, 1);
   if (n_pow <= c->n_pow_cap && c->frame_block.p) return hipSuccess;
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
-  hipError_t e = ensure(c->frame_block, bytes);
+  // keep the head (SAH values of the current tree) across a reallocation
+  double sah_keep[2] = {1.0, 1.0};
+  const bool had = c->frame_block.p != nullptr;
+  hipError_t e;
+  if (had) {
+    if ((e = hipMemcpyAsync(sah_keep, c->sah_dev, sizeof sah_keep, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  }
+  e = ensure(c->frame_block, bytes);
   if (e != hipSuccess) return e;
   if (c->host_block) (void)hipHostFree(c->host_block);
   c->host_block = nullptr;
@@ -187,8 +196,7 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   c->n_pow_cap = n_pow;
   e = hipMemsetAsync(b, 0, c->frame_block.bytes, c->stream);
   if (e != hipSuccess) return e;
-  const double one[2] = {1.0, 1.0};
-  e = hipMemcpyAsync(c->sah_dev, one, sizeof one, hipMemcpyHostToDevice, c->stream);
+  e = hipMemcpyAsync(c->sah_dev, sah_keep, sizeof sah_keep, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
 }

@@ -394,6 +394,232 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
+// Wavefront-per-ray tracing for short work lists (the rays a coherent frame
+// re-traces).  One ray is traced by a whole wavefront: the 64 lanes pop up to
+// 64 entries of a shared stack in LDS, each expands one 4-wide node (leaf
+// triangles tested at once, hit children pushed with their entry distance),
+// and the lanes' best hits are reduced to the lexicographic minimum of
+// (t, triangle id) after every step.  Nodes whose entry distance exceeds the
+// current best are skipped.  The set of triangles considered and the
+// intersection arithmetic are those of the per-thread traversal, so the hit
+// is the same; the point is latency: a traversal takes a few dependent
+// memory round trips instead of one per visited node.  Receivers are tested
+// by all lanes at once.
+constexpr int kWaveStack = 2048;
+constexpr int kWaveBlock = 128;
+constexpr int64_t kWaveTraceMax = 1 << 16;   // longest list traced a ray per wavefront
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline bool hit_less(float ta, int ia, float tb, int ib) { return ta < tb || (ta == tb && ia < ib); }
+
+__global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
+  __shared__ int stk_node[kWaveBlock / kWave][kWaveStack];
+  __shared__ float stk_t[kWaveBlock / kWave][kWaveStack];
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  int* sn = stk_node[wv];
+  float* stt = stk_t[wv];
+  const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+  const uint32_t n_work = a.counters[kCntWork];
+  uint32_t seg_count = 0, node_count = 0, tri_count = 0;
+  bool overflow = false, cap_over = false;
+  while (true) {
+    uint32_t wi = 0;
+    if (lane == 0) wi = atomicAdd(&a.counters[kCntQueue], 1u);
+    wi = __shfl(wi, 0);
+    if (wi >= n_work) break;
+    const uint32_t work = a.work_list[wi];
+    const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
+    const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
+    int k = (int)a.restart[work];
+    Ray r;
+    int excl = -1;
+    float L = 0.0f;
+    if (k == 0) {
+      r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
+      r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
+    } else {
+      const float4 so = a.seg_o[(size_t)k * a.n_work + work];
+      const float4 sd = a.seg_d[(size_t)k * a.n_work + work];
+      r.o = make_float3(so.x, so.y, so.z);
+      r.d = make_float3(sd.x, sd.y, sd.z);
+      L = sd.w;
+      excl = a.face_log[(size_t)(k - 1) * a.n_work + work];
+    }
+    setup_ray(r);
+    uint32_t state = 0;
+    for (; k <= a.K; ++k) {
+      // ---- closest hit, wavefront-wide
+      Hit h{FLT_MAX, -1, -1, -1};
+      float best_t = FLT_MAX;   // wavefront-uniform
+      int sp = 0;
+      if (n4 > 0) {
+        if (lane == 0) { sn[0] = 0; stt[0] = 0.0f; }
+        sp = 1;
+        wave_sync();
+      }
+      for (int guard = n4 + 2; sp > 0 && guard > 0; --guard) {
+        const int n_pop = min(kWave, sp);
+        bool act = lane < n_pop;
+        int node = 0;
+        float tn = 0.0f;
+        if (act) {
+          node = sn[sp - 1 - lane];
+          tn = stt[sp - 1 - lane];
+        }
+        wave_sync();
+        sp -= n_pop;
+        act = act && tn <= best_t;
+        float ct[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        int cc[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+        int m = 0;
+        if (act) {
+          const Node4 nd = a.nodes4[node];
+          ++node_count;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int ch = lane4(nd.child, e);
+            if (ch == kEmpty) continue;
+            float te;
+            if (!slab(r, lane4(nd.lox, e), lane4(nd.loy, e), lane4(nd.loz, e), lane4(nd.hix, e), lane4(nd.hiy, e),
+                      lane4(nd.hiz, e), fminf(h.t, best_t), te))
+              continue;
+            if (ch < 0) {
+              test_leaf(r, a.leaves, ~ch, excl, h);
+              ++tri_count;
+            } else {
+              ct[e] = te;
+              cc[e] = ch;
+              ++m;
+            }
+          }
+        }
+        // push the hit children: exclusive prefix of the per-lane counts
+        int incl = m;
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int v = __shfl_up(incl, off);
+          if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, kWave - 1);
+        int base = sp + incl - m;
+        if (sp + total > kWaveStack) overflow = true;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (cc[e] == kEmpty) continue;
+          if (base < kWaveStack) {
+            sn[base] = cc[e];
+            stt[base] = ct[e];
+          }
+          ++base;
+        }
+        sp = min(sp + total, kWaveStack);
+        wave_sync();
+        // wavefront-wide best so far
+        float bt = h.t;
+        int bi = h.tri;
+        for (int off = 32; off > 0; off >>= 1) {
+          const float ot = __shfl_xor(bt, off);
+          const int oi = __shfl_xor(bi, off);
+          if (hit_less(ot, oi, bt, bi)) { bt = ot; bi = oi; }
+        }
+        best_t = bt;
+      }
+      // the lane holding the winner broadcasts its record
+      {
+        float bt = h.t;
+        int bi = h.tri;
+        for (int off = 32; off > 0; off >>= 1) {
+          const float ot = __shfl_xor(bt, off);
+          const int oi = __shfl_xor(bi, off);
+          if (hit_less(ot, oi, bt, bi)) { bt = ot; bi = oi; }
+        }
+        const uint64_t owner = __ballot(h.tri == bi && h.t == bt && bi >= 0);
+        const int src = owner ? __ffsll((unsigned long long)owner) - 1 : 0;
+        h.t = bt;
+        h.tri = bi;
+        h.leaf = __shfl(h.leaf, src);
+        h.face = __shfl(h.face, src);
+        if (bi < 0) { h.leaf = -1; h.face = -1; h.t = FLT_MAX; }
+      }
+      ++seg_count;
+      const bool hit = h.tri >= 0;
+      const float tend = hit ? h.t : INFINITY;
+      if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
+      const float dl = __fsqrt_rn(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+      if (lane == 0) {
+        a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
+        a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
+        a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
+        if (a.log_tri) {
+          const size_t li = (size_t)work * (a.K + 1) + k;
+          a.log_tri[li] = h.tri;
+          a.log_t[li] = hit ? h.t : INFINITY;
+          a.log_len[li] = hit ? L + h.t * dl : INFINITY;
+        }
+      }
+      // ---- capture: lanes share the receivers
+      const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
+      const float za = r.o.z;
+      const float zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+      if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+        for (int c = lane; c < a.n_rx; c += kWave) {
+          if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
+            const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
+            if (slot < a.cap_capacity) {
+              Capture cp;
+              cp.work = work;
+              cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+              a.caps[slot] = cp;
+            } else {
+              cap_over = true;
+            }
+          }
+        }
+      }
+      if (!hit || k == a.K) { ++k; break; }
+      // ---- specular reflection (identical arithmetic on every lane)
+      L += h.t * dl;
+      const float4 p0 = a.leaves[h.leaf].v0, p1 = a.leaves[h.leaf].v1, p2 = a.leaves[h.leaf].v2;
+      const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
+      const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
+      float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+      const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
+      nx = __fdiv_rn(nx, nl); ny = __fdiv_rn(ny, nl); nz = __fdiv_rn(nz, nl);
+      const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
+      r.o = make_float3(fmaf(h.t, r.d.x, r.o.x), fmaf(h.t, r.d.y, r.o.y), fmaf(h.t, r.d.z, r.o.z));
+      r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
+      setup_ray(r);
+      excl = h.face;
+    }
+    if (lane == 0) {
+      for (int j = k; j <= a.K; ++j) {
+        a.face_log[(size_t)j * a.n_work + work] = -2;
+        if (a.log_tri) {
+          const size_t li = (size_t)work * (a.K + 1) + j;
+          a.log_tri[li] = -2;
+          a.log_t[li] = INFINITY;
+          a.log_len[li] = INFINITY;
+        }
+      }
+      a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    node_count += __shfl_xor(node_count, off);
+    tri_count += __shfl_xor(tri_count, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[kCntSegments], seg_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntNodes]), (unsigned long long)node_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntTris]), (unsigned long long)tri_count);
+  }
+  if (overflow) atomicOr(a.err, DCEM_ERR_STACK);
+  if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
+}
+
 __global__ void k_reset_counters(uint32_t* counters) {
   if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
 }
@@ -404,7 +630,6 @@ __global__ void k_reset_counters(uint32_t* counters) {
 // now.  A ray whose segments are all valid would be traced to exactly the same
 // hits and captures, so it is reused as it is; otherwise it is listed for
 // re-tracing from its first invalid segment (wavefront-aggregated append).
-// Rays are visited in the traversal order so the list stays spatially coherent.
 __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o,
                             const float4* __restrict__ seg_d, const int32_t* __restrict__ face_log,
                             const int32_t* __restrict__ face_object, const float* __restrict__ obj_box, int n_obj,
@@ -427,10 +652,8 @@ __global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4*
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   int first = 255;
-  uint32_t w = 0;
+  const uint32_t w = (uint32_t)i;
   if (i < n_work) {
-    const uint32_t txi = (uint32_t)(i / n_rays);
-    w = txi * (uint32_t)n_rays + ray_order[i - (int64_t)txi * n_rays];
     const uint32_t st = ray_state[w];
     const int nseg = (int)(st & 0x0fu);
     const bool moving_hit = (st & 0x80u) != 0;
@@ -603,6 +826,13 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected)
   a.caps = ptr<Capture>(c->caps[c->cur_caps]);
   a.cap_capacity = c->cap_capacity;
   a.err = c->err_dev;
+  if (!all_rays && expected <= kWaveTraceMax) {
+    // short re-trace list: one wavefront per ray
+    const int64_t want = (expected + expected / 4 + 1) / (kWaveBlock / kWave) + 1;
+    const int grid = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)trace_grid(c->device) * 2, want));
+    hipLaunchKernelGGL(k_trace_wave, dim3(grid), dim3(kWaveBlock), 0, c->stream, a);
+    return;
+  }
   const int64_t want = (expected + expected / 4 + kTraceBlock - 1) / kTraceBlock;
   const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(trace_grid(c->device), want));
   hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
