@@ -228,14 +228,40 @@ struct TraceArgs {
   uint32_t* err;
 };
 
+// Per-segment arithmetic shared by both trace kernels.  Contraction into fused
+// multiply-adds is disabled (fused operations are written out) so that every
+// kernel computes bitwise the same values: a reused ray must equal a re-traced one.
+
 // Capture test of one segment [o, o + tend d] against one sphere: closest
 // approach of the segment to the centre within the radius (FP32).
 __device__ inline bool captured(const Ray& r, float tend, float dd, float cx, float cy, float cz, float r2) {
+#pragma clang fp contract(off)
   const float wx = cx - r.o.x, wy = cy - r.o.y, wz = cz - r.o.z;
   float s = __fdiv_rn(wx * r.d.x + wy * r.d.y + wz * r.d.z, dd);
   s = fminf(fmaxf(s, 0.0f), tend);
   const float px = fmaf(s, r.d.x, -wx), py = fmaf(s, r.d.y, -wy), pz = fmaf(s, r.d.z, -wz);
   return px * px + py * py + pz * pz <= r2;
+}
+
+__device__ inline float dot_dd(const Ray& r) {
+#pragma clang fp contract(off)
+  return r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
+}
+
+// Specular reflection off the plane of triangle (p0, p1, p2) at parameter t.
+__device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const float4& p1, const float4& p2) {
+#pragma clang fp contract(off)
+  const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
+  const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
+  float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+  const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
+  nx = __fdiv_rn(nx, nl);
+  ny = __fdiv_rn(ny, nl);
+  nz = __fdiv_rn(nz, nl);
+  const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
+  r.o = make_float3(__fmaf_rn(t, r.d.x, r.o.x), __fmaf_rn(t, r.d.y, r.o.y), __fmaf_rn(t, r.d.z, r.o.z));
+  r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
+  setup_ray(r);
 }
 
 // Persistent trace kernel: each wavefront takes 64 consecutive work items from
@@ -299,17 +325,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
           a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
           a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
         }
-        const float dl = __fsqrt_rn(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+        const float dd = dot_dd(r);
+        const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
         if (a.log_tri) {
           const size_t li = (size_t)work * (a.K + 1) + k;
           a.log_tri[li] = h.tri;
           a.log_t[li] = hit ? h.t : INFINITY;
-          a.log_len[li] = hit ? L + h.t * dl : INFINITY;
+          a.log_len[li] = hit ? L_hit : INFINITY;
         }
         // capture: spheres whose padded box the segment meets, then the exact test
-        const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
         const float za = r.o.z;
-        const float zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+        const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
         if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
           int node = 0, sp = 0;
           for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
@@ -353,17 +379,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         }
         if (!hit || k == a.K) { ++k; break; }
         // specular reflection off the hit triangle's plane
-        L += h.t * dl;
-        const float4 p0 = a.leaves[h.leaf].v0, p1 = a.leaves[h.leaf].v1, p2 = a.leaves[h.leaf].v2;
-        const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
-        const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
-        float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-        const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
-        nx = __fdiv_rn(nx, nl); ny = __fdiv_rn(ny, nl); nz = __fdiv_rn(nz, nl);
-        const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
-        r.o = make_float3(fmaf(h.t, r.d.x, r.o.x), fmaf(h.t, r.d.y, r.o.y), fmaf(h.t, r.d.z, r.o.z));
-        r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
-        setup_ray(r);
+        L = L_hit;
+        reflect_ray(r, h.t, a.leaves[h.leaf].v0, a.leaves[h.leaf].v1, a.leaves[h.leaf].v2);
         excl = h.face;
       }
       // mark the remaining bounces as not reached
@@ -548,7 +565,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       const bool hit = h.tri >= 0;
       const float tend = hit ? h.t : INFINITY;
       if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
-      const float dl = __fsqrt_rn(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+      const float dd = dot_dd(r);
+      const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
       if (lane == 0) {
         a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
         a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
@@ -557,13 +575,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
           const size_t li = (size_t)work * (a.K + 1) + k;
           a.log_tri[li] = h.tri;
           a.log_t[li] = hit ? h.t : INFINITY;
-          a.log_len[li] = hit ? L + h.t * dl : INFINITY;
+          a.log_len[li] = hit ? L_hit : INFINITY;
         }
       }
       // ---- capture: lanes share the receivers
-      const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
       const float za = r.o.z;
-      const float zb = hit ? fmaf(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+      const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
       if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
         for (int c = lane; c < a.n_rx; c += kWave) {
           if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
@@ -581,17 +598,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       }
       if (!hit || k == a.K) { ++k; break; }
       // ---- specular reflection (identical arithmetic on every lane)
-      L += h.t * dl;
-      const float4 p0 = a.leaves[h.leaf].v0, p1 = a.leaves[h.leaf].v1, p2 = a.leaves[h.leaf].v2;
-      const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
-      const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
-      float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-      const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
-      nx = __fdiv_rn(nx, nl); ny = __fdiv_rn(ny, nl); nz = __fdiv_rn(nz, nl);
-      const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
-      r.o = make_float3(fmaf(h.t, r.d.x, r.o.x), fmaf(h.t, r.d.y, r.o.y), fmaf(h.t, r.d.z, r.o.z));
-      r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
-      setup_ray(r);
+      L = L_hit;
+      reflect_ray(r, h.t, a.leaves[h.leaf].v0, a.leaves[h.leaf].v1, a.leaves[h.leaf].v2);
       excl = h.face;
     }
     if (lane == 0) {
