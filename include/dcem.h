@@ -92,7 +92,7 @@ typedef int32_t dcem_status;
  *  object_vertex_range  [n_objects][2] half-open vertex range of each moving
  *                       object; ranges must not overlap
  *  mem_kind             DCEM_MEM_HOST or DCEM_MEM_DEVICE for all arrays
- * Limits: n_tris < 2^31 - 1, n_faces < 2^20, n_objects < 2^16. */
+ * Limits: n_tris < 2^27, n_vertices < 2^31, n_faces < 2^20, n_objects < 2^16. */
 typedef struct dcem_scene_desc {
   const float* vertices;
   int64_t n_vertices;
@@ -166,6 +166,7 @@ typedef struct dcem_frame_stats {
   int32_t coherent;          /* this frame reused the cache */
   double sah_ratio;          /* SAH cost of the tree relative to its last build */
   float ms_refit, ms_coherence, ms_trace, ms_candidates, ms_refine, ms_reduce;
+  int32_t trace_kernel;      /* closest-hit traversal used: 0 one thread per ray, 1 one wavefront per ray */
 } dcem_frame_stats;
 
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t;

@@ -290,7 +290,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
                     &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
-                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info};
+                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4};
   for (DevBuf* b : bufs) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
@@ -322,8 +322,8 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   if (!mem_kind_ok(s->mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad mem_kind");
   if (s->n_vertices < 0 || s->n_tris < 0 || s->n_faces < 0 || s->n_materials < 0 || s->n_objects < 0)
     return fail(c, DCEM_E_INVALID_ARG, "negative size");
-  if (s->n_tris >= (int64_t(1) << 31) - 1 || s->n_vertices >= (int64_t(1) << 31))
-    return fail(c, DCEM_E_UNSUPPORTED, "too many triangles or vertices");
+  if (s->n_tris >= (int64_t(1) << 27) || s->n_vertices >= (int64_t(1) << 31))
+    return fail(c, DCEM_E_UNSUPPORTED, "at most 2^27 - 1 triangles and 2^31 - 1 vertices");
   if (s->n_faces >= (1 << 20)) return fail(c, DCEM_E_UNSUPPORTED, "at most 2^20 - 1 faces");
   if (s->n_objects >= (1 << 16)) return fail(c, DCEM_E_UNSUPPORTED, "at most 2^16 - 1 objects");
   if (s->n_tris > 0 && s->n_faces == 0) return fail(c, DCEM_E_INVALID_ARG, "triangles without faces");
@@ -615,7 +615,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   c->cur_caps ^= 1;
   if (coherent) launch_coherence(c, n_prev);
   ev_record(c, 1);
-  if (n_work > 0) launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work);
+  c->last_trace_kernel = n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work) : 0;
   ev_record(c, 2);
   if (p->los_always) launch_los(c);
   HIP_TRY(hipGetLastError(), "trace kernels");
@@ -677,6 +677,7 @@ dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
   s.nodes_visited = (int64_t)nodes;
   s.tri_tests = (int64_t)tris;
   s.rebuilt = c->last_rebuilt;
+  s.trace_kernel = c->last_trace_kernel;
   s.sah_ratio = c->sah_last;
   if (c->refit_pending_timing) {
     s.ms_refit = ev_ms(c, 6, 7);

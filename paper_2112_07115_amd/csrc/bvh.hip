@@ -231,7 +231,8 @@ __device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
 // FP32 values: the result does not depend on the order of arrival.
 __global__ __launch_bounds__(kRefitBlock) void k_refit(
     const float* __restrict__ V, const int32_t* __restrict__ T, const int32_t* __restrict__ tri_face,
-    const int32_t* __restrict__ leaf_tri, const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range,
+    const int32_t* __restrict__ face_object, const int32_t* __restrict__ leaf_tri,
+    const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range,
     Node* __restrict__ nodes, Leaf* __restrict__ leaves, uint32_t* __restrict__ cnt, float* __restrict__ root_box,
     int n, float pad) {
   __shared__ uint32_t lcnt[kRefitBlock];
@@ -243,9 +244,10 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(
   const int tri = leaf_tri[i];
   float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
   Leaf L;
+  const int face = tri_face[tri];
   L.v0 = make_float4(a.x, a.y, a.z, __int_as_float(tri));
-  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(tri_face[tri]));
-  L.v2 = make_float4(c.x, c.y, c.z, 0.0f);
+  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(face));
+  L.v2 = make_float4(c.x, c.y, c.z, __int_as_float(face_object[face] >= 0 ? 1 : 0));
   leaves[i] = L;
   float lo[3] = {fminf(a.x, fminf(b.x, c.x)) - pad, fminf(a.y, fminf(b.y, c.y)) - pad,
                  fminf(a.z, fminf(b.z, c.z)) - pad};
@@ -349,47 +351,81 @@ __global__ void k_map4(const uint32_t* __restrict__ perm, const uint32_t* __rest
   map4[p] = q;
 }
 
+// Leaf-slot mask of the 4-wide node made from binary node p: its slots are,
+// in order, each leaf child of p, or the two children of each internal child
+// of p; bit j is set when slot j is a leaf.
+__device__ inline uint32_t slot_leaf_mask(const Node* __restrict__ nodes, int p) {
+  uint32_t m = 0;
+  int s = 0;
+  const int cp[2] = {nodes[p].c.x, nodes[p].c.y};
+  for (int i = 0; i < 2; ++i) {
+    if (cp[i] < 0) {
+      m |= 1u << s++;
+    } else {
+      if (nodes[cp[i]].c.x < 0) m |= 1u << s;
+      ++s;
+      if (nodes[cp[i]].c.y < 0) m |= 1u << s;
+      ++s;
+    }
+  }
+  return m;
+}
+
 // Fill every 4-wide node from its binary node p: a leaf child of p is one
 // entry (box from p's slot); an internal child c of p contributes its two
-// children (boxes from c's slots).  Run after every build and refit.
-__global__ void k_collapse(const Node* __restrict__ nodes, const int32_t* __restrict__ bvh2_of,
-                           const int32_t* __restrict__ map4, const uint32_t* __restrict__ n4_dev,
-                           Node4* __restrict__ out) {
+// children (boxes from c's slots).  Also stores the leaf-slot masks of the
+// node's child nodes (and the root's own mask in info[1]), and copies the
+// leaf triangles into slot order.  Run after every build and refit.
+__global__ void k_collapse(const Node* __restrict__ nodes, const Leaf* __restrict__ leaves,
+                           const int32_t* __restrict__ bvh2_of, const int32_t* __restrict__ map4,
+                           uint32_t* __restrict__ info, Node4* __restrict__ out, Leaf* __restrict__ tri4) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int)*n4_dev) return;
+  if (q >= (int)info[0]) return;
   const int p = bvh2_of[q];
   float lo[4][3], hi[4][3];
   int ch[4];
   int m = 0;
+  uint32_t own = 0, kids = 0;   // leaf-slot masks of this node and (4 bits per slot) of its child nodes
   const float* fp = reinterpret_cast<const float*>(&nodes[p]);
   const int cp[2] = {nodes[p].c.x, nodes[p].c.y};
   for (int s = 0; s < 2; ++s) {
     const int c = cp[s];
     if (c < 0) {
       for (int a = 0; a < 3; ++a) { lo[m][a] = fp[6 * s + a]; hi[m][a] = fp[6 * s + 3 + a]; }
+      own |= 1u << m;
       ch[m++] = c;
     } else {
       const float* fc = reinterpret_cast<const float*>(&nodes[c]);
       const int cc[2] = {nodes[c].c.x, nodes[c].c.y};
       for (int t = 0; t < 2; ++t) {
         for (int a = 0; a < 3; ++a) { lo[m][a] = fc[6 * t + a]; hi[m][a] = fc[6 * t + 3 + a]; }
-        ch[m++] = cc[t] < 0 ? cc[t] : map4[cc[t]];
+        if (cc[t] < 0) {
+          own |= 1u << m;
+          ch[m++] = cc[t];
+        } else {
+          kids |= slot_leaf_mask(nodes, cc[t]) << (4 * m);
+          ch[m++] = map4[cc[t]];
+        }
       }
     }
   }
-  for (; m < 4; ++m) {
-    for (int a = 0; a < 3; ++a) { lo[m][a] = 0.0f; hi[m][a] = 0.0f; }
-    ch[m] = kEmpty;
-  }
+  for (int e = 0; e < m; ++e)
+    if (ch[e] < 0) tri4[4 * (size_t)q + e] = leaves[~ch[e]];
   Node4 n;
-  n.lox = make_float4(lo[0][0], lo[1][0], lo[2][0], lo[3][0]);
-  n.loy = make_float4(lo[0][1], lo[1][1], lo[2][1], lo[3][1]);
-  n.loz = make_float4(lo[0][2], lo[1][2], lo[2][2], lo[3][2]);
-  n.hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
-  n.hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
-  n.hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
-  n.child = make_int4(ch[0], ch[1], ch[2], ch[3]);
-  n.pad = make_int4(0, 0, 0, 0);
+  for (int e = 0; e < 4; ++e) {
+    Slot4& sl = n.s[e];
+    if (e < m) {
+      sl.lx = lo[e][0]; sl.ly = lo[e][1]; sl.lz = lo[e][2];
+      sl.hx = hi[e][0]; sl.hy = hi[e][1]; sl.hz = hi[e][2];
+      sl.child = ch[e];
+      sl.mask = (kids >> (4 * e)) & 15u;
+    } else {
+      sl.lx = sl.ly = sl.lz = sl.hx = sl.hy = sl.hz = 0.0f;
+      sl.child = kEmpty;
+      sl.mask = 0;
+    }
+  }
+  if (q == 0) info[1] = own;
   out[q] = n;
 }
 
@@ -424,6 +460,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
   if ((e = ensure(c->nodes4, sizeof(Node4) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->tri4, sizeof(Leaf) * 4 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
@@ -476,14 +513,16 @@ hipError_t build_lbvh(dcem_ctx* c) {
 void launch_collapse(dcem_ctx* c) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_collapse, dim3((c->n_internal + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
-                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4), ptr<uint32_t>(c->tree_info), ptr<Node4>(c->nodes4));
+                     ptr<Leaf>(c->leaves), ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4),
+                     ptr<uint32_t>(c->tree_info), ptr<Node4>(c->nodes4), ptr<Leaf>(c->tri4));
 }
 
 void launch_refit(dcem_ctx* c) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
                      c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face),
-                     ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->leaf_parent), ptr<int2>(c->node_range),
+                     ptr<int32_t>(c->face_object), ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->leaf_parent),
+                     ptr<int2>(c->node_range),
                      ptr<Node>(c->nodes), ptr<Leaf>(c->leaves), ptr<uint32_t>(c->refit_cnt),
                      ptr<float>(c->scene_box), (int)c->nt, c->pad);
 }

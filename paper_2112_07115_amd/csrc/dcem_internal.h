@@ -28,19 +28,32 @@ struct __align__(16) Node {
   int4 c;
 };
 
-// 4-wide node used by the traversals, 128 bytes: child boxes as SoA lanes,
-// child entries (>= 0 node, < 0 leaf ~entry, kEmpty unused).  Built by
-// collapsing every other level of the binary tree; nodes are stored in
-// breadth-first order so the top of the tree is a prefix of the array.
+// One child slot of a 4-wide node, 32 bytes: the child's box, the child
+// entry (>= 0 node, < 0 leaf ~entry, kEmpty unused) and, for a child node, its
+// leaf-slot mask (bit j set: slot j of that child is a leaf).
+struct __align__(16) Slot4 {
+  float lx, ly, lz;
+  int child;
+  float hx, hy, hz;
+  uint32_t mask;
+};
+
+// 4-wide node used by the traversals, 128 bytes.  Built by collapsing every
+// other level of the binary tree; nodes are stored in breadth-first order so
+// the top of the tree is a prefix of the array.  A traversal that knows a
+// node's leaf-slot mask before reading it (from the parent's slot, or the
+// tree-info word for the root) can fetch the node and its leaf triangles at
+// the same time.
 struct __align__(16) Node4 {
-  float4 lox, loy, loz, hix, hiy, hiz;
-  int4 child;
-  int4 pad;
+  Slot4 s[4];
 };
 constexpr int kEmpty = (int)0x80000000;
 
-// Leaf triangle in BVH order, 48 bytes: vertices with the triangle id and its
-// face id in the w components (as integer bits).
+// Leaf triangle, 48 bytes: vertices with the triangle id, its face id and 1
+// if the face belongs to a moving object (else 0) in the w components (as
+// integer bits).  Stored twice: in sorted-leaf order (the binary tree's
+// leaves) and in slot order, [n4][4] with the leaf in slot e of 4-wide node q
+// at 4q + e (other slots unused).
 struct __align__(16) Leaf {
   float4 v0, v1, v2;
 };
@@ -74,6 +87,7 @@ struct DevBuf {
 
 struct dcem_ctx {
   int device = 0;
+  int n_cus = 0;                                     // compute units of the device (0: not queried yet)
   hipStream_t stream = nullptr;
   std::string err;
   bool timing = false;
@@ -93,10 +107,12 @@ struct dcem_ctx {
   int32_t n_internal = 0;
   double sah_build = 0.0, sah_last = 1.0;
   int32_t last_rebuilt = 0;
+  int32_t last_trace_kernel = 0;                     // traversal of the last frame (0 per thread, 1 per wavefront)
   dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
       node_range;
   dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
-  dcem::DevBuf tree_info;                            // uint32 [0]: number of 4-wide nodes
+  dcem::DevBuf tree_info;                            // uint32 [0]: number of 4-wide nodes, [1]: root leaf-slot mask
+  dcem::DevBuf tri4;                                 // leaf triangles in slot order (Leaf [n4][4])
 
   // -- rays and cache
   dcem::TraceConfig cfg;
@@ -188,7 +204,8 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
 
 // ---- trace (trace.hip)
 void launch_fibonacci(dcem_ctx* c);
-void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected);
+// Returns the traversal launched: 0 one thread per ray, 1 one wavefront per ray.
+int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected);
 void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps);
 void launch_los(dcem_ctx* c);
 void launch_reset_counters(dcem_ctx* c);

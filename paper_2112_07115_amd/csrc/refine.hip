@@ -457,17 +457,14 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
   // guarantees termination
   for (int64_t guard = (int64_t)n4 + 2; guard > 0; --guard) {
     const Node4 nd = a.nodes4[node];
-    const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
-    const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}, hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
-    const float hy[4] = {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w}, hz[4] = {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w};
-    const int ch[4] = {nd.child.x, nd.child.y, nd.child.z, nd.child.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if (ch[e] == kEmpty || !box(lx[e], ly[e], lz[e], hx[e], hy[e], hz[e])) continue;
-      if (ch[e] < 0) {
-        if (leaf(~ch[e])) return true;
+      const Slot4& sl = nd.s[e];
+      if (sl.child == kEmpty || !box(sl.lx, sl.ly, sl.lz, sl.hx, sl.hy, sl.hz)) continue;
+      if (sl.child < 0) {
+        if (leaf(~sl.child)) return true;
       } else if (sp < kStackSize) {
-        stack[(sp++) * stride] = ch[e];
+        stack[(sp++) * stride] = sl.child;
       } else {
         fault = true;
       }

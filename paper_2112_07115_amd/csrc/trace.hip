@@ -112,9 +112,6 @@ __device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ leaves, 
   }
 }
 
-__device__ inline float lane4(const float4& v, int e) { return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)); }
-__device__ inline int lane4(const int4& v, int e) { return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)); }
-
 __device__ inline void cswap(float& ta, int& ca, float& tb, int& cb) {
   if (tb < ta) {
     const float t = ta; ta = tb; tb = t;
@@ -145,12 +142,11 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
     for (int e = 0; e < 4; ++e) {
       t[e] = INFINITY;
       c[e] = kEmpty;
-      const int ch = lane4(nd.child, e);
+      const Slot4& sl = nd.s[e];
+      const int ch = sl.child;
       if (ch == kEmpty) continue;
       float tn;
-      if (!slab(r, lane4(nd.lox, e), lane4(nd.loy, e), lane4(nd.loz, e), lane4(nd.hix, e), lane4(nd.hiy, e),
-                lane4(nd.hiz, e), h.t, tn))
-        continue;
+      if (!slab(r, sl.lx, sl.ly, sl.lz, sl.hx, sl.hy, sl.hz, h.t, tn)) continue;
       if (ch < 0) {
         test_leaf(r, leaves, ~ch, excl, h);
         ++n_tris;
@@ -198,7 +194,8 @@ __global__ void k_fibonacci(float* __restrict__ dirs, int64_t n) {
 
 struct TraceArgs {
   const Node4* nodes4;
-  const Leaf* leaves;
+  const Leaf* leaves;         // leaf triangles in sorted-leaf order
+  const Leaf* tri4;           // leaf triangles in slot order
   const uint32_t* n4_dev;     // number of 4-wide nodes (null: empty scene)
   const float* dirs;
   const uint32_t* ray_order;  // traversal order of the rays (directions sorted along a space-filling curve)
@@ -412,19 +409,25 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 }
 
 // Wavefront-per-ray tracing for short work lists (the rays a coherent frame
-// re-traces).  One ray is traced by a whole wavefront: the 64 lanes pop up to
-// 64 entries of a shared stack in LDS, each expands one 4-wide node (leaf
-// triangles tested at once, hit children pushed with their entry distance),
-// and the lanes' best hits are reduced to the lexicographic minimum of
-// (t, triangle id) after every step.  Nodes whose entry distance exceeds the
-// current best are skipped.  The set of triangles considered and the
-// intersection arithmetic are those of the per-thread traversal, so the hit
-// is the same; the point is latency: a traversal takes a few dependent
-// memory round trips instead of one per visited node.  Receivers are tested
-// by all lanes at once.
-constexpr int kWaveStack = 2048;
-constexpr int kWaveBlock = 128;
-constexpr int64_t kWaveTraceMax = 1 << 16;   // longest list traced a ray per wavefront
+// re-traces).  One ray is traced by a whole wavefront, one tree level per
+// step: up to 16 entries are popped from a stack in LDS and each lane takes
+// one slot of one popped 4-wide node.  A stack entry carries its node's
+// leaf-slot mask, so a lane fetches its slot's leaf triangle or child box
+// directly (one memory round trip per step); hit child nodes are pushed with
+// their entry distance, and after every step the lanes' best hits are reduced
+// to the lexicographic minimum of (t, triangle id).  Entries whose distance
+// exceeds the current best are skipped.  The top of the tree and the
+// receivers are read from LDS.  Every triangle the per-thread traversal tests
+// is tested here too (leaf triangles without their boxes, which only drops a
+// conservative filter), with the same arithmetic, so the hit is the same.
+constexpr int kWaves = 4;                   // wavefronts per block
+constexpr int kWaveBlock = kWaves * kWave;
+constexpr int kWaveStack = 256;             // stack entries per wavefront
+constexpr int kWaveTop = 85;                // 4-wide nodes cached in LDS (four levels of a full tree)
+constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
+constexpr int kNodeBits = 27;               // stack entry: node | leaf-slot mask << kNodeBits
+constexpr uint32_t kNoEntry = 0xffffffffu;  // no child to push
+constexpr int64_t kWaveTraceMax = 1 << 16;  // longest list traced a ray per wavefront
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -433,21 +436,54 @@ __device__ inline void wave_sync() {
 
 __device__ inline bool hit_less(float ta, int ia, float tb, int ib) { return ta < tb || (ta == tb && ia < ib); }
 
+struct SlotHit {
+  float t;
+  int tri;    // original triangle id, -1 none
+  int slot;   // index into the slot triangle array
+  int face;
+  int moving; // the face belongs to a moving object
+};
+
+__device__ inline void test_slot(const Ray& r, const float4& p0, const float4& p1, const float4& p2, int slot,
+                                 int excl, SlotHit& h) {
+  const int face = __float_as_int(p1.w);
+  if (face == excl) return;
+  const float t = watertight(r, p0, p1, p2);
+  if (!(t > kTMin)) return;
+  const int tri = __float_as_int(p0.w);
+  if (hit_less(t, tri, h.t, h.tri)) {
+    h.t = t;
+    h.tri = tri;
+    h.slot = slot;
+    h.face = face;
+    h.moving = __float_as_int(p2.w);
+  }
+}
+
 __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
-  __shared__ int stk_node[kWaveBlock / kWave][kWaveStack];
-  __shared__ float stk_t[kWaveBlock / kWave][kWaveStack];
+  __shared__ Node4 top[kWaveTop];
+  __shared__ float4 rxs[kWaveRx];
+  __shared__ uint32_t stk_e[kWaves][kWaveStack];
+  __shared__ float stk_t[kWaves][kWaveStack];
   const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  int* sn = stk_node[wv];
-  float* stt = stk_t[wv];
-  const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+  const int jl = lane >> 2, el = lane & 3;   // this lane's node (of the popped ones) and slot
+  uint32_t* se = stk_e[wv];
+  float* st = stk_t[wv];
+  const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
+  const int n_top = min(kWaveTop, n4);
+  for (int i = threadIdx.x; i < n_top; i += kWaveBlock) top[i] = a.nodes4[i];
+  const bool rx_lds = a.n_rx <= kWaveRx;
+  if (rx_lds)
+    for (int i = threadIdx.x; i < a.n_rx; i += kWaveBlock)
+      rxs[i] = make_float4(a.rx[3 * i], a.rx[3 * i + 1], a.rx[3 * i + 2], 0.0f);
+  __syncthreads();
+  const uint32_t root = n4 > 0 ? a.n4_dev[1] << kNodeBits : 0u;
   const uint32_t n_work = a.counters[kCntWork];
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
-  while (true) {
-    uint32_t wi = 0;
-    if (lane == 0) wi = atomicAdd(&a.counters[kCntQueue], 1u);
-    wi = __shfl(wi, 0);
-    if (wi >= n_work) break;
+  // first item by position, then from the shared queue
+  uint32_t wi = blockIdx.x * kWaves + wv;
+  while (wi < n_work) {
     const uint32_t work = a.work_list[wi];
     const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
     const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
@@ -469,69 +505,65 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     setup_ray(r);
     uint32_t state = 0;
     for (; k <= a.K; ++k) {
-      // ---- closest hit, wavefront-wide
-      Hit h{FLT_MAX, -1, -1, -1};
-      float best_t = FLT_MAX;   // wavefront-uniform
+      // ---- closest hit, one tree level per step
+      SlotHit h{FLT_MAX, -1, -1, -1, 0};
+      float best_t = INFINITY;   // wavefront-uniform (infinite while nothing is hit)
       int sp = 0;
       if (n4 > 0) {
-        if (lane == 0) { sn[0] = 0; stt[0] = 0.0f; }
+        if (lane == 0) { se[0] = root; st[0] = 0.0f; }
         sp = 1;
         wave_sync();
       }
       for (int guard = n4 + 2; sp > 0 && guard > 0; --guard) {
-        const int n_pop = min(kWave, sp);
-        bool act = lane < n_pop;
-        int node = 0;
+        const int n_pop = min(kWave / 4, sp);
+        bool act = jl < n_pop;
+        uint32_t ent = 0;
         float tn = 0.0f;
         if (act) {
-          node = sn[sp - 1 - lane];
-          tn = stt[sp - 1 - lane];
+          ent = se[sp - 1 - jl];
+          tn = st[sp - 1 - jl];
         }
         wave_sync();
         sp -= n_pop;
         act = act && tn <= best_t;
-        float ct[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-        int cc[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
-        int m = 0;
-        if (act) {
-          const Node4 nd = a.nodes4[node];
-          ++node_count;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int ch = lane4(nd.child, e);
-            if (ch == kEmpty) continue;
-            float te;
-            if (!slab(r, lane4(nd.lox, e), lane4(nd.loy, e), lane4(nd.loz, e), lane4(nd.hix, e), lane4(nd.hiy, e),
-                      lane4(nd.hiz, e), fminf(h.t, best_t), te))
-              continue;
-            if (ch < 0) {
-              test_leaf(r, a.leaves, ~ch, excl, h);
-              ++tri_count;
-            } else {
-              ct[e] = te;
-              cc[e] = ch;
-              ++m;
-            }
+        const int node = (int)(ent & ((1u << kNodeBits) - 1));
+        const bool leaf = act && ((ent >> (kNodeBits + el)) & 1u);
+        const bool inner = act && !leaf;
+        // this lane's slot: the leaf triangle, or the child's box and entry
+        float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+        if (leaf) {
+          const Leaf& lf = a.tri4[4 * (size_t)node + el];
+          q0 = lf.v0;
+          q1 = lf.v1;
+          q2 = lf.v2;
+        } else if (inner) {
+          const float4* sl = reinterpret_cast<const float4*>(node < n_top ? &top[node].s[el] : &a.nodes4[node].s[el]);
+          q0 = sl[0];
+          q1 = sl[1];
+        }
+        uint32_t push = kNoEntry;
+        float pt = 0.0f;
+        if (leaf) {
+          test_slot(r, q0, q1, q2, 4 * node + el, excl, h);
+          ++tri_count;
+        } else if (inner) {
+          const int ch = __float_as_int(q0.w);
+          float te;
+          if (ch != kEmpty && slab(r, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z, fminf(h.t, best_t), te)) {
+            push = (uint32_t)ch | (__float_as_uint(q1.w) << kNodeBits);
+            pt = te;
           }
         }
-        // push the hit children: exclusive prefix of the per-lane counts
-        int incl = m;
-        for (int off = 1; off < kWave; off <<= 1) {
-          const int v = __shfl_up(incl, off);
-          if (lane >= off) incl += v;
+        if (act && el == 0) ++node_count;
+        // push the hit children in lane order
+        const uint64_t want = __ballot(push != kNoEntry);
+        const int total = __popcll(want);
+        const int pos = sp + __popcll(want & ((1ull << lane) - 1ull));
+        if (push != kNoEntry && pos < kWaveStack) {
+          se[pos] = push;
+          st[pos] = pt;
         }
-        const int total = __shfl(incl, kWave - 1);
-        int base = sp + incl - m;
         if (sp + total > kWaveStack) overflow = true;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (cc[e] == kEmpty) continue;
-          if (base < kWaveStack) {
-            sn[base] = cc[e];
-            stt[base] = ct[e];
-          }
-          ++base;
-        }
         sp = min(sp + total, kWaveStack);
         wave_sync();
         // wavefront-wide best so far
@@ -542,7 +574,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
           const int oi = __shfl_xor(bi, off);
           if (hit_less(ot, oi, bt, bi)) { bt = ot; bi = oi; }
         }
-        best_t = bt;
+        best_t = bi >= 0 ? bt : INFINITY;
       }
       // the lane holding the winner broadcasts its record
       {
@@ -555,16 +587,26 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
         }
         const uint64_t owner = __ballot(h.tri == bi && h.t == bt && bi >= 0);
         const int src = owner ? __ffsll((unsigned long long)owner) - 1 : 0;
+        h.slot = __shfl(h.slot, src);
+        h.face = __shfl(h.face, src);
+        h.moving = __shfl(h.moving, src);
         h.t = bt;
         h.tri = bi;
-        h.leaf = __shfl(h.leaf, src);
-        h.face = __shfl(h.face, src);
-        if (bi < 0) { h.leaf = -1; h.face = -1; h.t = FLT_MAX; }
+        if (bi < 0) { h.slot = -1; h.face = -1; h.moving = 0; h.t = FLT_MAX; }
       }
       ++seg_count;
       const bool hit = h.tri >= 0;
+      const bool more = hit && k < a.K;
+      // the reflecting triangle, fetched while the receivers are tested
+      float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
+      if (more) {
+        const Leaf& lf = a.tri4[h.slot];
+        w0 = lf.v0;
+        w1 = lf.v1;
+        w2 = lf.v2;
+      }
       const float tend = hit ? h.t : INFINITY;
-      if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
+      if (hit && h.moving) state |= 0x80u;
       const float dd = dot_dd(r);
       const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
       if (lane == 0) {
@@ -583,7 +625,18 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
       if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
         for (int c = lane; c < a.n_rx; c += kWave) {
-          if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
+          float cx, cy, cz;
+          if (rx_lds) {
+            const float4 q = rxs[c];
+            cx = q.x;
+            cy = q.y;
+            cz = q.z;
+          } else {
+            cx = a.rx[3 * c];
+            cy = a.rx[3 * c + 1];
+            cz = a.rx[3 * c + 2];
+          }
+          if (captured(r, tend, dd, cx, cy, cz, a.r2)) {
             const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
             if (slot < a.cap_capacity) {
               Capture cp;
@@ -596,10 +649,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
           }
         }
       }
-      if (!hit || k == a.K) { ++k; break; }
+      if (!more) { ++k; break; }
       // ---- specular reflection (identical arithmetic on every lane)
       L = L_hit;
-      reflect_ray(r, h.t, a.leaves[h.leaf].v0, a.leaves[h.leaf].v1, a.leaves[h.leaf].v2);
+      reflect_ray(r, h.t, w0, w1, w2);
       excl = h.face;
     }
     if (lane == 0) {
@@ -614,6 +667,9 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       }
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
     }
+    uint32_t next = 0;
+    if (lane == 0) next = gridDim.x * kWaves + atomicAdd(&a.counters[kCntQueue], 1u);
+    wi = __shfl(next, 0);
   }
   for (int off = 32; off > 0; off >>= 1) {
     node_count += __shfl_xor(node_count, off);
@@ -774,14 +830,17 @@ __global__ void k_los(Capture* __restrict__ caps, uint32_t* counters, int n_pair
   }
 }
 
-int trace_grid(int device) {
-  static int cus = 0;
-  if (cus == 0) {
+int cu_count(dcem_ctx* c) {
+  if (c->n_cus == 0) {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
-    if (cus <= 0) cus = 256;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cus = prop.multiProcessorCount;
+    if (c->n_cus <= 0) c->n_cus = 256;
   }
-  return cus * 5;   // 32 KB of LDS stack per block: five blocks per CU
+  return c->n_cus;
+}
+
+int trace_grid(dcem_ctx* c) {
+  return cu_count(c) * 5;   // 24 KB of LDS stack per block: five blocks per CU
 }
 
 }  // namespace
@@ -794,11 +853,12 @@ void launch_fibonacci(dcem_ctx* c) {
 // Trace all work items (all_rays) or those listed by the coherence pass.  The
 // persistent grid is sized for `expected` work items (any size is correct:
 // blocks drain a shared queue).
-void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) {
+int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) {
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.leaves = ptr<Leaf>(c->leaves);
+  a.tri4 = ptr<Leaf>(c->tri4);
   a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.dirs = ptr<float>(c->dirs);
   a.ray_order = ptr<uint32_t>(c->ray_order);
@@ -836,14 +896,15 @@ void launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected)
   a.err = c->err_dev;
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
-    const int64_t want = (expected + expected / 4 + 1) / (kWaveBlock / kWave) + 1;
-    const int grid = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)trace_grid(c->device) * 2, want));
+    const int64_t want = (expected + expected / 4 + kWaves - 1) / kWaves + 1;
+    const int grid = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)cu_count(c) * 8, want));
     hipLaunchKernelGGL(k_trace_wave, dim3(grid), dim3(kWaveBlock), 0, c->stream, a);
-    return;
+    return 1;
   }
   const int64_t want = (expected + expected / 4 + kTraceBlock - 1) / kTraceBlock;
-  const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(trace_grid(c->device), want));
+  const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(trace_grid(c), want));
   hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
+  return 0;
 }
 
 void launch_reset_counters(dcem_ctx* c) {

@@ -47,7 +47,8 @@ class FrameStats(ctypes.Structure):
                 ("captures", _I64), ("unique_candidates", _I64), ("valid_paths", _I64),
                 ("nodes_visited", _I64), ("tri_tests", _I64), ("rebuilt", _I32),
                 ("coherent", _I32), ("sah_ratio", _F64), ("ms_refit", _F32), ("ms_coherence", _F32),
-                ("ms_trace", _F32), ("ms_candidates", _F32), ("ms_refine", _F32), ("ms_reduce", _F32)]
+                ("ms_trace", _F32), ("ms_candidates", _F32), ("ms_refine", _F32), ("ms_reduce", _F32),
+                ("trace_kernel", _I32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
