@@ -459,7 +459,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
-  if ((e = ensure(c->nodes4, sizeof(Node4) * ni)) != hipSuccess) return e;
+  // one spare node: the re-trace reads 48 bytes from a 32-byte slot
+  if ((e = ensure(c->nodes4, sizeof(Node4) * (ni + 1))) != hipSuccess) return e;
   if ((e = ensure(c->tri4, sizeof(Leaf) * 4 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;

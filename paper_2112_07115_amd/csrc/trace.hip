@@ -52,16 +52,40 @@ __device__ inline void setup_ray(Ray& r) {
 // +z; the 2D edge functions decide the hit, with an FP64 re-evaluation when
 // one is exactly zero.  Edge functions are evaluated without FMA contraction
 // so that two triangles sharing an edge compute exactly opposite values.
-// Returns the hit distance t (IEEE division) or -1.
-__device__ inline float watertight(const Ray& r, const float4& p0, const float4& p1, const float4& p2) {
+// Returns the hit distance t (IEEE division) or -1.  The axis permutation is
+// read through a policy: the ray's axis indices (per-thread traversal) or
+// per-lane select masks precomputed once per segment (group traversal); the
+// arithmetic is the same.
+struct RayAxes {
+  int kx, ky, kz;
+  __device__ float x(const float3& v) const { return comp(v, kx); }
+  __device__ float y(const float3& v) const { return comp(v, ky); }
+  __device__ float z(const float3& v) const { return comp(v, kz); }
+};
+
+// Component selection by bit masks (all ones for the chosen component), so
+// that lanes tracing different rays need no branches.
+struct MaskAxes {
+  uint32_t x0, x1, x2, y0, y1, y2, z0, z1, z2;
+  __device__ static float pick(const float3& v, uint32_t m0, uint32_t m1, uint32_t m2) {
+    return __uint_as_float((__float_as_uint(v.x) & m0) | (__float_as_uint(v.y) & m1) | (__float_as_uint(v.z) & m2));
+  }
+  __device__ float x(const float3& v) const { return pick(v, x0, x1, x2); }
+  __device__ float y(const float3& v) const { return pick(v, y0, y1, y2); }
+  __device__ float z(const float3& v) const { return pick(v, z0, z1, z2); }
+};
+
+template <class Axes>
+__device__ inline float watertight_axes(const Ray& r, const Axes& ax, const float4& p0, const float4& p1,
+                                        const float4& p2) {
 #pragma clang fp contract(off)
   const float3 A = make_float3(p0.x - r.o.x, p0.y - r.o.y, p0.z - r.o.z);
   const float3 B = make_float3(p1.x - r.o.x, p1.y - r.o.y, p1.z - r.o.z);
   const float3 C = make_float3(p2.x - r.o.x, p2.y - r.o.y, p2.z - r.o.z);
-  const float Az = comp(A, r.kz), Bz = comp(B, r.kz), Cz = comp(C, r.kz);
-  const float Ax = comp(A, r.kx) - r.sx * Az, Ay = comp(A, r.ky) - r.sy * Az;
-  const float Bx = comp(B, r.kx) - r.sx * Bz, By = comp(B, r.ky) - r.sy * Bz;
-  const float Cx = comp(C, r.kx) - r.sx * Cz, Cy = comp(C, r.ky) - r.sy * Cz;
+  const float Az = ax.z(A), Bz = ax.z(B), Cz = ax.z(C);
+  const float Ax = ax.x(A) - r.sx * Az, Ay = ax.y(A) - r.sy * Az;
+  const float Bx = ax.x(B) - r.sx * Bz, By = ax.y(B) - r.sy * Bz;
+  const float Cx = ax.x(C) - r.sx * Cz, Cy = ax.y(C) - r.sy * Cz;
   float U = Cx * By - Cy * Bx;
   float V = Ax * Cy - Ay * Cx;
   float W = Bx * Ay - By * Ax;
@@ -75,6 +99,10 @@ __device__ inline float watertight(const Ray& r, const float4& p0, const float4&
   if (det == 0.0f) return -1.0f;
   const float T = U * (r.sz * Az) + V * (r.sz * Bz) + W * (r.sz * Cz);
   return __fdiv_rn(T, det);
+}
+
+__device__ inline float watertight(const Ray& r, const float4& p0, const float4& p1, const float4& p2) {
+  return watertight_axes(r, RayAxes{r.kx, r.ky, r.kz}, p0, p1, p2);
 }
 
 // Conservative slab test against a box given as (lo, hi) over (t0, tmax].
@@ -408,26 +436,29 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
-// Wavefront-per-ray tracing for short work lists (the rays a coherent frame
-// re-traces).  One ray is traced by a whole wavefront, one tree level per
-// step: up to 16 entries are popped from a stack in LDS and each lane takes
-// one slot of one popped 4-wide node.  A stack entry carries its node's
-// leaf-slot mask, so a lane fetches its slot's leaf triangle or child box
-// directly (one memory round trip per step); hit child nodes are pushed with
-// their entry distance, and after every step the lanes' best hits are reduced
-// to the lexicographic minimum of (t, triangle id).  Entries whose distance
-// exceeds the current best are skipped.  The top of the tree and the
-// receivers are read from LDS.  Every triangle the per-thread traversal tests
-// is tested here too (leaf triangles without their boxes, which only drops a
-// conservative filter), with the same arithmetic, so the hit is the same.
+// Group-per-ray tracing for short work lists (the rays a coherent frame
+// re-traces).  A ray is traced by a group of 16 lanes (one DPP row), four rays
+// per wavefront, one tree level per step: a group pops up to four entries of
+// its stack in LDS and each lane takes one slot of one popped 4-wide node.  A
+// stack entry carries its node's leaf-slot mask, so a lane fetches its slot's
+// leaf triangle or child box directly (one memory round trip per step); hit
+// child nodes are pushed with their entry distance, and after every step the
+// group's best hits are reduced to the lexicographic minimum of (t, triangle
+// id).  Entries whose distance exceeds the current best are skipped.  When a
+// group's stack empties it finishes the segment (logs, receivers, reflection)
+// and continues with the next segment or ray while the other groups keep
+// traversing.  Every triangle the per-thread traversal tests is tested here
+// too (leaf triangles without their boxes, which only drops a conservative
+// filter), with the same arithmetic, so the hit is the same.
+constexpr int kGroup = 16;                  // lanes per ray: one DPP row
+constexpr int kGroups = kWave / kGroup;     // rays per wavefront
 constexpr int kWaves = 4;                   // wavefronts per block
 constexpr int kWaveBlock = kWaves * kWave;
-constexpr int kWaveStack = 256;             // stack entries per wavefront
-constexpr int kWaveTop = 85;                // 4-wide nodes cached in LDS (four levels of a full tree)
+constexpr int kGroupStack = 128;            // stack entries per group
 constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
 constexpr int kNodeBits = 27;               // stack entry: node | leaf-slot mask << kNodeBits
 constexpr uint32_t kNoEntry = 0xffffffffu;  // no child to push
-constexpr int64_t kWaveTraceMax = 1 << 16;  // longest list traced a ray per wavefront
+constexpr int64_t kWaveTraceMax = 1 << 16;  // longest list traced by groups
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -435,6 +466,32 @@ __device__ inline void wave_sync() {
 }
 
 __device__ inline bool hit_less(float ta, int ia, float tb, int ib) { return ta < tb || (ta == tb && ia < ib); }
+
+// (t, triangle id) as one key ordered lexicographically: hit distances are
+// positive, so their bit patterns order like the values; no hit is all ones.
+__device__ inline uint64_t hit_key(float t, int tri) {
+  return tri < 0 ? ~0ull : ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)tri;
+}
+
+// Minimum over each row of 16 lanes by data-parallel primitives: swaps within
+// pairs and quads, then the mirrored halves of the row, then the whole row.
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return ((uint64_t)nhi << 32) | nlo;
+}
+__device__ inline uint64_t row_min_u64(uint64_t v) {
+  uint64_t o = dpp_u64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+  v = o < v ? o : v;
+  o = dpp_u64<0x4e>(v);            // quad_perm [2, 3, 0, 1]
+  v = o < v ? o : v;
+  o = dpp_u64<0x141>(v);           // row_half_mirror
+  v = o < v ? o : v;
+  o = dpp_u64<0x140>(v);           // row_mirror
+  return o < v ? o : v;
+}
 
 struct SlotHit {
   float t;
@@ -444,34 +501,24 @@ struct SlotHit {
   int moving; // the face belongs to a moving object
 };
 
-__device__ inline void test_slot(const Ray& r, const float4& p0, const float4& p1, const float4& p2, int slot,
-                                 int excl, SlotHit& h) {
-  const int face = __float_as_int(p1.w);
-  if (face == excl) return;
-  const float t = watertight(r, p0, p1, p2);
-  if (!(t > kTMin)) return;
-  const int tri = __float_as_int(p0.w);
-  if (hit_less(t, tri, h.t, h.tri)) {
-    h.t = t;
-    h.tri = tri;
-    h.slot = slot;
-    h.face = face;
-    h.moving = __float_as_int(p2.w);
-  }
+__device__ inline MaskAxes mask_axes(const Ray& r) {
+  auto m = [](int k, int j) { return k == j ? 0xffffffffu : 0u; };
+  return MaskAxes{m(r.kx, 0), m(r.kx, 1), m(r.kx, 2), m(r.ky, 0), m(r.ky, 1),
+                  m(r.ky, 2), m(r.kz, 0), m(r.kz, 1), m(r.kz, 2)};
 }
 
 __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
-  __shared__ Node4 top[kWaveTop];
   __shared__ float4 rxs[kWaveRx];
-  __shared__ uint32_t stk_e[kWaves][kWaveStack];
-  __shared__ float stk_t[kWaves][kWaveStack];
-  const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int jl = lane >> 2, el = lane & 3;   // this lane's node (of the popped ones) and slot
-  uint32_t* se = stk_e[wv];
-  float* st = stk_t[wv];
+  __shared__ uint32_t stk_e[kWaves * kGroups][kGroupStack];
+  __shared__ float stk_t[kWaves * kGroups][kGroupStack];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / kGroup, gl = lane & (kGroup - 1), jl = gl >> 2, el = gl & 3;
+  const int leader = lane & ~(kGroup - 1);
+  const uint64_t gmask = 0xffffull << (kGroup * g);
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t* se = stk_e[threadIdx.x / kGroup];
+  float* st = stk_t[threadIdx.x / kGroup];
   const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
-  const int n_top = min(kWaveTop, n4);
-  for (int i = threadIdx.x; i < n_top; i += kWaveBlock) top[i] = a.nodes4[i];
   const bool rx_lds = a.n_rx <= kWaveRx;
   if (rx_lds)
     for (int i = threadIdx.x; i < a.n_rx; i += kWaveBlock)
@@ -481,16 +528,39 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   const uint32_t n_work = a.counters[kCntWork];
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
-  // first item by position, then from the shared queue
-  uint32_t wi = blockIdx.x * kWaves + wv;
-  while (wi < n_work) {
-    const uint32_t work = a.work_list[wi];
-    const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
+
+  // this group's ray (equal on its lanes)
+  bool busy = false;
+  uint32_t work = 0, txi = 0, state = 0;
+  int k = 0, excl = -1, guard = 0, sp = 0;
+  float L = 0.0f, best_t = INFINITY;
+  Ray r;
+  MaskAxes ax;
+  SlotHit h{FLT_MAX, -1, -1, -1, 0};
+
+  auto begin_segment = [&]() {
+    h = SlotHit{FLT_MAX, -1, -1, -1, 0};
+    best_t = INFINITY;
+    guard = n4 + 2;
+    sp = 0;
+    if (n4 > 0) {
+      if (gl == 0) {
+        se[0] = root;
+        st[0] = 0.0f;
+      }
+      sp = 1;
+    }
+    ax = mask_axes(r);
+  };
+  auto start_ray = [&](uint32_t item) {
+    busy = item < n_work;
+    if (!busy) return;
+    work = a.work_list[item];
+    txi = (uint32_t)(work / (uint64_t)a.n_rays);
     const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
-    int k = (int)a.restart[work];
-    Ray r;
-    int excl = -1;
-    float L = 0.0f;
+    k = (int)a.restart[work];
+    excl = -1;
+    L = 0.0f;
     if (k == 0) {
       r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
       r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
@@ -503,159 +573,154 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       excl = a.face_log[(size_t)(k - 1) * a.n_work + work];
     }
     setup_ray(r);
-    uint32_t state = 0;
-    for (; k <= a.K; ++k) {
-      // ---- closest hit, one tree level per step
-      SlotHit h{FLT_MAX, -1, -1, -1, 0};
-      float best_t = INFINITY;   // wavefront-uniform (infinite while nothing is hit)
-      int sp = 0;
-      if (n4 > 0) {
-        if (lane == 0) { se[0] = root; st[0] = 0.0f; }
-        sp = 1;
-        wave_sync();
-      }
-      for (int guard = n4 + 2; sp > 0 && guard > 0; --guard) {
-        const int n_pop = min(kWave / 4, sp);
-        bool act = jl < n_pop;
-        uint32_t ent = 0;
-        float tn = 0.0f;
-        if (act) {
-          ent = se[sp - 1 - jl];
-          tn = st[sp - 1 - jl];
-        }
-        wave_sync();
-        sp -= n_pop;
-        act = act && tn <= best_t;
-        const int node = (int)(ent & ((1u << kNodeBits) - 1));
-        const bool leaf = act && ((ent >> (kNodeBits + el)) & 1u);
-        const bool inner = act && !leaf;
-        // this lane's slot: the leaf triangle, or the child's box and entry
-        float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
-        if (leaf) {
-          const Leaf& lf = a.tri4[4 * (size_t)node + el];
-          q0 = lf.v0;
-          q1 = lf.v1;
-          q2 = lf.v2;
-        } else if (inner) {
-          const float4* sl = reinterpret_cast<const float4*>(node < n_top ? &top[node].s[el] : &a.nodes4[node].s[el]);
-          q0 = sl[0];
-          q1 = sl[1];
-        }
-        uint32_t push = kNoEntry;
-        float pt = 0.0f;
-        if (leaf) {
-          test_slot(r, q0, q1, q2, 4 * node + el, excl, h);
-          ++tri_count;
-        } else if (inner) {
-          const int ch = __float_as_int(q0.w);
-          float te;
-          if (ch != kEmpty && slab(r, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z, fminf(h.t, best_t), te)) {
-            push = (uint32_t)ch | (__float_as_uint(q1.w) << kNodeBits);
-            pt = te;
-          }
-        }
-        if (act && el == 0) ++node_count;
-        // push the hit children in lane order
-        const uint64_t want = __ballot(push != kNoEntry);
-        const int total = __popcll(want);
-        const int pos = sp + __popcll(want & ((1ull << lane) - 1ull));
-        if (push != kNoEntry && pos < kWaveStack) {
-          se[pos] = push;
-          st[pos] = pt;
-        }
-        if (sp + total > kWaveStack) overflow = true;
-        sp = min(sp + total, kWaveStack);
-        wave_sync();
-        // wavefront-wide best so far
-        float bt = h.t;
-        int bi = h.tri;
-        for (int off = 32; off > 0; off >>= 1) {
-          const float ot = __shfl_xor(bt, off);
-          const int oi = __shfl_xor(bi, off);
-          if (hit_less(ot, oi, bt, bi)) { bt = ot; bi = oi; }
-        }
-        best_t = bi >= 0 ? bt : INFINITY;
-      }
-      // the lane holding the winner broadcasts its record
-      {
-        float bt = h.t;
-        int bi = h.tri;
-        for (int off = 32; off > 0; off >>= 1) {
-          const float ot = __shfl_xor(bt, off);
-          const int oi = __shfl_xor(bi, off);
-          if (hit_less(ot, oi, bt, bi)) { bt = ot; bi = oi; }
-        }
-        const uint64_t owner = __ballot(h.tri == bi && h.t == bt && bi >= 0);
-        const int src = owner ? __ffsll((unsigned long long)owner) - 1 : 0;
-        h.slot = __shfl(h.slot, src);
-        h.face = __shfl(h.face, src);
-        h.moving = __shfl(h.moving, src);
-        h.t = bt;
-        h.tri = bi;
-        if (bi < 0) { h.slot = -1; h.face = -1; h.moving = 0; h.t = FLT_MAX; }
-      }
-      ++seg_count;
-      const bool hit = h.tri >= 0;
-      const bool more = hit && k < a.K;
-      // the reflecting triangle, fetched while the receivers are tested
-      float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
-      if (more) {
-        const Leaf& lf = a.tri4[h.slot];
-        w0 = lf.v0;
-        w1 = lf.v1;
-        w2 = lf.v2;
-      }
-      const float tend = hit ? h.t : INFINITY;
-      if (hit && h.moving) state |= 0x80u;
-      const float dd = dot_dd(r);
-      const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
-      if (lane == 0) {
-        a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
-        a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
-        a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
-        if (a.log_tri) {
-          const size_t li = (size_t)work * (a.K + 1) + k;
-          a.log_tri[li] = h.tri;
-          a.log_t[li] = hit ? h.t : INFINITY;
-          a.log_len[li] = hit ? L_hit : INFINITY;
-        }
-      }
-      // ---- capture: lanes share the receivers
-      const float za = r.o.z;
-      const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
-      if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
-        for (int c = lane; c < a.n_rx; c += kWave) {
-          float cx, cy, cz;
-          if (rx_lds) {
-            const float4 q = rxs[c];
-            cx = q.x;
-            cy = q.y;
-            cz = q.z;
-          } else {
-            cx = a.rx[3 * c];
-            cy = a.rx[3 * c + 1];
-            cz = a.rx[3 * c + 2];
-          }
-          if (captured(r, tend, dd, cx, cy, cz, a.r2)) {
-            const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
-            if (slot < a.cap_capacity) {
-              Capture cp;
-              cp.work = work;
-              cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
-              a.caps[slot] = cp;
-            } else {
-              cap_over = true;
-            }
-          }
-        }
-      }
-      if (!more) { ++k; break; }
-      // ---- specular reflection (identical arithmetic on every lane)
-      L = L_hit;
-      reflect_ray(r, h.t, w0, w1, w2);
-      excl = h.face;
+    state = 0;
+    begin_segment();
+  };
+
+  // first item by position, then from the shared queue
+  start_ray((blockIdx.x * kWaves + threadIdx.x / kWave) * kGroups + g);
+  const uint32_t n_static = gridDim.x * kWaves * kGroups;
+  while (true) {
+    wave_sync();
+    if (__ballot(busy) == 0) break;
+    // ---- one traversal step of every group whose stack is not empty
+    const int n_pop = busy ? min(4, sp) : 0;
+    bool act = jl < n_pop;
+    uint32_t ent = 0;
+    float tn = 0.0f;
+    if (act) {
+      ent = se[sp - 1 - jl];
+      tn = st[sp - 1 - jl];
     }
-    if (lane == 0) {
+    wave_sync();
+    sp -= n_pop;
+    act = act && tn <= best_t;
+    const int node = (int)(ent & ((1u << kNodeBits) - 1));
+    const bool leaf = act && ((ent >> (kNodeBits + el)) & 1u);
+    const bool inner = act && !leaf;
+    // this lane's slot, 48 bytes in one load: the leaf triangle, or the
+    // child's box and entry (and 16 bytes of the next slot, unused)
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+    if (act) {
+      const float4* src = leaf ? reinterpret_cast<const float4*>(a.tri4 + 4 * (size_t)node + el)
+                               : reinterpret_cast<const float4*>(&a.nodes4[node].s[el]);
+      q0 = src[0];
+      q1 = src[1];
+      q2 = src[2];
+    }
+    uint32_t push = kNoEntry;
+    float pt = 0.0f;
+    if (leaf) {
+      const int face = __float_as_int(q1.w);
+      if (face != excl) {
+        const float t = watertight_axes(r, ax, q0, q1, q2);
+        const int tri = __float_as_int(q0.w);
+        if (t > kTMin && hit_less(t, tri, h.t, h.tri)) {
+          h.t = t;
+          h.tri = tri;
+          h.slot = 4 * node + el;
+          h.face = face;
+          h.moving = __float_as_int(q2.w);
+        }
+      }
+      ++tri_count;
+    } else if (inner) {
+      const int ch = __float_as_int(q0.w);
+      float te;
+      if (ch != kEmpty && slab(r, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z, fminf(h.t, best_t), te)) {
+        push = (uint32_t)ch | (__float_as_uint(q1.w) << kNodeBits);
+        pt = te;
+      }
+    }
+    if (act && el == 0) ++node_count;
+    // push each group's hit children in lane order
+    const uint64_t want = __ballot(push != kNoEntry) & gmask;
+    const int total = __popcll(want);
+    const int pos = sp + __popcll(want & below);
+    if (push != kNoEntry && pos < kGroupStack) {
+      se[pos] = push;
+      st[pos] = pt;
+    }
+    if (sp + total > kGroupStack) overflow = true;
+    sp = min(sp + total, kGroupStack);
+    if (n_pop > 0 && --guard <= 0 && sp > 0) {   // only a malformed tree gets here
+      overflow = true;
+      sp = 0;
+    }
+    const uint64_t best = row_min_u64(hit_key(h.t, h.tri));
+    best_t = best == ~0ull ? INFINITY : __uint_as_float((uint32_t)(best >> 32));
+    if (!(busy && sp == 0)) continue;
+    // ---- this group's traversal ended: finish the segment
+    const uint64_t own = __ballot(best != ~0ull && hit_key(h.t, h.tri) == best) & gmask;
+    const bool hit = own != 0;
+    const int src = hit ? __ffsll((unsigned long long)own) - 1 : leader;
+    const int slot = __shfl(h.slot, src), face = __shfl(h.face, src), moving = __shfl(h.moving, src);
+    const float th = hit ? __uint_as_float((uint32_t)(best >> 32)) : FLT_MAX;
+    const int tri = hit ? (int)(uint32_t)best : -1;
+    const bool more = hit && k < a.K;
+    // the reflecting triangle, fetched while the receivers are tested
+    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
+    if (more) {
+      const Leaf& lf = a.tri4[slot];
+      w0 = lf.v0;
+      w1 = lf.v1;
+      w2 = lf.v2;
+    }
+    const float tend = hit ? th : INFINITY;
+    if (hit && moving) state |= 0x80u;
+    const float dd = dot_dd(r);
+    const float L_hit = __fmaf_rn(th, __fsqrt_rn(dd), L);
+    if (gl == 0) {
+      ++seg_count;
+      a.face_log[(size_t)k * a.n_work + work] = hit ? face : -1;
+      a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
+      a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
+      if (a.log_tri) {
+        const size_t li = (size_t)work * (a.K + 1) + k;
+        a.log_tri[li] = tri;
+        a.log_t[li] = hit ? th : INFINITY;
+        a.log_len[li] = hit ? L_hit : INFINITY;
+      }
+    }
+    // capture: the group's lanes share the receivers
+    const float za = r.o.z;
+    const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+    if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+      for (int c = gl; c < a.n_rx; c += kGroup) {
+        float cx, cy, cz;
+        if (rx_lds) {
+          const float4 q = rxs[c];
+          cx = q.x;
+          cy = q.y;
+          cz = q.z;
+        } else {
+          cx = a.rx[3 * c];
+          cy = a.rx[3 * c + 1];
+          cz = a.rx[3 * c + 2];
+        }
+        if (captured(r, tend, dd, cx, cy, cz, a.r2)) {
+          const uint32_t cs = atomicAdd(&a.counters[kCntCaptures], 1u);
+          if (cs < a.cap_capacity) {
+            Capture cp;
+            cp.work = work;
+            cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+            a.caps[cs] = cp;
+          } else {
+            cap_over = true;
+          }
+        }
+      }
+    }
+    ++k;
+    if (more) {
+      // specular reflection (identical arithmetic on the group's lanes)
+      L = L_hit;
+      reflect_ray(r, th, w0, w1, w2);
+      excl = face;
+      begin_segment();
+      continue;
+    }
+    if (gl == 0) {
       for (int j = k; j <= a.K; ++j) {
         a.face_log[(size_t)j * a.n_work + work] = -2;
         if (a.log_tri) {
@@ -668,10 +733,11 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
     }
     uint32_t next = 0;
-    if (lane == 0) next = gridDim.x * kWaves + atomicAdd(&a.counters[kCntQueue], 1u);
-    wi = __shfl(next, 0);
+    if (gl == 0) next = n_static + atomicAdd(&a.counters[kCntQueue], 1u);
+    start_ray(__shfl(next, leader));
   }
   for (int off = 32; off > 0; off >>= 1) {
+    seg_count += __shfl_xor(seg_count, off);
     node_count += __shfl_xor(node_count, off);
     tri_count += __shfl_xor(tri_count, off);
   }
@@ -896,7 +962,7 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) 
   a.err = c->err_dev;
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
-    const int64_t want = (expected + expected / 4 + kWaves - 1) / kWaves + 1;
+    const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;
     const int grid = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)cu_count(c) * 8, want));
     hipLaunchKernelGGL(k_trace_wave, dim3(grid), dim3(kWaveBlock), 0, c->stream, a);
     return 1;
