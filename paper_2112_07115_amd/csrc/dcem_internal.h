@@ -49,6 +49,19 @@ struct __align__(16) Node4 {
 };
 constexpr int kEmpty = (int)0x80000000;
 
+// Stack entry of the group traversals: node index | leaf-slot mask << kNodeBits
+// (node indices stay below 2^27: at most 2^27 - 1 triangles).
+constexpr int kNodeBits = 27;
+constexpr uint32_t kNoEntry = 0xffffffffu;   // no child to push
+constexpr int kGroup = 16;                   // lanes per query in the group traversals: one DPP row
+constexpr int kGroupStack = 128;             // stack entries per group
+
+// Order LDS accesses of the lanes of one wavefront.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Leaf triangle, 48 bytes: vertices with the triangle id, its face id and 1
 // if the face belongs to a moving object (else 0) in the w components (as
 // integer bits).  Stored twice: in sorted-leaf order (the binary tree's

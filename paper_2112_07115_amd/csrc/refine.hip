@@ -370,8 +370,8 @@ struct RefineArgs {
   const int32_t* face_material;
   const double* materials;
   const Node4* nodes4;
-  const Leaf* leaves;
-  const uint32_t* n4_dev;   // null: empty scene
+  const Leaf* tri4;         // leaf triangles in slot order
+  const uint32_t* n4_dev;   // null: empty scene; [1] root leaf-slot mask
   const double* freqs;
   int n_freqs;
   double sqrt_pt;
@@ -421,9 +421,14 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
 
 // Any triangle (outside faces fa, fb) crossed by the open segment p -> q,
 // keeping t_min away from both ends?  FP64 orientation tests at the leaves;
-// 4-wide tree boxes (FP32, padded) tested in FP64.
-__device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* stack, int stride, bool& fault) {
-  const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+// 4-wide tree boxes (FP32, padded) tested in FP64.  Traversed by a group of
+// 16 lanes (one DPP row), one tree level per step: each lane takes one slot of
+// up to four popped nodes (a stack entry carries its node's leaf-slot mask, so
+// leaf triangles come straight from the slot array).  The answer does not
+// depend on the order: the first occluder found ends the query.
+__device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, uint32_t* se, int lane,
+                               uint64_t gmask, bool& fault) {
+  const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
   if (n4 == 0) return false;
   const D3 dv = q - p;
   const double L = len(dv);
@@ -432,47 +437,62 @@ __device__ bool occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, int* s
   const double big = 1e300;
   const double ix = dv.x != 0 ? 1.0 / dv.x : big, iy = dv.y != 0 ? 1.0 / dv.y : big,
                iz = dv.z != 0 ? 1.0 / dv.z : big;
-  auto box = [&](double lx, double ly, double lz, double hx, double hy, double hz) {
-    const double ax = (lx - p.x) * ix, bx = (hx - p.x) * ix;
-    const double ay = (ly - p.y) * iy, by = (hy - p.y) * iy;
-    const double az = (lz - p.z) * iz, bz = (hz - p.z) * iz;
-    const double tn = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmax(fmin(az, bz), 0.0));
-    const double tf = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmin(fmax(az, bz), 1.0));
-    return tn <= tf * (1.0 + 1e-12);
-  };
-  auto leaf = [&](int li) {
-    const Leaf& lf = a.leaves[li];
-    const int face = __float_as_int(lf.v1.w);
-    if (face == fa || face == fb) return false;
-    const D3 A = {lf.v0.x, lf.v0.y, lf.v0.z}, B = {lf.v1.x, lf.v1.y, lf.v1.z}, C = {lf.v2.x, lf.v2.y, lf.v2.z};
-    const double op = vol(A, B, C, p), oq = vol(A, B, C, q);
-    if (op == oq) return false;
-    const double t = op / (op - oq);
-    if (!(t > tlo && t < thi)) return false;
-    const double s0 = vol(p, q, A, B), s1 = vol(p, q, B, C), s2 = vol(p, q, C, A);
-    return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
-  };
-  int node = 0, sp = 0;
-  // a sound tree visits each node at most once per query; the bound only
-  // guarantees termination
-  for (int64_t guard = (int64_t)n4 + 2; guard > 0; --guard) {
-    const Node4 nd = a.nodes4[node];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const Slot4& sl = nd.s[e];
-      if (sl.child == kEmpty || !box(sl.lx, sl.ly, sl.lz, sl.hx, sl.hy, sl.hz)) continue;
-      if (sl.child < 0) {
-        if (leaf(~sl.child)) return true;
-      } else if (sp < kStackSize) {
-        stack[(sp++) * stride] = sl.child;
-      } else {
-        fault = true;
-      }
+  const int gl = lane & (kGroup - 1), jl = gl >> 2, el = gl & 3;
+  const uint64_t below = (1ull << lane) - 1ull;
+  if (gl == 0) se[0] = a.n4_dev[1] << kNodeBits;
+  int sp = 1;
+  wave_sync();
+  for (int guard = n4 + 2; sp > 0; --guard) {
+    if (guard == 0) {
+      fault = true;
+      return false;
     }
-    if (sp == 0) return false;
-    node = stack[(--sp) * stride];
+    const int n_pop = min(4, sp);
+    const bool act = jl < n_pop;
+    const uint32_t ent = act ? se[sp - 1 - jl] : 0u;
+    wave_sync();
+    sp -= n_pop;
+    const int node = (int)(ent & ((1u << kNodeBits) - 1));
+    const bool leaf = act && ((ent >> (kNodeBits + el)) & 1u);
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+    if (act) {
+      const float4* src = leaf ? reinterpret_cast<const float4*>(a.tri4 + 4 * (size_t)node + el)
+                               : reinterpret_cast<const float4*>(&a.nodes4[node].s[el]);
+      q0 = src[0];
+      q1 = src[1];
+      q2 = src[2];
+    }
+    bool hit = false;
+    uint32_t push = kNoEntry;
+    if (leaf) {
+      const int face = __float_as_int(q1.w);
+      if (face != fa && face != fb) {
+        const D3 A = {q0.x, q0.y, q0.z}, B = {q1.x, q1.y, q1.z}, C = {q2.x, q2.y, q2.z};
+        const double op = vol(A, B, C, p), oq = vol(A, B, C, q);
+        if (op != oq) {
+          const double t = op / (op - oq);
+          if (t > tlo && t < thi) {
+            const double s0 = vol(p, q, A, B), s1 = vol(p, q, B, C), s2 = vol(p, q, C, A);
+            hit = (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+          }
+        }
+      }
+    } else if (act && __float_as_int(q0.w) != kEmpty) {
+      const double ax = (q0.x - p.x) * ix, bx = (q1.x - p.x) * ix;
+      const double ay = (q0.y - p.y) * iy, by = (q1.y - p.y) * iy;
+      const double az = (q0.z - p.z) * iz, bz = (q1.z - p.z) * iz;
+      const double tn = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmax(fmin(az, bz), 0.0));
+      const double tf = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmin(fmax(az, bz), 1.0));
+      if (tn <= tf * (1.0 + 1e-12)) push = (uint32_t)__float_as_int(q0.w) | (__float_as_uint(q1.w) << kNodeBits);
+    }
+    if (__ballot(hit) & gmask) return true;
+    const uint64_t want = __ballot(push != kNoEntry) & gmask;
+    const int pos = sp + __popcll(want & below);
+    if (push != kNoEntry && pos < kGroupStack) se[pos] = push;
+    if (sp + __popcll(want) > kGroupStack) fault = true;
+    sp = min(sp + __popcll(want), kGroupStack);
+    wave_sync();
   }
-  fault = true;
   return false;
 }
 
@@ -530,41 +550,38 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine_geom(RefineArgs a) {
   a.length[u] = len(R - img[order]);
 }
 
-// Refinement, stage 2 (one thread per path and check): check c < K tests that
-// reflection point c+1 lies in its face; check K + j tests that sub-segment j
-// is unoccluded.  A failed check clears the path's valid flag.
-__global__ __launch_bounds__(kRefineBlock) void k_refine_check(RefineArgs a) {
-  __shared__ int stack_mem[kStackSize * kRefineBlock];
-  int* stack = stack_mem + threadIdx.x;
+// Refinement, stage 2 (one group of 16 lanes per path and sub-segment j):
+// sub-segment j must be unoccluded, and for j = 0 the group's first lanes
+// also test that each reflection point lies in its face.  A failed check
+// clears the path's valid flag.
+constexpr int kCheckBlock = 256;
+
+__global__ __launch_bounds__(kCheckBlock) void k_refine_check(RefineArgs a) {
+  __shared__ uint32_t stk[kCheckBlock / kGroup][kGroupStack];
   const int K = a.L.K;
-  const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const uint32_t u = (uint32_t)(gid / (2 * K + 1));
-  const int c = (int)(gid - (uint64_t)u * (2 * K + 1));
-  bool fault = false;
-  if (u < *a.n_unique && a.valid[u]) {
-    const int order = a.order[u];
-    const double* P = a.pts + (size_t)u * (K + 2) * 3;
-    const int32_t* faces = a.faces + (size_t)u * K;
-    bool fail = false;
-    if (c < K) {
-      if (c < order) {
-        const int f = faces[c];
-        const double4 pl = a.plane[f];
-        const D3 p = {P[3 * (c + 1)], P[3 * (c + 1) + 1], P[3 * (c + 1) + 2]};
-        fail = !in_face(a, f, p, D3{pl.x, pl.y, pl.z});
-      }
-    } else {
-      const int j = c - K;
-      if (j <= order) {
-        const int fa = j >= 1 ? faces[j - 1] : -1;
-        const int fb = j + 1 <= order ? faces[j] : -1;
-        const D3 p = {P[3 * j], P[3 * j + 1], P[3 * j + 2]};
-        const D3 q = {P[3 * (j + 1)], P[3 * (j + 1) + 1], P[3 * (j + 1) + 2]};
-        fail = occluded(a, p, q, fa, fb, stack, kRefineBlock, fault);
-      }
-    }
-    if (fail) a.valid[u] = 0;
+  const int lane = threadIdx.x & (kWave - 1), gl = lane & (kGroup - 1);
+  const uint64_t gmask = 0xffffull << (lane & ~(kGroup - 1));
+  const uint64_t gid = (blockIdx.x * (uint64_t)kCheckBlock + threadIdx.x) / kGroup;
+  const uint32_t u = (uint32_t)(gid / (K + 1));
+  const int j = (int)(gid - (uint64_t)u * (K + 1));
+  if (u >= *a.n_unique || !a.valid[u]) return;   // whole groups leave together
+  const int order = a.order[u];
+  if (j > order) return;
+  const double* P = a.pts + (size_t)u * (K + 2) * 3;
+  const int32_t* faces = a.faces + (size_t)u * K;
+  bool fail = false, fault = false;
+  if (j == 0 && gl < order) {
+    const int f = faces[gl];
+    const double4 pl = a.plane[f];
+    const D3 pt = {P[3 * (gl + 1)], P[3 * (gl + 1) + 1], P[3 * (gl + 1) + 2]};
+    fail = !in_face(a, f, pt, D3{pl.x, pl.y, pl.z});
   }
+  const int fa = j >= 1 ? faces[j - 1] : -1;
+  const int fb = j + 1 <= order ? faces[j] : -1;
+  const D3 p = {P[3 * j], P[3 * j + 1], P[3 * j + 2]};
+  const D3 q = {P[3 * (j + 1)], P[3 * (j + 1) + 1], P[3 * (j + 1) + 2]};
+  if (group_occluded(a, p, q, fa, fb, stk[threadIdx.x / kGroup], lane, gmask, fault) && gl == 0) fail = true;
+  if (fail) a.valid[u] = 0;
   if (fault) atomicOr(a.err, DCEM_ERR_STACK);
 }
 
@@ -836,7 +853,7 @@ void launch_refine(dcem_ctx* c) {
   a.face_material = ptr<int32_t>(c->face_material);
   a.materials = ptr<double>(c->materials);
   a.nodes4 = ptr<Node4>(c->nodes4);
-  a.leaves = ptr<Leaf>(c->leaves);
+  a.tri4 = ptr<Leaf>(c->tri4);
   a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.freqs = ptr<double>(c->freqs);
   a.n_freqs = c->n_freqs;
@@ -858,8 +875,8 @@ void launch_refine(dcem_ctx* c) {
   a.err = c->err_dev;
   const unsigned nb = (unsigned)((n + kRefineBlock - 1) / kRefineBlock);
   hipLaunchKernelGGL(k_refine_geom, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
-  const uint64_t nchk = (uint64_t)n * (2 * c->K + 1);
-  hipLaunchKernelGGL(k_refine_check, dim3((unsigned)((nchk + kRefineBlock - 1) / kRefineBlock)), dim3(kRefineBlock), 0,
+  const uint64_t nchk = (uint64_t)n * (c->K + 1) * kGroup;
+  hipLaunchKernelGGL(k_refine_check, dim3((unsigned)((nchk + kCheckBlock - 1) / kCheckBlock)), dim3(kCheckBlock), 0,
                      c->stream, a);
   hipLaunchKernelGGL(k_refine_field, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
 }

@@ -450,20 +450,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 // traversing.  Every triangle the per-thread traversal tests is tested here
 // too (leaf triangles without their boxes, which only drops a conservative
 // filter), with the same arithmetic, so the hit is the same.
-constexpr int kGroup = 16;                  // lanes per ray: one DPP row
 constexpr int kGroups = kWave / kGroup;     // rays per wavefront
 constexpr int kWaves = 4;                   // wavefronts per block
 constexpr int kWaveBlock = kWaves * kWave;
-constexpr int kGroupStack = 128;            // stack entries per group
 constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
-constexpr int kNodeBits = 27;               // stack entry: node | leaf-slot mask << kNodeBits
-constexpr uint32_t kNoEntry = 0xffffffffu;  // no child to push
 constexpr int64_t kWaveTraceMax = 1 << 16;  // longest list traced by groups
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __device__ inline bool hit_less(float ta, int ia, float tb, int ib) { return ta < tb || (ta == tb && ia < ib); }
 
@@ -760,82 +751,162 @@ __global__ void k_reset_counters(uint32_t* counters) {
 // now.  A ray whose segments are all valid would be traced to exactly the same
 // hits and captures, so it is reused as it is; otherwise it is listed for
 // re-tracing from its first invalid segment (wavefront-aggregated append).
-__global__ void k_coherence(const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o,
-                            const float4* __restrict__ seg_d, const int32_t* __restrict__ face_log,
-                            const int32_t* __restrict__ face_object, const float* __restrict__ obj_box, int n_obj,
-                            const uint32_t* __restrict__ ray_order, int64_t n_rays, int n_work, float margin,
-                            uint8_t* __restrict__ restart, uint32_t* __restrict__ list, uint32_t* counters) {
-  // z range of all moving-object boxes (exact min/max through order-preserving bits)
-  __shared__ uint32_t zr[2];
-  if (threadIdx.x == 0) {
-    zr[0] = 0xffffffffu;
-    zr[1] = 0u;
-  }
+// Each block bins the moving-object boxes on a 32 x 32 grid over their xy
+// extent in LDS, one bit per object and cell, so a segment tests only the
+// boxes of the cells its xy bounds cover (up to kCohGridObjects objects; more
+// are tested one by one).
+constexpr int kCohBlock = 256;
+constexpr int kCohGrid = 32;
+constexpr int kCohGridObjects = 256;
+constexpr int kCohMaxCells = 16;   // wider xy bounds test every box
+constexpr int kCohBatch = 5;       // cached segments loaded at once
+
+__global__ __launch_bounds__(kCohBlock) void k_coherence(
+    const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o, const float4* __restrict__ seg_d,
+    const int32_t* __restrict__ face_log, const int32_t* __restrict__ face_object, const float* __restrict__ obj_box,
+    int n_obj, int n_work, float margin, uint8_t* __restrict__ restart, uint32_t* __restrict__ list,
+    uint32_t* counters) {
+  // dynamic LDS (grid mode): cell bits [cell][word], then the boxes [6][n_obj]
+  extern __shared__ unsigned long long coh_lds[];
+  __shared__ uint32_t ext[6];   // ordered bits: min x, min y, min z, max x, max y, max z
+  const bool grid = n_obj <= kCohGridObjects;
+  const int words = (n_obj + 63) / 64;
+  unsigned long long* cell = coh_lds;
+  float* blf = reinterpret_cast<float*>(coh_lds + kCohGrid * kCohGrid * words);
+  auto bl = [&](int a, int b) -> float& { return blf[a * n_obj + b]; };
+  if (threadIdx.x < 6) ext[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;
+  if (grid)
+    for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += kCohBlock) cell[c] = 0ull;
   __syncthreads();
-  for (int b = threadIdx.x; b < n_obj; b += blockDim.x) {
-    atomicMin(&zr[0], ordered_bits(obj_box[6 * b + 2]));
-    atomicMax(&zr[1], ordered_bits(obj_box[6 * b + 5]));
-  }
-  __syncthreads();
-  const float zlo = n_obj ? from_ordered(zr[0]) - margin : INFINITY;
-  const float zhi = n_obj ? from_ordered(zr[1]) + margin : -INFINITY;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  int first = 255;
-  const uint32_t w = (uint32_t)i;
-  if (i < n_work) {
-    const uint32_t st = ray_state[w];
-    const int nseg = (int)(st & 0x0fu);
-    const bool moving_hit = (st & 0x80u) != 0;
-    for (int k = 0; k < nseg && first == 255; ++k) {
-      if (moving_hit) {
-        const int f = face_log[(size_t)k * n_work + w];
-        if (f >= 0 && face_object[f] >= 0) { first = k; break; }
+  for (int b = threadIdx.x; b < n_obj; b += kCohBlock) {
+    for (int a = 0; a < 3; ++a) {
+      const float lo = obj_box[6 * b + a], hi = obj_box[6 * b + 3 + a];
+      if (grid) {
+        bl(a, b) = lo;
+        bl(3 + a, b) = hi;
       }
-      const float4 o = seg_o[(size_t)k * n_work + w];
-      const float4 d = seg_d[(size_t)k * n_work + w];
-      // cull: the part of the segment inside the moving objects' z range, and
-      // its xy bounds (widened by `margin` so the cull never rejects a box the
-      // exact slab test below would accept)
-      float s0 = 0.0f, s1 = o.w;
-      if (d.z != 0.0f) {
-        const float a0 = (zlo - o.z) / d.z, a1 = (zhi - o.z) / d.z;
-        s0 = fmaxf(s0, fminf(a0, a1));
-        s1 = fminf(s1, fmaxf(a0, a1));
-      } else if (o.z < zlo || o.z > zhi) {
-        continue;
-      }
-      if (!(s0 <= s1)) continue;
-      const float xa = fmaf(s0, d.x, o.x), xb = fmaf(s1, d.x, o.x);
-      const float ya = fmaf(s0, d.y, o.y), yb = fmaf(s1, d.y, o.y);
-      const float bx0 = fminf(xa, xb) - margin, bx1 = fmaxf(xa, xb) + margin;
-      const float by0 = fminf(ya, yb) - margin, by1 = fmaxf(ya, yb) + margin;
-      Ray r;
-      r.o = make_float3(o.x, o.y, o.z);
-      r.d = make_float3(d.x, d.y, d.z);
-      const float tiny = 1e-30f;
-      r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny),
-                          __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
-                          __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
-      for (int b = 0; b < n_obj; ++b) {
-        const float* bx = obj_box + 6 * b;
-        if (bx[3] < bx0 || bx[0] > bx1 || bx[4] < by0 || bx[1] > by1) continue;
-        float tn;
-        if (slab(r, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o.w, tn)) { first = k; break; }
-      }
+      atomicMin(&ext[a], ordered_bits(lo));
+      atomicMax(&ext[3 + a], ordered_bits(hi));
     }
-    restart[w] = (uint8_t)first;
   }
-  const bool bad = first != 255;
-  const uint64_t m = __ballot(bad);
-  uint32_t base = 0;
-  if (lane == 0 && m) base = atomicAdd(&counters[kCntWork], (uint32_t)__popcll(m));
-  base = __shfl(base, 0);
-  if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = w;
+  __syncthreads();
+  const float gx0 = from_ordered(ext[0]), gy0 = from_ordered(ext[1]);
+  const float zlo = n_obj ? from_ordered(ext[2]) - margin : INFINITY;
+  const float zhi = n_obj ? from_ordered(ext[5]) + margin : -INFINITY;
+  const float sx = kCohGrid / fmaxf(from_ordered(ext[3]) - gx0, 1e-6f);
+  const float sy = kCohGrid / fmaxf(from_ordered(ext[4]) - gy0, 1e-6f);
+  // cell index of a coordinate, clamped to the grid (infinite bounds included):
+  // monotonic, so overlapping ranges share a cell
+  auto cell_of = [](float u) { return (int)fminf(fmaxf(floorf(u), 0.0f), (float)(kCohGrid - 1)); };
+  auto cx = [&](float x) { return cell_of((x - gx0) * sx); };
+  auto cy = [&](float y) { return cell_of((y - gy0) * sy); };
+  if (grid) {
+    for (int b = threadIdx.x; b < n_obj; b += kCohBlock) {
+      const int x0 = cx(bl(0, b)), x1 = cx(bl(3, b)), y0 = cy(bl(1, b)), y1 = cy(bl(4, b));
+      for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) atomicOr(&cell[(y * kCohGrid + x) * words + (b >> 6)], 1ull << (b & 63));
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  // blocks stride over the rays (the grid above is built once per block)
+  for (int base0 = blockIdx.x * kCohBlock; base0 < n_work; base0 += gridDim.x * kCohBlock) {
+    const int i = base0 + threadIdx.x;
+    int first = 255;
+    const uint32_t w = (uint32_t)i;
+    if (i < n_work) {
+      const uint32_t st = ray_state[w];
+      const int nseg = (int)(st & 0x0fu);
+      const bool moving_hit = (st & 0x80u) != 0;
+      // does the cached segment (o, d) meet a moving object's box now?
+      auto meets_moving = [&](const float4& o, const float4& d) {
+        // cull: the part of the segment inside the moving objects' z range, and
+        // its xy bounds (widened by `margin` so the cull never rejects a box
+        // the exact slab test below would accept)
+        float s0 = 0.0f, s1 = o.w;
+        if (d.z != 0.0f) {
+          const float a0 = (zlo - o.z) / d.z, a1 = (zhi - o.z) / d.z;
+          s0 = fmaxf(s0, fminf(a0, a1));
+          s1 = fminf(s1, fmaxf(a0, a1));
+        } else if (o.z < zlo || o.z > zhi) {
+          return false;
+        }
+        if (!(s0 <= s1)) return false;
+        const float xa = fmaf(s0, d.x, o.x), xb = fmaf(s1, d.x, o.x);
+        const float ya = fmaf(s0, d.y, o.y), yb = fmaf(s1, d.y, o.y);
+        const float bx0 = fminf(xa, xb) - margin, bx1 = fmaxf(xa, xb) + margin;
+        const float by0 = fminf(ya, yb) - margin, by1 = fmaxf(ya, yb) + margin;
+        Ray r;
+        r.o = make_float3(o.x, o.y, o.z);
+        r.d = make_float3(d.x, d.y, d.z);
+        const float tiny = 1e-30f;
+        r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny),
+                            __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
+                            __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
+        auto meets = [&](float lx, float ly, float lz, float hx, float hy, float hz) {
+          if (hx < bx0 || lx > bx1 || hy < by0 || ly > by1) return false;
+          float tn;
+          return slab(r, lx, ly, lz, hx, hy, hz, o.w, tn);
+        };
+        if (!grid) {
+          for (int b = 0; b < n_obj; ++b) {
+            const float* bx = obj_box + 6 * b;
+            if (meets(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5])) return true;
+          }
+          return false;
+        }
+        // candidate objects: the union of the covered cells' bits
+        const int x0 = cx(bx0), x1 = cx(bx1), y0 = cy(by0), y1 = cy(by1);
+        const bool all = (x1 - x0 + 1) * (y1 - y0 + 1) > kCohMaxCells;
+        for (int wd = 0; wd < words; ++wd) {
+          unsigned long long m = 0;
+          if (all) {
+            m = ~0ull;
+          } else {
+            for (int y = y0; y <= y1; ++y)
+              for (int x = x0; x <= x1; ++x) m |= cell[(y * kCohGrid + x) * words + wd];
+          }
+          while (m) {
+            const int b = 64 * wd + __ffsll(m) - 1;
+            m &= m - 1;
+            if (b >= n_obj) break;
+            if (meets(bl(0, b), bl(1, b), bl(2, b), bl(3, b), bl(4, b), bl(5, b))) return true;
+          }
+        }
+        return false;
+      };
+      // segments in batches whose loads are issued together
+      for (int k0 = 0; k0 < nseg && first == 255; k0 += kCohBatch) {
+        float4 bo[kCohBatch], bd[kCohBatch];
+        int bf[kCohBatch];
+#pragma unroll
+        for (int j = 0; j < kCohBatch; ++j) {
+          const int k = k0 + j;
+          bf[j] = -1;
+          if (k < nseg) {
+            bo[j] = seg_o[(size_t)k * n_work + w];
+            bd[j] = seg_d[(size_t)k * n_work + w];
+            if (moving_hit) bf[j] = face_log[(size_t)k * n_work + w];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kCohBatch; ++j) {
+          const int k = k0 + j;
+          if (k >= nseg || first != 255) break;
+          if ((bf[j] >= 0 && face_object[bf[j]] >= 0) || meets_moving(bo[j], bd[j])) first = k;
+        }
+      }
+      restart[w] = (uint8_t)first;
+    }
+    const bool bad = first != 255;
+    const uint64_t m = __ballot(bad);
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(&counters[kCntWork], (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = w;
+  }
 }
 
-// Keep the cached captures made before each ray's first invalid segment
-// (direct-path records are re-added every frame).
 __global__ void k_filter_caps(const Capture* __restrict__ prev, uint32_t n_prev,
                               const uint8_t* __restrict__ restart, Capture* __restrict__ cur, uint32_t* counters) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -980,11 +1051,14 @@ void launch_reset_counters(dcem_ctx* c) {
 void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
   const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
   uint32_t* cnt = c->cnt_dev;
-  hipLaunchKernelGGL(k_coherence, dim3((n_work + 255) / 256), dim3(256), 0, c->stream, ptr<uint8_t>(c->ray_state),
-                     ptr<float4>(c->seg_o), ptr<float4>(c->seg_d), ptr<int32_t>(c->face_log),
-                     ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, ptr<uint32_t>(c->ray_order),
-                     c->n_rays, n_work, 1e-3f + c->pad, ptr<uint8_t>(c->invalid_flag),
-                     ptr<uint32_t>(c->work_list), cnt);
+  const int blocks = (int)std::min<int64_t>((n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 8);
+  const size_t lds = c->no <= kCohGridObjects ? sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) +
+                                                    sizeof(float) * 6 * c->no
+                                              : 0;
+  hipLaunchKernelGGL(k_coherence, dim3(std::max(blocks, 1)), dim3(kCohBlock), lds, c->stream,
+                     ptr<uint8_t>(c->ray_state), ptr<float4>(c->seg_o), ptr<float4>(c->seg_d),
+                     ptr<int32_t>(c->face_log), ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, n_work,
+                     1e-3f + c->pad, ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
   const int prev = c->cur_caps ^ 1;
   if (n_prev_caps == 0) return;
   hipLaunchKernelGGL(k_filter_caps, dim3((n_prev_caps + 255) / 256), dim3(256), 0, c->stream,
