@@ -79,6 +79,71 @@ def cpu_baseline(scene, frame_index, stride):
                       "(trace, candidates, refinement, power), %.1f s wall" % (frame_index, stride, dirs.shape[0], dt)}
 
 
+# Algorithmic bytes of one closest-hit launch (what the traversal must read
+# and write, counted once per use; nothing assumed cached):
+#   per-thread kernel: 128 B per 4-wide node visit, 48 B per triangle test,
+#     per ray 13 B (direction, order entry, state), per segment 4 B (face log)
+#     + 32 B when the segment cache is kept, 8 B per capture record;
+#   group kernel: per node visit its four 32-byte slots (a leaf slot reads its
+#     48-byte triangle instead: +16 B per triangle test), per ray 42 B (list
+#     entry, restart, cached segment, face, state), per segment 84 B (face log,
+#     segment cache, reflecting triangle), 8 B per capture record.
+def trace_bytes(s, kernel_cache):
+    if s["trace_kernel"] == 1:
+        return 128 * s["nodes_visited"] + 16 * s["tri_tests"] + 42 * s["rays_traced"] + 84 * s["segments"] \
+            + 8 * s["captures"]
+    return 128 * s["nodes_visited"] + 48 * s["tri_tests"] + 13 * s["rays_traced"] \
+        + (4 + (32 if kernel_cache else 0)) * s["segments"] + 8 * s["captures"]
+
+
+PROFILE = os.path.join(ROOT, "profiles", "dynamic_urban_bench_kernels.md")
+KERNEL_SOURCES = ["paper_2112_07115_amd/csrc/dcem_internal.h", "paper_2112_07115_amd/csrc/bvh.hip",
+                  "paper_2112_07115_amd/csrc/trace.hip"]
+
+
+def measured_traffic(kernel, mode):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if not line.startswith("traffic-record:"):
+            continue
+        kv = dict(x.split("=", 1) for x in line.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("mode") == mode and kv.get("sources") == h.hexdigest()[:16]:
+            return float(kv["bytes"])
+    return None
+
+
+def roofline(stats, mode):
+    """Achieved algorithmic GB/s of the closest-hit kernel against HBM peak;
+    kernel time from the HIP events around the launch on the library's stream."""
+    sel = [s for s in stats if s["ms_trace"] > 0]
+    kinds = [s["trace_kernel"] for s in sel]
+    kind = max(set(kinds), key=kinds.count) if kinds else 0   # the traversal most frames used
+    sel = [s for s in sel if s["trace_kernel"] == kind]
+    name = "k_trace_wave" if kind == 1 else "k_trace"
+    ms = float(np.mean([s["ms_trace"] for s in sel]))
+    by = float(np.mean([trace_bytes(s, mode == "coherent") for s in sel]))
+    segs = float(sum(s["segments"] for s in sel))
+    achieved = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name + (" (coherent frame re-trace)" if kind == 1 else " (%s frame)" % mode),
+            "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+            "traffic": measured_traffic(name, "coh" if mode == "coherent" else "full"),
+            "bytes_per_launch": by, "ms_per_launch": ms,
+            "nodes_per_segment": float(sum(s["nodes_visited"] for s in sel)) / max(segs, 1.0),
+            "tris_per_segment": float(sum(s["tri_tests"] for s in sel)) / max(segs, 1.0),
+            "segments_per_launch": segs / max(len(sel), 1), "launches": len(sel)}
+
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -145,23 +210,11 @@ def main():
     out["ms_refit"] = float(np.mean([s["ms_refit"] for s in stats]))
     out["ms_stages"] = {k: float(np.mean([s[k] for s in stats])) for k in
                         ["ms_coherence", "ms_trace", "ms_candidates", "ms_refine", "ms_reduce"]}
-    # roofline of the trace kernel (dominant kernel of a full frame)
-    src = res["full"][2] if "full" in res else stats
-    ms = np.array([s["ms_trace"] for s in src])
-    nodes = np.array([s["nodes_visited"] for s in src], float)
-    tris = np.array([s["tri_tests"] for s in src], float)
-    segs = np.array([s["segments"] for s in src], float)
-    rays = np.array([s["rays_traced"] for s in src], float)
-    caps = np.array([s["captures"] for s in src], float)
-    cache = 0 if "full" in res else 32
-    alg_bytes = 128 * nodes + 48 * tris + (12 + 1) * rays + (4 + cache) * segs + 8 * caps
-    achieved = float(np.mean(alg_bytes) / (np.mean(ms) * 1e-3) / 1e9)
-    out["roofline"] = {"bound": "hbm", "kernel": "k_trace (full re-trace frame)", "achieved": achieved,
-                       "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
-                       "bytes_per_launch": float(np.mean(alg_bytes)), "ms_per_launch": float(np.mean(ms)),
-                       "nodes_per_segment": float(nodes.sum() / segs.sum()),
-                       "tris_per_segment": float(tris.sum() / segs.sum()),
-                       "segments_per_launch": float(np.mean(segs))}
+    # roofline of the closest-hit kernel, the largest kernel of both steps:
+    # the group re-trace in coherent frames, the per-thread trace in full ones
+    out["roofline"] = roofline(stats, "coherent" if main_mode == "coherent" else "full")
+    if "full" in res and main_mode != "full":
+        out["roofline_full_trace"] = roofline(res["full"][2], "full")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, 1, 16)
     print(json.dumps(out))

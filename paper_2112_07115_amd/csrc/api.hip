@@ -282,7 +282,7 @@ void dcem_destroy(dcem_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
-                    &c->obj_box, &c->face_plane, &c->nodes, &c->leaves, &c->leaf_tri, &c->leaf_parent,
+                    &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
                     &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
                     &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
@@ -290,7 +290,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
                     &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
-                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4};
+                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4};
   for (DevBuf* b : bufs) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
@@ -473,8 +473,7 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
     HIP_TRY(build_lbvh(c), "rebuild BVH");
     rb = 1;
   } else {
-    launch_refit(c);
-    launch_collapse(c);
+    launch_refit(c, true);
     launch_sah(c, c->sah_dev + 1);
     HIP_TRY(hipGetLastError(), "refit kernel");
     c->refit_since_build = true;

@@ -220,42 +220,64 @@ __device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
   }
 }
 
-// Bottom-up refit over a fixed topology.  One thread per leaf writes the leaf
-// triangle record and its padded box into its parent's slot; the second thread
-// to arrive at a node forms the union and climbs on.  An internal node covers a
-// contiguous range of sorted leaves and is one end of it, so a node whose range
-// lies inside this block's 1024 leaves has both children here: its arrival
-// counter lives in LDS and the hand-off needs only workgroup-scope ordering.
-// Only nodes spanning several blocks use device-wide counters (reset by their
-// second arrival, so the next refit needs no clearing).  Boxes are min/max of
-// FP32 values: the result does not depend on the order of arrival.
+// Leaf record of triangle `tri` (vertices; id, face and moving flag in w).
+__device__ inline Leaf leaf_record(const float* __restrict__ V, const int32_t* __restrict__ T,
+                                   const int32_t* __restrict__ tri_face, const int32_t* __restrict__ face_object,
+                                   int tri) {
+  const float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
+  const int face = tri_face[tri];
+  Leaf L;
+  L.v0 = make_float4(a.x, a.y, a.z, __int_as_float(tri));
+  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(face));
+  L.v2 = make_float4(c.x, c.y, c.z, __int_as_float(face_object[face] >= 0 ? 1 : 0));
+  return L;
+}
+
+__device__ inline void store_box4(Slot4* sl, const float* lo, const float* hi) {
+  sl->lx = lo[0]; sl->ly = lo[1]; sl->lz = lo[2];
+  sl->hx = hi[0]; sl->hy = hi[1]; sl->hz = hi[2];
+}
+
+// Bottom-up refit over a fixed topology.  One thread per leaf writes its padded
+// box into its parent's slot; the second thread to arrive at a node forms the
+// union and climbs on.  An internal node covers a contiguous range of sorted
+// leaves and is one end of it, so a node whose range lies inside this block's
+// 1024 leaves has both children here: its arrival counter lives in LDS and the
+// hand-off needs only workgroup-scope ordering.  Only nodes spanning several
+// blocks use device-wide counters (reset by their second arrival, so the next
+// refit needs no clearing).  Boxes are min/max of FP32 values: the result does
+// not depend on the order of arrival.  With `wide` (a refit of a collapsed
+// tree) every child box stored in a binary slot is also stored in the 4-wide
+// slot that holds it (slot4, -1 for boxes the 4-wide tree drops) and the leaf
+// thread writes its triangle to its slot, so no separate collapse is needed.
 __global__ __launch_bounds__(kRefitBlock) void k_refit(
     const float* __restrict__ V, const int32_t* __restrict__ T, const int32_t* __restrict__ tri_face,
     const int32_t* __restrict__ face_object, const int32_t* __restrict__ leaf_tri,
-    const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range,
-    Node* __restrict__ nodes, Leaf* __restrict__ leaves, uint32_t* __restrict__ cnt, float* __restrict__ root_box,
-    int n, float pad) {
+    const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range, Node* __restrict__ nodes,
+    uint32_t* __restrict__ cnt, float* __restrict__ root_box, int n, float pad, bool wide,
+    const int32_t* __restrict__ slot4, const int32_t* __restrict__ leaf_slot, Node4* __restrict__ nodes4,
+    Leaf* __restrict__ tri4) {
   __shared__ uint32_t lcnt[kRefitBlock];
   lcnt[threadIdx.x] = 0;
   __syncthreads();
   const int b0 = blockIdx.x * kRefitBlock;
   const int i = b0 + threadIdx.x;
   if (i >= n) return;
-  const int tri = leaf_tri[i];
-  float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
-  Leaf L;
-  const int face = tri_face[tri];
-  L.v0 = make_float4(a.x, a.y, a.z, __int_as_float(tri));
-  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(face));
-  L.v2 = make_float4(c.x, c.y, c.z, __int_as_float(face_object[face] >= 0 ? 1 : 0));
-  leaves[i] = L;
-  float lo[3] = {fminf(a.x, fminf(b.x, c.x)) - pad, fminf(a.y, fminf(b.y, c.y)) - pad,
-                 fminf(a.z, fminf(b.z, c.z)) - pad};
-  float hi[3] = {fmaxf(a.x, fmaxf(b.x, c.x)) + pad, fmaxf(a.y, fmaxf(b.y, c.y)) + pad,
-                 fmaxf(a.z, fmaxf(b.z, c.z)) + pad};
-  if (n == 1) {
+  const Leaf L = leaf_record(V, T, tri_face, face_object, leaf_tri[i]);
+  if (wide) tri4[leaf_slot[i]] = L;
+  float lo[3] = {fminf(L.v0.x, fminf(L.v1.x, L.v2.x)) - pad, fminf(L.v0.y, fminf(L.v1.y, L.v2.y)) - pad,
+                 fminf(L.v0.z, fminf(L.v1.z, L.v2.z)) - pad};
+  float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + pad,
+                 fmaxf(L.v0.z, fmaxf(L.v1.z, L.v2.z)) + pad};
+  if (n == 1) {   // the root holds the one leaf in both slots
     store_slot(&nodes[0], 0, lo, hi);
     store_slot(&nodes[0], 1, lo, hi);
+    if (wide) {
+      store_box4(&nodes4[0].s[0], lo, hi);
+      store_box4(&nodes4[0].s[1], lo, hi);
+      tri4[0] = L;
+      tri4[1] = L;
+    }
     for (int k = 0; k < 3; ++k) { root_box[k] = lo[k]; root_box[3 + k] = hi[k]; }
     return;
   }
@@ -263,6 +285,10 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(
   for (int guard = n; guard > 0; --guard) {   // depth < n in a sound tree
     const int node = p2 >> 1, slot = p2 & 1;
     store_slot(&nodes[node], slot, lo, hi);
+    if (wide) {
+      const int d = slot4[p2];
+      if (d >= 0) store_box4(&nodes4[d >> 2].s[d & 3], lo, hi);
+    }
     const int2 rg = range[node];
     float slo[3], shi[3];
     if (rg.x >= b0 && rg.y < b0 + kRefitBlock) {
@@ -294,9 +320,12 @@ __device__ inline double box_area(const float* lo, const float* hi) {
 }
 
 // Surface-area sum of the internal nodes below the root (each stored in its
-// parent's slot).  Per-block partial sums, combined in a fixed order.
-__global__ void k_sah_partial(const Node* __restrict__ nodes, int n_internal, double* __restrict__ part) {
+// parent's slot) over the root's area.  Per-block partial sums; the last block
+// to finish (ticket counter, left at zero) adds them in a fixed order.
+__global__ void k_sah(const Node* __restrict__ nodes, int n_internal, const float* __restrict__ root,
+                      double* __restrict__ part, uint32_t* __restrict__ ticket, double* __restrict__ out) {
   __shared__ double red[256];
+  __shared__ bool last;
   double s = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_internal; i += gridDim.x * blockDim.x) {
     const float* f = reinterpret_cast<const float*>(&nodes[i]);
@@ -310,20 +339,26 @@ __global__ void k_sah_partial(const Node* __restrict__ nodes, int n_internal, do
     if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-__global__ void k_sah_final(const double* __restrict__ part, int nb, const float* __restrict__ root,
-                            double* __restrict__ out) {
-  // out: the SAH sum ratio of the current tree
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += part[i];
-  double ar = box_area(root, root + 3);
-  out[0] = ar > 0 ? (s + ar) / ar : 1.0;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&part[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  double t = 0.0;
+  for (unsigned b = 0; b < gridDim.x; ++b) t += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *ticket = 0;
+  const float lo[3] = {root[0], root[1], root[2]}, hi[3] = {root[3], root[4], root[5]};
+  const double ar = box_area(lo, hi);
+  out[0] = ar > 0 ? (t + ar) / ar : 1.0;
 }
 
 constexpr int kSahBlocks = 64;
+
+// scene_box layout: root box (6 floats, 2 spare), the SAH per-block sums, then
+// the SAH ticket counter.
+double* sah_parts(dcem_ctx* c) { return reinterpret_cast<double*>(ptr<char>(c->scene_box) + 8 * sizeof(float)); }
+uint32_t* sah_ticket(dcem_ctx* c) { return reinterpret_cast<uint32_t*>(sah_parts(c) + kSahBlocks); }
 
 // Depth of each binary internal node (steps to the root) as a sort key: nodes
 // at even depth become 4-wide nodes and are ordered by (depth, index), i.e.
@@ -342,13 +377,18 @@ __global__ void k_depth_keys(const Node* __restrict__ nodes, int n_internal, uin
   if (even) atomicAdd(n_even, 1u);
 }
 
-__global__ void k_map4(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ n4_dev,
+// 4-wide node of each even-depth binary node (-1 for odd depth).
+__global__ void k_map4(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ n4_dev, int n_internal,
                        int32_t* __restrict__ bvh2_of, int32_t* __restrict__ map4) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int)*n4_dev) return;
+  if (q >= n_internal) return;
   const int p = (int)perm[q];
-  bvh2_of[q] = p;
-  map4[p] = q;
+  if (q < (int)*n4_dev) {
+    bvh2_of[q] = p;
+    map4[p] = q;
+  } else {
+    map4[p] = -1;
+  }
 }
 
 // Leaf-slot mask of the 4-wide node made from binary node p: its slots are,
@@ -371,14 +411,18 @@ __device__ inline uint32_t slot_leaf_mask(const Node* __restrict__ nodes, int p)
   return m;
 }
 
-// Fill every 4-wide node from its binary node p: a leaf child of p is one
-// entry (box from p's slot); an internal child c of p contributes its two
-// children (boxes from c's slots).  Also stores the leaf-slot masks of the
-// node's child nodes (and the root's own mask in info[1]), and copies the
-// leaf triangles into slot order.  Run after every build and refit.
-__global__ void k_collapse(const Node* __restrict__ nodes, const Leaf* __restrict__ leaves,
+// Fill every 4-wide node from its binary node p (after a build): a leaf child
+// of p is one entry (box from p's slot); an internal child c of p contributes
+// its two children (boxes from c's slots).  Also stores the leaf-slot masks of
+// the node's child nodes (and the root's own mask in info[1]), the leaf
+// triangles in slot order and, per sorted leaf, its slot (where refits write
+// the moved triangle).
+__global__ void k_collapse(const Node* __restrict__ nodes, const float* __restrict__ V,
+                           const int32_t* __restrict__ T, const int32_t* __restrict__ tri_face,
+                           const int32_t* __restrict__ face_object, const int32_t* __restrict__ leaf_tri,
                            const int32_t* __restrict__ bvh2_of, const int32_t* __restrict__ map4,
-                           uint32_t* __restrict__ info, Node4* __restrict__ out, Leaf* __restrict__ tri4) {
+                           uint32_t* __restrict__ info, Node4* __restrict__ out, Leaf* __restrict__ tri4,
+                           int32_t* __restrict__ leaf_slot, int32_t* __restrict__ slot4) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int)info[0]) return;
   const int p = bvh2_of[q];
@@ -393,11 +437,14 @@ __global__ void k_collapse(const Node* __restrict__ nodes, const Leaf* __restric
     if (c < 0) {
       for (int a = 0; a < 3; ++a) { lo[m][a] = fp[6 * s + a]; hi[m][a] = fp[6 * s + 3 + a]; }
       own |= 1u << m;
+      slot4[2 * p + s] = 4 * q + m;
       ch[m++] = c;
     } else {
       const float* fc = reinterpret_cast<const float*>(&nodes[c]);
       const int cc[2] = {nodes[c].c.x, nodes[c].c.y};
+      slot4[2 * p + s] = -1;   // an internal child's box is not kept in the 4-wide tree
       for (int t = 0; t < 2; ++t) {
+        slot4[2 * c + t] = 4 * q + m;
         for (int a = 0; a < 3; ++a) { lo[m][a] = fc[6 * t + a]; hi[m][a] = fc[6 * t + 3 + a]; }
         if (cc[t] < 0) {
           own |= 1u << m;
@@ -409,8 +456,11 @@ __global__ void k_collapse(const Node* __restrict__ nodes, const Leaf* __restric
       }
     }
   }
-  for (int e = 0; e < m; ++e)
-    if (ch[e] < 0) tri4[4 * (size_t)q + e] = leaves[~ch[e]];
+  for (int e = 0; e < m; ++e) {
+    if (ch[e] >= 0) continue;
+    tri4[4 * (size_t)q + e] = leaf_record(V, T, tri_face, face_object, leaf_tri[~ch[e]]);
+    leaf_slot[~ch[e]] = 4 * q + e;
+  }
   Node4 n;
   for (int e = 0; e < 4; ++e) {
     Slot4& sl = n.s[e];
@@ -452,7 +502,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   }
   const int ni = c->n_internal;
   if ((e = ensure(c->nodes, sizeof(Node) * ni)) != hipSuccess) return e;
-  if ((e = ensure(c->leaves, sizeof(Leaf) * nt)) != hipSuccess) return e;
+  if ((e = ensure(c->leaf_slot, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_tri, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_parent, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * ni)) != hipSuccess) return e;
@@ -464,6 +514,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->tri4, sizeof(Leaf) * 4 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->bvh2_of4, sizeof(int32_t) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->map4, sizeof(int32_t) * ni)) != hipSuccess) return e;
+  if ((e = ensure(c->slot4, sizeof(int32_t) * 2 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
   if ((e = ensure(c->tree_info, 64)) != hipSuccess) return e;
   uint32_t* code = ptr<uint32_t>(c->morton);
@@ -478,6 +529,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
                      ptr<int32_t>(c->tris), nt, nbox, code);
   if ((e = radix_sort_perm(c, code, 1, 30, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
+  uint32_t* ticket = sah_ticket(c);
+  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, ticket, 0u, ticket, 0u);
   if (nt == 1) {
     Node root{};
     root.c = make_int4(~0, ~0, -1, 0);
@@ -492,7 +545,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
                        ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri),
                        ptr<int2>(c->node_range));
   }
-  launch_refit(c);
+  launch_refit(c, false);
   // 4-wide tree: binary nodes at even depth, breadth-first
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
   uint32_t* dperm = dkey + ni;
@@ -502,8 +555,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
   hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, n4, 0u, dn, (uint32_t)ni);
   hipLaunchKernelGGL(k_depth_keys, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), ni, dkey, n4);
   if ((e = radix_sort_perm(c, dkey, 1, 32, dn, ni, dperm, dtmp, c->stream)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_map4, dim3((ni + 255) / 256), dim3(256), 0, c->stream, dperm, n4, ptr<int32_t>(c->bvh2_of4),
-                     ptr<int32_t>(c->map4));
+  hipLaunchKernelGGL(k_map4, dim3((ni + 255) / 256), dim3(256), 0, c->stream, dperm, n4, ni,
+                     ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4));
   launch_collapse(c);
   launch_sah(c, c->sah_dev + 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -514,26 +567,26 @@ hipError_t build_lbvh(dcem_ctx* c) {
 void launch_collapse(dcem_ctx* c) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_collapse, dim3((c->n_internal + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
-                     ptr<Leaf>(c->leaves), ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4),
-                     ptr<uint32_t>(c->tree_info), ptr<Node4>(c->nodes4), ptr<Leaf>(c->tri4));
+                     ptr<float>(c->vertices), ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face),
+                     ptr<int32_t>(c->face_object), ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->bvh2_of4),
+                     ptr<int32_t>(c->map4), ptr<uint32_t>(c->tree_info), ptr<Node4>(c->nodes4),
+                     ptr<Leaf>(c->tri4), ptr<int32_t>(c->leaf_slot), ptr<int32_t>(c->slot4));
 }
 
-void launch_refit(dcem_ctx* c) {
+void launch_refit(dcem_ctx* c, bool wide) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
                      c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face),
                      ptr<int32_t>(c->face_object), ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->leaf_parent),
-                     ptr<int2>(c->node_range),
-                     ptr<Node>(c->nodes), ptr<Leaf>(c->leaves), ptr<uint32_t>(c->refit_cnt),
-                     ptr<float>(c->scene_box), (int)c->nt, c->pad);
+                     ptr<int2>(c->node_range), ptr<Node>(c->nodes), ptr<uint32_t>(c->refit_cnt),
+                     ptr<float>(c->scene_box), (int)c->nt, c->pad, wide, ptr<int32_t>(c->slot4),
+                     ptr<int32_t>(c->leaf_slot), ptr<Node4>(c->nodes4), ptr<Leaf>(c->tri4));
 }
 
 void launch_sah(dcem_ctx* c, double* out) {
   if (c->nt == 0) return;
-  double* part = reinterpret_cast<double*>(ptr<char>(c->scene_box) + 8 * sizeof(float));
-  hipLaunchKernelGGL(k_sah_partial, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes),
-                     c->n_internal, part);
-  hipLaunchKernelGGL(k_sah_final, dim3(1), dim3(64), 0, c->stream, part, kSahBlocks, ptr<float>(c->scene_box), out);
+  hipLaunchKernelGGL(k_sah, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes), c->n_internal,
+                     ptr<float>(c->scene_box), sah_parts(c), sah_ticket(c), out);
 }
 
 }  // namespace dcem

@@ -64,9 +64,9 @@ __device__ inline void wave_sync() {
 
 // Leaf triangle, 48 bytes: vertices with the triangle id, its face id and 1
 // if the face belongs to a moving object (else 0) in the w components (as
-// integer bits).  Stored twice: in sorted-leaf order (the binary tree's
-// leaves) and in slot order, [n4][4] with the leaf in slot e of 4-wide node q
-// at 4q + e (other slots unused).
+// integer bits).  Stored in slot order, [n4][4] with the leaf in slot e of
+// 4-wide node q at 4q + e (other slots unused); leaf_slot maps each sorted
+// leaf of the binary tree to its slot.
 struct __align__(16) Leaf {
   float4 v0, v1, v2;
 };
@@ -121,9 +121,10 @@ struct dcem_ctx {
   double sah_build = 0.0, sah_last = 1.0;
   int32_t last_rebuilt = 0;
   int32_t last_trace_kernel = 0;                     // traversal of the last frame (0 per thread, 1 per wavefront)
-  dcem::DevBuf nodes, leaves, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
+  dcem::DevBuf nodes, leaf_slot, leaf_tri, leaf_parent, refit_cnt, morton, sort_tmp, sah_part, scene_box,
       node_range;
   dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
+  dcem::DevBuf slot4;                                // per binary child slot: the 4-wide slot holding its box, or -1
   dcem::DevBuf tree_info;                            // uint32 [0]: number of 4-wide nodes, [1]: root leaf-slot mask
   dcem::DevBuf tri4;                                 // leaf triangles in slot order (Leaf [n4][4])
 
@@ -204,7 +205,8 @@ T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
 // ---- launchers (bvh.hip)
 void launch_xform(dcem_ctx* c);
 hipError_t build_lbvh(dcem_ctx* c);
-void launch_refit(dcem_ctx* c);
+// Refit the binary tree; `wide` also updates the 4-wide tree in place (no collapse needed).
+void launch_refit(dcem_ctx* c, bool wide);
 void launch_collapse(dcem_ctx* c);
 void launch_sah(dcem_ctx* c, double* out);
 

@@ -121,12 +121,12 @@ __device__ inline bool slab(const Ray& r, float lx, float ly, float lz, float hx
 struct Hit {
   float t;
   int tri;    // original triangle id, -1 none
-  int leaf;   // leaf index, -1 none
+  int leaf;   // slot of the triangle in the slot triangle array, -1 none
   int face;
 };
 
-__device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ leaves, int li, int excl, Hit& h) {
-  const float4 p0 = leaves[li].v0, p1 = leaves[li].v1, p2 = leaves[li].v2;
+__device__ inline void test_leaf(const Ray& r, const Leaf* __restrict__ tri4, int li, int excl, Hit& h) {
+  const float4 p0 = tri4[li].v0, p1 = tri4[li].v1, p2 = tri4[li].v2;
   const int face = __float_as_int(p1.w);
   if (face == excl) return;
   const float t = watertight(r, p0, p1, p2);
@@ -153,7 +153,7 @@ __device__ inline void cswap(float& ta, int& ca, float& tb, int& cb) {
 // not depend on the tree shape: boxes are conservative and nodes are pruned
 // only when their entry distance exceeds the current best (ties are visited).
 __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const Node4* top, int n_top, int n4,
-                           const Leaf* __restrict__ leaves, int excl, int* stack, int stride, bool& overflow,
+                           const Leaf* __restrict__ tri4, int excl, int* stack, int stride, bool& overflow,
                            uint32_t& n_nodes, uint32_t& n_tris) {
   Hit h{FLT_MAX, -1, -1, -1};
   if (n4 == 0) return h;
@@ -176,7 +176,7 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
       float tn;
       if (!slab(r, sl.lx, sl.ly, sl.lz, sl.hx, sl.hy, sl.hz, h.t, tn)) continue;
       if (ch < 0) {
-        test_leaf(r, leaves, ~ch, excl, h);
+        test_leaf(r, tri4, 4 * node + e, excl, h);
         ++n_tris;
       } else {
         t[e] = tn;
@@ -222,7 +222,6 @@ __global__ void k_fibonacci(float* __restrict__ dirs, int64_t n) {
 
 struct TraceArgs {
   const Node4* nodes4;
-  const Leaf* leaves;         // leaf triangles in sorted-leaf order
   const Leaf* tri4;           // leaf triangles in slot order
   const uint32_t* n4_dev;     // number of 4-wide nodes (null: empty scene)
   const float* dirs;
@@ -339,7 +338,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       setup_ray(r);
       uint32_t state = 0;
       for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.leaves, excl, stack, kTraceBlock, overflow,
+        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, kTraceBlock, overflow,
                             node_count, tri_count);
         ++seg_count;
         const bool hit = h.tri >= 0;
@@ -405,7 +404,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         if (!hit || k == a.K) { ++k; break; }
         // specular reflection off the hit triangle's plane
         L = L_hit;
-        reflect_ray(r, h.t, a.leaves[h.leaf].v0, a.leaves[h.leaf].v1, a.leaves[h.leaf].v2);
+        reflect_ray(r, h.t, a.tri4[h.leaf].v0, a.tri4[h.leaf].v1, a.tri4[h.leaf].v2);
         excl = h.face;
       }
       // mark the remaining bounces as not reached
@@ -450,7 +449,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 // traversing.  Every triangle the per-thread traversal tests is tested here
 // too (leaf triangles without their boxes, which only drops a conservative
 // filter), with the same arithmetic, so the hit is the same.
-constexpr int kGroups = kWave / kGroup;     // rays per wavefront
+constexpr int kRayLanes = kGroup;           // lanes per ray: one DPP row (16) or two (32)
+constexpr int kGroups = kWave / kRayLanes;  // rays per wavefront
 constexpr int kWaves = 4;                   // wavefronts per block
 constexpr int kWaveBlock = kWaves * kWave;
 constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
@@ -492,6 +492,16 @@ struct SlotHit {
   int moving; // the face belongs to a moving object
 };
 
+// Minimum over each group of kRayLanes lanes.
+__device__ inline uint64_t group_min_u64(uint64_t v) {
+  v = row_min_u64(v);
+  if (kRayLanes == 32) {
+    const uint64_t o = __shfl_xor(v, 16);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
 __device__ inline MaskAxes mask_axes(const Ray& r) {
   auto m = [](int k, int j) { return k == j ? 0xffffffffu : 0u; };
   return MaskAxes{m(r.kx, 0), m(r.kx, 1), m(r.kx, 2), m(r.ky, 0), m(r.ky, 1),
@@ -503,12 +513,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   __shared__ uint32_t stk_e[kWaves * kGroups][kGroupStack];
   __shared__ float stk_t[kWaves * kGroups][kGroupStack];
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = lane / kGroup, gl = lane & (kGroup - 1), jl = gl >> 2, el = gl & 3;
-  const int leader = lane & ~(kGroup - 1);
-  const uint64_t gmask = 0xffffull << (kGroup * g);
+  const int g = lane / kRayLanes, gl = lane & (kRayLanes - 1), jl = gl >> 2, el = gl & 3;
+  const int leader = lane & ~(kRayLanes - 1);
+  const uint64_t gmask = ((1ull << kRayLanes) - 1ull) << (kRayLanes * g);
   const uint64_t below = (1ull << lane) - 1ull;
-  uint32_t* se = stk_e[threadIdx.x / kGroup];
-  float* st = stk_t[threadIdx.x / kGroup];
+  uint32_t* se = stk_e[threadIdx.x / kRayLanes];
+  float* st = stk_t[threadIdx.x / kRayLanes];
   const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
   const bool rx_lds = a.n_rx <= kWaveRx;
   if (rx_lds)
@@ -575,7 +585,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     wave_sync();
     if (__ballot(busy) == 0) break;
     // ---- one traversal step of every group whose stack is not empty
-    const int n_pop = busy ? min(4, sp) : 0;
+    const int n_pop = busy ? min(kRayLanes / 4, sp) : 0;
     bool act = jl < n_pop;
     uint32_t ent = 0;
     float tn = 0.0f;
@@ -638,7 +648,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       overflow = true;
       sp = 0;
     }
-    const uint64_t best = row_min_u64(hit_key(h.t, h.tri));
+    const uint64_t best = group_min_u64(hit_key(h.t, h.tri));
     best_t = best == ~0ull ? INFINITY : __uint_as_float((uint32_t)(best >> 32));
     if (!(busy && sp == 0)) continue;
     // ---- this group's traversal ended: finish the segment
@@ -677,7 +687,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const float za = r.o.z;
     const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
     if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
-      for (int c = gl; c < a.n_rx; c += kGroup) {
+      for (int c = gl; c < a.n_rx; c += kRayLanes) {
         float cx, cy, cz;
         if (rx_lds) {
           const float4 q = rxs[c];
@@ -994,7 +1004,6 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) 
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
-  a.leaves = ptr<Leaf>(c->leaves);
   a.tri4 = ptr<Leaf>(c->tri4);
   a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.dirs = ptr<float>(c->dirs);
