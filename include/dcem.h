@@ -196,11 +196,17 @@ dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n
 
 /* Bring the BVH up to date with the current vertices (paper Sec. III,
  * "Efficient BVH updating"): refit the node boxes bottom-up over the fixed
- * topology, measure quality as the SAH surface-area sum relative to the last
- * build, and rebuild when it exceeds rebuild_threshold (<= 0 selects 1.5;
- * +inf never rebuilds) or when flags has DCEM_FORCE_REBUILD.
- * rebuilt / sah_ratio (nullable, host) receive the decision and the ratio
- * (1.0 right after a rebuild).  Synchronises the stream. */
+ * topology (the binary tree and its 4-wide form together), measure quality as
+ * the SAH surface-area sum relative to the last build, and rebuild instead
+ * when the quality measured after the previous refit exceeds
+ * rebuild_threshold (<= 0 selects 1.5; +inf never rebuilds) or when flags
+ * has DCEM_FORCE_REBUILD.  The decision lags by one refit so that no host
+ * round trip is needed: the ratio of a refit is read back by the next
+ * synchronising call.  rebuilt / sah_ratio (nullable, host) receive the
+ * decision and the ratio it was based on (1.0 right after a rebuild).
+ * Asynchronous on the context stream; device errors are reported by the next
+ * synchronising call.  Rebuilding never changes traced results: hits are the
+ * lexicographic minimum of (distance, triangle id) over conservative boxes. */
 dcem_status dcem_refit_bvh(dcem_ctx* ctx, int32_t flags, double rebuild_threshold,
                            int32_t* rebuilt, double* sah_ratio);
 

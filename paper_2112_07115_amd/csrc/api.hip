@@ -422,7 +422,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   for (int o = 0; o < c->no; ++o) ident[12 * o] = ident[12 * o + 5] = ident[12 * o + 10] = 1.f;
   HIP_TRY(upload(c->xf, ident, c->stream), "upload transforms");
   HIP_TRY(ensure(c->obj_box, sizeof(float) * 6 * std::max(c->no, 1)), "alloc object boxes");
-  launch_xform(c);
+  launch_xform(c, ptr<float>(c->xf));
   HIP_TRY(hipGetLastError(), "transform kernel");
   HIP_TRY(build_lbvh(c), "build BVH");
   c->has_scene = true;
@@ -448,10 +448,10 @@ dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_o
       if (!std::isfinite(xf[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite transform entry %d", i);
     HIP_TRY(hipMemcpyAsync(c->xf.p, xf, sizeof(float) * 12 * n_objects, hipMemcpyHostToDevice, c->stream), "copy xf");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    launch_xform(c, ptr<float>(c->xf));
   } else {
-    HIP_TRY(hipMemcpyAsync(c->xf.p, xf, sizeof(float) * 12 * n_objects, hipMemcpyDeviceToDevice, c->stream), "copy xf");
+    launch_xform(c, xf);   // read in place: device inputs stay valid until the stream reaches the kernel
   }
-  launch_xform(c);
   HIP_TRY(hipGetLastError(), "transform kernel");
   c->bvh_stale = true;
   return DCEM_OK;
@@ -610,15 +610,14 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   const bool small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
   // -- schedule (no host round trip on the small path)
   ev_record(c, 0);
-  launch_reset_counters(c);
   c->cur_caps ^= 1;
-  if (coherent) launch_coherence(c, n_prev);
+  launch_frame_begin(c, p->los_always != 0);
+  if (coherent) launch_coherence(c);
   ev_record(c, 1);
-  c->last_trace_kernel = n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work) : 0;
+  c->last_trace_kernel =
+      n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work, n_prev) : 0;
   ev_record(c, 2);
-  if (p->los_always) launch_los(c);
   HIP_TRY(hipGetLastError(), "trace kernels");
-  launch_face_planes(c);
   HIP_TRY(build_candidates(c, small), "candidates");
   ev_record(c, 3);
   HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");

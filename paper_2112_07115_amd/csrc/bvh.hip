@@ -319,13 +319,35 @@ __device__ inline double box_area(const float* lo, const float* hi) {
   return 2.0 * (dx * dy + dy * dz + dz * dx);
 }
 
-// Surface-area sum of the internal nodes below the root (each stored in its
-// parent's slot) over the root's area.  Per-block partial sums; the last block
-// to finish (ticket counter, left at zero) adds them in a fixed order.
+// Unit normal n and offset n . a of the plane of face f (FP64, from the
+// face's reference triangle a, b, c: n = (b - a) x (c - a) normalised).
+__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
+                                  double4* __restrict__ plane, int f) {
+  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
+  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
+  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
+  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
+  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+  const double l = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= l;
+  ny /= l;
+  nz /= l;
+  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
+}
+
+// After a build or refit: the plane of every face (the refinement's image
+// method reflects through them), and the surface-area sum of the internal
+// nodes below the root (each stored in its parent's slot) over the root's
+// area.  Per-block partial sums; the last block to finish (ticket counter,
+// left at zero) adds them in a fixed order.
 __global__ void k_sah(const Node* __restrict__ nodes, int n_internal, const float* __restrict__ root,
-                      double* __restrict__ part, uint32_t* __restrict__ ticket, double* __restrict__ out) {
+                      double* __restrict__ part, uint32_t* __restrict__ ticket, double* __restrict__ out,
+                      const float* __restrict__ V, const int32_t* __restrict__ T,
+                      const int32_t* __restrict__ face_ref_tri, int nf, double4* __restrict__ plane) {
   __shared__ double red[256];
   __shared__ bool last;
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x)
+    face_plane(V, T, face_ref_tri[f], plane, f);
   double s = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_internal; i += gridDim.x * blockDim.x) {
     const float* f = reinterpret_cast<const float*>(&nodes[i]);
@@ -481,10 +503,10 @@ __global__ void k_collapse(const Node* __restrict__ nodes, const float* __restri
 
 }  // namespace
 
-void launch_xform(dcem_ctx* c) {
+void launch_xform(dcem_ctx* c, const float* xf) {
   if (c->no == 0) return;
   hipLaunchKernelGGL(k_xform, dim3(c->no), dim3(256), 0, c->stream, ptr<float>(c->ref_vertices),
-                     ptr<float>(c->vertices), ptr<int64_t>(c->obj_range), ptr<float>(c->xf),
+                     ptr<float>(c->vertices), ptr<int64_t>(c->obj_range), xf,
                      ptr<float>(c->obj_box), c->pad, c->err_dev);
 }
 
@@ -586,7 +608,8 @@ void launch_refit(dcem_ctx* c, bool wide) {
 void launch_sah(dcem_ctx* c, double* out) {
   if (c->nt == 0) return;
   hipLaunchKernelGGL(k_sah, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes), c->n_internal,
-                     ptr<float>(c->scene_box), sah_parts(c), sah_ticket(c), out);
+                     ptr<float>(c->scene_box), sah_parts(c), sah_ticket(c), out, ptr<float>(c->vertices),
+                     ptr<int32_t>(c->tris), ptr<int32_t>(c->face_ref_tri), c->nf, ptr<double4>(c->face_plane));
 }
 
 }  // namespace dcem

@@ -203,7 +203,8 @@ template <class T>
 T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
 
 // ---- launchers (bvh.hip)
-void launch_xform(dcem_ctx* c);
+// Transform the moving objects' vertices by xf ([n_objects][3][4], device).
+void launch_xform(dcem_ctx* c, const float* xf);
 hipError_t build_lbvh(dcem_ctx* c);
 // Refit the binary tree; `wide` also updates the 4-wide tree in place (no collapse needed).
 void launch_refit(dcem_ctx* c, bool wide);
@@ -219,18 +220,19 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
 
 // ---- trace (trace.hip)
 void launch_fibonacci(dcem_ctx* c);
-// Returns the traversal launched: 0 one thread per ray, 1 one wavefront per ray.
-int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected);
-void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps);
-void launch_los(dcem_ctx* c);
-void launch_reset_counters(dcem_ctx* c);
+// Trace all rays, or (coherent frame) the listed ones after keeping the
+// previous frame's still-valid captures.  Returns the traversal launched:
+// 0 one thread per ray, 1 one group of lanes per ray.
+int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps);
+void launch_coherence(dcem_ctx* c);
+// Clear the frame counters and seed the capture list with the LoS candidates.
+void launch_frame_begin(dcem_ctx* c, bool los);
 hipError_t build_ray_order(dcem_ctx* c);
 
 // ---- candidates, refinement and accumulation (refine.hip)
 hipError_t build_candidates(dcem_ctx* c, bool small);
 bool small_path_fits(const dcem_ctx* c);
 int64_t small_path_capacity();
-void launch_face_planes(dcem_ctx* c);
 hipError_t ensure_paths(dcem_ctx* c, int64_t n);
 void launch_refine(dcem_ctx* c);
 void launch_reduce(dcem_ctx* c);

@@ -79,11 +79,9 @@ __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32
   for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
 }
 
-// Whole de-duplication of a small capture list in one workgroup: keys, a
-// bitonic sort of (key, capture index) over the next power of two (padding
-// sorts last), unique heads and their compaction, all in LDS.  Ties of equal
-// keys are ordered by capture index, so the result is deterministic.  Used
-// when n <= kSmallN and W <= kSmallW.
+// Whole de-duplication of a small capture list in one workgroup: keys, stable
+// LSD radix sort (8-bit digits, wavefront-ballot ranking), unique heads and
+// their compaction, all in LDS.  Used when n <= kSmallN and W <= kSmallW.
 constexpr int kSmallN = 2048;
 constexpr int kSmallW = 3;
 constexpr int kSmallThreads = 1024;
@@ -104,18 +102,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
     }
     return;
   }
-  __shared__ uint32_t idx[kSmallN];
-  __shared__ uint32_t hist[kSmallThreads / kWave + 1];
+  __shared__ uint32_t pa[kSmallN], pb[kSmallN];
+  __shared__ uint32_t wcnt[kSmallThreads / kWave][256];
+  __shared__ uint32_t hist[256], running[256];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int kW = kSmallThreads / kWave;
-  uint32_t N = 1;
-  while (N < n) N <<= 1;
-  for (uint32_t i = tid; i < N; i += kSmallThreads) {
-    if (i >= n) {   // padding: all-ones keys, sorted behind every capture
-      for (int k = 0; k < L.W; ++k) key[k][i] = 0xffffffffu;
-      idx[i] = i;
-      continue;
-    }
+  for (uint32_t i = tid; i < n; i += kSmallThreads) {
     const Capture c = caps[i];
     const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
     const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
@@ -135,40 +127,70 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
       key[k][i] = w[k];
       keys_out[k * (int64_t)kSmallN + i] = w[k];
     }
-    idx[i] = i;
+    pa[i] = i;
   }
   __syncthreads();
-  // (key, index) of slot a before that of slot b?
-  auto before = [&](uint32_t a, uint32_t b) {
-    for (int k = 0; k < L.W; ++k)
-      if (key[k][a] != key[k][b]) return key[k][a] < key[k][b];
-    return idx[a] < idx[b];
-  };
-  // a wavefront owns 2 * 64 consecutive slots, so steps with stride <= 64 need
-  // only wavefront-level ordering
-  constexpr uint32_t kLocal = kWave;
-  for (uint32_t size = 2; size <= N; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      const uint32_t next = stride > 1 ? stride >> 1 : size;
-      for (uint32_t t = tid; t < N / 2; t += kSmallThreads) {
-        const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
-        const bool up = (a & size) == 0;
-        if (before(b, a) == up) {
-          for (int k = 0; k < L.W; ++k) {
-            const uint32_t x = key[k][a];
-            key[k][a] = key[k][b];
-            key[k][b] = x;
-          }
-          const uint32_t x = idx[a];
-          idx[a] = idx[b];
-          idx[b] = x;
-        }
+  uint32_t* src = pa;
+  uint32_t* dst = pb;
+  const int passes = (L.bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int word = L.W - 1 - (8 * p) / 32, shift = (8 * p) % 32;
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(key[word][src[i]] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    if (tid < kWave) {   // exclusive scan of the 256 digit counts: 4 per lane, then across lanes
+      const uint32_t h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
+      const uint32_t tot = h0 + h1 + h2 + h3;
+      uint32_t incl = tot;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off);
+        if (tid >= off) incl += v;
       }
-      if (stride > kLocal || next > kLocal || N > 2 * kSmallThreads) __syncthreads();
-      else wave_sync();
+      const uint32_t base = incl - tot;
+      running[4 * tid] = base;
+      running[4 * tid + 1] = base + h0;
+      running[4 * tid + 2] = base + h0 + h1;
+      running[4 * tid + 3] = base + h0 + h1 + h2;
     }
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += kSmallThreads) {
+      for (int w = 0; w < kW; ++w)
+        if (tid < 256) wcnt[w][tid] = 0;
+      __syncthreads();
+      const uint32_t i = base + tid;
+      const bool valid = i < n;
+      uint32_t idx = 0, d = 0;
+      if (valid) {
+        idx = src[i];
+        d = (key[word][idx] >> shift) & 0xffu;
+      }
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint64_t below = peers & ((1ull << lane) - 1ull);
+      if (valid && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = running[d] + (uint32_t)__popcll(below);
+        for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+        dst[pos] = idx;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t add = 0;
+        for (int w = 0; w < kW; ++w) add += wcnt[w][tid];
+        running[tid] += add;
+      }
+      __syncthreads();
+    }
+    uint32_t* t = src;
+    src = dst;
+    dst = t;
   }
-  __syncthreads();
   // unique heads of the sorted keys, compacted in order (chunks of 2 per thread)
   constexpr int kPer = kSmallN / kSmallThreads;
   uint32_t flags = 0, cnt = 0;
@@ -177,12 +199,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
     bool h = false;
     if (i < n) {
       h = i == 0;
-      for (int k = 0; k < L.W && !h; ++k) h = key[k][i] != key[k][i - 1];
+      for (int k = 0; k < L.W && !h; ++k) h = key[k][src[i]] != key[k][src[i - 1]];
     }
     flags |= (h ? 1u : 0u) << q;
     cnt += h ? 1u : 0u;
   }
-  // exclusive scan of cnt over the block (per-wavefront totals in hist)
+  // exclusive scan of cnt over the block (hist/running reused as scratch per wave)
   uint32_t incl = cnt;
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t v = __shfl_up(incl, off);
@@ -203,7 +225,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
   uint32_t off = hist[wave] + incl - cnt;
   for (int q = 0; q < kPer; ++q)
     if ((flags >> q) & 1u) uniq_pos[off++] = tid * kPer + q;
-  for (uint32_t i = tid; i < n; i += kSmallThreads) perm_out[i] = idx[i];
+  for (uint32_t i = tid; i < n; i += kSmallThreads) perm_out[i] = src[i];
   if (tid == 0) {
     *n_unique = hist[kW];
     uniq_pos[hist[kW]] = n;
@@ -270,20 +292,6 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ hea
   if (i == 0) uniq_pos[*n_unique] = n;
 }
 
-__global__ void k_face_planes(const float* __restrict__ V, const int32_t* __restrict__ T,
-                              const int32_t* __restrict__ ref_tri, int nf, double4* __restrict__ plane) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  const int t = ref_tri[f];
-  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
-  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
-  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
-  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
-  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
-  const double l = sqrt(nx * nx + ny * ny + nz * nz);
-  nx /= l; ny /= l; nz /= l;
-  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
-}
 
 struct D3 {
   double x, y, z;
@@ -784,12 +792,6 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_caps, cnt + kCntUnique,
                      ptr<uint32_t>(c->uniq_idx));
   return hipGetLastError();
-}
-
-void launch_face_planes(dcem_ctx* c) {
-  if (c->nf == 0) return;
-  hipLaunchKernelGGL(k_face_planes, dim3((c->nf + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
-                     ptr<int32_t>(c->tris), ptr<int32_t>(c->face_ref_tri), c->nf, ptr<double4>(c->face_plane));
 }
 
 hipError_t ensure_paths(dcem_ctx* c, int64_t n) {

@@ -250,7 +250,36 @@ struct TraceArgs {
   Capture* caps;
   int64_t cap_capacity;
   uint32_t* err;
+  const Capture* prev_caps;   // coherent frames: the previous frame's captures to filter
+  uint32_t n_prev;
 };
+
+// Coherent frames: keep each capture of the previous frame made before its
+// ray's first re-traced segment (those after it are found again by the
+// re-trace).  Appended with one atomic per wavefront; run by every block of
+// the trace kernel before it traces.
+__device__ void keep_previous_captures(const TraceArgs& a, bool& cap_over) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x - lane); base < a.n_prev; base += stride) {
+    const uint32_t i = base + lane;
+    bool keep = false;
+    Capture c{};
+    if (i < a.n_prev) {
+      c = a.prev_caps[i];
+      keep = c.work != kNoRay && (c.pair_order & 15u) < a.restart[c.work];
+    }
+    const uint64_t m = __ballot(keep);
+    uint32_t b = 0;
+    if (lane == 0 && m) b = atomicAdd(&a.counters[kCntCaptures], (uint32_t)__popcll(m));
+    b = __shfl(b, 0);
+    if (keep) {
+      const uint32_t slot = b + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (slot < a.cap_capacity) a.caps[slot] = c;
+      else cap_over = true;
+    }
+  }
+}
 
 // Per-segment arithmetic shared by both trace kernels.  Contraction into fused
 // multiply-adds is disabled (fused operations are written out) so that every
@@ -303,6 +332,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   const uint32_t n_work = a.work_list ? a.counters[kCntWork] : (uint32_t)a.n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
+  keep_previous_captures(a, cap_over);
   while (true) {
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&a.counters[kCntQueue], (uint32_t)kWave);
@@ -529,6 +559,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   const uint32_t n_work = a.counters[kCntWork];
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
+  keep_previous_captures(a, cap_over);
 
   // this group's ray (equal on its lanes)
   bool busy = false;
@@ -751,8 +782,21 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
-__global__ void k_reset_counters(uint32_t* counters) {
-  if (threadIdx.x < kCntSlots) counters[threadIdx.x] = 0;
+// Start of a frame: clear the counters and, with deterministic line of sight,
+// put one LoS candidate per (tx, rx) pair at the head of the capture list.
+__global__ void k_frame_begin(uint32_t* __restrict__ counters, Capture* __restrict__ caps, int n_los,
+                              int64_t cap_capacity, uint32_t* __restrict__ err) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < kCntSlots) counters[threadIdx.x] = threadIdx.x == kCntCaptures ? n_los : 0;
+  if (p >= n_los) return;
+  if (p < cap_capacity) {
+    Capture c;
+    c.work = kNoRay;
+    c.pair_order = (uint32_t)p << 4;
+    caps[p] = c;
+  } else if (p == cap_capacity) {
+    atomicOr(err, DCEM_ERR_CAPTURES);
+  }
 }
 
 // Coherence pass.  Segment k of a cached ray is still valid iff no earlier
@@ -917,22 +961,6 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
   }
 }
 
-__global__ void k_filter_caps(const Capture* __restrict__ prev, uint32_t n_prev,
-                              const uint8_t* __restrict__ restart, Capture* __restrict__ cur, uint32_t* counters) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  bool keep = false;
-  Capture c{};
-  if (i < n_prev) {
-    c = prev[i];
-    keep = c.work != kNoRay && (c.pair_order & 15u) < restart[c.work];
-  }
-  const uint64_t m = __ballot(keep);
-  uint32_t base = 0;
-  if (lane == 0 && m) base = atomicAdd(&counters[kCntCaptures], (uint32_t)__popcll(m));
-  base = __shfl(base, 0);
-  if (keep) cur[base + __popcll(m & ((1ull << lane) - 1ull))] = c;
-}
 
 // Spatial key of a direction: octahedral map to the unit square, 16 bits per
 // axis, interleaved.  Sorting rays by it groups neighbouring directions in a
@@ -962,21 +990,6 @@ __global__ void k_dir_keys(const float* __restrict__ dirs, int64_t n, uint32_t* 
   key[i] = (spread16(qu) << 1) | spread16(qv);
 }
 
-__global__ void k_los(Capture* __restrict__ caps, uint32_t* counters, int n_pairs, int64_t cap_capacity,
-                      uint32_t* err) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const uint32_t slot = atomicAdd(&counters[kCntCaptures], 1u);
-  if (slot < cap_capacity) {
-    Capture c;
-    c.work = kNoRay;
-    c.pair_order = (uint32_t)p << 4;
-    caps[slot] = c;
-  } else {
-    atomicOr(err, DCEM_ERR_CAPTURES);
-  }
-}
-
 int cu_count(dcem_ctx* c) {
   if (c->n_cus == 0) {
     hipDeviceProp_t prop;
@@ -1000,7 +1013,7 @@ void launch_fibonacci(dcem_ctx* c) {
 // Trace all work items (all_rays) or those listed by the coherence pass.  The
 // persistent grid is sized for `expected` work items (any size is correct:
 // blocks drain a shared queue).
-int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) {
+int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps) {
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
@@ -1040,6 +1053,8 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) 
   a.caps = ptr<Capture>(c->caps[c->cur_caps]);
   a.cap_capacity = c->cap_capacity;
   a.err = c->err_dev;
+  a.prev_caps = ptr<Capture>(c->caps[c->cur_caps ^ 1]);
+  a.n_prev = all_rays ? 0u : n_prev_caps;
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
     const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;
@@ -1053,11 +1068,13 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected) 
   return 0;
 }
 
-void launch_reset_counters(dcem_ctx* c) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, c->cnt_dev);
+void launch_frame_begin(dcem_ctx* c, bool los) {
+  const int n_los = los ? c->n_tx * c->n_rx : 0;
+  hipLaunchKernelGGL(k_frame_begin, dim3((unsigned)std::max(1, (n_los + 255) / 256)), dim3(256), 0, c->stream,
+                     c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), n_los, c->cap_capacity, c->err_dev);
 }
 
-void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
+void launch_coherence(dcem_ctx* c) {
   const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
   uint32_t* cnt = c->cnt_dev;
   const int blocks = (int)std::min<int64_t>((n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 8);
@@ -1068,11 +1085,6 @@ void launch_coherence(dcem_ctx* c, uint32_t n_prev_caps) {
                      ptr<uint8_t>(c->ray_state), ptr<float4>(c->seg_o), ptr<float4>(c->seg_d),
                      ptr<int32_t>(c->face_log), ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, n_work,
                      1e-3f + c->pad, ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
-  const int prev = c->cur_caps ^ 1;
-  if (n_prev_caps == 0) return;
-  hipLaunchKernelGGL(k_filter_caps, dim3((n_prev_caps + 255) / 256), dim3(256), 0, c->stream,
-                     ptr<Capture>(c->caps[prev]), n_prev_caps, ptr<uint8_t>(c->invalid_flag),
-                     ptr<Capture>(c->caps[c->cur_caps]), cnt);
 }
 
 hipError_t build_ray_order(dcem_ctx* c) {
@@ -1090,12 +1102,6 @@ hipError_t build_ray_order(dcem_ctx* c) {
   if ((e = hipMemcpyAsync(n_dev, &n32, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
   if ((e = radix_sort_perm(c, key, 1, 32, n_dev, n, order, tmp, c->stream)) != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
-}
-
-void launch_los(dcem_ctx* c) {
-  const int n_pairs = c->n_tx * c->n_rx;
-  hipLaunchKernelGGL(k_los, dim3((n_pairs + 255) / 256), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                     c->cnt_dev, n_pairs, c->cap_capacity, c->err_dev);
 }
 
 }  // namespace dcem
