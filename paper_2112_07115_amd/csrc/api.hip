@@ -290,7 +290,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
                     &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
-                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4};
+                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4, &c->cross};
   for (DevBuf* b : bufs) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)

@@ -238,78 +238,194 @@ __device__ inline void store_box4(Slot4* sl, const float* lo, const float* hi) {
   sl->hx = hi[0]; sl->hy = hi[1]; sl->hz = hi[2];
 }
 
-// Bottom-up refit over a fixed topology.  One thread per leaf writes its padded
-// box into its parent's slot; the second thread to arrive at a node forms the
-// union and climbs on.  An internal node covers a contiguous range of sorted
-// leaves and is one end of it, so a node whose range lies inside this block's
-// 1024 leaves has both children here: its arrival counter lives in LDS and the
-// hand-off needs only workgroup-scope ordering.  Only nodes spanning several
-// blocks use device-wide counters (reset by their second arrival, so the next
-// refit needs no clearing).  Boxes are min/max of FP32 values: the result does
-// not depend on the order of arrival.  With `wide` (a refit of a collapsed
-// tree) every child box stored in a binary slot is also stored in the 4-wide
-// slot that holds it (slot4, -1 for boxes the 4-wide tree drops) and the leaf
-// thread writes its triangle to its slot, so no separate collapse is needed.
-__global__ __launch_bounds__(kRefitBlock) void k_refit(
-    const float* __restrict__ V, const int32_t* __restrict__ T, const int32_t* __restrict__ tri_face,
-    const int32_t* __restrict__ face_object, const int32_t* __restrict__ leaf_tri,
-    const int32_t* __restrict__ leaf_parent, const int2* __restrict__ range, Node* __restrict__ nodes,
-    uint32_t* __restrict__ cnt, float* __restrict__ root_box, int n, float pad, bool wide,
-    const int32_t* __restrict__ slot4, const int32_t* __restrict__ leaf_slot, Node4* __restrict__ nodes4,
-    Leaf* __restrict__ tri4) {
-  __shared__ uint32_t lcnt[kRefitBlock];
-  lcnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int b0 = blockIdx.x * kRefitBlock;
-  const int i = b0 + threadIdx.x;
-  if (i >= n) return;
-  const Leaf L = leaf_record(V, T, tri_face, face_object, leaf_tri[i]);
-  if (wide) tri4[leaf_slot[i]] = L;
-  float lo[3] = {fminf(L.v0.x, fminf(L.v1.x, L.v2.x)) - pad, fminf(L.v0.y, fminf(L.v1.y, L.v2.y)) - pad,
-                 fminf(L.v0.z, fminf(L.v1.z, L.v2.z)) - pad};
-  float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + pad,
-                 fmaxf(L.v0.z, fmaxf(L.v1.z, L.v2.z)) + pad};
-  if (n == 1) {   // the root holds the one leaf in both slots
-    store_slot(&nodes[0], 0, lo, hi);
-    store_slot(&nodes[0], 1, lo, hi);
-    if (wide) {
-      store_box4(&nodes4[0].s[0], lo, hi);
-      store_box4(&nodes4[0].s[1], lo, hi);
-      tri4[0] = L;
-      tri4[1] = L;
-    }
-    for (int k = 0; k < 3; ++k) { root_box[k] = lo[k]; root_box[3 + k] = hi[k]; }
+// Binary nodes whose leaf range spans several refit blocks ("cross" nodes):
+// listed once per build with their list index per node (-1 otherwise) and the
+// list index and slot of their parent (the parent of a cross node is one too).
+__global__ void k_cross_mark(const int2* __restrict__ range, int n_internal, int32_t* __restrict__ cross_index,
+                             int32_t* __restrict__ cross_list, uint32_t* __restrict__ n_cross) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_internal) return;
+  const int2 rg = range[i];
+  if (rg.x / kRefitBlock == rg.y / kRefitBlock) {
+    cross_index[i] = -1;
     return;
   }
-  int p2 = leaf_parent[i];
-  for (int guard = n; guard > 0; --guard) {   // depth < n in a sound tree
-    const int node = p2 >> 1, slot = p2 & 1;
-    store_slot(&nodes[node], slot, lo, hi);
-    if (wide) {
-      const int d = slot4[p2];
-      if (d >= 0) store_box4(&nodes4[d >> 2].s[d & 3], lo, hi);
-    }
-    const int2 rg = range[node];
-    float slo[3], shi[3];
-    if (rg.x >= b0 && rg.y < b0 + kRefitBlock) {
-      const uint32_t old = __hip_atomic_fetch_add(&lcnt[node - b0], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) return;
-      load_slot_wg(&nodes[node], slot ^ 1, slo, shi);
+  const uint32_t k = atomicAdd(n_cross, 1u);
+  cross_index[i] = (int32_t)k;
+  cross_list[k] = i;
+}
+
+__global__ void k_cross_parent(const Node* __restrict__ nodes, const int32_t* __restrict__ cross_index,
+                               const int32_t* __restrict__ cross_list, const uint32_t* __restrict__ n_cross,
+                               int n_internal, int32_t* __restrict__ cross_parent) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_internal || k >= (int)*n_cross) return;
+  const int p2 = nodes[cross_list[k]].c.z;
+  cross_parent[k] = p2 < 0 ? -1 : (cross_index[p2 >> 1] << 1) | (p2 & 1);
+}
+
+struct RefitArgs {
+  const float* V;
+  const int32_t* T;
+  const int32_t* tri_face;
+  const int32_t* face_object;
+  const int32_t* leaf_tri;
+  const int32_t* leaf_parent;
+  Node* nodes;
+  uint32_t* cnt;              // device-wide arrival counters (cross nodes, when not two-phase)
+  float* root_box;
+  int n;                      // leaves
+  int n_internal;
+  float pad;
+  bool wide;                  // also update the 4-wide tree
+  const int32_t* slot4;
+  const int32_t* leaf_slot;
+  Node4* nodes4;
+  Leaf* tri4;
+  const int32_t* cross_index; // [n_internal]
+  const int32_t* cross_list;  // [n_cross]
+  const int32_t* cross_parent;
+  uint32_t* entries;          // binary slots of cross nodes filled by the block pass
+  uint32_t* info;             // [2] cross nodes, [3] entries, [4] finished blocks
+};
+
+// A child box of binary node `p2 >> 1` (slot p2 & 1): in the binary tree and,
+// refitting a collapsed tree, in the 4-wide slot that holds it.
+__device__ inline void put_child_box(const RefitArgs& a, int p2, const float* lo, const float* hi) {
+  store_slot(&a.nodes[p2 >> 1], p2 & 1, lo, hi);
+  if (a.wide) {
+    const int d = a.slot4[p2];
+    if (d >= 0) store_box4(&a.nodes4[d >> 2].s[d & 3], lo, hi);
+  }
+}
+
+constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
+
+// Bottom-up refit over a fixed topology, in two passes of one kernel.
+// Block pass: one thread per leaf writes its padded box into its parent's
+// slot; the second thread to arrive at a node forms the union and climbs on.
+// An internal node covers a contiguous range of sorted leaves and is one end
+// of it, so a node whose range lies inside this block's 1024 leaves has both
+// children here: its boxes, arrival counter and parent link live in LDS.  A
+// thread stops at the first cross node (range spanning blocks), leaving its
+// box in that node's slot and the slot in a list.  Last-block pass: the last
+// block to finish finishes every cross node the same way in LDS, from the
+// listed slots up to the root.  (With more cross nodes than LDS holds, cross
+// nodes use device-wide arrival counters in the block pass instead.)  Boxes
+// are min/max of FP32 values: the result does not depend on the order of
+// arrival.  With `wide` (a refit of a collapsed tree) every child box stored
+// in a binary slot is also stored in the 4-wide slot that holds it and the leaf
+// thread writes its triangle to its slot, so no separate collapse is needed.
+__global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
+  // block pass: slot boxes, counters, parent links and cross flags of the
+  // block's nodes; last-block pass: the same for the cross nodes
+  __shared__ float lbox[kRefitBlock][12];
+  __shared__ uint32_t lcnt[kRefitBlock];
+  __shared__ int32_t lpar[kRefitBlock];
+  __shared__ int32_t lnode[kRefitBlock];
+  __shared__ bool last;
+  const int b0 = blockIdx.x * kRefitBlock;
+  const int tid = threadIdx.x;
+  const uint32_t n_cross = a.info[2];
+  const bool two_phase = n_cross <= (uint32_t)kMaxCross;
+  {
+    const int node = b0 + tid;
+    lcnt[tid] = 0;
+    const bool ok = node < a.n_internal;
+    lpar[tid] = ok ? a.nodes[node].c.z : -1;
+    lnode[tid] = ok && a.cross_index[node] < 0;   // block-local
+  }
+  __syncthreads();
+  const int i = b0 + tid;
+  if (i < a.n) {
+    const Leaf L = leaf_record(a.V, a.T, a.tri_face, a.face_object, a.leaf_tri[i]);
+    if (a.wide) a.tri4[a.leaf_slot[i]] = L;
+    float lo[3] = {fminf(L.v0.x, fminf(L.v1.x, L.v2.x)) - a.pad, fminf(L.v0.y, fminf(L.v1.y, L.v2.y)) - a.pad,
+                   fminf(L.v0.z, fminf(L.v1.z, L.v2.z)) - a.pad};
+    float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + a.pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + a.pad,
+                   fmaxf(L.v0.z, fmaxf(L.v1.z, L.v2.z)) + a.pad};
+    if (a.n == 1) {   // the root holds the one leaf in both slots
+      put_child_box(a, 0, lo, hi);
+      put_child_box(a, 1, lo, hi);
+      if (a.wide) a.tri4[1] = L;
+      for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
     } else {
-      const uint32_t old = __hip_atomic_fetch_add(&cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == 0) return;
-      cnt[node] = 0;
-      load_slot_coherent(&nodes[node], slot ^ 1, slo, shi);
+      int p2 = a.leaf_parent[i];
+      for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
+        const int node = p2 >> 1, slot = p2 & 1;
+        put_child_box(a, p2, lo, hi);
+        const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
+        float slo[3], shi[3];
+        if (local) {
+          float* bx = lbox[node - b0] + 6 * slot;
+          for (int k = 0; k < 3; ++k) { bx[k] = lo[k]; bx[3 + k] = hi[k]; }
+          const uint32_t old = __hip_atomic_fetch_add(&lcnt[node - b0], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (old == 0) break;
+          const float* sb = lbox[node - b0] + 6 * (slot ^ 1);
+          for (int k = 0; k < 3; ++k) { slo[k] = sb[k]; shi[k] = sb[3 + k]; }
+        } else if (two_phase) {
+          a.entries[atomicAdd(&a.info[3], 1u)] = (uint32_t)p2;
+          break;
+        } else {
+          const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          if (old == 0) break;
+          a.cnt[node] = 0;
+          load_slot_coherent(&a.nodes[node], slot ^ 1, slo, shi);
+        }
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = fminf(lo[k], slo[k]);
+          hi[k] = fmaxf(hi[k], shi[k]);
+        }
+        p2 = local ? lpar[node - b0] : a.nodes[node].c.z;
+        if (p2 < 0) {
+          for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
+          break;
+        }
+      }
     }
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = fminf(lo[k], slo[k]);
-      hi[k] = fmaxf(hi[k], shi[k]);
-    }
-    p2 = nodes[node].c.z;
-    if (p2 < 0) {
-      for (int k = 0; k < 3; ++k) { root_box[k] = lo[k]; root_box[3 + k] = hi[k]; }
-      return;
+  }
+  if (!two_phase || n_cross == 0) return;
+  // ---- the last block to finish completes the cross nodes
+  __syncthreads();
+  if (tid == 0)
+    last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
+    lcnt[k] = 0;
+    lpar[k] = a.cross_parent[k];
+    lnode[k] = a.cross_list[k];
+  }
+  __syncthreads();
+  if (tid == 0) {   // ready for the next refit
+    a.info[3] = 0;
+    a.info[4] = 0;
+  }
+  for (uint32_t e = tid; e < n_ent; e += kRefitBlock) {
+    const int p2 = (int)__hip_atomic_load(&a.entries[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int k = a.cross_index[p2 >> 1], slot = p2 & 1;
+    float lo[3], hi[3];
+    load_slot_coherent(&a.nodes[p2 >> 1], slot, lo, hi);
+    for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
+      float* bx = lbox[k] + 6 * slot;
+      for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
+      const uint32_t old = __hip_atomic_fetch_add(&lcnt[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      const float* sb = lbox[k] + 6 * (slot ^ 1);
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = fminf(lo[q], sb[q]);
+        hi[q] = fmaxf(hi[q], sb[3 + q]);
+      }
+      const int kp = lpar[k];
+      if (kp < 0) {
+        for (int q = 0; q < 3; ++q) { a.root_box[q] = lo[q]; a.root_box[3 + q] = hi[q]; }
+        break;
+      }
+      k = kp >> 1;
+      slot = kp & 1;
+      put_child_box(a, (lnode[k] << 1) | slot, lo, hi);
     }
   }
 }
@@ -528,6 +644,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->leaf_tri, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->leaf_parent, sizeof(int32_t) * nt)) != hipSuccess) return e;
   if ((e = ensure(c->refit_cnt, sizeof(uint32_t) * ni)) != hipSuccess) return e;
+  // cross-node index, list, parents and the listed slots of a refit
+  if ((e = ensure(c->cross, sizeof(int32_t) * 5 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
@@ -559,14 +677,24 @@ hipError_t build_lbvh(dcem_ctx* c) {
     if ((e = hipMemcpyAsync(c->nodes.p, &root, sizeof(Node), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
       return e;
     int32_t zero = 0, lp = 0;
+    const int2 rg = make_int2(0, 0);
     if ((e = hipMemcpyAsync(c->leaf_tri.p, &zero, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(c->leaf_parent.p, &lp, 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(c->node_range.p, &rg, sizeof rg, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, code, perm, (int)nt,
                        ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri),
                        ptr<int2>(c->node_range));
   }
+  uint32_t* info = ptr<uint32_t>(c->tree_info);
+  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, info + 2, 0u, info + 3, 0u);
+  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, info + 4, 0u, info + 4, 0u);
+  int32_t* cross = ptr<int32_t>(c->cross);
+  hipLaunchKernelGGL(k_cross_mark, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<int2>(c->node_range), ni,
+                     cross, cross + ni, info + 2);
+  hipLaunchKernelGGL(k_cross_parent, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), cross,
+                     cross + ni, info + 2, ni, cross + 2 * (size_t)ni);
   launch_refit(c, false);
   // 4-wide tree: binary nodes at even depth, breadth-first
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
@@ -597,12 +725,33 @@ void launch_collapse(dcem_ctx* c) {
 
 void launch_refit(dcem_ctx* c, bool wide) {
   if (c->nt == 0) return;
+  const int ni = c->n_internal;
+  int32_t* cross = ptr<int32_t>(c->cross);
+  RefitArgs a;
+  a.V = ptr<float>(c->vertices);
+  a.T = ptr<int32_t>(c->tris);
+  a.tri_face = ptr<int32_t>(c->tri_face);
+  a.face_object = ptr<int32_t>(c->face_object);
+  a.leaf_tri = ptr<int32_t>(c->leaf_tri);
+  a.leaf_parent = ptr<int32_t>(c->leaf_parent);
+  a.nodes = ptr<Node>(c->nodes);
+  a.cnt = ptr<uint32_t>(c->refit_cnt);
+  a.root_box = ptr<float>(c->scene_box);
+  a.n = (int)c->nt;
+  a.n_internal = ni;
+  a.pad = c->pad;
+  a.wide = wide;
+  a.slot4 = ptr<int32_t>(c->slot4);
+  a.leaf_slot = ptr<int32_t>(c->leaf_slot);
+  a.nodes4 = ptr<Node4>(c->nodes4);
+  a.tri4 = ptr<Leaf>(c->tri4);
+  a.cross_index = cross;
+  a.cross_list = cross + ni;
+  a.cross_parent = cross + 2 * (size_t)ni;
+  a.entries = reinterpret_cast<uint32_t*>(cross + 3 * (size_t)ni);
+  a.info = ptr<uint32_t>(c->tree_info);
   hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
-                     c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris), ptr<int32_t>(c->tri_face),
-                     ptr<int32_t>(c->face_object), ptr<int32_t>(c->leaf_tri), ptr<int32_t>(c->leaf_parent),
-                     ptr<int2>(c->node_range), ptr<Node>(c->nodes), ptr<uint32_t>(c->refit_cnt),
-                     ptr<float>(c->scene_box), (int)c->nt, c->pad, wide, ptr<int32_t>(c->slot4),
-                     ptr<int32_t>(c->leaf_slot), ptr<Node4>(c->nodes4), ptr<Leaf>(c->tri4));
+                     c->stream, a);
 }
 
 void launch_sah(dcem_ctx* c, double* out) {

@@ -125,7 +125,9 @@ struct dcem_ctx {
       node_range;
   dcem::DevBuf nodes4, bvh2_of4, map4, depth_key;   // 4-wide tree and its mapping from the binary one
   dcem::DevBuf slot4;                                // per binary child slot: the 4-wide slot holding its box, or -1
-  dcem::DevBuf tree_info;                            // uint32 [0]: number of 4-wide nodes, [1]: root leaf-slot mask
+  dcem::DevBuf cross;                                // refit: nodes spanning refit blocks (index, list, parents, slots)
+  dcem::DevBuf tree_info;                            // uint32 [0]: 4-wide nodes, [1]: root leaf-slot mask,
+                                                     // [2]: cross nodes, [3], [4]: refit list length and block ticket
   dcem::DevBuf tri4;                                 // leaf triangles in slot order (Leaf [n4][4])
 
   // -- rays and cache
