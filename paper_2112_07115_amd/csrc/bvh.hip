@@ -290,13 +290,10 @@ struct RefitArgs {
 };
 
 // A child box of binary node `p2 >> 1` (slot p2 & 1): in the binary tree and,
-// refitting a collapsed tree, in the 4-wide slot that holds it.
-__device__ inline void put_child_box(const RefitArgs& a, int p2, const float* lo, const float* hi) {
+// refitting a collapsed tree, in the 4-wide slot d that holds it (slot4[p2]).
+__device__ inline void put_child_box(const RefitArgs& a, int p2, int d, const float* lo, const float* hi) {
   store_slot(&a.nodes[p2 >> 1], p2 & 1, lo, hi);
-  if (a.wide) {
-    const int d = a.slot4[p2];
-    if (d >= 0) store_box4(&a.nodes4[d >> 2].s[d & 3], lo, hi);
-  }
+  if (a.wide && d >= 0) store_box4(&a.nodes4[d >> 2].s[d & 3], lo, hi);
 }
 
 constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
@@ -323,6 +320,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
   __shared__ uint32_t lcnt[kRefitBlock];
   __shared__ int32_t lpar[kRefitBlock];
   __shared__ int32_t lnode[kRefitBlock];
+  __shared__ int2 lslot4[kRefitBlock];   // the 4-wide slots of the node's two child boxes
   __shared__ bool last;
   const int b0 = blockIdx.x * kRefitBlock;
   const int tid = threadIdx.x;
@@ -334,6 +332,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
     const bool ok = node < a.n_internal;
     lpar[tid] = ok ? a.nodes[node].c.z : -1;
     lnode[tid] = ok && a.cross_index[node] < 0;   // block-local
+    if (a.wide && ok) lslot4[tid] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
   }
   __syncthreads();
   const int i = b0 + tid;
@@ -345,16 +344,25 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
     float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + a.pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + a.pad,
                    fmaxf(L.v0.z, fmaxf(L.v1.z, L.v2.z)) + a.pad};
     if (a.n == 1) {   // the root holds the one leaf in both slots
-      put_child_box(a, 0, lo, hi);
-      put_child_box(a, 1, lo, hi);
+      put_child_box(a, 0, 0, lo, hi);
+      put_child_box(a, 1, 1, lo, hi);
       if (a.wide) a.tri4[1] = L;
       for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
     } else {
       int p2 = a.leaf_parent[i];
       for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
         const int node = p2 >> 1, slot = p2 & 1;
-        put_child_box(a, p2, lo, hi);
         const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
+        int d = -1;
+        if (a.wide) {
+          if (local) {
+            const int2 ds = lslot4[node - b0];
+            d = slot ? ds.y : ds.x;
+          } else {
+            d = a.slot4[p2];
+          }
+        }
+        put_child_box(a, p2, d, lo, hi);
         float slo[3], shi[3];
         if (local) {
           float* bx = lbox[node - b0] + 6 * slot;
@@ -397,6 +405,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
     lcnt[k] = 0;
     lpar[k] = a.cross_parent[k];
     lnode[k] = a.cross_list[k];
+    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * lnode[k]], a.slot4[2 * lnode[k] + 1]);
   }
   __syncthreads();
   if (tid == 0) {   // ready for the next refit
@@ -425,7 +434,8 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
       }
       k = kp >> 1;
       slot = kp & 1;
-      put_child_box(a, (lnode[k] << 1) | slot, lo, hi);
+      const int2 ds = a.wide ? lslot4[k] : make_int2(-1, -1);
+      put_child_box(a, (lnode[k] << 1) | slot, slot ? ds.y : ds.x, lo, hi);
     }
   }
 }
