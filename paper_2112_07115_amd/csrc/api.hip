@@ -473,8 +473,7 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
     HIP_TRY(build_lbvh(c), "rebuild BVH");
     rb = 1;
   } else {
-    launch_refit(c, true);
-    launch_sah(c, c->sah_dev + 1);
+    launch_refit(c, true, c->sah_dev + 1);
     HIP_TRY(hipGetLastError(), "refit kernel");
     c->refit_since_build = true;
   }

@@ -264,6 +264,27 @@ __global__ void k_cross_parent(const Node* __restrict__ nodes, const int32_t* __
   cross_parent[k] = p2 < 0 ? -1 : (cross_index[p2 >> 1] << 1) | (p2 & 1);
 }
 
+__device__ inline double box_area(const float* lo, const float* hi) {
+  double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+  return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+// Unit normal n and offset n . a of the plane of face f (FP64, from the
+// face's reference triangle a, b, c: n = (b - a) x (c - a) normalised).
+__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
+                                  double4* __restrict__ plane, int f) {
+  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
+  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
+  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
+  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
+  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+  const double l = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= l;
+  ny /= l;
+  nz /= l;
+  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
+}
+
 struct RefitArgs {
   const float* V;
   const int32_t* T;
@@ -287,6 +308,11 @@ struct RefitArgs {
   const int32_t* cross_parent;
   uint32_t* entries;          // binary slots of cross nodes filled by the block pass
   uint32_t* info;             // [2] cross nodes, [3] entries, [4] finished blocks
+  double* part;               // per-block surface-area sums
+  double* sah_out;            // SAH ratio of the refitted tree
+  const int32_t* face_ref_tri;
+  int nf;
+  double4* plane;             // per face: unit normal and offset
 };
 
 // A child box of binary node `p2 >> 1` (slot p2 & 1): in the binary tree and,
@@ -297,6 +323,48 @@ __device__ inline void put_child_box(const RefitArgs& a, int p2, int d, const fl
 }
 
 constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
+
+// Last-block pass of the refit: finish the cross nodes in LDS, from the slots
+// the block pass listed up to the root.
+__device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t n_cross, float (*lbox)[12], uint32_t* lcnt,
+                                   int32_t* lpar, int32_t* lnode, int2* lslot4) {
+  const int tid = threadIdx.x;
+  const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
+    lcnt[k] = 0;
+    lpar[k] = a.cross_parent[k];
+    lnode[k] = a.cross_list[k];
+    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * lnode[k]], a.slot4[2 * lnode[k] + 1]);
+  }
+  __syncthreads();
+  if (tid == 0) a.info[3] = 0;   // ready for the next refit
+  for (uint32_t e = tid; e < n_ent; e += kRefitBlock) {
+    const int p2 = (int)__hip_atomic_load(&a.entries[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int k = a.cross_index[p2 >> 1], slot = p2 & 1;
+    float lo[3], hi[3];
+    load_slot_coherent(&a.nodes[p2 >> 1], slot, lo, hi);
+    for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
+      float* bx = lbox[k] + 6 * slot;
+      for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
+      const uint32_t old = __hip_atomic_fetch_add(&lcnt[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      const float* sb = lbox[k] + 6 * (slot ^ 1);
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = fminf(lo[q], sb[q]);
+        hi[q] = fmaxf(hi[q], sb[3 + q]);
+      }
+      const int kp = lpar[k];
+      if (kp < 0) {
+        for (int q = 0; q < 3; ++q) { a.root_box[q] = lo[q]; a.root_box[3 + q] = hi[q]; }
+        break;
+      }
+      k = kp >> 1;
+      slot = kp & 1;
+      const int2 ds = a.wide ? lslot4[k] : make_int2(-1, -1);
+      put_child_box(a, (lnode[k] << 1) | slot, slot ? ds.y : ds.x, lo, hi);
+    }
+  }
+}
 
 // Bottom-up refit over a fixed topology, in two passes of one kernel.
 // Block pass: one thread per leaf writes its padded box into its parent's
@@ -313,6 +381,10 @@ constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last blo
 // arrival.  With `wide` (a refit of a collapsed tree) every child box stored
 // in a binary slot is also stored in the 4-wide slot that holds it and the leaf
 // thread writes its triangle to its slot, so no separate collapse is needed.
+// The same kernel measures the tree: the surface areas of the internal nodes
+// below the root (each node's internal children), summed per block in a fixed
+// order and over blocks by the last block, over the root's area (sah_out); and
+// it computes every face's plane (used by the refinement's image method).
 __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
   // block pass: slot boxes, counters, parent links and cross flags of the
   // block's nodes; last-block pass: the same for the cross nodes
@@ -321,7 +393,11 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
   __shared__ int32_t lpar[kRefitBlock];
   __shared__ int32_t lnode[kRefitBlock];
   __shared__ int2 lslot4[kRefitBlock];   // the 4-wide slots of the node's two child boxes
+  __shared__ int2 lkid[kRefitBlock];     // child entries (>= 0: internal)
+  __shared__ double red[kRefitBlock];
   __shared__ bool last;
+  for (int f = blockIdx.x * kRefitBlock + threadIdx.x; f < a.nf; f += gridDim.x * kRefitBlock)
+    face_plane(a.V, a.T, a.face_ref_tri[f], a.plane, f);
   const int b0 = blockIdx.x * kRefitBlock;
   const int tid = threadIdx.x;
   const uint32_t n_cross = a.info[2];
@@ -332,6 +408,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
     const bool ok = node < a.n_internal;
     lpar[tid] = ok ? a.nodes[node].c.z : -1;
     lnode[tid] = ok && a.cross_index[node] < 0;   // block-local
+    lkid[tid] = ok ? make_int2(a.nodes[node].c.x, a.nodes[node].c.y) : make_int2(-1, -1);
     if (a.wide && ok) lslot4[tid] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
   }
   __syncthreads();
@@ -393,120 +470,69 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
       }
     }
   }
-  if (!two_phase || n_cross == 0) return;
-  // ---- the last block to finish completes the cross nodes
   __syncthreads();
-  if (tid == 0)
-    last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
-    lcnt[k] = 0;
-    lpar[k] = a.cross_parent[k];
-    lnode[k] = a.cross_list[k];
-    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * lnode[k]], a.slot4[2 * lnode[k] + 1]);
-  }
-  __syncthreads();
-  if (tid == 0) {   // ready for the next refit
-    a.info[3] = 0;
-    a.info[4] = 0;
-  }
-  for (uint32_t e = tid; e < n_ent; e += kRefitBlock) {
-    const int p2 = (int)__hip_atomic_load(&a.entries[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int k = a.cross_index[p2 >> 1], slot = p2 & 1;
-    float lo[3], hi[3];
-    load_slot_coherent(&a.nodes[p2 >> 1], slot, lo, hi);
-    for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
-      float* bx = lbox[k] + 6 * slot;
-      for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
-      const uint32_t old = __hip_atomic_fetch_add(&lcnt[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) break;
-      const float* sb = lbox[k] + 6 * (slot ^ 1);
-      for (int q = 0; q < 3; ++q) {
-        lo[q] = fminf(lo[q], sb[q]);
-        hi[q] = fmaxf(hi[q], sb[3 + q]);
-      }
-      const int kp = lpar[k];
-      if (kp < 0) {
-        for (int q = 0; q < 3; ++q) { a.root_box[q] = lo[q]; a.root_box[3 + q] = hi[q]; }
-        break;
-      }
-      k = kp >> 1;
-      slot = kp & 1;
-      const int2 ds = a.wide ? lslot4[k] : make_int2(-1, -1);
-      put_child_box(a, (lnode[k] << 1) | slot, slot ? ds.y : ds.x, lo, hi);
+  // areas of the internal children of this block's local nodes
+  {
+    double ar = 0.0;
+    if (lnode[tid]) {
+      if (lkid[tid].x >= 0) ar += box_area(lbox[tid], lbox[tid] + 3);
+      if (lkid[tid].y >= 0) ar += box_area(lbox[tid] + 6, lbox[tid] + 9);
     }
-  }
-}
-
-__device__ inline double box_area(const float* lo, const float* hi) {
-  double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
-  return 2.0 * (dx * dy + dy * dz + dz * dx);
-}
-
-// Unit normal n and offset n . a of the plane of face f (FP64, from the
-// face's reference triangle a, b, c: n = (b - a) x (c - a) normalised).
-__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
-                                  double4* __restrict__ plane, int f) {
-  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
-  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
-  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
-  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
-  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
-  const double l = sqrt(nx * nx + ny * ny + nz * nz);
-  nx /= l;
-  ny /= l;
-  nz /= l;
-  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
-}
-
-// After a build or refit: the plane of every face (the refinement's image
-// method reflects through them), and the surface-area sum of the internal
-// nodes below the root (each stored in its parent's slot) over the root's
-// area.  Per-block partial sums; the last block to finish (ticket counter,
-// left at zero) adds them in a fixed order.
-__global__ void k_sah(const Node* __restrict__ nodes, int n_internal, const float* __restrict__ root,
-                      double* __restrict__ part, uint32_t* __restrict__ ticket, double* __restrict__ out,
-                      const float* __restrict__ V, const int32_t* __restrict__ T,
-                      const int32_t* __restrict__ face_ref_tri, int nf, double4* __restrict__ plane) {
-  __shared__ double red[256];
-  __shared__ bool last;
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x)
-    face_plane(V, T, face_ref_tri[f], plane, f);
-  double s = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_internal; i += gridDim.x * blockDim.x) {
-    const float* f = reinterpret_cast<const float*>(&nodes[i]);
-    const int c0 = nodes[i].c.x, c1 = nodes[i].c.y;
-    if (c0 >= 0) s += box_area(f, f + 3);
-    if (c1 >= 0) s += box_area(f + 6, f + 9);
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    red[tid] = ar;
+    __syncthreads();
+    for (int k = kRefitBlock / 2; k > 0; k >>= 1) {
+      if (tid < k) red[tid] += red[tid + k];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      __hip_atomic_store(&a.part[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&part[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
-  }
+  if (!last) return;
+  // ---- the last block to finish completes the cross nodes and the SAH sum
+  if (tid == 0) a.info[4] = 0;   // ready for the next refit
+  if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4);
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  double t = 0.0;
-  for (unsigned b = 0; b < gridDim.x; ++b) t += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  *ticket = 0;
-  const float lo[3] = {root[0], root[1], root[2]}, hi[3] = {root[3], root[4], root[5]};
-  const double ar = box_area(lo, hi);
-  out[0] = ar > 0 ? (t + ar) / ar : 1.0;
+  double ar = 0.0;
+  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
+    const int node = a.cross_list[k];
+    float lo[3], hi[3];
+    if (a.nodes[node].c.x >= 0) {
+      load_slot_coherent(&a.nodes[node], 0, lo, hi);
+      ar += box_area(lo, hi);
+    }
+    if (a.nodes[node].c.y >= 0) {
+      load_slot_coherent(&a.nodes[node], 1, lo, hi);
+      ar += box_area(lo, hi);
+    }
+  }
+  red[tid] = ar;
+  __syncthreads();
+  for (int k = kRefitBlock / 2; k > 0; k >>= 1) {
+    if (tid < k) red[tid] += red[tid + k];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  double t = red[0];
+  for (unsigned b = 0; b < gridDim.x; ++b) t += __hip_atomic_load(&a.part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float rlo[3], rhi[3];
+  for (int q = 0; q < 3; ++q) {
+    rlo[q] = __hip_atomic_load(&a.root_box[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rhi[q] = __hip_atomic_load(&a.root_box[3 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const double root = box_area(rlo, rhi);
+  *a.sah_out = root > 0 ? (t + root) / root : 1.0;
 }
 
-constexpr int kSahBlocks = 64;
 
-// scene_box layout: root box (6 floats, 2 spare), the SAH per-block sums, then
-// the SAH ticket counter.
+
+
+
+// scene_box layout: root box (6 floats, 2 spare), then the refit blocks'
+// surface-area sums.
 double* sah_parts(dcem_ctx* c) { return reinterpret_cast<double*>(ptr<char>(c->scene_box) + 8 * sizeof(float)); }
-uint32_t* sah_ticket(dcem_ctx* c) { return reinterpret_cast<uint32_t*>(sah_parts(c) + kSahBlocks); }
 
 // Depth of each binary internal node (steps to the root) as a sort key: nodes
 // at even depth become 4-wide nodes and are ordered by (depth, index), i.e.
@@ -658,7 +684,8 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->cross, sizeof(int32_t) * 5 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
   if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
-  if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (kSahBlocks + 2))) != hipSuccess) return e;
+  const int64_t refit_blocks = (nt + kRefitBlock - 1) / kRefitBlock;
+  if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (refit_blocks + 2))) != hipSuccess) return e;
   // one spare node: the re-trace reads 48 bytes from a 32-byte slot
   if ((e = ensure(c->nodes4, sizeof(Node4) * (ni + 1))) != hipSuccess) return e;
   if ((e = ensure(c->tri4, sizeof(Leaf) * 4 * (size_t)ni)) != hipSuccess) return e;
@@ -679,8 +706,6 @@ hipError_t build_lbvh(dcem_ctx* c) {
                      ptr<int32_t>(c->tris), nt, nbox, code);
   if ((e = radix_sort_perm(c, code, 1, 30, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
-  uint32_t* ticket = sah_ticket(c);
-  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, ticket, 0u, ticket, 0u);
   if (nt == 1) {
     Node root{};
     root.c = make_int4(~0, ~0, -1, 0);
@@ -705,7 +730,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
                      cross, cross + ni, info + 2);
   hipLaunchKernelGGL(k_cross_parent, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), cross,
                      cross + ni, info + 2, ni, cross + 2 * (size_t)ni);
-  launch_refit(c, false);
+  launch_refit(c, false, c->sah_dev + 0);
   // 4-wide tree: binary nodes at even depth, breadth-first
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
   uint32_t* dperm = dkey + ni;
@@ -718,7 +743,6 @@ hipError_t build_lbvh(dcem_ctx* c) {
   hipLaunchKernelGGL(k_map4, dim3((ni + 255) / 256), dim3(256), 0, c->stream, dperm, n4, ni,
                      ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4));
   launch_collapse(c);
-  launch_sah(c, c->sah_dev + 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   c->has_bvh = true;
   return hipSuccess;
@@ -733,7 +757,7 @@ void launch_collapse(dcem_ctx* c) {
                      ptr<Leaf>(c->tri4), ptr<int32_t>(c->leaf_slot), ptr<int32_t>(c->slot4));
 }
 
-void launch_refit(dcem_ctx* c, bool wide) {
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
   if (c->nt == 0) return;
   const int ni = c->n_internal;
   int32_t* cross = ptr<int32_t>(c->cross);
@@ -760,15 +784,14 @@ void launch_refit(dcem_ctx* c, bool wide) {
   a.cross_parent = cross + 2 * (size_t)ni;
   a.entries = reinterpret_cast<uint32_t*>(cross + 3 * (size_t)ni);
   a.info = ptr<uint32_t>(c->tree_info);
+  a.part = sah_parts(c);
+  a.sah_out = sah_out;
+  a.face_ref_tri = ptr<int32_t>(c->face_ref_tri);
+  a.nf = c->nf;
+  a.plane = ptr<double4>(c->face_plane);
   hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
                      c->stream, a);
 }
 
-void launch_sah(dcem_ctx* c, double* out) {
-  if (c->nt == 0) return;
-  hipLaunchKernelGGL(k_sah, dim3(kSahBlocks), dim3(256), 0, c->stream, ptr<Node>(c->nodes), c->n_internal,
-                     ptr<float>(c->scene_box), sah_parts(c), sah_ticket(c), out, ptr<float>(c->vertices),
-                     ptr<int32_t>(c->tris), ptr<int32_t>(c->face_ref_tri), c->nf, ptr<double4>(c->face_plane));
-}
 
 }  // namespace dcem

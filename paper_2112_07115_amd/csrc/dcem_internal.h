@@ -208,10 +208,10 @@ T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
 // Transform the moving objects' vertices by xf ([n_objects][3][4], device).
 void launch_xform(dcem_ctx* c, const float* xf);
 hipError_t build_lbvh(dcem_ctx* c);
-// Refit the binary tree; `wide` also updates the 4-wide tree in place (no collapse needed).
-void launch_refit(dcem_ctx* c, bool wide);
+// Refit the binary tree (`wide`: and the 4-wide tree in place, no collapse
+// needed), write the SAH ratio to sah_out and the face planes.
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out);
 void launch_collapse(dcem_ctx* c);
-void launch_sah(dcem_ctx* c, double* out);
 
 // ---- radix sort (sort.hip)
 // Stable LSD sort of n items by `bits` low bits of a multi-word key stored
