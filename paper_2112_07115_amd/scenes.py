@@ -380,6 +380,58 @@ def parallel_walls(tx, rx, x0: float = -10.0, x1: float = 10.0, half: float = 50
     return mb.finish("parallel_walls", [material], tx, rx, **kw)
 
 
+def box_field(n_static: int, n_moving: int, half: float = 200.0, seed: int = 5, n_frames: int = 4,
+              n_rays: int = 1 << 15, max_reflections: int = 3) -> Scene:
+    """Large or object-rich test scene: a ground plane with `n_static` concrete
+    boxes (sides U(1, 4) m, heights U(1, 12) m) and `n_moving` metal boxes
+    (2 x 1 x 1 m, 0.3 m clearance) at uniform positions in [-half, half]^2; the
+    moving boxes translate at U(-15, 15) m/s per axis.  Boxes are untessellated
+    (12 triangles, 6 faces each) and may overlap.  One Tx at 30 m, an 8 x 8
+    receiver grid at 1.5 m.  Built with array operations so that hundreds of
+    thousands of triangles stay cheap."""
+    rng = np.random.default_rng(seed)
+    unit = _MeshBuilder()
+    unit.add_box((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (1, 1, 1), 0)
+    uv, ut, uf = unit.verts[0].astype(np.float64), unit.tris[0], unit.tri_face[0]
+    n_box = n_static + n_moving
+    lo = np.zeros((n_box, 3))
+    size = np.zeros((n_box, 3))
+    lo[:, :2] = rng.uniform(-half, half, (n_box, 2))
+    size[:n_static, :2] = rng.uniform(1.0, 4.0, (n_static, 2))
+    size[:n_static, 2] = rng.uniform(1.0, 12.0, n_static)
+    size[n_static:] = (2.0, 1.0, 1.0)
+    lo[n_static:, 2] = 0.3
+    verts = (lo[:, None, :] + size[:, None, :] * uv[None, :, :]).astype(np.float32)   # [n_box, 8, 3]
+    nv_box = uv.shape[0]
+    tris = ut[None, :, :] + (np.arange(n_box) * nv_box)[:, None, None]
+    tri_face = uf[None, :] + (np.arange(n_box) * 6)[:, None]
+    g = 2.0 * half + 20.0
+    ground_v = np.array([[-g, -g, 0.0], [g, -g, 0.0], [g, g, 0.0], [-g, g, 0.0]], np.float32)
+    nvb = n_box * nv_box
+    all_v = np.concatenate([verts.reshape(-1, 3), ground_v])
+    all_t = np.concatenate([tris.reshape(-1, 3), np.array([[0, 1, 2], [0, 2, 3]]) + nvb]).astype(np.int32)
+    all_f = np.concatenate([tri_face.reshape(-1), [6 * n_box, 6 * n_box]]).astype(np.int32)
+    face_material = np.concatenate([np.zeros(6 * n_static), np.ones(6 * n_moving), [2]]).astype(np.int32)
+    face_object = np.concatenate([np.full(6 * n_static, -1), np.repeat(np.arange(n_moving), 6), [-1]]).astype(np.int32)
+    obj_range = np.stack([np.arange(n_static, n_box) * nv_box, np.arange(n_static + 1, n_box + 1) * nv_box], 1)
+    vel = rng.uniform(-15.0, 15.0, (n_moving, 2))
+    dt = 0.1
+
+    def transforms(frame: int) -> np.ndarray:
+        xf = identity_transforms(n_moving)
+        xf[:, 0, 3] = (vel[:, 0] * frame * dt).astype(np.float32)
+        xf[:, 1, 3] = (vel[:, 1] * frame * dt).astype(np.float32)
+        return xf
+
+    gx = np.linspace(-0.8 * half, 0.8 * half, 8)
+    rx = np.array([[x, y, 1.5] for x in gx for y in gx], np.float32)
+    return Scene(name="box_field", vertices=all_v, tris=all_t, tri_face=all_f, face_material=face_material,
+                 face_object=face_object, materials=np.array([CONCRETE, METAL, GROUND], np.float64),
+                 object_vertex_range=obj_range.astype(np.int64), tx=np.array([[0.0, 0.0, 30.0]], np.float32),
+                 rx=rx, rx_radius=0.5, n_rays=n_rays, max_reflections=max_reflections, n_frames=n_frames, dt=dt,
+                 transforms_fn=transforms)
+
+
 def random_sphere_dirs(n: int, seed: int) -> np.ndarray:
     """n random directions, uniform on the unit sphere (the paper's 'random sphere of rays')."""
     rng = np.random.default_rng(seed)
