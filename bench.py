@@ -36,9 +36,13 @@ def parse():
     return ap.parse_args()
 
 
-def run_mode(ctx, scene, mode, warmup, steps, n_rays, torch):
-    """Run warmup + steps frames; returns timing and per-frame outputs of the timed frames."""
+def run_mode(scene, mode, warmup, steps, n_rays, torch, instrumented):
+    """Warmup + steps frames on a fresh context; returns the wall time of the
+    timed frames, their powers and (instrumented: per-stage HIP event timings
+    on, per-frame statistics collected) their frame statistics."""
     from paper_2112_07115_amd import dcem
+    ctx = dcem.Context(0)
+    ctx.scene_upload(scene)
     nf = scene.n_frames
     coherent = mode == "coherent"
     # per-frame object transforms, resident on the GPU before timing starts
@@ -52,18 +56,20 @@ def run_mode(ctx, scene, mode, warmup, steps, n_rays, torch):
                         mode=dcem.MODE_COHERENT if coherent else dcem.MODE_FULL)
         return ctx.received_power()
 
+    ctx.set_timing(instrumented)
     for f in range(warmup):
         frame(f)
-    ctx.set_timing(True)
     outs, stats = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for f in range(warmup, warmup + steps):
         pc, _ = frame(f)
         outs.append(pc.copy())
-        stats.append(ctx.stats())
+        if instrumented:
+            stats.append(ctx.stats())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ctx.close()
     return dt, outs, stats
 
 
@@ -161,11 +167,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
     res = {}
+    # per mode: the timed run (no instrumentation: it gives `value`), then the
+    # same frames again on a fresh context with stage timings and statistics
     for mode in (["coherent", "full"] if args.mode == "both" else [args.mode]):
-        ctx = dcem.Context(0)
-        ctx.scene_upload(scene)
-        res[mode] = run_mode(ctx, scene, mode, args.warmup, args.steps, args.rays, torch)
-        ctx.close()
+        dt, outs, _ = run_mode(scene, mode, args.warmup, args.steps, args.rays, torch, False)
+        _, _, stats = run_mode(scene, mode, args.warmup, args.steps, args.rays, torch, True)
+        res[mode] = (dt, outs, stats)
     main_mode = "coherent" if "coherent" in res else "full"
     dt, outs, stats = res[main_mode]
     steps = args.steps
