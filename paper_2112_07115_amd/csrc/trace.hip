@@ -873,13 +873,17 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
       const int nseg = (int)(st & 0x0fu);
       const bool moving_hit = (st & 0x80u) != 0;
       // does the cached segment (o, d) meet a moving object's box now?
+      // Does the cached segment (o, d) meet a moving object's box now?  The
+      // answer only has to be conservative (a ray listed without need is traced
+      // again to the same result), so reciprocals are the hardware's (about one
+      // ulp) and every bound is widened by `margin`, far above those errors.
       auto meets_moving = [&](const float4& o, const float4& d) {
         // cull: the part of the segment inside the moving objects' z range, and
-        // its xy bounds (widened by `margin` so the cull never rejects a box
-        // the exact slab test below would accept)
+        // its xy bounds
         float s0 = 0.0f, s1 = o.w;
         if (d.z != 0.0f) {
-          const float a0 = (zlo - o.z) / d.z, a1 = (zhi - o.z) / d.z;
+          const float rz = __builtin_amdgcn_rcpf(d.z);
+          const float a0 = (zlo - o.z) * rz, a1 = (zhi - o.z) * rz;
           s0 = fmaxf(s0, fminf(a0, a1));
           s1 = fminf(s1, fmaxf(a0, a1));
         } else if (o.z < zlo || o.z > zhi) {
@@ -894,13 +898,13 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
         r.o = make_float3(o.x, o.y, o.z);
         r.d = make_float3(d.x, d.y, d.z);
         const float tiny = 1e-30f;
-        r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny),
-                            __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
-                            __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
+        r.inv = make_float3(__builtin_amdgcn_rcpf(r.d.x != 0.0f ? r.d.x : tiny),
+                            __builtin_amdgcn_rcpf(r.d.y != 0.0f ? r.d.y : tiny),
+                            __builtin_amdgcn_rcpf(r.d.z != 0.0f ? r.d.z : tiny));
         auto meets = [&](float lx, float ly, float lz, float hx, float hy, float hz) {
           if (hx < bx0 || lx > bx1 || hy < by0 || ly > by1) return false;
           float tn;
-          return slab(r, lx, ly, lz, hx, hy, hz, o.w, tn);
+          return slab(r, lx - margin, ly - margin, lz - margin, hx + margin, hy + margin, hz + margin, o.w, tn);
         };
         if (!grid) {
           for (int b = 0; b < n_obj; ++b) {
