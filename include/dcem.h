@@ -205,8 +205,13 @@ dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n
  * synchronising call.  rebuilt / sah_ratio (nullable, host) receive the
  * decision and the ratio it was based on (1.0 right after a rebuild).
  * Asynchronous on the context stream; device errors are reported by the next
- * synchronising call.  Rebuilding never changes traced results: hits are the
- * lexicographic minimum of (distance, triangle id) over conservative boxes. */
+ * synchronising call.  The build at scene upload and the rebuilds the quality
+ * test asks for put the static geometry and every moving object in subtrees
+ * of their own, so that refits under rigid motion keep the tree tight; a
+ * forced rebuild orders all triangles along one Morton curve, the better tree
+ * for a frame traced without refitting.  Rebuilding never changes traced
+ * results: hits are the lexicographic minimum of (distance, triangle id) over
+ * conservative boxes. */
 dcem_status dcem_refit_bvh(dcem_ctx* ctx, int32_t flags, double rebuild_threshold,
                            int32_t* rebuilt, double* sah_ratio);
 

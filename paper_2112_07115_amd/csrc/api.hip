@@ -424,7 +424,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   HIP_TRY(ensure(c->obj_box, sizeof(float) * 6 * std::max(c->no, 1)), "alloc object boxes");
   launch_xform(c, ptr<float>(c->xf));
   HIP_TRY(hipGetLastError(), "transform kernel");
-  HIP_TRY(build_lbvh(c), "build BVH");
+  HIP_TRY(build_lbvh(c, true), "build BVH");
   c->has_scene = true;
   c->cache_valid = false;
   c->has_frame = false;
@@ -470,7 +470,9 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   const double measured = c->pending_ratio;
   int32_t rb = 0;
   if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
-    HIP_TRY(build_lbvh(c), "rebuild BVH");
+    // a forced rebuild serves the frame at hand; one the quality test asks
+    // for keeps the objects apart for the refits that follow
+    HIP_TRY(build_lbvh(c, !(flags & DCEM_FORCE_REBUILD)), "rebuild BVH");
     rb = 1;
   } else {
     launch_refit(c, true, c->sah_dev + 1);

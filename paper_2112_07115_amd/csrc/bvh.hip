@@ -124,59 +124,121 @@ __device__ inline uint32_t spread10(uint32_t v) {
   return v;
 }
 
-// 30-bit Morton code of each centroid inside the centroid bounds.
-__global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
-                         const uint32_t* __restrict__ box, uint32_t* __restrict__ code) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nt) return;
-  float lo[3], ext[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = from_ordered(box[a]);
-    float h = from_ordered(box[3 + a]);
-    ext[a] = h > lo[a] ? h - lo[a] : 1.0f;
-  }
-  float3 a = load_v(V, T[3 * i]), b = load_v(V, T[3 * i + 1]), c = load_v(V, T[3 * i + 2]);
-  float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
-                (a.z + b.z + c.z) * (1.0f / 3.0f)};
+// 30-bit Morton code of point p inside the box (lo, lo + ext).
+__device__ inline uint32_t morton30(const float* p, const float* lo, const float* ext) {
   uint32_t q[3];
   for (int k = 0; k < 3; ++k) {
     float u = (p[k] - lo[k]) / ext[k];
     u = fminf(fmaxf(u, 0.0f), 1.0f);
     q[k] = (uint32_t)fminf(u * 1024.0f, 1023.0f);
   }
-  code[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
 }
 
-// Longest common prefix of sorted codes i and j (ties broken by index).
-__device__ inline int lcp(const uint32_t* __restrict__ code, const uint32_t* __restrict__ perm, int n, int i, int j) {
+__device__ inline void bounds_of(const uint32_t* box, float* lo, float* ext) {
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = from_ordered(box[a]);
+    const float h = from_ordered(box[3 + a]);
+    ext[a] = h > lo[a] ? h - lo[a] : 1.0f;
+  }
+}
+
+// Morton code of each moving object's box centre in the centroid bounds.
+__global__ void k_object_codes(const float* __restrict__ obj_box, int no, const uint32_t* __restrict__ box,
+                               uint32_t* __restrict__ ocode) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= no) return;
+  float lo[3], ext[3], p[3];
+  bounds_of(box, lo, ext);
+  for (int a = 0; a < 3; ++a) p[a] = 0.5f * (obj_box[6 * o + a] + obj_box[6 * o + 3 + a]);
+  ocode[o] = morton30(p, lo, ext);
+}
+
+// Rank of each moving object in the order of its code (ties by object id).
+__global__ void k_object_rank(const uint32_t* __restrict__ ocode, int no, int32_t* __restrict__ rank) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= no) return;
+  const uint32_t mine = ocode[o];
+  int r = 0;
+  for (int j = 0; j < no; ++j) {
+    const uint32_t cj = ocode[j];
+    r += (cj < mine || (cj == mine && j < o)) ? 1 : 0;
+  }
+  rank[o] = r;
+}
+
+// Sort key of each triangle.  Without moving objects: the 30-bit Morton code
+// of its centroid in the centroid bounds.  With them (key_hi non-null), a
+// prefix separates the static triangles (0) from each moving object's
+// (1 << rank_bits | rank of the object), and a moving triangle's Morton code is
+// taken in its object's box: the hierarchy built from these keys holds the
+// static geometry and every object in subtrees of their own, so rigid motion
+// leaves those subtrees tight under refitting.  Keys are stored as two words,
+// key_hi (bits 63..32) and key_lo (bits 31..0) of prefix << 30 | code.
+__global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
+                         const uint32_t* __restrict__ box, const int32_t* __restrict__ tri_face,
+                         const int32_t* __restrict__ face_object, const float* __restrict__ obj_box,
+                         const int32_t* __restrict__ rank, int rank_bits, uint32_t* __restrict__ key_hi,
+                         uint32_t* __restrict__ key_lo) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  float lo[3], ext[3];
+  bounds_of(box, lo, ext);
+  float3 a = load_v(V, T[3 * i]), b = load_v(V, T[3 * i + 1]), c = load_v(V, T[3 * i + 2]);
+  float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
+                (a.z + b.z + c.z) * (1.0f / 3.0f)};
+  const int obj = key_hi ? face_object[tri_face[i]] : -1;
+  uint32_t prefix = 0;
+  if (obj >= 0) {
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = obj_box[6 * obj + k];
+      const float h = obj_box[6 * obj + 3 + k];
+      ext[k] = h > lo[k] ? h - lo[k] : 1.0f;
+    }
+    prefix = (1u << rank_bits) | (uint32_t)rank[obj];
+  }
+  const uint32_t m = morton30(p, lo, ext);
+  if (key_hi) key_hi[i] = prefix >> 2;
+  key_lo[i] = (prefix << 30) | m;
+}
+
+// Longest common prefix of the sorted keys i and j (ties broken by index).
+__device__ inline int lcp(const uint32_t* __restrict__ key_hi, const uint32_t* __restrict__ key_lo,
+                          const uint32_t* __restrict__ perm, int n, int i, int j) {
   if (j < 0 || j >= n) return -1;
-  uint32_t a = code[perm[i]], b = code[perm[j]];
-  if (a != b) return __clz(a ^ b);
-  return 32 + __clz((uint32_t)(i ^ j));
+  const uint32_t pi = perm[i], pj = perm[j];
+  uint64_t a = key_lo[pi], b = key_lo[pj];
+  if (key_hi) {
+    a |= (uint64_t)key_hi[pi] << 32;
+    b |= (uint64_t)key_hi[pj] << 32;
+  }
+  if (a != b) return __clzll((long long)(a ^ b));
+  return 64 + __clz((uint32_t)(i ^ j));
 }
 
 // Hierarchy from the sorted Morton codes, one thread per internal node
 // (Karras, "Maximizing parallelism in the construction of BVHs", 2012).
-__global__ void k_karras(const uint32_t* __restrict__ code, const uint32_t* __restrict__ perm, int n,
+__global__ void k_karras(const uint32_t* __restrict__ key_hi, const uint32_t* __restrict__ key_lo,
+                         const uint32_t* __restrict__ perm, int n,
                          Node* __restrict__ nodes, int32_t* __restrict__ leaf_parent,
                          int32_t* __restrict__ leaf_tri, int2* __restrict__ range) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) leaf_tri[i] = (int32_t)perm[i];
   if (i >= n - 1) return;
-  int d = (lcp(code, perm, n, i, i + 1) - lcp(code, perm, n, i, i - 1)) >= 0 ? 1 : -1;
-  int dmin = lcp(code, perm, n, i, i - d);
+  int d = (lcp(key_hi, key_lo, perm, n, i, i + 1) - lcp(key_hi, key_lo, perm, n, i, i - 1)) >= 0 ? 1 : -1;
+  int dmin = lcp(key_hi, key_lo, perm, n, i, i - d);
   int lmax = 2;
-  while (lcp(code, perm, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  while (lcp(key_hi, key_lo, perm, n, i, i + lmax * d) > dmin) lmax <<= 1;
   int l = 0;
   for (int t = lmax >> 1; t >= 1; t >>= 1)
-    if (lcp(code, perm, n, i, i + (l + t) * d) > dmin) l += t;
+    if (lcp(key_hi, key_lo, perm, n, i, i + (l + t) * d) > dmin) l += t;
   int j = i + l * d;
-  int dnode = lcp(code, perm, n, i, j);
+  int dnode = lcp(key_hi, key_lo, perm, n, i, j);
   int s = 0;
   int t = l;
   do {
     t = (t + 1) >> 1;
-    if (lcp(code, perm, n, i, i + (s + t) * d) > dnode) s += t;
+    if (lcp(key_hi, key_lo, perm, n, i, i + (s + t) * d) > dnode) s += t;
   } while (t > 1);
   int gamma = i + s * d + min(d, 0);
   int lo = min(i, j), hi = max(i, j);
@@ -664,7 +726,7 @@ void launch_xform(dcem_ctx* c, const float* xf) {
 
 // Build the binary LBVH and its 4-wide collapse, entirely on the stream (no
 // host round trip).  The SAH sum ratio of the new tree goes to sah_dev[0].
-hipError_t build_lbvh(dcem_ctx* c) {
+hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   const int64_t nt = c->nt;
   hipError_t e;
   c->n_internal = nt > 1 ? (int32_t)(nt - 1) : (nt == 1 ? 1 : 0);
@@ -683,7 +745,12 @@ hipError_t build_lbvh(dcem_ctx* c) {
   // cross-node index, list, parents and the listed slots of a refit
   if ((e = ensure(c->cross, sizeof(int32_t) * 5 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
-  if ((e = ensure(c->morton, sizeof(uint32_t) * (3 * nt + 8))) != hipSuccess) return e;
+  // sort keys (two words with moving objects), permutation, scratch, bounds,
+  // then the objects' codes and ranks
+  const int key_words = separate_objects && c->no > 0 ? 2 : 1;
+  const int no = c->no;
+  if ((e = ensure(c->morton, sizeof(uint32_t) * ((key_words + 2) * nt + 8 + 2 * (size_t)no))) != hipSuccess)
+    return e;
   const int64_t refit_blocks = (nt + kRefitBlock - 1) / kRefitBlock;
   if ((e = ensure(c->scene_box, sizeof(float) * 8 + sizeof(double) * (refit_blocks + 2))) != hipSuccess) return e;
   // one spare node: the re-trace reads 48 bytes from a 32-byte slot
@@ -694,17 +761,31 @@ hipError_t build_lbvh(dcem_ctx* c) {
   if ((e = ensure(c->slot4, sizeof(int32_t) * 2 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->depth_key, sizeof(uint32_t) * (3 * (size_t)ni + 8))) != hipSuccess) return e;
   if ((e = ensure(c->tree_info, 64)) != hipSuccess) return e;
-  uint32_t* code = ptr<uint32_t>(c->morton);
-  uint32_t* perm = code + nt;
+  uint32_t* code = ptr<uint32_t>(c->morton);   // [key_words][nt]
+  uint32_t* key_hi = key_words == 2 ? code : nullptr;
+  uint32_t* key_lo = code + (key_words - 1) * (size_t)nt;
+  uint32_t* perm = code + key_words * (size_t)nt;
   uint32_t* perm_tmp = perm + nt;
   uint32_t* nbox = perm_tmp + nt;   // 6 ordered-bit words, then n
+  uint32_t* ocode = nbox + 8;
+  int32_t* orank = reinterpret_cast<int32_t*>(ocode + no);
+  int rank_bits = 1;
+  while ((1 << rank_bits) < no) ++rank_bits;
   hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox, (uint32_t)nt);
   const int nb = (int)std::min<int64_t>((nt + 255) / 256, 1024);
   hipLaunchKernelGGL(k_centroid_bounds, dim3(nb), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox);
+  if (key_words == 2) {
+    hipLaunchKernelGGL(k_object_codes, dim3((no + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->obj_box), no,
+                       nbox, ocode);
+    hipLaunchKernelGGL(k_object_rank, dim3((no + 255) / 256), dim3(256), 0, c->stream, ocode, no, orank);
+  }
   hipLaunchKernelGGL(k_morton, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
-                     ptr<int32_t>(c->tris), nt, nbox, code);
-  if ((e = radix_sort_perm(c, code, 1, 30, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess) return e;
+                     ptr<int32_t>(c->tris), nt, nbox, ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_object),
+                     ptr<float>(c->obj_box), orank, rank_bits, key_hi, key_lo);
+  const int key_bits = key_words == 2 ? 31 + rank_bits : 30;
+  if ((e = radix_sort_perm(c, code, key_words, key_bits, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess)
+    return e;
   if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
   if (nt == 1) {
     Node root{};
@@ -718,7 +799,7 @@ hipError_t build_lbvh(dcem_ctx* c) {
     if ((e = hipMemcpyAsync(c->node_range.p, &rg, sizeof rg, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, code, perm, (int)nt,
+    hipLaunchKernelGGL(k_karras, dim3((nt + 255) / 256), dim3(256), 0, c->stream, key_hi, key_lo, perm, (int)nt,
                        ptr<Node>(c->nodes), ptr<int32_t>(c->leaf_parent), ptr<int32_t>(c->leaf_tri),
                        ptr<int2>(c->node_range));
   }

@@ -207,7 +207,10 @@ T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }
 // ---- launchers (bvh.hip)
 // Transform the moving objects' vertices by xf ([n_objects][3][4], device).
 void launch_xform(dcem_ctx* c, const float* xf);
-hipError_t build_lbvh(dcem_ctx* c);
+// Build the binary and 4-wide trees.  `separate_objects`: every moving object
+// (and the static geometry) in a subtree of its own, for a tree that will be
+// refitted; otherwise one Morton order over all triangles.
+hipError_t build_lbvh(dcem_ctx* c, bool separate_objects);
 // Refit the binary tree (`wide`: and the 4-wide tree in place, no collapse
 // needed), write the SAH ratio to sah_out and the face planes.
 void launch_refit(dcem_ctx* c, bool wide, double* sah_out);

@@ -5,6 +5,7 @@
   counters for them): exact boxes, and the same hits as a rebuild.
 - More moving objects than the coherence pass bins on its grid (they are then
   tested one by one): coherent frames equal the full re-trace bitwise.
+- The build at upload keeps each moving object in a subtree of its own.
 """
 import sys
 
@@ -106,6 +107,24 @@ def test_large_scene_refit_equals_rebuild():
         log("frame", frame, "refit == rebuild")
     a.close()
     b.close()
+
+
+def test_upload_build_keeps_objects_in_own_subtrees():
+    """The build at upload gives every moving object (and the static geometry)
+    a subtree of its own: a node whose leaf range is exactly its triangles."""
+    s = scenes.dynamic_urban(n_rays=1 << 10)
+    ctx = dcem.Context(0)
+    ctx.scene_upload(s)
+    child, box, leaf = ctx.bvh()
+    lo, hi = leaf_ranges(child)
+    spans = set(zip(lo.tolist(), hi.tolist()))
+    tri_obj = s.face_object[s.tri_face][leaf]      # object of each sorted leaf (-1 static)
+    for o in range(-1, s.n_objects):
+        pos = np.flatnonzero(tri_obj == o)
+        assert pos.size and pos[-1] - pos[0] + 1 == pos.size, o
+        assert (int(pos[0]), int(pos[-1])) in spans, o
+    log("objects in own subtrees:", s.n_objects)
+    ctx.close()
 
 
 def test_many_moving_objects_coherent_equals_full():
