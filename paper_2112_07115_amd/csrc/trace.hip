@@ -814,6 +814,7 @@ constexpr int kCohGrid = 32;
 constexpr int kCohGridObjects = 256;
 constexpr int kCohMaxCells = 16;   // wider xy bounds test every box
 constexpr int kCohBatch = 5;       // cached segments loaded at once
+constexpr int kCohList = 4096;     // invalid rays a block collects before one list append
 
 __global__ __launch_bounds__(kCohBlock) void k_coherence(
     const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o, const float4* __restrict__ seg_d,
@@ -823,6 +824,11 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
   // dynamic LDS (grid mode): cell bits [cell][word], then the boxes [6][n_obj]
   extern __shared__ unsigned long long coh_lds[];
   __shared__ uint32_t ext[6];   // ordered bits: min x, min y, min z, max x, max y, max z
+  // the block's invalid rays, appended to the global list with one atomic at
+  // the end (a counter shared by every wavefront of the grid would serialise)
+  __shared__ uint32_t blist[kCohList];
+  __shared__ uint32_t bcount, bbase;
+  if (threadIdx.x == 0) bcount = 0;
   const bool grid = n_obj <= kCohGridObjects;
   const int words = (n_obj + 63) / 64;
   unsigned long long* cell = coh_lds;
@@ -958,11 +964,22 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
     }
     const bool bad = first != 255;
     const uint64_t m = __ballot(bad);
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(&counters[kCntWork], (uint32_t)__popcll(m));
-    base = __shfl(base, 0);
-    if (bad) list[base + __popcll(m & ((1ull << lane) - 1ull))] = w;
+    if (m) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&bcount, (uint32_t)__popcll(m));
+      base = __shfl(base, 0);
+      if (bad) {
+        const uint32_t p = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (p < kCohList) blist[p] = w;
+        else list[atomicAdd(&counters[kCntWork], 1u)] = w;   // only when a block is given more rays
+      }
+    }
   }
+  __syncthreads();
+  const uint32_t nb = min(bcount, (uint32_t)kCohList);
+  if (threadIdx.x == 0 && nb) bbase = atomicAdd(&counters[kCntWork], nb);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < nb; j += kCohBlock) list[bbase + j] = blist[j];
 }
 
 
@@ -1081,7 +1098,11 @@ void launch_frame_begin(dcem_ctx* c, bool los) {
 void launch_coherence(dcem_ctx* c) {
   const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
   uint32_t* cnt = c->cnt_dev;
-  const int blocks = (int)std::min<int64_t>((n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 8);
+  // four blocks per compute unit (each thread then checks several rays), and
+  // at most kCohList rays per block
+  const int blocks = (int)std::max<int64_t>(
+      std::min<int64_t>((n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 4),
+      (n_work + kCohList - 1) / kCohList);
   const size_t lds = c->no <= kCohGridObjects ? sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) +
                                                     sizeof(float) * 6 * c->no
                                               : 0;
