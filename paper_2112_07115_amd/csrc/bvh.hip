@@ -255,11 +255,16 @@ __global__ void k_karras(const uint32_t* __restrict__ key_hi, const uint32_t* __
   if (i == 0) nodes[0].c.z = -1;
 }
 
+// Binary slot 0 is floats 0-5 of the node (b0, b1.xy), slot 1 floats 6-11
+// (b1.zw, b2): two vector stores each.
 __device__ inline void store_slot(Node* nd, int slot, const float* lo, const float* hi) {
-  float* f = reinterpret_cast<float*>(nd);
-  const int base = slot * 6;
-  f[base + 0] = lo[0]; f[base + 1] = lo[1]; f[base + 2] = lo[2];
-  f[base + 3] = hi[0]; f[base + 4] = hi[1]; f[base + 5] = hi[2];
+  if (slot == 0) {
+    nd->b0 = make_float4(lo[0], lo[1], lo[2], hi[0]);
+    *reinterpret_cast<float2*>(&nd->b1.x) = make_float2(hi[1], hi[2]);
+  } else {
+    *reinterpret_cast<float2*>(&nd->b1.z) = make_float2(lo[0], lo[1]);
+    nd->b2 = make_float4(lo[2], hi[0], hi[1], hi[2]);
+  }
 }
 
 __device__ inline void load_slot_coherent(Node* nd, int slot, float* lo, float* hi) {
@@ -272,15 +277,6 @@ __device__ inline void load_slot_coherent(Node* nd, int slot, float* lo, float* 
 }
 
 constexpr int kRefitBlock = 1024;
-
-__device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
-  float* f = reinterpret_cast<float*>(nd);
-  const int base = slot * 6;
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-}
 
 // Leaf record of triangle `tri` (vertices; id, face and moving flag in w).
 __device__ inline Leaf leaf_record(const float* __restrict__ V, const int32_t* __restrict__ T,
@@ -296,8 +292,8 @@ __device__ inline Leaf leaf_record(const float* __restrict__ V, const int32_t* _
 }
 
 __device__ inline void store_box4(Slot4* sl, const float* lo, const float* hi) {
-  sl->lx = lo[0]; sl->ly = lo[1]; sl->lz = lo[2];
-  sl->hx = hi[0]; sl->hy = hi[1]; sl->hz = hi[2];
+  *reinterpret_cast<float3*>(&sl->lx) = make_float3(lo[0], lo[1], lo[2]);
+  *reinterpret_cast<float3*>(&sl->hx) = make_float3(hi[0], hi[1], hi[2]);
 }
 
 // Binary nodes whose leaf range spans several refit blocks ("cross" nodes):
@@ -386,17 +382,32 @@ __device__ inline void put_child_box(const RefitArgs& a, int p2, int d, const fl
 
 constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
 
+// Sum of v over the block (kRefitBlock threads), valid in thread 0, in a fixed
+// order: butterflies within each wavefront, then the wavefronts' sums in order.
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();   // red may still be read by an earlier sum
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kRefitBlock / kWave; ++w) t += red[w];
+  return t;
+}
+
 // Last-block pass of the refit: finish the cross nodes in LDS, from the slots
 // the block pass listed up to the root.
 __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t n_cross, float (*lbox)[12], uint32_t* lcnt,
-                                   int32_t* lpar, int32_t* lnode, int2* lslot4) {
+                                   int32_t* lpar, int32_t* lnode, int2* lslot4, int2* lkid) {
   const int tid = threadIdx.x;
   const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
     lcnt[k] = 0;
     lpar[k] = a.cross_parent[k];
-    lnode[k] = a.cross_list[k];
-    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * lnode[k]], a.slot4[2 * lnode[k] + 1]);
+    const int node = a.cross_list[k];
+    lnode[k] = node;
+    lkid[k] = make_int2(a.nodes[node].c.x, a.nodes[node].c.y);
+    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
   }
   __syncthreads();
   if (tid == 0) a.info[3] = 0;   // ready for the next refit
@@ -456,7 +467,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
   __shared__ int32_t lnode[kRefitBlock];
   __shared__ int2 lslot4[kRefitBlock];   // the 4-wide slots of the node's two child boxes
   __shared__ int2 lkid[kRefitBlock];     // child entries (>= 0: internal)
-  __shared__ double red[kRefitBlock];
+  __shared__ double red[kRefitBlock / kWave];
   __shared__ bool last;
   for (int f = blockIdx.x * kRefitBlock + threadIdx.x; f < a.nf; f += gridDim.x * kRefitBlock)
     face_plane(a.V, a.T, a.face_ref_tri[f], a.plane, f);
@@ -540,14 +551,9 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
       if (lkid[tid].x >= 0) ar += box_area(lbox[tid], lbox[tid] + 3);
       if (lkid[tid].y >= 0) ar += box_area(lbox[tid] + 6, lbox[tid] + 9);
     }
-    red[tid] = ar;
-    __syncthreads();
-    for (int k = kRefitBlock / 2; k > 0; k >>= 1) {
-      if (tid < k) red[tid] += red[tid + k];
-      __syncthreads();
-    }
+    ar = block_sum(ar, red);
     if (tid == 0) {
-      __hip_atomic_store(&a.part[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.part[blockIdx.x], ar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
     }
     __syncthreads();
@@ -555,10 +561,17 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
   if (!last) return;
   // ---- the last block to finish completes the cross nodes and the SAH sum
   if (tid == 0) a.info[4] = 0;   // ready for the next refit
-  if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4);
+  if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
   __syncthreads();
+  // areas of the cross nodes' internal children (in LDS after the two-phase
+  // pass, else in the binary nodes), plus the blocks' sums
   double ar = 0.0;
   for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
+    if (two_phase) {
+      if (lkid[k].x >= 0) ar += box_area(lbox[k], lbox[k] + 3);
+      if (lkid[k].y >= 0) ar += box_area(lbox[k] + 6, lbox[k] + 9);
+      continue;
+    }
     const int node = a.cross_list[k];
     float lo[3], hi[3];
     if (a.nodes[node].c.x >= 0) {
@@ -570,15 +583,10 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
       ar += box_area(lo, hi);
     }
   }
-  red[tid] = ar;
-  __syncthreads();
-  for (int k = kRefitBlock / 2; k > 0; k >>= 1) {
-    if (tid < k) red[tid] += red[tid + k];
-    __syncthreads();
-  }
+  for (unsigned b = tid; b < gridDim.x; b += kRefitBlock)
+    ar += __hip_atomic_load(&a.part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double t = block_sum(ar, red);
   if (tid != 0) return;
-  double t = red[0];
-  for (unsigned b = 0; b < gridDim.x; ++b) t += __hip_atomic_load(&a.part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   float rlo[3], rhi[3];
   for (int q = 0; q < 3; ++q) {
     rlo[q] = __hip_atomic_load(&a.root_box[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
