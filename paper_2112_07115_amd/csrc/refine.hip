@@ -79,157 +79,161 @@ __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32
   for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
 }
 
-// Whole de-duplication of a small capture list in one workgroup: keys, stable
-// LSD radix sort (8-bit digits, wavefront-ballot ranking), unique heads and
-// their compaction, all in LDS.  Used when n <= kSmallN and W <= kSmallW.
+// De-duplication of a small capture list (n <= kSmallN, read on the device)
+// without sorting passes.  A key's position in the stable sorted order is the
+// number of smaller keys plus the number of equal keys of lower capture index:
+// kRankLanes lanes count that for one key against all keys, held in LDS.  The
+// first key of each run of equal keys (no equal key of lower index) is a
+// unique candidate; a second kernel compacts their positions in sorted order.
+// The result equals a stable sort followed by run heads.
 constexpr int kSmallN = 2048;
 constexpr int kSmallW = 3;
-constexpr int kSmallThreads = 1024;
+constexpr int kRankBlock = 256;
+constexpr int kRankLanes = 32;
+constexpr int kRankItems = kRankBlock / kRankLanes;   // keys ranked per block
 
-__global__ __launch_bounds__(kSmallThreads) void k_small_dedupe(
+__global__ __launch_bounds__(256) void k_small_keys(
     const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, uint32_t capacity,
     const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos, uint32_t* __restrict__ n_unique,
-    uint32_t* __restrict__ fallback) {
-  __shared__ uint32_t key[kSmallW][kSmallN];
+    uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
   // the counter keeps counting past the buffer when captures overflow (the
   // trace kernel flags that); only the stored records are read
   const uint32_t n = min(*n_dev, capacity);
-  if (n > (uint32_t)kSmallN) {   // uniform: the host redoes this frame's candidates the exact way
-    if (threadIdx.x == 0) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > (uint32_t)kSmallN) {   // the host redoes this frame's candidates the exact way
+    if (i == 0) {
       *fallback = 1;
       *n_unique = 0;
     }
     return;
   }
-  __shared__ uint32_t pa[kSmallN], pb[kSmallN];
-  __shared__ uint32_t wcnt[kSmallThreads / kWave][256];
-  __shared__ uint32_t hist[256], running[256];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  constexpr int kW = kSmallThreads / kWave;
-  for (uint32_t i = tid; i < n; i += kSmallThreads) {
-    const Capture c = caps[i];
-    const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
-    const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
-    uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < L.K; ++j) {
-      uint32_t f = 0;
-      if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
-      put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
-    }
-    int pos = L.K * L.bf;
-    put_bits(w, L.W, pos, 4, order);
-    pos += 4;
-    put_bits(w, L.W, pos, L.br, rx);
-    pos += L.br;
-    put_bits(w, L.W, pos, L.bt, tx);
-    for (int k = 0; k < L.W; ++k) {
-      key[k][i] = w[k];
-      keys_out[k * (int64_t)kSmallN + i] = w[k];
-    }
-    pa[i] = i;
+  if (i >= n) return;
+  const Capture c = caps[i];
+  const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
+  const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
+  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < L.K; ++j) {
+    uint32_t f = 0;
+    if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
+    put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
+  }
+  int pos = L.K * L.bf;
+  put_bits(w, L.W, pos, 4, order);
+  pos += 4;
+  put_bits(w, L.W, pos, L.br, rx);
+  pos += L.br;
+  put_bits(w, L.W, pos, L.bt, tx);
+  for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
+}
+
+__global__ __launch_bounds__(kRankBlock) void k_small_rank(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, uint32_t capacity, int W,
+    uint32_t* __restrict__ perm_out, uint32_t* __restrict__ head) {
+  __shared__ uint32_t kk[kSmallW][kSmallN];
+  const uint32_t n = min(*n_dev, capacity);
+  if (n > (uint32_t)kSmallN) return;   // uniform: k_small_keys raised the fallback
+  const int tid = threadIdx.x;
+  const uint32_t first = blockIdx.x * kRankItems;
+  if (first < n) {
+    // all loads in flight at once, then the LDS stores
+    constexpr int kPer = kSmallN / kRankBlock;
+    uint32_t v[kSmallW][kPer];
+#pragma unroll
+    for (int k = 0; k < kSmallW; ++k)
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t j = tid + q * kRankBlock;
+        v[k][q] = k < W && j < n ? keys[k * (int64_t)kSmallN + j] : 0u;
+      }
+#pragma unroll
+    for (int k = 0; k < kSmallW; ++k)
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) kk[k][tid + q * kRankBlock] = v[k][q];
   }
   __syncthreads();
-  uint32_t* src = pa;
-  uint32_t* dst = pb;
-  const int passes = (L.bits + 7) / 8;
-  for (int p = 0; p < passes; ++p) {
-    const int word = L.W - 1 - (8 * p) / 32, shift = (8 * p) % 32;
-    if (tid < 256) hist[tid] = 0;
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(key[word][src[i]] >> shift) & 0xffu], 1u);
-    __syncthreads();
-    if (tid < kWave) {   // exclusive scan of the 256 digit counts: 4 per lane, then across lanes
-      const uint32_t h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
-      const uint32_t tot = h0 + h1 + h2 + h3;
-      uint32_t incl = tot;
-      for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t v = __shfl_up(incl, off);
-        if (tid >= off) incl += v;
+  const uint32_t i = first + tid / kRankLanes;
+  const uint32_t sub = tid % kRankLanes;
+  uint32_t less = 0, eq_before = 0;
+  if (i < n) {
+    uint32_t ki[kSmallW];
+    for (int k = 0; k < W; ++k) ki[k] = kk[k][i];
+    for (uint32_t j = sub; j < n; j += kRankLanes) {
+      int c = 0;   // sign of key j - key i, most significant word first
+      for (int k = 0; k < W && c == 0; ++k) {
+        const uint32_t v = kk[k][j];
+        c = v < ki[k] ? -1 : (v > ki[k] ? 1 : 0);
       }
-      const uint32_t base = incl - tot;
-      running[4 * tid] = base;
-      running[4 * tid + 1] = base + h0;
-      running[4 * tid + 2] = base + h0 + h1;
-      running[4 * tid + 3] = base + h0 + h1 + h2;
+      less += c < 0 ? 1u : 0u;
+      eq_before += (c == 0 && j < i) ? 1u : 0u;
     }
-    __syncthreads();
-    for (uint32_t base = 0; base < n; base += kSmallThreads) {
-      for (int w = 0; w < kW; ++w)
-        if (tid < 256) wcnt[w][tid] = 0;
-      __syncthreads();
-      const uint32_t i = base + tid;
-      const bool valid = i < n;
-      uint32_t idx = 0, d = 0;
-      if (valid) {
-        idx = src[i];
-        d = (key[word][idx] >> shift) & 0xffu;
-      }
-      uint64_t peers = __ballot(valid);
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      const uint64_t below = peers & ((1ull << lane) - 1ull);
-      if (valid && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = running[d] + (uint32_t)__popcll(below);
-        for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-        dst[pos] = idx;
-      }
-      __syncthreads();
-      if (tid < 256) {
-        uint32_t add = 0;
-        for (int w = 0; w < kW; ++w) add += wcnt[w][tid];
-        running[tid] += add;
-      }
-      __syncthreads();
-    }
-    uint32_t* t = src;
-    src = dst;
-    dst = t;
   }
-  // unique heads of the sorted keys, compacted in order (chunks of 2 per thread)
-  constexpr int kPer = kSmallN / kSmallThreads;
+  for (int off = kRankLanes / 2; off > 0; off >>= 1) {
+    less += __shfl_xor(less, off);
+    eq_before += __shfl_xor(eq_before, off);
+  }
+  if (i < n && sub == 0) {
+    const uint32_t r = less + eq_before;
+    perm_out[r] = i;
+    head[r] = eq_before == 0 ? 1u : 0u;
+  }
+}
+
+// Positions of the run heads in sorted order (one block).
+__global__ __launch_bounds__(kRankBlock) void k_small_heads(const uint32_t* __restrict__ n_dev, uint32_t capacity,
+                                                            const uint32_t* __restrict__ head,
+                                                            uint32_t* __restrict__ uniq_pos,
+                                                            uint32_t* __restrict__ n_unique) {
+  __shared__ uint32_t wsum[kRankBlock / kWave + 1];
+  const uint32_t n = min(*n_dev, capacity);
+  if (n > (uint32_t)kSmallN) return;   // uniform: k_small_keys raised the fallback
+  constexpr int kPer = kSmallN / kRankBlock;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   uint32_t flags = 0, cnt = 0;
   for (int q = 0; q < kPer; ++q) {
-    const uint32_t i = tid * kPer + q;
-    bool h = false;
-    if (i < n) {
-      h = i == 0;
-      for (int k = 0; k < L.W && !h; ++k) h = key[k][src[i]] != key[k][src[i - 1]];
-    }
+    const uint32_t p = tid * kPer + q;
+    const bool h = p < n && head[p] != 0;
     flags |= (h ? 1u : 0u) << q;
     cnt += h ? 1u : 0u;
   }
-  // exclusive scan of cnt over the block (hist/running reused as scratch per wave)
   uint32_t incl = cnt;
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t v = __shfl_up(incl, off);
     if (lane >= off) incl += v;
   }
-  if (lane == kWave - 1) hist[wave] = incl;
+  if (lane == kWave - 1) wsum[wave] = incl;
   __syncthreads();
   if (tid == 0) {
     uint32_t run = 0;
-    for (int w = 0; w < kW; ++w) {
-      const uint32_t v = hist[w];
-      hist[w] = run;
+    for (int w = 0; w < kRankBlock / kWave; ++w) {
+      const uint32_t v = wsum[w];
+      wsum[w] = run;
       run += v;
     }
-    hist[kW] = run;
+    wsum[kRankBlock / kWave] = run;
   }
   __syncthreads();
-  uint32_t off = hist[wave] + incl - cnt;
+  uint32_t o = wsum[wave] + incl - cnt;
   for (int q = 0; q < kPer; ++q)
-    if ((flags >> q) & 1u) uniq_pos[off++] = tid * kPer + q;
-  for (uint32_t i = tid; i < n; i += kSmallThreads) perm_out[i] = src[i];
+    if ((flags >> q) & 1u) uniq_pos[o++] = tid * kPer + q;
   if (tid == 0) {
-    *n_unique = hist[kW];
-    uniq_pos[hist[kW]] = n;
+    const uint32_t nu = wsum[kRankBlock / kWave];
+    *n_unique = nu;
+    uniq_pos[nu] = n;
   }
+}
+
+// De-duplication of a small list: keys, ranks, run heads.
+void launch_small_dedupe(dcem_ctx* c, const KeyLayout& L, int64_t n_work) {
+  uint32_t* cnt = c->cnt_dev;
+  hipLaunchKernelGGL(k_small_keys, dim3(kSmallN / 256), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
+                     cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
+                     ptr<uint32_t>(c->cand_keys), cnt + kCntUnique, cnt + kCntFallback);
+  hipLaunchKernelGGL(k_small_rank, dim3(kSmallN / kRankItems), dim3(kRankBlock), 0, c->stream,
+                     ptr<uint32_t>(c->cand_keys), cnt + kCntCaptures, (uint32_t)c->cap_capacity, L.W,
+                     ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->cand_tmp));
+  hipLaunchKernelGGL(k_small_heads, dim3(1), dim3(kRankBlock), 0, c->stream, cnt + kCntCaptures,
+                     (uint32_t)c->cap_capacity, ptr<uint32_t>(c->cand_tmp), ptr<uint32_t>(c->uniq_idx),
+                     cnt + kCntUnique);
 }
 
 __global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
@@ -742,14 +746,11 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+    if ((e = ensure(c->cand_tmp, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     c->key_stride = kSmallN;
     c->path_cap = kSmallN;
     c->small_path = true;
-    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                       cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
-                       ptr<uint32_t>(c->cand_keys),
-                       ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
-                       cnt + kCntFallback);
+    launch_small_dedupe(c, L, n_work);
     return hipGetLastError();
   }
   c->small_path = false;
@@ -764,12 +765,9 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+    if ((e = ensure(c->cand_tmp, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     c->key_stride = kSmallN;
-    hipLaunchKernelGGL(k_small_dedupe, dim3(1), dim3(kSmallThreads), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                       cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
-                       ptr<uint32_t>(c->cand_keys),
-                       ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
-                       cnt + kCntFallback);
+    launch_small_dedupe(c, L, n_work);
     return hipGetLastError();
   }
   c->key_stride = n;
