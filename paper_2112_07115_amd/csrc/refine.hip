@@ -389,9 +389,10 @@ struct RefineArgs {
   uint32_t* err;
 };
 
-// Is point p inside face f (inclusive)?  2D edge functions on the plane
-// projection that drops the normal's dominant axis.
-__device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
+// Is point p inside one of the triangles k0, k0 + step, ... of face f
+// (inclusive)?  2D edge functions on the plane projection that drops the
+// normal's dominant axis.  (k0 = 0, step = 1: inside the face.)
+__device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n, int k0 = 0, int step = 1) {
   const double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
   const int drop = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
   auto pr = [drop](D3 v, double& u, double& w) {
@@ -401,7 +402,7 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
   };
   double pu, pw;
   pr(p, pu, pw);
-  for (int k = a.face_tri_off[f]; k < a.face_tri_off[f + 1]; ++k) {
+  for (int k = a.face_tri_off[f] + k0; k < a.face_tri_off[f + 1]; k += step) {
     const int t = a.face_tris[k];
     D3 A = fvec(a.V, a.tris[3 * t]), B = fvec(a.V, a.tris[3 * t + 1]), C = fvec(a.V, a.tris[3 * t + 2]);
     double au, aw, bu, bw, cu, cw;
@@ -419,10 +420,18 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n) {
 // Any triangle (outside faces fa, fb) crossed by the open segment p -> q,
 // keeping t_min away from both ends?  FP64 orientation tests at the leaves;
 // 4-wide tree boxes (FP32, padded) tested in FP64.  Traversed by a group of
-// 16 lanes (one DPP row), one tree level per step: each lane takes one slot of
-// up to four popped nodes (a stack entry carries its node's leaf-slot mask, so
-// leaf triangles come straight from the slot array).  The answer does not
-// depend on the order: the first occluder found ends the query.
+// kCheckLanes lanes, one tree level per step: each lane takes one slot of up
+// to kCheckLanes / 4 popped nodes (a stack entry carries its node's leaf-slot
+// mask, so leaf triangles come straight from the slot array).  The answer does
+// not depend on the order: the first occluder found ends the query, and an
+// unoccluded segment visits every box it meets, so a wide group takes few
+// steps.
+#ifndef DCEM_CHECK_LANES
+#define DCEM_CHECK_LANES 64
+#endif
+constexpr int kCheckLanes = DCEM_CHECK_LANES;   // lanes per occlusion query
+constexpr int kCheckStack = 256;                // stack entries per query
+
 __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, uint32_t* se, int lane,
                                uint64_t gmask, bool& fault) {
   const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
@@ -434,7 +443,7 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
   const double big = 1e300;
   const double ix = dv.x != 0 ? 1.0 / dv.x : big, iy = dv.y != 0 ? 1.0 / dv.y : big,
                iz = dv.z != 0 ? 1.0 / dv.z : big;
-  const int gl = lane & (kGroup - 1), jl = gl >> 2, el = gl & 3;
+  const int gl = lane & (kCheckLanes - 1), jl = gl >> 2, el = gl & 3;
   const uint64_t below = (1ull << lane) - 1ull;
   if (gl == 0) se[0] = a.n4_dev[1] << kNodeBits;
   int sp = 1;
@@ -444,7 +453,7 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
       fault = true;
       return false;
     }
-    const int n_pop = min(4, sp);
+    const int n_pop = min(kCheckLanes / 4, sp);
     const bool act = jl < n_pop;
     const uint32_t ent = act ? se[sp - 1 - jl] : 0u;
     wave_sync();
@@ -485,179 +494,186 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
     if (__ballot(hit) & gmask) return true;
     const uint64_t want = __ballot(push != kNoEntry) & gmask;
     const int pos = sp + __popcll(want & below);
-    if (push != kNoEntry && pos < kGroupStack) se[pos] = push;
-    if (sp + __popcll(want) > kGroupStack) fault = true;
-    sp = min(sp + __popcll(want), kGroupStack);
+    if (push != kNoEntry && pos < kCheckStack) se[pos] = push;
+    if (sp + __popcll(want) > kCheckStack) fault = true;
+    sp = min(sp + __popcll(want), kCheckStack);
     wave_sync();
   }
   return false;
 }
 
-constexpr int kRefineBlock = 64;
+// Refinement of one unique candidate u by one block of K + 1 wavefronts.
+//  1. Geometry (thread 0; first ray over the candidate's captures on wave 0):
+//     decode the key, image sources through the face planes and reflection
+//     points walked back from the receiver, each strictly inside its segment
+//     (Sec. III step 3).
+//  2. Validation (wavefront j, j <= order): sub-segment j must be unoccluded
+//     (every triangle outside its end faces), and wavefront 0 also tests that
+//     each reflection point lies in its face, the face's triangles spread over
+//     the lanes (Sec. III step 4).
+//  3. Field (lane f of wavefront 0 for frequency f): length, delay,
+//     directions and the field: theta-hat of the departure direction carried
+//     through each reflection by the Fresnel coefficients, times
+//     sqrt(Pt) lambda / (4 pi d), the specific attenuation and the phase
+//     e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
+constexpr int kRefineMaxThreads = kWave * (kMaxK + 1);
 
-// Refinement, stage 1 (one thread per unique key): decode the key, image
-// sources through the face planes and reflection points walked back from the
-// receiver, each strictly inside its segment.  Points go to pts[u][0..order+1].
-__global__ __launch_bounds__(kRefineBlock) void k_refine_geom(RefineArgs a) {
-  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= *a.n_unique) return;
-  const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
-  const uint32_t idx = a.perm[h];
-  const KeyLayout& L = a.L;
-  int faces[kMaxK];
-  for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
-  int pos = L.K * L.bf;
-  const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
-  pos += 4;
-  const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
-  pos += L.br;
-  const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
-  a.pair[u] = tx * L.n_rx + rx;
-  a.order[u] = (uint8_t)order;
-  for (int j = 0; j < L.K; ++j) a.faces[(size_t)u * L.K + j] = j < order ? faces[j] : -1;
-  uint32_t fr = kNoRay;
-  for (uint32_t j = h; j < e; ++j) fr = min(fr, a.caps[a.perm[j]].work);
-  a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
-
-  const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
-  D3 img[kMaxK + 1];
-  img[0] = T;
-  for (int j = 1; j <= order; ++j) {
-    const double4 pl = a.plane[faces[j - 1]];
-    const D3 n = {pl.x, pl.y, pl.z};
-    img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
-  }
-  double* P = a.pts + (size_t)u * (L.K + 2) * 3;
-  bool ok = true;
-  D3 Q = R;
-  for (int j = order; j >= 1; --j) {
-    const double4 pl = a.plane[faces[j - 1]];
-    const D3 n = {pl.x, pl.y, pl.z};
-    const D3 D = img[j] - Q;
-    const double den = dot(D, n);
-    if (den == 0.0) { ok = false; break; }
-    const double s = (pl.w - dot(Q, n)) / den;
-    if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
-    Q = Q + s * D;
-    P[3 * j] = Q.x; P[3 * j + 1] = Q.y; P[3 * j + 2] = Q.z;
-  }
-  P[0] = T.x; P[1] = T.y; P[2] = T.z;
-  P[3 * (order + 1)] = R.x; P[3 * (order + 1) + 1] = R.y; P[3 * (order + 1) + 2] = R.z;
-  a.valid[u] = ok ? 1 : 0;
-  a.length[u] = len(R - img[order]);
-}
-
-// Refinement, stage 2 (one group of 16 lanes per path and sub-segment j):
-// sub-segment j must be unoccluded, and for j = 0 the group's first lanes
-// also test that each reflection point lies in its face.  A failed check
-// clears the path's valid flag.
-constexpr int kCheckBlock = 256;
-
-__global__ __launch_bounds__(kCheckBlock) void k_refine_check(RefineArgs a) {
-  __shared__ uint32_t stk[kCheckBlock / kGroup][kGroupStack];
+__global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
+  __shared__ double sP[(kMaxK + 2) * 3];      // transmitter, reflection points, receiver
+  __shared__ int sfaces[kMaxK];
+  __shared__ int sorder, sok, sfail;
+  __shared__ uint32_t stk[kMaxK + 1][kCheckStack];
+  const uint32_t u = blockIdx.x;
+  if (u >= *a.n_unique) return;   // uniform over the block
   const int K = a.L.K;
-  const int lane = threadIdx.x & (kWave - 1), gl = lane & (kGroup - 1);
-  const uint64_t gmask = 0xffffull << (lane & ~(kGroup - 1));
-  const uint64_t gid = (blockIdx.x * (uint64_t)kCheckBlock + threadIdx.x) / kGroup;
-  const uint32_t u = (uint32_t)(gid / (K + 1));
-  const int j = (int)(gid - (uint64_t)u * (K + 1));
-  if (u >= *a.n_unique || !a.valid[u]) return;   // whole groups leave together
-  const int order = a.order[u];
-  if (j > order) return;
-  const double* P = a.pts + (size_t)u * (K + 2) * 3;
-  const int32_t* faces = a.faces + (size_t)u * K;
-  bool fail = false, fault = false;
-  if (j == 0 && gl < order) {
-    const int f = faces[gl];
-    const double4 pl = a.plane[f];
-    const D3 pt = {P[3 * (gl + 1)], P[3 * (gl + 1) + 1], P[3 * (gl + 1) + 2]};
-    fail = !in_face(a, f, pt, D3{pl.x, pl.y, pl.z});
-  }
-  const int fa = j >= 1 ? faces[j - 1] : -1;
-  const int fb = j + 1 <= order ? faces[j] : -1;
-  const D3 p = {P[3 * j], P[3 * j + 1], P[3 * j + 2]};
-  const D3 q = {P[3 * (j + 1)], P[3 * (j + 1) + 1], P[3 * (j + 1) + 2]};
-  if (group_occluded(a, p, q, fa, fb, stk[threadIdx.x / kGroup], lane, gmask, fault) && gl == 0) fail = true;
-  if (fail) a.valid[u] = 0;
-  if (fault) atomicOr(a.err, DCEM_ERR_STACK);
-}
-
-// Refinement, stage 3 (one thread per path): length, delay, directions and the
-// field: theta-hat of the departure direction carried through each reflection
-// by the Fresnel coefficients, times sqrt(Pt) lambda / (4 pi d), the specific
-// attenuation and the phase e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
-__global__ __launch_bounds__(kRefineBlock) void k_refine_field(RefineArgs a) {
-  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t nu = *a.n_unique;
-  const int lane = threadIdx.x & 63;
-  bool ok = false;
-  if (u < nu) {
-    const int K = a.L.K;
-    ok = a.valid[u] != 0;
-    const int order = a.order[u];
-    const double* P = a.pts + (size_t)u * (K + 2) * 3;
-    const int32_t* faces = a.faces + (size_t)u * K;
-    auto pt = [P](int j) { return D3{P[3 * j], P[3 * j + 1], P[3 * j + 2]}; };
-    const double d = a.length[u];
-    a.tau[u] = ok ? d / kC0 : 0.0;
-    if (!ok) a.length[u] = 0.0;
-    D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
-    if (ok) {
-      aod = normed(pt(1) - pt(0));
-      aoa = normed(pt(order) - pt(order + 1));
-    }
-    a.aod[3 * u] = aod.x; a.aod[3 * u + 1] = aod.y; a.aod[3 * u + 2] = aod.z;
-    a.aoa[3 * u] = aoa.x; a.aoa[3 * u + 1] = aoa.y; a.aoa[3 * u + 2] = aoa.z;
-    const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
-    const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
-    for (int fi = 0; fi < a.n_freqs; ++fi) {
-      const double f = a.freqs[fi];
-      double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
-      if (!ok) {
-        for (int k = 0; k < 6; ++k) out[k] = 0.0;
-        continue;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const KeyLayout& L = a.L;
+  const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
+  // ---- 1. geometry
+  if (w == 0) {
+    uint32_t fr = kNoRay;
+    for (uint32_t j = h + lane; j < e; j += kWave) fr = min(fr, a.caps[a.perm[j]].work);
+    for (int off = 32; off > 0; off >>= 1) fr = min(fr, (uint32_t)__shfl_xor(fr, off));
+    if (lane == 0) {
+      const uint32_t idx = a.perm[h];
+      int faces[kMaxK];
+      for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
+      int pos = L.K * L.bf;
+      const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
+      pos += 4;
+      const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
+      pos += L.br;
+      const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
+      a.pair[u] = tx * L.n_rx + rx;
+      a.order[u] = (uint8_t)order;
+      for (int j = 0; j < L.K; ++j) {
+        a.faces[(size_t)u * L.K + j] = j < order ? faces[j] : -1;
+        sfaces[j] = faces[j];
       }
-      Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
+      a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
+      const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
+      D3 img[kMaxK + 1];
+      img[0] = T;
       for (int j = 1; j <= order; ++j) {
         const double4 pl = a.plane[faces[j - 1]];
         const D3 n = {pl.x, pl.y, pl.z};
-        const D3 ki = normed(pt(j) - pt(j - 1));
-        const D3 kr = normed(pt(j + 1) - pt(j));
-        const double cos_t = fabs(dot(ki, n));
-        D3 s = cross(ki, n);
-        const double sl = len(s);
-        if (sl < 1e-12) {
-          const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
-          s = normed(cross(ki, ax));
-        } else {
-          s = (1.0 / sl) * s;
-        }
-        const D3 pin = cross(s, ki), pout = cross(s, kr);
-        Cx te, tm;
-        fresnel_coeffs(a.materials + 3 * a.face_material[faces[j - 1]], f, cos_t, te, tm);
-        const Cx es = cadd(cadd(cscl(s.x, E[0]), cscl(s.y, E[1])), cscl(s.z, E[2]));
-        const Cx ep = cadd(cadd(cscl(pin.x, E[0]), cscl(pin.y, E[1])), cscl(pin.z, E[2]));
-        const Cx cs = cmul(te, es), cp = cmul(tm, ep);
-        E[0] = cadd(cscl(s.x, cs), cscl(pout.x, cp));
-        E[1] = cadd(cscl(s.y, cs), cscl(pout.y, cp));
-        E[2] = cadd(cscl(s.z, cs), cscl(pout.z, cp));
+        img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
       }
-      const double lam = kC0 / f;
-      const double k0 = 2.0 * kPi * f / kC0;
-      const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
-      double sn, cs;
-      sincos(k0 * d, &sn, &cs);
-      const Cx ph = {mag * cs, -mag * sn};
-      for (int c = 0; c < 3; ++c) {
-        const Cx v = cmul(ph, E[c]);
-        out[2 * c] = v.re;
-        out[2 * c + 1] = v.im;
+      double* P = a.pts + (size_t)u * (L.K + 2) * 3;
+      bool ok = true;
+      D3 Q = R;
+      for (int j = order; j >= 1; --j) {
+        const double4 pl = a.plane[faces[j - 1]];
+        const D3 n = {pl.x, pl.y, pl.z};
+        const D3 D = img[j] - Q;
+        const double den = dot(D, n);
+        if (den == 0.0) { ok = false; break; }
+        const double s = (pl.w - dot(Q, n)) / den;
+        if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
+        Q = Q + s * D;
+        P[3 * j] = Q.x; P[3 * j + 1] = Q.y; P[3 * j + 2] = Q.z;
+        sP[3 * j] = Q.x; sP[3 * j + 1] = Q.y; sP[3 * j + 2] = Q.z;
       }
+      P[0] = T.x; P[1] = T.y; P[2] = T.z;
+      P[3 * (order + 1)] = R.x; P[3 * (order + 1) + 1] = R.y; P[3 * (order + 1) + 2] = R.z;
+      sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
+      sP[3 * (order + 1)] = R.x; sP[3 * (order + 1) + 1] = R.y; sP[3 * (order + 1) + 2] = R.z;
+      a.length[u] = len(R - img[order]);
+      sorder = order;
+      sok = ok ? 1 : 0;
+      sfail = 0;
     }
   }
-  const uint64_t m = __ballot(ok);
-  if (lane == 0 && m) atomicAdd(&a.counters[kCntValid], (uint32_t)__popcll(m));
+  __syncthreads();
+  const int order = sorder;
+  bool ok = sok != 0;
+  // ---- 2. validation, one wavefront per sub-segment
+  if (ok && w <= order) {
+    const uint64_t all = ~0ull;
+    bool fail = false, fault = false;
+    if (w == 0) {
+      for (int r = 0; r < order && !fail; ++r) {
+        const int f = sfaces[r];
+        const double4 pl = a.plane[f];
+        const D3 pt = {sP[3 * (r + 1)], sP[3 * (r + 1) + 1], sP[3 * (r + 1) + 2]};
+        const bool inside = in_face(a, f, pt, D3{pl.x, pl.y, pl.z}, lane, kWave);
+        fail = __ballot(inside) == 0;
+      }
+    }
+    const int fa = w >= 1 ? sfaces[w - 1] : -1;
+    const int fb = w + 1 <= order ? sfaces[w] : -1;
+    const D3 p = {sP[3 * w], sP[3 * w + 1], sP[3 * w + 2]};
+    const D3 q = {sP[3 * (w + 1)], sP[3 * (w + 1) + 1], sP[3 * (w + 1) + 2]};
+    if (!fail && group_occluded(a, p, q, fa, fb, stk[w], lane, all, fault)) fail = true;
+    if (fail && lane == 0) sfail = 1;
+    if (fault && lane == 0) atomicOr(a.err, DCEM_ERR_STACK);
+  }
+  __syncthreads();
+  if (w != 0) return;
+  ok = ok && sfail == 0;
+  if (lane == 0) a.valid[u] = ok ? 1 : 0;
+  // ---- 3. field, one lane per frequency
+  auto pt = [&](int j) { return D3{sP[3 * j], sP[3 * j + 1], sP[3 * j + 2]}; };
+  const double d = a.length[u];
+  D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
+  if (ok) {
+    aod = normed(pt(1) - pt(0));
+    aoa = normed(pt(order) - pt(order + 1));
+  }
+  if (lane == 0) {
+    a.tau[u] = ok ? d / kC0 : 0.0;
+    if (!ok) a.length[u] = 0.0;
+    a.aod[3 * u] = aod.x; a.aod[3 * u + 1] = aod.y; a.aod[3 * u + 2] = aod.z;
+    a.aoa[3 * u] = aoa.x; a.aoa[3 * u + 1] = aoa.y; a.aoa[3 * u + 2] = aoa.z;
+  }
+  const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
+  const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+  for (int fi = lane; fi < a.n_freqs; fi += kWave) {
+    const double f = a.freqs[fi];
+    double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
+    if (!ok) {
+      for (int k = 0; k < 6; ++k) out[k] = 0.0;
+      continue;
+    }
+    Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
+    for (int j = 1; j <= order; ++j) {
+      const double4 pl = a.plane[sfaces[j - 1]];
+      const D3 n = {pl.x, pl.y, pl.z};
+      const D3 ki = normed(pt(j) - pt(j - 1));
+      const D3 kr = normed(pt(j + 1) - pt(j));
+      const double cos_t = fabs(dot(ki, n));
+      D3 s = cross(ki, n);
+      const double sl = len(s);
+      if (sl < 1e-12) {
+        const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
+        s = normed(cross(ki, ax));
+      } else {
+        s = (1.0 / sl) * s;
+      }
+      const D3 pin = cross(s, ki), pout = cross(s, kr);
+      Cx te, tm;
+      fresnel_coeffs(a.materials + 3 * a.face_material[sfaces[j - 1]], f, cos_t, te, tm);
+      const Cx es = cadd(cadd(cscl(s.x, E[0]), cscl(s.y, E[1])), cscl(s.z, E[2]));
+      const Cx ep = cadd(cadd(cscl(pin.x, E[0]), cscl(pin.y, E[1])), cscl(pin.z, E[2]));
+      const Cx cs = cmul(te, es), cp = cmul(tm, ep);
+      E[0] = cadd(cscl(s.x, cs), cscl(pout.x, cp));
+      E[1] = cadd(cscl(s.y, cs), cscl(pout.y, cp));
+      E[2] = cadd(cscl(s.z, cs), cscl(pout.z, cp));
+    }
+    const double lam = kC0 / f;
+    const double k0 = 2.0 * kPi * f / kC0;
+    const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
+    double sn, cs;
+    sincos(k0 * d, &sn, &cs);
+    const Cx ph = {mag * cs, -mag * sn};
+    for (int c = 0; c < 3; ++c) {
+      const Cx v = cmul(ph, E[c]);
+      out[2 * c] = v.re;
+      out[2 * c + 1] = v.im;
+    }
+  }
 }
+
 
 // One wavefront per (tx, rx): sum the valid paths of that pair (contiguous in
 // key order) with a fixed lane assignment and butterfly, so the result is
@@ -665,45 +681,55 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine_field(RefineArgs a) {
 __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair, const uint8_t* __restrict__ valid,
                                                 const double* __restrict__ amp, const uint32_t* __restrict__ n_unique,
                                                 int n_pairs, int n_freqs, double* __restrict__ p_coh,
-                                                double* __restrict__ p_inc) {
+                                                double* __restrict__ p_inc, uint32_t* __restrict__ counters) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (wave >= n_pairs) return;
-  const int n = (int)*n_unique;
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pair[mid] < wave) lo = mid + 1; else hi = mid;
-  }
-  const int start = lo;
-  hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
-  }
-  const int end = lo;
-  for (int fi = 0; fi < n_freqs; ++fi) {
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    double inc = 0.0;
-    for (int u = start + lane; u < end; u += 64) {
-      if (!valid[u]) continue;
-      const double* v = amp + ((size_t)u * n_freqs + fi) * 6;
-      for (int k = 0; k < 6; ++k) {
-        acc[k] += v[k];
-        inc += v[k] * v[k];
+  __shared__ uint32_t nvalid;   // valid paths of the block's pairs
+  if (threadIdx.x == 0) nvalid = 0;
+  __syncthreads();
+  if (wave < n_pairs) {
+    const int n = (int)*n_unique;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (pair[mid] < wave) lo = mid + 1; else hi = mid;
+    }
+    const int start = lo;
+    hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
+    }
+    const int end = lo;
+    uint32_t nv = 0;
+    for (int u = start + lane; u < end; u += 64) nv += valid[u] ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
+    if (lane == 0 && nv) atomicAdd(&nvalid, nv);
+    for (int fi = 0; fi < n_freqs; ++fi) {
+      double acc[6] = {0, 0, 0, 0, 0, 0};
+      double inc = 0.0;
+      for (int u = start + lane; u < end; u += 64) {
+        if (!valid[u]) continue;
+        const double* v = amp + ((size_t)u * n_freqs + fi) * 6;
+        for (int k = 0; k < 6; ++k) {
+          acc[k] += v[k];
+          inc += v[k] * v[k];
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        for (int k = 0; k < 6; ++k) acc[k] += __shfl_xor(acc[k], off);
+        inc += __shfl_xor(inc, off);
+      }
+      if (lane == 0) {
+        double pc = 0.0;
+        for (int k = 0; k < 6; ++k) pc += acc[k] * acc[k];
+        p_coh[(size_t)fi * n_pairs + wave] = pc;
+        p_inc[(size_t)fi * n_pairs + wave] = inc;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      for (int k = 0; k < 6; ++k) acc[k] += __shfl_xor(acc[k], off);
-      inc += __shfl_xor(inc, off);
-    }
-    if (lane == 0) {
-      double pc = 0.0;
-      for (int k = 0; k < 6; ++k) pc += acc[k] * acc[k];
-      p_coh[(size_t)fi * n_pairs + wave] = pc;
-      p_inc[(size_t)fi * n_pairs + wave] = inc;
-    }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && nvalid) atomicAdd(&counters[kCntValid], nvalid);
 }
 
 int bits_for(int64_t n_values) {
@@ -858,12 +884,7 @@ void launch_refine(dcem_ctx* c) {
   a.pts = ptr<double>(c->path_pts);
   a.counters = c->cnt_dev;
   a.err = c->err_dev;
-  const unsigned nb = (unsigned)((n + kRefineBlock - 1) / kRefineBlock);
-  hipLaunchKernelGGL(k_refine_geom, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
-  const uint64_t nchk = (uint64_t)n * (c->K + 1) * kGroup;
-  hipLaunchKernelGGL(k_refine_check, dim3((unsigned)((nchk + kCheckBlock - 1) / kCheckBlock)), dim3(kCheckBlock), 0,
-                     c->stream, a);
-  hipLaunchKernelGGL(k_refine_field, dim3(nb), dim3(kRefineBlock), 0, c->stream, a);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 1)), 0, c->stream, a);
 }
 
 void launch_reduce(dcem_ctx* c) {
@@ -871,7 +892,7 @@ void launch_reduce(dcem_ctx* c) {
   hipLaunchKernelGGL(k_reduce, dim3((n_pairs * 64 + 255) / 256), dim3(256), 0, c->stream,
                      ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
                      c->cnt_dev + kCntUnique, n_pairs, c->n_freqs, c->pcoh_dev,
-                     c->pinc_dev);
+                     c->pinc_dev, c->cnt_dev);
 }
 
 }  // namespace dcem
