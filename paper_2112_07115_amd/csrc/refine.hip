@@ -426,10 +426,7 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n, int k0 = 0, int 
 // not depend on the order: the first occluder found ends the query, and an
 // unoccluded segment visits every box it meets, so a wide group takes few
 // steps.
-#ifndef DCEM_CHECK_LANES
-#define DCEM_CHECK_LANES 64
-#endif
-constexpr int kCheckLanes = DCEM_CHECK_LANES;   // lanes per occlusion query
+constexpr int kCheckLanes = kWave;              // lanes per occlusion query
 constexpr int kCheckStack = 256;                // stack entries per query
 
 __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, uint32_t* se, int lane,

@@ -479,8 +479,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
 // traversing.  Every triangle the per-thread traversal tests is tested here
 // too (leaf triangles without their boxes, which only drops a conservative
 // filter), with the same arithmetic, so the hit is the same.
-constexpr int kRayLanes = kGroup;           // lanes per ray: one DPP row (16) or two (32)
+// Lanes per ray: one DPP row.  (Measured on the re-trace of the urban
+// workload: 8 and 32 lanes per ray take 1.7x and 1.1x as long.)
+constexpr int kRayLanes = kGroup;
 constexpr int kGroups = kWave / kRayLanes;  // rays per wavefront
+constexpr int kRayStack = kRayLanes == 64 ? 256 : kGroupStack;   // stack entries per ray
 constexpr int kWaves = 4;                   // wavefronts per block
 constexpr int kWaveBlock = kWaves * kWave;
 constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
@@ -494,24 +497,13 @@ __device__ inline uint64_t hit_key(float t, int tri) {
   return tri < 0 ? ~0ull : ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)tri;
 }
 
-// Minimum over each row of 16 lanes by data-parallel primitives: swaps within
-// pairs and quads, then the mirrored halves of the row, then the whole row.
+// A 64-bit value from another lane of the same row (DPP control CTRL).
 template <int CTRL>
 __device__ inline uint64_t dpp_u64(uint64_t v) {
   const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
   const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
   const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
   return ((uint64_t)nhi << 32) | nlo;
-}
-__device__ inline uint64_t row_min_u64(uint64_t v) {
-  uint64_t o = dpp_u64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
-  v = o < v ? o : v;
-  o = dpp_u64<0x4e>(v);            // quad_perm [2, 3, 0, 1]
-  v = o < v ? o : v;
-  o = dpp_u64<0x141>(v);           // row_half_mirror
-  v = o < v ? o : v;
-  o = dpp_u64<0x140>(v);           // row_mirror
-  return o < v ? o : v;
 }
 
 struct SlotHit {
@@ -522,11 +514,28 @@ struct SlotHit {
   int moving; // the face belongs to a moving object
 };
 
-// Minimum over each group of kRayLanes lanes.
+// Minimum over each group of kRayLanes lanes: swaps within pairs and quads,
+// then the mirrored halves of each 8-lane half-row and of each row, then
+// across rows.
 __device__ inline uint64_t group_min_u64(uint64_t v) {
-  v = row_min_u64(v);
-  if (kRayLanes == 32) {
-    const uint64_t o = __shfl_xor(v, 16);
+  uint64_t o = dpp_u64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+  v = o < v ? o : v;
+  o = dpp_u64<0x4e>(v);            // quad_perm [2, 3, 0, 1]
+  v = o < v ? o : v;
+  if (kRayLanes >= 8) {
+    o = dpp_u64<0x141>(v);         // row_half_mirror
+    v = o < v ? o : v;
+  }
+  if (kRayLanes >= 16) {
+    o = dpp_u64<0x140>(v);         // row_mirror
+    v = o < v ? o : v;
+  }
+  if (kRayLanes >= 32) {
+    o = __shfl_xor(v, 16);
+    v = o < v ? o : v;
+  }
+  if (kRayLanes == 64) {
+    o = __shfl_xor(v, 32);
     v = o < v ? o : v;
   }
   return v;
@@ -540,12 +549,12 @@ __device__ inline MaskAxes mask_axes(const Ray& r) {
 
 __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   __shared__ float4 rxs[kWaveRx];
-  __shared__ uint32_t stk_e[kWaves * kGroups][kGroupStack];
-  __shared__ float stk_t[kWaves * kGroups][kGroupStack];
+  __shared__ uint32_t stk_e[kWaves * kGroups][kRayStack];
+  __shared__ float stk_t[kWaves * kGroups][kRayStack];
   const int lane = threadIdx.x & (kWave - 1);
   const int g = lane / kRayLanes, gl = lane & (kRayLanes - 1), jl = gl >> 2, el = gl & 3;
   const int leader = lane & ~(kRayLanes - 1);
-  const uint64_t gmask = ((1ull << kRayLanes) - 1ull) << (kRayLanes * g);
+  const uint64_t gmask = kRayLanes == kWave ? ~0ull : ((1ull << (kRayLanes % kWave)) - 1ull) << (kRayLanes * g);
   const uint64_t below = (1ull << lane) - 1ull;
   uint32_t* se = stk_e[threadIdx.x / kRayLanes];
   float* st = stk_t[threadIdx.x / kRayLanes];
@@ -669,12 +678,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const uint64_t want = __ballot(push != kNoEntry) & gmask;
     const int total = __popcll(want);
     const int pos = sp + __popcll(want & below);
-    if (push != kNoEntry && pos < kGroupStack) {
+    if (push != kNoEntry && pos < kRayStack) {
       se[pos] = push;
       st[pos] = pt;
     }
-    if (sp + total > kGroupStack) overflow = true;
-    sp = min(sp + total, kGroupStack);
+    if (sp + total > kRayStack) overflow = true;
+    sp = min(sp + total, kRayStack);
     if (n_pop > 0 && --guard <= 0 && sp > 0) {   // only a malformed tree gets here
       overflow = true;
       sp = 0;
