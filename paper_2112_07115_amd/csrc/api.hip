@@ -154,8 +154,15 @@ std::vector<Node> build_rx_tree(const std::vector<float>& rx, float radius) {
   return t.nodes;
 }
 
-void ev_record(dcem_ctx* c, int i) {
-  if (c->timing) (void)hipEventRecord(c->ev[i], c->stream);
+void ev_record(dcem_ctx* c, int i, hipStream_t s = nullptr) {
+  if (c->timing) (void)hipEventRecord(c->ev[i], s ? s : c->stream);
+}
+
+// Order the context stream after a refit still running on the refit stream.
+hipError_t join_refit(dcem_ctx* c) {
+  if (!c->refit_in_flight) return hipSuccess;
+  c->refit_in_flight = false;
+  return hipStreamWaitEvent(c->stream, c->ev_join, 0);
 }
 
 float ev_ms(dcem_ctx* c, int a, int b) {
@@ -171,6 +178,8 @@ constexpr size_t kBlockHead = 512;
 hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   n_pow = std::max<int64_t>(n_pow, 1);
   if (n_pow <= c->n_pow_cap && c->frame_block.p) return hipSuccess;
+  hipError_t je = join_refit(c);   // a refit in flight writes its SAH value here
+  if (je != hipSuccess) return je;
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
   // keep the head (SAH values of the current tree) across a reallocation
   double sah_keep[2] = {1.0, 1.0};
@@ -203,14 +212,25 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
 
 dcem_status finish_candidates(dcem_ctx* c);
 
+size_t frame_block_bytes(const dcem_ctx* c) {
+  return kBlockHead + 2 * sizeof(double) * (size_t)std::max<int64_t>(c->n_pow_cap, 1);
+}
+
 // Wait for the stream and read the frame block in one transfer: counters,
 // device error word, SAH values and powers.  Redoes a frame's candidates when
 // the small de-duplication path overflowed.  Reports device errors.
 dcem_status sync_frame(dcem_ctx* c) {
-  const size_t n_pow = (size_t)std::max<int64_t>(c->n_pow_cap, 1);
-  const size_t bytes = kBlockHead + 2 * sizeof(double) * n_pow;
-  HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, bytes, hipMemcpyDeviceToHost, c->stream), "read results");
-  HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  if (c->copy_pending) {
+    // the frame's own copy, enqueued right behind its last kernel: later work
+    // on the stream (the next frame's transforms and refit) is not waited for
+    c->copy_pending = false;
+    HIP_TRY(hipEventSynchronize(c->ev_copy), "synchronize");
+  } else {
+    HIP_TRY(join_refit(c), "wait for refit");   // a refit in flight writes its SAH value into the block
+    HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, frame_block_bytes(c), hipMemcpyDeviceToHost, c->stream),
+            "read results");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  }
   const char* hb = static_cast<const char*>(c->host_block);
   std::memcpy(c->last_cnt, hb, sizeof(uint32_t) * kCntSlots);
   uint32_t err = 0;
@@ -272,6 +292,13 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
     return DCEM_E_OUT_OF_MEMORY;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming) != hipSuccess) {
+    dcem_destroy(c);
+    return DCEM_E_DEVICE;
+  }
   *out = c;
   return DCEM_OK;
 }
@@ -279,6 +306,7 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
 void dcem_destroy(dcem_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
@@ -295,6 +323,10 @@ void dcem_destroy(dcem_ctx* c) {
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -333,6 +365,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
       (s->n_objects && !s->object_vertex_range))
     return fail(c, DCEM_E_INVALID_ARG, "null array with nonzero size");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   std::vector<float> V;
   std::vector<int32_t> T, TF, FM, FO;
   std::vector<double> M;
@@ -443,6 +476,7 @@ dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_o
   if (n_objects == 0) return DCEM_OK;
   if (!xf) return fail(c, DCEM_E_INVALID_ARG, "null transforms");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   if (mem_kind == DCEM_MEM_HOST) {
     for (int i = 0; i < 12 * n_objects; ++i)
       if (!std::isfinite(xf[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite transform entry %d", i);
@@ -464,22 +498,30 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   if (std::isnan(threshold)) return fail(c, DCEM_E_INVALID_ARG, "threshold is NaN");
   if (threshold <= 0.0) threshold = 1.5;
   HIP_TRY(hipSetDevice(c->device), "set device");
-  ev_record(c, 6);
+  HIP_TRY(join_refit(c), "wait for refit");
   // the decision uses the quality measured after the previous refit (read at
   // the last synchronisation), so no host round trip is needed here
   const double measured = c->pending_ratio;
   int32_t rb = 0;
   if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
+    ev_record(c, 6);
     // a forced rebuild serves the frame at hand; one the quality test asks
     // for keeps the objects apart for the refits that follow
     HIP_TRY(build_lbvh(c, !(flags & DCEM_FORCE_REBUILD)), "rebuild BVH");
     rb = 1;
   } else {
-    launch_refit(c, true, c->sah_dev + 1);
+    // on the refit stream, after the transforms enqueued so far
+    HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork refit");
+    HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0), "fork refit");
+    ev_record(c, 6, c->aux);
+    launch_refit(c, true, c->sah_dev + 1, c->aux);
     HIP_TRY(hipGetLastError(), "refit kernel");
+    ev_record(c, 7, c->aux);
+    HIP_TRY(hipEventRecord(c->ev_join, c->aux), "join refit");
+    c->refit_in_flight = true;
     c->refit_since_build = true;
   }
-  ev_record(c, 7);
+  if (rb) ev_record(c, 7);
   c->bvh_stale = false;
   c->last_rebuilt = rb;
   c->refit_pending_timing = true;
@@ -603,6 +645,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   // its re-trace count (sizes the persistent grid) and its capture count (picks
   // the de-duplication path)
   if (c->has_frame && !c->counts_current) {
+    HIP_TRY(join_refit(c), "wait for refit");
     dcem_status st = sync_frame(c);
     if (st != DCEM_OK) return st;
   }
@@ -613,8 +656,9 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   ev_record(c, 0);
   c->cur_caps ^= 1;
   launch_frame_begin(c, p->los_always != 0);
-  if (coherent) launch_coherence(c);
+  if (coherent) launch_coherence(c);   // does not read the tree: overlaps a refit in flight
   ev_record(c, 1);
+  HIP_TRY(join_refit(c), "wait for refit");
   c->last_trace_kernel =
       n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work, n_prev) : 0;
   ev_record(c, 2);
@@ -627,6 +671,11 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   launch_reduce(c);
   ev_record(c, 5);
   HIP_TRY(hipGetLastError(), "refine kernels");
+  // the results of the frame, read back behind its last kernel
+  HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, frame_block_bytes(c), hipMemcpyDeviceToHost, c->stream),
+          "read results");
+  HIP_TRY(hipEventRecord(c->ev_copy, c->stream), "read results");
+  c->copy_pending = true;
   c->cache_valid = keep_cache;
   c->has_frame = true;
   c->counts_current = false;
@@ -698,6 +747,7 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
@@ -754,6 +804,7 @@ dcem_status dcem_get_trace_log(dcem_ctx* c, int32_t* tri, float* t, float* lengt
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (!c->record_log) return fail(c, DCEM_E_STATE, "trace log not recorded (record_trace_log = 0)");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const size_t n = (size_t)c->n_tx * c->n_rays * (c->K + 1);
@@ -769,6 +820,7 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const int64_t nc = c->n_caps_host;
@@ -812,6 +864,7 @@ dcem_status dcem_get_bvh(dcem_ctx* c, int64_t cap_internal, int32_t* n_internal,
   c->err.clear();
   if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   const int32_t ni = c->nt > 0 ? c->n_internal : 0;
   if (n_internal) *n_internal = ni;
@@ -835,6 +888,7 @@ dcem_status dcem_get_vertices(dcem_ctx* c, float* out) {
   c->err.clear();
   if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   if (c->nv) HIP_TRY(hipMemcpy(out, c->vertices.p, sizeof(float) * 3 * c->nv, hipMemcpyDeviceToHost), "copy vertices");
   return check_device_error(c);
@@ -845,6 +899,7 @@ dcem_status dcem_get_ray_dirs(dcem_ctx* c, float* out) {
   c->err.clear();
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(join_refit(c), "wait for refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   if (c->n_rays) HIP_TRY(hipMemcpy(out, c->dirs.p, sizeof(float) * 3 * c->n_rays, hipMemcpyDeviceToHost), "copy dirs");
   return DCEM_OK;

@@ -819,7 +819,7 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
                      cross, cross + ni, info + 2);
   hipLaunchKernelGGL(k_cross_parent, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), cross,
                      cross + ni, info + 2, ni, cross + 2 * (size_t)ni);
-  launch_refit(c, false, c->sah_dev + 0);
+  launch_refit(c, false, c->sah_dev + 0, c->stream);
   // 4-wide tree: binary nodes at even depth, breadth-first
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
   uint32_t* dperm = dkey + ni;
@@ -846,7 +846,7 @@ void launch_collapse(dcem_ctx* c) {
                      ptr<Leaf>(c->tri4), ptr<int32_t>(c->leaf_slot), ptr<int32_t>(c->slot4));
 }
 
-void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out, hipStream_t s) {
   if (c->nt == 0) return;
   const int ni = c->n_internal;
   int32_t* cross = ptr<int32_t>(c->cross);
@@ -878,8 +878,7 @@ void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
   a.face_ref_tri = ptr<int32_t>(c->face_ref_tri);
   a.nf = c->nf;
   a.plane = ptr<double4>(c->face_plane);
-  hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0,
-                     c->stream, a);
+  hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0, s, a);
 }
 
 

@@ -102,6 +102,14 @@ struct dcem_ctx {
   int device = 0;
   int n_cus = 0;                                     // compute units of the device (0: not queried yet)
   hipStream_t stream = nullptr;
+  // A refit runs on its own stream, concurrently with the revalidation pass of
+  // the next frame (which does not read the tree); the context stream waits
+  // for ev_join before anything that reads the tree or the vertices.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool refit_in_flight = false;
+  hipEvent_t ev_copy = nullptr;   // the last traced frame's results have reached host_block
+  bool copy_pending = false;
   std::string err;
   bool timing = false;
   int64_t cap_capacity = int64_t(1) << 22;
@@ -213,7 +221,7 @@ void launch_xform(dcem_ctx* c, const float* xf);
 hipError_t build_lbvh(dcem_ctx* c, bool separate_objects);
 // Refit the binary tree (`wide`: and the 4-wide tree in place, no collapse
 // needed), write the SAH ratio to sah_out and the face planes.
-void launch_refit(dcem_ctx* c, bool wide, double* sah_out);
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out, hipStream_t s);
 void launch_collapse(dcem_ctx* c);
 
 // ---- radix sort (sort.hip)
