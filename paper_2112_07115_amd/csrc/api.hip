@@ -318,7 +318,8 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
                     &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
-                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4, &c->cross};
+                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4, &c->cross,
+                    &c->face_build};
   for (DevBuf* b : bufs) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
@@ -439,6 +440,16 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   c->no = s->n_objects;
   c->pad = (float)(4e-6 * (2.0 * R + 1.0));
   c->h_face_object = FO;
+  {
+    // faces per group (the static geometry, each moving object): the sort
+    // keys of the build hold a face's rank within its group
+    std::vector<int32_t> per((size_t)c->no + 1, 0);
+    for (int32_t o : FO) ++per[(size_t)(o + 1)];
+    int32_t most = 1;
+    for (int32_t v : per) most = std::max(most, v);
+    c->face_bits = 0;
+    while ((int64_t(1) << c->face_bits) < most) ++c->face_bits;
+  }
   HIP_TRY(upload(c->ref_vertices, V, c->stream), "upload vertices");
   HIP_TRY(upload(c->vertices, V, c->stream), "upload vertices");
   HIP_TRY(upload(c->tris, T, c->stream), "upload tris");

@@ -167,18 +167,88 @@ __global__ void k_object_rank(const uint32_t* __restrict__ ocode, int no, int32_
   rank[o] = r;
 }
 
-// Sort key of each triangle.  Without moving objects: the 30-bit Morton code
-// of its centroid in the centroid bounds.  With them (key_hi non-null), a
-// prefix separates the static triangles (0) from each moving object's
-// (1 << rank_bits | rank of the object), and a moving triangle's Morton code is
-// taken in its object's box: the hierarchy built from these keys holds the
-// static geometry and every object in subtrees of their own, so rigid motion
-// leaves those subtrees tight under refitting.  Keys are stored as two words,
-// key_hi (bits 63..32) and key_lo (bits 31..0) of prefix << 30 | code.
+// Group prefix of a face: 0 for static geometry, 1 << rank_bits | the object's
+// spatial rank for a moving object's face.
+__device__ inline uint32_t group_prefix(const int32_t* face_object, const int32_t* orank, int rank_bits, int f) {
+  const int obj = face_object[f];
+  return obj < 0 ? 0u : ((1u << rank_bits) | (uint32_t)orank[obj]);
+}
+
+// Box of each face (its triangles' vertices) and its sort key within the
+// faces: group prefix << 30 | Morton code of the box centre in the group's box
+// (the centroid bounds for static faces, the object's box for moving ones),
+// as two words.  Thread 0 also stores the face count for the sort.
+__global__ void k_face_keys(const float* __restrict__ V, const int32_t* __restrict__ T,
+                            const int32_t* __restrict__ face_tri_off, const int32_t* __restrict__ face_tris, int nf,
+                            const int32_t* __restrict__ face_object, const float* __restrict__ obj_box,
+                            const int32_t* __restrict__ orank, int rank_bits, const uint32_t* __restrict__ box,
+                            float* __restrict__ fbox, uint32_t* __restrict__ fkey_hi, uint32_t* __restrict__ fkey_lo,
+                            uint32_t* __restrict__ n_faces) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f == 0) *n_faces = (uint32_t)nf;
+  if (f >= nf) return;
+  float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int k = face_tri_off[f]; k < face_tri_off[f + 1]; ++k) {
+    const int t = face_tris[k];
+    for (int v = 0; v < 3; ++v) {
+      const float3 p = load_v(V, T[3 * t + v]);
+      lo[0] = fminf(lo[0], p.x); lo[1] = fminf(lo[1], p.y); lo[2] = fminf(lo[2], p.z);
+      hi[0] = fmaxf(hi[0], p.x); hi[1] = fmaxf(hi[1], p.y); hi[2] = fmaxf(hi[2], p.z);
+    }
+  }
+  float glo[3], gext[3], c[3];
+  bounds_of(box, glo, gext);
+  const int obj = face_object[f];
+  if (obj >= 0)
+    for (int k = 0; k < 3; ++k) {
+      glo[k] = obj_box[6 * obj + k];
+      const float h = obj_box[6 * obj + 3 + k];
+      gext[k] = h > glo[k] ? h - glo[k] : 1.0f;
+    }
+  for (int k = 0; k < 3; ++k) {
+    fbox[6 * f + k] = lo[k];
+    fbox[6 * f + 3 + k] = hi[k];
+    c[k] = lo[k] <= hi[k] ? 0.5f * (lo[k] + hi[k]) : glo[k];   // a face without triangles sorts first
+  }
+  const uint64_t key = ((uint64_t)group_prefix(face_object, orank, rank_bits, f) << 30) | morton30(c, glo, gext);
+  fkey_hi[f] = (uint32_t)(key >> 32);
+  fkey_lo[f] = (uint32_t)key;
+}
+
+// First sorted position of each group's faces.
+__global__ void k_face_first(const uint32_t* __restrict__ fperm, int nf, const int32_t* __restrict__ face_object,
+                             int32_t* __restrict__ first) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nf) return;
+  const int g = face_object[fperm[q]];
+  if (q == 0 || face_object[fperm[q - 1]] != g) first[g + 1] = q;
+}
+
+// Rank of each face among its group's faces, in sorted order.
+__global__ void k_face_rank(const uint32_t* __restrict__ fperm, int nf, const int32_t* __restrict__ face_object,
+                            const int32_t* __restrict__ first, int32_t* __restrict__ frank) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nf) return;
+  const int f = (int)fperm[q];
+  frank[f] = q - first[face_object[f] + 1];
+}
+
+// Sort key of each triangle.  Without moving objects (or for a forced
+// rebuild): the 30-bit Morton code of its centroid in the centroid bounds.
+// Otherwise (key_hi non-null) the key is, from the most significant bit, the
+// group prefix of its face (static geometry 0, a moving object
+// 1 << rank_bits | the object's spatial rank), the face's rank among its
+// group's faces (face_bits bits) and the Morton code of the centroid in the
+// face's box.  The hierarchy built from these keys holds the static geometry,
+// every moving object and, inside those, every face in subtrees of their own:
+// rigid motion leaves the objects' subtrees tight under refitting, and a
+// planar face's triangles sit under a flat box.  Keys are stored as two words,
+// key_hi (bits 63..32) and key_lo (bits 31..0).
 __global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
                          const uint32_t* __restrict__ box, const int32_t* __restrict__ tri_face,
-                         const int32_t* __restrict__ face_object, const float* __restrict__ obj_box,
-                         const int32_t* __restrict__ rank, int rank_bits, uint32_t* __restrict__ key_hi,
+                         const int32_t* __restrict__ face_object, const int32_t* __restrict__ orank, int rank_bits,
+                         const int32_t* __restrict__ frank, int face_bits, const float* __restrict__ fbox,
+                         const float* __restrict__ obj_box, uint32_t* __restrict__ key_hi,
                          uint32_t* __restrict__ key_lo) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nt) return;
@@ -187,19 +257,24 @@ __global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict_
   float3 a = load_v(V, T[3 * i]), b = load_v(V, T[3 * i + 1]), c = load_v(V, T[3 * i + 2]);
   float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
                 (a.z + b.z + c.z) * (1.0f / 3.0f)};
-  const int obj = key_hi ? face_object[tri_face[i]] : -1;
-  uint32_t prefix = 0;
-  if (obj >= 0) {
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = obj_box[6 * obj + k];
-      const float h = obj_box[6 * obj + 3 + k];
-      ext[k] = h > lo[k] ? h - lo[k] : 1.0f;
-    }
-    prefix = (1u << rank_bits) | (uint32_t)rank[obj];
+  if (!key_hi) {
+    key_lo[i] = morton30(p, lo, ext);
+    return;
   }
-  const uint32_t m = morton30(p, lo, ext);
-  if (key_hi) key_hi[i] = prefix >> 2;
-  key_lo[i] = (prefix << 30) | m;
+  const int f = tri_face[i];
+  const float* fb = fbox ? fbox + 6 * f : nullptr;   // without the face level: the object's box
+  const int obj = face_object[f];
+  if (fb || obj >= 0) {
+    if (!fb) fb = obj_box + 6 * obj;
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fb[k];
+      ext[k] = fb[3 + k] > lo[k] ? fb[3 + k] - lo[k] : 1.0f;
+    }
+  }
+  const uint64_t key = ((((uint64_t)group_prefix(face_object, orank, rank_bits, f) << face_bits) |
+                         (uint64_t)(frank ? frank[f] : 0)) << 30) | morton30(p, lo, ext);
+  key_hi[i] = (uint32_t)(key >> 32);
+  key_lo[i] = (uint32_t)key;
 }
 
 // Longest common prefix of the sorted keys i and j (ties broken by index).
@@ -779,6 +854,8 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   int32_t* orank = reinterpret_cast<int32_t*>(ocode + no);
   int rank_bits = 1;
   while ((1 << rank_bits) < no) ++rank_bits;
+  // face level of the keys: group prefix (rank_bits + 1), face rank, Morton code
+  const int face_bits = 31 + rank_bits + c->face_bits <= 64 ? c->face_bits : -1;
   hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox, (uint32_t)nt);
   const int nb = (int)std::min<int64_t>((nt + 255) / 256, 1024);
   hipLaunchKernelGGL(k_centroid_bounds, dim3(nb), dim3(256), 0, c->stream, ptr<float>(c->vertices),
@@ -788,10 +865,35 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
                        nbox, ocode);
     hipLaunchKernelGGL(k_object_rank, dim3((no + 255) / 256), dim3(256), 0, c->stream, ocode, no, orank);
   }
+  int32_t* frank = nullptr;
+  float* fbox = nullptr;
+  int fbits = 0;
+  if (key_words == 2 && face_bits >= 0) {
+    // faces in their groups' spatial order: boxes and keys, sort, ranks
+    const int nf = c->nf;
+    if ((e = ensure(c->face_build, sizeof(uint32_t) * (12 * (size_t)nf + (size_t)no + 16))) != hipSuccess) return e;
+    fbox = ptr<float>(c->face_build);
+    uint32_t* fkey = reinterpret_cast<uint32_t*>(fbox + 6 * (size_t)nf);   // [2][nf]
+    uint32_t* fperm = fkey + 2 * (size_t)nf;
+    uint32_t* ftmp = fperm + nf;
+    frank = reinterpret_cast<int32_t*>(ftmp + nf);
+    int32_t* ffirst = frank + nf;                                           // [no + 1]
+    uint32_t* fn = reinterpret_cast<uint32_t*>(ffirst + no + 1);
+    const int fb = (nf + 255) / 256;
+    hipLaunchKernelGGL(k_face_keys, dim3(fb), dim3(256), 0, c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris),
+                       ptr<int32_t>(c->face_tri_off), ptr<int32_t>(c->face_tris), nf, ptr<int32_t>(c->face_object),
+                       ptr<float>(c->obj_box), orank, rank_bits, nbox, fbox, fkey, fkey + nf, fn);
+    if ((e = radix_sort_perm(c, fkey, 2, 31 + rank_bits, fn, nf, fperm, ftmp, c->stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_face_first, dim3(fb), dim3(256), 0, c->stream, fperm, nf, ptr<int32_t>(c->face_object),
+                       ffirst);
+    hipLaunchKernelGGL(k_face_rank, dim3(fb), dim3(256), 0, c->stream, fperm, nf, ptr<int32_t>(c->face_object),
+                       ffirst, frank);
+    fbits = face_bits;
+  }
   hipLaunchKernelGGL(k_morton, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox, ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_object),
-                     ptr<float>(c->obj_box), orank, rank_bits, key_hi, key_lo);
-  const int key_bits = key_words == 2 ? 31 + rank_bits : 30;
+                     orank, rank_bits, frank, fbits, fbox, ptr<float>(c->obj_box), key_hi, key_lo);
+  const int key_bits = key_words == 2 ? 31 + rank_bits + fbits : 30;
   if ((e = radix_sort_perm(c, code, key_words, key_bits, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess)
     return e;
   if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;

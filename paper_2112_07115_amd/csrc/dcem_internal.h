@@ -137,6 +137,8 @@ struct dcem_ctx {
   dcem::DevBuf tree_info;                            // uint32 [0]: 4-wide nodes, [1]: root leaf-slot mask,
                                                      // [2]: cross nodes, [3], [4]: refit list length and block ticket
   dcem::DevBuf tri4;                                 // leaf triangles in slot order (Leaf [n4][4])
+  dcem::DevBuf face_build;                           // build scratch: face boxes, keys, order and ranks
+  int face_bits = 0;                                 // bits of a face's rank among its group's faces
 
   // -- rays and cache
   dcem::TraceConfig cfg;

@@ -547,6 +547,7 @@ __device__ inline MaskAxes mask_axes(const Ray& r) {
                   m(r.ky, 2), m(r.kz, 0), m(r.kz, 1), m(r.kz, 2)};
 }
 
+
 __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   __shared__ float4 rxs[kWaveRx];
   __shared__ uint32_t stk_e[kWaves * kGroups][kRayStack];
@@ -578,10 +579,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   Ray r;
   MaskAxes ax;
   SlotHit h{FLT_MAX, -1, -1, -1, 0};
+  uint64_t best = ~0ull;   // the group's lexicographic minimum of (t, triangle)
 
   auto begin_segment = [&]() {
     h = SlotHit{FLT_MAX, -1, -1, -1, 0};
     best_t = INFINITY;
+    best = ~0ull;
     guard = n4 + 2;
     sp = 0;
     if (n4 > 0) {
@@ -651,12 +654,14 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     }
     uint32_t push = kNoEntry;
     float pt = 0.0f;
+    bool improved = false;
     if (leaf) {
       const int face = __float_as_int(q1.w);
       if (face != excl) {
         const float t = watertight_axes(r, ax, q0, q1, q2);
         const int tri = __float_as_int(q0.w);
         if (t > kTMin && hit_less(t, tri, h.t, h.tri)) {
+          improved = true;
           h.t = t;
           h.tri = tri;
           h.slot = 4 * node + el;
@@ -688,8 +693,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       overflow = true;
       sp = 0;
     }
-    const uint64_t best = group_min_u64(hit_key(h.t, h.tri));
-    best_t = best == ~0ull ? INFINITY : __uint_as_float((uint32_t)(best >> 32));
+    if (__ballot(improved)) {   // the groups' minima change only where a lane found a nearer hit
+      best = group_min_u64(hit_key(h.t, h.tri));
+      best_t = best == ~0ull ? INFINITY : __uint_as_float((uint32_t)(best >> 32));
+    }
     if (!(busy && sp == 0)) continue;
     // ---- this group's traversal ended: finish the segment
     const uint64_t own = __ballot(best != ~0ull && hit_key(h.t, h.tri) == best) & gmask;

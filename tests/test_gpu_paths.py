@@ -1,11 +1,13 @@
 """GPU: code paths the urban workload does not reach.
 
-- A refit of a 300k-triangle scene, whose nodes spanning refit blocks are too
-  many for the last-block pass (the block pass then uses device-wide arrival
-  counters for them): exact boxes, and the same hits as a rebuild.
+- A refit of a 300k-triangle scene built by a forced rebuild, whose nodes
+  spanning refit blocks are too many for the last-block pass (the block pass
+  then uses device-wide arrival counters for them): exact boxes, and the same
+  hits as a rebuild.
 - More moving objects than the coherence pass bins on its grid (they are then
   tested one by one): coherent frames equal the full re-trace bitwise.
-- The build at upload keeps each moving object in a subtree of its own.
+- The build at upload keeps each moving object, and each face, in a subtree of
+  its own.
 """
 import sys
 
@@ -84,6 +86,9 @@ def test_large_scene_refit_equals_rebuild():
     a, b = dcem.Context(0), dcem.Context(0)
     a.scene_upload(s)
     b.scene_upload(s)
+    # a forced rebuild orders all triangles along one Morton curve, whose nodes
+    # straddle the refit blocks' boundaries at every level
+    a.refit_bvh(force_rebuild=True)
     child, box, leaf = a.bvh()
     lo, hi = leaf_ranges(child)
     n_cross = int(np.sum(lo // REFIT_BLOCK != hi // REFIT_BLOCK))
@@ -111,7 +116,8 @@ def test_large_scene_refit_equals_rebuild():
 
 def test_upload_build_keeps_objects_in_own_subtrees():
     """The build at upload gives every moving object (and the static geometry)
-    a subtree of its own: a node whose leaf range is exactly its triangles."""
+    a subtree of its own, and every face one inside it: a node whose leaf
+    range is exactly its triangles."""
     s = scenes.dynamic_urban(n_rays=1 << 10)
     ctx = dcem.Context(0)
     ctx.scene_upload(s)
@@ -123,7 +129,14 @@ def test_upload_build_keeps_objects_in_own_subtrees():
         pos = np.flatnonzero(tri_obj == o)
         assert pos.size and pos[-1] - pos[0] + 1 == pos.size, o
         assert (int(pos[0]), int(pos[-1])) in spans, o
-    log("objects in own subtrees:", s.n_objects)
+    # and every face inside its group
+    tri_face = s.tri_face[leaf]
+    for f in range(s.face_object.shape[0]):
+        pos = np.flatnonzero(tri_face == f)
+        if pos.size > 1:
+            assert pos[-1] - pos[0] + 1 == pos.size, f
+            assert (int(pos[0]), int(pos[-1])) in spans, f
+    log("objects and faces in own subtrees:", s.n_objects, s.face_object.shape[0])
     ctx.close()
 
 
