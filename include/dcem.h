@@ -206,8 +206,9 @@ dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n
  * decision and the ratio it was based on (1.0 right after a rebuild).
  * Asynchronous on the context stream; device errors are reported by the next
  * synchronising call.  The build at scene upload and the rebuilds the quality
- * test asks for put the static geometry and every moving object in subtrees
- * of their own, so that refits under rigid motion keep the tree tight; a
+ * test asks for put the static geometry and every moving object, and inside
+ * them every face, in subtrees of their own, so that refits under rigid motion
+ * keep the tree tight; a
  * forced rebuild orders all triangles along one Morton curve, the better tree
  * for a frame traced without refitting.  Rebuilding never changes traced
  * results: hits are the lexicographic minimum of (distance, triangle id) over

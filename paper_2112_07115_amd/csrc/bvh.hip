@@ -167,10 +167,14 @@ __global__ void k_object_rank(const uint32_t* __restrict__ ocode, int no, int32_
   rank[o] = r;
 }
 
-// Group prefix of a face: 0 for static geometry, 1 << rank_bits | the object's
-// spatial rank for a moving object's face.
+// Group of a face: its moving object, or -1 for static geometry (and for
+// every face when the objects are not separated: orank null).  Group prefix:
+// 0 for group -1, else 1 << rank_bits | the object's spatial rank.
+__device__ inline int face_group(const int32_t* face_object, const int32_t* orank, int f) {
+  return orank ? face_object[f] : -1;
+}
 __device__ inline uint32_t group_prefix(const int32_t* face_object, const int32_t* orank, int rank_bits, int f) {
-  const int obj = face_object[f];
+  const int obj = face_group(face_object, orank, f);
   return obj < 0 ? 0u : ((1u << rank_bits) | (uint32_t)orank[obj]);
 }
 
@@ -198,7 +202,7 @@ __global__ void k_face_keys(const float* __restrict__ V, const int32_t* __restri
   }
   float glo[3], gext[3], c[3];
   bounds_of(box, glo, gext);
-  const int obj = face_object[f];
+  const int obj = face_group(face_object, orank, f);
   if (obj >= 0)
     for (int k = 0; k < 3; ++k) {
       glo[k] = obj_box[6 * obj + k];
@@ -217,33 +221,35 @@ __global__ void k_face_keys(const float* __restrict__ V, const int32_t* __restri
 
 // First sorted position of each group's faces.
 __global__ void k_face_first(const uint32_t* __restrict__ fperm, int nf, const int32_t* __restrict__ face_object,
-                             int32_t* __restrict__ first) {
+                             const int32_t* __restrict__ orank, int32_t* __restrict__ first) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nf) return;
-  const int g = face_object[fperm[q]];
-  if (q == 0 || face_object[fperm[q - 1]] != g) first[g + 1] = q;
+  const int g = face_group(face_object, orank, (int)fperm[q]);
+  if (q == 0 || face_group(face_object, orank, (int)fperm[q - 1]) != g) first[g + 1] = q;
 }
 
 // Rank of each face among its group's faces, in sorted order.
 __global__ void k_face_rank(const uint32_t* __restrict__ fperm, int nf, const int32_t* __restrict__ face_object,
-                            const int32_t* __restrict__ first, int32_t* __restrict__ frank) {
+                            const int32_t* __restrict__ orank, const int32_t* __restrict__ first,
+                            int32_t* __restrict__ frank) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nf) return;
   const int f = (int)fperm[q];
-  frank[f] = q - first[face_object[f] + 1];
+  frank[f] = q - first[face_group(face_object, orank, f) + 1];
 }
 
-// Sort key of each triangle.  Without moving objects (or for a forced
-// rebuild): the 30-bit Morton code of its centroid in the centroid bounds.
-// Otherwise (key_hi non-null) the key is, from the most significant bit, the
-// group prefix of its face (static geometry 0, a moving object
-// 1 << rank_bits | the object's spatial rank), the face's rank among its
-// group's faces (face_bits bits) and the Morton code of the centroid in the
-// face's box.  The hierarchy built from these keys holds the static geometry,
-// every moving object and, inside those, every face in subtrees of their own:
-// rigid motion leaves the objects' subtrees tight under refitting, and a
-// planar face's triangles sit under a flat box.  Keys are stored as two words,
-// key_hi (bits 63..32) and key_lo (bits 31..0).
+// Sort key of each triangle.  key_hi null: the 30-bit Morton code of its
+// centroid in the centroid bounds.  Otherwise the key is, from the most
+// significant bit, the group prefix of its face (static geometry 0, a moving
+// object 1 << rank_bits | the object's spatial rank; no prefix when the
+// objects are not separated), the face's rank among its group's faces
+// (face_bits bits, frank null: none) and the Morton code of the centroid in
+// the face's box (frank null: in the object's box, or the centroid bounds).
+// The hierarchy built from these keys holds the static geometry, every moving
+// object and, inside those, every face in subtrees of their own: rigid motion
+// leaves the objects' subtrees tight under refitting, and a planar face's
+// triangles sit under a flat box.  Keys are stored as two words, key_hi (bits
+// 63..32) and key_lo (bits 31..0).
 __global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
                          const uint32_t* __restrict__ box, const int32_t* __restrict__ tri_face,
                          const int32_t* __restrict__ face_object, const int32_t* __restrict__ orank, int rank_bits,
@@ -262,8 +268,8 @@ __global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict_
     return;
   }
   const int f = tri_face[i];
+  const int obj = face_group(face_object, orank, f);
   const float* fb = fbox ? fbox + 6 * f : nullptr;   // without the face level: the object's box
-  const int obj = face_object[f];
   if (fb || obj >= 0) {
     if (!fb) fb = obj_box + 6 * obj;
     for (int k = 0; k < 3; ++k) {
@@ -828,10 +834,16 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   // cross-node index, list, parents and the listed slots of a refit
   if ((e = ensure(c->cross, sizeof(int32_t) * 5 * (size_t)ni)) != hipSuccess) return e;
   if ((e = ensure(c->node_range, sizeof(int2) * ni)) != hipSuccess) return e;
-  // sort keys (two words with moving objects), permutation, scratch, bounds,
-  // then the objects' codes and ranks
-  const int key_words = separate_objects && c->no > 0 ? 2 : 1;
+  // sort keys (two words with the object or face level), permutation,
+  // scratch, bounds, then the objects' codes and ranks
   const int no = c->no;
+  const bool objects = separate_objects && no > 0;
+  int rank_bits = 1;
+  while ((1 << rank_bits) < no) ++rank_bits;
+  const int prefix_bits = objects ? rank_bits + 1 : 0;
+  // the face level (with separated objects): a face's rank among its group's faces
+  const bool faces = objects && prefix_bits + c->face_bits + 30 <= 64;
+  const int key_words = objects || faces ? 2 : 1;
   if ((e = ensure(c->morton, sizeof(uint32_t) * ((key_words + 2) * nt + 8 + 2 * (size_t)no))) != hipSuccess)
     return e;
   const int64_t refit_blocks = (nt + kRefitBlock - 1) / kRefitBlock;
@@ -851,16 +863,12 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   uint32_t* perm_tmp = perm + nt;
   uint32_t* nbox = perm_tmp + nt;   // 6 ordered-bit words, then n
   uint32_t* ocode = nbox + 8;
-  int32_t* orank = reinterpret_cast<int32_t*>(ocode + no);
-  int rank_bits = 1;
-  while ((1 << rank_bits) < no) ++rank_bits;
-  // face level of the keys: group prefix (rank_bits + 1), face rank, Morton code
-  const int face_bits = 31 + rank_bits + c->face_bits <= 64 ? c->face_bits : -1;
+  int32_t* orank = objects ? reinterpret_cast<int32_t*>(ocode + no) : nullptr;
   hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, c->stream, nbox, (uint32_t)nt);
   const int nb = (int)std::min<int64_t>((nt + 255) / 256, 1024);
   hipLaunchKernelGGL(k_centroid_bounds, dim3(nb), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox);
-  if (key_words == 2) {
+  if (objects) {
     hipLaunchKernelGGL(k_object_codes, dim3((no + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->obj_box), no,
                        nbox, ocode);
     hipLaunchKernelGGL(k_object_rank, dim3((no + 255) / 256), dim3(256), 0, c->stream, ocode, no, orank);
@@ -868,7 +876,7 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   int32_t* frank = nullptr;
   float* fbox = nullptr;
   int fbits = 0;
-  if (key_words == 2 && face_bits >= 0) {
+  if (faces) {
     // faces in their groups' spatial order: boxes and keys, sort, ranks
     const int nf = c->nf;
     if ((e = ensure(c->face_build, sizeof(uint32_t) * (12 * (size_t)nf + (size_t)no + 16))) != hipSuccess) return e;
@@ -883,17 +891,17 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
     hipLaunchKernelGGL(k_face_keys, dim3(fb), dim3(256), 0, c->stream, ptr<float>(c->vertices), ptr<int32_t>(c->tris),
                        ptr<int32_t>(c->face_tri_off), ptr<int32_t>(c->face_tris), nf, ptr<int32_t>(c->face_object),
                        ptr<float>(c->obj_box), orank, rank_bits, nbox, fbox, fkey, fkey + nf, fn);
-    if ((e = radix_sort_perm(c, fkey, 2, 31 + rank_bits, fn, nf, fperm, ftmp, c->stream)) != hipSuccess) return e;
+    if ((e = radix_sort_perm(c, fkey, 2, 30 + prefix_bits, fn, nf, fperm, ftmp, c->stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_face_first, dim3(fb), dim3(256), 0, c->stream, fperm, nf, ptr<int32_t>(c->face_object),
-                       ffirst);
+                       orank, ffirst);
     hipLaunchKernelGGL(k_face_rank, dim3(fb), dim3(256), 0, c->stream, fperm, nf, ptr<int32_t>(c->face_object),
-                       ffirst, frank);
-    fbits = face_bits;
+                       orank, ffirst, frank);
+    fbits = c->face_bits;
   }
   hipLaunchKernelGGL(k_morton, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->vertices),
                      ptr<int32_t>(c->tris), nt, nbox, ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_object),
                      orank, rank_bits, frank, fbits, fbox, ptr<float>(c->obj_box), key_hi, key_lo);
-  const int key_bits = key_words == 2 ? 31 + rank_bits + fbits : 30;
+  const int key_bits = key_words == 2 ? prefix_bits + fbits + 30 : 30;
   if ((e = radix_sort_perm(c, code, key_words, key_bits, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess)
     return e;
   if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
