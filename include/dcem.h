@@ -204,8 +204,10 @@ dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n
  * round trip is needed: the ratio of a refit is read back by the next
  * synchronising call.  rebuilt / sah_ratio (nullable, host) receive the
  * decision and the ratio it was based on (1.0 right after a rebuild).
- * Asynchronous on the context stream; device errors are reported by the next
- * synchronising call.  The build at scene upload and the rebuilds the quality
+ * A rebuild is enqueued on the context stream at once; a refit is deferred to
+ * the next call that reads the tree or the vertices (a coherent
+ * dcem_trace_frame runs it in the same launch as its revalidation pass).
+ * Device errors are reported by the next synchronising call.  The build at scene upload and the rebuilds the quality
  * test asks for put the static geometry and every moving object, and inside
  * them every face, in subtrees of their own, so that refits under rigid motion
  * keep the tree tight; a

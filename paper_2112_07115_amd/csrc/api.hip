@@ -154,15 +154,19 @@ std::vector<Node> build_rx_tree(const std::vector<float>& rx, float radius) {
   return t.nodes;
 }
 
-void ev_record(dcem_ctx* c, int i, hipStream_t s = nullptr) {
-  if (c->timing) (void)hipEventRecord(c->ev[i], s ? s : c->stream);
+void ev_record(dcem_ctx* c, int i) {
+  if (c->timing) (void)hipEventRecord(c->ev[i], c->stream);
 }
 
-// Order the context stream after a refit still running on the refit stream.
-hipError_t join_refit(dcem_ctx* c) {
-  if (!c->refit_in_flight) return hipSuccess;
-  c->refit_in_flight = false;
-  return hipStreamWaitEvent(c->stream, c->ev_join, 0);
+// Enqueue a pending refit by itself (before anything that reads the tree or
+// the vertices, or when no revalidation pass can take it along).
+hipError_t flush_refit(dcem_ctx* c) {
+  if (!c->refit_pending) return hipSuccess;
+  c->refit_pending = false;
+  ev_record(c, 6);
+  launch_refit(c, true, c->sah_dev + 1);
+  ev_record(c, 7);
+  return hipGetLastError();
 }
 
 float ev_ms(dcem_ctx* c, int a, int b) {
@@ -178,7 +182,7 @@ constexpr size_t kBlockHead = 512;
 hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   n_pow = std::max<int64_t>(n_pow, 1);
   if (n_pow <= c->n_pow_cap && c->frame_block.p) return hipSuccess;
-  hipError_t je = join_refit(c);   // a refit in flight writes its SAH value here
+  hipError_t je = flush_refit(c);   // a pending refit writes its SAH value here
   if (je != hipSuccess) return je;
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
   // keep the head (SAH values of the current tree) across a reallocation
@@ -226,7 +230,7 @@ dcem_status sync_frame(dcem_ctx* c) {
     c->copy_pending = false;
     HIP_TRY(hipEventSynchronize(c->ev_copy), "synchronize");
   } else {
-    HIP_TRY(join_refit(c), "wait for refit");   // a refit in flight writes its SAH value into the block
+    HIP_TRY(flush_refit(c), "refit");   // a pending refit writes its SAH value into the block
     HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, frame_block_bytes(c), hipMemcpyDeviceToHost, c->stream),
             "read results");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
@@ -292,10 +296,7 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
     return DCEM_E_OUT_OF_MEMORY;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
-  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming) != hipSuccess) {
     dcem_destroy(c);
     return DCEM_E_DEVICE;
   }
@@ -306,7 +307,6 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
 void dcem_destroy(dcem_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  if (c->aux) (void)hipStreamSynchronize(c->aux);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
@@ -324,10 +324,7 @@ void dcem_destroy(dcem_ctx* c) {
   if (c->host_block) (void)hipHostFree(c->host_block);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
-  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -366,7 +363,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
       (s->n_objects && !s->object_vertex_range))
     return fail(c, DCEM_E_INVALID_ARG, "null array with nonzero size");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  c->refit_pending = false;   // the new scene is built from scratch
   std::vector<float> V;
   std::vector<int32_t> T, TF, FM, FO;
   std::vector<double> M;
@@ -487,7 +484,7 @@ dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_o
   if (n_objects == 0) return DCEM_OK;
   if (!xf) return fail(c, DCEM_E_INVALID_ARG, "null transforms");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   if (mem_kind == DCEM_MEM_HOST) {
     for (int i = 0; i < 12 * n_objects; ++i)
       if (!std::isfinite(xf[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite transform entry %d", i);
@@ -509,30 +506,25 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   if (std::isnan(threshold)) return fail(c, DCEM_E_INVALID_ARG, "threshold is NaN");
   if (threshold <= 0.0) threshold = 1.5;
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  // a refit still pending reads the same vertices as this one: it is kept (or dropped by a rebuild)
   // the decision uses the quality measured after the previous refit (read at
   // the last synchronisation), so no host round trip is needed here
   const double measured = c->pending_ratio;
   int32_t rb = 0;
   if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
+    c->refit_pending = false;
     ev_record(c, 6);
     // a forced rebuild serves the frame at hand; one the quality test asks
     // for keeps the objects apart for the refits that follow
     HIP_TRY(build_lbvh(c, !(flags & DCEM_FORCE_REBUILD)), "rebuild BVH");
     rb = 1;
+    ev_record(c, 7);
   } else {
-    // on the refit stream, after the transforms enqueued so far
-    HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork refit");
-    HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0), "fork refit");
-    ev_record(c, 6, c->aux);
-    launch_refit(c, true, c->sah_dev + 1, c->aux);
-    HIP_TRY(hipGetLastError(), "refit kernel");
-    ev_record(c, 7, c->aux);
-    HIP_TRY(hipEventRecord(c->ev_join, c->aux), "join refit");
-    c->refit_in_flight = true;
+    // enqueued by the next call that needs the tree (a coherent trace runs
+    // it in one launch with its revalidation pass)
+    c->refit_pending = true;
     c->refit_since_build = true;
   }
-  if (rb) ev_record(c, 7);
   c->bvh_stale = false;
   c->last_rebuilt = rb;
   c->refit_pending_timing = true;
@@ -656,7 +648,6 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   // its re-trace count (sizes the persistent grid) and its capture count (picks
   // the de-duplication path)
   if (c->has_frame && !c->counts_current) {
-    HIP_TRY(join_refit(c), "wait for refit");
     dcem_status st = sync_frame(c);
     if (st != DCEM_OK) return st;
   }
@@ -667,9 +658,17 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   ev_record(c, 0);
   c->cur_caps ^= 1;
   launch_frame_begin(c, p->los_always != 0);
-  if (coherent) launch_coherence(c);   // does not read the tree: overlaps a refit in flight
+  if (coherent && c->refit_pending) {
+    // the revalidation does not read the tree: one launch with the refit
+    c->refit_pending = false;
+    ev_record(c, 6);
+    launch_refit_coherence(c);
+    ev_record(c, 7);
+  } else {
+    HIP_TRY(flush_refit(c), "refit");
+    if (coherent) launch_coherence(c);
+  }
   ev_record(c, 1);
-  HIP_TRY(join_refit(c), "wait for refit");
   c->last_trace_kernel =
       n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work, n_prev) : 0;
   ev_record(c, 2);
@@ -758,7 +757,7 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
@@ -815,7 +814,7 @@ dcem_status dcem_get_trace_log(dcem_ctx* c, int32_t* tri, float* t, float* lengt
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (!c->record_log) return fail(c, DCEM_E_STATE, "trace log not recorded (record_trace_log = 0)");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const size_t n = (size_t)c->n_tx * c->n_rays * (c->K + 1);
@@ -831,7 +830,7 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   if (cap < 0) return fail(c, DCEM_E_INVALID_ARG, "negative capacity");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
   const int64_t nc = c->n_caps_host;
@@ -875,7 +874,7 @@ dcem_status dcem_get_bvh(dcem_ctx* c, int64_t cap_internal, int32_t* n_internal,
   c->err.clear();
   if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   const int32_t ni = c->nt > 0 ? c->n_internal : 0;
   if (n_internal) *n_internal = ni;
@@ -899,7 +898,7 @@ dcem_status dcem_get_vertices(dcem_ctx* c, float* out) {
   c->err.clear();
   if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   if (c->nv) HIP_TRY(hipMemcpy(out, c->vertices.p, sizeof(float) * 3 * c->nv, hipMemcpyDeviceToHost), "copy vertices");
   return check_device_error(c);
@@ -910,7 +909,7 @@ dcem_status dcem_get_ray_dirs(dcem_ctx* c, float* out) {
   c->err.clear();
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  HIP_TRY(join_refit(c), "wait for refit");
+  HIP_TRY(flush_refit(c), "refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   if (c->n_rays) HIP_TRY(hipMemcpy(out, c->dirs.p, sizeof(float) * 3 * c->n_rays, hipMemcpyDeviceToHost), "copy dirs");
   return DCEM_OK;

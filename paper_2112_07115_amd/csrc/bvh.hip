@@ -7,6 +7,7 @@
 // refit bottom-up with arrival counters, and scored by the SAH surface-area
 // sum relative to the last build.
 #include "dcem_internal.h"
+#include "refit.h"
 
 #include <cfloat>
 
@@ -86,8 +87,6 @@ __global__ void k_set2(uint32_t* p, uint32_t a, uint32_t* q, uint32_t b) {
     *q = b;
   }
 }
-
-__device__ inline float3 load_v(const float* v, int i) { return make_float3(v[3 * i], v[3 * i + 1], v[3 * i + 2]); }
 
 // Bounds of the triangle centroids (exact min/max through order-preserving bits).
 __global__ void k_centroid_bounds(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nt,
@@ -336,47 +335,6 @@ __global__ void k_karras(const uint32_t* __restrict__ key_hi, const uint32_t* __
   if (i == 0) nodes[0].c.z = -1;
 }
 
-// Binary slot 0 is floats 0-5 of the node (b0, b1.xy), slot 1 floats 6-11
-// (b1.zw, b2): two vector stores each.
-__device__ inline void store_slot(Node* nd, int slot, const float* lo, const float* hi) {
-  if (slot == 0) {
-    nd->b0 = make_float4(lo[0], lo[1], lo[2], hi[0]);
-    *reinterpret_cast<float2*>(&nd->b1.x) = make_float2(hi[1], hi[2]);
-  } else {
-    *reinterpret_cast<float2*>(&nd->b1.z) = make_float2(lo[0], lo[1]);
-    nd->b2 = make_float4(lo[2], hi[0], hi[1], hi[2]);
-  }
-}
-
-__device__ inline void load_slot_coherent(Node* nd, int slot, float* lo, float* hi) {
-  float* f = reinterpret_cast<float*>(nd);
-  const int base = slot * 6;
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-constexpr int kRefitBlock = 1024;
-
-// Leaf record of triangle `tri` (vertices; id, face and moving flag in w).
-__device__ inline Leaf leaf_record(const float* __restrict__ V, const int32_t* __restrict__ T,
-                                   const int32_t* __restrict__ tri_face, const int32_t* __restrict__ face_object,
-                                   int tri) {
-  const float3 a = load_v(V, T[3 * tri]), b = load_v(V, T[3 * tri + 1]), c = load_v(V, T[3 * tri + 2]);
-  const int face = tri_face[tri];
-  Leaf L;
-  L.v0 = make_float4(a.x, a.y, a.z, __int_as_float(tri));
-  L.v1 = make_float4(b.x, b.y, b.z, __int_as_float(face));
-  L.v2 = make_float4(c.x, c.y, c.z, __int_as_float(face_object[face] >= 0 ? 1 : 0));
-  return L;
-}
-
-__device__ inline void store_box4(Slot4* sl, const float* lo, const float* hi) {
-  *reinterpret_cast<float3*>(&sl->lx) = make_float3(lo[0], lo[1], lo[2]);
-  *reinterpret_cast<float3*>(&sl->hx) = make_float3(hi[0], hi[1], hi[2]);
-}
-
 // Binary nodes whose leaf range spans several refit blocks ("cross" nodes):
 // listed once per build with their list index per node (-1 otherwise) and the
 // list index and slot of their parent (the parent of a cross node is one too).
@@ -403,279 +361,7 @@ __global__ void k_cross_parent(const Node* __restrict__ nodes, const int32_t* __
   cross_parent[k] = p2 < 0 ? -1 : (cross_index[p2 >> 1] << 1) | (p2 & 1);
 }
 
-__device__ inline double box_area(const float* lo, const float* hi) {
-  double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
-  return 2.0 * (dx * dy + dy * dz + dz * dx);
-}
-
-// Unit normal n and offset n . a of the plane of face f (FP64, from the
-// face's reference triangle a, b, c: n = (b - a) x (c - a) normalised).
-__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
-                                  double4* __restrict__ plane, int f) {
-  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
-  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
-  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
-  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
-  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
-  const double l = sqrt(nx * nx + ny * ny + nz * nz);
-  nx /= l;
-  ny /= l;
-  nz /= l;
-  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
-}
-
-struct RefitArgs {
-  const float* V;
-  const int32_t* T;
-  const int32_t* tri_face;
-  const int32_t* face_object;
-  const int32_t* leaf_tri;
-  const int32_t* leaf_parent;
-  Node* nodes;
-  uint32_t* cnt;              // device-wide arrival counters (cross nodes, when not two-phase)
-  float* root_box;
-  int n;                      // leaves
-  int n_internal;
-  float pad;
-  bool wide;                  // also update the 4-wide tree
-  const int32_t* slot4;
-  const int32_t* leaf_slot;
-  Node4* nodes4;
-  Leaf* tri4;
-  const int32_t* cross_index; // [n_internal]
-  const int32_t* cross_list;  // [n_cross]
-  const int32_t* cross_parent;
-  uint32_t* entries;          // binary slots of cross nodes filled by the block pass
-  uint32_t* info;             // [2] cross nodes, [3] entries, [4] finished blocks
-  double* part;               // per-block surface-area sums
-  double* sah_out;            // SAH ratio of the refitted tree
-  const int32_t* face_ref_tri;
-  int nf;
-  double4* plane;             // per face: unit normal and offset
-};
-
-// A child box of binary node `p2 >> 1` (slot p2 & 1): in the binary tree and,
-// refitting a collapsed tree, in the 4-wide slot d that holds it (slot4[p2]).
-__device__ inline void put_child_box(const RefitArgs& a, int p2, int d, const float* lo, const float* hi) {
-  store_slot(&a.nodes[p2 >> 1], p2 & 1, lo, hi);
-  if (a.wide && d >= 0) store_box4(&a.nodes4[d >> 2].s[d & 3], lo, hi);
-}
-
-constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
-
-// Sum of v over the block (kRefitBlock threads), valid in thread 0, in a fixed
-// order: butterflies within each wavefront, then the wavefronts' sums in order.
-__device__ inline double block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  __syncthreads();   // red may still be read by an earlier sum
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kRefitBlock / kWave; ++w) t += red[w];
-  return t;
-}
-
-// Last-block pass of the refit: finish the cross nodes in LDS, from the slots
-// the block pass listed up to the root.
-__device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t n_cross, float (*lbox)[12], uint32_t* lcnt,
-                                   int32_t* lpar, int32_t* lnode, int2* lslot4, int2* lkid) {
-  const int tid = threadIdx.x;
-  const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
-    lcnt[k] = 0;
-    lpar[k] = a.cross_parent[k];
-    const int node = a.cross_list[k];
-    lnode[k] = node;
-    lkid[k] = make_int2(a.nodes[node].c.x, a.nodes[node].c.y);
-    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
-  }
-  __syncthreads();
-  if (tid == 0) a.info[3] = 0;   // ready for the next refit
-  for (uint32_t e = tid; e < n_ent; e += kRefitBlock) {
-    const int p2 = (int)__hip_atomic_load(&a.entries[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int k = a.cross_index[p2 >> 1], slot = p2 & 1;
-    float lo[3], hi[3];
-    load_slot_coherent(&a.nodes[p2 >> 1], slot, lo, hi);
-    for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
-      float* bx = lbox[k] + 6 * slot;
-      for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
-      const uint32_t old = __hip_atomic_fetch_add(&lcnt[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) break;
-      const float* sb = lbox[k] + 6 * (slot ^ 1);
-      for (int q = 0; q < 3; ++q) {
-        lo[q] = fminf(lo[q], sb[q]);
-        hi[q] = fmaxf(hi[q], sb[3 + q]);
-      }
-      const int kp = lpar[k];
-      if (kp < 0) {
-        for (int q = 0; q < 3; ++q) { a.root_box[q] = lo[q]; a.root_box[3 + q] = hi[q]; }
-        break;
-      }
-      k = kp >> 1;
-      slot = kp & 1;
-      const int2 ds = a.wide ? lslot4[k] : make_int2(-1, -1);
-      put_child_box(a, (lnode[k] << 1) | slot, slot ? ds.y : ds.x, lo, hi);
-    }
-  }
-}
-
-// Bottom-up refit over a fixed topology, in two passes of one kernel.
-// Block pass: one thread per leaf writes its padded box into its parent's
-// slot; the second thread to arrive at a node forms the union and climbs on.
-// An internal node covers a contiguous range of sorted leaves and is one end
-// of it, so a node whose range lies inside this block's 1024 leaves has both
-// children here: its boxes, arrival counter and parent link live in LDS.  A
-// thread stops at the first cross node (range spanning blocks), leaving its
-// box in that node's slot and the slot in a list.  Last-block pass: the last
-// block to finish finishes every cross node the same way in LDS, from the
-// listed slots up to the root.  (With more cross nodes than LDS holds, cross
-// nodes use device-wide arrival counters in the block pass instead.)  Boxes
-// are min/max of FP32 values: the result does not depend on the order of
-// arrival.  With `wide` (a refit of a collapsed tree) every child box stored
-// in a binary slot is also stored in the 4-wide slot that holds it and the leaf
-// thread writes its triangle to its slot, so no separate collapse is needed.
-// The same kernel measures the tree: the surface areas of the internal nodes
-// below the root (each node's internal children), summed per block in a fixed
-// order and over blocks by the last block, over the root's area (sah_out); and
-// it computes every face's plane (used by the refinement's image method).
-__global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) {
-  // block pass: slot boxes, counters, parent links and cross flags of the
-  // block's nodes; last-block pass: the same for the cross nodes
-  __shared__ float lbox[kRefitBlock][12];
-  __shared__ uint32_t lcnt[kRefitBlock];
-  __shared__ int32_t lpar[kRefitBlock];
-  __shared__ int32_t lnode[kRefitBlock];
-  __shared__ int2 lslot4[kRefitBlock];   // the 4-wide slots of the node's two child boxes
-  __shared__ int2 lkid[kRefitBlock];     // child entries (>= 0: internal)
-  __shared__ double red[kRefitBlock / kWave];
-  __shared__ bool last;
-  for (int f = blockIdx.x * kRefitBlock + threadIdx.x; f < a.nf; f += gridDim.x * kRefitBlock)
-    face_plane(a.V, a.T, a.face_ref_tri[f], a.plane, f);
-  const int b0 = blockIdx.x * kRefitBlock;
-  const int tid = threadIdx.x;
-  const uint32_t n_cross = a.info[2];
-  const bool two_phase = n_cross <= (uint32_t)kMaxCross;
-  {
-    const int node = b0 + tid;
-    lcnt[tid] = 0;
-    const bool ok = node < a.n_internal;
-    lpar[tid] = ok ? a.nodes[node].c.z : -1;
-    lnode[tid] = ok && a.cross_index[node] < 0;   // block-local
-    lkid[tid] = ok ? make_int2(a.nodes[node].c.x, a.nodes[node].c.y) : make_int2(-1, -1);
-    if (a.wide && ok) lslot4[tid] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
-  }
-  __syncthreads();
-  const int i = b0 + tid;
-  if (i < a.n) {
-    const Leaf L = leaf_record(a.V, a.T, a.tri_face, a.face_object, a.leaf_tri[i]);
-    if (a.wide) a.tri4[a.leaf_slot[i]] = L;
-    float lo[3] = {fminf(L.v0.x, fminf(L.v1.x, L.v2.x)) - a.pad, fminf(L.v0.y, fminf(L.v1.y, L.v2.y)) - a.pad,
-                   fminf(L.v0.z, fminf(L.v1.z, L.v2.z)) - a.pad};
-    float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + a.pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + a.pad,
-                   fmaxf(L.v0.z, fmaxf(L.v1.z, L.v2.z)) + a.pad};
-    if (a.n == 1) {   // the root holds the one leaf in both slots
-      put_child_box(a, 0, 0, lo, hi);
-      put_child_box(a, 1, 1, lo, hi);
-      if (a.wide) a.tri4[1] = L;
-      for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
-    } else {
-      int p2 = a.leaf_parent[i];
-      for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
-        const int node = p2 >> 1, slot = p2 & 1;
-        const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
-        int d = -1;
-        if (a.wide) {
-          if (local) {
-            const int2 ds = lslot4[node - b0];
-            d = slot ? ds.y : ds.x;
-          } else {
-            d = a.slot4[p2];
-          }
-        }
-        put_child_box(a, p2, d, lo, hi);
-        float slo[3], shi[3];
-        if (local) {
-          float* bx = lbox[node - b0] + 6 * slot;
-          for (int k = 0; k < 3; ++k) { bx[k] = lo[k]; bx[3 + k] = hi[k]; }
-          const uint32_t old = __hip_atomic_fetch_add(&lcnt[node - b0], 1u, __ATOMIC_ACQ_REL,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (old == 0) break;
-          const float* sb = lbox[node - b0] + 6 * (slot ^ 1);
-          for (int k = 0; k < 3; ++k) { slo[k] = sb[k]; shi[k] = sb[3 + k]; }
-        } else if (two_phase) {
-          a.entries[atomicAdd(&a.info[3], 1u)] = (uint32_t)p2;
-          break;
-        } else {
-          const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-          if (old == 0) break;
-          a.cnt[node] = 0;
-          load_slot_coherent(&a.nodes[node], slot ^ 1, slo, shi);
-        }
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = fminf(lo[k], slo[k]);
-          hi[k] = fmaxf(hi[k], shi[k]);
-        }
-        p2 = local ? lpar[node - b0] : a.nodes[node].c.z;
-        if (p2 < 0) {
-          for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
-          break;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // areas of the internal children of this block's local nodes
-  {
-    double ar = 0.0;
-    if (lnode[tid]) {
-      if (lkid[tid].x >= 0) ar += box_area(lbox[tid], lbox[tid] + 3);
-      if (lkid[tid].y >= 0) ar += box_area(lbox[tid] + 6, lbox[tid] + 9);
-    }
-    ar = block_sum(ar, red);
-    if (tid == 0) {
-      __hip_atomic_store(&a.part[blockIdx.x], ar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
-    }
-    __syncthreads();
-  }
-  if (!last) return;
-  // ---- the last block to finish completes the cross nodes and the SAH sum
-  if (tid == 0) a.info[4] = 0;   // ready for the next refit
-  if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
-  __syncthreads();
-  // areas of the cross nodes' internal children (in LDS after the two-phase
-  // pass, else in the binary nodes), plus the blocks' sums
-  double ar = 0.0;
-  for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
-    if (two_phase) {
-      if (lkid[k].x >= 0) ar += box_area(lbox[k], lbox[k] + 3);
-      if (lkid[k].y >= 0) ar += box_area(lbox[k] + 6, lbox[k] + 9);
-      continue;
-    }
-    const int node = a.cross_list[k];
-    float lo[3], hi[3];
-    if (a.nodes[node].c.x >= 0) {
-      load_slot_coherent(&a.nodes[node], 0, lo, hi);
-      ar += box_area(lo, hi);
-    }
-    if (a.nodes[node].c.y >= 0) {
-      load_slot_coherent(&a.nodes[node], 1, lo, hi);
-      ar += box_area(lo, hi);
-    }
-  }
-  for (unsigned b = tid; b < gridDim.x; b += kRefitBlock)
-    ar += __hip_atomic_load(&a.part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double t = block_sum(ar, red);
-  if (tid != 0) return;
-  float rlo[3], rhi[3];
-  for (int q = 0; q < 3; ++q) {
-    rlo[q] = __hip_atomic_load(&a.root_box[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    rhi[q] = __hip_atomic_load(&a.root_box[3 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  const double root = box_area(rlo, rhi);
-  *a.sah_out = root > 0 ? (t + root) / root : 1.0;
-}
+__global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) { refit_block(a, blockIdx.x, gridDim.x); }
 
 
 
@@ -929,7 +615,7 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
                      cross, cross + ni, info + 2);
   hipLaunchKernelGGL(k_cross_parent, dim3((ni + 255) / 256), dim3(256), 0, c->stream, ptr<Node>(c->nodes), cross,
                      cross + ni, info + 2, ni, cross + 2 * (size_t)ni);
-  launch_refit(c, false, c->sah_dev + 0, c->stream);
+  launch_refit(c, false, c->sah_dev + 0);
   // 4-wide tree: binary nodes at even depth, breadth-first
   uint32_t* dkey = ptr<uint32_t>(c->depth_key);
   uint32_t* dperm = dkey + ni;
@@ -956,8 +642,7 @@ void launch_collapse(dcem_ctx* c) {
                      ptr<Leaf>(c->tri4), ptr<int32_t>(c->leaf_slot), ptr<int32_t>(c->slot4));
 }
 
-void launch_refit(dcem_ctx* c, bool wide, double* sah_out, hipStream_t s) {
-  if (c->nt == 0) return;
+RefitArgs make_refit_args(dcem_ctx* c, bool wide, double* sah_out) {
   const int ni = c->n_internal;
   int32_t* cross = ptr<int32_t>(c->cross);
   RefitArgs a;
@@ -988,7 +673,15 @@ void launch_refit(dcem_ctx* c, bool wide, double* sah_out, hipStream_t s) {
   a.face_ref_tri = ptr<int32_t>(c->face_ref_tri);
   a.nf = c->nf;
   a.plane = ptr<double4>(c->face_plane);
-  hipLaunchKernelGGL(k_refit, dim3((unsigned)((c->nt + kRefitBlock - 1) / kRefitBlock)), dim3(kRefitBlock), 0, s, a);
+  return a;
+}
+
+int refit_blocks(const dcem_ctx* c) { return (int)((c->nt + kRefitBlock - 1) / kRefitBlock); }
+
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
+  if (c->nt == 0) return;
+  hipLaunchKernelGGL(k_refit, dim3((unsigned)refit_blocks(c)), dim3(kRefitBlock), 0, c->stream,
+                     make_refit_args(c, wide, sah_out));
 }
 
 

@@ -102,12 +102,10 @@ struct dcem_ctx {
   int device = 0;
   int n_cus = 0;                                     // compute units of the device (0: not queried yet)
   hipStream_t stream = nullptr;
-  // A refit runs on its own stream, concurrently with the revalidation pass of
-  // the next frame (which does not read the tree); the context stream waits
-  // for ev_join before anything that reads the tree or the vertices.
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool refit_in_flight = false;
+  // A refit is enqueued lazily: by the next trace, in one launch with the
+  // revalidation pass of a coherent frame (which does not read the tree), or
+  // by the first call that reads the tree or the vertices.
+  bool refit_pending = false;
   hipEvent_t ev_copy = nullptr;   // the last traced frame's results have reached host_block
   bool copy_pending = false;
   std::string err;
@@ -223,7 +221,7 @@ void launch_xform(dcem_ctx* c, const float* xf);
 hipError_t build_lbvh(dcem_ctx* c, bool separate_objects);
 // Refit the binary tree (`wide`: and the 4-wide tree in place, no collapse
 // needed), write the SAH ratio to sah_out and the face planes.
-void launch_refit(dcem_ctx* c, bool wide, double* sah_out, hipStream_t s);
+void launch_refit(dcem_ctx* c, bool wide, double* sah_out);
 void launch_collapse(dcem_ctx* c);
 
 // ---- radix sort (sort.hip)
@@ -240,6 +238,8 @@ void launch_fibonacci(dcem_ctx* c);
 // 0 one thread per ray, 1 one group of lanes per ray.
 int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps);
 void launch_coherence(dcem_ctx* c);
+// The pending refit of the 4-wide tree and the revalidation pass in one launch.
+void launch_refit_coherence(dcem_ctx* c);
 // Clear the frame counters and seed the capture list with the LoS candidates.
 void launch_frame_begin(dcem_ctx* c, bool los);
 hipError_t build_ray_order(dcem_ctx* c);

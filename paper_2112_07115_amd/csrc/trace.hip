@@ -9,6 +9,7 @@
 // when none of its segments can meet moved geometry; only the others are
 // traced again, which reproduces the full re-trace exactly.
 #include "dcem_internal.h"
+#include "refit.h"
 
 #include <cfloat>
 
@@ -832,29 +833,60 @@ constexpr int kCohMaxCells = 16;   // wider xy bounds test every box
 constexpr int kCohBatch = 5;       // cached segments loaded at once
 constexpr int kCohList = 4096;     // invalid rays a block collects before one list append
 
-__global__ __launch_bounds__(kCohBlock) void k_coherence(
-    const uint8_t* __restrict__ ray_state, const float4* __restrict__ seg_o, const float4* __restrict__ seg_d,
-    const int32_t* __restrict__ face_log, const int32_t* __restrict__ face_object, const float* __restrict__ obj_box,
-    int n_obj, int n_work, float margin, uint8_t* __restrict__ restart, uint32_t* __restrict__ list,
-    uint32_t* counters) {
+struct CohArgs {
+  const uint8_t* ray_state;
+  const float4* seg_o;
+  const float4* seg_d;
+  const int32_t* face_log;
+  const int32_t* face_object;
+  const float* obj_box;
+  int n_obj;
+  int n_work;
+  const float* tx;
+  int64_t n_rays;
+  float margin;
+  uint8_t* restart;
+  uint32_t* list;
+  uint32_t* counters;
+  int list_cap;   // invalid rays a block collects in LDS (dynamic, after the grid)
+};
+
+// One block of the revalidation pass: block cb of n_cb, blockDim.x threads.
+__device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int n_cb) {
+  const uint8_t* __restrict__ ray_state = args.ray_state;
+  const float4* __restrict__ seg_o = args.seg_o;
+  const float4* __restrict__ seg_d = args.seg_d;
+  const int32_t* __restrict__ face_log = args.face_log;
+  const int32_t* __restrict__ face_object = args.face_object;
+  const float* __restrict__ obj_box = args.obj_box;
+  const int n_obj = args.n_obj, n_work = args.n_work;
+  const float* __restrict__ tx = args.tx;
+  const int64_t n_rays = args.n_rays;
+  const float margin = args.margin;
+  uint8_t* __restrict__ restart = args.restart;
+  uint32_t* __restrict__ list = args.list;
+  uint32_t* counters = args.counters;
+  const int nth = blockDim.x;
   // dynamic LDS (grid mode): cell bits [cell][word], then the boxes [6][n_obj]
   extern __shared__ unsigned long long coh_lds[];
   __shared__ uint32_t ext[6];   // ordered bits: min x, min y, min z, max x, max y, max z
-  // the block's invalid rays, appended to the global list with one atomic at
-  // the end (a counter shared by every wavefront of the grid would serialise)
-  __shared__ uint32_t blist[kCohList];
+  // the block's invalid rays (dynamic LDS after the grid), appended to the
+  // global list with one atomic at the end (a counter shared by every
+  // wavefront of the grid would serialise)
   __shared__ uint32_t bcount, bbase;
+  const int kList = args.list_cap;
   if (threadIdx.x == 0) bcount = 0;
   const bool grid = n_obj <= kCohGridObjects;
   const int words = (n_obj + 63) / 64;
   unsigned long long* cell = coh_lds;
-  float* blf = reinterpret_cast<float*>(coh_lds + kCohGrid * kCohGrid * words);
+  float* blf = reinterpret_cast<float*>(coh_lds + (grid ? kCohGrid * kCohGrid * words : 0));
+  uint32_t* blist = reinterpret_cast<uint32_t*>(blf + (grid ? 6 * n_obj : 0));
   auto bl = [&](int a, int b) -> float& { return blf[a * n_obj + b]; };
   if (threadIdx.x < 6) ext[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;
   if (grid)
-    for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += kCohBlock) cell[c] = 0ull;
+    for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += nth) cell[c] = 0ull;
   __syncthreads();
-  for (int b = threadIdx.x; b < n_obj; b += kCohBlock) {
+  for (int b = threadIdx.x; b < n_obj; b += nth) {
     for (int a = 0; a < 3; ++a) {
       const float lo = obj_box[6 * b + a], hi = obj_box[6 * b + 3 + a];
       if (grid) {
@@ -877,7 +909,7 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
   auto cx = [&](float x) { return cell_of((x - gx0) * sx); };
   auto cy = [&](float y) { return cell_of((y - gy0) * sy); };
   if (grid) {
-    for (int b = threadIdx.x; b < n_obj; b += kCohBlock) {
+    for (int b = threadIdx.x; b < n_obj; b += nth) {
       const int x0 = cx(bl(0, b)), x1 = cx(bl(3, b)), y0 = cy(bl(1, b)), y1 = cy(bl(4, b));
       for (int y = y0; y <= y1; ++y)
         for (int x = x0; x <= x1; ++x) atomicOr(&cell[(y * kCohGrid + x) * words + (b >> 6)], 1ull << (b & 63));
@@ -886,7 +918,7 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   // blocks stride over the rays (the grid above is built once per block)
-  for (int base0 = blockIdx.x * kCohBlock; base0 < n_work; base0 += gridDim.x * kCohBlock) {
+  for (int base0 = cb * nth; base0 < n_work; base0 += n_cb * nth) {
     const int i = base0 + threadIdx.x;
     int first = 255;
     const uint32_t w = (uint32_t)i;
@@ -955,25 +987,41 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
         }
         return false;
       };
-      // segments in batches whose loads are issued together
-      for (int k0 = 0; k0 < nseg && first == 255; k0 += kCohBatch) {
-        float4 bo[kCohBatch], bd[kCohBatch];
+      // The ray's polyline: its transmitter, then the origin of each later
+      // segment (a reflection starts exactly at the previous segment's end
+      // point), then the last segment's direction and extent.  Segment k < last
+      // runs from origin k to origin k + 1.  Origins are loaded in batches, so
+      // a ray of n >= 2 segments reads n cached 16-byte records.
+      const int last = nseg - 1;
+      const uint32_t txi = (uint32_t)(w / (uint64_t)n_rays);
+      float4 prev = make_float4(tx[3 * txi], tx[3 * txi + 1], tx[3 * txi + 2], 0.0f);   // origin of segment k0
+      if (last == 0) prev.w = seg_o[w].w;   // the one segment's extent
+      for (int k0 = 0; k0 <= last && first == 255; k0 += kCohBatch) {
+        float4 nxt[kCohBatch];   // origin of segment k0 + j + 1 (its extent in w)
         int bf[kCohBatch];
+        float4 dl = make_float4(0.f, 0.f, 0.f, 0.f);
+        const bool has_last = last < k0 + kCohBatch;
 #pragma unroll
         for (int j = 0; j < kCohBatch; ++j) {
           const int k = k0 + j;
           bf[j] = -1;
-          if (k < nseg) {
-            bo[j] = seg_o[(size_t)k * n_work + w];
-            bd[j] = seg_d[(size_t)k * n_work + w];
-            if (moving_hit) bf[j] = face_log[(size_t)k * n_work + w];
-          }
+          if (k + 1 <= last) nxt[j] = seg_o[(size_t)(k + 1) * n_work + w];
+          if (k <= last && moving_hit) bf[j] = face_log[(size_t)k * n_work + w];
         }
+        if (has_last) dl = seg_d[(size_t)last * n_work + w];
 #pragma unroll
         for (int j = 0; j < kCohBatch; ++j) {
           const int k = k0 + j;
-          if (k >= nseg || first != 255) break;
-          if ((bf[j] >= 0 && face_object[bf[j]] >= 0) || meets_moving(bo[j], bd[j])) first = k;
+          if (k > last || first != 255) break;
+          float4 o = prev, d;
+          if (k < last) {
+            o.w = 1.0f;
+            d = make_float4(nxt[j].x - prev.x, nxt[j].y - prev.y, nxt[j].z - prev.z, 0.0f);
+            prev = nxt[j];
+          } else {
+            d = dl;
+          }
+          if ((bf[j] >= 0 && face_object[bf[j]] >= 0) || meets_moving(o, d)) first = k;
         }
       }
       restart[w] = (uint8_t)first;
@@ -986,16 +1034,26 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(
       base = __shfl(base, 0);
       if (bad) {
         const uint32_t p = base + __popcll(m & ((1ull << lane) - 1ull));
-        if (p < kCohList) blist[p] = w;
+        if (p < (uint32_t)kList) blist[p] = w;
         else list[atomicAdd(&counters[kCntWork], 1u)] = w;   // only when a block is given more rays
       }
     }
   }
   __syncthreads();
-  const uint32_t nb = min(bcount, (uint32_t)kCohList);
+  const uint32_t nb = min(bcount, (uint32_t)kList);
   if (threadIdx.x == 0 && nb) bbase = atomicAdd(&counters[kCntWork], nb);
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < nb; j += kCohBlock) list[bbase + j] = blist[j];
+  for (uint32_t j = threadIdx.x; j < nb; j += nth) list[bbase + j] = blist[j];
+}
+
+__global__ __launch_bounds__(kCohBlock) void k_coherence(CohArgs a) { coherence_block(a, blockIdx.x, gridDim.x); }
+
+// A coherent frame's refit and revalidation in one launch: blocks [0, n_rb)
+// refit the tree, the others revalidate the cached rays (which do not read the
+// tree), so the latency-bound refit overlaps the revalidation.
+__global__ __launch_bounds__(kRefitBlock) void k_refit_coherence(RefitArgs ra, CohArgs ca, int n_rb) {
+  if ((int)blockIdx.x < n_rb) refit_block(ra, blockIdx.x, n_rb);
+  else coherence_block(ca, blockIdx.x - n_rb, gridDim.x - n_rb);
 }
 
 
@@ -1111,21 +1169,59 @@ void launch_frame_begin(dcem_ctx* c, bool los) {
                      c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), n_los, c->cap_capacity, c->err_dev);
 }
 
+CohArgs coherence_args(dcem_ctx* c) {
+  CohArgs a;
+  a.ray_state = ptr<uint8_t>(c->ray_state);
+  a.seg_o = ptr<float4>(c->seg_o);
+  a.seg_d = ptr<float4>(c->seg_d);
+  a.face_log = ptr<int32_t>(c->face_log);
+  a.face_object = ptr<int32_t>(c->face_object);
+  a.obj_box = ptr<float>(c->obj_box);
+  a.n_obj = c->no;
+  a.n_work = (int)((int64_t)c->n_tx * c->n_rays);
+  a.tx = ptr<float>(c->tx_pos);
+  a.n_rays = c->n_rays;
+  a.margin = 1e-3f + c->pad;
+  a.restart = ptr<uint8_t>(c->invalid_flag);
+  a.list = ptr<uint32_t>(c->work_list);
+  a.counters = c->cnt_dev;
+  return a;
+}
+
+// dynamic LDS of the revalidation: the object grid and boxes (none beyond
+// kCohGridObjects objects, which are then tested one by one), then the
+// block's list of invalid rays
+size_t coherence_lds(const dcem_ctx* c, int list_cap) {
+  return (c->no <= kCohGridObjects
+              ? sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) + sizeof(float) * 6 * c->no
+              : 0) +
+         sizeof(uint32_t) * list_cap;
+}
+
 void launch_coherence(dcem_ctx* c) {
-  const int n_work = (int)((int64_t)c->n_tx * c->n_rays);
-  uint32_t* cnt = c->cnt_dev;
+  CohArgs a = coherence_args(c);
+  a.list_cap = kCohList;
   // four blocks per compute unit (each thread then checks several rays), and
   // at most kCohList rays per block
   const int blocks = (int)std::max<int64_t>(
-      std::min<int64_t>((n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 4),
-      (n_work + kCohList - 1) / kCohList);
-  const size_t lds = c->no <= kCohGridObjects ? sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) +
-                                                    sizeof(float) * 6 * c->no
-                                              : 0;
-  hipLaunchKernelGGL(k_coherence, dim3(std::max(blocks, 1)), dim3(kCohBlock), lds, c->stream,
-                     ptr<uint8_t>(c->ray_state), ptr<float4>(c->seg_o), ptr<float4>(c->seg_d),
-                     ptr<int32_t>(c->face_log), ptr<int32_t>(c->face_object), ptr<float>(c->obj_box), c->no, n_work,
-                     1e-3f + c->pad, ptr<uint8_t>(c->invalid_flag), ptr<uint32_t>(c->work_list), cnt);
+      std::min<int64_t>((a.n_work + kCohBlock - 1) / kCohBlock, (int64_t)cu_count(c) * 4),
+      (a.n_work + kCohList - 1) / kCohList);
+  hipLaunchKernelGGL(k_coherence, dim3(std::max(blocks, 1)), dim3(kCohBlock), coherence_lds(c, a.list_cap), c->stream,
+                     a);
+}
+
+void launch_refit_coherence(dcem_ctx* c) {
+  CohArgs ca = coherence_args(c);
+  ca.list_cap = 2 * kCohList;
+  const int n_rb = refit_blocks(c);
+  // one revalidation block per compute unit the refit leaves free (the
+  // refit's LDS allows one block of either kind per unit), at most
+  // list_cap rays per block
+  const int cb = (int)std::max<int64_t>(
+      std::min<int64_t>((ca.n_work + kRefitBlock - 1) / kRefitBlock, std::max(cu_count(c) - n_rb, 1)),
+      (ca.n_work + ca.list_cap - 1) / ca.list_cap);
+  hipLaunchKernelGGL(k_refit_coherence, dim3(n_rb + std::max(cb, 1)), dim3(kRefitBlock),
+                     coherence_lds(c, ca.list_cap), c->stream, make_refit_args(c, true, c->sah_dev + 1), ca, n_rb);
 }
 
 hipError_t build_ray_order(dcem_ctx* c) {
