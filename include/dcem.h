@@ -165,6 +165,9 @@ typedef struct dcem_frame_stats {
   int32_t rebuilt;           /* last dcem_refit_bvh rebuilt the tree */
   int32_t coherent;          /* this frame reused the cache */
   double sah_ratio;          /* SAH cost of the tree relative to its last build */
+  /* stage times (dcem_set_timing): the refit or rebuild, then the trace's
+   * stages; in a coherent frame the refit shares the revalidation launch, so
+   * ms_refit is that launch and ms_coherence includes it */
   float ms_refit, ms_coherence, ms_trace, ms_candidates, ms_refine, ms_reduce;
   int32_t trace_kernel;      /* closest-hit traversal used: 0 one thread per ray, 1 one wavefront per ray */
 } dcem_frame_stats;
