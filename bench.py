@@ -114,7 +114,7 @@ def trace_bytes(s, kernel_cache):
 
 PROFILE = os.path.join(ROOT, "profiles", "dynamic_urban_bench_kernels.md")
 KERNEL_SOURCES = ["paper_2112_07115_amd/csrc/dcem_internal.h", "paper_2112_07115_amd/csrc/bvh.hip",
-                  "paper_2112_07115_amd/csrc/trace.hip"]
+                  "paper_2112_07115_amd/csrc/trace.hip", "paper_2112_07115_amd/csrc/refit.h"]
 
 
 def measured_traffic(kernel, mode):

@@ -216,6 +216,24 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
 
 dcem_status finish_candidates(dcem_ctx* c);
 
+// Begin the next frame and enqueue its revalidation with the pending refit,
+// once nothing of the last frame remains to be read back (see frame_begun).
+void go_ahead(dcem_ctx* c) {
+  if (!c->refit_pending || c->revalidated_ahead || !c->has_frame || !c->cache_valid || !c->counts_current) return;
+  if (!c->frame_begun) {
+    c->cur_caps ^= 1;
+    c->frame_begun = true;
+  }
+  ev_record(c, 0);
+  launch_frame_begin(c, c->last_los);
+  c->refit_pending = false;
+  ev_record(c, 6);
+  launch_refit_coherence(c);
+  ev_record(c, 7);
+  ev_record(c, 1);
+  c->revalidated_ahead = true;
+}
+
 size_t frame_block_bytes(const dcem_ctx* c) {
   return kBlockHead + 2 * sizeof(double) * (size_t)std::max<int64_t>(c->n_pow_cap, 1);
 }
@@ -229,6 +247,8 @@ dcem_status sync_frame(dcem_ctx* c) {
     // on the stream (the next frame's transforms and refit) is not waited for
     c->copy_pending = false;
     HIP_TRY(hipEventSynchronize(c->ev_copy), "synchronize");
+  } else if (c->frame_begun) {
+    // the next frame has begun on the device: host_block keeps the last one
   } else {
     HIP_TRY(flush_refit(c), "refit");   // a pending refit writes its SAH value into the block
     HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, frame_block_bytes(c), hipMemcpyDeviceToHost, c->stream),
@@ -236,6 +256,20 @@ dcem_status sync_frame(dcem_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   }
   const char* hb = static_cast<const char*>(c->host_block);
+  if (c->has_frame && !c->frame_begun && c->timing) {
+    // the frame's stage events have all completed: its revalidation (0..1,
+    // begun early or not), re-trace (8..2), candidates, refinement, reduction
+    dcem_frame_stats& s = c->stats;
+    if (c->refit_pending_timing) {
+      s.ms_refit = ev_ms(c, 6, 7);
+      c->refit_pending_timing = false;
+    }
+    s.ms_coherence = ev_ms(c, 0, 1);
+    s.ms_trace = ev_ms(c, 8, 2);
+    s.ms_candidates = ev_ms(c, 2, 3);
+    s.ms_refine = ev_ms(c, 3, 4);
+    s.ms_reduce = ev_ms(c, 4, 5);
+  }
   std::memcpy(c->last_cnt, hb, sizeof(uint32_t) * kCntSlots);
   uint32_t err = 0;
   std::memcpy(&err, hb + 128, 4);
@@ -364,6 +398,8 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
     return fail(c, DCEM_E_INVALID_ARG, "null array with nonzero size");
   HIP_TRY(hipSetDevice(c->device), "set device");
   c->refit_pending = false;   // the new scene is built from scratch
+  c->frame_begun = false;
+  c->revalidated_ahead = false;
   std::vector<float> V;
   std::vector<int32_t> T, TF, FM, FO;
   std::vector<double> M;
@@ -483,6 +519,7 @@ dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_o
   if (!mem_kind_ok(mem_kind)) return fail(c, DCEM_E_INVALID_ARG, "bad mem_kind");
   if (n_objects == 0) return DCEM_OK;
   if (!xf) return fail(c, DCEM_E_INVALID_ARG, "null transforms");
+  c->revalidated_ahead = false;   // it saw the old object boxes (the frame stays begun)
   HIP_TRY(hipSetDevice(c->device), "set device");
   HIP_TRY(flush_refit(c), "refit");
   if (mem_kind == DCEM_MEM_HOST) {
@@ -521,9 +558,12 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
     ev_record(c, 7);
   } else {
     // enqueued by the next call that needs the tree (a coherent trace runs
-    // it in one launch with its revalidation pass)
+    // it in one launch with its revalidation pass), or at once with the next
+    // frame's revalidation when the last frame's results are already in
     c->refit_pending = true;
     c->refit_since_build = true;
+    go_ahead(c);
+    HIP_TRY(hipGetLastError(), "revalidation");
   }
   c->bvh_stale = false;
   c->last_rebuilt = rb;
@@ -643,6 +683,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   HIP_TRY(ensure(c->caps[1], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
   HIP_TRY(ensure(c->work_list, sizeof(uint32_t) * nw), "alloc work list");
   HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
+  const void* block_before = c->frame_block.p;
   HIP_TRY(ensure_frame_block(c, (int64_t)p->n_freqs * p->n_tx * p->n_rx), "alloc results");
   // counts of the previous frame: its capture list (reused by a coherent frame),
   // its re-trace count (sizes the persistent grid) and its capture count (picks
@@ -655,20 +696,30 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   const int64_t expected_work = (c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work;
   const bool small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
   // -- schedule (no host round trip on the small path)
-  ev_record(c, 0);
-  c->cur_caps ^= 1;
-  launch_frame_begin(c, p->los_always != 0);
-  if (coherent && c->refit_pending) {
-    // the revalidation does not read the tree: one launch with the refit
-    c->refit_pending = false;
-    ev_record(c, 6);
-    launch_refit_coherence(c);
-    ev_record(c, 7);
-  } else {
-    HIP_TRY(flush_refit(c), "refit");
-    if (coherent) launch_coherence(c);
+  // a revalidation enqueued ahead (go_ahead) serves a coherent frame with the
+  // same configuration, as long as the result block stayed in place
+  const bool ahead = c->revalidated_ahead && coherent && (p->los_always != 0) == c->last_los &&
+                     c->frame_block.p == block_before;
+  if (!ahead) {
+    ev_record(c, 0);
+    if (!c->frame_begun) c->cur_caps ^= 1;
+    launch_frame_begin(c, p->los_always != 0);
+    if (coherent && c->refit_pending) {
+      // the revalidation does not read the tree: one launch with the refit
+      c->refit_pending = false;
+      ev_record(c, 6);
+      launch_refit_coherence(c);
+      ev_record(c, 7);
+    } else {
+      HIP_TRY(flush_refit(c), "refit");
+      if (coherent) launch_coherence(c);
+    }
+    ev_record(c, 1);
   }
-  ev_record(c, 1);
+  c->frame_begun = false;
+  c->revalidated_ahead = false;
+  c->last_los = p->los_always != 0;
+  ev_record(c, 8);
   c->last_trace_kernel =
       n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work, n_prev) : 0;
   ev_record(c, 2);
@@ -713,6 +764,8 @@ dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32
       HIP_TRY(hipMemcpyAsync(p_inc, c->pinc_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream), "copy power");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   }
+  go_ahead(c);   // a refit requested before these powers were read: start the next frame
+  HIP_TRY(hipGetLastError(), "revalidation");
   return DCEM_OK;
 }
 
@@ -737,16 +790,7 @@ dcem_status dcem_get_stats(dcem_ctx* c, dcem_frame_stats* out) {
   s.rebuilt = c->last_rebuilt;
   s.trace_kernel = c->last_trace_kernel;
   s.sah_ratio = c->sah_last;
-  if (c->refit_pending_timing) {
-    s.ms_refit = ev_ms(c, 6, 7);
-    c->refit_pending_timing = false;
-  }
-  s.ms_coherence = ev_ms(c, 0, 1);
-  s.ms_trace = ev_ms(c, 1, 2);
-  s.ms_candidates = ev_ms(c, 2, 3);
-  s.ms_refine = ev_ms(c, 3, 4);
-  s.ms_reduce = ev_ms(c, 4, 5);
-  *out = s;
+  *out = s;   // stage times: taken when the frame's results arrived (sync_frame)
   return DCEM_OK;
 }
 
@@ -837,7 +881,8 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   if (n_out) *n_out = nc;
   if (!rows || nc == 0) return DCEM_OK;
   std::vector<Capture> cp(nc);
-  HIP_TRY(hipMemcpy(cp.data(), c->caps[c->cur_caps].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
+  const int list = c->frame_begun ? c->cur_caps ^ 1 : c->cur_caps;   // the last traced frame's
+  HIP_TRY(hipMemcpy(cp.data(), c->caps[list].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   const int K = c->K;
   std::vector<int32_t> flog((size_t)(K + 1) * std::max<int64_t>(n_work, 1));

@@ -106,6 +106,13 @@ struct dcem_ctx {
   // revalidation pass of a coherent frame (which does not read the tree), or
   // by the first call that reads the tree or the vertices.
   bool refit_pending = false;
+  // Going ahead: once a frame's results are in and a refit is pending, the
+  // next frame is begun (capture list switched, counters cleared) and its
+  // revalidation enqueued with the refit; a coherent trace with the same
+  // configuration then starts at the re-trace.
+  bool frame_begun = false;
+  bool revalidated_ahead = false;
+  bool last_los = true;
   hipEvent_t ev_copy = nullptr;   // the last traced frame's results have reached host_block
   bool copy_pending = false;
   std::string err;
@@ -187,7 +194,7 @@ struct dcem_ctx {
   bool has_frame = false;
   int32_t record_log = 0;
   dcem_frame_stats stats{};
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[9] = {};   // stage boundaries of a frame (timing on): see dcem_get_stats
 };
 
 namespace dcem {

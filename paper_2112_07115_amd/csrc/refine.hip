@@ -55,16 +55,13 @@ __device__ inline uint32_t get_bits(const uint32_t* __restrict__ keys, int64_t s
   return v;
 }
 
-// Sort key of every capture: (tx, rx, order, f1..fK) packed most significant
+// Sort key of a capture: (tx, rx, order, f1..fK) packed most significant
 // first, faces read from the per-bounce face log of the capturing ray.
-__global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log,
-                       int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys, int64_t stride) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Capture c = caps[i];
+__device__ inline void capture_key(const Capture& c, const int32_t* __restrict__ face_log, int64_t n_work,
+                                   const KeyLayout& L, uint32_t* w) {
   const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
   const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
-  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < 8; ++k) w[k] = 0;
   for (int j = 0; j < L.K; ++j) {
     uint32_t f = 0;
     if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
@@ -76,126 +73,135 @@ __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32
   put_bits(w, L.W, pos, L.br, rx);
   pos += L.br;
   put_bits(w, L.W, pos, L.bt, tx);
+}
+
+__global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log,
+                       int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys, int64_t stride) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[8];
+  capture_key(caps[i], face_log, n_work, L, w);
   for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
 }
 
 // De-duplication of a small capture list (n <= kSmallN, read on the device)
-// without sorting passes.  A key's position in the stable sorted order is the
-// number of smaller keys plus the number of equal keys of lower capture index:
-// kRankLanes lanes count that for one key against all keys, held in LDS.  The
-// first key of each run of equal keys (no equal key of lower index) is a
-// unique candidate; a second kernel compacts their positions in sorted order.
-// The result equals a stable sort followed by run heads.
+// in one workgroup, without a sort of the captures:
+//  1. every capture's key goes into LDS and, by linear probing, into a hash
+//     table of capture indices, so equal keys meet in one slot; the slot
+//     keeps the capture with the lowest (ray, index) of its key;
+//  2. the occupied slots (the unique keys) are bucketed by their (tx, rx)
+//     pair, the key's most significant field (pairs >> shift, a monotone map);
+//  3. a key's position in sorted order is its bucket's start plus the number
+//     of smaller keys in its bucket.
+// Output, per unique key u in ascending key order: perm[u] = the chosen
+// capture (its key words stay in `keys_out`, its ray is the lowest ray that
+// found the candidate); uniq_pos is the identity, so each unique key's
+// capture range [uniq_pos[u], uniq_pos[u + 1]) holds that one capture.  The
+// set of keys, their order and the lowest ray per key equal those of a stable
+// sort of all captures followed by run heads.
 constexpr int kSmallN = 2048;
 constexpr int kSmallW = 3;
-constexpr int kRankBlock = 256;
-constexpr int kRankLanes = 32;
-constexpr int kRankItems = kRankBlock / kRankLanes;   // keys ranked per block
+constexpr int kCandBlock = 1024;
+constexpr int kCandPer = kSmallN / kCandBlock;   // captures per thread
+constexpr int kHashSlots = 2 * kSmallN;          // load factor <= 1/2
+constexpr int kSlotsPer = kHashSlots / kCandBlock;
+constexpr int kBuckets = 2048;
+constexpr int kBucketsPer = kBuckets / kCandBlock;
+constexpr uint32_t kEmptySlot = 0xffffffffu;
 
-__global__ __launch_bounds__(256) void k_small_keys(
+__device__ inline uint32_t key_hash(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return h & (kHashSlots - 1);
+}
+
+__device__ inline bool key_less(const uint4& a, const uint4& b) {
+  return a.x < b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && a.z < b.z)));
+}
+
+__global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, uint32_t capacity,
-    const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys_out,
+    const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, int pair_shift,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos,
     uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
+  __shared__ uint32_t kk[kSmallW][kSmallN];              // key words per capture
+  __shared__ uint32_t cpair[kSmallN];                    // (tx, rx) pair per capture
+  __shared__ uint32_t slot_idx[kHashSlots];              // a capture of the slot's key
+  __shared__ unsigned long long slot_best[kHashSlots];   // min (ray << 32 | capture) of the key
+  __shared__ uint32_t bstart[kBuckets];                  // counts, then exclusive starts
+  __shared__ uint32_t wsum[kCandBlock / kWave + 1];
+  uint4* bkey = reinterpret_cast<uint4*>(slot_best);     // after step 2: unique keys by bucket
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   // the counter keeps counting past the buffer when captures overflow (the
   // trace kernel flags that); only the stored records are read
   const uint32_t n = min(*n_dev, capacity);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n > (uint32_t)kSmallN) {   // the host redoes this frame's candidates the exact way
-    if (i == 0) {
+  if (n > (uint32_t)kSmallN) {   // uniform: the host redoes this frame's candidates the exact way
+    if (tid == 0) {
       *fallback = 1;
       *n_unique = 0;
     }
     return;
   }
-  if (i >= n) return;
-  const Capture c = caps[i];
-  const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
-  const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
-  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < L.K; ++j) {
-    uint32_t f = 0;
-    if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
-    put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
+  for (int q = 0; q < kSlotsPer; ++q) {
+    slot_idx[tid + q * kCandBlock] = kEmptySlot;
+    slot_best[tid + q * kCandBlock] = ~0ull;
   }
-  int pos = L.K * L.bf;
-  put_bits(w, L.W, pos, 4, order);
-  pos += 4;
-  put_bits(w, L.W, pos, L.br, rx);
-  pos += L.br;
-  put_bits(w, L.W, pos, L.bt, tx);
-  for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
-}
-
-__global__ __launch_bounds__(kRankBlock) void k_small_rank(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, uint32_t capacity, int W,
-    uint32_t* __restrict__ perm_out, uint32_t* __restrict__ head) {
-  __shared__ uint32_t kk[kSmallW][kSmallN];
-  const uint32_t n = min(*n_dev, capacity);
-  if (n > (uint32_t)kSmallN) return;   // uniform: k_small_keys raised the fallback
-  const int tid = threadIdx.x;
-  const uint32_t first = blockIdx.x * kRankItems;
-  if (first < n) {
-    // all loads in flight at once, then the LDS stores
-    constexpr int kPer = kSmallN / kRankBlock;
-    uint32_t v[kSmallW][kPer];
+  for (int q = 0; q < kBucketsPer; ++q) bstart[tid + q * kCandBlock] = 0;
+  uint32_t work[kCandPer];
 #pragma unroll
-    for (int k = 0; k < kSmallW; ++k)
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const uint32_t j = tid + q * kRankBlock;
-        v[k][q] = k < W && j < n ? keys[k * (int64_t)kSmallN + j] : 0u;
-      }
-#pragma unroll
-    for (int k = 0; k < kSmallW; ++k)
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) kk[k][tid + q * kRankBlock] = v[k][q];
-  }
-  __syncthreads();
-  const uint32_t i = first + tid / kRankLanes;
-  const uint32_t sub = tid % kRankLanes;
-  uint32_t less = 0, eq_before = 0;
-  if (i < n) {
-    uint32_t ki[kSmallW];
-    for (int k = 0; k < W; ++k) ki[k] = kk[k][i];
-    for (uint32_t j = sub; j < n; j += kRankLanes) {
-      int c = 0;   // sign of key j - key i, most significant word first
-      for (int k = 0; k < W && c == 0; ++k) {
-        const uint32_t v = kk[k][j];
-        c = v < ki[k] ? -1 : (v > ki[k] ? 1 : 0);
-      }
-      less += c < 0 ? 1u : 0u;
-      eq_before += (c == 0 && j < i) ? 1u : 0u;
+  for (int q = 0; q < kCandPer; ++q) {
+    const uint32_t i = tid + q * kCandBlock;
+    work[q] = 0;
+    if (i < n) {
+      const Capture c = caps[i];
+      uint32_t w[8];
+      capture_key(c, face_log, n_work, L, w);
+      for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
+      for (int k = 0; k < kSmallW; ++k) kk[k][i] = k < L.W ? w[k] : 0u;
+      cpair[i] = c.pair_order >> 4;
+      work[q] = c.work;
     }
   }
-  for (int off = kRankLanes / 2; off > 0; off >>= 1) {
-    less += __shfl_xor(less, off);
-    eq_before += __shfl_xor(eq_before, off);
+  __syncthreads();
+  // ---- 1. hash insertion: a slot, once claimed, names a capture whose key
+  // is already in LDS; at most n < kHashSlots slots are ever claimed
+#pragma unroll
+  for (int q = 0; q < kCandPer; ++q) {
+    const uint32_t i = tid + q * kCandBlock;
+    if (i >= n) continue;
+    const uint32_t k0 = kk[0][i], k1 = kk[1][i], k2 = kk[2][i];
+    uint32_t h = key_hash(k0, k1, k2);
+    while (true) {
+      const uint32_t prev = atomicCAS(&slot_idx[h], kEmptySlot, i);
+      if (prev == kEmptySlot || (kk[0][prev] == k0 && kk[1][prev] == k1 && kk[2][prev] == k2)) break;
+      h = (h + 1) & (kHashSlots - 1);
+    }
+    atomicMin(&slot_best[h], ((unsigned long long)work[q] << 32) | i);
   }
-  if (i < n && sub == 0) {
-    const uint32_t r = less + eq_before;
-    perm_out[r] = i;
-    head[r] = eq_before == 0 ? 1u : 0u;
+  __syncthreads();
+  // ---- 2. bucket the unique keys by pair
+  uint32_t rep[kSlotsPer], bpos[kSlotsPer], bkt[kSlotsPer];
+#pragma unroll
+  for (int q = 0; q < kSlotsPer; ++q) {
+    const int j = tid + q * kCandBlock;
+    rep[q] = kEmptySlot;
+    if (slot_idx[j] != kEmptySlot) {
+      rep[q] = (uint32_t)slot_best[j];
+      bkt[q] = cpair[rep[q]] >> pair_shift;
+      bpos[q] = atomicAdd(&bstart[bkt[q]], 1u);
+    }
   }
-}
-
-// Positions of the run heads in sorted order (one block).
-__global__ __launch_bounds__(kRankBlock) void k_small_heads(const uint32_t* __restrict__ n_dev, uint32_t capacity,
-                                                            const uint32_t* __restrict__ head,
-                                                            uint32_t* __restrict__ uniq_pos,
-                                                            uint32_t* __restrict__ n_unique) {
-  __shared__ uint32_t wsum[kRankBlock / kWave + 1];
-  const uint32_t n = min(*n_dev, capacity);
-  if (n > (uint32_t)kSmallN) return;   // uniform: k_small_keys raised the fallback
-  constexpr int kPer = kSmallN / kRankBlock;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  uint32_t flags = 0, cnt = 0;
-  for (int q = 0; q < kPer; ++q) {
-    const uint32_t p = tid * kPer + q;
-    const bool h = p < n && head[p] != 0;
-    flags |= (h ? 1u : 0u) << q;
-    cnt += h ? 1u : 0u;
+  __syncthreads();
+  // exclusive scan of the bucket counts (kBucketsPer consecutive per thread)
+  uint32_t cnt[kBucketsPer], local = 0;
+#pragma unroll
+  for (int q = 0; q < kBucketsPer; ++q) {
+    cnt[q] = bstart[tid * kBucketsPer + q];
+    local += cnt[q];
   }
-  uint32_t incl = cnt;
+  uint32_t incl = local;
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t v = __shfl_up(incl, off);
     if (lane >= off) incl += v;
@@ -204,36 +210,53 @@ __global__ __launch_bounds__(kRankBlock) void k_small_heads(const uint32_t* __re
   __syncthreads();
   if (tid == 0) {
     uint32_t run = 0;
-    for (int w = 0; w < kRankBlock / kWave; ++w) {
-      const uint32_t v = wsum[w];
-      wsum[w] = run;
-      run += v;
+    for (int v = 0; v < kCandBlock / kWave; ++v) {
+      const uint32_t x = wsum[v];
+      wsum[v] = run;
+      run += x;
     }
-    wsum[kRankBlock / kWave] = run;
+    wsum[kCandBlock / kWave] = run;
   }
   __syncthreads();
-  uint32_t o = wsum[wave] + incl - cnt;
-  for (int q = 0; q < kPer; ++q)
-    if ((flags >> q) & 1u) uniq_pos[o++] = tid * kPer + q;
+  uint32_t run = wsum[wave] + incl - local;
+#pragma unroll
+  for (int q = 0; q < kBucketsPer; ++q) {
+    bstart[tid * kBucketsPer + q] = run;
+    run += cnt[q];
+  }
+  const uint32_t nu = wsum[kCandBlock / kWave];
+  __syncthreads();   // slot_best is read no more: bkey may overwrite it
+#pragma unroll
+  for (int q = 0; q < kSlotsPer; ++q)
+    if (rep[q] != kEmptySlot) bkey[bstart[bkt[q]] + bpos[q]] = make_uint4(kk[0][rep[q]], kk[1][rep[q]], kk[2][rep[q]], rep[q]);
+  __syncthreads();
+  // ---- 3. rank within the bucket (keys are distinct)
+  for (uint32_t p = tid; p < nu; p += kCandBlock) {
+    const uint4 me = bkey[p];
+    const uint32_t b = cpair[me.w] >> pair_shift;
+    const uint32_t b0 = bstart[b], b1 = b + 1 < (uint32_t)kBuckets ? bstart[b + 1] : nu;
+    uint32_t r = b0;
+    for (uint32_t v = b0; v < b1; ++v) r += key_less(bkey[v], me) ? 1u : 0u;
+    perm_out[r] = me.w;
+    uniq_pos[r] = r;
+  }
   if (tid == 0) {
-    const uint32_t nu = wsum[kRankBlock / kWave];
     *n_unique = nu;
-    uniq_pos[nu] = n;
+    uniq_pos[nu] = nu;
   }
 }
 
-// De-duplication of a small list: keys, ranks, run heads.
+// De-duplication of a small list in one launch.
 void launch_small_dedupe(dcem_ctx* c, const KeyLayout& L, int64_t n_work) {
   uint32_t* cnt = c->cnt_dev;
-  hipLaunchKernelGGL(k_small_keys, dim3(kSmallN / 256), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]),
-                     cnt + kCntCaptures, (uint32_t)c->cap_capacity, ptr<int32_t>(c->face_log), n_work, L,
-                     ptr<uint32_t>(c->cand_keys), cnt + kCntUnique, cnt + kCntFallback);
-  hipLaunchKernelGGL(k_small_rank, dim3(kSmallN / kRankItems), dim3(kRankBlock), 0, c->stream,
-                     ptr<uint32_t>(c->cand_keys), cnt + kCntCaptures, (uint32_t)c->cap_capacity, L.W,
-                     ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->cand_tmp));
-  hipLaunchKernelGGL(k_small_heads, dim3(1), dim3(kRankBlock), 0, c->stream, cnt + kCntCaptures,
-                     (uint32_t)c->cap_capacity, ptr<uint32_t>(c->cand_tmp), ptr<uint32_t>(c->uniq_idx),
-                     cnt + kCntUnique);
+  const uint32_t n_pairs = (uint32_t)c->n_tx * (uint32_t)c->n_rx;
+  int shift = 0;
+  while (n_pairs > 0 && ((n_pairs - 1) >> shift) >= (uint32_t)kBuckets) ++shift;
+  hipLaunchKernelGGL(k_small_candidates, dim3(1), dim3(kCandBlock), 0, c->stream,
+                     ptr<Capture>(c->caps[c->cur_caps]), cnt + kCntCaptures, (uint32_t)c->cap_capacity,
+                     ptr<int32_t>(c->face_log), n_work, L, shift, ptr<uint32_t>(c->cand_keys),
+                     ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
+                     cnt + kCntFallback);
 }
 
 __global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
@@ -769,7 +792,6 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
-    if ((e = ensure(c->cand_tmp, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     c->key_stride = kSmallN;
     c->path_cap = kSmallN;
     c->small_path = true;
@@ -788,7 +810,6 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
-    if ((e = ensure(c->cand_tmp, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
     c->key_stride = kSmallN;
     launch_small_dedupe(c, L, n_work);
     return hipGetLastError();

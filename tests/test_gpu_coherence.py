@@ -89,3 +89,78 @@ def test_repeat_runs_bitwise_identical():
         outs.append(frame_outputs(c))
     assert_same(outs[0], outs[1])
     c.close()
+
+
+def test_revalidation_ahead_follows_every_call_order():
+    """Once a frame's results are read and a refit is requested, the next
+    frame's revalidation is started early.  Transforms set again, a change of
+    the line-of-sight option or of the mode, reading results after the early
+    start, and the pipelined order (next frame's geometry before this frame's
+    read-back) all still give the full re-trace's results bitwise."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    full, coh = dcem.Context(0), dcem.Context(0)
+    full.scene_upload(s)
+    coh.scene_upload(s)
+    kw = dict(max_reflections=s.max_reflections, freqs_hz=s.freqs_hz, tx_power_w=s.tx_power_w, record_trace_log=True)
+
+    def reference(frame, los=True):
+        full.set_object_transforms(s.transforms(frame))
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s.tx, s.rx, s.rx_radius, n, mode=dcem.MODE_FULL, los_always=los, **kw)
+        return frame_outputs(full)
+
+    def trace(frame, mode=dcem.MODE_COHERENT, los=True):
+        coh.trace_frame(s.tx, s.rx, s.rx_radius, n, mode=mode, los_always=los, **kw)
+
+    def geometry(frame):
+        coh.set_object_transforms(s.transforms(frame))
+        coh.refit_bvh()
+
+    geometry(0)
+    trace(0)
+    assert_same(reference(0), frame_outputs(coh))
+    # transforms set twice after the early start
+    geometry(1)
+    geometry(2)
+    trace(2)
+    assert_same(reference(2), frame_outputs(coh))
+    log("transforms set again: equal")
+    # line of sight switched off after the early start
+    geometry(3)
+    trace(3, los=False)
+    assert_same(reference(3, los=False), frame_outputs(coh))
+    log("line-of-sight change: equal")
+    # results of the last frame read after the early start of the next, which
+    # then traces with line of sight on again
+    caps = coh.captures()
+    paths = coh.paths()
+    pc = coh.received_power()[0]
+    geometry(4)
+    assert np.array_equal(coh.captures(), caps)
+    assert np.array_equal(coh.paths()["keys"], paths["keys"])
+    assert np.array_equal(coh.received_power()[0], pc)
+    assert coh.stats()["coherent"] == 1
+    trace(4)
+    assert_same(reference(4), frame_outputs(coh))
+    log("reads after an early start: equal")
+    # a full frame after the early start, then a coherent request without a cache
+    geometry(5)
+    trace(5, mode=dcem.MODE_FULL)
+    assert_same(reference(5), frame_outputs(coh))
+    geometry(6)
+    trace(6)
+    assert_same(reference(6), frame_outputs(coh))
+    assert coh.stats()["coherent"] == 0
+    log("full frame after an early start: equal")
+    # pipelined: the next frame's geometry before this frame's read-back
+    geometry(7)
+    for frame in range(7, 11):
+        trace(frame)
+        geometry(frame + 1)
+        out = frame_outputs(coh)
+        assert coh.stats()["coherent"] == 1
+        assert_same(reference(frame), out)
+    log("pipelined order: equal")
+    full.close()
+    coh.close()

@@ -41,13 +41,14 @@ def radius_of(scene):
     return float(np.linalg.norm(pts, axis=1).max())
 
 
-def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True):
+def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True,
+             los_always=True):
     """Trace one frame on both sides and compare everything; returns stats."""
     K = scene.max_reflections if K is None else K
     log("case", scene.name, "frame", frame, "K", K, "rays", n_rays if dirs is None else len(dirs))
     ctx.scene_upload(scene)
     out = dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=dirs, n_rays=n_rays, K=K,
-                                 record_trace_log=True)
+                                 record_trace_log=True, los_always=los_always)
     g_tri, g_t, g_len = ctx.trace_log()
     if dirs is None:
         g_dirs = ctx.ray_dirs()
@@ -55,7 +56,7 @@ def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captu
         assert np.array_equal(g_dirs, o_dirs), "Fibonacci directions differ"
     else:
         o_dirs = dirs
-    ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K)
+    ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K, los_always=los_always)
     st = parity.compare_trace(g_tri, g_t, g_len, ofr.trace, scene.tri_face, radius=radius_of(scene))
     log("  trace", st)
     n = o_dirs.shape[0]
@@ -96,6 +97,23 @@ def test_large_capture_list(ctx, O):
     dirs = scenes.random_sphere_dirs(1_000_000, seed=13)
     st, out, ofr = run_pair(ctx, O, s2, dirs=dirs)
     assert ofr.trace.caps.shape[0] > 4096
+
+
+def test_many_pairs_small_capture_list(ctx, O):
+    """More (tx, rx) pairs than the one-workgroup de-duplication has pair
+    buckets (2 x 1156 > 2048), with fewer than 2048 captures: keys are bucketed
+    by pair >> 1 and ranked inside their bucket."""
+    s = scenes.static_toy()
+    g = np.linspace(-88.0, 88.0, 34, dtype=np.float32)
+    rx = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    rx = np.concatenate([rx, np.full((rx.shape[0], 1), 1.5, np.float32)], 1)
+    s2 = scenes.Scene(**{**s.__dict__, "rx": rx, "tx": np.array([[0, 0, 5], [-60, 10, 3]], np.float32)})
+    dirs = scenes.random_sphere_dirs(6000, seed=21)
+    st, out, ofr = run_pair(ctx, O, s2, dirs=dirs, los_always=False)
+    n_caps = int((ctx.captures()[:, 0] >= 0).sum())
+    log("  captures", n_caps, "unique keys", len(ofr.keys))
+    assert 100 < n_caps <= 2048
+    assert out.p_coh.shape == (1, 2, rx.shape[0])
 
 
 def test_ragged_ray_counts_and_orders(ctx, O):
