@@ -40,21 +40,6 @@ __device__ inline void put_bits(uint32_t* w, int W, int pos, int nbits, uint32_t
   }
 }
 
-__device__ inline uint32_t get_bits(const uint32_t* __restrict__ keys, int64_t stride, uint32_t idx, int W, int pos,
-                                    int nbits) {
-  uint32_t v = 0;
-  int got = 0;
-  while (got < nbits) {
-    const int word = W - 1 - pos / 32, off = pos % 32;
-    const int take = min(nbits - got, 32 - off);
-    const uint32_t mask = take == 32 ? 0xffffffffu : ((1u << take) - 1u);
-    v |= ((keys[word * stride + idx] >> off) & mask) << got;
-    got += take;
-    pos += take;
-  }
-  return v;
-}
-
 // Sort key of a capture: (tx, rx, order, f1..fK) packed most significant
 // first, faces read from the per-bounce face log of the capturing ray.
 __device__ inline void capture_key(const Capture& c, const int32_t* __restrict__ face_log, int64_t n_work,
@@ -96,9 +81,10 @@ __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32
 // Output, per unique key u in ascending key order: perm[u] = the chosen
 // capture (its key words stay in `keys_out`, its ray is the lowest ray that
 // found the candidate); uniq_pos is the identity, so each unique key's
-// capture range [uniq_pos[u], uniq_pos[u + 1]) holds that one capture.  The
-// set of keys, their order and the lowest ray per key equal those of a stable
-// sort of all captures followed by run heads.
+// capture range [uniq_pos[u], uniq_pos[u + 1]) holds that one capture; and
+// the decoded candidate (see UniqueOut).  The set of keys, their order and
+// the lowest ray per key equal those of a stable sort of all captures
+// followed by run heads.
 constexpr int kSmallN = 2048;
 constexpr int kSmallW = 3;
 constexpr int kCandBlock = 1024;
@@ -117,6 +103,46 @@ __device__ inline uint32_t key_hash(uint32_t a, uint32_t b, uint32_t c) {
   return h & (kHashSlots - 1);
 }
 
+// A unique candidate, decoded from its key: (tx, rx) pair, reflection order,
+// face sequence (-1 past the order) and the lowest ray that captured it (-1:
+// only the line-of-sight record).  Written per unique key in key order; the
+// refinement reads it.
+struct UniqueOut {
+  int32_t* pair;
+  uint8_t* order;
+  int32_t* faces;   // [n][K]
+  int32_t* first_ray;
+};
+
+__device__ inline uint32_t key_bits(const uint32_t* w, int W, int pos, int nbits) {
+  uint32_t v = 0;
+  int got = 0;
+  while (got < nbits) {
+    const int word = W - 1 - pos / 32, off = pos % 32;
+    const int take = min(nbits - got, 32 - off);
+    const uint32_t mask = take == 32 ? 0xffffffffu : ((1u << take) - 1u);
+    v |= ((w[word] >> off) & mask) << got;
+    got += take;
+    pos += take;
+  }
+  return v;
+}
+
+__device__ inline void write_unique(const UniqueOut& o, const KeyLayout& L, uint32_t u, const uint32_t* w,
+                                    uint32_t first_work) {
+  int pos = L.K * L.bf;
+  const uint32_t order = key_bits(w, L.W, pos, 4);
+  pos += 4;
+  const uint32_t rx = key_bits(w, L.W, pos, L.br);
+  pos += L.br;
+  const uint32_t tx = key_bits(w, L.W, pos, L.bt);
+  o.pair[u] = (int32_t)(tx * (uint32_t)L.n_rx + rx);
+  o.order[u] = (uint8_t)order;
+  for (int j = 0; j < L.K; ++j)
+    o.faces[(size_t)u * L.K + j] = (uint32_t)j < order ? (int32_t)key_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf) : -1;
+  o.first_ray[u] = first_work == kNoRay ? -1 : (int32_t)first_work;
+}
+
 __device__ inline bool key_less(const uint4& a, const uint4& b) {
   return a.x < b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && a.z < b.z)));
 }
@@ -125,9 +151,10 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, uint32_t capacity,
     const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, int pair_shift,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ perm_out, uint32_t* __restrict__ uniq_pos,
-    uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
+    UniqueOut out, uint32_t* __restrict__ n_unique, uint32_t* __restrict__ fallback) {
   __shared__ uint32_t kk[kSmallW][kSmallN];              // key words per capture
   __shared__ uint32_t cpair[kSmallN];                    // (tx, rx) pair per capture
+  __shared__ uint32_t cwork[kSmallN];                    // lowest ray of the key, at its chosen capture
   __shared__ uint32_t slot_idx[kHashSlots];              // a capture of the slot's key
   __shared__ unsigned long long slot_best[kHashSlots];   // min (ray << 32 | capture) of the key
   __shared__ uint32_t bstart[kBuckets];                  // counts, then exclusive starts
@@ -188,7 +215,9 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     const int j = tid + q * kCandBlock;
     rep[q] = kEmptySlot;
     if (slot_idx[j] != kEmptySlot) {
-      rep[q] = (uint32_t)slot_best[j];
+      const unsigned long long best = slot_best[j];
+      rep[q] = (uint32_t)best;
+      cwork[rep[q]] = (uint32_t)(best >> 32);
       bkt[q] = cpair[rep[q]] >> pair_shift;
       bpos[q] = atomicAdd(&bstart[bkt[q]], 1u);
     }
@@ -239,11 +268,18 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     for (uint32_t v = b0; v < b1; ++v) r += key_less(bkey[v], me) ? 1u : 0u;
     perm_out[r] = me.w;
     uniq_pos[r] = r;
+    const uint32_t w[kSmallW] = {me.x, me.y, me.z};
+    write_unique(out, L, r, w, cwork[me.w]);
   }
   if (tid == 0) {
     *n_unique = nu;
     uniq_pos[nu] = nu;
   }
+}
+
+UniqueOut unique_out(dcem_ctx* c) {
+  return UniqueOut{ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_order), ptr<int32_t>(c->path_faces),
+                   ptr<int32_t>(c->first_ray)};
 }
 
 // De-duplication of a small list in one launch.
@@ -255,7 +291,7 @@ void launch_small_dedupe(dcem_ctx* c, const KeyLayout& L, int64_t n_work) {
   hipLaunchKernelGGL(k_small_candidates, dim3(1), dim3(kCandBlock), 0, c->stream,
                      ptr<Capture>(c->caps[c->cur_caps]), cnt + kCntCaptures, (uint32_t)c->cap_capacity,
                      ptr<int32_t>(c->face_log), n_work, L, shift, ptr<uint32_t>(c->cand_keys),
-                     ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique,
+                     ptr<uint32_t>(c->cand_perm), ptr<uint32_t>(c->uniq_idx), unique_out(c), cnt + kCntUnique,
                      cnt + kCntFallback);
 }
 
@@ -319,6 +355,24 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ hea
   if (i == 0) uniq_pos[*n_unique] = n;
 }
 
+// Decoded candidate of every unique key of the sorted list: its key from the
+// first capture of its run, its lowest ray over the run.
+__global__ __launch_bounds__(256) void k_unique_info(const uint32_t* __restrict__ keys, int64_t stride, KeyLayout L,
+                                                     const uint32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ uniq_pos,
+                                                     const uint32_t* __restrict__ n_unique,
+                                                     const Capture* __restrict__ caps, UniqueOut out) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= *n_unique) return;
+  const uint32_t h = uniq_pos[u], e = uniq_pos[u + 1];
+  uint32_t fr = kNoRay;
+  for (uint32_t j = h; j < e; ++j) fr = min(fr, caps[perm[j]].work);
+  uint32_t w[8];
+  const uint32_t idx = perm[h];
+  for (int k = 0; k < L.W; ++k) w[k] = keys[k * stride + idx];
+  write_unique(out, L, u, w, fr);
+}
+
 
 struct D3 {
   double x, y, z;
@@ -373,13 +427,9 @@ __device__ inline void fresnel_coeffs(const double* mat, double freq, double cos
 __device__ inline double vol(D3 a, D3 b, D3 c, D3 d) { return dot(b - a, cross(c - a, d - a)); }
 
 struct RefineArgs {
-  const uint32_t* keys;
-  int64_t stride;
-  KeyLayout L;
-  const uint32_t* perm;
-  const uint32_t* uniq_pos;
+  int K;                     // maximum reflection order (row length of faces)
+  int n_rx;
   const uint32_t* n_unique;
-  const Capture* caps;
   const float* tx;
   const float* rx;
   const double4* plane;
@@ -403,10 +453,9 @@ struct RefineArgs {
   double* aod;
   double* aoa;
   double* amp;       // [n][n_freqs][3][2]
-  int32_t* first_ray;
-  int32_t* pair;
-  uint8_t* order;    // [n] reflection order
-  int32_t* faces;    // [n][K] face sequence
+  const int32_t* pair;      // decoded candidates (written by the de-duplication)
+  const uint8_t* order;     // [n] reflection order
+  const int32_t* faces;     // [n][K] face sequence
   double* pts;       // [n][K+2][3] transmitter, reflection points, receiver
   uint32_t* counters;
   uint32_t* err;
@@ -536,56 +585,52 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
 //     through each reflection by the Fresnel coefficients, times
 //     sqrt(Pt) lambda / (4 pi d), the specific attenuation and the phase
 //     e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
-constexpr int kRefineMaxThreads = kWave * (kMaxK + 1);
+constexpr int kRefineMaxThreads = kWave * (kMaxK + 2);
 
 __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ double sP[(kMaxK + 2) * 3];      // transmitter, reflection points, receiver
   __shared__ int sfaces[kMaxK];
   __shared__ int sorder, sok, sfail;
+  __shared__ double sd;
+  __shared__ double4 spl[kMaxK];              // planes of the faces
+  __shared__ double simg[(kMaxK + 1) * 3];    // transmitter images
   __shared__ uint32_t stk[kMaxK + 1][kCheckStack];
   const uint32_t u = blockIdx.x;
   if (u >= *a.n_unique) return;   // uniform over the block
-  const int K = a.L.K;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const KeyLayout& L = a.L;
-  const uint32_t h = a.uniq_pos[u], e = a.uniq_pos[u + 1];
-  // ---- 1. geometry
+  const int K = a.K;
+  // ---- 1. geometry (the candidate's pair, order and faces were decoded by
+  // the de-duplication): lane j loads face j and its plane, lane 0 then runs
+  // the image method on LDS copies
   if (w == 0) {
-    uint32_t fr = kNoRay;
-    for (uint32_t j = h + lane; j < e; j += kWave) fr = min(fr, a.caps[a.perm[j]].work);
-    for (int off = 32; off > 0; off >>= 1) fr = min(fr, (uint32_t)__shfl_xor(fr, off));
+    const int order = a.order[u];
+    const int pair = a.pair[u];
+    if (lane < order) {
+      const int f = a.faces[(size_t)u * K + lane];
+      sfaces[lane] = f;
+      spl[lane] = a.plane[f];
+    }
+    wave_sync();
     if (lane == 0) {
-      const uint32_t idx = a.perm[h];
-      int faces[kMaxK];
-      for (int j = 0; j < L.K; ++j) faces[j] = (int)get_bits(a.keys, a.stride, idx, L.W, (L.K - 1 - j) * L.bf, L.bf);
-      int pos = L.K * L.bf;
-      const int order = (int)get_bits(a.keys, a.stride, idx, L.W, pos, 4);
-      pos += 4;
-      const int rx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.br);
-      pos += L.br;
-      const int tx = (int)get_bits(a.keys, a.stride, idx, L.W, pos, L.bt);
-      a.pair[u] = tx * L.n_rx + rx;
-      a.order[u] = (uint8_t)order;
-      for (int j = 0; j < L.K; ++j) {
-        a.faces[(size_t)u * L.K + j] = j < order ? faces[j] : -1;
-        sfaces[j] = faces[j];
-      }
-      a.first_ray[u] = fr == kNoRay ? -1 : (int32_t)fr;
+      const int tx = pair / a.n_rx, rx = pair - tx * a.n_rx;
       const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
-      D3 img[kMaxK + 1];
-      img[0] = T;
+      // images of the transmitter through the face planes in turn (Sec. III)
+      D3 im = T;
+      simg[0] = im.x; simg[1] = im.y; simg[2] = im.z;
       for (int j = 1; j <= order; ++j) {
-        const double4 pl = a.plane[faces[j - 1]];
+        const double4 pl = spl[j - 1];
         const D3 n = {pl.x, pl.y, pl.z};
-        img[j] = img[j - 1] - (2.0 * (dot(img[j - 1], n) - pl.w)) * n;
+        im = im - (2.0 * (dot(im, n) - pl.w)) * n;
+        simg[3 * j] = im.x; simg[3 * j + 1] = im.y; simg[3 * j + 2] = im.z;
       }
-      double* P = a.pts + (size_t)u * (L.K + 2) * 3;
+      // reflection points walked back from the receiver
+      double* P = a.pts + (size_t)u * (K + 2) * 3;
       bool ok = true;
       D3 Q = R;
       for (int j = order; j >= 1; --j) {
-        const double4 pl = a.plane[faces[j - 1]];
+        const double4 pl = spl[j - 1];
         const D3 n = {pl.x, pl.y, pl.z};
-        const D3 D = img[j] - Q;
+        const D3 D = D3{simg[3 * j], simg[3 * j + 1], simg[3 * j + 2]} - Q;
         const double den = dot(D, n);
         if (den == 0.0) { ok = false; break; }
         const double s = (pl.w - dot(Q, n)) / den;
@@ -598,7 +643,8 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       P[3 * (order + 1)] = R.x; P[3 * (order + 1) + 1] = R.y; P[3 * (order + 1) + 2] = R.z;
       sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
       sP[3 * (order + 1)] = R.x; sP[3 * (order + 1) + 1] = R.y; sP[3 * (order + 1) + 2] = R.z;
-      a.length[u] = len(R - img[order]);
+      sd = len(R - im);
+      a.length[u] = sd;
       sorder = order;
       sok = ok ? 1 : 0;
       sfail = 0;
@@ -607,18 +653,17 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __syncthreads();
   const int order = sorder;
   bool ok = sok != 0;
-  // ---- 2. validation, one wavefront per sub-segment
+  // ---- 2. validation, one wavefront per sub-segment: wavefront w >= 1 also
+  // checks reflection point w against its face
   if (ok && w <= order) {
     const uint64_t all = ~0ull;
     bool fail = false, fault = false;
-    if (w == 0) {
-      for (int r = 0; r < order && !fail; ++r) {
-        const int f = sfaces[r];
-        const double4 pl = a.plane[f];
-        const D3 pt = {sP[3 * (r + 1)], sP[3 * (r + 1) + 1], sP[3 * (r + 1) + 2]};
-        const bool inside = in_face(a, f, pt, D3{pl.x, pl.y, pl.z}, lane, kWave);
-        fail = __ballot(inside) == 0;
-      }
+    if (w >= 1) {
+      const int f = sfaces[w - 1];
+      const double4 pl = spl[w - 1];
+      const D3 pt = {sP[3 * w], sP[3 * w + 1], sP[3 * w + 2]};
+      const bool inside = in_face(a, f, pt, D3{pl.x, pl.y, pl.z}, lane, kWave);
+      fail = __ballot(inside) == 0;
     }
     const int fa = w >= 1 ? sfaces[w - 1] : -1;
     const int fb = w + 1 <= order ? sfaces[w] : -1;
@@ -628,70 +673,74 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
     if (fail && lane == 0) sfail = 1;
     if (fault && lane == 0) atomicOr(a.err, DCEM_ERR_STACK);
   }
-  __syncthreads();
-  if (w != 0) return;
-  ok = ok && sfail == 0;
-  if (lane == 0) a.valid[u] = ok ? 1 : 0;
-  // ---- 3. field, one lane per frequency
+  // ---- 3. field, one lane per frequency, by wavefront K + 1 while the
+  // others validate (a path found invalid is zeroed after the barrier)
+  const int fw = K + 1;
   auto pt = [&](int j) { return D3{sP[3 * j], sP[3 * j + 1], sP[3 * j + 2]}; };
-  const double d = a.length[u];
+  if (w == fw && ok) {
+    const double d = sd;
+    const D3 aod = normed(pt(1) - pt(0));
+    const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
+    const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+    for (int fi = lane; fi < a.n_freqs; fi += kWave) {
+      const double f = a.freqs[fi];
+      double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
+      Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
+      for (int j = 1; j <= order; ++j) {
+        const double4 pl = spl[j - 1];
+        const D3 n = {pl.x, pl.y, pl.z};
+        const D3 ki = normed(pt(j) - pt(j - 1));
+        const D3 kr = normed(pt(j + 1) - pt(j));
+        const double cos_t = fabs(dot(ki, n));
+        D3 s = cross(ki, n);
+        const double sl = len(s);
+        if (sl < 1e-12) {
+          const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
+          s = normed(cross(ki, ax));
+        } else {
+          s = (1.0 / sl) * s;
+        }
+        const D3 pin = cross(s, ki), pout = cross(s, kr);
+        Cx te, tm;
+        fresnel_coeffs(a.materials + 3 * a.face_material[sfaces[j - 1]], f, cos_t, te, tm);
+        const Cx es = cadd(cadd(cscl(s.x, E[0]), cscl(s.y, E[1])), cscl(s.z, E[2]));
+        const Cx ep = cadd(cadd(cscl(pin.x, E[0]), cscl(pin.y, E[1])), cscl(pin.z, E[2]));
+        const Cx cs = cmul(te, es), cp = cmul(tm, ep);
+        E[0] = cadd(cscl(s.x, cs), cscl(pout.x, cp));
+        E[1] = cadd(cscl(s.y, cs), cscl(pout.y, cp));
+        E[2] = cadd(cscl(s.z, cs), cscl(pout.z, cp));
+      }
+      const double lam = kC0 / f;
+      const double k0 = 2.0 * kPi * f / kC0;
+      const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
+      double sn, cs;
+      sincos(k0 * d, &sn, &cs);
+      const Cx ph = {mag * cs, -mag * sn};
+      for (int c = 0; c < 3; ++c) {
+        const Cx v = cmul(ph, E[c]);
+        out[2 * c] = v.re;
+        out[2 * c + 1] = v.im;
+      }
+    }
+  }
+  __syncthreads();
+  if (w != fw) return;
+  ok = ok && sfail == 0;
   D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
   if (ok) {
     aod = normed(pt(1) - pt(0));
     aoa = normed(pt(order) - pt(order + 1));
   }
   if (lane == 0) {
-    a.tau[u] = ok ? d / kC0 : 0.0;
+    a.valid[u] = ok ? 1 : 0;
+    a.tau[u] = ok ? sd / kC0 : 0.0;
     if (!ok) a.length[u] = 0.0;
     a.aod[3 * u] = aod.x; a.aod[3 * u + 1] = aod.y; a.aod[3 * u + 2] = aod.z;
     a.aoa[3 * u] = aoa.x; a.aoa[3 * u + 1] = aoa.y; a.aoa[3 * u + 2] = aoa.z;
   }
-  const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
-  const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
-  for (int fi = lane; fi < a.n_freqs; fi += kWave) {
-    const double f = a.freqs[fi];
-    double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
-    if (!ok) {
-      for (int k = 0; k < 6; ++k) out[k] = 0.0;
-      continue;
-    }
-    Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
-    for (int j = 1; j <= order; ++j) {
-      const double4 pl = a.plane[sfaces[j - 1]];
-      const D3 n = {pl.x, pl.y, pl.z};
-      const D3 ki = normed(pt(j) - pt(j - 1));
-      const D3 kr = normed(pt(j + 1) - pt(j));
-      const double cos_t = fabs(dot(ki, n));
-      D3 s = cross(ki, n);
-      const double sl = len(s);
-      if (sl < 1e-12) {
-        const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
-        s = normed(cross(ki, ax));
-      } else {
-        s = (1.0 / sl) * s;
-      }
-      const D3 pin = cross(s, ki), pout = cross(s, kr);
-      Cx te, tm;
-      fresnel_coeffs(a.materials + 3 * a.face_material[sfaces[j - 1]], f, cos_t, te, tm);
-      const Cx es = cadd(cadd(cscl(s.x, E[0]), cscl(s.y, E[1])), cscl(s.z, E[2]));
-      const Cx ep = cadd(cadd(cscl(pin.x, E[0]), cscl(pin.y, E[1])), cscl(pin.z, E[2]));
-      const Cx cs = cmul(te, es), cp = cmul(tm, ep);
-      E[0] = cadd(cscl(s.x, cs), cscl(pout.x, cp));
-      E[1] = cadd(cscl(s.y, cs), cscl(pout.y, cp));
-      E[2] = cadd(cscl(s.z, cs), cscl(pout.z, cp));
-    }
-    const double lam = kC0 / f;
-    const double k0 = 2.0 * kPi * f / kC0;
-    const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
-    double sn, cs;
-    sincos(k0 * d, &sn, &cs);
-    const Cx ph = {mag * cs, -mag * sn};
-    for (int c = 0; c < 3; ++c) {
-      const Cx v = cmul(ph, E[c]);
-      out[2 * c] = v.re;
-      out[2 * c + 1] = v.im;
-    }
-  }
+  if (!ok)
+    for (int fi = lane; fi < a.n_freqs; fi += kWave)
+      for (int k = 0; k < 6; ++k) a.amp[((size_t)u * a.n_freqs + fi) * 6 + k] = 0.0;
 }
 
 
@@ -775,12 +824,31 @@ KeyLayout key_layout(const dcem_ctx* c) {
 bool small_path_fits(const dcem_ctx* c) { return key_layout(c).W <= kSmallW; }
 int64_t small_path_capacity() { return kSmallN; }
 
+hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
+  hipError_t e;
+  n = std::max<int64_t>(n, 1);
+  if ((e = ensure(c->path_valid, n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_len, 8 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_tau, 8 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_aod, 24 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_aoa, 24 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_amp, 48 * n * (size_t)c->n_freqs)) != hipSuccess) return e;
+  if ((e = ensure(c->first_ray, 4 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->pair_range, 4 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_order, n)) != hipSuccess) return e;
+  if ((e = ensure(c->path_faces, 4 * n * (size_t)std::max(c->K, 1))) != hipSuccess) return e;
+  if ((e = ensure(c->path_pts, 24 * n * (size_t)(c->K + 2))) != hipSuccess) return e;
+  return hipSuccess;
+}
+
 // Candidate keys, sort and unique.  `small`: one workgroup de-duplicates up to
 // kSmallN captures whose count it reads on the device (no host round trip; a
 // larger count raises the fallback counter and the host redoes the frame's
 // candidates exactly).  Otherwise the capture count is read back first.
 hipError_t build_candidates(dcem_ctx* c, bool small) {
   hipError_t e;
+  // the de-duplication writes each unique candidate's decoded record into
+  // the path arrays
   uint32_t* cnt = c->cnt_dev;
   const KeyLayout L = key_layout(c);
   c->key_words = L.W;
@@ -795,6 +863,7 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     c->key_stride = kSmallN;
     c->path_cap = kSmallN;
     c->small_path = true;
+    if ((e = ensure_paths(c, c->path_cap)) != hipSuccess) return e;
     launch_small_dedupe(c, L, n_work);
     return hipGetLastError();
   }
@@ -806,6 +875,7 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   c->n_caps_host = n_caps;
   const int64_t n = std::max<int64_t>(n_caps, 1);
   c->path_cap = n_caps;
+  if ((e = ensure_paths(c, n)) != hipSuccess) return e;
   if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
@@ -833,45 +903,19 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nb, cnt + kCntUnique);
   hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_caps, cnt + kCntUnique,
                      ptr<uint32_t>(c->uniq_idx));
+  hipLaunchKernelGGL(k_unique_info, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L, perm,
+                     ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique, ptr<Capture>(c->caps[c->cur_caps]),
+                     unique_out(c));
   return hipGetLastError();
-}
-
-hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
-  hipError_t e;
-  n = std::max<int64_t>(n, 1);
-  if ((e = ensure(c->path_valid, n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_len, 8 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_tau, 8 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_aod, 24 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_aoa, 24 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_amp, 48 * n * (size_t)c->n_freqs)) != hipSuccess) return e;
-  if ((e = ensure(c->first_ray, 4 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->pair_range, 4 * n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_order, n)) != hipSuccess) return e;
-  if ((e = ensure(c->path_faces, 4 * n * (size_t)std::max(c->K, 1))) != hipSuccess) return e;
-  if ((e = ensure(c->path_pts, 24 * n * (size_t)(c->K + 2))) != hipSuccess) return e;
-  return hipSuccess;
 }
 
 void launch_refine(dcem_ctx* c) {
   const int64_t n = c->path_cap;
   if (n == 0) return;
-  KeyLayout L;
-  L.bt = c->bits_tx;
-  L.br = c->bits_rx;
-  L.bf = c->bits_face;
-  L.K = c->K;
-  L.n_rx = c->n_rx;
-  L.bits = L.bt + L.br + 4 + L.K * L.bf;
-  L.W = c->key_words;
   RefineArgs a;
-  a.keys = ptr<uint32_t>(c->cand_keys);
-  a.stride = c->key_stride;
-  a.L = L;
-  a.perm = ptr<uint32_t>(c->cand_perm);
-  a.uniq_pos = ptr<uint32_t>(c->uniq_idx);
+  a.K = c->K;
+  a.n_rx = c->n_rx;
   a.n_unique = c->cnt_dev + kCntUnique;
-  a.caps = ptr<Capture>(c->caps[c->cur_caps]);
   a.tx = ptr<float>(c->tx_pos);
   a.rx = ptr<float>(c->rx_pos);
   a.plane = ptr<double4>(c->face_plane);
@@ -895,14 +939,13 @@ void launch_refine(dcem_ctx* c) {
   a.aod = ptr<double>(c->path_aod);
   a.aoa = ptr<double>(c->path_aoa);
   a.amp = ptr<double>(c->path_amp);
-  a.first_ray = ptr<int32_t>(c->first_ray);
   a.pair = ptr<int32_t>(c->pair_range);
   a.order = ptr<uint8_t>(c->path_order);
   a.faces = ptr<int32_t>(c->path_faces);
   a.pts = ptr<double>(c->path_pts);
   a.counters = c->cnt_dev;
   a.err = c->err_dev;
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 1)), 0, c->stream, a);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 2)), 0, c->stream, a);
 }
 
 void launch_reduce(dcem_ctx* c) {

@@ -234,6 +234,7 @@ struct TraceArgs {
   int n_rx_nodes;
   float r2;
   float rx_zlo, rx_zhi; // z range of all capture spheres
+  float rx_cull;        // xy margin of the group kernel's receiver cull (radius plus slack)
   const uint8_t* restart;     // work-list mode: first segment to trace again
   int64_t n_rays;
   int n_work;
@@ -735,6 +736,25 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const float za = r.o.z;
     const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
     if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+      // cull by the xy bounds of the segment's part inside the receivers' z
+      // band: a sphere the segment meets has its centre within a radius of
+      // that part (rx_cull adds slack far above the rounding here)
+      float bx0 = -INFINITY, bx1 = INFINITY, by0 = -INFINITY, by1 = INFINITY;
+      float s0 = 0.0f, s1 = tend;
+      if (fabsf(r.d.z) > 1e-20f) {
+        const float rz = __builtin_amdgcn_rcpf(r.d.z);
+        const float a0 = (a.rx_zlo - r.o.z) * rz, a1 = (a.rx_zhi - r.o.z) * rz;
+        s0 = fmaxf(s0, fminf(a0, a1));
+        s1 = fminf(s1, fmaxf(a0, a1));
+      }
+      if (s1 < 1e30f) {
+        const float xa = fmaf(s0, r.d.x, r.o.x), xb = fmaf(s1, r.d.x, r.o.x);
+        const float ya = fmaf(s0, r.d.y, r.o.y), yb = fmaf(s1, r.d.y, r.o.y);
+        bx0 = fminf(xa, xb) - a.rx_cull;
+        bx1 = fmaxf(xa, xb) + a.rx_cull;
+        by0 = fminf(ya, yb) - a.rx_cull;
+        by1 = fmaxf(ya, yb) + a.rx_cull;
+      }
       for (int c = gl; c < a.n_rx; c += kRayLanes) {
         float cx, cy, cz;
         if (rx_lds) {
@@ -747,6 +767,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
           cy = a.rx[3 * c + 1];
           cz = a.rx[3 * c + 2];
         }
+        if (cx < bx0 || cx > bx1 || cy < by0 || cy > by1) continue;
         if (captured(r, tend, dd, cx, cy, cz, a.r2)) {
           const uint32_t cs = atomicAdd(&a.counters[kCntCaptures], 1u);
           if (cs < a.cap_capacity) {
@@ -781,9 +802,14 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       }
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
     }
-    uint32_t next = 0;
-    if (gl == 0) next = n_static + atomicAdd(&a.counters[kCntQueue], 1u);
-    start_ray(__shfl(next, leader));
+    // the next item from the shared queue, unless the first items covered
+    // every ray (no atomic round trip then)
+    uint32_t next = n_work;
+    if (n_static < n_work) {
+      if (gl == 0) next = n_static + atomicAdd(&a.counters[kCntQueue], 1u);
+      next = __shfl(next, leader);
+    }
+    start_ray(next);
   }
   for (int off = 32; off > 0; off >>= 1) {
     seg_count += __shfl_xor(seg_count, off);
@@ -1132,6 +1158,7 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   const float rr = c->cfg.rx_radius * 1.001f + 1e-3f;
   a.rx_zlo = zlo - rr;
   a.rx_zhi = zhi + rr;
+  a.rx_cull = c->cfg.rx_radius * 1.001f + 1e-2f;
   a.n_rays = c->n_rays;
   a.n_work = (int)n_work;
   a.work_list = all_rays ? nullptr : ptr<uint32_t>(c->work_list);
