@@ -132,6 +132,40 @@ struct RxTree {
   }
 };
 
+// Receivers counting-sorted into kRxCols columns of equal x width (stable in
+// receiver index), for the capture test of the group re-trace: a segment
+// scans only the columns its xy extent covers.  The device evaluates the same
+// column formula in the same FP32 operations.
+hipError_t upload_rx_columns(dcem_ctx* c, const std::vector<float>& rx) {
+  const int n = (int)(rx.size() / 3);
+  float x0 = INFINITY, x1 = -INFINITY;
+  for (int i = 0; i < n; ++i) {
+    x0 = std::min(x0, rx[3 * i]);
+    x1 = std::max(x1, rx[3 * i]);
+  }
+  const float scale = x1 > x0 ? (float)kRxCols / (x1 - x0) : 0.0f;
+  auto col = [&](float x) {
+    const float v = std::floor((x - x0) * scale);
+    return (int)std::min(std::max(v, 0.0f), (float)(kRxCols - 1));
+  };
+  std::vector<int32_t> start(kRxCols + 1, 0);
+  for (int i = 0; i < n; ++i) ++start[col(rx[3 * i]) + 1];
+  for (int k = 0; k < kRxCols; ++k) start[k + 1] += start[k];
+  std::vector<float> rec(4 * (size_t)n + (kRxCols + 1));
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  for (int i = 0; i < n; ++i) {
+    const int at = fill[col(rx[3 * i])]++;
+    rec[4 * at] = rx[3 * i];
+    rec[4 * at + 1] = rx[3 * i + 1];
+    rec[4 * at + 2] = rx[3 * i + 2];
+    std::memcpy(&rec[4 * at + 3], &i, 4);
+  }
+  std::memcpy(&rec[4 * (size_t)n], start.data(), sizeof(int32_t) * (kRxCols + 1));
+  c->rx_col_x0 = x0;
+  c->rx_col_scale = scale;
+  return upload(c->rx_cols, rec, c->stream);
+}
+
 std::vector<Node> build_rx_tree(const std::vector<float>& rx, float radius) {
   RxTree t;
   t.rx = &rx;
@@ -346,7 +380,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
                     &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
-                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
+                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
                     &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
                     &c->frame_block, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
@@ -647,6 +681,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
     std::vector<Node> rt = build_rx_tree(rxh, p->rx_radius);
     c->n_rx_nodes = (int32_t)rt.size();
     HIP_TRY(upload(c->rx_nodes, rt, c->stream), "upload receiver tree");
+    HIP_TRY(upload_rx_columns(c, rxh), "upload receiver columns");
   }
   {
     std::vector<double> fv(p->freqs_hz, p->freqs_hz + p->n_freqs);

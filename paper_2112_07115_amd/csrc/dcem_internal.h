@@ -55,6 +55,7 @@ constexpr int kNodeBits = 27;
 constexpr uint32_t kNoEntry = 0xffffffffu;   // no child to push
 constexpr int kGroup = 16;                   // lanes per query in the group traversals: one DPP row
 constexpr int kGroupStack = 128;             // stack entries per group
+constexpr int kRxCols = 64;                  // x columns of the receivers (group re-trace capture test)
 
 // Order LDS accesses of the lanes of one wavefront.
 __device__ inline void wave_sync() {
@@ -150,6 +151,11 @@ struct dcem_ctx {
   bool cache_valid = false;
   bool geometry_moved = true;   // transforms changed since the cached frame
   dcem::DevBuf dirs, ray_order, tx_pos, rx_pos, freqs, rx_nodes;
+  // receivers ordered by x column: [n_rx] float4 (x, y, z, receiver index
+  // bits), then kRxCols + 1 int32 column starts; column of x:
+  // clamp(floor((x - rx_col_x0) * rx_col_scale), 0, kRxCols - 1)
+  dcem::DevBuf rx_cols;
+  float rx_col_x0 = 0.0f, rx_col_scale = 0.0f;
   std::vector<double> freqs_host;
   int32_t n_rx_nodes = 0;
   dcem::DevBuf face_log;     // [K+1][n_work] int32 face hit per bounce (-1 miss)

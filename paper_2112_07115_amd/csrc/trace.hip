@@ -235,6 +235,8 @@ struct TraceArgs {
   float r2;
   float rx_zlo, rx_zhi; // z range of all capture spheres
   float rx_cull;        // xy margin of the group kernel's receiver cull (radius plus slack)
+  const float4* rx_cols;      // receivers by x column, then the column starts (see dcem_ctx::rx_cols)
+  float rx_col_x0, rx_col_scale;
   const uint8_t* restart;     // work-list mode: first segment to trace again
   int64_t n_rays;
   int n_work;
@@ -489,6 +491,7 @@ constexpr int kRayStack = kRayLanes == 64 ? 256 : kGroupStack;   // stack entrie
 constexpr int kWaves = 4;                   // wavefronts per block
 constexpr int kWaveBlock = kWaves * kWave;
 constexpr int kWaveRx = 512;                // receivers cached in LDS (more are read from memory)
+constexpr int kCapStage = 256;              // new captures a block stages in LDS
 constexpr int64_t kWaveTraceMax = 1 << 16;  // longest list traced by groups
 
 __device__ inline bool hit_less(float ta, int ia, float tb, int ib) { return ta < tb || (ta == tb && ia < ib); }
@@ -514,6 +517,7 @@ struct SlotHit {
   int slot;   // index into the slot triangle array
   int face;
   int moving; // the face belongs to a moving object
+  float3 v0, v1, v2;   // the triangle (for the reflection)
 };
 
 // Minimum over each group of kRayLanes lanes: swaps within pairs and quads,
@@ -551,7 +555,10 @@ __device__ inline MaskAxes mask_axes(const Ray& r) {
 
 
 __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
-  __shared__ float4 rxs[kWaveRx];
+  __shared__ float4 rxs[kWaveRx];             // receivers by x column (x, y, z, index bits)
+  __shared__ int32_t rx_col[kRxCols + 1];       // column starts
+  __shared__ Capture scap[kCapStage];          // the block's new captures, appended at the end
+  __shared__ uint32_t scap_n, scap_base;
   __shared__ uint32_t stk_e[kWaves * kGroups][kRayStack];
   __shared__ float stk_t[kWaves * kGroups][kRayStack];
   const int lane = threadIdx.x & (kWave - 1);
@@ -564,9 +571,14 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
   const bool rx_lds = a.n_rx <= kWaveRx;
   if (rx_lds)
-    for (int i = threadIdx.x; i < a.n_rx; i += kWaveBlock)
-      rxs[i] = make_float4(a.rx[3 * i], a.rx[3 * i + 1], a.rx[3 * i + 2], 0.0f);
+    for (int i = threadIdx.x; i < a.n_rx; i += kWaveBlock) rxs[i] = a.rx_cols[i];
+  const int32_t* col_start = reinterpret_cast<const int32_t*>(a.rx_cols + a.n_rx);
+  for (int i = threadIdx.x; i <= kRxCols; i += kWaveBlock) rx_col[i] = col_start[i];
+  if (threadIdx.x == 0) scap_n = 0;
   __syncthreads();
+  auto rx_column = [&](float x) {
+    return (int)fminf(fmaxf(floorf((x - a.rx_col_x0) * a.rx_col_scale), 0.0f), (float)(kRxCols - 1));
+  };
   const uint32_t root = n4 > 0 ? a.n4_dev[1] << kNodeBits : 0u;
   const uint32_t n_work = a.counters[kCntWork];
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
@@ -580,11 +592,11 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   float L = 0.0f, best_t = INFINITY;
   Ray r;
   MaskAxes ax;
-  SlotHit h{FLT_MAX, -1, -1, -1, 0};
+  SlotHit h{FLT_MAX, -1, -1, -1, 0, {}, {}, {}};
   uint64_t best = ~0ull;   // the group's lexicographic minimum of (t, triangle)
 
   auto begin_segment = [&]() {
-    h = SlotHit{FLT_MAX, -1, -1, -1, 0};
+    h = SlotHit{FLT_MAX, -1, -1, -1, 0, {}, {}, {}};
     best_t = INFINITY;
     best = ~0ull;
     guard = n4 + 2;
@@ -669,6 +681,9 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
           h.slot = 4 * node + el;
           h.face = face;
           h.moving = __float_as_int(q2.w);
+          h.v0 = make_float3(q0.x, q0.y, q0.z);
+          h.v1 = make_float3(q1.x, q1.y, q1.z);
+          h.v2 = make_float3(q2.x, q2.y, q2.z);
         }
       }
       ++tri_count;
@@ -704,18 +719,14 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const uint64_t own = __ballot(best != ~0ull && hit_key(h.t, h.tri) == best) & gmask;
     const bool hit = own != 0;
     const int src = hit ? __ffsll((unsigned long long)own) - 1 : leader;
-    const int slot = __shfl(h.slot, src), face = __shfl(h.face, src), moving = __shfl(h.moving, src);
+    const int face = __shfl(h.face, src), moving = __shfl(h.moving, src);
     const float th = hit ? __uint_as_float((uint32_t)(best >> 32)) : FLT_MAX;
     const int tri = hit ? (int)(uint32_t)best : -1;
     const bool more = hit && k < a.K;
-    // the reflecting triangle, fetched while the receivers are tested
-    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
-    if (more) {
-      const Leaf& lf = a.tri4[slot];
-      w0 = lf.v0;
-      w1 = lf.v1;
-      w2 = lf.v2;
-    }
+    // the reflecting triangle, from the lane that found it
+    const float4 w0 = make_float4(__shfl(h.v0.x, src), __shfl(h.v0.y, src), __shfl(h.v0.z, src), 0.0f);
+    const float4 w1 = make_float4(__shfl(h.v1.x, src), __shfl(h.v1.y, src), __shfl(h.v1.z, src), 0.0f);
+    const float4 w2 = make_float4(__shfl(h.v2.x, src), __shfl(h.v2.y, src), __shfl(h.v2.z, src), 0.0f);
     const float tend = hit ? th : INFINITY;
     if (hit && moving) state |= 0x80u;
     const float dd = dot_dd(r);
@@ -755,28 +766,26 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
         by0 = fminf(ya, yb) - a.rx_cull;
         by1 = fmaxf(ya, yb) + a.rx_cull;
       }
-      for (int c = gl; c < a.n_rx; c += kRayLanes) {
-        float cx, cy, cz;
-        if (rx_lds) {
-          const float4 q = rxs[c];
-          cx = q.x;
-          cy = q.y;
-          cz = q.z;
-        } else {
-          cx = a.rx[3 * c];
-          cy = a.rx[3 * c + 1];
-          cz = a.rx[3 * c + 2];
-        }
-        if (cx < bx0 || cx > bx1 || cy < by0 || cy > by1) continue;
-        if (captured(r, tend, dd, cx, cy, cz, a.r2)) {
-          const uint32_t cs = atomicAdd(&a.counters[kCntCaptures], 1u);
-          if (cs < a.cap_capacity) {
-            Capture cp;
-            cp.work = work;
-            cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
-            a.caps[cs] = cp;
+      // receivers of the columns the box covers (one more on each side)
+      int c0 = 0, c1 = a.n_rx;
+      if (bx1 < INFINITY) {
+        c0 = rx_col[max(rx_column(bx0) - 1, 0)];
+        c1 = rx_col[min(rx_column(bx1) + 1, kRxCols - 1) + 1];
+      }
+      for (int c = c0 + gl; c < c1; c += kRayLanes) {
+        const float4 q = rx_lds ? rxs[c] : a.rx_cols[c];
+        if (q.x < bx0 || q.x > bx1 || q.y < by0 || q.y > by1) continue;
+        if (captured(r, tend, dd, q.x, q.y, q.z, a.r2)) {
+          Capture cp;
+          cp.work = work;
+          cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)__float_as_int(q.w)) << 4) | (uint32_t)k;
+          const uint32_t p = atomicAdd(&scap_n, 1u);
+          if (p < (uint32_t)kCapStage) {
+            scap[p] = cp;
           } else {
-            cap_over = true;
+            const uint32_t cs = atomicAdd(&a.counters[kCntCaptures], 1u);
+            if (cs < a.cap_capacity) a.caps[cs] = cp;
+            else cap_over = true;
           }
         }
       }
@@ -810,6 +819,16 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       next = __shfl(next, leader);
     }
     start_ray(next);
+  }
+  // append the block's staged captures with one atomic
+  __syncthreads();
+  const uint32_t ns = min(scap_n, (uint32_t)kCapStage);
+  if (threadIdx.x == 0 && ns) scap_base = atomicAdd(&a.counters[kCntCaptures], ns);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < ns; j += kWaveBlock) {
+    const uint32_t slot = scap_base + j;
+    if (slot < a.cap_capacity) a.caps[slot] = scap[j];
+    else cap_over = true;
   }
   for (int off = 32; off > 0; off >>= 1) {
     seg_count += __shfl_xor(seg_count, off);
@@ -1159,6 +1178,9 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   a.rx_zlo = zlo - rr;
   a.rx_zhi = zhi + rr;
   a.rx_cull = c->cfg.rx_radius * 1.001f + 1e-2f;
+  a.rx_cols = ptr<float4>(c->rx_cols);
+  a.rx_col_x0 = c->rx_col_x0;
+  a.rx_col_scale = c->rx_col_scale;
   a.n_rays = c->n_rays;
   a.n_work = (int)n_work;
   a.work_list = all_rays ? nullptr : ptr<uint32_t>(c->work_list);
