@@ -60,6 +60,38 @@ def test_coherent_equals_full_retrace():
     coh.close()
 
 
+def test_objects_lifted_above_the_summary_cap():
+    """Cached rays are first screened by the box of their path below a height
+    cap (the objects' tops at the last full frame plus 2 m).  Objects lifted
+    above the cap switch the screen off, and it comes back when they return;
+    every frame must still equal the full re-trace."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    full, coh = dcem.Context(0), dcem.Context(0)
+    full.scene_upload(s)
+    coh.scene_upload(s)
+    lift = {2: 3.0, 3: 6.0, 4: 0.0, 5: 1.0}
+    for frame in range(0, 7):
+        xf = s.transforms(frame).copy()
+        xf[::3, 2, 3] += lift.get(frame, 0.0)   # every third vehicle
+        log("frame", frame, "lift", lift.get(frame, 0.0))
+        full.set_object_transforms(xf)
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=s.freqs_hz,
+                         tx_power_w=s.tx_power_w, mode=dcem.MODE_FULL, record_trace_log=True)
+        coh.set_object_transforms(xf)
+        coh.refit_bvh()
+        coh.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=s.freqs_hz,
+                        tx_power_w=s.tx_power_w, mode=dcem.MODE_COHERENT, record_trace_log=True)
+        assert_same(frame_outputs(full), frame_outputs(coh))
+        st = coh.stats()
+        log("  traced", st["rays_traced"])
+        if frame > 0:
+            assert st["coherent"] == 1
+    full.close()
+    coh.close()
+
+
 def test_refit_equals_rebuild():
     s = scenes.dynamic_urban()
     a, b = dcem.Context(0), dcem.Context(0)
