@@ -381,7 +381,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
                     &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
-                    &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag, &c->ray_sum, &c->ray_pre, &c->sum_cap,
+                    &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
                     &c->frame_block, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
                     &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
@@ -449,21 +449,6 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   for (size_t i = 0; i < V.size(); ++i) {
     if (!std::isfinite(V[i])) return fail(c, DCEM_E_INVALID_ARG, "non-finite vertex coordinate %zu", i / 3);
     R = std::max(R, (double)std::fabs(V[i]));
-  }
-  {
-    // quantisation domain of the ray summaries: the scene's xy extent at
-    // upload, widened (coordinates outside clamp to its edges)
-    float x0 = 0.f, x1 = 0.f, y0 = 0.f, y1 = 0.f;
-    for (size_t i = 0; i + 2 < V.size(); i += 3) {
-      x0 = i ? std::min(x0, V[i]) : V[i];
-      x1 = i ? std::max(x1, V[i]) : V[i];
-      y0 = i ? std::min(y0, V[i + 1]) : V[i + 1];
-      y1 = i ? std::max(y1, V[i + 1]) : V[i + 1];
-    }
-    const float w = std::max(x1 - x0, y1 - y0) * 1.1f + 2.0f;
-    c->sum_x0 = 0.5f * (x0 + x1) - 0.5f * w;
-    c->sum_y0 = 0.5f * (y0 + y1) - 0.5f * w;
-    c->sum_scale = 65535.0f / w;
   }
   for (size_t i = 0; i < T.size(); ++i)
     if (T[i] < 0 || T[i] >= s->n_vertices) return fail(c, DCEM_E_INVALID_ARG, "triangle %zu: vertex index out of range", i / 3);
@@ -732,11 +717,6 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   HIP_TRY(ensure(c->caps[0], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
   HIP_TRY(ensure(c->caps[1], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
   HIP_TRY(ensure(c->work_list, sizeof(uint32_t) * nw), "alloc work list");
-  if (keep_cache) {
-    HIP_TRY(ensure(c->ray_sum, sizeof(uint32_t) * 2 * nw), "alloc ray summaries");
-    HIP_TRY(ensure(c->ray_pre, sizeof(uint32_t) * 2 * nw), "alloc ray summaries");
-    HIP_TRY(ensure(c->sum_cap, 16), "alloc summary cap");
-  }
   HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
   const void* block_before = c->frame_block.p;
   HIP_TRY(ensure_frame_block(c, (int64_t)p->n_freqs * p->n_tx * p->n_rx), "alloc results");

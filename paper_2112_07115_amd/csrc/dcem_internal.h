@@ -165,13 +165,6 @@ struct dcem_ctx {
   dcem::DevBuf caps[2];      // double-buffered capture lists
   int cur_caps = 0;
   dcem::DevBuf work_list, invalid_flag;   // re-trace list; per-ray first invalid segment (255 = valid)
-  // per cached ray: xy box of its path at or below the height cap, 16 bits per
-  // bound over the scene's xy extent (the revalidation's fast test); the same
-  // for the valid segments of an invalid ray (written by the revalidation,
-  // merged by the re-trace: a revalidation discarded before its re-trace
-  // leaves the summaries intact); the cap (one float, set by each full trace)
-  dcem::DevBuf ray_sum, ray_pre, sum_cap;
-  float sum_x0 = 0.f, sum_y0 = 0.f, sum_scale = 0.f;
   // One device block holding everything the host reads after a frame, copied
   // in one transfer to pinned host memory: counters (128 B), error word
   // (128 B), SAH values (256 B), then p_coh and p_inc.

@@ -119,71 +119,6 @@ __device__ inline bool slab(const Ray& r, float lx, float ly, float lz, float hx
   return tn <= tf * 1.0000004f;
 }
 
-// ---- Low-band summary of a cached ray, the revalidation's fast test.  The
-// part of a ray's path at or below a height cap (the moving objects' tops at
-// the last full trace plus kSumCapSlack) is bounded in xy by a box, stored as
-// 16-bit bounds over the scene's xy extent: lower bounds rounded down and
-// upper bounds up after widening by kSumSlack, far above the rounding of the
-// segment arithmetic here and in the exact test.  While every moving object
-// stays below the cap, a ray whose box meets no widened object box cannot be
-// invalid, and its segments need not be read.  Word layout: (upper << 16) |
-// lower for x, then y; an empty box (no part below the cap) has lower > upper.
-constexpr float kSumSlack = 0.05f;      // metres
-constexpr float kSumCapSlack = 2.0f;    // metres
-constexpr uint32_t kSumEmpty = 0x0000ffffu;
-constexpr uint32_t kSumAll = 0xffff0000u;
-
-struct SumGrid {
-  float x0, y0, scale;   // quantisation domain
-};
-
-struct LowBand {
-  float x0, x1, y0, y1;
-  bool unbounded;
-};
-
-__device__ inline LowBand lowband_empty() { return LowBand{INFINITY, -INFINITY, INFINITY, -INFINITY, false}; }
-
-// Add the part of segment o + s d, s in [0, tend], at or below the cap.
-__device__ inline void lowband_add(LowBand& b, const float3& o, const float3& d, float tend, float cap) {
-  float s0 = 0.0f, s1 = tend;
-  if (d.z > 0.0f) s1 = fminf(s1, __fdiv_rn(cap - o.z, d.z));
-  else if (d.z < 0.0f) s0 = fmaxf(s0, __fdiv_rn(cap - o.z, d.z));
-  else if (o.z > cap) return;
-  if (!(s0 <= s1)) return;
-  if (!(s1 < INFINITY)) {
-    b.unbounded = true;
-    return;
-  }
-  const float xa = fmaf(s0, d.x, o.x), xb = fmaf(s1, d.x, o.x);
-  const float ya = fmaf(s0, d.y, o.y), yb = fmaf(s1, d.y, o.y);
-  b.x0 = fminf(b.x0, fminf(xa, xb));
-  b.x1 = fmaxf(b.x1, fmaxf(xa, xb));
-  b.y0 = fminf(b.y0, fminf(ya, yb));
-  b.y1 = fmaxf(b.y1, fmaxf(ya, yb));
-}
-
-__device__ inline uint32_t sum_lo(float v, float origin, float scale) {
-  return (uint32_t)fminf(fmaxf(floorf((v - kSumSlack - origin) * scale), 0.0f), 65535.0f);
-}
-__device__ inline uint32_t sum_hi(float v, float origin, float scale) {
-  return (uint32_t)fminf(fmaxf(floorf((v + kSumSlack - origin) * scale) + 1.0f, 0.0f), 65535.0f);
-}
-
-__device__ inline uint2 lowband_pack(const LowBand& b, const SumGrid& g) {
-  if (b.unbounded) return make_uint2(kSumAll, kSumAll);
-  if (!(b.x0 <= b.x1)) return make_uint2(kSumEmpty, kSumEmpty);
-  return make_uint2(sum_lo(b.x0, g.x0, g.scale) | (sum_hi(b.x1, g.x0, g.scale) << 16),
-                    sum_lo(b.y0, g.y0, g.scale) | (sum_hi(b.y1, g.y0, g.scale) << 16));
-}
-
-__device__ inline uint2 lowband_merge(uint2 a, uint2 b) {
-  if ((a.x & 0xffffu) > (a.x >> 16)) return b;
-  if ((b.x & 0xffffu) > (b.x >> 16)) return a;
-  return make_uint2(min(a.x & 0xffffu, b.x & 0xffffu) | (max(a.x >> 16, b.x >> 16) << 16),
-                    min(a.y & 0xffffu, b.y & 0xffffu) | (max(a.y >> 16, b.y >> 16) << 16));
-}
-
 struct Hit {
   float t;
   int tri;    // original triangle id, -1 none
@@ -321,12 +256,6 @@ struct TraceArgs {
   uint32_t* err;
   const Capture* prev_caps;   // coherent frames: the previous frame's captures to filter
   uint32_t n_prev;
-  uint2* ray_sum;             // low-band summaries (with the segment cache) or null
-  const uint2* ray_pre;       // re-traced rays: summaries of their kept segments
-  float* sum_cap;             // the cap: written by a full frame, read by a re-trace
-  SumGrid sum_grid;
-  const float* obj_box;       // moving objects' boxes [n_obj][6] (the cap of a full frame)
-  int n_obj;
 };
 
 // Coherent frames: keep each capture of the previous frame made before its
@@ -408,16 +337,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
   keep_previous_captures(a, cap_over);
-  // the summaries' height cap: set by a full frame, kept by a re-trace
-  float cap = -INFINITY;
-  if (a.ray_sum) {
-    if (a.restart) {
-      cap = *a.sum_cap;
-    } else {
-      for (int b = 0; b < a.n_obj; ++b) cap = fmaxf(cap, a.obj_box[6 * b + 5] + kSumCapSlack);
-      if (blockIdx.x == 0 && threadIdx.x == 0) *a.sum_cap = cap;
-    }
-  }
   while (true) {
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&a.counters[kCntQueue], (uint32_t)kWave);
@@ -452,7 +371,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       }
       setup_ray(r);
       uint32_t state = 0;
-      LowBand lb = lowband_empty();
       for (; k <= a.K; ++k) {
         Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, kTraceBlock, overflow,
                             node_count, tri_count);
@@ -461,7 +379,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         const float tend = hit ? h.t : INFINITY;
         a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
         if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
-        if (a.ray_sum) lowband_add(lb, r.o, r.d, tend, cap);
         if (a.seg_o) {
           a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
           a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
@@ -535,12 +452,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         }
       }
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
-      if (a.ray_sum) {
-        // a re-traced ray keeps the summary of its earlier segments (written
-        // by the revalidation)
-        const uint2 pre = a.restart ? a.ray_pre[work] : make_uint2(kSumEmpty, kSumEmpty);
-        a.ray_sum[work] = lowband_merge(pre, lowband_pack(lb, a.sum_grid));
-      }
     }
   }
   // one atomic per wavefront for the counters
@@ -674,11 +585,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   bool overflow = false, cap_over = false;
   keep_previous_captures(a, cap_over);
 
-  const float cap = a.ray_sum ? *a.sum_cap : -INFINITY;   // summaries' height cap (of the last full frame)
   // this group's ray (equal on its lanes)
   bool busy = false;
-  LowBand lb = lowband_empty();
-  uint2 pre = make_uint2(kSumEmpty, kSumEmpty);   // summary of the kept segments
   uint32_t work = 0, txi = 0, state = 0;
   int k = 0, excl = -1, guard = 0, sp = 0;
   float L = 0.0f, best_t = INFINITY;
@@ -724,8 +632,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     }
     setup_ray(r);
     state = 0;
-    lb = lowband_empty();
-    if (a.ray_sum) pre = a.ray_pre[work];
     begin_segment();
   };
 
@@ -823,7 +729,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const float4 w2 = make_float4(__shfl(h.v2.x, src), __shfl(h.v2.y, src), __shfl(h.v2.z, src), 0.0f);
     const float tend = hit ? th : INFINITY;
     if (hit && moving) state |= 0x80u;
-    if (a.ray_sum) lowband_add(lb, r.o, r.d, tend, cap);
     const float dd = dot_dd(r);
     const float L_hit = __fmaf_rn(th, __fsqrt_rn(dd), L);
     if (gl == 0) {
@@ -905,7 +810,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
         }
       }
       a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
-      if (a.ray_sum) a.ray_sum[work] = lowband_merge(pre, lowband_pack(lb, a.sum_grid));
     }
     // the next item from the shared queue, unless the first items covered
     // every ray (no atomic round trip then)
@@ -990,10 +894,6 @@ struct CohArgs {
   uint32_t* list;
   uint32_t* counters;
   int list_cap;   // invalid rays a block collects in LDS (dynamic, after the grid)
-  const uint2* ray_sum;   // low-band summaries
-  uint2* ray_pre;         // written for invalid rays: the summary of their valid segments
-  const float* sum_cap;
-  SumGrid sum_grid;
 };
 
 // One block of the revalidation pass: block cb of n_cb, blockDim.x threads.
@@ -1024,17 +924,12 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
   const bool grid = n_obj <= kCohGridObjects;
   const int words = (n_obj + 63) / 64;
   unsigned long long* cell = coh_lds;
-  unsigned long long* qcell = coh_lds + (grid ? kCohGrid * kCohGrid * words : 0);   // summary grid
-  float* blf = reinterpret_cast<float*>(qcell + (grid ? kCohGrid * kCohGrid * words : 0));
-  uint4* qbox = reinterpret_cast<uint4*>(blf + (grid ? 6 * n_obj : 0));   // quantised widened boxes
-  uint32_t* blist = reinterpret_cast<uint32_t*>(qbox + (grid ? n_obj : 0));
+  float* blf = reinterpret_cast<float*>(coh_lds + (grid ? kCohGrid * kCohGrid * words : 0));
+  uint32_t* blist = reinterpret_cast<uint32_t*>(blf + (grid ? 6 * n_obj : 0));
   auto bl = [&](int a, int b) -> float& { return blf[a * n_obj + b]; };
   if (threadIdx.x < 6) ext[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;
   if (grid)
-    for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += nth) {
-      cell[c] = 0ull;
-      qcell[c] = 0ull;
-    }
+    for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += nth) cell[c] = 0ull;
   __syncthreads();
   for (int b = threadIdx.x; b < n_obj; b += nth) {
     for (int a = 0; a < 3; ++a) {
@@ -1058,25 +953,14 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
   auto cell_of = [](float u) { return (int)fminf(fmaxf(floorf(u), 0.0f), (float)(kCohGrid - 1)); };
   auto cx = [&](float x) { return cell_of((x - gx0) * sx); };
   auto cy = [&](float y) { return cell_of((y - gy0) * sy); };
-  const SumGrid& sg = args.sum_grid;
   if (grid) {
     for (int b = threadIdx.x; b < n_obj; b += nth) {
       const int x0 = cx(bl(0, b)), x1 = cx(bl(3, b)), y0 = cy(bl(1, b)), y1 = cy(bl(4, b));
       for (int y = y0; y <= y1; ++y)
         for (int x = x0; x <= x1; ++x) atomicOr(&cell[(y * kCohGrid + x) * words + (b >> 6)], 1ull << (b & 63));
-      // the box widened by the exact test's margin, quantised like the summaries
-      const uint4 q = make_uint4(sum_lo(bl(0, b) - margin, sg.x0, sg.scale), sum_hi(bl(3, b) + margin, sg.x0, sg.scale),
-                                 sum_lo(bl(1, b) - margin, sg.y0, sg.scale), sum_hi(bl(4, b) + margin, sg.y0, sg.scale));
-      qbox[b] = q;
-      for (uint32_t y = q.z >> 11; y <= q.w >> 11; ++y)
-        for (uint32_t x = q.x >> 11; x <= q.y >> 11; ++x)
-          atomicOr(&qcell[(y * kCohGrid + x) * words + (b >> 6)], 1ull << (b & 63));
     }
   }
   __syncthreads();
-  // the fast test applies while every moving object stays below the cap the
-  // cached summaries were made with
-  const bool use_sum = grid && args.ray_sum && n_obj > 0 && zhi + kSumSlack <= *args.sum_cap;
   const int lane = threadIdx.x & (kWave - 1);
   // blocks stride over the rays (the grid above is built once per block)
   for (int base0 = cb * nth; base0 < n_work; base0 += n_cb * nth) {
@@ -1087,36 +971,6 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
       const uint32_t st = ray_state[w];
       const int nseg = (int)(st & 0x0fu);
       const bool moving_hit = (st & 0x80u) != 0;
-      // fast test: the summary box against the objects' quantised boxes
-      bool maybe = true;
-      if (use_sum && !moving_hit) {
-        const uint2 sm = args.ray_sum[w];
-        const uint32_t x0 = sm.x & 0xffffu, x1 = sm.x >> 16, y0 = sm.y & 0xffffu, y1 = sm.y >> 16;
-        maybe = false;
-        if (x0 <= x1) {
-          const uint32_t cx0 = x0 >> 11, cx1 = x1 >> 11, cy0 = y0 >> 11, cy1 = y1 >> 11;
-          const bool all = (cx1 - cx0 + 1) * (cy1 - cy0 + 1) > (uint32_t)kCohMaxCells;
-          for (int wd = 0; wd < words && !maybe; ++wd) {
-            unsigned long long m = 0;
-            if (all) {
-              m = ~0ull;
-            } else {
-              for (uint32_t y = cy0; y <= cy1; ++y)
-                for (uint32_t x = cx0; x <= cx1; ++x) m |= qcell[(y * kCohGrid + x) * words + wd];
-            }
-            while (m) {
-              const int b = 64 * wd + __ffsll(m) - 1;
-              m &= m - 1;
-              if (b >= n_obj) break;
-              const uint4 q = qbox[b];
-              if (!(x1 < q.x || x0 > q.y || y1 < q.z || y0 > q.w)) {
-                maybe = true;
-                break;
-              }
-            }
-          }
-        }
-      }
       // does the cached segment (o, d) meet a moving object's box now?
       // Does the cached segment (o, d) meet a moving object's box now?  The
       // answer only has to be conservative (a ray listed without need is traced
@@ -1183,12 +1037,10 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
       // point), then the last segment's direction and extent.  Segment k < last
       // runs from origin k to origin k + 1.  Origins are loaded in batches, so
       // a ray of n >= 2 segments reads n cached 16-byte records.
-      const int last = maybe ? nseg - 1 : -1;
+      const int last = nseg - 1;
       const uint32_t txi = (uint32_t)(w / (uint64_t)n_rays);
       float4 prev = make_float4(tx[3 * txi], tx[3 * txi + 1], tx[3 * txi + 2], 0.0f);   // origin of segment k0
       if (last == 0) prev.w = seg_o[w].w;   // the one segment's extent
-      const float cap = args.ray_sum ? *args.sum_cap : -INFINITY;
-      LowBand lb = lowband_empty();   // the valid segments' low band (a re-traced ray keeps it)
       for (int k0 = 0; k0 <= last && first == 255; k0 += kCohBatch) {
         float4 nxt[kCohBatch];   // origin of segment k0 + j + 1 (its extent in w)
         int bf[kCohBatch];
@@ -1215,11 +1067,9 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
             d = dl;
           }
           if ((bf[j] >= 0 && face_object[bf[j]] >= 0) || meets_moving(o, d)) first = k;
-          else if (args.ray_sum) lowband_add(lb, make_float3(o.x, o.y, o.z), make_float3(d.x, d.y, d.z), o.w, cap);
         }
       }
       restart[w] = (uint8_t)first;
-      if (first != 255 && args.ray_sum) args.ray_pre[w] = lowband_pack(lb, args.sum_grid);
     }
     const bool bad = first != 255;
     const uint64_t m = __ballot(bad);
@@ -1349,12 +1199,6 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   a.err = c->err_dev;
   a.prev_caps = ptr<Capture>(c->caps[c->cur_caps ^ 1]);
   a.n_prev = all_rays ? 0u : n_prev_caps;
-  a.ray_sum = keep_cache ? ptr<uint2>(c->ray_sum) : nullptr;
-  a.ray_pre = ptr<uint2>(c->ray_pre);
-  a.sum_cap = keep_cache ? ptr<float>(c->sum_cap) : nullptr;
-  a.sum_grid = SumGrid{c->sum_x0, c->sum_y0, c->sum_scale};
-  a.obj_box = ptr<float>(c->obj_box);
-  a.n_obj = c->no;
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
     const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;
@@ -1390,10 +1234,6 @@ CohArgs coherence_args(dcem_ctx* c) {
   a.restart = ptr<uint8_t>(c->invalid_flag);
   a.list = ptr<uint32_t>(c->work_list);
   a.counters = c->cnt_dev;
-  a.ray_sum = ptr<uint2>(c->ray_sum);
-  a.ray_pre = ptr<uint2>(c->ray_pre);
-  a.sum_cap = ptr<float>(c->sum_cap);
-  a.sum_grid = SumGrid{c->sum_x0, c->sum_y0, c->sum_scale};
   return a;
 }
 
@@ -1401,9 +1241,9 @@ CohArgs coherence_args(dcem_ctx* c) {
 // kCohGridObjects objects, which are then tested one by one), then the
 // block's list of invalid rays
 size_t coherence_lds(const dcem_ctx* c, int list_cap) {
-  return (c->no <= kCohGridObjects ? 2 * sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) +
-                                         sizeof(float) * 6 * c->no + sizeof(uint4) * c->no
-                                   : 0) +
+  return (c->no <= kCohGridObjects
+              ? sizeof(unsigned long long) * kCohGrid * kCohGrid * ((c->no + 63) / 64) + sizeof(float) * 6 * c->no
+              : 0) +
          sizeof(uint32_t) * list_cap;
 }
 

@@ -60,11 +60,10 @@ def test_coherent_equals_full_retrace():
     coh.close()
 
 
-def test_objects_lifted_above_the_summary_cap():
-    """Cached rays are first screened by the box of their path below a height
-    cap (the objects' tops at the last full frame plus 2 m).  Objects lifted
-    above the cap switch the screen off, and it comes back when they return;
-    every frame must still equal the full re-trace."""
+def test_objects_lifted_and_lowered():
+    """Vertical motion: every third vehicle lifted by up to 6 m and lowered
+    again (its cached rays above and below the street change validity); every
+    frame must still equal the full re-trace."""
     s = scenes.dynamic_urban()
     n = 1 << 16
     full, coh = dcem.Context(0), dcem.Context(0)
