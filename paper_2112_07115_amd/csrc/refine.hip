@@ -161,6 +161,14 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
   __shared__ uint32_t wsum[kCandBlock / kWave + 1];
   uint4* bkey = reinterpret_cast<uint4*>(slot_best);     // after step 2: unique keys by bucket
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  // the records are loaded while their count is (every record below the
+  // buffer's capacity is readable; those past the count go unused)
+  Capture cr[kCandPer];
+#pragma unroll
+  for (int q = 0; q < kCandPer; ++q) {
+    const uint32_t i = tid + q * kCandBlock;
+    cr[q] = i < capacity ? caps[i] : Capture{kNoRay, 0u};
+  }
   // the counter keeps counting past the buffer when captures overflow (the
   // trace kernel flags that); only the stored records are read
   const uint32_t n = min(*n_dev, capacity);
@@ -182,7 +190,7 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     const uint32_t i = tid + q * kCandBlock;
     work[q] = 0;
     if (i < n) {
-      const Capture c = caps[i];
+      const Capture c = cr[q];
       uint32_t w[8];
       capture_key(c, face_log, n_work, L, w);
       for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
@@ -596,19 +604,24 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ double simg[(kMaxK + 1) * 3];    // transmitter images
   __shared__ uint32_t stk[kMaxK + 1][kCheckStack];
   const uint32_t u = blockIdx.x;
-  if (u >= *a.n_unique) return;   // uniform over the block
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int K = a.K;
-  // ---- 1. geometry (the candidate's pair, order and faces were decoded by
-  // the de-duplication): lane j loads face j and its plane, lane 0 then runs
-  // the image method on LDS copies
+  // the decoded candidate (pair, order, faces: written by the
+  // de-duplication) is loaded while the count is; the arrays hold an entry
+  // for every block, and entries past the count are never used
+  int order0 = 0, pair = 0, face = -1;
   if (w == 0) {
-    const int order = a.order[u];
-    const int pair = a.pair[u];
-    if (lane < order) {
-      const int f = a.faces[(size_t)u * K + lane];
-      sfaces[lane] = f;
-      spl[lane] = a.plane[f];
+    order0 = a.order[u];
+    pair = a.pair[u];
+    if (lane < K) face = a.faces[(size_t)u * K + lane];
+  }
+  if (u >= *a.n_unique) return;   // uniform over the block
+  // ---- 1. geometry: lane j takes face j and loads its plane, lane 0 then
+  // runs the image method on LDS copies
+  if (w == 0) {
+    if (lane < order0) {
+      sfaces[lane] = face;
+      spl[lane] = a.plane[face];
     }
     wave_sync();
     if (lane == 0) {
@@ -617,7 +630,7 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       // images of the transmitter through the face planes in turn (Sec. III)
       D3 im = T;
       simg[0] = im.x; simg[1] = im.y; simg[2] = im.z;
-      for (int j = 1; j <= order; ++j) {
+      for (int j = 1; j <= order0; ++j) {
         const double4 pl = spl[j - 1];
         const D3 n = {pl.x, pl.y, pl.z};
         im = im - (2.0 * (dot(im, n) - pl.w)) * n;
@@ -627,7 +640,7 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       double* P = a.pts + (size_t)u * (K + 2) * 3;
       bool ok = true;
       D3 Q = R;
-      for (int j = order; j >= 1; --j) {
+      for (int j = order0; j >= 1; --j) {
         const double4 pl = spl[j - 1];
         const D3 n = {pl.x, pl.y, pl.z};
         const D3 D = D3{simg[3 * j], simg[3 * j + 1], simg[3 * j + 2]} - Q;
@@ -640,12 +653,12 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
         sP[3 * j] = Q.x; sP[3 * j + 1] = Q.y; sP[3 * j + 2] = Q.z;
       }
       P[0] = T.x; P[1] = T.y; P[2] = T.z;
-      P[3 * (order + 1)] = R.x; P[3 * (order + 1) + 1] = R.y; P[3 * (order + 1) + 2] = R.z;
+      P[3 * (order0 + 1)] = R.x; P[3 * (order0 + 1) + 1] = R.y; P[3 * (order0 + 1) + 2] = R.z;
       sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
-      sP[3 * (order + 1)] = R.x; sP[3 * (order + 1) + 1] = R.y; sP[3 * (order + 1) + 2] = R.z;
+      sP[3 * (order0 + 1)] = R.x; sP[3 * (order0 + 1) + 1] = R.y; sP[3 * (order0 + 1) + 2] = R.z;
       sd = len(R - im);
       a.length[u] = sd;
-      sorder = order;
+      sorder = order0;
       sok = ok ? 1 : 0;
       sfail = 0;
     }
