@@ -377,7 +377,7 @@ void dcem_destroy(dcem_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
-                    &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->face_ref_tri, &c->xf,
+                    &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->tri_slot, &c->face_slots, &c->face_ref_tri, &c->xf,
                     &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
                     &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
@@ -555,6 +555,12 @@ dcem_status dcem_set_object_transforms(dcem_ctx* c, const float* xf, int32_t n_o
   if (!xf) return fail(c, DCEM_E_INVALID_ARG, "null transforms");
   c->revalidated_ahead = false;   // it saw the old object boxes (the frame stays begun)
   HIP_TRY(hipSetDevice(c->device), "set device");
+  if (c->refit_pending && c->copy_pending) {
+    // the pending refit is about to change the tree an unread frame may still
+    // need (see dcem_refit_bvh): finish that frame first
+    const dcem_status st = sync_frame(c);
+    if (st != DCEM_OK) return st;
+  }
   HIP_TRY(flush_refit(c), "refit");
   if (mem_kind == DCEM_MEM_HOST) {
     for (int i = 0; i < 12 * n_objects; ++i)
@@ -583,6 +589,13 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   const double measured = c->pending_ratio;
   int32_t rb = 0;
   if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
+    // a frame whose results are still unread may have to redo its candidates
+    // (more captures than the device path holds), which reads the tree it
+    // was traced with: finish it before the tree is rebuilt
+    if (c->copy_pending) {
+      const dcem_status st = sync_frame(c);
+      if (st != DCEM_OK) return st;
+    }
     c->refit_pending = false;
     ev_record(c, 6);
     // a forced rebuild serves the frame at hand; one the quality test asks

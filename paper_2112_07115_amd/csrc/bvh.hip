@@ -501,6 +501,18 @@ void launch_xform(dcem_ctx* c, const float* xf) {
 
 // Build the binary LBVH and its 4-wide collapse, entirely on the stream (no
 // host round trip).  The SAH sum ratio of the new tree goes to sah_dev[0].
+__global__ void k_tri_slot(const int32_t* __restrict__ leaf_tri, const int32_t* __restrict__ leaf_slot, int n,
+                           int32_t* __restrict__ tri_slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) tri_slot[leaf_tri[i]] = leaf_slot[i];
+}
+
+__global__ void k_face_slots(const int32_t* __restrict__ face_tris, const int32_t* __restrict__ tri_slot, int n,
+                             int32_t* __restrict__ face_slots) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) face_slots[k] = tri_slot[face_tris[k]];
+}
+
 hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   const int64_t nt = c->nt;
   hipError_t e;
@@ -628,6 +640,16 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   hipLaunchKernelGGL(k_map4, dim3((ni + 255) / 256), dim3(256), 0, c->stream, dperm, n4, ni,
                      ptr<int32_t>(c->bvh2_of4), ptr<int32_t>(c->map4));
   launch_collapse(c);
+  // slot of every face triangle, for the refinement's face test (face_tris
+  // lists every triangle once, grouped by face)
+  const int64_t nft = nt;
+  if ((e = ensure(c->tri_slot, sizeof(int32_t) * nt)) != hipSuccess) return e;
+  if ((e = ensure(c->face_slots, sizeof(int32_t) * std::max<int64_t>(nft, 1))) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tri_slot, dim3((nt + 255) / 256), dim3(256), 0, c->stream, ptr<int32_t>(c->leaf_tri),
+                     ptr<int32_t>(c->leaf_slot), (int)nt, ptr<int32_t>(c->tri_slot));
+  if (nft > 0)
+    hipLaunchKernelGGL(k_face_slots, dim3((unsigned)((nft + 255) / 256)), dim3(256), 0, c->stream,
+                       ptr<int32_t>(c->face_tris), ptr<int32_t>(c->tri_slot), (int)nft, ptr<int32_t>(c->face_slots));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   c->has_bvh = true;
   return hipSuccess;

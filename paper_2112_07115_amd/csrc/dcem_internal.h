@@ -127,6 +127,10 @@ struct dcem_ctx {
   float pad = 0.f;          // absolute padding of leaf boxes (conservative traversal)
   dcem::DevBuf ref_vertices, vertices, tris, tri_face, face_material, face_object, materials,
       obj_range, face_tri_off, face_tris, face_ref_tri, xf, obj_box, face_plane;
+  // per entry of face_tris: the slot of that triangle in the slot triangle
+  // array (set by each build), so the refinement's face test reads the
+  // vertices the tree holds (the refit's, not a later transform's)
+  dcem::DevBuf tri_slot, face_slots;
   std::vector<int32_t> h_face_object;
 
   // -- BVH

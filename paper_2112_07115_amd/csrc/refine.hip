@@ -443,8 +443,7 @@ struct RefineArgs {
   const double4* plane;
   const int32_t* face_tri_off;
   const int32_t* face_tris;
-  const int32_t* tris;
-  const float* V;
+  const int32_t* face_slots;   // slot triangle of each face_tris entry
   const int32_t* face_material;
   const double* materials;
   const Node4* nodes4;
@@ -483,8 +482,8 @@ __device__ bool in_face(const RefineArgs& a, int f, D3 p, D3 n, int k0 = 0, int 
   double pu, pw;
   pr(p, pu, pw);
   for (int k = a.face_tri_off[f] + k0; k < a.face_tri_off[f + 1]; k += step) {
-    const int t = a.face_tris[k];
-    D3 A = fvec(a.V, a.tris[3 * t]), B = fvec(a.V, a.tris[3 * t + 1]), C = fvec(a.V, a.tris[3 * t + 2]);
+    const Leaf L = a.tri4[a.face_slots[k]];
+    const D3 A = {L.v0.x, L.v0.y, L.v0.z}, B = {L.v1.x, L.v1.y, L.v1.z}, C = {L.v2.x, L.v2.y, L.v2.z};
     double au, aw, bu, bw, cu, cw;
     pr(A, au, aw);
     pr(B, bu, bw);
@@ -934,8 +933,7 @@ void launch_refine(dcem_ctx* c) {
   a.plane = ptr<double4>(c->face_plane);
   a.face_tri_off = ptr<int32_t>(c->face_tri_off);
   a.face_tris = ptr<int32_t>(c->face_tris);
-  a.tris = ptr<int32_t>(c->tris);
-  a.V = ptr<float>(c->vertices);
+  a.face_slots = ptr<int32_t>(c->face_slots);
   a.face_material = ptr<int32_t>(c->face_material);
   a.materials = ptr<double>(c->materials);
   a.nodes4 = ptr<Node4>(c->nodes4);

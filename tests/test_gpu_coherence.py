@@ -91,6 +91,47 @@ def test_objects_lifted_and_lowered():
     coh.close()
 
 
+def test_pipelined_frames_with_large_capture_lists():
+    """More captures than the one-workgroup de-duplication holds: the host
+    redoes a frame's candidates when it reads the results, after the next
+    frame's transforms (and refit or rebuild requests) were already given.
+    The redo must still see the traced frame's geometry."""
+    s = scenes.dynamic_urban()
+    s2 = scenes.Scene(**{**s.__dict__, "rx_radius": 3.0})
+    n = 1 << 16
+    full, coh = dcem.Context(0), dcem.Context(0)
+    full.scene_upload(s2)
+    coh.scene_upload(s2)
+    kw = dict(max_reflections=s2.max_reflections, freqs_hz=s2.freqs_hz, tx_power_w=s2.tx_power_w,
+              record_trace_log=True)
+
+    def reference(frame):
+        full.set_object_transforms(s2.transforms(frame))
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s2.tx, s2.rx, s2.rx_radius, n, mode=dcem.MODE_FULL, **kw)
+        return frame_outputs(full)
+
+    coh.set_object_transforms(s2.transforms(0))
+    coh.refit_bvh()
+    for frame in range(0, 5):
+        coh.trace_frame(s2.tx, s2.rx, s2.rx_radius, n, mode=dcem.MODE_COHERENT, **kw)
+        # the next frame's geometry before this frame's read-back: a refit,
+        # transforms set twice, or a forced rebuild
+        nxt = s2.transforms(frame + 1)
+        if frame == 2:
+            coh.set_object_transforms(s2.transforms(frame + 3))
+            coh.refit_bvh()
+        coh.set_object_transforms(nxt)
+        coh.refit_bvh(force_rebuild=(frame == 3))
+        out = frame_outputs(coh)
+        st = coh.stats()
+        log("frame", frame, "captures", st["captures"], "unique", st["unique_candidates"])
+        assert st["captures"] > 2048
+        assert_same(reference(frame), out)
+    full.close()
+    coh.close()
+
+
 def test_refit_equals_rebuild():
     s = scenes.dynamic_urban()
     a, b = dcem.Context(0), dcem.Context(0)
