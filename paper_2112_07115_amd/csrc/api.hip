@@ -219,6 +219,7 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   hipError_t je = flush_refit(c);   // a pending refit writes its SAH value here
   if (je != hipSuccess) return je;
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
+  c->list_clear = false;   // the new block's counters start undefined
   // keep the head (SAH values of the current tree) across a reallocation
   double sah_keep[2] = {1.0, 1.0};
   const bool had = c->frame_block.p != nullptr;
@@ -258,11 +259,16 @@ void go_ahead(dcem_ctx* c) {
     c->cur_caps ^= 1;
     c->frame_begun = true;
   }
+  // the last frame's reduction zeroed the list counter: the revalidation's
+  // launch also starts the frame (one launch instead of two), unless an
+  // earlier early start of this frame appended to it
+  const bool fresh = c->list_clear;
   ev_record(c, 0);
-  launch_frame_begin(c, c->last_los);
+  if (!fresh) launch_frame_begin(c, c->last_los);
   c->refit_pending = false;
   ev_record(c, 6);
-  launch_refit_coherence(c);
+  launch_refit_coherence(c, fresh);
+  c->list_clear = false;
   ev_record(c, 7);
   ev_record(c, 1);
   c->revalidated_ahead = true;
@@ -756,12 +762,13 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
       // the revalidation does not read the tree: one launch with the refit
       c->refit_pending = false;
       ev_record(c, 6);
-      launch_refit_coherence(c);
+      launch_refit_coherence(c, false);
       ev_record(c, 7);
     } else {
       HIP_TRY(flush_refit(c), "refit");
       if (coherent) launch_coherence(c);
     }
+    c->list_clear = false;
     ev_record(c, 1);
   }
   c->frame_begun = false;
@@ -778,6 +785,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   launch_refine(c);
   ev_record(c, 4);
   launch_reduce(c);
+  c->list_clear = true;
   ev_record(c, 5);
   HIP_TRY(hipGetLastError(), "refine kernels");
   // the results of the frame, read back behind its last kernel

@@ -113,6 +113,7 @@ struct dcem_ctx {
   // configuration then starts at the re-trace.
   bool frame_begun = false;
   bool revalidated_ahead = false;
+  bool list_clear = false;   // kCntList of the current frame block is zero (its last frame's reduction ran)
   bool last_los = true;
   hipEvent_t ev_copy = nullptr;   // the last traced frame's results have reached host_block
   bool copy_pending = false;
@@ -220,6 +221,9 @@ enum : int {
   kCntNodes = 6,      // BVH nodes visited by the trace kernel (64-bit, slots 6-7)
   kCntTris = 8,       // triangle tests of the trace kernel (64-bit, slots 8-9)
   kCntFallback = 10,  // the small de-duplication path saw more captures than it holds
+  kCntList = 11,      // rays the revalidation listed for the re-trace (the trace copies it to kCntWork);
+                      // zeroed at the end of each frame, so the next frame's revalidation may start
+                      // before that frame's other counters are reset
   kCntSlots = 12,     // number of counter words cleared per frame
 };
 
@@ -256,7 +260,7 @@ void launch_fibonacci(dcem_ctx* c);
 int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps);
 void launch_coherence(dcem_ctx* c);
 // The pending refit of the 4-wide tree and the revalidation pass in one launch.
-void launch_refit_coherence(dcem_ctx* c);
+void launch_refit_coherence(dcem_ctx* c, bool begin);
 // Clear the frame counters and seed the capture list with the LoS candidates.
 void launch_frame_begin(dcem_ctx* c, bool los);
 hipError_t build_ray_order(dcem_ctx* c);

@@ -765,6 +765,9 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair
                                                 double* __restrict__ p_inc, uint32_t* __restrict__ counters) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
+  // the re-trace has read this frame's list length: zero it for the next
+  // frame's revalidation (which may start before that frame's lists are reset)
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCntList] = 0;
   __shared__ uint32_t nvalid;   // valid paths of the block's pairs
   if (threadIdx.x == 0) nvalid = 0;
   __syncthreads();

@@ -333,7 +333,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   for (int i = threadIdx.x; i < n_top; i += blockDim.x) top[i] = a.nodes4[i];
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t n_work = a.work_list ? a.counters[kCntWork] : (uint32_t)a.n_work;
+  const uint32_t n_work = a.work_list ? a.counters[kCntList] : (uint32_t)a.n_work;
+  if (a.work_list && blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
   keep_previous_captures(a, cap_over);
@@ -580,7 +581,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     return (int)fminf(fmaxf(floorf((x - a.rx_col_x0) * a.rx_col_scale), 0.0f), (float)(kRxCols - 1));
   };
   const uint32_t root = n4 > 0 ? a.n4_dev[1] << kNodeBits : 0u;
-  const uint32_t n_work = a.counters[kCntWork];
+  const uint32_t n_work = a.counters[kCntList];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
   keep_previous_captures(a, cap_over);
@@ -844,21 +846,34 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
-// Start of a frame: clear the counters and, with deterministic line of sight,
-// put one LoS candidate per (tx, rx) pair at the head of the capture list.
-__global__ void k_frame_begin(uint32_t* __restrict__ counters, Capture* __restrict__ caps, int n_los,
-                              int64_t cap_capacity, uint32_t* __restrict__ err) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < kCntSlots) counters[threadIdx.x] = threadIdx.x == kCntCaptures ? n_los : 0;
-  if (p >= n_los) return;
-  if (p < cap_capacity) {
-    Capture c;
-    c.work = kNoRay;
-    c.pair_order = (uint32_t)p << 4;
-    caps[p] = c;
-  } else if (p == cap_capacity) {
-    atomicOr(err, DCEM_ERR_CAPTURES);
+// Start of a frame's lists: the counters reset (the revalidation's list
+// counter kept when `keep_list`: a revalidation in the same launch appends to
+// it) and one line-of-sight record per (tx, rx) pair at the head of the
+// capture list.  Threads `t` of `nt` share the records.
+struct FrameBegin {
+  uint32_t* counters;
+  Capture* caps;
+  int n_los;
+  int64_t cap_capacity;
+  uint32_t* err;
+};
+
+__device__ inline void frame_begin_part(const FrameBegin& f, int t, int nt, bool keep_list) {
+  if (t < kCntSlots && !(keep_list && t == kCntList)) f.counters[t] = t == kCntCaptures ? f.n_los : 0;
+  for (int p = t; p < f.n_los; p += nt) {
+    if (p < f.cap_capacity) {
+      Capture c;
+      c.work = kNoRay;
+      c.pair_order = (uint32_t)p << 4;
+      f.caps[p] = c;
+    } else if (p == f.cap_capacity) {
+      atomicOr(f.err, DCEM_ERR_CAPTURES);
+    }
   }
+}
+
+__global__ void k_frame_begin(FrameBegin f) {
+  frame_begin_part(f, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, false);
 }
 
 // Coherence pass.  Segment k of a cached ray is still valid iff no earlier
@@ -1080,13 +1095,13 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
       if (bad) {
         const uint32_t p = base + __popcll(m & ((1ull << lane) - 1ull));
         if (p < (uint32_t)kList) blist[p] = w;
-        else list[atomicAdd(&counters[kCntWork], 1u)] = w;   // only when a block is given more rays
+        else list[atomicAdd(&counters[kCntList], 1u)] = w;   // only when a block is given more rays
       }
     }
   }
   __syncthreads();
   const uint32_t nb = min(bcount, (uint32_t)kList);
-  if (threadIdx.x == 0 && nb) bbase = atomicAdd(&counters[kCntWork], nb);
+  if (threadIdx.x == 0 && nb) bbase = atomicAdd(&counters[kCntList], nb);
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < nb; j += nth) list[bbase + j] = blist[j];
 }
@@ -1096,9 +1111,17 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(CohArgs a) { coherence_
 // A coherent frame's refit and revalidation in one launch: blocks [0, n_rb)
 // refit the tree, the others revalidate the cached rays (which do not read the
 // tree), so the latency-bound refit overlaps the revalidation.
-__global__ __launch_bounds__(kRefitBlock) void k_refit_coherence(RefitArgs ra, CohArgs ca, int n_rb) {
-  if ((int)blockIdx.x < n_rb) refit_block(ra, blockIdx.x, n_rb);
-  else coherence_block(ca, blockIdx.x - n_rb, gridDim.x - n_rb);
+// With `begin`, the first revalidation block also starts the frame's lists
+// (all but the list counter the revalidation appends to, which the previous
+// frame's reduction zeroed).
+__global__ __launch_bounds__(kRefitBlock) void k_refit_coherence(RefitArgs ra, CohArgs ca, int n_rb, FrameBegin fb,
+                                                                 int begin) {
+  if ((int)blockIdx.x < n_rb) {
+    refit_block(ra, blockIdx.x, n_rb);
+  } else {
+    if (begin && (int)blockIdx.x == n_rb) frame_begin_part(fb, threadIdx.x, blockDim.x, true);
+    coherence_block(ca, blockIdx.x - n_rb, gridDim.x - n_rb);
+  }
 }
 
 
@@ -1212,10 +1235,14 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   return 0;
 }
 
+FrameBegin frame_begin_args(dcem_ctx* c, bool los) {
+  return FrameBegin{c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), los ? c->n_tx * c->n_rx : 0, c->cap_capacity,
+                    c->err_dev};
+}
+
 void launch_frame_begin(dcem_ctx* c, bool los) {
-  const int n_los = los ? c->n_tx * c->n_rx : 0;
-  hipLaunchKernelGGL(k_frame_begin, dim3((unsigned)std::max(1, (n_los + 255) / 256)), dim3(256), 0, c->stream,
-                     c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), n_los, c->cap_capacity, c->err_dev);
+  const FrameBegin f = frame_begin_args(c, los);
+  hipLaunchKernelGGL(k_frame_begin, dim3((unsigned)std::max(1, (f.n_los + 255) / 256)), dim3(256), 0, c->stream, f);
 }
 
 CohArgs coherence_args(dcem_ctx* c) {
@@ -1259,7 +1286,7 @@ void launch_coherence(dcem_ctx* c) {
                      a);
 }
 
-void launch_refit_coherence(dcem_ctx* c) {
+void launch_refit_coherence(dcem_ctx* c, bool begin) {
   CohArgs ca = coherence_args(c);
   ca.list_cap = 2 * kCohList;
   const int n_rb = refit_blocks(c);
@@ -1270,7 +1297,8 @@ void launch_refit_coherence(dcem_ctx* c) {
       std::min<int64_t>((ca.n_work + kRefitBlock - 1) / kRefitBlock, std::max(cu_count(c) - n_rb, 1)),
       (ca.n_work + ca.list_cap - 1) / ca.list_cap);
   hipLaunchKernelGGL(k_refit_coherence, dim3(n_rb + std::max(cb, 1)), dim3(kRefitBlock),
-                     coherence_lds(c, ca.list_cap), c->stream, make_refit_args(c, true, c->sah_dev + 1), ca, n_rb);
+                     coherence_lds(c, ca.list_cap), c->stream, make_refit_args(c, true, c->sah_dev + 1), ca, n_rb,
+                     frame_begin_args(c, c->last_los), begin ? 1 : 0);
 }
 
 hipError_t build_ray_order(dcem_ctx* c) {
