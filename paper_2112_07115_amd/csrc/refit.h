@@ -5,6 +5,7 @@
 #include "dcem_internal.h"
 
 #include <cfloat>
+#include <type_traits>
 
 namespace dcem {
 
@@ -121,6 +122,17 @@ __device__ inline void put_child_box(const RefitArgs& a, int p2, int d, const fl
 
 constexpr int kMaxCross = 1024;   // cross nodes finished in LDS by the last block
 
+// Arrival at a node whose two child boxes meet in LDS: the count of earlier
+// arrivals.  The boxes are exchanged through LDS only, so the ordering is an
+// LDS-only release and acquire (no wait for the global box stores of the
+// level, which only the last block reads, after the device-scope ticket).
+__device__ inline uint32_t lds_arrive(uint32_t* cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  return old;
+}
+
 // Sum of v over the block (kRefitBlock threads), valid in thread 0, in a fixed
 // order: butterflies within each wavefront, then the wavefronts' sums in order.
 __device__ inline double block_sum(double v, double* red) {
@@ -158,7 +170,7 @@ __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t 
     for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
       float* bx = lbox[k] + 6 * slot;
       for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
-      const uint32_t old = __hip_atomic_fetch_add(&lcnt[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const uint32_t old = lds_arrive(&lcnt[k]);
       if (old == 0) break;
       const float* sb = lbox[k] + 6 * (slot ^ 1);
       for (int q = 0; q < 3; ++q) {
@@ -240,48 +252,53 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
       if (a.wide) a.tri4[1] = L;
       for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
     } else {
-      int p2 = a.leaf_parent[i];
-      for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
-        const int node = p2 >> 1, slot = p2 & 1;
-        const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
-        int d = -1;
-        if (a.wide) {
+      // the climb, compiled apart for the two-phase case (the usual one), so
+      // that its in-block levels contain no global load to wait for
+      auto climb = [&](auto two_phase_t) {
+        constexpr bool kTwoPhase = decltype(two_phase_t)::value;
+        int p2 = a.leaf_parent[i];
+        // the leaf's loads are complete before the loop (vmcnt 0): otherwise
+        // the wait for them sits at the loop head and every level would wait
+        // for the previous level's box stores as well
+        if (kTwoPhase) __builtin_amdgcn_s_waitcnt(0x0f70);
+        for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
+          const int node = p2 >> 1, slot = p2 & 1;
+          const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
+          float slo[3], shi[3];
           if (local) {
             const int2 ds = lslot4[node - b0];
-            d = slot ? ds.y : ds.x;
+            put_child_box(a, p2, a.wide ? (slot ? ds.y : ds.x) : -1, lo, hi);
+            float* bx = lbox[node - b0] + 6 * slot;
+            for (int k = 0; k < 3; ++k) { bx[k] = lo[k]; bx[3 + k] = hi[k]; }
+            if (lds_arrive(&lcnt[node - b0]) == 0) break;
+            const float* sb = lbox[node - b0] + 6 * (slot ^ 1);
+            for (int k = 0; k < 3; ++k) { slo[k] = sb[k]; shi[k] = sb[3 + k]; }
+          } else if (kTwoPhase) {
+            // a cross node: its slot, listed, is finished by the last block
+            put_child_box(a, p2, a.wide ? a.slot4[p2] : -1, lo, hi);
+            a.entries[atomicAdd(&a.info[3], 1u)] = (uint32_t)p2;
+            break;
           } else {
-            d = a.slot4[p2];
+            put_child_box(a, p2, a.wide ? a.slot4[p2] : -1, lo, hi);
+            const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == 0) break;
+            a.cnt[node] = 0;
+            load_slot_coherent(&a.nodes[node], slot ^ 1, slo, shi);
+          }
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], slo[k]);
+            hi[k] = fmaxf(hi[k], shi[k]);
+          }
+          if (kTwoPhase) p2 = lpar[node - b0];   // local here
+          else p2 = local ? lpar[node - b0] : a.nodes[node].c.z;
+          if (p2 < 0) {
+            for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
+            break;
           }
         }
-        put_child_box(a, p2, d, lo, hi);
-        float slo[3], shi[3];
-        if (local) {
-          float* bx = lbox[node - b0] + 6 * slot;
-          for (int k = 0; k < 3; ++k) { bx[k] = lo[k]; bx[3 + k] = hi[k]; }
-          const uint32_t old = __hip_atomic_fetch_add(&lcnt[node - b0], 1u, __ATOMIC_ACQ_REL,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (old == 0) break;
-          const float* sb = lbox[node - b0] + 6 * (slot ^ 1);
-          for (int k = 0; k < 3; ++k) { slo[k] = sb[k]; shi[k] = sb[3 + k]; }
-        } else if (two_phase) {
-          a.entries[atomicAdd(&a.info[3], 1u)] = (uint32_t)p2;
-          break;
-        } else {
-          const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-          if (old == 0) break;
-          a.cnt[node] = 0;
-          load_slot_coherent(&a.nodes[node], slot ^ 1, slo, shi);
-        }
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = fminf(lo[k], slo[k]);
-          hi[k] = fmaxf(hi[k], shi[k]);
-        }
-        p2 = local ? lpar[node - b0] : a.nodes[node].c.z;
-        if (p2 < 0) {
-          for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
-          break;
-        }
-      }
+      };
+      if (two_phase) climb(std::true_type{});
+      else climb(std::false_type{});
     }
   }
   __syncthreads();
