@@ -176,6 +176,26 @@ inline void fresnel(const Material& m, double freq, double cos_t, cplx& g_te, cp
     g_tm = (eps_c * cos_t - root) / (eps_c * cos_t + root);
 }
 
+// Derivatives of the Fresnel coefficients above with respect to the complex
+// relative permittivity eps_c (both are analytic in eps_c).  With
+// r = sqrt(eps_c - sin^2) and c = cos(theta), dr/deps_c = 1 / (2 r):
+//   d Gamma_TE / d eps_c = -c / (r (c + r)^2),
+//   d Gamma_TM / d eps_c = 2 c (r - eps_c / (2 r)) / (eps_c c + r)^2.
+// A constant-gamma material does not depend on (eps_r, sigma): zero.
+inline void fresnel_deps(const Material& m, double freq, double cos_t, cplx& d_te, cplx& d_tm) {
+    if (!std::isnan(m.const_gamma)) {
+        d_te = d_tm = cplx(0.0, 0.0);
+        return;
+    }
+    cplx eps_c(m.eps_r, -m.sigma / (2.0 * kPi * freq * kEps0));
+    double sin2 = 1.0 - cos_t * cos_t;
+    cplx r = std::sqrt(eps_c - sin2);
+    cplx ctr = cos_t + r;
+    d_te = -cos_t / (r * ctr * ctr);
+    cplx den = eps_c * cos_t + r;
+    d_tm = 2.0 * cos_t * (r - eps_c / (2.0 * r)) / (den * den);
+}
+
 // Flags per traced segment.
 enum : int32_t {
     SEG_TIE = 1,    // another face is hit within the tie tolerance: the rest of the ray is uncertain
@@ -351,14 +371,19 @@ struct PathOut {
     double length = 0, tau = 0;
     V3 aod, aoa;
     std::vector<CV3> amp;   // one C^3 amplitude per frequency
+    // with n_grad materials requested: d amp / d eps_c of each material's
+    // faces, [freq][material] (zero for materials the path does not reflect on)
+    std::vector<CV3> damp;
 };
 
 // Image-method refinement of one candidate (tx, rx, faces[0..order)) and its
 // field.  Paper Sec. III, steps 3, 4 and 6.
 PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order, const double* freqs,
-                   int nfreq, double tx_power, double atten_db_per_km, double t_min, double eps_rel) {
+                   int nfreq, double tx_power, double atten_db_per_km, double t_min, double eps_rel,
+                   int n_grad = 0) {
     PathOut out;
     out.amp.assign(nfreq, CV3{});
+    out.damp.assign((size_t)nfreq * n_grad, CV3{});
     // image chain I_0 = T, I_j = mirror of I_{j-1} in the plane of face j
     std::vector<V3> img(order + 1);
     img[0] = T;
@@ -420,6 +445,8 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
     for (int fi = 0; fi < nfreq; ++fi) {
         const double f = freqs[fi];
         CV3 E{cplx(e0.x, 0), cplx(e0.y, 0), cplx(e0.z, 0)};
+        // forward-mode derivatives of E, one per material (its eps_c)
+        std::vector<CV3> dE(n_grad, CV3{});
         for (int j = 1; j <= order; ++j) {
             const Face& fc = sc.faces[faces[j - 1]];
             V3 ki = unit(pts[j] - pts[j - 1]);
@@ -439,6 +466,17 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
             V3 p_out = cross(sv, kr);
             cplx gte, gtm;
             fresnel(sc.mats[fc.material], f, cos_t, gte, gtm);
+            // E -> Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out; a derivative
+            // passes through the same map, and the reflection on a face of
+            // material m adds the map with the Gammas' derivatives applied to E
+            for (int m = 0; m < n_grad; ++m)
+                dE[m] = cadd(cscale(gte * cdot(dE[m], sv), sv), cscale(gtm * cdot(dE[m], p_in), p_out));
+            if (fc.material < n_grad) {
+                cplx dte, dtm;
+                fresnel_deps(sc.mats[fc.material], f, cos_t, dte, dtm);
+                dE[fc.material] = cadd(dE[fc.material],
+                                       cadd(cscale(dte * cdot(E, sv), sv), cscale(dtm * cdot(E, p_in), p_out)));
+            }
             E = cadd(cscale(gte * cdot(E, sv), sv), cscale(gtm * cdot(E, p_in), p_out));
         }
         const double lam = kC0 / f;
@@ -447,6 +485,7 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
                      std::pow(10.0, -atten_db_per_km * length / 1000.0 / 20.0);
         cplx ph = std::polar(mag, -k0 * length);
         out.amp[fi] = CV3{ph * E.x, ph * E.y, ph * E.z};
+        for (int m = 0; m < n_grad; ++m) out.damp[(size_t)fi * n_grad + m] = CV3{ph * dE[m].x, ph * dE[m].y, ph * dE[m].z};
     }
     return out;
 }
@@ -638,6 +677,31 @@ void oracle_refine(const void* scene, const float* tx, const float* rx, const in
             a[2] = e.y.real(); a[3] = e.y.imag();
             a[4] = e.z.real(); a[5] = e.z.imag();
         }
+    });
+}
+
+// Derivatives of every candidate's amplitude with respect to each material's
+// complex permittivity: damp [n][nfreq][n_mat][3][2] (re, im); zero for an
+// invalid candidate.  Same candidates and validity as oracle_refine.
+void oracle_refine_grad(const void* scene, const float* tx, const float* rx, const int32_t* keys, int64_t n,
+                        int32_t K, const double* freqs, int32_t nfreq, double tx_power, double atten_db_per_km,
+                        double t_min, double eps_rel, int32_t nthreads, double* damp) {
+    const Scene& sc = *static_cast<const Scene*>(scene);
+    const int nm = (int)sc.mats.size();
+    parallel_for(n, nthreads, [&](int64_t i, int) {
+        const int32_t* key = keys + i * (3 + K);
+        int t = key[0], c = key[1], order = key[2];
+        V3 T{tx[3 * t], tx[3 * t + 1], tx[3 * t + 2]};
+        V3 R{rx[3 * c], rx[3 * c + 1], rx[3 * c + 2]};
+        PathOut p = refine_one(sc, T, R, key + 3, order, freqs, nfreq, tx_power, atten_db_per_km, t_min, eps_rel, nm);
+        for (int f = 0; f < nfreq; ++f)
+            for (int m = 0; m < nm; ++m) {
+                double* a = damp + (((i * nfreq + f) * nm + m) * 3) * 2;
+                const CV3 e = p.valid ? p.damp[(size_t)f * nm + m] : CV3{};
+                a[0] = e.x.real(); a[1] = e.x.imag();
+                a[2] = e.y.real(); a[3] = e.y.imag();
+                a[4] = e.z.real(); a[5] = e.z.imag();
+            }
     });
 }
 

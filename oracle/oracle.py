@@ -20,6 +20,10 @@ Functions and the passages they follow:
                      Eq. (3) with n = 2 for the free-space magnitude)
   received_power     phase-coherent sum per receiver ("phase calculation")
   frame              all of the above for one frame
+  refine_grad,       derivatives of each receiver's coherent power along the
+  power_gradients    frame's paths with respect to every material's eps_r and
+                     sigma (the Fresnel coefficients of the field model,
+                     differentiated in closed form) and the transmit power
 """
 from __future__ import annotations
 
@@ -41,6 +45,7 @@ CAP_HIT, CAP_MARGINAL, CAP_UNCERTAIN = 1, 2, 4
 T_MIN = 1e-4          # metres; hits closer than this to a segment start are ignored
 EPS_TRACE = 4e-6      # relative position tolerance of an FP32 tracer (see flags)
 EPS_REFINE = 1e-9     # relative tolerance of an FP64 validation
+EPS0 = 8.8541878128e-12   # vacuum permittivity [F/m]
 
 
 def build(force: bool = False) -> str:
@@ -76,6 +81,7 @@ def _load():
         lib.oracle_refine.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32,
                                       P, P, P, P, P, P, P]
         lib.oracle_fresnel.argtypes = [F64, F64, F64, F64, F64, P]
+        lib.oracle_refine_grad.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32, P]
         _lib = lib
     return _lib
 
@@ -252,6 +258,48 @@ def refine(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w
                           _ptr(length), _ptr(tau), _ptr(aod), _ptr(aoa), _ptr(amp))
     return Paths(keys, valid.astype(bool), marginal.astype(bool), length, tau, aod, aoa,
                  amp[..., 0] + 1j * amp[..., 1])
+
+
+def refine_grad(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w: float, n_mat: int,
+                atten_db_per_km: float = 0.0, t_min: float = T_MIN, eps_rel: float = EPS_REFINE,
+                nthreads: Optional[int] = None) -> np.ndarray:
+    """d amp / d eps_c of each material, c128 [n, nfreq, n_mat, 3] (zero for an
+    invalid candidate): the same candidates and validity as refine()."""
+    lib = _load()
+    tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
+    rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
+    keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3 + K)
+    freqs = np.ascontiguousarray(freqs, dtype=np.float64).reshape(-1)
+    n, nf = keys.shape[0], freqs.shape[0]
+    damp = np.zeros((n, nf, n_mat, 3, 2))
+    if n:
+        lib.oracle_refine_grad(osc.handle, _ptr(tx), _ptr(rx), _ptr(keys), n, K, _ptr(freqs), nf,
+                               float(tx_power_w), float(atten_db_per_km), t_min, eps_rel,
+                               nthreads or default_threads(), _ptr(damp))
+    return damp[..., 0] + 1j * damp[..., 1]
+
+
+def power_gradients(paths: Paths, damp: np.ndarray, ntx: int, nrx: int, freqs, tx_power_w: float):
+    """Derivatives of the coherent power P = sum_c |A_c|^2, A = sum_p a_p, per
+    (freq, tx, rx): dP/d theta = 2 Re sum_c conj(A_c) dA_c/d theta.  With
+    eps_c = eps_r - j sigma / (2 pi f eps0): d/d eps_r = d/d eps_c and
+    d/d sigma = -j / (2 pi f eps0) d/d eps_c.  P is proportional to the transmit
+    power: dP/dP_t = P / P_t.  Returns (d_eps_r, d_sigma) [nfreq, ntx, nrx, n_mat]
+    and d_pt [nfreq, ntx, nrx]."""
+    freqs = np.asarray(freqs, dtype=np.float64).reshape(-1)
+    nf, n_mat = len(freqs), damp.shape[2]
+    acc = np.zeros((nf, ntx, nrx, 3), dtype=np.complex128)
+    dacc = np.zeros((nf, ntx, nrx, n_mat, 3), dtype=np.complex128)
+    for i in range(len(paths.keys)):
+        if paths.valid[i]:
+            t, r = int(paths.keys[i, 0]), int(paths.keys[i, 1])
+            acc[:, t, r] += paths.amp[i]
+            dacc[:, t, r] += damp[i]
+    g = 2.0 * np.real(np.sum(np.conj(acc)[:, :, :, None, :] * dacc, axis=-1))
+    dsig_fac = -1j / (2.0 * np.pi * freqs * EPS0)
+    g_sig = 2.0 * np.real(np.sum(np.conj(acc)[:, :, :, None, :] * dacc * dsig_fac[:, None, None, None, None], axis=-1))
+    p_coh = np.sum(np.abs(acc) ** 2, axis=-1)
+    return g, g_sig, p_coh / tx_power_w
 
 
 def received_power(paths: Paths, ntx: int, nrx: int, nfreq: int):

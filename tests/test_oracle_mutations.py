@@ -36,12 +36,21 @@ MUTATIONS = {
     "no_side_check": ("if (!(s > 0.0 && s < 1.0)) return out;", ""),
     "xform_order": ("r = r + (double)row[3];", "r = r - (double)row[3];"),
     "tie_flag_dropped": ("flags |= SEG_TIE;", "(void)0;"),
+    # the power gradients (caught by the gradient pins)
+    "dgamma_tm_sign": ("d_tm = 2.0 * cos_t * (r - eps_c / (2.0 * r))",
+                       "d_tm = 2.0 * cos_t * (r + eps_c / (2.0 * r))", "test_oracle_gradients.py"),
+    "dgamma_te_root": ("d_te = -cos_t / (r * ctr * ctr);", "d_te = -cos_t / (ctr * ctr);",
+                       "test_oracle_gradients.py"),
+    "derivative_not_propagated": (
+        "dE[m] = cadd(cscale(gte * cdot(dE[m], sv), sv), cscale(gtm * cdot(dE[m], p_in), p_out));",
+        "(void)m;", "test_oracle_gradients.py"),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_mutation(name, tmp_path):
-    old, new = MUTATIONS[name]
+    old, new = MUTATIONS[name][:2]
+    suite = MUTATIONS[name][2] if len(MUTATIONS[name]) > 2 else "test_oracle_pins.py"
     src = open(SRC).read()
     assert src.count(old) >= 1, "mutation anchor not found: %s" % name
     mutated = src.replace(old, new)
@@ -52,6 +61,6 @@ def test_pins_catch_mutation(name, tmp_path):
                            str(cpp), "-o", str(lib)])
     env = dict(os.environ, DCEM_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", suite)],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
