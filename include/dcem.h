@@ -231,6 +231,27 @@ dcem_status dcem_trace_frame(dcem_ctx* ctx, const dcem_trace_params* params);
  * the frame and reports any device error. */
 dcem_status dcem_received_power(dcem_ctx* ctx, double* p_coh, double* p_incoh, int32_t mem_kind);
 
+/* Derivatives of the last frame's coherent received power p_coh (see
+ * dcem_received_power) along its fixed set of valid paths: the path geometry
+ * is held, and the field of each path (Sec. III, Eq. (3) with the Fresnel
+ * reflection coefficients of its faces' materials, eps_c = eps_r -
+ * j sigma / (2 pi f eps0)) is differentiated exactly, the Fresnel coefficients
+ * in closed form with respect to eps_c:
+ *   dP/dtheta = 2 Re sum_c conj(A_c) dA_c/dtheta,  A = sum_p a_p.
+ * Outputs (host, caller-owned, each nullable):
+ *   d_eps_r, d_sigma  [n_freqs][n_tx][n_rx][n_materials]: dP/d eps_r and
+ *                     dP/d sigma of every material of the scene (zero for a
+ *                     constant-gamma material and for materials the paths do
+ *                     not reflect on), W per unit and W per S/m;
+ *   d_tx_power        [n_freqs][n_tx][n_rx]: dP/dP_t = P / P_t (P is
+ *                     proportional to the transmit power).
+ * Sums run over each receiver's paths in key order (bitwise reproducible).
+ * Waits for the frame; valid until the next dcem_trace_frame, also when the
+ * next frame's refit and revalidation have already been started.
+ * Errors: DCEM_E_STATE without a traced frame; device errors as for
+ * dcem_received_power. */
+dcem_status dcem_power_gradients(dcem_ctx* ctx, double* d_eps_r, double* d_sigma, double* d_tx_power);
+
 /* Paths of the last frame in key order (tx, rx, order, faces), host memory.
  * keys [cap][3 + K] int32 (faces padded with -1, K = max_reflections),
  * valid [cap], length [cap] (m), tau [cap] (s), aod/aoa [cap][3] unit vectors

@@ -386,7 +386,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->tri_slot, &c->face_slots, &c->face_ref_tri, &c->xf,
                     &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
                     &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
-                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
+                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->grad_buf, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
                     &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
                     &c->frame_block, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
                     &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
@@ -822,6 +822,36 @@ dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32
   }
   go_ahead(c);   // a refit requested before these powers were read: start the next frame
   HIP_TRY(hipGetLastError(), "revalidation");
+  return DCEM_OK;
+}
+
+dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, double* d_tx_power) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  dcem_status st = sync_frame(c);
+  if (st != DCEM_OK) return st;
+  const size_t n = (size_t)c->n_freqs * c->n_tx * c->n_rx;
+  if (d_tx_power) {
+    // P is proportional to the transmit power
+    const double* hp = reinterpret_cast<const double*>(static_cast<const char*>(c->host_block) + kBlockHead);
+    const double pt = c->sqrt_pt * c->sqrt_pt;
+    for (size_t i = 0; i < n; ++i) d_tx_power[i] = pt > 0 ? hp[i] / pt : 0.0;
+  }
+  const size_t ng = n * (size_t)std::max(c->nm, 0);
+  if ((d_eps_r || d_sigma) && ng > 0) {
+    HIP_TRY(ensure(c->grad_buf, 2 * sizeof(double) * ng), "alloc gradients");
+    double* g = ptr<double>(c->grad_buf);
+    // the frame's unique candidates (its path arrays stay until the next
+    // frame's trace, also when that frame has begun)
+    const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
+    launch_power_grad(c, nu, g, g + ng);
+    HIP_TRY(hipGetLastError(), "gradient kernel");
+    if (d_eps_r) HIP_TRY(hipMemcpyAsync(d_eps_r, g, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (d_sigma) HIP_TRY(hipMemcpyAsync(d_sigma, g + ng, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  }
   return DCEM_OK;
 }
 

@@ -160,6 +160,7 @@ struct dcem_ctx {
   // bits), then kRxCols + 1 int32 column starts; column of x:
   // clamp(floor((x - rx_col_x0) * rx_col_scale), 0, kRxCols - 1)
   dcem::DevBuf rx_cols;
+  dcem::DevBuf grad_buf;   // power gradients: [2][freq][pair][material]
   float rx_col_x0 = 0.0f, rx_col_scale = 0.0f;
   std::vector<double> freqs_host;
   int32_t n_rx_nodes = 0;
@@ -272,5 +273,6 @@ int64_t small_path_capacity();
 hipError_t ensure_paths(dcem_ctx* c, int64_t n);
 void launch_refine(dcem_ctx* c);
 void launch_reduce(dcem_ctx* c);
+void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig);
 
 }  // namespace dcem

@@ -434,6 +434,26 @@ __device__ inline void fresnel_coeffs(const double* mat, double freq, double cos
 
 __device__ inline double vol(D3 a, D3 b, D3 c, D3 d) { return dot(b - a, cross(c - a, d - a)); }
 
+// Derivatives of the Fresnel coefficients with respect to the complex
+// permittivity eps_c (both are analytic in it): with r = sqrt(eps_c - sin^2)
+// and c = cos(theta), dr/deps_c = 1 / (2 r), so
+//   dGamma_TE/deps_c = -c / (r (c + r)^2),
+//   dGamma_TM/deps_c = 2 c (r - eps_c / (2 r)) / (eps_c c + r)^2;
+// zero for a constant-gamma material.
+__device__ inline void fresnel_deps(const double* mat, double freq, double cos_t, Cx& dte, Cx& dtm) {
+  if (!isnan(mat[2])) {
+    dte = dtm = Cx{0.0, 0.0};
+    return;
+  }
+  const Cx ec = {mat[0], -mat[1] / (2.0 * kPi * freq * kEps0)};
+  const Cx r = csqrt_p({ec.re - (1.0 - cos_t * cos_t), ec.im});
+  const Cx ctr = cadd(Cx{cos_t, 0.0}, r);
+  dte = cdiv(Cx{-cos_t, 0.0}, cmul(r, cmul(ctr, ctr)));
+  const Cx den = cadd(cscl(cos_t, ec), r);
+  const Cx num = cscl(2.0 * cos_t, csub(r, cdiv(ec, cscl(2.0, r))));
+  dtm = cdiv(num, cmul(den, den));
+}
+
 struct RefineArgs {
   int K;                     // maximum reflection order (row length of faces)
   int n_rx;
@@ -816,6 +836,134 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair
   if (threadIdx.x == 0 && nvalid) atomicAdd(&counters[kCntValid], nvalid);
 }
 
+// Power gradients along the frame's paths, one wavefront per (tx, rx) pair:
+// the coherent field A = sum_p a_p per frequency (fixed butterfly), then for
+// each material m the derivative of every valid path's amplitude with respect
+// to m's eps_c, carried forward through its reflections (E -> Gamma_TE (E.s) s
+// + Gamma_TM (E.p_in) p_out, plus the map with the Gammas' derivatives at a
+// face of material m), and dP/dtheta = 2 Re sum_c conj(A_c) dA_c/dtheta with
+// d/deps_r = d/deps_c and d/dsigma = -j / (2 pi f eps0) d/deps_c.  Each
+// reflection's normal is taken from the path itself (along k_out - k_in), so
+// the pass reads only the frame's path arrays.  Out: [freq][pair][material].
+__global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ pair, const uint8_t* __restrict__ valid,
+                                                    const double* __restrict__ amp, const double* __restrict__ pts,
+                                                    const uint8_t* __restrict__ order, const int32_t* __restrict__ faces,
+                                                    const double* __restrict__ length, uint32_t n_unique, int K,
+                                                    int n_pairs, const double* __restrict__ freqs, int n_freqs,
+                                                    const int32_t* __restrict__ face_material,
+                                                    const double* __restrict__ materials, int n_mat, double sqrt_pt,
+                                                    double atten_db_per_km, double* __restrict__ g_eps,
+                                                    double* __restrict__ g_sig) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= n_pairs) return;   // uniform per wavefront
+  const int n = (int)n_unique;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pair[mid] < wave) lo = mid + 1; else hi = mid;
+  }
+  const int start = lo;
+  hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
+  }
+  const int end = lo;
+  auto butterfly = [](double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+  };
+  for (int fi = 0; fi < n_freqs; ++fi) {
+    const double f = freqs[fi];
+    double A[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = start + lane; u < end; u += 64) {
+      if (!valid[u]) continue;
+      const double* v = amp + ((size_t)u * n_freqs + fi) * 6;
+      for (int k = 0; k < 6; ++k) A[k] += v[k];
+    }
+    for (int k = 0; k < 6; ++k) A[k] = butterfly(A[k]);
+    const double lam = kC0 / f, k0 = 2.0 * kPi * f / kC0;
+    const Cx dsig = {0.0, -1.0 / (2.0 * kPi * f * kEps0)};
+    for (int m = 0; m < n_mat; ++m) {
+      double ge = 0.0, gs = 0.0;
+      for (int u = start + lane; u < end; u += 64) {
+        if (!valid[u]) continue;
+        const int ord = order[u];
+        bool uses = false;
+        for (int j = 0; j < ord; ++j) uses = uses || face_material[faces[(size_t)u * K + j]] == m;
+        if (!uses) continue;
+        const double* P = pts + (size_t)u * (K + 2) * 3;
+        auto pt = [&](int j) { return D3{P[3 * j], P[3 * j + 1], P[3 * j + 2]}; };
+        const D3 aod = normed(pt(1) - pt(0));
+        const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
+        const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+        Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
+        Cx dE[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int j = 1; j <= ord; ++j) {
+          const int mat = face_material[faces[(size_t)u * K + j - 1]];
+          const D3 ki = normed(pt(j) - pt(j - 1));
+          const D3 kr = normed(pt(j + 1) - pt(j));
+          const D3 dk = kr - ki;   // along the normal (zero only at grazing incidence)
+          const double dkl = len(dk);
+          const D3 nrm = dkl > 0.0 ? (1.0 / dkl) * dk : D3{0.0, 0.0, 1.0};
+          const double cos_t = fabs(dot(ki, nrm));
+          D3 sv = cross(ki, nrm);
+          const double sl = len(sv);
+          if (sl < 1e-12) {
+            const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
+            sv = normed(cross(ki, ax));
+          } else {
+            sv = (1.0 / sl) * sv;
+          }
+          const D3 pin = cross(sv, ki), pout = cross(sv, kr);
+          Cx te, tm;
+          fresnel_coeffs(materials + 3 * mat, f, cos_t, te, tm);
+          auto apply = [&](const Cx* X, Cx a, Cx b, Cx* Y) {   // Y = a (X.s) s + b (X.p_in) p_out
+            const Cx xs = cadd(cadd(cscl(sv.x, X[0]), cscl(sv.y, X[1])), cscl(sv.z, X[2]));
+            const Cx xp = cadd(cadd(cscl(pin.x, X[0]), cscl(pin.y, X[1])), cscl(pin.z, X[2]));
+            const Cx cs = cmul(a, xs), cp = cmul(b, xp);
+            Y[0] = cadd(cscl(sv.x, cs), cscl(pout.x, cp));
+            Y[1] = cadd(cscl(sv.y, cs), cscl(pout.y, cp));
+            Y[2] = cadd(cscl(sv.z, cs), cscl(pout.z, cp));
+          };
+          Cx nd[3], ne[3];
+          apply(dE, te, tm, nd);
+          if (mat == m) {
+            Cx dte, dtm, extra[3];
+            fresnel_deps(materials + 3 * mat, f, cos_t, dte, dtm);
+            apply(E, dte, dtm, extra);
+            for (int c = 0; c < 3; ++c) nd[c] = cadd(nd[c], extra[c]);
+          }
+          apply(E, te, tm, ne);
+          for (int c = 0; c < 3; ++c) {
+            dE[c] = nd[c];
+            E[c] = ne[c];
+          }
+        }
+        const double d = length[u];
+        const double mag = sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -atten_db_per_km * d / 20000.0);
+        double sn, cs;
+        sincos(k0 * d, &sn, &cs);
+        const Cx ph = {mag * cs, -mag * sn};
+        for (int c = 0; c < 3; ++c) {
+          const Cx da = cmul(ph, dE[c]);              // d a_c / d eps_c
+          const Cx ds = cmul(dsig, da);               // d a_c / d sigma
+          const Cx Ac = {A[2 * c], -A[2 * c + 1]};    // conj(A_c)
+          ge += 2.0 * cmul(Ac, da).re;
+          gs += 2.0 * cmul(Ac, ds).re;
+        }
+      }
+      ge = butterfly(ge);
+      gs = butterfly(gs);
+      if (lane == 0) {
+        g_eps[((size_t)fi * n_pairs + wave) * n_mat + m] = ge;
+        g_sig[((size_t)fi * n_pairs + wave) * n_mat + m] = gs;
+      }
+    }
+  }
+}
+
 int bits_for(int64_t n_values) {
   int b = 0;
   while (((int64_t)1 << b) < n_values) ++b;
@@ -960,6 +1108,16 @@ void launch_refine(dcem_ctx* c) {
   a.counters = c->cnt_dev;
   a.err = c->err_dev;
   hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 2)), 0, c->stream, a);
+}
+
+void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig) {
+  const int n_pairs = c->n_tx * c->n_rx;
+  hipLaunchKernelGGL(k_power_grad, dim3((n_pairs * 64 + 255) / 256), dim3(256), 0, c->stream,
+                     ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
+                     ptr<double>(c->path_pts), ptr<uint8_t>(c->path_order), ptr<int32_t>(c->path_faces),
+                     ptr<double>(c->path_len), n_unique, c->K, n_pairs, ptr<double>(c->freqs),
+                     c->n_freqs, ptr<int32_t>(c->face_material), ptr<double>(c->materials), c->nm, c->sqrt_pt,
+                     c->atten_db_per_km, g_eps, g_sig);
 }
 
 void launch_reduce(dcem_ctx* c) {

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("dcem_refit_bvh", _I32, [_P, _I32, _F64, ctypes.POINTER(_I32), ctypes.POINTER(_F64)]),
     ("dcem_trace_frame", _I32, [_P, ctypes.POINTER(TraceParams)]),
     ("dcem_received_power", _I32, [_P, _P, _P, _I32]),
+    ("dcem_power_gradients", _I32, [_P, _P, _P, _P]),
     ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("dcem_get_trace_log", _I32, [_P, _P, _P, _P]),
     ("dcem_get_captures", _I32, [_P, _I64, _P, ctypes.POINTER(_I64)]),
@@ -175,6 +176,7 @@ class Context:
         self.n_vertices = V.shape[0]
         self.n_tris = T.shape[0]
         self.n_objects = OR.shape[0]
+        self.n_materials = M.shape[0]
 
     def set_object_transforms(self, xf):
         a = xf if not isinstance(xf, np.ndarray) else _host(xf, np.float32)
@@ -220,6 +222,17 @@ class Context:
             pc, pi = out
         self._check(self.lib.dcem_received_power(self.handle, _addr(pc), _addr(pi), _kind(pc)))
         return pc, pi
+
+    def power_gradients(self):
+        """Derivatives of the last frame's coherent power along its paths:
+        (d_eps_r, d_sigma) [n_freqs, n_tx, n_rx, n_materials] and d_tx_power
+        [n_freqs, n_tx, n_rx], FP64 host arrays."""
+        shape = (self.n_freqs, self.n_tx, self.n_rx)
+        de = np.empty(shape + (self.n_materials,), np.float64)
+        ds = np.empty(shape + (self.n_materials,), np.float64)
+        dp = np.empty(shape, np.float64)
+        self._check(self.lib.dcem_power_gradients(self.handle, _addr(de), _addr(ds), _addr(dp)))
+        return de, ds, dp
 
     def stats(self) -> dict:
         s = FrameStats()

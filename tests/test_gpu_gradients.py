@@ -1,0 +1,105 @@
+"""GPU: derivatives of the coherent received power along a frame's paths
+(dcem_power_gradients) against the FP64 oracle's, through the C ABI.
+
+Workloads: the static toy scene (2 frequencies, an added constant-gamma
+material) with 20,000 random rays and K = 2, and the dynamic urban grid
+(K = 4, moving metal vehicles) with 65,536 random rays.  Receivers whose
+path sets are certain on both sides are compared; the rest are skipped as in
+the power parity tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2112_07115_amd import dcem, scenes
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.build()
+    return oracle
+
+
+@pytest.fixture()
+def ctx():
+    c = dcem.Context(0)
+    yield c
+    c.close()
+
+
+def oracle_gradients(O, s, frame, dirs):
+    ofr = O.frame(s, frame_index=frame, dirs=dirs)
+    xf = s.transforms(frame) if s.object_vertex_range.shape[0] else None
+    osc = O.OracleScene(s, xf)
+    damp = O.refine_grad(osc, s.tx, s.rx, ofr.keys, s.max_reflections, s.freqs_hz, s.tx_power_w,
+                         s.materials.shape[0])
+    return ofr, O.power_gradients(ofr.paths, damp, s.tx.shape[0], s.rx.shape[0], s.freqs_hz, s.tx_power_w)
+
+
+def compare(ctx, O, s, frame, dirs):
+    log("case", s.name, "frame", frame, "rays", len(dirs))
+    ctx.scene_upload(s)
+    dcem.trace_scene_frame(ctx, s, frame=frame, ray_dirs=dirs)
+    g_eps, g_sig, g_pt = ctx.power_gradients()
+    ofr, (o_eps, o_sig, o_pt) = oracle_gradients(O, s, frame, dirs)
+    comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
+    assert comparable.mean() >= 0.8
+    n_cmp = 0
+    for t in range(s.tx.shape[0]):
+        for r in range(s.rx.shape[0]):
+            if not comparable[t, r]:
+                continue
+            for g, o in ((g_eps, o_eps), (g_sig, o_sig)):
+                ref = np.abs(o[:, t, r]).max()
+                np.testing.assert_allclose(g[:, t, r], o[:, t, r], rtol=1e-6, atol=1e-6 * ref + 1e-300)
+            np.testing.assert_allclose(g_pt[:, t, r], o_pt[:, t, r], rtol=1e-6, atol=0)
+            n_cmp += 1
+    nz = int((np.abs(o_eps) > 0).sum())
+    log("  compared receivers", n_cmp, "nonzero oracle d/deps_r entries", nz)
+    assert n_cmp > 0 and nz > 0
+    return g_eps, g_sig, g_pt
+
+
+def test_toy_gradients(ctx, O):
+    s = scenes.static_toy()
+    mats = np.vstack([s.materials, [[3.0, 0.01, 0.8]]])
+    s = scenes.Scene(**{**s.__dict__, "materials": mats, "freqs_hz": [28e9, 3.5e9]})
+    g_eps, g_sig, _ = compare(ctx, O, s, 0, scenes.random_sphere_dirs(20_000, seed=3))
+    assert np.all(g_eps[..., 2] == 0) and np.all(g_sig[..., 2] == 0)   # constant gamma, on no face
+
+
+def test_urban_gradients(ctx, O):
+    s = scenes.dynamic_urban()
+    compare(ctx, O, s, 7, scenes.random_sphere_dirs(65_536, seed=11))
+
+
+def test_gradients_after_the_next_frame_started():
+    """Gradients read after the next frame's refit and revalidation were
+    started (objects moved before the read) equal those read before."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    c = dcem.Context(0)
+    c.scene_upload(s)
+    kw = dict(max_reflections=s.max_reflections, freqs_hz=s.freqs_hz, tx_power_w=s.tx_power_w)
+    for f in range(3):
+        c.set_object_transforms(s.transforms(f))
+        c.refit_bvh()
+        c.trace_frame(s.tx, s.rx, s.rx_radius, n, mode=dcem.MODE_COHERENT, **kw)
+        before = c.power_gradients()
+        c.received_power()
+        c.set_object_transforms(s.transforms(f + 1))
+        c.refit_bvh()   # starts the next frame early
+        after = c.power_gradients()
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b)
+    c.close()
