@@ -83,6 +83,29 @@ def run_mode(scene, mode, warmup, steps, n_rays, torch, instrumented):
     return dt, outs, stats
 
 
+def gradient_timing(scene, n_rays, calls=20):
+    """Mean wall time of dcem_power_gradients on one traced frame (the derivative
+    pass, its wait and the read-back of the results)."""
+    from paper_2112_07115_amd import dcem
+    ctx = dcem.Context(0)
+    ctx.scene_upload(scene)
+    ctx.set_object_transforms(scene.transforms(1))
+    ctx.refit_bvh()
+    ctx.trace_frame(scene.tx, scene.rx, scene.rx_radius, n_rays, max_reflections=scene.max_reflections,
+                    freqs_hz=scene.freqs_hz, tx_power_w=scene.tx_power_w)
+    ctx.received_power()
+    ctx.power_gradients()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ctx.power_gradients()
+    dt = (time.perf_counter() - t0) / calls
+    st = ctx.stats()
+    ctx.close()
+    return {"ms_per_call": dt * 1e3, "calls": calls, "valid_paths": st["valid_paths"],
+            "outputs": "dP/d eps_r and dP/d sigma of %d materials and dP/dP_t for %d receivers, frame 1"
+                       % (scene.materials.shape[0], scene.rx.shape[0])}
+
+
 def cpu_baseline(scene, frame_index, stride):
     from oracle import oracle
     dirs = oracle.fibonacci(scene.n_rays)[::stride].copy()
@@ -232,6 +255,7 @@ def main():
     out["roofline"] = roofline(stats, "coherent" if main_mode == "coherent" else "full")
     if "full" in res and main_mode != "full":
         out["roofline_full_trace"] = roofline(res["full"][2], "full")
+    out["power_gradients"] = gradient_timing(scene, n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, 1, 16)
     print(json.dumps(out))
