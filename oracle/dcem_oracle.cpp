@@ -376,11 +376,33 @@ struct PathOut {
     std::vector<CV3> damp;
 };
 
+// Transmit field pattern, an extension of the paper's ideal omnidirectional
+// antenna: g(u) = sum_j w_j B_j(phi), phi the azimuth of the departure
+// direction u and B_j the periodic hat of half-width 2 pi / 16 centred on
+// azimuth 2 pi j / 16 (the hats sum to one, so w = 1 is the isotropic
+// antenna).  g scales the field, so the power scales with g^2.  No pattern
+// (w == nullptr): g = 1.
+constexpr int kPatternTaps = 16;
+
+double hat(int j, double phi) {
+    const double step = 2.0 * kPi / kPatternTaps;
+    const double d = std::fabs(std::remainder(phi - j * step, 2.0 * kPi));   // periodic distance
+    return std::max(0.0, 1.0 - d / step);
+}
+
+double pattern_gain(const double* w, V3 u) {
+    if (!w) return 1.0;
+    const double phi = std::atan2(u.y, u.x);
+    double g = 0.0;
+    for (int j = 0; j < kPatternTaps; ++j) g += w[j] * hat(j, phi);
+    return g;
+}
+
 // Image-method refinement of one candidate (tx, rx, faces[0..order)) and its
 // field.  Paper Sec. III, steps 3, 4 and 6.
 PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order, const double* freqs,
                    int nfreq, double tx_power, double atten_db_per_km, double t_min, double eps_rel,
-                   int n_grad = 0) {
+                   int n_grad = 0, const double* pattern = nullptr) {
     PathOut out;
     out.amp.assign(nfreq, CV3{});
     out.damp.assign((size_t)nfreq * n_grad, CV3{});
@@ -482,7 +504,7 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
         const double lam = kC0 / f;
         const double k0 = 2.0 * kPi * f / kC0;
         double mag = std::sqrt(tx_power) * lam / (4.0 * kPi * length) *
-                     std::pow(10.0, -atten_db_per_km * length / 1000.0 / 20.0);
+                     std::pow(10.0, -atten_db_per_km * length / 1000.0 / 20.0) * pattern_gain(pattern, out.aod);
         cplx ph = std::polar(mag, -k0 * length);
         out.amp[fi] = CV3{ph * E.x, ph * E.y, ph * E.z};
         for (int m = 0; m < n_grad; ++m) out.damp[(size_t)fi * n_grad + m] = CV3{ph * dE[m].x, ph * dE[m].y, ph * dE[m].z};
@@ -650,18 +672,20 @@ int64_t oracle_trace(const void* scene, const float* tx, int32_t ntx, const floa
 
 // Refine candidate paths keys [n][3 + K] = (tx, rx, order, faces... padded
 // -1).  Outputs per path: valid, marginal (validity within eps of flipping),
-// length, tau, aod[3], aoa[3], amp [n][nfreq][3][2] (re, im).
+// length, tau, aod[3], aoa[3], amp [n][nfreq][3][2] (re, im).  pattern:
+// the 16 transmit pattern weights, or null for the isotropic antenna.
 void oracle_refine(const void* scene, const float* tx, const float* rx, const int32_t* keys, int64_t n,
                    int32_t K, const double* freqs, int32_t nfreq, double tx_power, double atten_db_per_km,
                    double t_min, double eps_rel, int32_t nthreads, uint8_t* valid, uint8_t* marginal,
-                   double* length, double* tau, double* aod, double* aoa, double* amp) {
+                   double* length, double* tau, double* aod, double* aoa, double* amp, const double* pattern) {
     const Scene& sc = *static_cast<const Scene*>(scene);
     parallel_for(n, nthreads, [&](int64_t i, int) {
         const int32_t* key = keys + i * (3 + K);
         int t = key[0], c = key[1], order = key[2];
         V3 T{tx[3 * t], tx[3 * t + 1], tx[3 * t + 2]};
         V3 R{rx[3 * c], rx[3 * c + 1], rx[3 * c + 2]};
-        PathOut p = refine_one(sc, T, R, key + 3, order, freqs, nfreq, tx_power, atten_db_per_km, t_min, eps_rel);
+        PathOut p = refine_one(sc, T, R, key + 3, order, freqs, nfreq, tx_power, atten_db_per_km, t_min, eps_rel,
+                               0, pattern);
         valid[i] = p.valid;
         marginal[i] = p.marginal;
         length[i] = p.length;
@@ -685,7 +709,7 @@ void oracle_refine(const void* scene, const float* tx, const float* rx, const in
 // invalid candidate.  Same candidates and validity as oracle_refine.
 void oracle_refine_grad(const void* scene, const float* tx, const float* rx, const int32_t* keys, int64_t n,
                         int32_t K, const double* freqs, int32_t nfreq, double tx_power, double atten_db_per_km,
-                        double t_min, double eps_rel, int32_t nthreads, double* damp) {
+                        double t_min, double eps_rel, int32_t nthreads, double* damp, const double* pattern) {
     const Scene& sc = *static_cast<const Scene*>(scene);
     const int nm = (int)sc.mats.size();
     parallel_for(n, nthreads, [&](int64_t i, int) {
@@ -693,7 +717,8 @@ void oracle_refine_grad(const void* scene, const float* tx, const float* rx, con
         int t = key[0], c = key[1], order = key[2];
         V3 T{tx[3 * t], tx[3 * t + 1], tx[3 * t + 2]};
         V3 R{rx[3 * c], rx[3 * c + 1], rx[3 * c + 2]};
-        PathOut p = refine_one(sc, T, R, key + 3, order, freqs, nfreq, tx_power, atten_db_per_km, t_min, eps_rel, nm);
+        PathOut p = refine_one(sc, T, R, key + 3, order, freqs, nfreq, tx_power, atten_db_per_km, t_min, eps_rel, nm,
+                               pattern);
         for (int f = 0; f < nfreq; ++f)
             for (int m = 0; m < nm; ++m) {
                 double* a = damp + (((i * nfreq + f) * nm + m) * 3) * 2;
@@ -703,6 +728,11 @@ void oracle_refine_grad(const void* scene, const float* tx, const float* rx, con
                 a[4] = e.z.real(); a[5] = e.z.imag();
             }
     });
+}
+
+// Transmit pattern gain of a departure direction (for unit pins).
+double oracle_pattern_gain(const double* w, double ux, double uy, double uz) {
+    return pattern_gain(w, V3{ux, uy, uz});
 }
 
 // Fresnel coefficients (for unit pins): out = (re TE, im TE, re TM, im TM).

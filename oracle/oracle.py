@@ -24,6 +24,9 @@ Functions and the passages they follow:
   power_gradients    frame's paths with respect to every material's eps_r and
                      sigma (the Fresnel coefficients of the field model,
                      differentiated in closed form) and the transmit power
+  pattern_gain,      the transmit field pattern (an extension of the paper's
+  pattern_gradients  isotropic antenna: 16 periodic azimuth hats, weights 1 =
+                     isotropic) and dP/dw of its weights along the paths
 """
 from __future__ import annotations
 
@@ -46,6 +49,7 @@ T_MIN = 1e-4          # metres; hits closer than this to a segment start are ign
 EPS_TRACE = 4e-6      # relative position tolerance of an FP32 tracer (see flags)
 EPS_REFINE = 1e-9     # relative tolerance of an FP64 validation
 EPS0 = 8.8541878128e-12   # vacuum permittivity [F/m]
+PATTERN_TAPS = 16         # azimuth hats of the transmit pattern
 
 
 def build(force: bool = False) -> str:
@@ -79,9 +83,11 @@ def _load():
         lib.oracle_trace.argtypes = [P, P, I32, P, I32, F64, P, P, I64, I32, F64, F64, I32,
                                      P, P, P, P, P, P, P, I64]
         lib.oracle_refine.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32,
-                                      P, P, P, P, P, P, P]
+                                      P, P, P, P, P, P, P, P]
         lib.oracle_fresnel.argtypes = [F64, F64, F64, F64, F64, P]
-        lib.oracle_refine_grad.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32, P]
+        lib.oracle_refine_grad.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32, P, P]
+        lib.oracle_pattern_gain.restype = F64
+        lib.oracle_pattern_gain.argtypes = [P, F64, F64, F64]
         _lib = lib
     return _lib
 
@@ -234,10 +240,37 @@ class Paths:
     amp: np.ndarray       # c128 [n, nfreq, 3]
 
 
+def _pattern(pattern) -> Optional[np.ndarray]:
+    if pattern is None:
+        return None
+    w = np.ascontiguousarray(pattern, dtype=np.float64).reshape(-1)
+    assert w.shape[0] == PATTERN_TAPS
+    return w
+
+
+def pattern_gain(pattern, u) -> float:
+    """Transmit field gain of departure direction u (1 without a pattern)."""
+    w = _pattern(pattern)
+    return _load().oracle_pattern_gain(_ptr(w), float(u[0]), float(u[1]), float(u[2]))
+
+
+def pattern_basis(aod: np.ndarray) -> np.ndarray:
+    """B_j(phi) of each departure direction, [n, 16]: periodic hats of
+    half-width 2 pi / 16 centred on azimuth 2 pi j / 16."""
+    phi = np.arctan2(aod[:, 1], aod[:, 0])
+    step = 2.0 * np.pi / PATTERN_TAPS
+    centres = step * np.arange(PATTERN_TAPS)
+    d = np.abs(np.remainder(phi[:, None] - centres[None, :] + np.pi, 2.0 * np.pi) - np.pi)
+    return np.maximum(0.0, 1.0 - d / step)
+
+
 def refine(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w: float,
            atten_db_per_km: float = 0.0, t_min: float = T_MIN, eps_rel: float = EPS_REFINE,
-           nthreads: Optional[int] = None) -> Paths:
+           nthreads: Optional[int] = None, pattern=None) -> Paths:
+    """Image-method refinement and field of each candidate; pattern: the 16
+    transmit pattern weights (None: the paper's isotropic antenna)."""
     lib = _load()
+    pattern = _pattern(pattern)
     tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
     rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
     keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3 + K)
@@ -255,17 +288,18 @@ def refine(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w
         lib.oracle_refine(osc.handle, _ptr(tx), _ptr(rx), _ptr(keys), n, K, _ptr(freqs), nf,
                           float(tx_power_w), float(atten_db_per_km), t_min, eps_rel,
                           nthreads or default_threads(), _ptr(valid), _ptr(marginal),
-                          _ptr(length), _ptr(tau), _ptr(aod), _ptr(aoa), _ptr(amp))
+                          _ptr(length), _ptr(tau), _ptr(aod), _ptr(aoa), _ptr(amp), _ptr(pattern))
     return Paths(keys, valid.astype(bool), marginal.astype(bool), length, tau, aod, aoa,
                  amp[..., 0] + 1j * amp[..., 1])
 
 
 def refine_grad(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_power_w: float, n_mat: int,
                 atten_db_per_km: float = 0.0, t_min: float = T_MIN, eps_rel: float = EPS_REFINE,
-                nthreads: Optional[int] = None) -> np.ndarray:
+                nthreads: Optional[int] = None, pattern=None) -> np.ndarray:
     """d amp / d eps_c of each material, c128 [n, nfreq, n_mat, 3] (zero for an
     invalid candidate): the same candidates and validity as refine()."""
     lib = _load()
+    pattern = _pattern(pattern)
     tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
     rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
     keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3 + K)
@@ -275,7 +309,7 @@ def refine_grad(osc: OracleScene, tx, rx, keys: np.ndarray, K: int, freqs, tx_po
     if n:
         lib.oracle_refine_grad(osc.handle, _ptr(tx), _ptr(rx), _ptr(keys), n, K, _ptr(freqs), nf,
                                float(tx_power_w), float(atten_db_per_km), t_min, eps_rel,
-                               nthreads or default_threads(), _ptr(damp))
+                               nthreads or default_threads(), _ptr(damp), _ptr(pattern))
     return damp[..., 0] + 1j * damp[..., 1]
 
 
@@ -300,6 +334,24 @@ def power_gradients(paths: Paths, damp: np.ndarray, ntx: int, nrx: int, freqs, t
     g_sig = 2.0 * np.real(np.sum(np.conj(acc)[:, :, :, None, :] * dacc * dsig_fac[:, None, None, None, None], axis=-1))
     p_coh = np.sum(np.abs(acc) ** 2, axis=-1)
     return g, g_sig, p_coh / tx_power_w
+
+
+def pattern_gradients(paths: Paths, paths_iso: Paths, ntx: int, nrx: int) -> np.ndarray:
+    """dP/dw_j of the coherent power, [nfreq, ntx, nrx, 16].  A path's field is
+    a_p = g(phi_p) a_p^iso with g = sum_j w_j B_j, so
+    dP/dw_j = 2 Re sum_c conj(A_c) sum_p B_j(phi_p) a_pc^iso.  paths: the
+    frame's paths under the pattern; paths_iso: the same candidates refined
+    without one."""
+    nf = paths.amp.shape[1]
+    acc = np.zeros((nf, ntx, nrx, 3), dtype=np.complex128)
+    dacc = np.zeros((nf, ntx, nrx, PATTERN_TAPS, 3), dtype=np.complex128)
+    basis = pattern_basis(paths.aod)
+    for i in range(len(paths.keys)):
+        if paths.valid[i]:
+            t, r = int(paths.keys[i, 0]), int(paths.keys[i, 1])
+            acc[:, t, r] += paths.amp[i]
+            dacc[:, t, r] += basis[i][None, :, None] * paths_iso.amp[i][:, None, :]
+    return 2.0 * np.real(np.sum(np.conj(acc)[:, :, :, None, :] * dacc, axis=-1))
 
 
 def received_power(paths: Paths, ntx: int, nrx: int, nfreq: int):
@@ -334,7 +386,7 @@ class FrameResult:
 
 def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Optional[int] = None,
           freqs=None, tx_power_w: Optional[float] = None, atten_db_per_km: float = 0.0,
-          los_always: bool = True, nthreads: Optional[int] = None) -> FrameResult:
+          los_always: bool = True, nthreads: Optional[int] = None, pattern=None) -> FrameResult:
     """One frame, from scratch: the oracle keeps nothing between frames."""
     K = scene.max_reflections if K is None else K
     freqs = scene.freqs_hz if freqs is None else freqs
@@ -347,7 +399,7 @@ def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Opt
     ntx, nrx = scene.tx.shape[0], scene.rx.shape[0]
     keys, certain, possible = candidates(tr, ntx, nrx, K, los_always)
     paths = refine(osc, scene.tx, scene.rx, keys, K, freqs, tx_power_w, atten_db_per_km,
-                   nthreads=nthreads)
+                   nthreads=nthreads, pattern=pattern)
     p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))
     return FrameResult(tr, keys, certain, possible, paths, p_coh, p_inc)
 

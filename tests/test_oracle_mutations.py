@@ -44,6 +44,14 @@ MUTATIONS = {
     "derivative_not_propagated": (
         "dE[m] = cadd(cscale(gte * cdot(dE[m], sv), sv), cscale(gtm * cdot(dE[m], p_in), p_out));",
         "(void)m;", "test_oracle_gradients.py"),
+    # the transmit pattern (caught by the pattern pins)
+    "pattern_half_width": ("return std::max(0.0, 1.0 - d / step);",
+                           "return std::max(0.0, 1.0 - 2.0 * d / step);", "test_oracle_pattern.py"),
+    "pattern_azimuth_axes": ("const double phi = std::atan2(u.y, u.x);",
+                             "const double phi = std::atan2(u.x, u.y);", "test_oracle_pattern.py"),
+    "pattern_on_power": ("* pattern_gain(pattern, out.aod);",
+                         "* pattern_gain(pattern, out.aod) * pattern_gain(pattern, out.aod);",
+                         "test_oracle_pattern.py"),
 }
 
 
