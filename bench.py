@@ -102,7 +102,8 @@ def gradient_timing(scene, n_rays, calls=20):
     st = ctx.stats()
     ctx.close()
     return {"ms_per_call": dt * 1e3, "calls": calls, "valid_paths": st["valid_paths"],
-            "outputs": "dP/d eps_r and dP/d sigma of %d materials and dP/dP_t for %d receivers, frame 1"
+            "outputs": "dP/d eps_r and dP/d sigma of %d materials, dP/dP_t and dP/dw of the 16 transmit "
+                       "pattern weights for %d receivers, frame 1"
                        % (scene.materials.shape[0], scene.rx.shape[0])}
 
 

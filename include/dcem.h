@@ -68,6 +68,7 @@ typedef int32_t dcem_status;
 #define DCEM_FORCE_REBUILD 1  /* dcem_refit_bvh flag: rebuild instead of refitting */
 
 #define DCEM_MAX_REFLECTIONS 10  /* paper, Sec. III: at most 10 reflections */
+#define DCEM_PATTERN_TAPS 16     /* weights of the transmit pattern (dcem_set_tx_pattern) */
 
 /* bits of the device error word (reported as DCEM_E_CAPACITY / DCEM_E_INVALID_ARG) */
 #define DCEM_ERR_STACK 1u      /* traversal stack overflow */
@@ -231,6 +232,18 @@ dcem_status dcem_trace_frame(dcem_ctx* ctx, const dcem_trace_params* params);
  * the frame and reports any device error. */
 dcem_status dcem_received_power(dcem_ctx* ctx, double* p_coh, double* p_incoh, int32_t mem_kind);
 
+/* Transmit field pattern, an extension of the paper's ideal omnidirectional
+ * antenna (Sec. III takes the transmitter as isotropic): each path's field is
+ * scaled by g(phi) = sum_j w_j B_j(phi), phi the azimuth (atan2(y, x)) of its
+ * departure direction and B_j the periodic hat of half-width 2 pi / 16
+ * centred on azimuth 2 pi j / 16.  The hats sum to one, so all weights 1 is
+ * the isotropic antenna; the power scales with g^2.
+ * weights: host, DCEM_PATTERN_TAPS finite values (any sign), copied; null with
+ * n_weights = 0 restores the isotropic antenna (the default).  Applies to the
+ * frames traced after the call, for every transmitter; scene uploads keep it.
+ * Errors: DCEM_E_INVALID_ARG for another count or a non-finite weight. */
+dcem_status dcem_set_tx_pattern(dcem_ctx* ctx, const double* weights, int32_t n_weights);
+
 /* Derivatives of the last frame's coherent received power p_coh (see
  * dcem_received_power) along its fixed set of valid paths: the path geometry
  * is held, and the field of each path (Sec. III, Eq. (3) with the Fresnel
@@ -244,13 +257,20 @@ dcem_status dcem_received_power(dcem_ctx* ctx, double* p_coh, double* p_incoh, i
  *                     constant-gamma material and for materials the paths do
  *                     not reflect on), W per unit and W per S/m;
  *   d_tx_power        [n_freqs][n_tx][n_rx]: dP/dP_t = P / P_t (P is
- *                     proportional to the transmit power).
+ *                     proportional to the transmit power);
+ *   d_pattern         [n_freqs][n_tx][n_rx][DCEM_PATTERN_TAPS]: dP/dw_j of
+ *                     the transmit pattern weights (dcem_set_tx_pattern) at
+ *                     the weights the frame was traced with, also for the
+ *                     isotropic antenna (w = 1): each path's field is
+ *                     g(phi_p) a_p^iso, so dA/dw_j = sum_p B_j(phi_p) a_p^iso.
+ * The material derivatives include the pattern's gain.
  * Sums run over each receiver's paths in key order (bitwise reproducible).
  * Waits for the frame; valid until the next dcem_trace_frame, also when the
  * next frame's refit and revalidation have already been started.
  * Errors: DCEM_E_STATE without a traced frame; device errors as for
  * dcem_received_power. */
-dcem_status dcem_power_gradients(dcem_ctx* ctx, double* d_eps_r, double* d_sigma, double* d_tx_power);
+dcem_status dcem_power_gradients(dcem_ctx* ctx, double* d_eps_r, double* d_sigma, double* d_tx_power,
+                                 double* d_pattern);
 
 /* Paths of the last frame in key order (tx, rx, order, faces), host memory.
  * keys [cap][3 + K] int32 (faces padded with -1, K = max_reflections),

@@ -693,6 +693,7 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   c->n_freqs = p->n_freqs;
   c->sqrt_pt = std::sqrt(p->tx_power_w);
   c->atten_db_per_km = p->atten_db_per_km;
+  c->pattern_frame = c->pattern_next;
   c->record_log = p->record_trace_log != 0;
   if (need_dirs) {   // transmitters, receivers or rays changed
     HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
@@ -825,7 +826,26 @@ dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32
   return DCEM_OK;
 }
 
-dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, double* d_tx_power) {
+dcem_status dcem_set_tx_pattern(dcem_ctx* c, const double* weights, int32_t n_weights) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!weights) {
+    if (n_weights != 0) return fail(c, DCEM_E_INVALID_ARG, "null weights need n_weights = 0");
+    c->pattern_next = TxPattern{};
+    return DCEM_OK;
+  }
+  if (n_weights != kPatternTaps) return fail(c, DCEM_E_INVALID_ARG, "need %d pattern weights", kPatternTaps);
+  for (int j = 0; j < kPatternTaps; ++j)
+    if (!std::isfinite(weights[j])) return fail(c, DCEM_E_INVALID_ARG, "non-finite pattern weight");
+  TxPattern p{};
+  for (int j = 0; j < kPatternTaps; ++j) p.w[j] = weights[j];
+  p.on = 1;
+  c->pattern_next = p;
+  return DCEM_OK;
+}
+
+dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, double* d_tx_power,
+                                 double* d_pattern) {
   if (!c) return DCEM_E_INVALID_ARG;
   c->err.clear();
   if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
@@ -840,16 +860,20 @@ dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, 
     for (size_t i = 0; i < n; ++i) d_tx_power[i] = pt > 0 ? hp[i] / pt : 0.0;
   }
   const size_t ng = n * (size_t)std::max(c->nm, 0);
-  if ((d_eps_r || d_sigma) && ng > 0) {
-    HIP_TRY(ensure(c->grad_buf, 2 * sizeof(double) * ng), "alloc gradients");
+  const size_t np = n * kPatternTaps;
+  const bool want_mat = (d_eps_r || d_sigma) && ng > 0;
+  if (want_mat || d_pattern) {
+    HIP_TRY(ensure(c->grad_buf, sizeof(double) * (2 * ng + np)), "alloc gradients");
     double* g = ptr<double>(c->grad_buf);
     // the frame's unique candidates (its path arrays stay until the next
     // frame's trace, also when that frame has begun)
     const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
-    launch_power_grad(c, nu, g, g + ng);
+    launch_power_grad(c, nu, want_mat ? g : nullptr, g + ng, d_pattern ? g + 2 * ng : nullptr);
     HIP_TRY(hipGetLastError(), "gradient kernel");
     if (d_eps_r) HIP_TRY(hipMemcpyAsync(d_eps_r, g, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
     if (d_sigma) HIP_TRY(hipMemcpyAsync(d_sigma, g + ng, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (d_pattern)
+      HIP_TRY(hipMemcpyAsync(d_pattern, g + 2 * ng, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   }
   return DCEM_OK;

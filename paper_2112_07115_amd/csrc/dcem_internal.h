@@ -81,6 +81,16 @@ struct Capture {
 
 // Frame-invariant description of the current trace configuration, used to
 // decide whether the coherence cache still applies.
+// Transmit field pattern: gain sum_j w[j] B_j(azimuth of the departure
+// direction), B_j the periodic hat of half-width 2 pi / 16 centred on azimuth
+// 2 pi j / 16.  on == 0: the isotropic antenna (gain 1).  Passed to kernels by
+// value, so a launch keeps the weights it was given.
+constexpr int kPatternTaps = 16;
+struct TxPattern {
+  double w[kPatternTaps];
+  int on;
+};
+
 struct TraceConfig {
   int32_t n_tx = 0, n_rx = 0, K = -1;
   int64_t n_rays = 0;
@@ -160,7 +170,7 @@ struct dcem_ctx {
   // bits), then kRxCols + 1 int32 column starts; column of x:
   // clamp(floor((x - rx_col_x0) * rx_col_scale), 0, kRxCols - 1)
   dcem::DevBuf rx_cols;
-  dcem::DevBuf grad_buf;   // power gradients: [2][freq][pair][material]
+  dcem::DevBuf grad_buf;   // power gradients: [2][freq][pair][material], then [freq][pair][16]
   float rx_col_x0 = 0.0f, rx_col_scale = 0.0f;
   std::vector<double> freqs_host;
   int32_t n_rx_nodes = 0;
@@ -202,6 +212,9 @@ struct dcem_ctx {
   dcem::DevBuf sort_hist;
   int64_t n_caps_host = 0;
   double sqrt_pt = 0.0, atten_db_per_km = 0.0;
+  // transmit pattern: the weights of the next traced frame, and those the
+  // last traced frame used (its paths' fields, and its gradients)
+  dcem::TxPattern pattern_next{}, pattern_frame{};
   bool bvh_stale = false;     // transforms changed since the last refit
   bool has_frame = false;
   int32_t record_log = 0;
@@ -273,6 +286,6 @@ int64_t small_path_capacity();
 hipError_t ensure_paths(dcem_ctx* c, int64_t n);
 void launch_refine(dcem_ctx* c);
 void launch_reduce(dcem_ctx* c);
-void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig);
+void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig, double* g_pat);
 
 }  // namespace dcem

@@ -454,6 +454,28 @@ __device__ inline void fresnel_deps(const double* mat, double freq, double cos_t
   dtm = cdiv(num, cmul(den, den));
 }
 
+// Azimuth cell of a departure direction u: the pattern taps j and j + 1
+// (mod 16) around its azimuth and the fraction t in [0, 1) of the way to j + 1,
+// so B_j = 1 - t, B_{j+1} = t and every other hat is zero there.
+__device__ inline void pattern_cell(D3 u, int& j, double& t) {
+  double x = atan2(u.y, u.x) * (kPatternTaps / (2.0 * kPi));   // [-8, 8]
+  if (x < 0.0) x += kPatternTaps;
+  const double fl = floor(x);
+  t = x - fl;
+  j = (int)fl & (kPatternTaps - 1);   // x = 16 after the wrap is tap 0
+}
+
+// Gain of the pattern at u, as w_j + t (w_{j+1} - w_j): exactly 1 when all
+// weights are 1.
+__device__ inline double pattern_gain(const TxPattern& p, D3 u) {
+  if (!p.on) return 1.0;
+  int j;
+  double t;
+  pattern_cell(u, j, t);
+  const double w0 = p.w[j], w1 = p.w[(j + 1) & (kPatternTaps - 1)];
+  return w0 + t * (w1 - w0);
+}
+
 struct RefineArgs {
   int K;                     // maximum reflection order (row length of faces)
   int n_rx;
@@ -473,6 +495,7 @@ struct RefineArgs {
   int n_freqs;
   double sqrt_pt;
   double atten_db_per_km;
+  TxPattern pat;
   int64_t n_rays;
   uint8_t* valid;
   double* length;
@@ -714,6 +737,7 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
     const D3 aod = normed(pt(1) - pt(0));
     const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
     const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+    const double gain = pattern_gain(a.pat, aod);
     for (int fi = lane; fi < a.n_freqs; fi += kWave) {
       const double f = a.freqs[fi];
       double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
@@ -744,7 +768,7 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       }
       const double lam = kC0 / f;
       const double k0 = 2.0 * kPi * f / kC0;
-      const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0);
+      const double mag = a.sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -a.atten_db_per_km * d / 20000.0) * gain;
       double sn, cs;
       sincos(k0 * d, &sn, &cs);
       const Cx ph = {mag * cs, -mag * sn};
@@ -844,7 +868,10 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair
 // face of material m), and dP/dtheta = 2 Re sum_c conj(A_c) dA_c/dtheta with
 // d/deps_r = d/deps_c and d/dsigma = -j / (2 pi f eps0) d/deps_c.  Each
 // reflection's normal is taken from the path itself (along k_out - k_in), so
-// the pass reads only the frame's path arrays.  Out: [freq][pair][material].
+// the pass reads only the frame's path arrays.  Out: [freq][pair][material]
+// (g_eps null: skipped).  With the transmit pattern, a_p = g(phi_p) a_p^iso:
+// the material derivatives carry the gain, and g_pat (nullable) receives
+// dP/dw_j = 2 Re sum_c conj(A_c) sum_p B_j(phi_p) a_pc^iso, [freq][pair][16].
 __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ pair, const uint8_t* __restrict__ valid,
                                                     const double* __restrict__ amp, const double* __restrict__ pts,
                                                     const uint8_t* __restrict__ order, const int32_t* __restrict__ faces,
@@ -852,8 +879,8 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
                                                     int n_pairs, const double* __restrict__ freqs, int n_freqs,
                                                     const int32_t* __restrict__ face_material,
                                                     const double* __restrict__ materials, int n_mat, double sqrt_pt,
-                                                    double atten_db_per_km, double* __restrict__ g_eps,
-                                                    double* __restrict__ g_sig) {
+                                                    double atten_db_per_km, TxPattern pat, double* __restrict__ g_eps,
+                                                    double* __restrict__ g_sig, double* __restrict__ g_pat) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= n_pairs) return;   // uniform per wavefront
@@ -874,6 +901,66 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
   };
+  auto departure = [&](int u) {
+    const double* P = pts + (size_t)u * (K + 2) * 3;
+    return normed(D3{P[3] - P[0], P[4] - P[1], P[5] - P[2]});
+  };
+  // Field of path u at frequency f through its reflection chain (unit
+  // magnitude and phase), and with m >= 0 its forward-mode derivative with
+  // respect to material m's eps_c.
+  auto walk = [&](int u, double f, int m, Cx* E, Cx* dE) {
+    const int ord = order[u];
+    const double* P = pts + (size_t)u * (K + 2) * 3;
+    auto pt = [&](int j) { return D3{P[3 * j], P[3 * j + 1], P[3 * j + 2]}; };
+    const D3 aod = normed(pt(1) - pt(0));
+    const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
+    const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
+    E[0] = {e0.x, 0};
+    E[1] = {e0.y, 0};
+    E[2] = {e0.z, 0};
+    for (int c = 0; c < 3; ++c) dE[c] = {0, 0};
+    for (int j = 1; j <= ord; ++j) {
+      const int mat = face_material[faces[(size_t)u * K + j - 1]];
+      const D3 ki = normed(pt(j) - pt(j - 1));
+      const D3 kr = normed(pt(j + 1) - pt(j));
+      const D3 dk = kr - ki;   // along the normal (zero only at grazing incidence)
+      const double dkl = len(dk);
+      const D3 nrm = dkl > 0.0 ? (1.0 / dkl) * dk : D3{0.0, 0.0, 1.0};
+      const double cos_t = fabs(dot(ki, nrm));
+      D3 sv = cross(ki, nrm);
+      const double sl = len(sv);
+      if (sl < 1e-12) {
+        const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
+        sv = normed(cross(ki, ax));
+      } else {
+        sv = (1.0 / sl) * sv;
+      }
+      const D3 pin = cross(sv, ki), pout = cross(sv, kr);
+      Cx te, tm;
+      fresnel_coeffs(materials + 3 * mat, f, cos_t, te, tm);
+      auto apply = [&](const Cx* X, Cx a, Cx b, Cx* Y) {   // Y = a (X.s) s + b (X.p_in) p_out
+        const Cx xs = cadd(cadd(cscl(sv.x, X[0]), cscl(sv.y, X[1])), cscl(sv.z, X[2]));
+        const Cx xp = cadd(cadd(cscl(pin.x, X[0]), cscl(pin.y, X[1])), cscl(pin.z, X[2]));
+        const Cx cs = cmul(a, xs), cp = cmul(b, xp);
+        Y[0] = cadd(cscl(sv.x, cs), cscl(pout.x, cp));
+        Y[1] = cadd(cscl(sv.y, cs), cscl(pout.y, cp));
+        Y[2] = cadd(cscl(sv.z, cs), cscl(pout.z, cp));
+      };
+      Cx nd[3], ne[3];
+      if (m >= 0) {
+        apply(dE, te, tm, nd);
+        if (mat == m) {
+          Cx dte, dtm, extra[3];
+          fresnel_deps(materials + 3 * mat, f, cos_t, dte, dtm);
+          apply(E, dte, dtm, extra);
+          for (int c = 0; c < 3; ++c) nd[c] = cadd(nd[c], extra[c]);
+        }
+        for (int c = 0; c < 3; ++c) dE[c] = nd[c];
+      }
+      apply(E, te, tm, ne);
+      for (int c = 0; c < 3; ++c) E[c] = ne[c];
+    }
+  };
   for (int fi = 0; fi < n_freqs; ++fi) {
     const double f = freqs[fi];
     double A[6] = {0, 0, 0, 0, 0, 0};
@@ -885,7 +972,15 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
     for (int k = 0; k < 6; ++k) A[k] = butterfly(A[k]);
     const double lam = kC0 / f, k0 = 2.0 * kPi * f / kC0;
     const Cx dsig = {0.0, -1.0 / (2.0 * kPi * f * kEps0)};
-    for (int m = 0; m < n_mat; ++m) {
+    // magnitude and phase of path u without the pattern's gain
+    auto phase = [&](int u) {
+      const double d = length[u];
+      const double mag = sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -atten_db_per_km * d / 20000.0);
+      double sn, cs;
+      sincos(k0 * d, &sn, &cs);
+      return Cx{mag * cs, -mag * sn};
+    };
+    for (int m = 0; m < n_mat && g_eps; ++m) {
       double ge = 0.0, gs = 0.0;
       for (int u = start + lane; u < end; u += 64) {
         if (!valid[u]) continue;
@@ -893,59 +988,9 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
         bool uses = false;
         for (int j = 0; j < ord; ++j) uses = uses || face_material[faces[(size_t)u * K + j]] == m;
         if (!uses) continue;
-        const double* P = pts + (size_t)u * (K + 2) * 3;
-        auto pt = [&](int j) { return D3{P[3 * j], P[3 * j + 1], P[3 * j + 2]}; };
-        const D3 aod = normed(pt(1) - pt(0));
-        const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
-        const D3 e0 = rho > 0 ? D3{aod.z * aod.x / rho, aod.z * aod.y / rho, -rho} : D3{aod.z, 0.0, 0.0};
-        Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
-        Cx dE[3] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int j = 1; j <= ord; ++j) {
-          const int mat = face_material[faces[(size_t)u * K + j - 1]];
-          const D3 ki = normed(pt(j) - pt(j - 1));
-          const D3 kr = normed(pt(j + 1) - pt(j));
-          const D3 dk = kr - ki;   // along the normal (zero only at grazing incidence)
-          const double dkl = len(dk);
-          const D3 nrm = dkl > 0.0 ? (1.0 / dkl) * dk : D3{0.0, 0.0, 1.0};
-          const double cos_t = fabs(dot(ki, nrm));
-          D3 sv = cross(ki, nrm);
-          const double sl = len(sv);
-          if (sl < 1e-12) {
-            const D3 ax = fabs(ki.x) < 0.9 ? D3{1, 0, 0} : D3{0, 1, 0};
-            sv = normed(cross(ki, ax));
-          } else {
-            sv = (1.0 / sl) * sv;
-          }
-          const D3 pin = cross(sv, ki), pout = cross(sv, kr);
-          Cx te, tm;
-          fresnel_coeffs(materials + 3 * mat, f, cos_t, te, tm);
-          auto apply = [&](const Cx* X, Cx a, Cx b, Cx* Y) {   // Y = a (X.s) s + b (X.p_in) p_out
-            const Cx xs = cadd(cadd(cscl(sv.x, X[0]), cscl(sv.y, X[1])), cscl(sv.z, X[2]));
-            const Cx xp = cadd(cadd(cscl(pin.x, X[0]), cscl(pin.y, X[1])), cscl(pin.z, X[2]));
-            const Cx cs = cmul(a, xs), cp = cmul(b, xp);
-            Y[0] = cadd(cscl(sv.x, cs), cscl(pout.x, cp));
-            Y[1] = cadd(cscl(sv.y, cs), cscl(pout.y, cp));
-            Y[2] = cadd(cscl(sv.z, cs), cscl(pout.z, cp));
-          };
-          Cx nd[3], ne[3];
-          apply(dE, te, tm, nd);
-          if (mat == m) {
-            Cx dte, dtm, extra[3];
-            fresnel_deps(materials + 3 * mat, f, cos_t, dte, dtm);
-            apply(E, dte, dtm, extra);
-            for (int c = 0; c < 3; ++c) nd[c] = cadd(nd[c], extra[c]);
-          }
-          apply(E, te, tm, ne);
-          for (int c = 0; c < 3; ++c) {
-            dE[c] = nd[c];
-            E[c] = ne[c];
-          }
-        }
-        const double d = length[u];
-        const double mag = sqrt_pt * lam / (4.0 * kPi * d) * pow(10.0, -atten_db_per_km * d / 20000.0);
-        double sn, cs;
-        sincos(k0 * d, &sn, &cs);
-        const Cx ph = {mag * cs, -mag * sn};
+        Cx E[3], dE[3];
+        walk(u, f, m, E, dE);
+        const Cx ph = cscl(pattern_gain(pat, departure(u)), phase(u));
         for (int c = 0; c < 3; ++c) {
           const Cx da = cmul(ph, dE[c]);              // d a_c / d eps_c
           const Cx ds = cmul(dsig, da);               // d a_c / d sigma
@@ -960,6 +1005,31 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
         g_eps[((size_t)fi * n_pairs + wave) * n_mat + m] = ge;
         g_sig[((size_t)fi * n_pairs + wave) * n_mat + m] = gs;
       }
+    }
+    if (!g_pat) continue;
+    // a_p = g(phi_p) a_p^iso with g = sum_j w_j B_j: d a_p / d w_j = B_j(phi_p) a_p^iso,
+    // nonzero for the two taps around the path's departure azimuth
+    double acc[kPatternTaps];
+#pragma unroll
+    for (int q = 0; q < kPatternTaps; ++q) acc[q] = 0.0;
+    for (int u = start + lane; u < end; u += 64) {
+      if (!valid[u]) continue;
+      Cx E[3], dE[3];
+      walk(u, f, -1, E, dE);
+      const Cx ph = phase(u);
+      double sp = 0.0;   // 2 Re sum_c conj(A_c) a_pc^iso
+      for (int c = 0; c < 3; ++c) sp += 2.0 * cmul(Cx{A[2 * c], -A[2 * c + 1]}, cmul(ph, E[c])).re;
+      int j;
+      double t;
+      pattern_cell(departure(u), j, t);
+      const int j1 = (j + 1) & (kPatternTaps - 1);
+#pragma unroll
+      for (int q = 0; q < kPatternTaps; ++q) acc[q] += (q == j ? (1.0 - t) * sp : 0.0) + (q == j1 ? t * sp : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < kPatternTaps; ++q) {
+      const double v = butterfly(acc[q]);
+      if (lane == 0) g_pat[((size_t)fi * n_pairs + wave) * kPatternTaps + q] = v;
     }
   }
 }
@@ -1094,6 +1164,7 @@ void launch_refine(dcem_ctx* c) {
   a.n_freqs = c->n_freqs;
   a.sqrt_pt = c->sqrt_pt;
   a.atten_db_per_km = c->atten_db_per_km;
+  a.pat = c->pattern_frame;
   a.n_rays = c->n_rays;
   a.valid = ptr<uint8_t>(c->path_valid);
   a.length = ptr<double>(c->path_len);
@@ -1110,14 +1181,14 @@ void launch_refine(dcem_ctx* c) {
   hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 2)), 0, c->stream, a);
 }
 
-void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig) {
+void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig, double* g_pat) {
   const int n_pairs = c->n_tx * c->n_rx;
   hipLaunchKernelGGL(k_power_grad, dim3((n_pairs * 64 + 255) / 256), dim3(256), 0, c->stream,
                      ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
                      ptr<double>(c->path_pts), ptr<uint8_t>(c->path_order), ptr<int32_t>(c->path_faces),
                      ptr<double>(c->path_len), n_unique, c->K, n_pairs, ptr<double>(c->freqs),
                      c->n_freqs, ptr<int32_t>(c->face_material), ptr<double>(c->materials), c->nm, c->sqrt_pt,
-                     c->atten_db_per_km, g_eps, g_sig);
+                     c->atten_db_per_km, c->pattern_frame, g_eps, g_sig, g_pat);
 }
 
 void launch_reduce(dcem_ctx* c) {

@@ -24,6 +24,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 MODE_FULL, MODE_COHERENT = 0, 1
 FORCE_REBUILD = 1
 MAX_REFLECTIONS = 10
+PATTERN_TAPS = 16
 
 _P = ctypes.c_void_p
 _I32, _I64, _F32, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
@@ -66,7 +67,8 @@ SIGNATURES = [
     ("dcem_refit_bvh", _I32, [_P, _I32, _F64, ctypes.POINTER(_I32), ctypes.POINTER(_F64)]),
     ("dcem_trace_frame", _I32, [_P, ctypes.POINTER(TraceParams)]),
     ("dcem_received_power", _I32, [_P, _P, _P, _I32]),
-    ("dcem_power_gradients", _I32, [_P, _P, _P, _P]),
+    ("dcem_set_tx_pattern", _I32, [_P, _P, _I32]),
+    ("dcem_power_gradients", _I32, [_P, _P, _P, _P, _P]),
     ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("dcem_get_trace_log", _I32, [_P, _P, _P, _P]),
     ("dcem_get_captures", _I32, [_P, _I64, _P, ctypes.POINTER(_I64)]),
@@ -223,16 +225,27 @@ class Context:
         self._check(self.lib.dcem_received_power(self.handle, _addr(pc), _addr(pi), _kind(pc)))
         return pc, pi
 
+    def set_tx_pattern(self, weights=None):
+        """Transmit pattern weights (16 azimuth hats) for the next frames;
+        None restores the isotropic antenna."""
+        if weights is None:
+            self._check(self.lib.dcem_set_tx_pattern(self.handle, None, 0))
+            return
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        self._check(self.lib.dcem_set_tx_pattern(self.handle, _addr(w), int(w.shape[0])))
+
     def power_gradients(self):
         """Derivatives of the last frame's coherent power along its paths:
-        (d_eps_r, d_sigma) [n_freqs, n_tx, n_rx, n_materials] and d_tx_power
-        [n_freqs, n_tx, n_rx], FP64 host arrays."""
+        (d_eps_r, d_sigma) [n_freqs, n_tx, n_rx, n_materials], d_tx_power
+        [n_freqs, n_tx, n_rx] and d_pattern [n_freqs, n_tx, n_rx, 16], FP64
+        host arrays."""
         shape = (self.n_freqs, self.n_tx, self.n_rx)
         de = np.empty(shape + (self.n_materials,), np.float64)
         ds = np.empty(shape + (self.n_materials,), np.float64)
         dp = np.empty(shape, np.float64)
-        self._check(self.lib.dcem_power_gradients(self.handle, _addr(de), _addr(ds), _addr(dp)))
-        return de, ds, dp
+        dw = np.empty(shape + (PATTERN_TAPS,), np.float64)
+        self._check(self.lib.dcem_power_gradients(self.handle, _addr(de), _addr(ds), _addr(dp), _addr(dw)))
+        return de, ds, dp, dw
 
     def stats(self) -> dict:
         s = FrameStats()

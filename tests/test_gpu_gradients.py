@@ -1,11 +1,12 @@
 """GPU: derivatives of the coherent received power along a frame's paths
-(dcem_power_gradients) against the FP64 oracle's, through the C ABI.
+(dcem_power_gradients) against the FP64 oracle's, through the C ABI, and the
+transmit pattern (dcem_set_tx_pattern) in the forward power.
 
 Workloads: the static toy scene (2 frequencies, an added constant-gamma
 material) with 20,000 random rays and K = 2, and the dynamic urban grid
-(K = 4, moving metal vehicles) with 65,536 random rays.  Receivers whose
-path sets are certain on both sides are compared; the rest are skipped as in
-the power parity tests.
+(K = 4, moving metal vehicles) with 65,536 random rays, the latter under a
+random transmit pattern.  Receivers whose path sets are certain on both sides
+are compared; the rest are skipped as in the power parity tests.
 """
 import sys
 
@@ -37,21 +38,27 @@ def ctx():
     c.close()
 
 
-def oracle_gradients(O, s, frame, dirs):
-    ofr = O.frame(s, frame_index=frame, dirs=dirs)
+def oracle_gradients(O, s, frame, dirs, pattern=None):
+    ofr = O.frame(s, frame_index=frame, dirs=dirs, pattern=pattern)
     xf = s.transforms(frame) if s.object_vertex_range.shape[0] else None
     osc = O.OracleScene(s, xf)
+    ntx, nrx = s.tx.shape[0], s.rx.shape[0]
     damp = O.refine_grad(osc, s.tx, s.rx, ofr.keys, s.max_reflections, s.freqs_hz, s.tx_power_w,
-                         s.materials.shape[0])
-    return ofr, O.power_gradients(ofr.paths, damp, s.tx.shape[0], s.rx.shape[0], s.freqs_hz, s.tx_power_w)
+                         s.materials.shape[0], pattern=pattern)
+    iso = ofr.paths if pattern is None else O.refine(osc, s.tx, s.rx, ofr.keys, s.max_reflections,
+                                                     s.freqs_hz, s.tx_power_w)
+    g = O.power_gradients(ofr.paths, damp, ntx, nrx, s.freqs_hz, s.tx_power_w)
+    return ofr, g + (O.pattern_gradients(ofr.paths, iso, ntx, nrx),)
 
 
-def compare(ctx, O, s, frame, dirs):
-    log("case", s.name, "frame", frame, "rays", len(dirs))
+def compare(ctx, O, s, frame, dirs, pattern=None):
+    log("case", s.name, "frame", frame, "rays", len(dirs), "pattern", pattern is not None)
     ctx.scene_upload(s)
+    ctx.set_tx_pattern(pattern)
     dcem.trace_scene_frame(ctx, s, frame=frame, ray_dirs=dirs)
-    g_eps, g_sig, g_pt = ctx.power_gradients()
-    ofr, (o_eps, o_sig, o_pt) = oracle_gradients(O, s, frame, dirs)
+    p_coh, _ = ctx.received_power()
+    g_eps, g_sig, g_pt, g_pat = ctx.power_gradients()
+    ofr, (o_eps, o_sig, o_pt, o_pat) = oracle_gradients(O, s, frame, dirs, pattern)
     comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
     assert comparable.mean() >= 0.8
     n_cmp = 0
@@ -59,14 +66,16 @@ def compare(ctx, O, s, frame, dirs):
         for r in range(s.rx.shape[0]):
             if not comparable[t, r]:
                 continue
-            for g, o in ((g_eps, o_eps), (g_sig, o_sig)):
+            np.testing.assert_allclose(p_coh[:, t, r], ofr.p_coh[:, t, r], rtol=1e-6, atol=0)
+            for g, o in ((g_eps, o_eps), (g_sig, o_sig), (g_pat, o_pat)):
                 ref = np.abs(o[:, t, r]).max()
                 np.testing.assert_allclose(g[:, t, r], o[:, t, r], rtol=1e-6, atol=1e-6 * ref + 1e-300)
             np.testing.assert_allclose(g_pt[:, t, r], o_pt[:, t, r], rtol=1e-6, atol=0)
             n_cmp += 1
     nz = int((np.abs(o_eps) > 0).sum())
-    log("  compared receivers", n_cmp, "nonzero oracle d/deps_r entries", nz)
-    assert n_cmp > 0 and nz > 0
+    log("  compared receivers", n_cmp, "nonzero oracle d/deps_r entries", nz,
+        "nonzero d/dw entries", int((np.abs(o_pat) > 0).sum()))
+    assert n_cmp > 0 and nz > 0 and np.abs(o_pat).max() > 0
     return g_eps, g_sig, g_pt
 
 
@@ -78,9 +87,43 @@ def test_toy_gradients(ctx, O):
     assert np.all(g_eps[..., 2] == 0) and np.all(g_sig[..., 2] == 0)   # constant gamma, on no face
 
 
-def test_urban_gradients(ctx, O):
+def test_urban_gradients_under_a_pattern(ctx, O):
     s = scenes.dynamic_urban()
-    compare(ctx, O, s, 7, scenes.random_sphere_dirs(65_536, seed=11))
+    w = np.random.default_rng(4).uniform(0.5, 1.5, dcem.PATTERN_TAPS)
+    compare(ctx, O, s, 7, scenes.random_sphere_dirs(65_536, seed=11), pattern=w)
+
+
+def test_pattern_applies_from_the_next_frame(ctx):
+    """The weights take effect at the next traced frame; all-ones is the
+    isotropic antenna bitwise, and a constant 0.5 quarters every power
+    exactly (a scale by a power of two)."""
+    s = scenes.static_toy()
+    ctx.scene_upload(s)
+    kw = dict(ray_dirs=scenes.random_sphere_dirs(20_000, seed=3))
+    dcem.trace_scene_frame(ctx, s, **kw)
+    p_iso, _ = ctx.received_power()
+    g_iso = ctx.power_gradients()
+    ctx.set_tx_pattern(np.full(dcem.PATTERN_TAPS, 0.5))
+    p_same, _ = ctx.received_power()
+    assert np.array_equal(p_same, p_iso)            # no frame traced since the call
+    for a, b in zip(g_iso, ctx.power_gradients()):
+        assert np.array_equal(a, b)
+    dcem.trace_scene_frame(ctx, s, **kw)
+    p_half, _ = ctx.received_power()
+    assert np.array_equal(p_half, 0.25 * p_iso)
+    ctx.set_tx_pattern(np.ones(dcem.PATTERN_TAPS))
+    dcem.trace_scene_frame(ctx, s, **kw)
+    assert np.array_equal(ctx.received_power()[0], p_iso)
+    ctx.set_tx_pattern(None)
+    dcem.trace_scene_frame(ctx, s, **kw)
+    assert np.array_equal(ctx.received_power()[0], p_iso)
+    assert p_iso.max() > 0
+
+
+def test_pattern_argument_errors(ctx):
+    for bad in (np.ones(15), np.ones(17), np.array([1.0] * 15 + [np.nan])):
+        with pytest.raises(dcem.DcemError):
+            ctx.set_tx_pattern(bad)
 
 
 def test_gradients_after_the_next_frame_started():
