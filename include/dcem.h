@@ -244,6 +244,18 @@ dcem_status dcem_received_power(dcem_ctx* ctx, double* p_coh, double* p_incoh, i
  * Errors: DCEM_E_INVALID_ARG for another count or a non-finite weight. */
 dcem_status dcem_set_tx_pattern(dcem_ctx* ctx, const double* weights, int32_t n_weights);
 
+/* Replace the scene's material table (same count and row layout as
+ * dcem_scene_desc.materials: eps_r >= 1, sigma >= 0, const_gamma in [0, 1] or
+ * NaN) without a new upload: the geometry, the BVH and the coherent-frame
+ * cache stay, since materials change only the fields (Sec. III, the Fresnel
+ * coefficients of Eq. (3)'s reflected paths).  materials: host, copied.
+ * Applies to the frames traced after the call; the last frame's powers and
+ * gradients keep the table it was traced with.  For calibration loops that
+ * fit materials with dcem_power_gradients.
+ * Errors: DCEM_E_STATE without a scene; DCEM_E_INVALID_ARG for another count
+ * or an invalid row. */
+dcem_status dcem_set_materials(dcem_ctx* ctx, const double* materials, int32_t n_materials);
+
 /* Derivatives of the last frame's coherent received power p_coh (see
  * dcem_received_power) along its fixed set of valid paths: the path geometry
  * is held, and the field of each path (Sec. III, Eq. (3) with the Fresnel

@@ -419,6 +419,16 @@ dcem_status dcem_set_timing(dcem_ctx* c, int32_t enabled) {
   return DCEM_OK;
 }
 
+// Material rows (eps_r, sigma, const_gamma): DCEM_E_INVALID_ARG for the first bad one.
+dcem_status check_materials(dcem_ctx* c, const double* M, int32_t n) {
+  for (int32_t m = 0; m < n; ++m) {
+    const double er = M[3 * m], sg = M[3 * m + 1], g = M[3 * m + 2];
+    if (!std::isfinite(er) || !std::isfinite(sg) || er < 1.0 || sg < 0.0 || (!std::isnan(g) && !(g >= 0.0 && g <= 1.0)))
+      return fail(c, DCEM_E_INVALID_ARG, "material %d: need eps_r >= 1, sigma >= 0, const_gamma in [0,1] or NaN", m);
+  }
+  return DCEM_OK;
+}
+
 dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   if (!c) return DCEM_E_INVALID_ARG;
   c->err.clear();
@@ -464,10 +474,9 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
     if (FM[f] < 0 || FM[f] >= s->n_materials) return fail(c, DCEM_E_INVALID_ARG, "face %d: material out of range", f);
     if (FO[f] < -1 || FO[f] >= s->n_objects) return fail(c, DCEM_E_INVALID_ARG, "face %d: object out of range", f);
   }
-  for (int32_t m = 0; m < s->n_materials; ++m) {
-    const double er = M[3 * m], sg = M[3 * m + 1], g = M[3 * m + 2];
-    if (!std::isfinite(er) || !std::isfinite(sg) || er < 1.0 || sg < 0.0 || (!std::isnan(g) && !(g >= 0.0 && g <= 1.0)))
-      return fail(c, DCEM_E_INVALID_ARG, "material %d: need eps_r >= 1, sigma >= 0, const_gamma in [0,1] or NaN", m);
+  {
+    const dcem_status ms = check_materials(c, M.data(), s->n_materials);
+    if (ms != DCEM_OK) return ms;
   }
   std::vector<std::pair<int64_t, int64_t>> ranges;
   for (int32_t o = 0; o < s->n_objects; ++o) {
@@ -510,6 +519,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   c->nt = s->n_tris;
   c->nf = nf;
   c->nm = s->n_materials;
+  c->mat_pending = false;
   c->no = s->n_objects;
   c->pad = (float)(4e-6 * (2.0 * R + 1.0));
   c->h_face_object = FO;
@@ -694,6 +704,10 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   c->sqrt_pt = std::sqrt(p->tx_power_w);
   c->atten_db_per_km = p->atten_db_per_km;
   c->pattern_frame = c->pattern_next;
+  if (c->mat_pending) {   // stream-ordered after the last frame's field and gradient kernels
+    HIP_TRY(upload(c->materials, c->mat_next, c->stream), "upload materials");
+    c->mat_pending = false;
+  }
   c->record_log = p->record_trace_log != 0;
   if (need_dirs) {   // transmitters, receivers or rays changed
     HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
@@ -841,6 +855,19 @@ dcem_status dcem_set_tx_pattern(dcem_ctx* c, const double* weights, int32_t n_we
   for (int j = 0; j < kPatternTaps; ++j) p.w[j] = weights[j];
   p.on = 1;
   c->pattern_next = p;
+  return DCEM_OK;
+}
+
+dcem_status dcem_set_materials(dcem_ctx* c, const double* materials, int32_t n_materials) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  if (n_materials != c->nm) return fail(c, DCEM_E_INVALID_ARG, "the scene has %d materials", c->nm);
+  if (n_materials > 0 && !materials) return fail(c, DCEM_E_INVALID_ARG, "null materials");
+  const dcem_status ms = check_materials(c, materials, n_materials);
+  if (ms != DCEM_OK) return ms;
+  c->mat_next.assign(materials, materials + 3 * (size_t)n_materials);
+  c->mat_pending = true;
   return DCEM_OK;
 }
 

@@ -215,6 +215,9 @@ struct dcem_ctx {
   // transmit pattern: the weights of the next traced frame, and those the
   // last traced frame used (its paths' fields, and its gradients)
   dcem::TxPattern pattern_next{}, pattern_frame{};
+  // material table set after the scene upload, uploaded by the next traced frame
+  std::vector<double> mat_next;
+  bool mat_pending = false;
   bool bvh_stale = false;     // transforms changed since the last refit
   bool has_frame = false;
   int32_t record_log = 0;

@@ -68,6 +68,7 @@ SIGNATURES = [
     ("dcem_trace_frame", _I32, [_P, ctypes.POINTER(TraceParams)]),
     ("dcem_received_power", _I32, [_P, _P, _P, _I32]),
     ("dcem_set_tx_pattern", _I32, [_P, _P, _I32]),
+    ("dcem_set_materials", _I32, [_P, _P, _I32]),
     ("dcem_power_gradients", _I32, [_P, _P, _P, _P, _P]),
     ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("dcem_get_trace_log", _I32, [_P, _P, _P, _P]),
@@ -233,6 +234,12 @@ class Context:
             return
         w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
         self._check(self.lib.dcem_set_tx_pattern(self.handle, _addr(w), int(w.shape[0])))
+
+    def set_materials(self, materials):
+        """New material table [n_materials, 3] (eps_r, sigma, const_gamma) for
+        the next frames; geometry and caches stay."""
+        m = np.ascontiguousarray(materials, dtype=np.float64).reshape(-1, 3)
+        self._check(self.lib.dcem_set_materials(self.handle, _addr(m), int(m.shape[0])))
 
     def power_gradients(self):
         """Derivatives of the last frame's coherent power along its paths:

@@ -146,3 +146,72 @@ def test_gradients_after_the_next_frame_started():
         for a, b in zip(before, after):
             assert np.array_equal(a, b)
     c.close()
+
+
+def toy_two_bands():
+    s = scenes.static_toy()
+    return scenes.Scene(**{**s.__dict__, "freqs_hz": [28e9, 3.5e9]})
+
+
+HIDDEN = ((7.0, 1.0), (10.0, 0.5))   # concrete and ground, far from the scene's own
+
+
+def test_set_materials_applies_from_the_next_frame(ctx, O):
+    s = toy_two_bands()
+    dirs = scenes.random_sphere_dirs(20_000, seed=3)
+    hidden = s.materials.copy()
+    hidden[:, :2] = HIDDEN
+    sh = scenes.Scene(**{**s.__dict__, "materials": hidden})
+    ctx.scene_upload(s)
+    dcem.trace_scene_frame(ctx, s, ray_dirs=dirs)
+    p0, _ = ctx.received_power()
+    g0 = ctx.power_gradients()
+    ctx.set_materials(hidden)
+    assert np.array_equal(ctx.received_power()[0], p0)   # the last frame keeps its table
+    for a, b in zip(g0, ctx.power_gradients()):
+        assert np.array_equal(a, b)
+    dcem.trace_scene_frame(ctx, s, ray_dirs=dirs)
+    p1, _ = ctx.received_power()
+    g1 = ctx.power_gradients()
+    # the same as a fresh upload of the hidden table, and as the oracle's
+    c2 = dcem.Context(0)
+    try:
+        c2.scene_upload(sh)
+        dcem.trace_scene_frame(c2, sh, ray_dirs=dirs)
+        assert np.array_equal(c2.received_power()[0], p1)
+        for a, b in zip(c2.power_gradients(), g1):
+            assert np.array_equal(a, b)
+    finally:
+        c2.close()
+    ofr = O.frame(sh, dirs=dirs)
+    comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
+    assert comparable.mean() >= 0.8 and not np.array_equal(p1, p0)
+    np.testing.assert_allclose(p1[:, comparable], ofr.p_coh[:, comparable], rtol=1e-6, atol=0)
+    with pytest.raises(dcem.DcemError):
+        ctx.set_materials(hidden[:1])
+    bad = hidden.copy()
+    bad[0, 0] = 0.5   # eps_r below 1
+    with pytest.raises(dcem.DcemError):
+        ctx.set_materials(bad)
+
+
+def test_materials_fit_by_adam(ctx, O):
+    """Calibration: the materials of the toy scene are fitted by Adam through
+    the library's frames and gradients to the oracle's powers at hidden
+    materials (noise-free), on the receivers whose path sets are certain."""
+    from paper_2112_07115_amd import calibrate
+    s = toy_two_bands()
+    dirs = scenes.random_sphere_dirs(20_000, seed=3)
+    hidden = s.materials.copy()
+    hidden[:, :2] = HIDDEN
+    ofr = O.frame(scenes.Scene(**{**s.__dict__, "materials": hidden}), dirs=dirs)
+    meas = 10.0 * np.log10(np.where(ofr.p_coh > 0, ofr.p_coh, np.nan))
+    ctx.scene_upload(s)
+    dcem.trace_scene_frame(ctx, s, ray_dirs=dirs)
+    # path sets (geometry only) compared at the starting table, amplitudes included
+    comparable, _ = parity.compare_paths(ctx.paths(), O.frame(s, dirs=dirs), len(dirs))
+    mask = np.broadcast_to(comparable, meas.shape)
+    r = calibrate.fit_materials(ctx, s, meas, s.materials, mask=mask, ray_dirs=dirs, steps=400, lr=0.1)
+    log("  fit: loss %.3g -> %.3g dB^2 in %d steps" % (r.loss_db2[0], r.loss_db2[-1], r.steps), r.materials[:, :2])
+    assert r.loss_db2[0] > 1e-3 and r.loss_db2[-1] < 1e-10
+    np.testing.assert_allclose(r.materials[:, :2], hidden[:, :2], rtol=1e-4)
