@@ -396,6 +396,7 @@ void dcem_destroy(dcem_ctx* c) {
                     &c->face_build};
   for (DevBuf* b : bufs) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
+  if (c->grad_host) (void)hipHostFree(c->grad_host);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
@@ -897,11 +898,22 @@ dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, 
     const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
     launch_power_grad(c, nu, want_mat ? g : nullptr, g + ng, d_pattern ? g + 2 * ng : nullptr);
     HIP_TRY(hipGetLastError(), "gradient kernel");
-    if (d_eps_r) HIP_TRY(hipMemcpyAsync(d_eps_r, g, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
-    if (d_sigma) HIP_TRY(hipMemcpyAsync(d_sigma, g + ng, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
-    if (d_pattern)
-      HIP_TRY(hipMemcpyAsync(d_pattern, g + 2 * ng, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream), "copy");
+    // one transfer into pinned memory, then host copies into the caller's arrays
+    const size_t lo = want_mat ? 0 : 2 * ng, hi = d_pattern ? 2 * ng + np : 2 * ng;
+    const size_t bytes = sizeof(double) * (2 * ng + np);
+    if (c->grad_host_bytes < bytes) {
+      if (c->grad_host) (void)hipHostFree(c->grad_host);
+      c->grad_host = nullptr;
+      c->grad_host_bytes = 0;
+      HIP_TRY(hipHostMalloc(&c->grad_host, bytes, hipHostMallocDefault), "alloc pinned gradients");
+      c->grad_host_bytes = bytes;
+    }
+    double* h = static_cast<double*>(c->grad_host);
+    HIP_TRY(hipMemcpyAsync(h + lo, g + lo, sizeof(double) * (hi - lo), hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    if (d_eps_r && want_mat) std::memcpy(d_eps_r, h, sizeof(double) * ng);
+    if (d_sigma && want_mat) std::memcpy(d_sigma, h + ng, sizeof(double) * ng);
+    if (d_pattern) std::memcpy(d_pattern, h + 2 * ng, sizeof(double) * np);
   }
   return DCEM_OK;
 }

@@ -171,6 +171,8 @@ struct dcem_ctx {
   // clamp(floor((x - rx_col_x0) * rx_col_scale), 0, kRxCols - 1)
   dcem::DevBuf rx_cols;
   dcem::DevBuf grad_buf;   // power gradients: [2][freq][pair][material], then [freq][pair][16]
+  void* grad_host = nullptr;   // pinned copy of grad_buf, read back in one transfer
+  size_t grad_host_bytes = 0;
   float rx_col_x0 = 0.0f, rx_col_scale = 0.0f;
   std::vector<double> freqs_host;
   int32_t n_rx_nodes = 0;

@@ -861,9 +861,9 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair
 }
 
 // Power gradients along the frame's paths, one wavefront per (tx, rx) pair:
-// the coherent field A = sum_p a_p per frequency (fixed butterfly), then for
-// each material m the derivative of every valid path's amplitude with respect
-// to m's eps_c, carried forward through its reflections (E -> Gamma_TE (E.s) s
+// the coherent field A = sum_p a_p per frequency (fixed butterfly), then, one
+// lane per (path, material) item, the derivative of the path's amplitude with
+// respect to the material's eps_c, carried forward through its reflections (E -> Gamma_TE (E.s) s
 // + Gamma_TM (E.p_in) p_out, plus the map with the Gammas' derivatives at a
 // face of material m), and dP/dtheta = 2 Re sum_c conj(A_c) dA_c/dtheta with
 // d/deps_r = d/deps_c and d/dsigma = -j / (2 pi f eps0) d/deps_c.  Each
@@ -961,6 +961,9 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
       for (int c = 0; c < 3; ++c) E[c] = ne[c];
     }
   };
+  const int nme = g_eps ? n_mat : 0;                // material tasks
+  const int T = nme + (g_pat ? 1 : 0);               // tasks per path
+  const int n_items = (end - start) * T;
   for (int fi = 0; fi < n_freqs; ++fi) {
     const double f = freqs[fi];
     double A[6] = {0, 0, 0, 0, 0, 0};
@@ -980,56 +983,63 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
       sincos(k0 * d, &sn, &cs);
       return Cx{mag * cs, -mag * sn};
     };
-    for (int m = 0; m < n_mat && g_eps; ++m) {
-      double ge = 0.0, gs = 0.0;
-      for (int u = start + lane; u < end; u += 64) {
-        if (!valid[u]) continue;
-        const int ord = order[u];
-        bool uses = false;
-        for (int j = 0; j < ord; ++j) uses = uses || face_material[faces[(size_t)u * K + j]] == m;
-        if (!uses) continue;
-        Cx E[3], dE[3];
-        walk(u, f, m, E, dE);
-        const Cx ph = cscl(pattern_gain(pat, departure(u)), phase(u));
-        for (int c = 0; c < 3; ++c) {
-          const Cx da = cmul(ph, dE[c]);              // d a_c / d eps_c
-          const Cx ds = cmul(dsig, da);               // d a_c / d sigma
-          const Cx Ac = {A[2 * c], -A[2 * c + 1]};    // conj(A_c)
-          ge += 2.0 * cmul(Ac, da).re;
-          gs += 2.0 * cmul(Ac, ds).re;
+    // Items (path, task) over the lanes, task < nme: material task, task ==
+    // nme: the pattern; each round's per-task sums by fixed butterflies, the
+    // rounds added in order by lane 0 (bitwise reproducible).
+    for (int base = 0; base < max(n_items, 1); base += 64) {   // uniform per wavefront
+      const int it = base + lane;
+      int task = -1, jt = 0;
+      double v0 = 0.0, v1 = 0.0;
+      if (it < n_items) {
+        const int u = start + it / T;
+        task = it % T;
+        const int m = task < nme ? task : -1;
+        bool act = valid[u] != 0;
+        if (act && m >= 0) {
+          bool uses = false;
+          for (int j = 0; j < order[u]; ++j) uses = uses || face_material[faces[(size_t)u * K + j]] == m;
+          act = uses;
+        }
+        if (act) {
+          Cx E[3], dE[3];
+          walk(u, f, m, E, dE);
+          const Cx ph = phase(u);
+          if (m >= 0) {
+            const Cx phg = cscl(pattern_gain(pat, departure(u)), ph);
+            for (int c = 0; c < 3; ++c) {
+              const Cx da = cmul(phg, dE[c]);             // d a_c / d eps_c
+              const Cx ds = cmul(dsig, da);               // d a_c / d sigma
+              const Cx Ac = {A[2 * c], -A[2 * c + 1]};    // conj(A_c)
+              v0 += 2.0 * cmul(Ac, da).re;
+              v1 += 2.0 * cmul(Ac, ds).re;
+            }
+          } else {
+            // a_p = g(phi_p) a_p^iso: d a_p / d w_j = B_j(phi_p) a_p^iso, nonzero
+            // for the two taps around the departure azimuth
+            for (int c = 0; c < 3; ++c) v0 += 2.0 * cmul(Cx{A[2 * c], -A[2 * c + 1]}, cmul(ph, E[c])).re;
+            pattern_cell(departure(u), jt, v1);
+          }
         }
       }
-      ge = butterfly(ge);
-      gs = butterfly(gs);
-      if (lane == 0) {
-        g_eps[((size_t)fi * n_pairs + wave) * n_mat + m] = ge;
-        g_sig[((size_t)fi * n_pairs + wave) * n_mat + m] = gs;
+      const size_t row = (size_t)fi * n_pairs + wave;
+      for (int m = 0; m < nme; ++m) {
+        const double e = butterfly(task == m ? v0 : 0.0);
+        const double sg = butterfly(task == m ? v1 : 0.0);
+        if (lane == 0) {
+          g_eps[row * n_mat + m] = (base ? g_eps[row * n_mat + m] : 0.0) + e;
+          g_sig[row * n_mat + m] = (base ? g_sig[row * n_mat + m] : 0.0) + sg;
+        }
       }
-    }
-    if (!g_pat) continue;
-    // a_p = g(phi_p) a_p^iso with g = sum_j w_j B_j: d a_p / d w_j = B_j(phi_p) a_p^iso,
-    // nonzero for the two taps around the path's departure azimuth
-    double acc[kPatternTaps];
+      if (g_pat) {
+        const bool ip = task == nme;
+        const int j1 = (jt + 1) & (kPatternTaps - 1);
 #pragma unroll
-    for (int q = 0; q < kPatternTaps; ++q) acc[q] = 0.0;
-    for (int u = start + lane; u < end; u += 64) {
-      if (!valid[u]) continue;
-      Cx E[3], dE[3];
-      walk(u, f, -1, E, dE);
-      const Cx ph = phase(u);
-      double sp = 0.0;   // 2 Re sum_c conj(A_c) a_pc^iso
-      for (int c = 0; c < 3; ++c) sp += 2.0 * cmul(Cx{A[2 * c], -A[2 * c + 1]}, cmul(ph, E[c])).re;
-      int j;
-      double t;
-      pattern_cell(departure(u), j, t);
-      const int j1 = (j + 1) & (kPatternTaps - 1);
-#pragma unroll
-      for (int q = 0; q < kPatternTaps; ++q) acc[q] += (q == j ? (1.0 - t) * sp : 0.0) + (q == j1 ? t * sp : 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < kPatternTaps; ++q) {
-      const double v = butterfly(acc[q]);
-      if (lane == 0) g_pat[((size_t)fi * n_pairs + wave) * kPatternTaps + q] = v;
+        for (int q = 0; q < kPatternTaps; ++q) {
+          const double cq = ip ? (q == jt ? (1.0 - v1) * v0 : 0.0) + (q == j1 ? v1 * v0 : 0.0) : 0.0;
+          const double v = butterfly(cq);
+          if (lane == 0) g_pat[row * kPatternTaps + q] = (base ? g_pat[row * kPatternTaps + q] : 0.0) + v;
+        }
+      }
     }
   }
 }
