@@ -215,3 +215,30 @@ def test_materials_fit_by_adam(ctx, O):
     log("  fit: loss %.3g -> %.3g dB^2 in %d steps" % (r.loss_db2[0], r.loss_db2[-1], r.steps), r.materials[:, :2])
     assert r.loss_db2[0] > 1e-3 and r.loss_db2[-1] < 1e-10
     np.testing.assert_allclose(r.materials[:, :2], hidden[:, :2], rtol=1e-4)
+
+
+def test_autograd_function_against_the_oracle(ctx, O):
+    """torch autograd through the frame's power: the backward pass's
+    contraction of a random weighting of the receivers' powers equals the
+    same contraction of the oracle's gradients (comparable receivers only)."""
+    import torch
+    from paper_2112_07115_amd import autograd
+    s = toy_two_bands()
+    dirs = scenes.random_sphere_dirs(20_000, seed=3)
+    w = np.random.default_rng(8).uniform(0.6, 1.4, dcem.PATTERN_TAPS)
+    eps = torch.tensor(s.materials[:, 0], dtype=torch.float64, requires_grad=True)
+    sig = torch.tensor(s.materials[:, 1], dtype=torch.float64, requires_grad=True)
+    pt = torch.tensor(float(s.tx_power_w), dtype=torch.float64, requires_grad=True)
+    pat = torch.tensor(w, dtype=torch.float64, requires_grad=True)
+    ctx.scene_upload(s)
+    p = autograd.received_power(ctx, s, eps, sig, pt, pat, ray_dirs=dirs)
+    ofr, (o_eps, o_sig, o_pt, o_pat) = oracle_gradients(O, s, 0, dirs, pattern=w)
+    comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
+    assert comparable.mean() >= 0.8
+    wt = np.random.default_rng(2).uniform(0.5, 1.5, p.shape) * comparable[None]
+    (p * torch.from_numpy(wt)).sum().backward()
+    np.testing.assert_allclose(p.detach().numpy()[:, comparable], ofr.p_coh[:, comparable], rtol=1e-6)
+    for got, o in ((eps.grad, o_eps), (sig.grad, o_sig), (pat.grad, o_pat)):
+        ref = np.tensordot(wt, o, axes=([0, 1, 2], [0, 1, 2]))
+        np.testing.assert_allclose(got.numpy(), ref, rtol=1e-6, atol=1e-9 * np.abs(ref).max())
+    assert float(pt.grad) == pytest.approx(float((wt * o_pt).sum()), rel=1e-6)
