@@ -89,6 +89,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libdcem.so not built (%s); run `python -m paper_2112_07115_amd.build`" % path)
+    # torch carries its own HIP runtime with the same soname: loaded first, it is
+    # the one runtime of the process and libdcem binds to it, so torch's streams
+    # and tensors are valid here.  Loaded after libdcem, torch would bind to the
+    # system runtime and find no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)
