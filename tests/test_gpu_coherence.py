@@ -236,3 +236,36 @@ def test_revalidation_ahead_follows_every_call_order():
     log("pipelined order: equal")
     full.close()
     coh.close()
+
+
+def test_coherent_frames_under_changing_pattern_and_materials():
+    """The transmit pattern and the material table change fields only: coherent
+    frames that change them every frame equal full re-traces bitwise, powers,
+    paths and gradients alike."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    rng = np.random.default_rng(12)
+    full, coh = dcem.Context(0), dcem.Context(0)
+    full.scene_upload(s)
+    coh.scene_upload(s)
+    kw = dict(max_reflections=s.max_reflections, freqs_hz=s.freqs_hz, tx_power_w=s.tx_power_w,
+              record_trace_log=True)
+    for frame in range(4):
+        w = rng.uniform(0.3, 1.7, dcem.PATTERN_TAPS)
+        mats = s.materials.copy()
+        mats[:, 0] *= rng.uniform(0.8, 1.2, mats.shape[0])
+        mats[:, 0] = np.maximum(mats[:, 0], 1.0)
+        outs = []
+        for c, mode, rebuild in ((full, dcem.MODE_FULL, True), (coh, dcem.MODE_COHERENT, False)):
+            c.set_tx_pattern(w)
+            c.set_materials(mats)
+            c.set_object_transforms(s.transforms(frame))
+            c.refit_bvh(force_rebuild=rebuild)
+            c.trace_frame(s.tx, s.rx, s.rx_radius, n, mode=mode, **kw)
+            outs.append((frame_outputs(c), c.power_gradients()))
+        log("frame", frame, "rays traced", coh.stats()["rays_traced"])
+        assert_same(outs[0][0], outs[1][0])
+        for a, b in zip(outs[0][1], outs[1][1]):
+            assert np.array_equal(a, b)
+    full.close()
+    coh.close()
