@@ -85,20 +85,33 @@ def adam_fit(evaluate: Callable[[np.ndarray], tuple], materials0: np.ndarray, me
 
 
 def fit_materials(ctx: "dcem.Context", scene, measured_db: np.ndarray, materials0: np.ndarray,
-                  mask: Optional[np.ndarray] = None, frame: int = 0, ray_dirs=None, **adam) -> FitResult:
-    """Fit the scene's materials to measured powers [n_freqs, n_tx, n_rx] in
-    dBW at one frame of the scene.  The context must hold the scene (uploaded);
-    the first step traces the frame, later steps re-trace it coherently."""
+                  mask: Optional[np.ndarray] = None, frame: int = 0, ray_dirs=None, frames=None,
+                  **adam) -> FitResult:
+    """Fit the scene's materials to measured powers in dBW: [n_freqs, n_tx,
+    n_rx] at one frame of the scene, or, with `frames` (a list of frame
+    indices), [len(frames), n_freqs, n_tx, n_rx] over those frames (the loss
+    is the mean over all of them).  The context must hold the scene
+    (uploaded); the first step traces each frame in full, later steps trace
+    coherently (every frame's objects are placed again, so only the rays their
+    motion invalidates are re-traced)."""
     state = {"traced": False}
+    seq = [frame] if frames is None else list(frames)
 
     def evaluate(mats):
         ctx.set_materials(mats)
-        dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=ray_dirs,
-                               mode=dcem.MODE_COHERENT if state["traced"] else dcem.MODE_FULL,
-                               keep_cache=True)
+        ps, des, dss = [], [], []
+        for f in seq:
+            dcem.trace_scene_frame(ctx, scene, frame=f, ray_dirs=ray_dirs,
+                                   mode=dcem.MODE_COHERENT if state["traced"] else dcem.MODE_FULL,
+                                   keep_cache=True)
+            p, _ = ctx.received_power()
+            d_eps, d_sig, _, _ = ctx.power_gradients()
+            ps.append(p)
+            des.append(d_eps)
+            dss.append(d_sig)
         state["traced"] = True
-        p, _ = ctx.received_power()
-        d_eps, d_sig, _, _ = ctx.power_gradients()
-        return p, d_eps, d_sig
+        if frames is None:
+            return ps[0], des[0], dss[0]
+        return np.stack(ps), np.stack(des), np.stack(dss)
 
     return adam_fit(evaluate, materials0, measured_db, mask, **adam)

@@ -242,3 +242,34 @@ def test_autograd_function_against_the_oracle(ctx, O):
         ref = np.tensordot(wt, o, axes=([0, 1, 2], [0, 1, 2]))
         np.testing.assert_allclose(got.numpy(), ref, rtol=1e-6, atol=1e-9 * np.abs(ref).max())
     assert float(pt.grad) == pytest.approx(float((wt * o_pt).sum()), rel=1e-6)
+
+
+def test_materials_fit_over_moving_frames(ctx, O):
+    """Calibration over three frames of the urban scene (moving vehicles,
+    65,536 random rays, K = 4): concrete and ground are fitted to the oracle's
+    powers at hidden values on every frame's comparable receivers; the metal
+    (eps_r = 1) has no eps_r freedom left and keeps its table values."""
+    from paper_2112_07115_amd import calibrate
+    s = scenes.dynamic_urban()
+    s = scenes.Scene(**{**s.__dict__, "freqs_hz": [28e9, 3.5e9]})
+    dirs = scenes.random_sphere_dirs(65_536, seed=11)
+    hidden = s.materials.copy()
+    hidden[0, :2] = HIDDEN[0]
+    hidden[1, :2] = HIDDEN[1]
+    sh = scenes.Scene(**{**s.__dict__, "materials": hidden})
+    frames = [0, 3, 6]
+    ctx.scene_upload(s)
+    meas, masks = [], []
+    for f in frames:
+        ofr = O.frame(sh, frame_index=f, dirs=dirs)
+        meas.append(10.0 * np.log10(np.where(ofr.p_coh > 0, ofr.p_coh, np.nan)))
+        dcem.trace_scene_frame(ctx, s, frame=f, ray_dirs=dirs)
+        comparable, _ = parity.compare_paths(ctx.paths(), O.frame(s, frame_index=f, dirs=dirs), len(dirs))
+        masks.append(np.broadcast_to(comparable, meas[-1].shape))
+    r = calibrate.fit_materials(ctx, s, np.stack(meas), s.materials, mask=np.stack(masks), ray_dirs=dirs,
+                                frames=frames, steps=300, lr=0.1)
+    log("  fit over frames %s: loss %.3g -> %.3g dB^2 in %d steps" % (frames, r.loss_db2[0], r.loss_db2[-1],
+                                                                     r.steps), r.materials[:, :2])
+    assert r.loss_db2[-1] < 1e-3 * r.loss_db2[0]
+    np.testing.assert_allclose(r.materials[:2, :2], hidden[:2, :2], rtol=1e-2)
+    assert r.materials[2, 0] == pytest.approx(s.materials[2, 0], abs=1e-6)
