@@ -563,6 +563,7 @@ void* oracle_scene_new(const float* V, int64_t nv, const int32_t* T, const int32
         sc->faces[f].object = face_object[f];
     }
     auto vtx = [&](int32_t i) { return V3{W[3 * i], W[3 * i + 1], W[3 * i + 2]}; };
+    auto vref = [&](int32_t i) { return V3{V[3 * i], V[3 * i + 1], V[3 * i + 2]}; };
     for (int64_t i = 0; i < 3 * nv; i += 3) {
         V3 p{W[i], W[i + 1], W[i + 2]};
         sc->radius = std::max(sc->radius, norm(p));
@@ -581,8 +582,14 @@ void* oracle_scene_new(const float* V, int64_t nv, const int32_t* T, const int32
         tr.h2 = twice_area / norm(tr.b - tr.a);
         Face& f = sc->faces[tr.face];
         f.tris.push_back((int)i);
-        if (twice_area > best_area[tr.face]) {   // plane from the face's largest triangle
-            best_area[tr.face] = twice_area;
+        // The plane of a face is that of its largest triangle, chosen in the
+        // upload pose (first of equal ones): a rotated face's FP32 vertices
+        // are no longer exactly coplanar, and the choice must not depend on
+        // the rounding of the current pose.
+        const V3 ra = vref(T[3 * i]), rb = vref(T[3 * i + 1]), rc = vref(T[3 * i + 2]);
+        const double ref_area = norm(cross(rb - ra, rc - ra));
+        if (ref_area > best_area[tr.face]) {
+            best_area[tr.face] = ref_area;
             f.n = unit(cross(tr.b - tr.a, tr.c - tr.a));
             f.p = tr.a;
         }

@@ -15,6 +15,16 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def oracle_mod():
+    # DCEM_ORACLE_PY names a planted-mistake copy of oracle.py (see
+    # test_oracle_mutations.py); otherwise the real oracle
+    alt = os.environ.get("DCEM_ORACLE_PY")
+    if alt:
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("oracle_mutant", alt)
+        mod = importlib.util.module_from_spec(spec)
+        sys.modules["oracle_mutant"] = mod   # dataclasses resolve their module by name
+        spec.loader.exec_module(mod)
+        return mod
     from oracle import oracle
     oracle.build()
     return oracle

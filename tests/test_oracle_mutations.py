@@ -13,6 +13,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "dcem_oracle.cpp")
+PY = os.path.join(ROOT, "oracle", "oracle.py")
 
 MUTATIONS = {
     "gamma_te_sign": ("g_te = (cos_t - root) / (cos_t + root);",
@@ -54,6 +55,18 @@ MUTATIONS = {
                          "test_oracle_pattern.py"),
 }
 
+# Mistakes planted in the Python half of the oracle (the per-receiver sums).
+PY_MUTATIONS = {
+    # incoherent power as the coherent one (square of the sum over paths)
+    "p_inc_square_of_sum": ("return p_coh, p_inc", "return p_coh, p_coh.copy()"),
+    # squared sum of component magnitudes instead of the sum of their squares
+    "p_inc_component_sum": ("p_inc[:, t, r] += np.sum(np.abs(paths.amp[i]) ** 2, axis=-1)",
+                            "p_inc[:, t, r] += np.sum(np.abs(paths.amp[i]), axis=-1) ** 2"),
+    # coherent sum over only the last path of a receiver
+    "p_coh_last_path": ("acc[:, int(paths.keys[i, 0]), int(paths.keys[i, 1])] += paths.amp[i]",
+                        "acc[:, int(paths.keys[i, 0]), int(paths.keys[i, 1])] = paths.amp[i]"),
+}
+
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_mutation(name, tmp_path):
@@ -72,3 +85,29 @@ def test_pins_catch_mutation(name, tmp_path):
                         os.path.join(ROOT, "tests", suite)],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
+
+
+def _run_pins_on_python_copy(tmp_path, old, new):
+    src = open(PY).read()
+    assert src.count(old) == 1, "mutation anchor not found: %r" % old
+    mod = tmp_path / "oracle_mutant.py"
+    mod.write_text(src.replace(old, new).replace(
+        '_HERE = os.path.dirname(os.path.abspath(__file__))',
+        '_HERE = %r' % os.path.join(ROOT, "oracle")))
+    env = dict(os.environ, DCEM_ORACLE_PY=str(mod))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
+
+
+def test_unmutated_python_copy_passes_the_pins(tmp_path):
+    # control: the copy mechanism alone must not make the pins fail
+    r = _run_pins_on_python_copy(tmp_path, "return p_coh, p_inc", "return p_coh, p_inc")
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_pins_catch_python_mutation(name, tmp_path):
+    r = _run_pins_on_python_copy(tmp_path, *PY_MUTATIONS[name])
+    assert r.returncode == 1, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
+    assert " failed" in r.stdout and " error" not in r.stdout, r.stdout[-2000:]

@@ -328,6 +328,58 @@ def test_constant_gamma_orders(oracle_mod):
                                               unfolded(40.0), unfolded(-40.0)], rtol=1e-12)
 
 
+def test_incoherent_and_coherent_sums_over_paths(oracle_mod):
+    """Received power over several paths of one receiver, in closed form.
+
+    Two facing walls x = -10 and x = +10 with Table II's constant coefficient
+    g = 0.8, transmitter and receiver at the same height: every path runs
+    horizontally, so the transmitted field -z-hat is perpendicular to every
+    plane of incidence (pure TE) and each reflection multiplies it by
+    Gamma_TE = -g.  With unfolded lengths d_p and orders k_p:
+      P_inc = Pt (lambda/4 pi)^2 sum_p g^(2 k_p) / d_p^2,
+      P_coh = Pt (lambda/4 pi)^2 |sum_p (-g)^k_p exp(-j k0 d_p) / d_p|^2.
+    """
+    g = table2()["wall_outdoor"][1]
+    f, pt = 28e9, 5.0
+    lam = C0 / f
+    k0 = 2 * math.pi / lam
+    tx, rx = (0.0, 0.0, 1.5), (3.0, 40.0, 1.5)
+    sc = scenes.parallel_walls([tx], [rx], material=(5.0, 0.0, g))
+    keys = [[0, 0, 0, -1, -1], [0, 0, 1, 0, -1], [0, 0, 1, 1, -1], [0, 0, 2, 0, 1], [0, 0, 2, 1, 0]]
+    # transmitter x after unfolding through the walls of each key
+    x_img = [0.0, -20.0, 20.0, 40.0, -40.0]
+    d = np.array([math.hypot(xi - rx[0], rx[1]) for xi in x_img])
+    order = np.array([k[2] for k in keys])
+    paths = refine_keys(oracle_mod, sc, keys, 2)
+    assert paths.valid.all()
+    np.testing.assert_allclose(paths.length, d, rtol=1e-12)
+    pc, pi = oracle_mod.received_power(paths, 1, 1, 1)
+    scale = pt * (lam / (4 * math.pi)) ** 2
+    want_inc = scale * np.sum(g ** (2 * order) / d ** 2)
+    want_coh = scale * abs(np.sum((-g) ** order * np.exp(-1j * k0 * d) / d)) ** 2
+    assert abs(pi[0, 0, 0] - want_inc) <= 1e-9 * want_inc
+    assert abs(pc[0, 0, 0] - want_coh) <= 1e-9 * want_inc
+    # the two sums differ here (interference), so neither can stand in for the other
+    assert abs(want_coh - want_inc) > 0.05 * want_inc
+    # a constant-coefficient mirror scales any polarisation by g, so off any
+    # symmetry plane (fields with three components) a ground reflection still
+    # adds g^2 Pt (lambda / 4 pi d_2)^2 to the incoherent sum
+    tx, rxs = (0.0, 0.0, 5.0), [(30.0, 20.0, 1.5), (-7.0, 55.0, 2.5), (12.0, -4.0, 0.5)]
+    sc = scenes.ground_only([tx], rxs, material=(15.0, 0.035, g))
+    keys = []
+    for r in range(len(rxs)):
+        keys += [[0, r, 0, -1], [0, r, 1, 0]]
+    paths = refine_keys(oracle_mod, sc, keys, 1)
+    assert paths.valid.all()
+    assert np.count_nonzero(np.abs(paths.amp[0, 0]) > 1e-3 * np.abs(paths.amp[0, 0]).max()) == 3
+    pc, pi = oracle_mod.received_power(paths, 1, len(rxs), 1)
+    for r, (x, y, z) in enumerate(rxs):
+        d1 = math.dist(tx, (x, y, z))
+        d2 = math.dist((tx[0], tx[1], -tx[2]), (x, y, z))
+        want = scale * (1.0 / d1 ** 2 + g * g / d2 ** 2)
+        assert abs(pi[0, 0, r] - want) <= 1e-9 * want
+
+
 def test_corner_reflector_double_bounce(oracle_mod):
     """Two reflections in perpendicular walls = point reflection through the corner axis.
 
