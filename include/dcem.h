@@ -182,6 +182,16 @@ const char* dcem_last_error(const dcem_ctx* ctx);
 /* Capacity of the capture buffer (default 1<<22 records).  Overflow sets
  * DCEM_ERR_CAPTURES. */
 dcem_status dcem_set_capture_capacity(dcem_ctx* ctx, int64_t max_captures);
+/* Cap the closest-hit traversal stacks at `entries` entries per query (0
+ * restores the full depth: 48 per ray in the per-thread traversal, 128 in the
+ * group traversal; larger values are clamped to those).  Results do not
+ * change unless a stack overflows; an overflow drops the entries that do not
+ * fit, sets DCEM_ERR_STACK, and is reported as DCEM_E_CAPACITY by the next
+ * synchronising call (that frame's outputs are undefined).  The full depth
+ * holds every tree this library builds; smaller caps exercise the overflow
+ * path.  Applies to frames traced after the call.
+ * Errors: DCEM_E_INVALID_ARG for a negative count. */
+dcem_status dcem_set_stack_limit(dcem_ctx* ctx, int32_t entries);
 /* Enable per-stage HIP event timings in dcem_frame_stats (default off). */
 dcem_status dcem_set_timing(dcem_ctx* ctx, int32_t enabled);
 

@@ -30,21 +30,29 @@ class _ReceivedPower(torch.autograd.Function):
         dcem.trace_scene_frame(dctx, s, frame=frame, ray_dirs=ray_dirs, mode=mode, keep_cache=True)
         p, _ = dctx.received_power()
         de, ds, dp, dw = dctx.power_gradients()
-        fctx.save_for_backward(*(torch.from_numpy(a) for a in (de, ds, dp, dw)))
-        return torch.from_numpy(p)
+        # gradients are returned on each parameter's device and in its dtype;
+        # the power lives where eps_r does
+        fctx.like = [(t.device, t.dtype) for t in (eps_r, sigma, tx_power, pattern)]
+        dev = eps_r.device
+        fctx.save_for_backward(*(torch.from_numpy(a).to(dev) for a in (de, ds, dp, dw)))
+        return torch.from_numpy(p).to(dev)
 
     @staticmethod
     def backward(fctx, grad_p):
         de, ds, dp, dw = fctx.saved_tensors
-        g = grad_p.double()
-        return ((g[..., None] * de).sum((0, 1, 2)), (g[..., None] * ds).sum((0, 1, 2)), (g * dp).sum(),
-                (g[..., None] * dw).sum((0, 1, 2)), None, None, None, None, None)
+        g = grad_p.double().to(de.device)
+        grads = ((g[..., None] * de).sum((0, 1, 2)), (g[..., None] * ds).sum((0, 1, 2)), (g * dp).sum(),
+                 (g[..., None] * dw).sum((0, 1, 2)))
+        grads = tuple(x.to(device=d, dtype=t) for x, (d, t) in zip(grads, fctx.like))
+        return grads + (None, None, None, None, None)
 
 
 def received_power(dctx: "dcem.Context", scene, eps_r: torch.Tensor, sigma: torch.Tensor, tx_power: torch.Tensor,
                    pattern: torch.Tensor, frame: int = 0, ray_dirs=None, mode: int = dcem.MODE_COHERENT):
-    """Coherent power [n_freqs, n_tx, n_rx] (FP64, CPU tensor) of `scene`'s
-    frame with eps_r, sigma [n_materials], tx_power [] and pattern [16]; the
-    context must hold the scene.  Differentiable in all four.  Materials with a
-    constant gamma ignore their eps_r and sigma (zero gradients)."""
+    """Coherent power [n_freqs, n_tx, n_rx] (FP64, on eps_r's device) of
+    `scene`'s frame with eps_r, sigma [n_materials], tx_power [] and pattern
+    [16] (each on any device; its gradient comes back on that device and in
+    its dtype); the context must hold the scene.  Differentiable in all four.
+    Materials with a constant gamma ignore their eps_r and sigma (zero
+    gradients)."""
     return _ReceivedPower.apply(eps_r, sigma, tx_power, pattern, dctx, scene, frame, ray_dirs, mode)

@@ -414,6 +414,14 @@ dcem_status dcem_set_capture_capacity(dcem_ctx* c, int64_t max_captures) {
   return DCEM_OK;
 }
 
+dcem_status dcem_set_stack_limit(dcem_ctx* c, int32_t entries) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (entries < 0) return fail(c, DCEM_E_INVALID_ARG, "stack limit must be >= 0");
+  c->stack_limit = entries;
+  return DCEM_OK;
+}
+
 dcem_status dcem_set_timing(dcem_ctx* c, int32_t enabled) {
   if (!c) return DCEM_E_INVALID_ARG;
   c->timing = enabled != 0;
@@ -667,6 +675,15 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
       return fail(c, DCEM_E_UNSUPPORTED, "candidate key exceeds 256 bits");
   }
   HIP_TRY(hipSetDevice(c->device), "set device");
+  // An unread previous frame is finished before anything of this frame
+  // replaces its configuration or buffers: its results land in the frame
+  // block this call may reallocate, its captures and counters are what a
+  // coherent frame reuses, and a candidate redo (more captures than the
+  // device path holds) must run with that frame's layout.
+  if (c->has_frame && !c->counts_current) {
+    const dcem_status st = sync_frame(c);
+    if (st != DCEM_OK) return st;
+  }
   // -- configuration and cache applicability
   std::vector<float> txh, rxh;
   HIP_TRY(fetch(txh, p->tx_pos, 3 * (size_t)p->n_tx, p->mem_kind, c->stream), "read tx");
@@ -755,13 +772,9 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
   const void* block_before = c->frame_block.p;
   HIP_TRY(ensure_frame_block(c, (int64_t)p->n_freqs * p->n_tx * p->n_rx), "alloc results");
-  // counts of the previous frame: its capture list (reused by a coherent frame),
-  // its re-trace count (sizes the persistent grid) and its capture count (picks
-  // the de-duplication path)
-  if (c->has_frame && !c->counts_current) {
-    dcem_status st = sync_frame(c);
-    if (st != DCEM_OK) return st;
-  }
+  // counts of the previous frame (read above): its capture list (reused by a
+  // coherent frame), its re-trace count (sizes the persistent grid) and its
+  // capture count (picks the de-duplication path)
   const uint32_t n_prev = (uint32_t)c->n_caps_host;
   const int64_t expected_work = (c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work;
   const bool small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);

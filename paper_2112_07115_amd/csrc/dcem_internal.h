@@ -130,6 +130,7 @@ struct dcem_ctx {
   std::string err;
   bool timing = false;
   int64_t cap_capacity = int64_t(1) << 22;
+  int32_t stack_limit = 0;   // traversal stack cap (dcem_set_stack_limit); 0 = full depth
 
   // -- scene
   bool has_scene = false;

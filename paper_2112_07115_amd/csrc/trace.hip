@@ -154,8 +154,8 @@ __device__ inline void cswap(float& ta, int& ca, float& tb, int& cb) {
 // not depend on the tree shape: boxes are conservative and nodes are pruned
 // only when their entry distance exceeds the current best (ties are visited).
 __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const Node4* top, int n_top, int n4,
-                           const Leaf* __restrict__ tri4, int excl, int* stack, int stride, bool& overflow,
-                           uint32_t& n_nodes, uint32_t& n_tris) {
+                           const Leaf* __restrict__ tri4, int excl, int* stack, int stride, int stack_cap,
+                           bool& overflow, uint32_t& n_nodes, uint32_t& n_tris) {
   Hit h{FLT_MAX, -1, -1, -1};
   if (n4 == 0) return h;
   int node = 0, sp = 0;
@@ -197,7 +197,7 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
 #pragma unroll
     for (int e = 3; e >= 1; --e) {
       if (c[e] == kEmpty) continue;
-      if (sp < kStackSize) stack[(sp++) * stride] = c[e];
+      if (sp < stack_cap) stack[(sp++) * stride] = c[e];
       else overflow = true;
     }
     node = c[0];
@@ -256,6 +256,8 @@ struct TraceArgs {
   uint32_t* err;
   const Capture* prev_caps;   // coherent frames: the previous frame's captures to filter
   uint32_t n_prev;
+  int stack_thread;           // stack entries a per-thread traversal may use (<= kStackSize)
+  int stack_group;            // stack entries a group traversal may use (<= kRayStack)
 };
 
 // Coherent frames: keep each capture of the previous frame made before its
@@ -373,8 +375,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       setup_ray(r);
       uint32_t state = 0;
       for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, kTraceBlock, overflow,
-                            node_count, tri_count);
+        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, kTraceBlock, a.stack_thread,
+                            overflow, node_count, tri_count);
         ++seg_count;
         const bool hit = h.tri >= 0;
         const float tend = hit ? h.t : INFINITY;
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
             h0 = h0 && c0 >= 0;
             h1 = h1 && c1 >= 0;
             if (h0 && h1) {
-              if (sp < kStackSize) stack[(sp++) * kTraceBlock] = c1;
+              if (sp < a.stack_thread) stack[(sp++) * kTraceBlock] = c1;
               else overflow = true;
               node = c0;
             } else if (h0) {
@@ -702,12 +704,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     const uint64_t want = __ballot(push != kNoEntry) & gmask;
     const int total = __popcll(want);
     const int pos = sp + __popcll(want & below);
-    if (push != kNoEntry && pos < kRayStack) {
+    if (push != kNoEntry && pos < a.stack_group) {
       se[pos] = push;
       st[pos] = pt;
     }
-    if (sp + total > kRayStack) overflow = true;
-    sp = min(sp + total, kRayStack);
+    if (sp + total > a.stack_group) overflow = true;
+    sp = min(sp + total, a.stack_group);
     if (n_pop > 0 && --guard <= 0 && sp > 0) {   // only a malformed tree gets here
       overflow = true;
       sp = 0;
@@ -1222,6 +1224,8 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   a.err = c->err_dev;
   a.prev_caps = ptr<Capture>(c->caps[c->cur_caps ^ 1]);
   a.n_prev = all_rays ? 0u : n_prev_caps;
+  a.stack_thread = c->stack_limit > 0 ? std::min(c->stack_limit, kStackSize) : kStackSize;
+  a.stack_group = c->stack_limit > 0 ? std::min(c->stack_limit, kRayStack) : kRayStack;
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
     const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;

@@ -62,6 +62,7 @@ SIGNATURES = [
     ("dcem_last_error", ctypes.c_char_p, [_P]),
     ("dcem_set_capture_capacity", _I32, [_P, _I64]),
     ("dcem_set_timing", _I32, [_P, _I32]),
+    ("dcem_set_stack_limit", _I32, [_P, _I32]),
     ("dcem_scene_upload", _I32, [_P, ctypes.POINTER(SceneDesc)]),
     ("dcem_set_object_transforms", _I32, [_P, _P, _I32, _I32]),
     ("dcem_refit_bvh", _I32, [_P, _I32, _F64, ctypes.POINTER(_I32), ctypes.POINTER(_F64)]),
@@ -170,6 +171,10 @@ class Context:
 
     def set_capture_capacity(self, n: int):
         self._check(self.lib.dcem_set_capture_capacity(self.handle, int(n)))
+
+    def set_stack_limit(self, entries: int = 0):
+        """Cap the traversal stacks (0: full depth); an overflow is reported as E_CAPACITY."""
+        self._check(self.lib.dcem_set_stack_limit(self.handle, int(entries)))
 
     def set_timing(self, on: bool = True):
         self._check(self.lib.dcem_set_timing(self.handle, 1 if on else 0))
@@ -332,7 +337,7 @@ class FrameOutput:
 def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL, ray_dirs=None,
                       n_rays: Optional[int] = None, K: Optional[int] = None, rebuild: bool = False,
                       keep_cache: bool = False, record_trace_log: bool = False, los_always: bool = True,
-                      threshold: float = 1.5) -> FrameOutput:
+                      threshold: float = 1.5, atten_db_per_km: float = 0.0) -> FrameOutput:
     """Convenience: place the scene's objects for `frame`, update the BVH, trace, read power."""
     if scene.object_vertex_range.shape[0]:
         ctx.set_object_transforms(scene.transforms(frame))
@@ -342,7 +347,7 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
         n = ray_dirs.shape[0]
     ctx.trace_frame(scene.tx, scene.rx, scene.rx_radius, n, ray_dirs=ray_dirs,
                     max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
-                    tx_power_w=scene.tx_power_w, mode=mode, los_always=los_always, keep_cache=keep_cache,
-                    record_trace_log=record_trace_log)
+                    tx_power_w=scene.tx_power_w, atten_db_per_km=atten_db_per_km, mode=mode,
+                    los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log)
     pc, pi = ctx.received_power()
     return FrameOutput(pc, pi)

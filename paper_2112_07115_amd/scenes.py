@@ -165,6 +165,24 @@ class _MeshBuilder:
         self.face_object.append(-1)
         self.nv += len(pts)
 
+    def add_faces(self, faces, material, obj: int = -1) -> None:
+        """Planar faces given as (points [n][3], triangles [m][3] local to
+        the points), with contiguous vertices; obj >= 0 makes them one moving
+        object."""
+        v0 = self.nv
+        for pts, tris in faces:
+            pts = np.asarray(pts, dtype=np.float64).astype(np.float32)
+            f = len(self.face_material)
+            base = self.nv
+            self.verts.append(pts)
+            self.tris.append(np.asarray(tris, dtype=np.int64) + base)
+            self.tri_face.append(np.full(len(tris), f, dtype=np.int64))
+            self.face_material.append(material)
+            self.face_object.append(obj)
+            self.nv += len(pts)
+        if obj >= 0:
+            self.object_ranges.append((v0, self.nv))
+
     def finish(self, name, materials, tx, rx, **kw) -> Scene:
         return Scene(
             name=name,
@@ -432,6 +450,159 @@ def box_field(n_static: int, n_moving: int, half: float = 200.0, seed: int = 5, 
                  transforms_fn=transforms)
 
 
+def _quad_grid(p0, p1, p3, na: int, nb: int):
+    """Planar quad p0, p1, p0 + (p1 - p0) + (p3 - p0), p3 split into na x nb
+    cells of two triangles: (points, triangles)."""
+    p0, p1, p3 = (np.asarray(p, np.float64) for p in (p0, p1, p3))
+    ea, eb = p1 - p0, p3 - p0
+    pts = [p0 + ea * (i / na) + eb * (j / nb) for j in range(nb + 1) for i in range(na + 1)]
+    tris = []
+    for j in range(nb):
+        for i in range(na):
+            a = j * (na + 1) + i
+            tris += [(a, a + 1, a + na + 2), (a, a + na + 2, a + na + 1)]
+    return np.array(pts), tris
+
+
+def _rot_z(a: float) -> np.ndarray:
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def _rot_x(a: float) -> np.ndarray:
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+
+def _box_faces(centre, half, R, cells=(1, 1, 1), skip_bottom: bool = False):
+    """The six sides of the box centre + R [-half, half]^3 (R a rotation) as
+    tessellated planar faces."""
+    c, h = np.asarray(centre, np.float64), np.asarray(half, np.float64)
+
+    def P(sx, sy, sz):
+        return c + R @ (h * np.array([sx, sy, sz], np.float64))
+
+    nx, ny, nz = cells
+    sides = [
+        (P(-1, -1, -1), P(-1, -1, 1), P(-1, 1, -1), nz, ny),   # -x
+        (P(1, -1, -1), P(1, 1, -1), P(1, -1, 1), ny, nz),      # +x
+        (P(-1, -1, -1), P(1, -1, -1), P(-1, -1, 1), nx, nz),   # -y
+        (P(-1, 1, -1), P(-1, 1, 1), P(1, 1, -1), nz, nx),      # +y
+        (P(-1, -1, -1), P(-1, 1, -1), P(1, -1, -1), ny, nx),   # -z
+        (P(-1, -1, 1), P(1, -1, 1), P(-1, 1, 1), nx, ny),      # +z
+    ]
+    return [_quad_grid(p0, p1, p3, na, nb) for i, (p0, p1, p3, na, nb) in enumerate(sides)
+            if not (skip_bottom and i == 4)]
+
+
+def oblique_town(seed: int = 3, n_rays: int = 1 << 16, max_reflections: int = 3, n_frames: int = 20) -> Scene:
+    """Small town whose reflecting planes are mostly oblique, with objects that
+    rotate between frames.
+
+    Ground [-150, 150]^2.  Eight concrete buildings (centres U(-100, 100)^2,
+    15 m clear of the transmitter and 2 m of each other) yawed by U(0, pi/2),
+    half footprints U(6, 14) m, heights U(10, 35) m, walls tessellated 2 x 3;
+    half have flat roofs and half gable roofs (two slopes of U(20, 40) degrees
+    with Table II's outdoor-wall coefficient 0.8, and two gable walls).  A
+    static billboard 8 x 4 m tilted 35 degrees from vertical.  Moving: five
+    metal cars (4.5 x 1.8 x 1.5 m boxes, 0.3 m clearance) driving round
+    circles about the transmitter of radius U(20, 60) m at U(8, 16) m/s, each
+    turned to its heading every frame (yaw rotations; the cars may pass
+    through buildings), and a 6 x 0.3 x 2 m metal sign turning about a
+    horizontal axis at 1.5 rad/s.  Transforms are relative to the frame-0
+    pose.  Tx on a 12 m pole at the origin; 64 receivers uniform in
+    [-100, 100]^2 outside the buildings at 1.5 m, capture radius 1 m.
+    """
+    rng = np.random.default_rng(seed)
+    tx = np.array([[0.0, 0.0, 12.0]])
+    mb = _MeshBuilder()
+    mb.add_ground(150.0, material=1)
+    placed = []
+    n_bld = 0
+    while n_bld < 8:
+        hx, hy = rng.uniform(6.0, 14.0, size=2)
+        h = rng.uniform(10.0, 35.0)
+        yaw = rng.uniform(0.0, np.pi / 2)
+        cx, cy = rng.uniform(-100.0, 100.0, size=2)
+        rad = np.hypot(hx, hy)
+        if np.hypot(cx, cy) < rad + 15.0:
+            continue
+        if any(np.hypot(cx - q[0], cy - q[1]) < rad + q[2] + 2.0 for q in placed):
+            continue
+        placed.append((cx, cy, rad))
+        R = _rot_z(yaw)
+        gable = n_bld % 2 == 1
+        faces = _box_faces((cx, cy, h / 2), (hx, hy, h / 2), R, cells=(2, 2, 3), skip_bottom=True)
+        if gable:
+            pitch = np.radians(rng.uniform(20.0, 40.0))
+            ridge = h + hy * np.tan(pitch)
+
+            def W(lx, ly, z):
+                return np.array([cx, cy, 0.0]) + R @ np.array([lx, ly, 0.0]) + np.array([0, 0, z])
+
+            roof = [_quad_grid(W(-hx, -hy, h), W(hx, -hy, h), W(-hx, 0.0, ridge), 2, 1),
+                    _quad_grid(W(-hx, hy, h), W(-hx, 0.0, ridge), W(hx, hy, h), 1, 2)]
+            ends = [(np.array([W(sx, -hy, h), W(sx, hy, h), W(sx, 0.0, ridge)]), [(0, 1, 2)]) for sx in (-hx, hx)]
+            mb.add_faces(faces[:4] + ends, material=0)
+            mb.add_faces(roof, material=3)
+        else:
+            mb.add_faces(faces, material=0)
+        n_bld += 1
+
+    def inside_building(x, y, margin):
+        for (cx, cy, rad) in placed:
+            if np.hypot(x - cx, y - cy) < rad + margin:
+                return True
+        return False
+
+    rx = []
+    while len(rx) < 64:
+        x, y = rng.uniform(-100.0, 100.0, size=2)
+        if not inside_building(x, y, 1.0) and np.hypot(x, y) > 5.0:
+            rx.append((x, y, 1.5))
+    rx_all = np.array(rx)
+    # tilted billboard on the side of the plaza
+    Rb = _rot_z(0.6) @ _rot_x(np.radians(35.0))
+    mb.add_faces([_quad_grid(*(np.array([-30.0, 25.0, 6.0]) + Rb @ np.array(p, np.float64)
+                               for p in ([-4, 0, -2], [4, 0, -2], [-4, 0, 2])), 2, 1)], material=2)
+    # moving objects: cars on circles (yaw), a turning sign (pitch)
+    cars = []
+    for v in range(5):
+        r = rng.uniform(20.0, 60.0)
+        th0 = rng.uniform(0.0, 2 * np.pi)
+        w = rng.uniform(8.0, 16.0) / r * (1 if v % 2 == 0 else -1)
+        cars.append((r, th0, w))
+    dt = 0.1
+
+    def car_pose(r, th0, w, frame):
+        th = th0 + w * frame * dt
+        p = np.array([r * np.cos(th), r * np.sin(th), VEHICLE_CLEARANCE + VEHICLE[2] / 2])
+        return p, _rot_z(th + np.sign(w) * np.pi / 2)
+
+    for v, (r, th0, w) in enumerate(cars):
+        p, R = car_pose(r, th0, w, 0)
+        mb.add_faces(_box_faces(p, np.array(VEHICLE) / 2, R), material=2, obj=v)
+    sign_c = np.array([12.0, -8.0, 4.0])
+    mb.add_faces(_box_faces(sign_c, (3.0, 0.15, 1.0), np.eye(3)), material=2, obj=5)
+
+    def transforms(frame: int) -> np.ndarray:
+        xf = np.zeros((6, 3, 4), np.float64)
+        for v, (r, th0, w) in enumerate(cars):
+            p0, R0 = car_pose(r, th0, w, 0)
+            p1, R1 = car_pose(r, th0, w, frame)
+            M = R1 @ R0.T                       # x' = M (x - p0) + p1
+            xf[v, :, :3] = M
+            xf[v, :, 3] = p1 - M @ p0
+        M = _rot_x(1.5 * frame * dt)
+        xf[5, :, :3] = M
+        xf[5, :, 3] = sign_c - M @ sign_c
+        return xf.astype(np.float32)
+
+    return mb.finish("oblique_town", [CONCRETE, GROUND, METAL, (5.31, 0.48, 0.8)], tx, rx_all,
+                     rx_radius=1.0, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=[28e9],
+                     tx_power_w=5.0, n_frames=n_frames, dt=dt, transforms_fn=transforms)
+
+
 def random_sphere_dirs(n: int, seed: int) -> np.ndarray:
     """n random directions, uniform on the unit sphere (the paper's 'random sphere of rays')."""
     rng = np.random.default_rng(seed)
@@ -443,4 +614,5 @@ def random_sphere_dirs(n: int, seed: int) -> np.ndarray:
 CONFIGS = {
     "static_toy": static_toy,
     "dynamic_urban": dynamic_urban,
+    "oblique_town": oblique_town,
 }

@@ -1,0 +1,75 @@
+"""Helpers of the GPU parity tests: trace a frame through the C ABI and compare
+everything the oracle computes for it (per-ray hits and lengths, captures,
+candidate keys, refined paths, coherent and incoherent received power)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from paper_2112_07115_amd import dcem
+from tests import parity
+
+# fraction of receivers whose path sets must be certain on both sides (the
+# rest sit within the FP32 uncertainty of a capture or a hit)
+MIN_COMPARABLE = 0.95
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def radius_of(scene):
+    pts = np.concatenate([scene.vertices, scene.tx, scene.rx]).astype(np.float64)
+    return float(np.linalg.norm(pts, axis=1).max())
+
+
+def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=True, check_paths=True):
+    """Compare the context's last frame with the oracle's FrameResult `ofr`
+    (traced over the same n_rays directions).  Returns a dict of statistics."""
+    st = {}
+    if check_log:
+        g_tri, g_t, g_len = ctx.trace_log()
+        st = parity.compare_trace(g_tri, g_t, g_len, ofr.trace, scene.tri_face, radius=radius_of(scene))
+        log("  trace", st)
+    if check_captures:
+        g_caps = ctx.captures()
+        g_caps = g_caps[g_caps[:, 0] >= 0]
+        cs = parity.compare_captures(g_caps, ofr.trace, np.arange(n_rays), n_rays)
+        log("  captures", cs)
+    if check_paths:
+        gp = ctx.paths()
+        comparable, n_common = parity.compare_paths(gp, ofr, n_rays)
+        worst = parity.compare_power(out.p_coh, ofr.p_coh, comparable)
+        worst_inc = parity.compare_power(out.p_inc, ofr.p_inc, comparable)
+        log("  paths: gpu %d oracle %d common %d valid %d; comparable rx %d/%d; worst %.2e dB (P_inc %.2e dB)" %
+            (len(gp["keys"]), len(ofr.keys), n_common, int(ofr.paths.valid.sum()), comparable.sum(),
+             comparable.size, worst, worst_inc))
+        st["comparable"] = float(comparable.mean())
+        st["valid_paths"] = int(ofr.paths.valid.sum())
+    return st
+
+
+def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True,
+             los_always=True, atten_db_per_km=0.0, upload=True):
+    """Trace one FULL frame on both sides and compare everything; returns
+    (stats, GPU output, oracle FrameResult)."""
+    K = scene.max_reflections if K is None else K
+    log("case", scene.name, "frame", frame, "K", K, "rays", n_rays if dirs is None else len(dirs),
+        "atten", atten_db_per_km)
+    if upload:
+        ctx.scene_upload(scene)
+    out = dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=dirs, n_rays=n_rays, K=K,
+                                 record_trace_log=True, los_always=los_always, atten_db_per_km=atten_db_per_km)
+    if dirs is None:
+        g_dirs = ctx.ray_dirs()
+        o_dirs = O.fibonacci(n_rays or scene.n_rays)
+        assert np.array_equal(g_dirs, o_dirs), "Fibonacci directions differ"
+    else:
+        o_dirs = dirs
+    ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K, los_always=los_always,
+                  atten_db_per_km=atten_db_per_km)
+    st = compare_frame(ctx, scene, ofr, out, o_dirs.shape[0], check_captures=check_captures,
+                       check_paths=check_paths)
+    return st, out, ofr

@@ -56,15 +56,19 @@ def compare_trace(g_tri, g_t, g_len, o, tri_face, eps_rel=4e-6, radius=1.0):
                         (t, r, k, o_tri[t, r, k], o.flags[t, r, k], g_tri[t, r, k]))
     hit = check & (o_tri >= 0) & ok
     # FP32 distances against FP64: positions agree to eps_rel * (k+1) * (R + L)
-    tol = eps_rel * (ks[None, None, :] + 1) * (radius + np.where(np.isfinite(o.length), o.length, 0.0))
-    dt = np.abs(g_t.astype(np.float64) - o.t)
-    dl = np.abs(g_len.astype(np.float64) - o.length)
-    bad_t = hit & ((dt > tol) | (dl > tol))
+    # (misses carry infinities on both sides: compared only where the oracle hit,
+    # and a NaN on the GPU side fails the check)
+    o_t = np.where(hit, o.t, 0.0)
+    o_l = np.where(hit, o.length, 0.0)
+    tol = eps_rel * (ks[None, None, :] + 1) * (radius + o_l)
+    dt = np.abs(np.where(hit, g_t.astype(np.float64), 0.0) - o_t)
+    dl = np.abs(np.where(hit, g_len.astype(np.float64), 0.0) - o_l)
+    bad_t = hit & ~((dt <= tol) & (dl <= tol))
     if bad_t.any():
         for (t, r, k) in np.argwhere(bad_t)[:10]:
             msgs.append("tx %d ray %d bounce %d: t %.9g vs %.9g, len %.9g vs %.9g" %
                         (t, r, k, g_t[t, r, k], o.t[t, r, k], g_len[t, r, k], o.length[t, r, k]))
-    rel_len = np.where(hit, dl / np.maximum(o.length, 1e-30), 0.0)
+    rel_len = np.where(hit, dl / np.maximum(o_l, 1e-30), 0.0)
     stats = {
         "rays": int(np.prod(fu.shape)),
         "rays_fully_certain": int((fu == K1).sum()),
@@ -112,6 +116,36 @@ def compare_captures(g_rows, o, ray_index, n_rays):
     return {"gpu_captures": len(g), "oracle_certain": len(certain), "oracle_possible": len(possible)}
 
 
+C0 = 299792458.0
+
+
+def compare_path_attrs(gp: dict, i: int, op, j: int, eps_len=1e-9, eps_amp=1e-6, eps_dir=1e-9):
+    """Attributes of GPU path i against oracle path j (both FP64): validity,
+    length and delay within eps_len relative, departure and arrival unit
+    vectors within eps_dir, field within eps_amp relative.  Returns a list of
+    mismatch descriptions (NaN never passes)."""
+    bad = []
+    if bool(gp["valid"][i]) != bool(op.valid[j]):
+        return [("valid", bool(gp["valid"][i]), bool(op.valid[j]))]
+    if not op.valid[j]:
+        return bad
+    lo = op.length[j]
+    if not abs(gp["length"][i] - lo) <= eps_len * lo:
+        bad.append(("length", gp["length"][i], lo))
+    if not abs(gp["tau"][i] - op.tau[j]) <= eps_len * op.tau[j]:
+        bad.append(("tau", gp["tau"][i], op.tau[j]))
+    if not abs(op.tau[j] - lo / C0) <= 1e-12 * op.tau[j]:
+        bad.append(("oracle tau", op.tau[j], lo / C0))
+    for name in ("aod", "aoa"):
+        g, o = np.asarray(gp[name][i]), np.asarray(getattr(op, name)[j])
+        if not np.linalg.norm(g - o) <= eps_dir:
+            bad.append((name, g.tolist(), o.tolist()))
+    ao = op.amp[j]
+    if not np.linalg.norm(gp["amp"][i] - ao) <= eps_amp * np.linalg.norm(ao) + 1e-300:
+        bad.append(("amp", gp["amp"][i].tolist(), ao.tolist()))
+    return bad
+
+
 def compare_paths(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6, tol_db=0.01,
                   min_comparable=0.9):
     """Candidate keys, refined paths and per-receiver power of one frame."""
@@ -145,17 +179,8 @@ def compare_paths(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6, tol_db
         n_common += 1
         if ofr.paths.marginal[j]:
             continue
-        if bool(gp["valid"][i]) != bool(ofr.paths.valid[j]):
-            bad.append((k, "valid", bool(gp["valid"][i]), bool(ofr.paths.valid[j])))
-            continue
-        if not ofr.paths.valid[j]:
-            continue
-        lo = ofr.paths.length[j]
-        if abs(gp["length"][i] - lo) > eps_len * lo:
-            bad.append((k, "length", gp["length"][i], lo))
-        ao = ofr.paths.amp[j]
-        if np.linalg.norm(gp["amp"][i] - ao) > eps_amp * np.linalg.norm(ao) + 1e-300:
-            bad.append((k, "amp", gp["amp"][i].tolist(), ao.tolist()))
+        for b in compare_path_attrs(gp, i, ofr.paths, j, eps_len=eps_len, eps_amp=eps_amp):
+            bad.append((k,) + b)
     assert not bad, "path mismatches: %s" % bad[:5]
     # per-receiver power
     ntx, nrx = ofr.p_coh.shape[1], ofr.p_coh.shape[2]
@@ -173,6 +198,8 @@ def compare_paths(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6, tol_db
 
 
 def compare_power(g_pc, o_pc, comparable, tol_db=0.01):
+    """Largest |10 log10(g / o)| over the comparable receivers (every
+    frequency); fails above tol_db, and on a NaN."""
     both0 = (g_pc == 0) & (o_pc == 0)
     with np.errstate(divide="ignore", invalid="ignore"):
         db = np.abs(10 * np.log10(g_pc / o_pc))
@@ -180,4 +207,5 @@ def compare_power(g_pc, o_pc, comparable, tol_db=0.01):
     sel = np.broadcast_to(comparable, db.shape)
     worst = float(np.max(db[sel])) if sel.any() else 0.0
     assert worst <= tol_db, "power differs by %.4g dB on a comparable receiver" % worst
+    assert not np.isnan(g_pc).any(), "NaN power on the GPU"
     return worst

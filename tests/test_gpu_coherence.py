@@ -269,3 +269,31 @@ def test_coherent_frames_under_changing_pattern_and_materials():
             assert np.array_equal(a, b)
     full.close()
     coh.close()
+
+
+def test_unread_frame_then_coherent_frame_with_more_frequencies():
+    """A frame whose results are never read, followed by a coherent frame with
+    an extra frequency (a larger result block): the second frame must equal a
+    full re-trace of it bitwise."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    coh, full = dcem.Context(0), dcem.Context(0)
+    coh.scene_upload(s)
+    full.scene_upload(s)
+    for frame, freqs in [(0, [28e9]), (1, [28e9]), (2, [28e9, 60e9]), (3, [28e9, 60e9, 73e9])]:
+        log("frame", frame, "freqs", freqs)
+        xf = s.transforms(frame)
+        coh.set_object_transforms(xf)
+        coh.refit_bvh()
+        coh.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=freqs,
+                        tx_power_w=s.tx_power_w, mode=dcem.MODE_COHERENT, record_trace_log=True)
+        if frame in (0, 2):
+            continue   # left unread: the next trace call finishes it first
+        full.set_object_transforms(xf)
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s.tx, s.rx, s.rx_radius, n, max_reflections=s.max_reflections, freqs_hz=freqs,
+                         tx_power_w=s.tx_power_w, mode=dcem.MODE_FULL, record_trace_log=True)
+        assert_same(frame_outputs(full), frame_outputs(coh))
+        assert coh.stats()["coherent"] == 1
+    coh.close()
+    full.close()

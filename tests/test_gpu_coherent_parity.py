@@ -1,0 +1,79 @@
+"""GPU: coherent frames against the CPU oracle, element by element.
+
+A coherent frame (Sec. III, "Propagation path caching") reuses the cached rays
+whose segments cannot meet moved geometry, keeps their captures and re-traces
+only the others.  Here one context traces a moving scene frame after frame in
+COHERENT mode, so each checked frame is built on the caches of all frames
+before it; the oracle computes the same frame from scratch (it keeps nothing
+between frames).  Hits, lengths, captures, keys, refined paths and both
+received powers are compared as for full re-traces.
+"""
+import numpy as np
+import pytest
+
+from paper_2112_07115_amd import dcem, scenes
+from tests.gpu_frames import MIN_COMPARABLE, compare_frame, log
+from tests.test_gpu_parity import check_full_size_sampled
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.build()
+    return oracle
+
+
+@pytest.fixture()
+def ctx():
+    c = dcem.Context(0)
+    yield c
+    c.close()
+
+
+def coherent_run(ctx, O, s, dirs, frames, checks):
+    ctx.scene_upload(s)
+    n = s.n_rays if dirs is None else len(dirs)
+    reused = 0
+    for frame in frames:
+        out = dcem.trace_scene_frame(ctx, s, frame=frame, ray_dirs=dirs, mode=dcem.MODE_COHERENT,
+                                     record_trace_log=True)
+        st = ctx.stats()
+        if frame != frames[0]:
+            assert st["coherent"] == 1 and st["rays_traced"] < n
+            reused += st["rays_reused"]
+        if frame in checks:
+            log("case", s.name, "coherent frame", frame, "traced", st["rays_traced"], "of", n)
+            yield frame, out
+    assert reused > 0
+
+
+def test_coherent_urban_frames_against_oracle(ctx, O):
+    s = scenes.dynamic_urban()
+    dirs = scenes.random_sphere_dirs(65536, seed=7)
+    for frame, out in coherent_run(ctx, O, s, dirs, range(60), {1, 2, 30, 59}):
+        ofr = O.frame(s, frame_index=frame, dirs=dirs)
+        st = compare_frame(ctx, s, ofr, out, len(dirs))
+        assert st["rays_fully_certain"] > 0.99 * st["rays"]
+        assert st["comparable"] >= MIN_COMPARABLE
+
+
+def test_coherent_oblique_frames_against_oracle(ctx, O):
+    """Rotating objects: their cached rays are revalidated against rotated
+    boxes, and re-traced rays reflect off rotated planes."""
+    s = scenes.oblique_town()
+    dirs = scenes.random_sphere_dirs(1 << 17, seed=37)
+    for frame, out in coherent_run(ctx, O, s, dirs, range(20), {1, 10, 19}):
+        ofr = O.frame(s, frame_index=frame, dirs=dirs)
+        st = compare_frame(ctx, s, ofr, out, len(dirs))
+        assert st["comparable"] >= MIN_COMPARABLE
+
+
+@pytest.mark.timeout(600)
+def test_coherent_full_size_frame59_sampled(ctx, O):
+    """The bench's configuration (2^20 Fibonacci rays, K = 4): frames 0..59
+    traced coherently, frame 59 checked against the oracle on every 16th ray."""
+    s = scenes.dynamic_urban()
+    for frame, out in coherent_run(ctx, O, s, None, range(60), {59}):
+        check_full_size_sampled(ctx, O, s, frame)

@@ -57,3 +57,68 @@ def test_capture_capacity_overflow_is_reported():
     c.trace_frame(s.tx, s.rx, s.rx_radius, 100_000, max_reflections=2, los_always=True)
     c.received_power()
     c.close()
+
+
+def test_stack_overflow_is_reported():
+    """A traversal stack capped at one entry overflows on the urban tree: the
+    frame reports DCEM_E_CAPACITY (forced from the host; the traversals drop
+    what does not fit and exit normally); the full depth traces again."""
+    s = scenes.dynamic_urban(n_rays=4096)
+    c = dcem.Context(0)
+    c.scene_upload(s)
+    c.set_stack_limit(1)
+    c.trace_frame(s.tx, s.rx, s.rx_radius, 4096, max_reflections=4)
+    expect(dcem.E_CAPACITY, c.received_power)
+    # the group re-trace of a coherent frame too
+    c.set_object_transforms(s.transforms(1))
+    c.refit_bvh()
+    c.set_stack_limit(0)
+    c.trace_frame(s.tx, s.rx, s.rx_radius, 4096, max_reflections=4, keep_cache=True)
+    c.received_power()
+    c.set_object_transforms(s.transforms(2))
+    c.refit_bvh()
+    c.set_stack_limit(1)
+    c.trace_frame(s.tx, s.rx, s.rx_radius, 4096, max_reflections=4, mode=dcem.MODE_COHERENT)
+    expect(dcem.E_CAPACITY, c.received_power)
+    st = c.stats()   # the error is reported once
+    assert st["trace_kernel"] == 1 and st["coherent"] == 1
+    c.set_stack_limit(0)
+    c.trace_frame(s.tx, s.rx, s.rx_radius, 4096, max_reflections=4)
+    pc, _ = c.received_power()
+    fresh = dcem.Context(0)
+    fresh.scene_upload(s)
+    out = dcem.trace_scene_frame(fresh, s, frame=2, n_rays=4096)
+    assert np.array_equal(pc, out.p_coh)
+    expect(dcem.E_INVALID_ARG, c.set_stack_limit, -1)
+    fresh.close()
+    c.close()
+
+
+def test_nonfinite_transform_is_reported():
+    """Finite transform entries whose products overflow FP32, and (device
+    memory, not checked on the host) NaN entries: the transform kernel flags
+    the non-finite vertices and the next synchronising call reports
+    DCEM_E_INVALID_ARG; valid transforms then restore the scene."""
+    import torch
+    s = scenes.dynamic_urban(n_rays=4096)
+    c = dcem.Context(0)
+    c.scene_upload(s)
+    big = s.transforms(0).copy()
+    big[0, :, :3] *= np.float32(1e37)
+    c.set_object_transforms(big)
+    expect(dcem.E_INVALID_ARG, c.vertices)
+    bad = torch.tensor(s.transforms(0), device="cuda")
+    bad[1, 2, 3] = float("nan")
+    c.set_object_transforms(bad)
+    torch.cuda.synchronize()
+    expect(dcem.E_INVALID_ARG, c.vertices)
+    c.set_object_transforms(s.transforms(4))
+    c.refit_bvh()
+    c.trace_frame(s.tx, s.rx, s.rx_radius, 4096, max_reflections=4)
+    pc, _ = c.received_power()
+    fresh = dcem.Context(0)
+    fresh.scene_upload(s)
+    out = dcem.trace_scene_frame(fresh, s, frame=4, n_rays=4096)
+    assert np.array_equal(pc, out.p_coh)
+    fresh.close()
+    c.close()

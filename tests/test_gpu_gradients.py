@@ -244,6 +244,34 @@ def test_autograd_function_against_the_oracle(ctx, O):
     assert float(pt.grad) == pytest.approx(float((wt * o_pt).sum()), rel=1e-6)
 
 
+def test_autograd_with_device_parameters(ctx):
+    """Parameters on the GPU (a torch training loop's natural place): the
+    power comes back on their device and every gradient on its parameter's
+    device and dtype, equal to the CPU-parameter run."""
+    import torch
+    from paper_2112_07115_amd import autograd
+    s = toy_two_bands()
+    dirs = scenes.random_sphere_dirs(20_000, seed=3)
+    ctx.scene_upload(s)
+    res = []
+    for dev, dt in (("cpu", torch.float64), ("cuda", torch.float64), ("cuda", torch.float32)):
+        eps = torch.tensor(s.materials[:, 0], dtype=dt, device=dev, requires_grad=True)
+        sig = torch.tensor(s.materials[:, 1], dtype=dt, device=dev, requires_grad=True)
+        pt = torch.tensor(float(s.tx_power_w), dtype=dt, device=dev, requires_grad=True)
+        pat = torch.ones(dcem.PATTERN_TAPS, dtype=dt, device=dev, requires_grad=True)
+        p = autograd.received_power(ctx, s, eps, sig, pt, pat, ray_dirs=dirs, mode=dcem.MODE_FULL)
+        assert p.device.type == dev and p.dtype == torch.float64
+        (p * torch.arange(p.numel(), device=dev, dtype=torch.float64).reshape(p.shape)).sum().backward()
+        for t in (eps, sig, pt, pat):
+            assert t.grad.device.type == dev and t.grad.dtype == dt
+        res.append([p.detach().cpu().double()] + [t.grad.detach().cpu().double() for t in (eps, sig, pt, pat)])
+    assert torch.equal(res[0][0], res[1][0])   # the same frame
+    for a, b in zip(res[0][1:], res[1][1:]):   # contractions summed on another device
+        np.testing.assert_allclose(b.numpy(), a.numpy(), rtol=1e-12, atol=1e-12 * float(a.abs().max()))
+    for a, b in zip(res[0][1:], res[2][1:]):
+        np.testing.assert_allclose(b.numpy(), a.numpy(), rtol=1e-6, atol=1e-6 * float(a.abs().max()))
+
+
 def test_materials_fit_over_moving_frames(ctx, O):
     """Calibration over three frames of the urban scene (moving vehicles,
     65,536 random rays, K = 4): concrete and ground are fitted to the oracle's
