@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2112_07115_amd import dcem, scenes
-from tests.gpu_frames import MIN_COMPARABLE, compare_frame, log
+from tests.gpu_frames import assert_comparable, compare_frame, log
 from tests.test_gpu_parity import check_full_size_sampled
 
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def test_coherent_urban_frames_against_oracle(ctx, O):
         ofr = O.frame(s, frame_index=frame, dirs=dirs)
         st = compare_frame(ctx, s, ofr, out, len(dirs))
         assert st["rays_fully_certain"] > 0.99 * st["rays"]
-        assert st["comparable"] >= MIN_COMPARABLE
+        assert_comparable(st)
 
 
 def test_coherent_oblique_frames_against_oracle(ctx, O):
@@ -67,7 +67,7 @@ def test_coherent_oblique_frames_against_oracle(ctx, O):
     for frame, out in coherent_run(ctx, O, s, dirs, range(20), {1, 10, 19}):
         ofr = O.frame(s, frame_index=frame, dirs=dirs)
         st = compare_frame(ctx, s, ofr, out, len(dirs))
-        assert st["comparable"] >= MIN_COMPARABLE
+        assert_comparable(st)
 
 
 @pytest.mark.timeout(600)

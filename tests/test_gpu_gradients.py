@@ -60,7 +60,7 @@ def compare(ctx, O, s, frame, dirs, pattern=None):
     g_eps, g_sig, g_pt, g_pat = ctx.power_gradients()
     ofr, (o_eps, o_sig, o_pt, o_pat) = oracle_gradients(O, s, frame, dirs, pattern)
     comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
-    assert comparable.mean() >= 0.8
+    assert (~comparable).sum() <= max(1, int(0.05 * comparable.size))
     n_cmp = 0
     for t in range(s.tx.shape[0]):
         for r in range(s.rx.shape[0]):
@@ -185,7 +185,7 @@ def test_set_materials_applies_from_the_next_frame(ctx, O):
         c2.close()
     ofr = O.frame(sh, dirs=dirs)
     comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
-    assert comparable.mean() >= 0.8 and not np.array_equal(p1, p0)
+    assert (~comparable).sum() <= max(1, int(0.05 * comparable.size)) and not np.array_equal(p1, p0)
     np.testing.assert_allclose(p1[:, comparable], ofr.p_coh[:, comparable], rtol=1e-6, atol=0)
     with pytest.raises(dcem.DcemError):
         ctx.set_materials(hidden[:1])
@@ -234,7 +234,7 @@ def test_autograd_function_against_the_oracle(ctx, O):
     p = autograd.received_power(ctx, s, eps, sig, pt, pat, ray_dirs=dirs)
     ofr, (o_eps, o_sig, o_pt, o_pat) = oracle_gradients(O, s, 0, dirs, pattern=w)
     comparable, _ = parity.compare_paths(ctx.paths(), ofr, len(dirs))
-    assert comparable.mean() >= 0.8
+    assert (~comparable).sum() <= max(1, int(0.05 * comparable.size))
     wt = np.random.default_rng(2).uniform(0.5, 1.5, p.shape) * comparable[None]
     (p * torch.from_numpy(wt)).sum().backward()
     np.testing.assert_allclose(p.detach().numpy()[:, comparable], ofr.p_coh[:, comparable], rtol=1e-6)
