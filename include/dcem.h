@@ -42,6 +42,7 @@
 #ifndef DCEM_H
 #define DCEM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -173,9 +174,26 @@ typedef struct dcem_frame_stats {
   int32_t trace_kernel;      /* closest-hit traversal used: 0 one thread per ray, 1 one wavefront per ray */
 } dcem_frame_stats;
 
+/* Source of a context's device memory, so that a framework (a caching
+ * allocator such as torch's) owns it.  alloc returns `bytes` of device memory
+ * usable on `stream` (NULL on failure, reported as DCEM_E_OUT_OF_MEMORY);
+ * free returns a block alloc gave, with its size.  Both are called on the
+ * thread that makes the dcem call, only from dcem calls on the context, with
+ * the context's stream: memory freed there may be reused by later work on
+ * that stream only (stream-ordered reuse).  `user` is passed through. */
+typedef struct dcem_allocator {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+  void* user;
+} dcem_allocator;
+
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t;
- * NULL = the device's null stream). */
-dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream);
+ * NULL = the device's null stream).  allocator (nullable, copied): where every
+ * device buffer of the context comes from; NULL selects hipMalloc / hipFree.
+ * Pinned host staging (the per-frame result block, the gradients' read-back)
+ * is the library's own.  Errors: DCEM_E_INVALID_ARG for a bad device or an
+ * allocator without both functions. */
+dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream, const dcem_allocator* allocator);
 void dcem_destroy(dcem_ctx* ctx);
 /* Human-readable description of the last failure on ctx ("" if none). */
 const char* dcem_last_error(const dcem_ctx* ctx);

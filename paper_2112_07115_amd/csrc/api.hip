@@ -14,26 +14,56 @@ using namespace dcem;
 
 namespace dcem {
 
+namespace {
+
+hipError_t dev_free(const Allocator* al, void* p, size_t bytes) {
+  if (al->user) {
+    al->fn.free(p, bytes, al->stream, al->fn.user);
+    return hipSuccess;
+  }
+  return hipFree(p);
+}
+
+}  // namespace
+
+namespace {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+}  // namespace
+
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
+}
+
 hipError_t ensure(DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes && b.p) return hipSuccess;
+  if (!b.al) return hipErrorInvalidValue;   // a buffer outside dcem_ctx::buffers()
   if (b.p) {
-    hipError_t e = hipFree(b.p);
+    hipError_t e = dev_free(b.al, b.p, b.bytes);
     if (e != hipSuccess) return e;
     b.p = nullptr;
     b.bytes = 0;
   }
   size_t want = std::max<size_t>(bytes, 256);
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return e;
+  if (b.al->user) {
+    b.p = b.al->fn.alloc(want, b.al->stream, b.al->fn.user);
+    if (!b.p) return hipErrorOutOfMemory;
+  } else {
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return e;
+    }
   }
   b.bytes = want;
   return hipSuccess;
 }
 
 void release(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  if (b.p && b.al) (void)dev_free(b.al, b.p, b.bytes);
   b.p = nullptr;
   b.bytes = 0;
 }
@@ -242,8 +272,8 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   c->pcoh_dev = reinterpret_cast<double*>(b + kBlockHead);
   c->pinc_dev = c->pcoh_dev + n_pow;
   c->n_pow_cap = n_pow;
-  e = hipMemsetAsync(b, 0, c->frame_block.bytes, c->stream);
-  if (e != hipSuccess) return e;
+  fill_u32(reinterpret_cast<uint32_t*>(b), 0u, c->frame_block.bytes / 4, c->stream);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   e = hipMemcpyAsync(c->sah_dev, sah_keep, sizeof sah_keep, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
@@ -330,7 +360,8 @@ dcem_status sync_frame(dcem_ctx* c) {
     }
   }
   if (err) {
-    HIP_TRY(hipMemsetAsync(c->err_dev, 0, 4, c->stream), "clear error word");
+    fill_u32(c->err_dev, 0u, 1, c->stream);
+    HIP_TRY(hipGetLastError(), "clear error word");
     if (err & DCEM_ERR_NONFINITE) return fail(c, DCEM_E_INVALID_ARG, "non-finite vertex after a transform");
     return fail(c, DCEM_E_CAPACITY, "device capacity exceeded (%s%s)",
                 (err & DCEM_ERR_STACK) ? "traversal stack " : "", (err & DCEM_ERR_CAPTURES) ? "capture buffer" : "");
@@ -354,15 +385,22 @@ dcem_status finish_candidates(dcem_ctx* c) {
 
 extern "C" {
 
-dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream) {
+dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream, const dcem_allocator* allocator) {
   if (!out) return DCEM_E_INVALID_ARG;
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) return DCEM_E_INVALID_ARG;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DCEM_E_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return DCEM_E_DEVICE;
   dcem_ctx* c = new dcem_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->alloc.stream = c->stream;
+  if (allocator) {
+    c->alloc.fn = *allocator;
+    c->alloc.user = true;
+  }
+  for (DevBuf* b : c->buffers()) b->al = &c->alloc;
   if (ensure_frame_block(c, 1) != hipSuccess) {
     release(c->frame_block);
     if (c->host_block) (void)hipHostFree(c->host_block);
@@ -382,19 +420,7 @@ void dcem_destroy(dcem_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->ref_vertices, &c->vertices, &c->tris, &c->tri_face, &c->face_material, &c->face_object,
-                    &c->materials, &c->obj_range, &c->face_tri_off, &c->face_tris, &c->tri_slot, &c->face_slots, &c->face_ref_tri, &c->xf,
-                    &c->obj_box, &c->face_plane, &c->nodes, &c->leaf_slot, &c->leaf_tri, &c->leaf_parent,
-                    &c->refit_cnt, &c->morton, &c->sort_tmp, &c->sah_part, &c->scene_box, &c->dirs, &c->tx_pos,
-                    &c->rx_pos, &c->freqs, &c->ray_order, &c->rx_nodes, &c->rx_cols, &c->grad_buf, &c->face_log, &c->ray_state, &c->seg_o, &c->seg_d, &c->log_tri,
-                    &c->log_t, &c->log_len, &c->caps[0], &c->caps[1], &c->work_list, &c->invalid_flag,
-                    &c->frame_block, &c->cand_keys, &c->cand_perm, &c->cand_tmp, &c->uniq_idx,
-                    &c->first_ray, &c->path_valid, &c->path_len, &c->path_tau, &c->path_aod, &c->path_aoa,
-                    &c->path_amp, &c->pair_range, &c->sort_hist, &c->path_order,
-                    &c->path_faces, &c->path_pts, &c->node_range, &c->nodes4,
-                    &c->bvh2_of4, &c->map4, &c->depth_key, &c->tree_info, &c->tri4, &c->slot4, &c->cross,
-                    &c->face_build};
-  for (DevBuf* b : bufs) release(*b);
+  for (DevBuf* b : c->buffers()) release(*b);
   if (c->host_block) (void)hipHostFree(c->host_block);
   if (c->grad_host) (void)hipHostFree(c->grad_host);
   for (auto& e : c->ev)

@@ -602,7 +602,8 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   const int key_bits = key_words == 2 ? prefix_bits + fbits + 30 : 30;
   if ((e = radix_sort_perm(c, code, key_words, key_bits, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess)
     return e;
-  if ((e = hipMemsetAsync(c->refit_cnt.p, 0, sizeof(uint32_t) * ni, c->stream)) != hipSuccess) return e;
+  fill_u32(ptr<uint32_t>(c->refit_cnt), 0u, (size_t)ni, c->stream);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (nt == 1) {
     Node root{};
     root.c = make_int4(~0, ~0, -1, 0);

@@ -101,10 +101,21 @@ struct TraceConfig {
   std::vector<float> dirs_host;
 };
 
-// Growable device allocation owned by the context.
+// Where a context's device memory comes from: the caller's allocator
+// (dcem_allocator, e.g. a framework's caching allocator) or, without one,
+// hipMalloc / hipFree.  Allocations and frees are ordered on `stream`.
+struct Allocator {
+  dcem_allocator fn{};
+  bool user = false;
+  hipStream_t stream = nullptr;
+};
+
+// Growable device allocation owned by the context (its allocator set when the
+// context is created).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  const Allocator* al = nullptr;
 };
 
 }  // namespace dcem
@@ -113,6 +124,7 @@ struct dcem_ctx {
   int device = 0;
   int n_cus = 0;                                     // compute units of the device (0: not queried yet)
   hipStream_t stream = nullptr;
+  dcem::Allocator alloc;                             // source of every DevBuf below
   // A refit is enqueued lazily: by the next trace, in one launch with the
   // revalidation pass of a coherent frame (which does not read the tree), or
   // by the first call that reads the tree or the vertices.
@@ -226,6 +238,20 @@ struct dcem_ctx {
   int32_t record_log = 0;
   dcem_frame_stats stats{};
   hipEvent_t ev[9] = {};   // stage boundaries of a frame (timing on): see dcem_get_stats
+
+  // Every device buffer of the context (given its allocator at creation,
+  // released at destruction).
+  std::vector<dcem::DevBuf*> buffers() {
+    return {&ref_vertices, &vertices, &tris, &tri_face, &face_material, &face_object, &materials, &obj_range,
+            &face_tri_off, &face_tris, &face_ref_tri, &xf, &obj_box, &face_plane, &tri_slot, &face_slots,
+            &nodes, &leaf_slot, &leaf_tri, &leaf_parent, &refit_cnt, &morton, &sort_tmp, &sah_part, &scene_box,
+            &node_range, &nodes4, &bvh2_of4, &map4, &depth_key, &slot4, &cross, &tree_info, &tri4, &face_build,
+            &dirs, &ray_order, &tx_pos, &rx_pos, &freqs, &rx_nodes, &rx_cols, &grad_buf, &face_log, &ray_state,
+            &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag,
+            &frame_block, &cand_keys, &cand_perm, &cand_tmp, &uniq_idx, &first_ray, &path_valid, &path_len,
+            &path_tau, &path_aod, &path_aoa, &path_amp, &pair_range, &path_order, &path_faces, &path_pts,
+            &sort_hist};
+  }
 };
 
 namespace dcem {
@@ -249,6 +275,9 @@ enum : int {
 
 hipError_t ensure(DevBuf& b, size_t bytes);
 void release(DevBuf& b);
+// Set n 32-bit words at p to v on stream s (a kernel: no memset node, so the
+// work can be captured in a graph).
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 
 template <class T>
 T* ptr(DevBuf& b) { return static_cast<T*>(b.p); }

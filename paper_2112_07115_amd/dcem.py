@@ -55,9 +55,46 @@ class FrameStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(_P, ctypes.c_size_t, _P, _P)
+_FREE_FN = ctypes.CFUNCTYPE(None, _P, ctypes.c_size_t, _P, _P)
+
+
+class AllocatorDesc(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", _P)]
+
+
+class TorchAllocator:
+    """dcem_allocator backed by torch's CUDA caching allocator: the library's
+    device buffers are then torch's memory (counted by
+    torch.cuda.memory_allocated, reused through its pools)."""
+
+    def __init__(self, device: int):
+        import torch
+        self.device = device
+        self.live = {}
+
+        def alloc(nbytes, stream, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=int(stream or 0))
+            except Exception:   # reported by the library as out of memory
+                return None
+            self.live[p] = int(nbytes)
+            return p
+
+        def free(p, nbytes, stream, user):
+            if self.live.pop(p, None) is not None:
+                try:
+                    torch.cuda.caching_allocator_delete(p)
+                except Exception:   # interpreter shutdown: torch already torn down
+                    pass
+
+        self._alloc, self._free = _ALLOC_FN(alloc), _FREE_FN(free)   # kept alive with the context
+        self.desc = AllocatorDesc(self._alloc, self._free, None)
+
+
 # (name, restype, argtypes) of every exported entry point of include/dcem.h
 SIGNATURES = [
-    ("dcem_create", _I32, [ctypes.POINTER(_P), _I32, _P]),
+    ("dcem_create", _I32, [ctypes.POINTER(_P), _I32, _P, ctypes.POINTER(AllocatorDesc)]),
     ("dcem_destroy", None, [_P]),
     ("dcem_last_error", ctypes.c_char_p, [_P]),
     ("dcem_set_capture_capacity", _I32, [_P, _I64]),
@@ -136,16 +173,21 @@ def _host(a, dtype):
 
 
 class Context:
-    """One dcem context: a device, a HIP stream and the scene, BVH and ray cache on it."""
+    """One dcem context: a device, a HIP stream and the scene, BVH and ray cache on it.
 
-    def __init__(self, device: int = 0, stream=None):
+    allocator: "torch" (default when torch is loaded) takes every device
+    buffer from torch's caching allocator, None uses hipMalloc."""
+
+    def __init__(self, device: int = 0, stream=None, allocator="torch"):
         self.lib = load_library()
+        torch = sys.modules.get("torch")
         if stream is None:
             # follow torch's current stream when torch is in use; else the null stream
-            torch = sys.modules.get("torch")
             stream = torch.cuda.current_stream(device).cuda_stream if torch is not None else 0
+        self.allocator = TorchAllocator(device) if (allocator == "torch" and torch is not None) else None
         self.handle = _P()
-        st = self.lib.dcem_create(ctypes.byref(self.handle), device, _P(stream or None))
+        st = self.lib.dcem_create(ctypes.byref(self.handle), device, _P(stream or None),
+                                  ctypes.byref(self.allocator.desc) if self.allocator else None)
         if st != OK:
             raise DcemError(st, "dcem_create failed (device %d)" % device)
         self._keep = []

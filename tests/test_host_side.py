@@ -43,9 +43,11 @@ int main(void) {
   printf("dcem_scene_desc %zu\\n", sizeof(dcem_scene_desc));
   printf("dcem_trace_params %zu\\n", sizeof(dcem_trace_params));
   printf("dcem_frame_stats %zu\\n", sizeof(dcem_frame_stats));
+  printf("dcem_allocator %zu\\n", sizeof(dcem_allocator));
   P(dcem_scene_desc, mem_kind) P(dcem_scene_desc, n_objects) P(dcem_scene_desc, materials)
   P(dcem_trace_params, rx_radius) P(dcem_trace_params, n_rays) P(dcem_trace_params, tx_power_w)
   P(dcem_trace_params, mem_kind) P(dcem_frame_stats, sah_ratio) P(dcem_frame_stats, ms_reduce)
+  P(dcem_allocator, free) P(dcem_allocator, user)
   return 0;
 }
 """)
@@ -55,8 +57,9 @@ int main(void) {
     assert int(got["dcem_scene_desc"]) == ctypes.sizeof(dcem.SceneDesc)
     assert int(got["dcem_trace_params"]) == ctypes.sizeof(dcem.TraceParams)
     assert int(got["dcem_frame_stats"]) == ctypes.sizeof(dcem.FrameStats)
+    assert int(got["dcem_allocator"]) == ctypes.sizeof(dcem.AllocatorDesc)
     for key, cls in [("dcem_scene_desc", dcem.SceneDesc), ("dcem_trace_params", dcem.TraceParams),
-                     ("dcem_frame_stats", dcem.FrameStats)]:
+                     ("dcem_frame_stats", dcem.FrameStats), ("dcem_allocator", dcem.AllocatorDesc)]:
         for k, v in got.items():
             if k.startswith(key + "."):
                 assert getattr(cls, k.split(".")[1]).offset == int(v), k
