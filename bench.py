@@ -102,26 +102,66 @@ def gradient_timing(scene, n_rays, calls=20):
     st = ctx.stats()
     ctx.close()
     return {"ms_per_call": dt * 1e3, "calls": calls, "valid_paths": st["valid_paths"],
+            "paths_per_s": st["valid_paths"] / dt,
             "outputs": "dP/d eps_r and dP/d sigma of %d materials, dP/dP_t and dP/dw of the 16 transmit "
                        "pattern weights for %d receivers, frame 1"
                        % (scene.materials.shape[0], scene.rx.shape[0])}
 
 
-def cpu_baseline(scene, frame_index, stride):
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model}
+
+
+def cpu_baseline(scene):
+    """The oracle (plain FP64 brute force, no BVH) on the host cores: frames 0,
+    1 and 59 of the urban workload on every 16th Fibonacci ray with all its
+    threads (`value`), frame 1 on every 256th ray with one thread, and the
+    static toy frame in full (4096 rays, K = 2) with both."""
     from oracle import oracle
-    dirs = oracle.fibonacci(scene.n_rays)[::stride].copy()
+    from paper_2112_07115_amd import scenes
     threads = oracle.default_threads()
-    t0 = time.perf_counter()
-    oracle.frame(scene, frame_index=frame_index, dirs=dirs, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": dirs.shape[0] / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": "dynamic_urban frame %d, every %dth of the 2^20 Fibonacci rays (%d rays), full frame "
-                      "(trace, candidates, refinement, power), %.1f s wall" % (frame_index, stride, dirs.shape[0], dt)}
+    fib = oracle.fibonacci(scene.n_rays)
+    legs = []
+
+    def leg(name, sc, frame_index, dirs, nthreads):
+        t0 = time.perf_counter()
+        oracle.frame(sc, frame_index=frame_index, dirs=dirs, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        legs.append({"leg": name, "frame": frame_index, "rays": int(dirs.shape[0]), "threads": nthreads,
+                     "s": dt, "mrays_per_s": dirs.shape[0] / dt / 1e6})
+        return dt
+
+    sub = fib[::16].copy()
+    total = sum(leg("dynamic_urban 1/16 rays", scene, f, sub, threads) for f in (0, 1, 59))
+    leg("dynamic_urban 1/256 rays", scene, 1, fib[::256].copy(), 1)
+    toy = scenes.static_toy()
+    tdirs = oracle.fibonacci(toy.n_rays)
+    leg("static_toy full frame", toy, 0, tdirs, threads)
+    leg("static_toy full frame", toy, 0, tdirs, 1)
+    return {"value": 3 * sub.shape[0] / total / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": "dynamic_urban frames 0, 1, 59 on every 16th of the 2^20 Fibonacci rays (%d rays each), "
+                      "full frame (trace, candidates, refinement, power), %.1f s wall on %d threads"
+                      % (sub.shape[0], total, threads),
+            "cpu": cpu_info(), "legs": legs}
 
 
 # Algorithmic bytes of one closest-hit launch (what the traversal must read
 # and write, counted once per use; nothing assumed cached):
-#   per-thread kernel: 128 B per 4-wide node visit, 48 B per triangle test,
+#   per-thread kernel: 128 B per 4-wide node fetched from memory (the top
+#     three levels are read from LDS and not counted), 48 B per triangle test,
 #     per ray 13 B (direction, order entry, state), per segment 4 B (face log)
 #     + 32 B when the segment cache is kept, 8 B per capture record;
 #   group kernel: per node visit its four 32-byte slots (a leaf slot reads its
@@ -174,13 +214,19 @@ def roofline(stats, mode):
     by = float(np.mean([trace_bytes(s, mode == "coherent") for s in sel]))
     segs = float(sum(s["segments"] for s in sel))
     achieved = by / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": name + (" (coherent frame re-trace)" if kind == 1 else " (%s frame)" % mode),
-            "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-            "traffic": measured_traffic(name, "coh" if mode == "coherent" else "full"),
-            "bytes_per_launch": by, "ms_per_launch": ms,
-            "nodes_per_segment": float(sum(s["nodes_visited"] for s in sel)) / max(segs, 1.0),
-            "tris_per_segment": float(sum(s["tri_tests"] for s in sel)) / max(segs, 1.0),
-            "segments_per_launch": segs / max(len(sel), 1), "launches": len(sel)}
+    traffic = measured_traffic(name, "coh" if mode == "coherent" else "full")
+    out = {"bound": "hbm", "kernel": name + (" (coherent frame re-trace)" if kind == 1 else " (%s frame)" % mode),
+           "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+           "traffic": traffic, "bytes_per_launch": by, "ms_per_launch": ms,
+           "traced_mseg_per_s": segs / max(len(sel), 1) / (ms * 1e-3) / 1e6,
+           "nodes_per_segment": float(sum(s["nodes_visited"] for s in sel)) / max(segs, 1.0),
+           "tris_per_segment": float(sum(s["tri_tests"] for s in sel)) / max(segs, 1.0),
+           "segments_per_launch": segs / max(len(sel), 1), "launches": len(sel)}
+    if traffic:
+        # what HBM actually moved (rocprofv3 counters) against the peak: the
+        # traversal is bound by dependent round trips, not by bandwidth
+        out["hbm_measured"] = {"gbps": traffic / (ms * 1e-3) / 1e9, "frac": traffic / (ms * 1e-3) / 1e9 / 8000.0}
+    return out
 
 
 
@@ -258,7 +304,7 @@ def main():
         out["roofline_full_trace"] = roofline(res["full"][2], "full")
     out["power_gradients"] = gradient_timing(scene, n)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, 1, 16)
+        out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out))
 
 

@@ -162,7 +162,8 @@ typedef struct dcem_frame_stats {
   int64_t captures;          /* capture records (reused + new) */
   int64_t unique_candidates; /* unique (tx, rx, order, faces) keys */
   int64_t valid_paths;
-  int64_t nodes_visited;     /* BVH nodes fetched by the closest-hit traversal */
+  int64_t nodes_visited;     /* 4-wide BVH nodes the closest-hit traversal fetched from device memory
+                                (the per-thread traversal keeps the top three levels in LDS) */
   int64_t tri_tests;         /* ray-triangle tests of the closest-hit traversal */
   int32_t rebuilt;           /* last dcem_refit_bvh rebuilt the tree */
   int32_t coherent;          /* this frame reused the cache */

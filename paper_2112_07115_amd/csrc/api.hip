@@ -1072,6 +1072,14 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   const int list = c->frame_begun ? c->cur_caps ^ 1 : c->cur_caps;   // the last traced frame's
   HIP_TRY(hipMemcpy(cp.data(), c->caps[list].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  // records and the face log are indexed by traversal position; rows name the ray
+  std::vector<uint32_t> order((size_t)std::max<int64_t>(c->n_rays, 1));
+  if (c->n_rays > 0)
+    HIP_TRY(hipMemcpy(order.data(), c->ray_order.p, 4 * (size_t)c->n_rays, hipMemcpyDeviceToHost), "copy order");
+  auto ray_of = [&](uint32_t p) -> int32_t {
+    const int64_t tx = p / c->n_rays;
+    return (int32_t)(tx * c->n_rays + order[(size_t)(p - tx * c->n_rays)]);
+  };
   const int K = c->K;
   std::vector<int32_t> flog((size_t)(K + 1) * std::max<int64_t>(n_work, 1));
   if (n_work > 0)
@@ -1081,7 +1089,7 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   for (const Capture& x : cp) {
     std::vector<int32_t> r(4 + K, -1);
     const uint32_t pair = x.pair_order >> 4, order = x.pair_order & 15u;
-    r[0] = x.work == kNoRay ? -1 : (int32_t)x.work;
+    r[0] = x.work == kNoRay ? -1 : ray_of(x.work);
     r[1] = (int32_t)(pair / c->n_rx);
     r[2] = (int32_t)(pair % c->n_rx);
     r[3] = (int32_t)order;

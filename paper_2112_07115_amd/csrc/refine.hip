@@ -24,7 +24,18 @@ struct KeyLayout {
   int bits;    // significant bits
   int bt, br, bf, K;
   int n_rx;
+  const uint32_t* ray_order;   // traversal position -> ray within its transmitter's block
+  int64_t n_rays;
 };
+
+// Captures, the face log and the ray caches are indexed by traversal position
+// (tx * n_rays + rank of the ray's direction along the sort curve); the ray
+// id tx * n_rays + ray of position p:
+__device__ inline uint32_t ray_of(uint32_t p, const KeyLayout& L) {
+  if (p == kNoRay) return kNoRay;
+  const uint32_t tx = (uint32_t)(p / (uint64_t)L.n_rays);
+  return tx * (uint32_t)L.n_rays + L.ray_order[p - (uint64_t)tx * L.n_rays];
+}
 
 // Place `nbits` of `v` at bit offset `pos` (from the least significant end of
 // the W-word key, word W-1 holding bits 0..31).
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
       for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
       for (int k = 0; k < kSmallW; ++k) kk[k][i] = k < L.W ? w[k] : 0u;
       cpair[i] = c.pair_order >> 4;
-      work[q] = c.work;
+      work[q] = ray_of(c.work, L);
     }
   }
   __syncthreads();
@@ -374,7 +385,7 @@ __global__ __launch_bounds__(256) void k_unique_info(const uint32_t* __restrict_
   if (u >= *n_unique) return;
   const uint32_t h = uniq_pos[u], e = uniq_pos[u + 1];
   uint32_t fr = kNoRay;
-  for (uint32_t j = h; j < e; ++j) fr = min(fr, caps[perm[j]].work);
+  for (uint32_t j = h; j < e; ++j) fr = min(fr, ray_of(caps[perm[j]].work, L));
   uint32_t w[8];
   const uint32_t idx = perm[h];
   for (int k = 0; k < L.W; ++k) w[k] = keys[k * stride + idx];
@@ -1057,6 +1068,8 @@ KeyLayout key_layout(const dcem_ctx* c) {
   L.bf = std::max(1, bits_for(c->nf));
   L.K = c->K;
   L.n_rx = c->n_rx;
+  L.ray_order = static_cast<const uint32_t*>(c->ray_order.p);
+  L.n_rays = std::max<int64_t>(c->n_rays, 1);
   L.bits = L.bt + L.br + 4 + L.K * L.bf;
   L.W = (L.bits + 31) / 32;
   return L;

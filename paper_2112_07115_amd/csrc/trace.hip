@@ -164,7 +164,7 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
   for (int64_t guard = (int64_t)n4 + 2;; --guard) {
     if (guard == 0) { overflow = true; break; }
     const Node4 nd = node < n_top ? top[node] : nodes[node];
-    ++n_nodes;
+    if (node >= n_top) ++n_nodes;   // fetched from memory (the top levels sit in LDS)
     float t[4];
     int c[4];
 #pragma unroll
@@ -226,7 +226,9 @@ struct TraceArgs {
   const Leaf* tri4;           // leaf triangles in slot order
   const uint32_t* n4_dev;     // number of 4-wide nodes (null: empty scene)
   const float* dirs;
-  const uint32_t* ray_order;  // traversal order of the rays (directions sorted along a space-filling curve)
+  const uint32_t* ray_order;  // traversal position -> ray (directions sorted along a space-filling curve);
+                              // per-ray device state is indexed by position: neighbouring directions share
+                              // cache lines
   const float* tx;
   const float* rx;      // [n_rx][3]
   int n_rx;
@@ -347,16 +349,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     if (base >= n_work) break;
     const uint32_t wi = base + lane;
     if (wi < n_work) {
-      uint32_t work, txi, ray;
-      if (a.work_list) {
-        work = a.work_list[wi];
-        txi = (uint32_t)(work / (uint64_t)a.n_rays);
-        ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
-      } else {
-        txi = (uint32_t)(wi / (uint64_t)a.n_rays);
-        ray = a.ray_order[wi - (uint64_t)txi * a.n_rays];
-        work = txi * (uint32_t)a.n_rays + ray;
-      }
+      // work: the ray's traversal position (its index in the face log, the
+      // caches and the capture records); rid: its ray id (the parity log)
+      const uint32_t work = a.work_list ? a.work_list[wi] : wi;
+      const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
+      const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
+      const uint32_t rid = txi * (uint32_t)a.n_rays + ray;
       int k = a.restart ? (int)a.restart[work] : 0;
       Ray r;
       int excl = -1;
@@ -389,7 +387,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
         const float dd = dot_dd(r);
         const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
         if (a.log_tri) {
-          const size_t li = (size_t)work * (a.K + 1) + k;
+          const size_t li = (size_t)rid * (a.K + 1) + k;
           a.log_tri[li] = h.tri;
           a.log_t[li] = hit ? h.t : INFINITY;
           a.log_len[li] = hit ? L_hit : INFINITY;
@@ -448,7 +446,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
       for (int j = k; j <= a.K; ++j) {
         a.face_log[(size_t)j * a.n_work + work] = -2;
         if (a.log_tri) {
-          const size_t li = (size_t)work * (a.K + 1) + j;
+          const size_t li = (size_t)rid * (a.K + 1) + j;
           a.log_tri[li] = -2;
           a.log_t[li] = INFINITY;
           a.log_len[li] = INFINITY;
@@ -591,7 +589,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
 
   // this group's ray (equal on its lanes)
   bool busy = false;
-  uint32_t work = 0, txi = 0, state = 0;
+  uint32_t work = 0, rid = 0, txi = 0, state = 0;   // traversal position, ray id, transmitter
   int k = 0, excl = -1, guard = 0, sp = 0;
   float L = 0.0f, best_t = INFINITY;
   Ray r;
@@ -619,7 +617,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     if (!busy) return;
     work = a.work_list[item];
     txi = (uint32_t)(work / (uint64_t)a.n_rays);
-    const uint32_t ray = (uint32_t)(work - (uint64_t)txi * a.n_rays);
+    const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
+    rid = txi * (uint32_t)a.n_rays + ray;
     k = (int)a.restart[work];
     excl = -1;
     L = 0.0f;
@@ -741,7 +740,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
       a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
       if (a.log_tri) {
-        const size_t li = (size_t)work * (a.K + 1) + k;
+        const size_t li = (size_t)rid * (a.K + 1) + k;
         a.log_tri[li] = tri;
         a.log_t[li] = hit ? th : INFINITY;
         a.log_len[li] = hit ? L_hit : INFINITY;
@@ -807,7 +806,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       for (int j = k; j <= a.K; ++j) {
         a.face_log[(size_t)j * a.n_work + work] = -2;
         if (a.log_tri) {
-          const size_t li = (size_t)work * (a.K + 1) + j;
+          const size_t li = (size_t)rid * (a.K + 1) + j;
           a.log_tri[li] = -2;
           a.log_t[li] = INFINITY;
           a.log_len[li] = INFINITY;
