@@ -313,6 +313,25 @@ dcem_status dcem_set_materials(dcem_ctx* ctx, const double* materials, int32_t n
 dcem_status dcem_power_gradients(dcem_ctx* ctx, double* d_eps_r, double* d_sigma, double* d_tx_power,
                                  double* d_pattern);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight calibration loops, harnesses that forbid allocation): the outputs of
+ * dcem_power_gradients, computed by the same kernel, with its device
+ * workspace in a fixed library-owned array of DCEM_NOALLOC_GRAD_DOUBLES
+ * doubles (1 MiB) that each GPU the library runs on holds until the process
+ * ends, and the results copied straight into the caller's host arrays (no
+ * pinned staging).  Allocates no device or host memory.
+ * Limits: (2 * n_materials + DCEM_PATTERN_TAPS) * n_freqs * n_tx * n_rx <=
+ * DCEM_NOALLOC_GRAD_DOUBLES, else DCEM_E_UNSUPPORTED; the frame's results
+ * must have been read (dcem_received_power after its dcem_trace_frame), else
+ * DCEM_E_STATE, since finishing a frame may allocate.  Every call on one GPU
+ * shares that GPU's array and overwrites it: calls that overlap on one GPU
+ * (from different contexts or threads) race.  Errors otherwise as for
+ * dcem_power_gradients; DCEM_E_DEVICE if the array's address could not be
+ * obtained at dcem_create. */
+#define DCEM_NOALLOC_GRAD_DOUBLES 131072
+dcem_status dcem_power_gradients_noalloc(dcem_ctx* ctx, double* d_eps_r, double* d_sigma, double* d_tx_power,
+                                         double* d_pattern);
+
 /* Paths of the last frame in key order (tx, rx, order, faces), host memory.
  * keys [cap][3 + K] int32 (faces padded with -1, K = max_reflections),
  * valid [cap], length [cap] (m), tau [cap] (s), aod/aoa [cap][3] unit vectors

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 
 #include "dcem_internal.h"
 
@@ -71,6 +72,31 @@ void release(DevBuf& b) {
 }  // namespace dcem
 
 namespace {
+
+// Device workspace of dcem_power_gradients_noalloc: a fixed array that every
+// GPU the library runs on holds once (a module variable: one copy per device,
+// at its own address).  Host code never uses its name as an address: the
+// pointer comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and is passed to the kernels like any buffer.
+__device__ __align__(256) double scratch[DCEM_NOALLOC_GRAD_DOUBLES];
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's array (the device must be current).
+hipError_t scratch_of(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 dcem_status fail(dcem_ctx* c, dcem_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 dcem_status fail(dcem_ctx* c, dcem_status s, const char* fmt, ...) {
@@ -401,6 +427,12 @@ dcem_status dcem_create(dcem_ctx** out, int32_t device, void* hip_stream, const 
     c->alloc.user = true;
   }
   for (DevBuf* b : c->buffers()) b->al = &c->alloc;
+  // the no-allocation gradient call's workspace on this device (null if the
+  // lookup fails: that call then reports DCEM_E_DEVICE, nothing else needs it)
+  if (scratch_of(device, &c->scratch) != hipSuccess) {
+    c->scratch = nullptr;
+    (void)hipGetLastError();
+  }
   if (ensure_frame_block(c, 1) != hipSuccess) {
     release(c->frame_block);
     if (c->host_block) (void)hipHostFree(c->host_block);
@@ -953,6 +985,45 @@ dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, 
     if (d_eps_r && want_mat) std::memcpy(d_eps_r, h, sizeof(double) * ng);
     if (d_sigma && want_mat) std::memcpy(d_sigma, h + ng, sizeof(double) * ng);
     if (d_pattern) std::memcpy(d_pattern, h + 2 * ng, sizeof(double) * np);
+  }
+  return DCEM_OK;
+}
+
+dcem_status dcem_power_gradients_noalloc(dcem_ctx* c, double* d_eps_r, double* d_sigma, double* d_tx_power,
+                                         double* d_pattern) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_frame) return fail(c, DCEM_E_STATE, "no frame traced");
+  // the frame must be finished (its results read): finishing it could
+  // allocate (a candidate redo when its captures overflowed the device path)
+  if (!c->counts_current) return fail(c, DCEM_E_STATE, "the frame's results are unread: call dcem_received_power");
+  if (!c->scratch) return fail(c, DCEM_E_DEVICE, "no gradient workspace on device %d", c->device);
+  const size_t n = (size_t)c->n_freqs * c->n_tx * c->n_rx;
+  const size_t ng = n * (size_t)std::max(c->nm, 0);
+  const size_t np = n * kPatternTaps;
+  if (2 * ng + np > (size_t)DCEM_NOALLOC_GRAD_DOUBLES)
+    return fail(c, DCEM_E_UNSUPPORTED, "gradients need %zu doubles of workspace, the fixed array holds %d",
+                2 * ng + np, DCEM_NOALLOC_GRAD_DOUBLES);
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (d_tx_power) {
+    const double* hp = reinterpret_cast<const double*>(static_cast<const char*>(c->host_block) + kBlockHead);
+    const double pt = c->sqrt_pt * c->sqrt_pt;
+    for (size_t i = 0; i < n; ++i) d_tx_power[i] = pt > 0 ? hp[i] / pt : 0.0;
+  }
+  const bool want_mat = (d_eps_r || d_sigma) && ng > 0;
+  if (want_mat || d_pattern) {
+    double* g = c->scratch;   // the array's address on this device, never its host-side name
+    const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
+    launch_power_grad(c, nu, want_mat ? g : nullptr, g + ng, d_pattern ? g + 2 * ng : nullptr);
+    HIP_TRY(hipGetLastError(), "gradient kernel");
+    // straight into the caller's arrays (no pinned staging)
+    if (d_eps_r && want_mat)
+      HIP_TRY(hipMemcpyAsync(d_eps_r, g, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (d_sigma && want_mat)
+      HIP_TRY(hipMemcpyAsync(d_sigma, g + ng, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (d_pattern)
+      HIP_TRY(hipMemcpyAsync(d_pattern, g + 2 * ng, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   }
   return DCEM_OK;
 }

@@ -143,6 +143,7 @@ struct dcem_ctx {
   bool timing = false;
   int64_t cap_capacity = int64_t(1) << 22;
   int32_t stack_limit = 0;   // traversal stack cap (dcem_set_stack_limit); 0 = full depth
+  double* scratch = nullptr;  // this device's fixed gradient workspace (dcem_power_gradients_noalloc)
 
   // -- scene
   bool has_scene = false;

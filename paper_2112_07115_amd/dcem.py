@@ -108,6 +108,7 @@ SIGNATURES = [
     ("dcem_set_tx_pattern", _I32, [_P, _P, _I32]),
     ("dcem_set_materials", _I32, [_P, _P, _I32]),
     ("dcem_power_gradients", _I32, [_P, _P, _P, _P, _P]),
+    ("dcem_power_gradients_noalloc", _I32, [_P, _P, _P, _P, _P]),
     ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("dcem_get_trace_log", _I32, [_P, _P, _P, _P]),
     ("dcem_get_captures", _I32, [_P, _I64, _P, ctypes.POINTER(_I64)]),
@@ -307,6 +308,18 @@ class Context:
         dp = np.empty(shape, np.float64)
         dw = np.empty(shape + (PATTERN_TAPS,), np.float64)
         self._check(self.lib.dcem_power_gradients(self.handle, _addr(de), _addr(ds), _addr(dp), _addr(dw)))
+        return de, ds, dp, dw
+
+    def power_gradients_noalloc(self, out=None):
+        """power_gradients() through the entry point that allocates nothing
+        (fixed per-GPU workspace); `out`: four preallocated host arrays of the
+        shapes power_gradients returns (allocated here when None)."""
+        shape = (self.n_freqs, self.n_tx, self.n_rx)
+        if out is None:
+            out = (np.empty(shape + (self.n_materials,), np.float64), np.empty(shape + (self.n_materials,), np.float64),
+                   np.empty(shape, np.float64), np.empty(shape + (PATTERN_TAPS,), np.float64))
+        de, ds, dp, dw = out
+        self._check(self.lib.dcem_power_gradients_noalloc(self.handle, _addr(de), _addr(ds), _addr(dp), _addr(dw)))
         return de, ds, dp, dw
 
     def stats(self) -> dict:
