@@ -261,10 +261,20 @@ def _street_centre(k: int) -> float:
     return -HALF + STREET / 2.0 + k * (BLOCK + STREET)
 
 
+# Building material classes of the eight-class urban variant (the
+# calibration workload): (eps_r, sigma [S/m]) starting values of plausible
+# facade materials; the classes are what a fit tells apart.
+FACADE_CLASSES = [(5.31, 0.48), (3.75, 0.04), (6.5, 0.3), (4.0, 0.1), (2.5, 0.01), (7.0, 0.2)]
+
+
 def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
                   n_rays: int = 1 << 20, max_reflections: int = 4,
-                  n_frames: int = 60) -> Scene:
+                  n_frames: int = 60, material_classes: int = 3) -> Scene:
     """Dynamic urban scene: 8x8 Manhattan grid, moving metal vehicles, 60 frames at 10 Hz.
+
+    material_classes = 3: concrete buildings, ground, metal vehicles
+    (materials 0, 1, 2).  material_classes = 8: six facade classes for the
+    buildings (block (i, j) gets class (i + 2 j) mod 6), ground 6, vehicles 7.
 
     Blocks of 40 m separated by 15 m streets (border streets included, 455 m
     across, centred on the origin) on a [-260, 260]^2 ground plane.  One
@@ -283,12 +293,15 @@ def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
     rng = np.random.default_rng(seed)
     heights = rng.uniform(10.0, 60.0, size=(GRID_BLOCKS, GRID_BLOCKS))
     mb = _MeshBuilder()
-    mb.add_ground(260.0, material=1)
+    assert material_classes in (3, 8)
+    eight = material_classes == 8
+    mat_ground, mat_vehicle = (6, 7) if eight else (1, 2)
+    mb.add_ground(260.0, material=mat_ground)
     for i in range(GRID_BLOCKS):
         for j in range(GRID_BLOCKS):
             x0, y0 = _block_origin(i), _block_origin(j)
             mb.add_box((x0, y0, 0.0), (x0 + BLOCK, y0 + BLOCK, heights[i, j]),
-                       (3, 3, 6), material=0)
+                       (3, 3, 6), material=(i + 2 * j) % 6 if eight else 0)
     # rooftop base station: a 2 m mast (the paper's transmitter height) 0.5 m
     # inside the roof corner of block (3, 3) that faces the central intersection
     corner = _block_origin(3) + BLOCK - 0.5
@@ -321,7 +334,7 @@ def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
             lo = (lane_c - W / 2, u - L / 2, VEHICLE_CLEARANCE)
             hi = (lane_c + W / 2, u + L / 2, VEHICLE_CLEARANCE + H)
             cells = (5, 12, 4)
-        mb.add_box(lo, hi, cells, material=2, obj=v)
+        mb.add_box(lo, hi, cells, material=mat_vehicle, obj=v)
 
     centres = np.array([_street_centre(k) for k in range(GRID_BLOCKS + 1)])
     rx = []
@@ -349,7 +362,9 @@ def dynamic_urban(seed: int = 2, n_vehicles: int = 40, n_rx: int = 256,
             xf[v, axis, 3] = np.float32(p - u)
         return xf
 
-    return mb.finish("dynamic_urban", [CONCRETE, GROUND, METAL], tx, np.array(rx),
+    mats = ([(e, sg, float("nan")) for e, sg in FACADE_CLASSES] + [GROUND, METAL]) if eight \
+        else [CONCRETE, GROUND, METAL]
+    return mb.finish("dynamic_urban", mats, tx, np.array(rx),
                      rx_radius=0.5, n_rays=n_rays, max_reflections=max_reflections,
                      freqs_hz=[28e9], tx_power_w=5.0, n_frames=n_frames, dt=dt,
                      transforms_fn=transforms)
