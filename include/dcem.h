@@ -202,8 +202,8 @@ const char* dcem_last_error(const dcem_ctx* ctx);
  * DCEM_ERR_CAPTURES. */
 dcem_status dcem_set_capture_capacity(dcem_ctx* ctx, int64_t max_captures);
 /* Cap the closest-hit traversal stacks at `entries` entries per query (0
- * restores the full depth: 48 per ray in the per-thread traversal, 128 in the
- * group traversal; larger values are clamped to those).  Results do not
+ * restores the full depth: 64 per ray in the per-thread traversal, the first
+ * 32 in LDS, 128 in the group traversal; larger values are clamped to those).  Results do not
  * change unless a stack overflows; an overflow drops the entries that do not
  * fit, sets DCEM_ERR_STACK, and is reported as DCEM_E_CAPACITY by the next
  * synchronising call (that frame's outputs are undefined).  The full depth
@@ -369,6 +369,64 @@ dcem_status dcem_get_vertices(dcem_ctx* ctx, float* out);
 dcem_status dcem_get_ray_dirs(dcem_ctx* ctx, float* out);
 
 dcem_status dcem_get_stats(dcem_ctx* ctx, dcem_frame_stats* out);
+
+/* ---- Batches: one frame of many scenes at once.
+ * Each scene is a context holding its own scene, BVH and caches; a batch
+ * traces one frame of every context (the frame algorithm of Sec. III per
+ * scene, as dcem_trace_frame) with ONE persistent closest-hit launch for the
+ * full traces of all of them: a queue of (scene, chunk of work items) that
+ * wavefronts drain, so scenes of very different sizes (ragged triangle
+ * counts, transmitters, ray budgets, reflection limits, receivers, bands)
+ * keep every compute unit busy to the end.  Contexts in coherent mode trace
+ * their own (short) re-trace lists.  Results are per context, read with
+ * dcem_received_power / dcem_get_* on each, and equal those of
+ * dcem_trace_frame bitwise. */
+typedef struct dcem_batch dcem_batch;
+
+/* Launch shape and tuning state of a batch. */
+typedef struct dcem_batch_info {
+  int32_t n_ctx;
+  int32_t lds_stack;       /* per-thread traversal stack entries kept in LDS (16 or 32; the rest in device memory) */
+  int32_t blocks_per_cu;   /* persistent blocks of 128 threads per compute unit */
+  int32_t chunk;           /* work items per queue chunk */
+  int32_t tuned;           /* the shape comes from dcem_batch_tune */
+  int32_t graph_frames;    /* frames launched as one captured HIP graph */
+  float ms_trace_tuned;    /* batched trace time of the tuned shape (ms, HIP events) */
+} dcem_batch_info;
+
+/* A batch over ctxs[0..n) (not copied beyond the pointers; each context must
+ * outlive the batch).  All contexts must use one device and one HIP stream.
+ * Errors: DCEM_E_INVALID_ARG (null, n < 1, mixed devices or streams, a
+ * context twice), DCEM_E_DEVICE. */
+dcem_status dcem_batch_create(dcem_batch** out, dcem_ctx* const* ctxs, int32_t n);
+void dcem_batch_destroy(dcem_batch* batch);
+
+/* enabled = 1: each batched frame whose device work needs no host round trip
+ * (every context on the one-workgroup candidate path, no stage timing) is
+ * captured from the stream as one HIP graph and launched with one call; the
+ * executable graph is updated in place from frame to frame.  Needs a
+ * non-null stream.  Default 0 (direct launches). */
+dcem_status dcem_batch_set_graph(dcem_batch* batch, int32_t enabled);
+
+/* Fix the launch shape (see dcem_batch_info): lds_stack 16 or 32,
+ * blocks_per_cu 1..32, chunk a positive multiple of 64 up to 2^20.  Results
+ * never depend on it.  Default 32, 8, 256. */
+dcem_status dcem_batch_set_shape(dcem_batch* batch, int32_t lds_stack, int32_t blocks_per_cu, int32_t chunk);
+
+/* Trace one frame of every context of the batch; params[j] (as for
+ * dcem_trace_frame) for context j.  Asynchronous like dcem_trace_frame;
+ * errors are those of dcem_trace_frame, reported on the context concerned. */
+dcem_status dcem_batch_trace(dcem_batch* batch, const dcem_trace_params* params);
+
+/* Autotuner of the batched trace: traces the batch's frame `repeats` times for
+ * each candidate shape (LDS stack 32 with 4, 6 or 8 blocks per compute unit,
+ * LDS stack 16 with 4 to 16 blocks, chunk 256; then chunks 64 and 1024 at the
+ * best of those), times the batched launch with HIP events, and keeps the
+ * fastest shape.  The contexts hold the last traced frame (equal to every
+ * other one).  Synchronises. */
+dcem_status dcem_batch_tune(dcem_batch* batch, const dcem_trace_params* params, int32_t repeats);
+
+dcem_status dcem_batch_get_info(const dcem_batch* batch, dcem_batch_info* out);
 
 #ifdef __cplusplus
 }

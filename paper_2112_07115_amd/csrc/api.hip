@@ -703,7 +703,26 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   return DCEM_OK;
 }
 
-dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
+}  // extern "C"
+
+namespace {
+
+// What the device part of a frame does, decided by its host part.
+struct FramePlan {
+  bool coherent = false;    // reuse the cached rays, re-trace the listed ones
+  bool keep_cache = false;  // store the segment cache for the next coherent frame
+  bool small = false;       // one-workgroup candidate de-duplication
+  bool ahead = false;       // the frame's start and revalidation are already enqueued
+  bool los = true;
+  int64_t n_work = 0;       // n_tx * n_rays
+  int64_t expected = 0;     // work items the trace is sized for
+  uint32_t n_prev = 0;      // captures of the previous frame (kept by a coherent frame)
+};
+
+// Host part of a frame: argument checks, the unread previous frame, the
+// configuration, uploads and buffers.  Enqueues nothing of the frame itself
+// beyond the uploads (and, when the rays changed, their directions and order).
+dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan) {
   if (!c) return DCEM_E_INVALID_ARG;
   c->err.clear();
   if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
@@ -833,19 +852,29 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   // counts of the previous frame (read above): its capture list (reused by a
   // coherent frame), its re-trace count (sizes the persistent grid) and its
   // capture count (picks the de-duplication path)
-  const uint32_t n_prev = (uint32_t)c->n_caps_host;
-  const int64_t expected_work = (c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work;
-  const bool small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
-  // -- schedule (no host round trip on the small path)
+  plan.n_prev = (uint32_t)c->n_caps_host;
+  plan.n_work = n_work;
+  plan.expected = coherent ? ((c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work) : n_work;
+  plan.small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
+  plan.coherent = coherent;
+  plan.keep_cache = keep_cache;
+  plan.los = p->los_always != 0;
   // a revalidation enqueued ahead (go_ahead) serves a coherent frame with the
   // same configuration, as long as the result block stayed in place
-  const bool ahead = c->revalidated_ahead && coherent && (p->los_always != 0) == c->last_los &&
-                     c->frame_block.p == block_before;
-  if (!ahead) {
+  plan.ahead = c->revalidated_ahead && coherent && plan.los == c->last_los && c->frame_block.p == block_before;
+  if (plan.small) HIP_TRY(prepare_small_candidates(c), "alloc candidates");
+  HIP_TRY(prepare_trace(c), "alloc traversal stack");
+  return DCEM_OK;
+}
+
+// Device part of a frame up to the trace: the frame's start (counters, line
+// of sight records), the pending refit, the revalidation pass.
+dcem_status frame_front(dcem_ctx* c, const FramePlan& plan) {
+  if (!plan.ahead) {
     ev_record(c, 0);
     if (!c->frame_begun) c->cur_caps ^= 1;
-    launch_frame_begin(c, p->los_always != 0);
-    if (coherent && c->refit_pending) {
+    launch_frame_begin(c, plan.los);
+    if (plan.coherent && c->refit_pending) {
       // the revalidation does not read the tree: one launch with the refit
       c->refit_pending = false;
       ev_record(c, 6);
@@ -853,20 +882,34 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
       ev_record(c, 7);
     } else {
       HIP_TRY(flush_refit(c), "refit");
-      if (coherent) launch_coherence(c);
+      if (plan.coherent) launch_coherence(c);
     }
     c->list_clear = false;
     ev_record(c, 1);
   }
   c->frame_begun = false;
   c->revalidated_ahead = false;
-  c->last_los = p->los_always != 0;
+  c->last_los = plan.los;
+  HIP_TRY(hipGetLastError(), "frame start");
+  return DCEM_OK;
+}
+
+// The frame's own closest-hit launch.
+dcem_status frame_trace(dcem_ctx* c, const FramePlan& plan) {
   ev_record(c, 8);
-  c->last_trace_kernel =
-      n_work > 0 ? launch_trace(c, !coherent, keep_cache, coherent ? expected_work : n_work, n_prev) : 0;
+  const int traversal =
+      plan.n_work > 0 ? launch_trace(c, !plan.coherent, plan.keep_cache, plan.expected, plan.n_prev) : 0;
+  if (traversal < 0) return fail(c, DCEM_E_OUT_OF_MEMORY, "alloc traversal stack");
+  c->last_trace_kernel = traversal;
   ev_record(c, 2);
   HIP_TRY(hipGetLastError(), "trace kernels");
-  HIP_TRY(build_candidates(c, small), "candidates");
+  return DCEM_OK;
+}
+
+// Device part after the trace: candidates, refinement, reduction, and the
+// copy of the frame block to pinned host memory behind them.
+dcem_status frame_back(dcem_ctx* c, const FramePlan& plan) {
+  HIP_TRY(build_candidates(c, plan.small), "candidates");
   ev_record(c, 3);
   HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");
   launch_refine(c);
@@ -875,17 +918,35 @@ dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
   c->list_clear = true;
   ev_record(c, 5);
   HIP_TRY(hipGetLastError(), "refine kernels");
-  // the results of the frame, read back behind its last kernel
   HIP_TRY(hipMemcpyAsync(c->host_block, c->frame_block.p, frame_block_bytes(c), hipMemcpyDeviceToHost, c->stream),
           "read results");
+  return DCEM_OK;
+}
+
+// Host state once a frame's work is enqueued: its results are on their way.
+dcem_status frame_done(dcem_ctx* c, const FramePlan& plan) {
   HIP_TRY(hipEventRecord(c->ev_copy, c->stream), "read results");
   c->copy_pending = true;
-  c->cache_valid = keep_cache;
+  c->cache_valid = plan.keep_cache;
   c->has_frame = true;
   c->counts_current = false;
-  c->stats.coherent = coherent ? 1 : 0;
-  c->stats.rays_total = n_work;
+  c->stats.coherent = plan.coherent ? 1 : 0;
+  c->stats.rays_total = plan.n_work;
   return DCEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcem_status dcem_trace_frame(dcem_ctx* c, const dcem_trace_params* p) {
+  FramePlan plan;
+  dcem_status st = frame_setup(c, p, plan);
+  if (st == DCEM_OK) st = frame_front(c, plan);
+  if (st == DCEM_OK) st = frame_trace(c, plan);
+  if (st == DCEM_OK) st = frame_back(c, plan);
+  if (st == DCEM_OK) st = frame_done(c, plan);
+  return st;
 }
 
 dcem_status dcem_received_power(dcem_ctx* c, double* p_coh, double* p_inc, int32_t mem_kind) {
@@ -1224,6 +1285,262 @@ dcem_status dcem_get_ray_dirs(dcem_ctx* c, float* out) {
   HIP_TRY(flush_refit(c), "refit");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
   if (c->n_rays) HIP_TRY(hipMemcpy(out, c->dirs.p, sizeof(float) * 3 * c->n_rays, hipMemcpyDeviceToHost), "copy dirs");
+  return DCEM_OK;
+}
+
+}  // extern "C"
+
+// ---- batches: one frame of several contexts with one persistent trace launch
+
+struct dcem_batch {
+  std::vector<dcem_ctx*> ctx;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  dcem::DevBuf table, spill;          // per-context trace arguments + chunk table; stack spill space
+  void* host_table = nullptr;         // pinned staging of `table`
+  size_t host_table_bytes = 0;
+  dcem::BatchShape shape;
+  bool tuned = false;
+  bool use_graph = false;
+  hipGraphExec_t exec = nullptr;      // the last captured frame, updated in place when its topology holds
+  int graph_frames = 0;               // frames launched as one graph
+  hipEvent_t ev[2] = {};
+  float ms_trace = 0.f;               // the last directly launched batch trace (or graph frame)
+};
+
+namespace {
+
+dcem_status batch_fail(dcem_batch* b, dcem_status s, const char* msg) {
+  for (dcem_ctx* c : b->ctx) c->err = msg;
+  return s;
+}
+
+// Buffers of a batch launch of `shape` (from the first context's allocator).
+hipError_t batch_buffers(dcem_batch* b, const dcem::BatchShape& shape) {
+  hipError_t e;
+  const size_t tb = batch_table_bytes((int)b->ctx.size());
+  if ((e = ensure(b->table, tb)) != hipSuccess) return e;
+  if ((e = ensure(b->spill, batch_spill_bytes(b->ctx[0], shape))) != hipSuccess) return e;
+  if (b->host_table_bytes < tb) {
+    if (b->host_table) (void)hipHostFree(b->host_table);
+    b->host_table = nullptr;
+    b->host_table_bytes = 0;
+    if ((e = hipHostMalloc(&b->host_table, tb, hipHostMallocDefault)) != hipSuccess) return e;
+    b->host_table_bytes = tb;
+  }
+  return hipSuccess;
+}
+
+// One batched frame: every context's host part, then the device work of all
+// of them (frame starts and refits, the full traces in one persistent launch
+// (coherent contexts trace their own re-trace lists), candidates, refinement,
+// reductions and read-backs), captured as one HIP graph when asked for and
+// possible.  `timed`: HIP events around the batched trace (direct launch).
+dcem_status batch_frame(dcem_batch* b, const dcem_trace_params* params, const dcem::BatchShape& shape, bool timed) {
+  const int n = (int)b->ctx.size();
+  std::vector<FramePlan> plan(n);
+  for (int j = 0; j < n; ++j) {
+    const dcem_status st = frame_setup(b->ctx[j], &params[j], plan[j]);
+    if (st != DCEM_OK) return st;
+  }
+  dcem_ctx* c = b->ctx[0];   // for HIP_TRY's messages
+  HIP_TRY(hipSetDevice(b->device), "set device");
+  if (batch_buffers(b, shape) != hipSuccess) return batch_fail(b, DCEM_E_OUT_OF_MEMORY, "alloc batch buffers");
+  std::vector<dcem_ctx*> full;
+  std::vector<uint8_t> full_cache;   // the full trace stores the segment cache (a coherent frame follows)
+  bool capturable = b->use_graph && b->stream != nullptr && !timed;
+  for (int j = 0; j < n; ++j) {
+    dcem_ctx* cj = b->ctx[j];
+    if (!plan[j].coherent && plan[j].n_work > 0) {
+      full.push_back(cj);
+      full_cache.push_back(plan[j].keep_cache ? 1 : 0);
+    }
+    // device-side decisions only (no host round trip, no timing events)
+    capturable = capturable && plan[j].small && !cj->timing;
+  }
+  if (capturable) HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed), "begin capture");
+  dcem_status st = DCEM_OK;
+  for (int j = 0; j < n && st == DCEM_OK; ++j) st = frame_front(b->ctx[j], plan[j]);
+  if (st == DCEM_OK && timed) (void)hipEventRecord(b->ev[0], b->stream);
+  if (st == DCEM_OK && !full.empty()) {
+    for (dcem_ctx* f : full) ev_record(f, 8);
+    const hipError_t e = launch_trace_batch(full.data(), full_cache.data(), (int)full.size(), shape, b->table,
+                                            b->host_table, b->host_table_bytes, b->spill, b->stream);
+    if (e != hipSuccess) st = hip_fail(c, e, "batched trace");
+    for (dcem_ctx* f : full) {
+      f->last_trace_kernel = 0;
+      ev_record(f, 2);
+    }
+  }
+  if (st == DCEM_OK && timed) (void)hipEventRecord(b->ev[1], b->stream);
+  for (int j = 0; j < n && st == DCEM_OK; ++j)
+    if (plan[j].coherent) st = frame_trace(b->ctx[j], plan[j]);
+  for (int j = 0; j < n && st == DCEM_OK; ++j) st = frame_back(b->ctx[j], plan[j]);
+  if (capturable) {
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != DCEM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    HIP_TRY(e, "end capture");
+    bool updated = false;
+    if (b->exec) {
+      hipGraphExecUpdateResult res;
+      hipGraphNode_t bad = nullptr;
+      updated = hipGraphExecUpdate(b->exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+      if (!updated) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+      }
+    }
+    if (!updated) {
+      const hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->exec = nullptr;
+        return hip_fail(c, ie, "instantiate graph");
+      }
+    }
+    (void)hipGraphDestroy(g);
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream), "launch graph");
+    ++b->graph_frames;
+  }
+  if (st != DCEM_OK) return st;
+  for (int j = 0; j < n; ++j) {
+    st = frame_done(b->ctx[j], plan[j]);
+    if (st != DCEM_OK) return st;
+  }
+  return DCEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcem_status dcem_batch_create(dcem_batch** out, dcem_ctx* const* ctxs, int32_t n) {
+  if (!out) return DCEM_E_INVALID_ARG;
+  *out = nullptr;
+  if (!ctxs || n < 1) return DCEM_E_INVALID_ARG;
+  for (int32_t j = 0; j < n; ++j) {
+    if (!ctxs[j]) return DCEM_E_INVALID_ARG;
+    if (ctxs[j]->device != ctxs[0]->device || ctxs[j]->stream != ctxs[0]->stream)
+      return fail(ctxs[j], DCEM_E_INVALID_ARG, "batched contexts must share one device and one stream");
+    for (int32_t k = 0; k < j; ++k)
+      if (ctxs[k] == ctxs[j]) return fail(ctxs[j], DCEM_E_INVALID_ARG, "a context appears twice in the batch");
+  }
+  dcem_batch* b = new dcem_batch();
+  b->ctx.assign(ctxs, ctxs + n);
+  b->device = ctxs[0]->device;
+  b->stream = ctxs[0]->stream;
+  b->table.al = b->spill.al = &ctxs[0]->alloc;
+  if (hipSetDevice(b->device) != hipSuccess || hipEventCreate(&b->ev[0]) != hipSuccess ||
+      hipEventCreate(&b->ev[1]) != hipSuccess) {
+    dcem_batch_destroy(b);
+    return DCEM_E_DEVICE;
+  }
+  *out = b;
+  return DCEM_OK;
+}
+
+void dcem_batch_destroy(dcem_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  release(b->table);
+  release(b->spill);
+  if (b->host_table) (void)hipHostFree(b->host_table);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete b;
+}
+
+dcem_status dcem_batch_set_graph(dcem_batch* b, int32_t enabled) {
+  if (!b) return DCEM_E_INVALID_ARG;
+  b->use_graph = enabled != 0;
+  return DCEM_OK;
+}
+
+dcem_status dcem_batch_set_shape(dcem_batch* b, int32_t lds_stack, int32_t blocks_per_cu, int32_t chunk) {
+  if (!b) return DCEM_E_INVALID_ARG;
+  if ((lds_stack != 16 && lds_stack != 32) || blocks_per_cu < 1 || blocks_per_cu > 32 || chunk < 64 ||
+      chunk % 64 != 0 || chunk > (1 << 20))
+    return batch_fail(b, DCEM_E_INVALID_ARG, "shape: lds_stack 16 or 32, 1..32 blocks per CU, chunk a multiple of 64");
+  b->shape.lds_stack = lds_stack;
+  b->shape.blocks_per_cu = blocks_per_cu;
+  b->shape.chunk = chunk;
+  return DCEM_OK;
+}
+
+dcem_status dcem_batch_trace(dcem_batch* b, const dcem_trace_params* params) {
+  if (!b) return DCEM_E_INVALID_ARG;
+  if (!params) return batch_fail(b, DCEM_E_INVALID_ARG, "null params");
+  return batch_frame(b, params, b->shape, false);
+}
+
+dcem_status dcem_batch_tune(dcem_batch* b, const dcem_trace_params* params, int32_t repeats) {
+  if (!b) return DCEM_E_INVALID_ARG;
+  if (!params || repeats < 1) return batch_fail(b, DCEM_E_INVALID_ARG, "null params or repeats < 1");
+  // block shape and LDS stack depth first (chunk 256), then the chunk
+  std::vector<dcem::BatchShape> cand;
+  for (int lds : {32, 16})
+    for (int bpc : {4, 6, 8, 12, 16}) {
+      if (lds == 32 && bpc > 8) continue;   // 16 KB of LDS stack per block: at most 9 blocks per CU
+      cand.push_back(dcem::BatchShape{lds, bpc, 256});
+    }
+  auto time_shape = [&](const dcem::BatchShape& sh, float* best_ms) -> dcem_status {
+    float sum = 0.f;
+    for (int r = 0; r < repeats; ++r) {
+      dcem_status st = batch_frame(b, params, sh, true);
+      if (st != DCEM_OK) return st;
+      dcem_ctx* c = b->ctx[0];
+      HIP_TRY(hipEventSynchronize(b->ev[1]), "synchronize");
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]), "elapsed");
+      sum += ms;
+    }
+    *best_ms = sum / repeats;
+    return DCEM_OK;
+  };
+  float best = INFINITY;
+  dcem::BatchShape best_shape = b->shape;
+  for (const auto& sh : cand) {
+    float ms = 0.f;
+    const dcem_status st = time_shape(sh, &ms);
+    if (st != DCEM_OK) return st;
+    if (ms < best) {
+      best = ms;
+      best_shape = sh;
+    }
+  }
+  for (int chunk : {64, 1024}) {
+    dcem::BatchShape sh = best_shape;
+    sh.chunk = chunk;
+    float ms = 0.f;
+    const dcem_status st = time_shape(sh, &ms);
+    if (st != DCEM_OK) return st;
+    if (ms < best) {
+      best = ms;
+      best_shape = sh;
+    }
+  }
+  b->shape = best_shape;
+  b->tuned = true;
+  b->ms_trace = best;
+  return DCEM_OK;
+}
+
+dcem_status dcem_batch_get_info(const dcem_batch* b, dcem_batch_info* out) {
+  if (!b || !out) return DCEM_E_INVALID_ARG;
+  out->n_ctx = (int32_t)b->ctx.size();
+  out->lds_stack = b->shape.lds_stack;
+  out->blocks_per_cu = b->shape.blocks_per_cu;
+  out->chunk = b->shape.chunk;
+  out->tuned = b->tuned ? 1 : 0;
+  out->graph_frames = b->graph_frames;
+  out->ms_trace_tuned = b->ms_trace;
   return DCEM_OK;
 }
 

@@ -14,7 +14,9 @@ namespace dcem {
 constexpr int kWave = 64;
 constexpr float kTMin = 1e-4f;           // hits closer than this to a segment start are ignored
 constexpr double kTMinD = 1e-4;
-constexpr int kStackSize = 48;           // traversal stack entries per lane (LDS)
+constexpr int kStackLds = 32;            // per-thread traversal stack entries kept in LDS
+constexpr int kStackSpill = 32;          // further entries per thread in device memory (rarely reached)
+constexpr int kStackSize = kStackLds + kStackSpill;
 constexpr int kTopNodes = 21;            // 4-wide nodes of the top three levels, kept in LDS
 constexpr int kTraceBlock = 128;         // threads per trace block
 constexpr uint32_t kNoRay = 0xffffffffu;
@@ -197,6 +199,7 @@ struct dcem_ctx {
   dcem::DevBuf caps[2];      // double-buffered capture lists
   int cur_caps = 0;
   dcem::DevBuf work_list, invalid_flag;   // re-trace list; per-ray first invalid segment (255 = valid)
+  dcem::DevBuf stack_spill;  // per-thread traversal stack entries beyond the LDS part (kStackSpill each)
   // One device block holding everything the host reads after a frame, copied
   // in one transfer to pinned host memory: counters (128 B), error word
   // (128 B), SAH values (256 B), then p_coh and p_inc.
@@ -248,7 +251,7 @@ struct dcem_ctx {
             &nodes, &leaf_slot, &leaf_tri, &leaf_parent, &refit_cnt, &morton, &sort_tmp, &sah_part, &scene_box,
             &node_range, &nodes4, &bvh2_of4, &map4, &depth_key, &slot4, &cross, &tree_info, &tri4, &face_build,
             &dirs, &ray_order, &tx_pos, &rx_pos, &freqs, &rx_nodes, &rx_cols, &grad_buf, &face_log, &ray_state,
-            &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag,
+            &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag, &stack_spill,
             &frame_block, &cand_keys, &cand_perm, &cand_tmp, &uniq_idx, &first_ray, &path_valid, &path_len,
             &path_tau, &path_aod, &path_aoa, &path_amp, &pair_range, &path_order, &path_faces, &path_pts,
             &sort_hist};
@@ -306,7 +309,8 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
 void launch_fibonacci(dcem_ctx* c);
 // Trace all rays, or (coherent frame) the listed ones after keeping the
 // previous frame's still-valid captures.  Returns the traversal launched:
-// 0 one thread per ray, 1 one group of lanes per ray.
+// 0 one thread per ray, 1 one group of lanes per ray; -1 when its stack
+// space could not be allocated (nothing launched).
 int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps);
 void launch_coherence(dcem_ctx* c);
 // The pending refit of the 4-wide tree and the revalidation pass in one launch.
@@ -314,9 +318,31 @@ void launch_refit_coherence(dcem_ctx* c, bool begin);
 // Clear the frame counters and seed the capture list with the LoS candidates.
 void launch_frame_begin(dcem_ctx* c, bool los);
 hipError_t build_ray_order(dcem_ctx* c);
+// Buffers a frame's trace needs (the per-thread stack's spill space), sized
+// before anything of the frame is enqueued.
+hipError_t prepare_trace(dcem_ctx* c);
+// Launch configuration of a batched trace (several contexts' full frames in
+// one persistent launch): per-thread stack entries kept in LDS, blocks per
+// compute unit, work items per queue chunk.
+struct BatchShape {
+  int lds_stack = 32;
+  int blocks_per_cu = 8;
+  int chunk = 256;
+};
+// Bytes of spill space a batched trace of this shape needs.
+size_t batch_spill_bytes(const dcem_ctx* c, const BatchShape& shape);
+// One persistent launch tracing every ray of the given contexts (full frames
+// on one stream; keep_cache[j]: context j stores its segment cache).  `table`
+// holds the per-context arguments and the chunk table (staged through pinned
+// `host_table`), `spill` the stack spill space.
+hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, int n, const BatchShape& shape,
+                              DevBuf& table, void* host_table, size_t host_table_bytes, DevBuf& spill, hipStream_t s);
+size_t batch_table_bytes(int n);
 
 // ---- candidates, refinement and accumulation (refine.hip)
 hipError_t build_candidates(dcem_ctx* c, bool small);
+// Buffers of the one-workgroup de-duplication path and of its paths.
+hipError_t prepare_small_candidates(dcem_ctx* c);
 bool small_path_fits(const dcem_ctx* c);
 int64_t small_path_capacity();
 hipError_t ensure_paths(dcem_ctx* c, int64_t n);

@@ -1097,6 +1097,15 @@ hipError_t ensure_paths(dcem_ctx* c, int64_t n) {
   return hipSuccess;
 }
 
+hipError_t prepare_small_candidates(dcem_ctx* c) {
+  hipError_t e;
+  const KeyLayout L = key_layout(c);
+  if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
+  if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+  return ensure_paths(c, kSmallN);
+}
+
 // Candidate keys, sort and unique.  `small`: one workgroup de-duplicates up to
 // kSmallN captures whose count it reads on the device (no host round trip; a
 // larger count raises the fallback counter and the host redoes the frame's

@@ -148,14 +148,33 @@ __device__ inline void cswap(float& ta, int& ca, float& tb, int& cb) {
   }
 }
 
+// Per-thread traversal stack: the first kStackLds entries in LDS (strided by
+// the block size), deeper ones in this thread's region of device memory.  A
+// 4-wide traversal pushes at most three entries per level, so the spill part
+// is reached only by rays in unusually deep parts of a tree.
+struct ThreadStack {
+  int* lds;
+  int* spill;           // this thread's first spill entry
+  size_t spill_stride;  // threads of the grid
+  int cap;              // entries usable (<= kStackSize)
+  int lds_entries = kStackLds;
+  __device__ void put(int i, int v) {
+    if (i < lds_entries) lds[i * kTraceBlock] = v;
+    else spill[(size_t)(i - lds_entries) * spill_stride] = v;
+  }
+  __device__ int get(int i) const {
+    return i < lds_entries ? lds[i * kTraceBlock] : spill[(size_t)(i - lds_entries) * spill_stride];
+  }
+};
+
 // Closest hit: lexicographic minimum of (t, triangle id) over all triangles
 // with t > t_min outside face `excl`, by a stack traversal of the 4-wide tree
 // (nearest child first; the top levels are read from LDS).  The result does
 // not depend on the tree shape: boxes are conservative and nodes are pruned
 // only when their entry distance exceeds the current best (ties are visited).
 __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const Node4* top, int n_top, int n4,
-                           const Leaf* __restrict__ tri4, int excl, int* stack, int stride, int stack_cap,
-                           bool& overflow, uint32_t& n_nodes, uint32_t& n_tris) {
+                           const Leaf* __restrict__ tri4, int excl, ThreadStack& stack, bool& overflow,
+                           uint32_t& n_nodes, uint32_t& n_tris) {
   Hit h{FLT_MAX, -1, -1, -1};
   if (n4 == 0) return h;
   int node = 0, sp = 0;
@@ -191,13 +210,13 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
     cswap(t[1], c[1], t[2], c[2]);
     if (c[0] == kEmpty) {
       if (sp == 0) break;
-      node = stack[(--sp) * stride];
+      node = stack.get(--sp);
       continue;
     }
 #pragma unroll
     for (int e = 3; e >= 1; --e) {
       if (c[e] == kEmpty) continue;
-      if (sp < stack_cap) stack[(sp++) * stride] = c[e];
+      if (sp < stack.cap) stack.put(sp++, c[e]);
       else overflow = true;
     }
     node = c[0];
@@ -258,6 +277,7 @@ struct TraceArgs {
   uint32_t* err;
   const Capture* prev_caps;   // coherent frames: the previous frame's captures to filter
   uint32_t n_prev;
+  int* stack_spill;           // [kStackSpill][grid threads] per-thread stack entries beyond the LDS part
   int stack_thread;           // stack entries a per-thread traversal may use (<= kStackSize)
   int stack_group;            // stack entries a group traversal may use (<= kRayStack)
 };
@@ -325,13 +345,153 @@ __device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const floa
   setup_ray(r);
 }
 
+// Per-thread tracing of one work item (a ray, from its first segment or, in
+// work-list mode, from its restart segment): closest hits, captures,
+// reflections, the per-bounce face log and segment cache.
+struct ItemCounts {
+  uint32_t seg = 0, node = 0, tri = 0;
+  bool overflow = false, cap_over = false;
+};
+
+__device__ void trace_item(const TraceArgs& a, uint32_t wi, const Node4* top, int n_top, int n4, ThreadStack& stack,
+                           ItemCounts& ic) {
+  uint32_t& seg_count = ic.seg;
+  uint32_t& node_count = ic.node;
+  uint32_t& tri_count = ic.tri;
+  bool& overflow = ic.overflow;
+  bool& cap_over = ic.cap_over;
+  // work: the ray's traversal position (its index in the face log, the
+  // caches and the capture records); rid: its ray id (the parity log)
+  const uint32_t work = a.work_list ? a.work_list[wi] : wi;
+  const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
+  const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
+  const uint32_t rid = txi * (uint32_t)a.n_rays + ray;
+  int k = a.restart ? (int)a.restart[work] : 0;
+  Ray r;
+  int excl = -1;
+  float L = 0.0f;
+  if (k == 0) {
+    r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
+    r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
+  } else {
+    const float4 so = a.seg_o[(size_t)k * a.n_work + work];
+    const float4 sd = a.seg_d[(size_t)k * a.n_work + work];
+    r.o = make_float3(so.x, so.y, so.z);
+    r.d = make_float3(sd.x, sd.y, sd.z);
+    L = sd.w;
+    excl = a.face_log[(size_t)(k - 1) * a.n_work + work];
+  }
+  setup_ray(r);
+  uint32_t state = 0;
+  for (; k <= a.K; ++k) {
+    Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, overflow, node_count, tri_count);
+    ++seg_count;
+    const bool hit = h.tri >= 0;
+    const float tend = hit ? h.t : INFINITY;
+    a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
+    if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
+    if (a.seg_o) {
+      a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
+      a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
+    }
+    const float dd = dot_dd(r);
+    const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
+    if (a.log_tri) {
+      const size_t li = (size_t)rid * (a.K + 1) + k;
+      a.log_tri[li] = h.tri;
+      a.log_t[li] = hit ? h.t : INFINITY;
+      a.log_len[li] = hit ? L_hit : INFINITY;
+    }
+    // capture: spheres whose padded box the segment meets, then the exact test
+    const float za = r.o.z;
+    const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+    if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+      int node = 0, sp = 0;
+      for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
+        const Node nd = a.rx_nodes[node];
+        float t0, t1;
+        bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, tend, t0);
+        bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, tend, t1);
+        const int c0 = nd.c.x, c1 = nd.c.y;
+        for (int side = 0; side < 2; ++side) {
+          const int cc = side ? c1 : c0;
+          const bool hh = side ? h1 : h0;
+          if (!(hh && cc < 0) || (side == 1 && c1 == c0)) continue;   // a lone sphere fills both slots
+          const int c = ~cc;
+          if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
+            const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
+            if (slot < a.cap_capacity) {
+              Capture cp;
+              cp.work = work;
+              cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+              a.caps[slot] = cp;
+            } else {
+              cap_over = true;
+            }
+          }
+        }
+        h0 = h0 && c0 >= 0;
+        h1 = h1 && c1 >= 0;
+        if (h0 && h1) {
+          if (sp < stack.cap) stack.put(sp++, c1);
+          else overflow = true;
+          node = c0;
+        } else if (h0) {
+          node = c0;
+        } else if (h1) {
+          node = c1;
+        } else {
+          if (sp == 0) break;
+          node = stack.get(--sp);
+        }
+      }
+    }
+    if (!hit || k == a.K) { ++k; break; }
+    // specular reflection off the hit triangle's plane
+    L = L_hit;
+    reflect_ray(r, h.t, a.tri4[h.leaf].v0, a.tri4[h.leaf].v1, a.tri4[h.leaf].v2);
+    excl = h.face;
+  }
+  // mark the remaining bounces as not reached
+  for (int j = k; j <= a.K; ++j) {
+    a.face_log[(size_t)j * a.n_work + work] = -2;
+    if (a.log_tri) {
+      const size_t li = (size_t)rid * (a.K + 1) + j;
+      a.log_tri[li] = -2;
+      a.log_t[li] = INFINITY;
+      a.log_len[li] = INFINITY;
+    }
+  }
+  a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
+}
+
+// Wavefront-wide sums of a block's item counts, added to the frame counters
+// (one atomic per wavefront), and its error flags.
+__device__ void flush_counts(const TraceArgs& a, ItemCounts& ic) {
+  uint32_t seg_count = ic.seg, node_count = ic.node, tri_count = ic.tri;
+  for (int off = 32; off > 0; off >>= 1) {
+    seg_count += __shfl_xor(seg_count, off);
+    node_count += __shfl_xor(node_count, off);
+    tri_count += __shfl_xor(tri_count, off);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicAdd(&a.counters[kCntSegments], seg_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntNodes]), (unsigned long long)node_count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntTris]), (unsigned long long)tri_count);
+  }
+  if (ic.overflow) atomicOr(a.err, DCEM_ERR_STACK);
+  if (ic.cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
+  ic = ItemCounts{};
+}
+
 // Persistent trace kernel: each wavefront takes 64 consecutive work items from
 // a global queue and traces them through all bounces.  In work-list mode a ray
 // restarts at its first invalidated segment from the cached segment state.
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
-  __shared__ int stack_mem[kStackSize * kTraceBlock];
+  __shared__ int stack_mem[kStackLds * kTraceBlock];
   __shared__ Node4 top[kTopNodes];
-  int* stack = stack_mem + threadIdx.x;
+  ThreadStack stack{stack_mem + threadIdx.x, a.stack_spill + blockIdx.x * (size_t)kTraceBlock + threadIdx.x,
+                    (size_t)gridDim.x * kTraceBlock, a.stack_thread};
   const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
   const int n_top = min(kTopNodes, n4);
   for (int i = threadIdx.x; i < n_top; i += blockDim.x) top[i] = a.nodes4[i];
@@ -339,135 +499,57 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t n_work = a.work_list ? a.counters[kCntList] : (uint32_t)a.n_work;
   if (a.work_list && blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
-  uint32_t seg_count = 0, node_count = 0, tri_count = 0;
-  bool overflow = false, cap_over = false;
-  keep_previous_captures(a, cap_over);
+  ItemCounts ic;
+  keep_previous_captures(a, ic.cap_over);
   while (true) {
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&a.counters[kCntQueue], (uint32_t)kWave);
     base = __shfl(base, 0);
     if (base >= n_work) break;
     const uint32_t wi = base + lane;
-    if (wi < n_work) {
-      // work: the ray's traversal position (its index in the face log, the
-      // caches and the capture records); rid: its ray id (the parity log)
-      const uint32_t work = a.work_list ? a.work_list[wi] : wi;
-      const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
-      const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
-      const uint32_t rid = txi * (uint32_t)a.n_rays + ray;
-      int k = a.restart ? (int)a.restart[work] : 0;
-      Ray r;
-      int excl = -1;
-      float L = 0.0f;
-      if (k == 0) {
-        r.o = make_float3(a.tx[3 * txi], a.tx[3 * txi + 1], a.tx[3 * txi + 2]);
-        r.d = make_float3(a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]);
-      } else {
-        const float4 so = a.seg_o[(size_t)k * a.n_work + work];
-        const float4 sd = a.seg_d[(size_t)k * a.n_work + work];
-        r.o = make_float3(so.x, so.y, so.z);
-        r.d = make_float3(sd.x, sd.y, sd.z);
-        L = sd.w;
-        excl = a.face_log[(size_t)(k - 1) * a.n_work + work];
-      }
-      setup_ray(r);
-      uint32_t state = 0;
-      for (; k <= a.K; ++k) {
-        Hit h = closest_hit(r, a.nodes4, top, n_top, n4, a.tri4, excl, stack, kTraceBlock, a.stack_thread,
-                            overflow, node_count, tri_count);
-        ++seg_count;
-        const bool hit = h.tri >= 0;
-        const float tend = hit ? h.t : INFINITY;
-        a.face_log[(size_t)k * a.n_work + work] = hit ? h.face : -1;
-        if (hit && a.face_object[h.face] >= 0) state |= 0x80u;
-        if (a.seg_o) {
-          a.seg_o[(size_t)k * a.n_work + work] = make_float4(r.o.x, r.o.y, r.o.z, tend);
-          a.seg_d[(size_t)k * a.n_work + work] = make_float4(r.d.x, r.d.y, r.d.z, L);
-        }
-        const float dd = dot_dd(r);
-        const float L_hit = __fmaf_rn(h.t, __fsqrt_rn(dd), L);
-        if (a.log_tri) {
-          const size_t li = (size_t)rid * (a.K + 1) + k;
-          a.log_tri[li] = h.tri;
-          a.log_t[li] = hit ? h.t : INFINITY;
-          a.log_len[li] = hit ? L_hit : INFINITY;
-        }
-        // capture: spheres whose padded box the segment meets, then the exact test
-        const float za = r.o.z;
-        const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
-        if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
-          int node = 0, sp = 0;
-          for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
-            const Node nd = a.rx_nodes[node];
-            float t0, t1;
-            bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, tend, t0);
-            bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, tend, t1);
-            const int c0 = nd.c.x, c1 = nd.c.y;
-            for (int side = 0; side < 2; ++side) {
-              const int cc = side ? c1 : c0;
-              const bool hh = side ? h1 : h0;
-              if (!(hh && cc < 0) || (side == 1 && c1 == c0)) continue;   // a lone sphere fills both slots
-              const int c = ~cc;
-              if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
-                const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
-                if (slot < a.cap_capacity) {
-                  Capture cp;
-                  cp.work = work;
-                  cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
-                  a.caps[slot] = cp;
-                } else {
-                  cap_over = true;
-                }
-              }
-            }
-            h0 = h0 && c0 >= 0;
-            h1 = h1 && c1 >= 0;
-            if (h0 && h1) {
-              if (sp < a.stack_thread) stack[(sp++) * kTraceBlock] = c1;
-              else overflow = true;
-              node = c0;
-            } else if (h0) {
-              node = c0;
-            } else if (h1) {
-              node = c1;
-            } else {
-              if (sp == 0) break;
-              node = stack[(--sp) * kTraceBlock];
-            }
-          }
-        }
-        if (!hit || k == a.K) { ++k; break; }
-        // specular reflection off the hit triangle's plane
-        L = L_hit;
-        reflect_ray(r, h.t, a.tri4[h.leaf].v0, a.tri4[h.leaf].v1, a.tri4[h.leaf].v2);
-        excl = h.face;
-      }
-      // mark the remaining bounces as not reached
-      for (int j = k; j <= a.K; ++j) {
-        a.face_log[(size_t)j * a.n_work + work] = -2;
-        if (a.log_tri) {
-          const size_t li = (size_t)rid * (a.K + 1) + j;
-          a.log_tri[li] = -2;
-          a.log_t[li] = INFINITY;
-          a.log_len[li] = INFINITY;
-        }
-      }
-      a.ray_state[work] = (uint8_t)(state | (uint32_t)k);
+    if (wi < n_work) trace_item(a, wi, top, n_top, n4, stack, ic);
+  }
+  flush_counts(a, ic);
+}
+
+// Full traces of several scenes in one persistent launch.  args[j] describes
+// scene j's frame (all rays, no work list); its items are cut into chunks of
+// `chunk` consecutive work items, chunk_start[j] the first chunk of scene j in
+// one queue over all scenes (chunk_start[n] the total).  A wavefront takes the
+// next chunk, finds its scene and traces the chunk's items, 64 at a time;
+// counts and errors go to that scene's frame.  The per-thread stack keeps its
+// first S entries in LDS.  No top-level node cache: consecutive chunks may
+// belong to different scenes.
+template <int S>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_batch(const TraceArgs* __restrict__ args,
+                                                             const uint32_t* __restrict__ chunk_start, int n_scene,
+                                                             uint32_t chunk, uint32_t* __restrict__ queue,
+                                                             int* __restrict__ spill) {
+  __shared__ int stack_mem[S * kTraceBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t total = chunk_start[n_scene];
+  while (true) {
+    uint32_t g = 0;
+    if (lane == 0) g = atomicAdd(queue, 1u);
+    g = __builtin_amdgcn_readfirstlane(g);   // uniform: the scene's arguments load as scalars
+    if (g >= total) break;
+    int lo = 0, hi = n_scene - 1;   // the last scene whose first chunk is <= g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (chunk_start[mid] <= g) lo = mid; else hi = mid - 1;
     }
+    const TraceArgs a = args[lo];
+    ThreadStack stack{stack_mem + threadIdx.x, spill + blockIdx.x * (size_t)kTraceBlock + threadIdx.x,
+                      (size_t)gridDim.x * kTraceBlock, a.stack_thread};
+    stack.lds_entries = S;
+    const int n4 = a.n4_dev ? (int)*a.n4_dev : 0;
+    const uint32_t base = (g - chunk_start[lo]) * chunk;
+    const uint32_t end = min(base + chunk, (uint32_t)a.n_work);
+    ItemCounts ic;
+    for (uint32_t b = base; b < end; b += kWave)
+      if (b + lane < end) trace_item(a, b + lane, nullptr, 0, n4, stack, ic);
+    flush_counts(a, ic);
   }
-  // one atomic per wavefront for the counters
-  for (int off = 32; off > 0; off >>= 1) {
-    seg_count += __shfl_xor(seg_count, off);
-    node_count += __shfl_xor(node_count, off);
-    tri_count += __shfl_xor(tri_count, off);
-  }
-  if (lane == 0) {
-    atomicAdd(&a.counters[kCntSegments], seg_count);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntNodes]), (unsigned long long)node_count);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntTris]), (unsigned long long)tri_count);
-  }
-  if (overflow) atomicOr(a.err, DCEM_ERR_STACK);
-  if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
 // Group-per-ray tracing for short work lists (the rays a coherent frame
@@ -1164,7 +1246,7 @@ int cu_count(dcem_ctx* c) {
 }
 
 int trace_grid(dcem_ctx* c) {
-  return cu_count(c) * 5;   // 24 KB of LDS stack per block: five blocks per CU
+  return cu_count(c) * 8;   // 16 KB of LDS stack and 2.7 KB of top nodes per block: eight blocks per CU
 }
 
 }  // namespace
@@ -1177,7 +1259,10 @@ void launch_fibonacci(dcem_ctx* c) {
 // Trace all work items (all_rays) or those listed by the coherence pass.  The
 // persistent grid is sized for `expected` work items (any size is correct:
 // blocks drain a shared queue).
-int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps) {
+namespace {
+
+// Arguments of a context's trace launch.
+TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_prev_caps) {
   const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
@@ -1223,8 +1308,16 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   a.err = c->err_dev;
   a.prev_caps = ptr<Capture>(c->caps[c->cur_caps ^ 1]);
   a.n_prev = all_rays ? 0u : n_prev_caps;
+  a.stack_spill = nullptr;
   a.stack_thread = c->stack_limit > 0 ? std::min(c->stack_limit, kStackSize) : kStackSize;
   a.stack_group = c->stack_limit > 0 ? std::min(c->stack_limit, kRayStack) : kRayStack;
+  return a;
+}
+
+}  // namespace
+
+int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps) {
+  TraceArgs a = trace_args(c, all_rays, keep_cache, n_prev_caps);
   if (!all_rays && expected <= kWaveTraceMax) {
     // short re-trace list: one wavefront per ray
     const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;
@@ -1234,8 +1327,66 @@ int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, 
   }
   const int64_t want = (expected + expected / 4 + kTraceBlock - 1) / kTraceBlock;
   const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(trace_grid(c), want));
+  if (prepare_trace(c) != hipSuccess) {   // sized already by the frame's setup
+    (void)hipGetLastError();
+    return -1;
+  }
+  a.stack_spill = ptr<int>(c->stack_spill);
   hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
   return 0;
+}
+
+size_t batch_table_bytes(int n) {
+  return ((sizeof(TraceArgs) * (size_t)n + 255) / 256) * 256 + sizeof(uint32_t) * ((size_t)n + 1) + 256;
+}
+
+size_t batch_spill_bytes(const dcem_ctx* c, const BatchShape& shape) {
+  const int grid = std::max(1, cu_count(const_cast<dcem_ctx*>(c)) * shape.blocks_per_cu);
+  return sizeof(int) * (size_t)(kStackSize - shape.lds_stack) * kTraceBlock * (size_t)grid;
+}
+
+hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, int n, const BatchShape& shape,
+                              DevBuf& table, void* host_table, size_t host_table_bytes, DevBuf& spill, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t args_bytes = ((sizeof(TraceArgs) * (size_t)n + 255) / 256) * 256;
+  if (host_table_bytes < batch_table_bytes(n) || table.bytes < batch_table_bytes(n)) return hipErrorInvalidValue;
+  if (spill.bytes < batch_spill_bytes(cs[0], shape)) return hipErrorInvalidValue;
+  // per-context arguments and the chunk table, staged in pinned memory
+  char* h = static_cast<char*>(host_table);
+  TraceArgs* ha = reinterpret_cast<TraceArgs*>(h);
+  uint32_t* hc = reinterpret_cast<uint32_t*>(h + args_bytes);
+  uint64_t total = 0;
+  for (int j = 0; j < n; ++j) {
+    ha[j] = trace_args(cs[j], true, keep_cache[j] != 0, 0u);
+    hc[j] = (uint32_t)total;
+    total += ((uint64_t)ha[j].n_work + shape.chunk - 1) / shape.chunk;
+  }
+  hc[n] = (uint32_t)total;
+  if (total >= (uint64_t)1 << 32) return hipErrorInvalidValue;
+  uint32_t* queue = reinterpret_cast<uint32_t*>(static_cast<char*>(table.p) + args_bytes + sizeof(uint32_t) * (n + 1));
+  hipError_t e = hipMemcpyAsync(table.p, host_table, args_bytes + sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  fill_u32(queue, 0u, 1, s);
+  const TraceArgs* dargs = static_cast<const TraceArgs*>(table.p);
+  const uint32_t* dchunk = reinterpret_cast<const uint32_t*>(static_cast<char*>(table.p) + args_bytes);
+  const int want = (int)std::min<uint64_t>((total * shape.chunk + kTraceBlock - 1) / kTraceBlock + 1,
+                                           (uint64_t)cu_count(cs[0]) * shape.blocks_per_cu);
+  const int grid = std::max(1, want);
+  int* sp = ptr<int>(spill);
+  if (shape.lds_stack == 16)
+    hipLaunchKernelGGL(k_trace_batch<16>, dim3(grid), dim3(kTraceBlock), 0, s, dargs, dchunk, n,
+                       (uint32_t)shape.chunk, queue, sp);
+  else if (shape.lds_stack == 32)
+    hipLaunchKernelGGL(k_trace_batch<32>, dim3(grid), dim3(kTraceBlock), 0, s, dargs, dchunk, n,
+                       (uint32_t)shape.chunk, queue, sp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t prepare_trace(dcem_ctx* c) {
+  // spill space for the largest grid, so it never changes from frame to frame
+  return ensure(c->stack_spill, sizeof(int) * kStackSpill * kTraceBlock * (size_t)std::max(trace_grid(c), 16));
 }
 
 FrameBegin frame_begin_args(dcem_ctx* c, bool los) {

@@ -7,9 +7,11 @@ context if the shared library has not been built: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import sys
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -82,7 +84,7 @@ class TorchAllocator:
             return p
 
         def free(p, nbytes, stream, user):
-            if self.live.pop(p, None) is not None:
+            if self.live.pop(p, None) is not None and not sys.is_finalizing():
                 try:
                     torch.cuda.caching_allocator_delete(p)
                 except Exception:   # interpreter shutdown: torch already torn down
@@ -90,6 +92,14 @@ class TorchAllocator:
 
         self._alloc, self._free = _ALLOC_FN(alloc), _FREE_FN(free)   # kept alive with the context
         self.desc = AllocatorDesc(self._alloc, self._free, None)
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_ctx", _I32), ("lds_stack", _I32), ("blocks_per_cu", _I32), ("chunk", _I32), ("tuned", _I32),
+                ("graph_frames", _I32), ("ms_trace_tuned", _F32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 # (name, restype, argtypes) of every exported entry point of include/dcem.h
@@ -116,9 +126,29 @@ SIGNATURES = [
     ("dcem_get_vertices", _I32, [_P, _P]),
     ("dcem_get_ray_dirs", _I32, [_P, _P]),
     ("dcem_get_stats", _I32, [_P, ctypes.POINTER(FrameStats)]),
+    ("dcem_batch_create", _I32, [ctypes.POINTER(_P), ctypes.POINTER(_P), _I32]),
+    ("dcem_batch_destroy", None, [_P]),
+    ("dcem_batch_set_graph", _I32, [_P, _I32]),
+    ("dcem_batch_set_shape", _I32, [_P, _I32, _I32, _I32]),
+    ("dcem_batch_trace", _I32, [_P, ctypes.POINTER(TraceParams)]),
+    ("dcem_batch_tune", _I32, [_P, ctypes.POINTER(TraceParams), _I32]),
+    ("dcem_batch_get_info", _I32, [_P, ctypes.POINTER(BatchInfo)]),
 ]
 
 _lib = None
+
+# Contexts and batches still open: closed at interpreter exit while torch (whose
+# allocator may own their buffers) is still alive; batches before contexts.
+_live_batches = weakref.WeakSet()
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for b in list(_live_batches):
+        b.close()
+    for c in list(_live_contexts):
+        c.close()
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -191,13 +221,17 @@ class Context:
                                   ctypes.byref(self.allocator.desc) if self.allocator else None)
         if st != OK:
             raise DcemError(st, "dcem_create failed (device %d)" % device)
+        _live_contexts.add(self)
         self._keep = []
+        self._batches = []
         self.K = 0
         self.n_freqs = 1
         self.n_tx = self.n_rx = 0
         self.n_rays = 0
 
     def close(self):
+        for b in list(getattr(self, "_batches", [])):
+            b.close()   # a batch holds the context's handle
         if getattr(self, "handle", None) and self.handle.value:
             self.lib.dcem_destroy(self.handle)
             self.handle = _P()
@@ -249,10 +283,11 @@ class Context:
                                             float(threshold), ctypes.byref(rb), ctypes.byref(ratio)))
         return bool(rb.value), float(ratio.value)
 
-    def trace_frame(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None,
-                    max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
-                    tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
-                    los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False):
+    def _params(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None, max_reflections: int = 2,
+                freqs_hz: Sequence[float] = (28e9,), tx_power_w: float = 5.0, atten_db_per_km: float = 0.0,
+                mode: int = MODE_FULL, los_always: bool = True, keep_cache: bool = False,
+                record_trace_log: bool = False):
+        """dcem_trace_params of one frame (arrays kept alive on the context)."""
         dev = ray_dirs is not None and not isinstance(ray_dirs, np.ndarray) and ray_dirs.is_cuda
         if dev:
             txa, rxa, dirs = tx, rx, ray_dirs
@@ -265,11 +300,20 @@ class Context:
                         int(n_rays), _addr(dirs), int(max_reflections), _addr(fr), int(fr.shape[0]),
                         float(tx_power_w), float(atten_db_per_km), int(mode), int(bool(los_always)),
                         int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST)
+        shape = (int(max_reflections), int(fr.shape[0]), int(txa.shape[0]), int(rxa.shape[0]), int(n_rays))
+        return p, shape
+
+    def _traced(self, shape):
+        self.K, self.n_freqs, self.n_tx, self.n_rx, self.n_rays = shape
+
+    def trace_frame(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None,
+                    max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
+                    tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
+                    los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False):
+        p, shape = self._params(tx, rx, rx_radius, n_rays, ray_dirs, max_reflections, freqs_hz, tx_power_w,
+                                atten_db_per_km, mode, los_always, keep_cache, record_trace_log)
         self._check(self.lib.dcem_trace_frame(self.handle, ctypes.byref(p)))
-        self.K = int(max_reflections)
-        self.n_freqs = int(fr.shape[0])
-        self.n_tx, self.n_rx = int(txa.shape[0]), int(rxa.shape[0])
-        self.n_rays = int(n_rays)
+        self._traced(shape)
 
     def received_power(self, out=None):
         """(p_coh, p_inc) [n_freqs, n_tx, n_rx] FP64; host arrays unless `out` tensors are given."""
@@ -381,6 +425,82 @@ class Context:
         out = np.empty((self.n_rays, 3), np.float32)
         self._check(self.lib.dcem_get_ray_dirs(self.handle, _addr(out)))
         return out
+
+
+class Batch:
+    """One frame of several contexts (each with its own scene) traced together:
+    one persistent launch carries every full trace (dcem_batch_*)."""
+
+    def __init__(self, contexts):
+        self.ctxs = list(contexts)
+        self.lib = self.ctxs[0].lib
+        arr = (_P * len(self.ctxs))(*[c.handle.value for c in self.ctxs])
+        self.handle = _P()
+        st = self.lib.dcem_batch_create(ctypes.byref(self.handle), arr, len(self.ctxs))
+        if st != OK:
+            raise DcemError(st, self.ctxs[0].lib.dcem_last_error(self.ctxs[0].handle).decode())
+        _live_batches.add(self)
+        for c in self.ctxs:
+            c._batches.append(self)
+
+    def _check(self, st):
+        if st != OK:
+            msgs = {c.lib.dcem_last_error(c.handle).decode() for c in self.ctxs} - {""}
+            raise DcemError(st, "; ".join(sorted(msgs)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.dcem_batch_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _params(self, frames):
+        """frames: one dict of Context.trace_frame keyword arguments per context."""
+        arr = (TraceParams * len(self.ctxs))()
+        shapes = []
+        for j, (c, kw) in enumerate(zip(self.ctxs, frames)):
+            p, shape = c._params(**kw)
+            arr[j] = p
+            shapes.append(shape)
+        return arr, shapes
+
+    def trace(self, frames):
+        arr, shapes = self._params(frames)
+        self._check(self.lib.dcem_batch_trace(self.handle, arr))
+        for c, sh in zip(self.ctxs, shapes):
+            c._traced(sh)
+
+    def tune(self, frames, repeats: int = 1):
+        arr, shapes = self._params(frames)
+        self._check(self.lib.dcem_batch_tune(self.handle, arr, int(repeats)))
+        for c, sh in zip(self.ctxs, shapes):
+            c._traced(sh)
+        return self.info()
+
+    def set_graph(self, on: bool = True):
+        self._check(self.lib.dcem_batch_set_graph(self.handle, 1 if on else 0))
+
+    def set_shape(self, lds_stack: int, blocks_per_cu: int, chunk: int):
+        self._check(self.lib.dcem_batch_set_shape(self.handle, int(lds_stack), int(blocks_per_cu), int(chunk)))
+
+    def info(self) -> dict:
+        out = BatchInfo()
+        self._check(self.lib.dcem_batch_get_info(self.handle, ctypes.byref(out)))
+        return out.as_dict()
+
+
+def scene_frame_args(scene, frame: int = 0, mode: int = MODE_FULL, **kw) -> dict:
+    """Context.trace_frame keyword arguments of one frame of a scene."""
+    args = dict(tx=scene.tx, rx=scene.rx, rx_radius=scene.rx_radius, n_rays=scene.n_rays,
+                max_reflections=scene.max_reflections, freqs_hz=scene.freqs_hz, tx_power_w=scene.tx_power_w,
+                mode=mode)
+    args.update(kw)
+    return args
 
 
 @dataclass

@@ -618,6 +618,131 @@ def oblique_town(seed: int = 3, n_rays: int = 1 << 16, max_reflections: int = 3,
                      tx_power_w=5.0, n_frames=n_frames, dt=dt, transforms_fn=transforms)
 
 
+def _box_template(cells):
+    """Unit box [0, 1]^3 tessellated into cells: (vertices, triangles, local face of each triangle)."""
+    mb = _MeshBuilder()
+    mb.add_box((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), cells, material=0)
+    return mb.verts[0].astype(np.float64), mb.tris[0], mb.tri_face[0]
+
+
+def ragged_city(seed: int, target_tris: int, n_tx: int = 1, n_rx: int = 256, n_rays: int = 1 << 18,
+                max_reflections: int = 4, freqs_hz=(28e9,), n_frames: int = 10) -> Scene:
+    """A grid-and-vehicles city of about `target_tris` triangles, built with
+    array operations so that hundreds of thousands of triangles stay cheap.
+
+    G x G blocks of 40 m with 15 m streets, one concrete building per block
+    (height U(10, 60) m, facades tessellated t x 2t cells per side, roofs
+    t x t), V metal vehicles (4.5 x 1.8 x 1.5 m, 0.3 m clearance, 512
+    triangles) on random streets and lanes at U(10, 20) m/s, wrapping at the
+    grid edge.  V ~ 15% of the triangle budget (2..200), then G and t fill the
+    rest (G in 2..16).  n_tx transmitters on 2 m masts at roof corners of
+    random blocks, n_rx receivers on sidewalks at 1.5 m (capture radius
+    0.5 m).  Materials: concrete, ground, metal."""
+    rng = np.random.default_rng(seed)
+    V = int(np.clip(round(0.15 * target_tris / 512), 2, 200))
+    rest = max(target_tris - 512 * V, 2000)
+    G = int(np.clip(round(np.sqrt(rest / 2000.0)), 2, 16))
+    t = max(1, int(round(np.sqrt(rest / (20.0 * G * G)))))
+    extent = G * BLOCK + (G + 1) * STREET
+    half = extent / 2.0
+    origin = lambda i: -half + STREET + i * (BLOCK + STREET)
+    centre = lambda k: -half + STREET / 2.0 + k * (BLOCK + STREET)
+    heights = rng.uniform(10.0, 60.0, size=(G, G))
+    bv, bt, bf = _box_template((t, t, 2 * t))
+    ii, jj = np.meshgrid(np.arange(G), np.arange(G), indexing="ij")
+    lo = np.stack([origin(ii.ravel()), origin(jj.ravel()), np.zeros(G * G)], 1)
+    size = np.stack([np.full(G * G, BLOCK), np.full(G * G, BLOCK), heights.ravel()], 1)
+    bverts = lo[:, None, :] + size[:, None, :] * bv[None]
+    vv, vt, vf = _box_template((12, 5, 4))
+    veh = []
+    vlo, vsize = [], []
+    for v in range(V):
+        street = int(rng.integers(0, 2 * (G + 1)))
+        lane = int(rng.integers(0, 2))
+        u = rng.uniform(-half, half)
+        speed = rng.uniform(10.0, 20.0)
+        c = centre(street % (G + 1))
+        L, W, H = VEHICLE
+        if street <= G:
+            axis, lane_c, dirn = 0, c - LANE_OFFSET if lane == 0 else c + LANE_OFFSET, 1.0 if lane == 0 else -1.0
+            vlo.append((u - L / 2, lane_c - W / 2, VEHICLE_CLEARANCE))
+            vsize.append((L, W, H))
+        else:
+            axis, lane_c, dirn = 1, c + LANE_OFFSET if lane == 0 else c - LANE_OFFSET, 1.0 if lane == 0 else -1.0
+            vlo.append((lane_c - W / 2, u - L / 2, VEHICLE_CLEARANCE))
+            vsize.append((W, L, H))
+        veh.append((axis, dirn, u, speed))
+    # vehicles use the template in (x, y) order; a vehicle along y swaps the cell counts' roles,
+    # which only changes the tessellation pattern, not the box
+    vverts = np.asarray(vlo)[:, None, :] + np.asarray(vsize)[:, None, :] * vv[None]
+    n_b, n_v = G * G, V
+    nbv, nvv = bv.shape[0], vv.shape[0]
+    ground = np.array([[-half - 5, -half - 5, 0.0], [half + 5, -half - 5, 0.0], [half + 5, half + 5, 0.0],
+                       [-half - 5, half + 5, 0.0]])
+    verts = np.concatenate([ground, bverts.reshape(-1, 3), vverts.reshape(-1, 3)]).astype(np.float32)
+    g_t = np.array([[0, 1, 2], [0, 2, 3]])
+    b_tris = (bt[None] + 4 + (np.arange(n_b) * nbv)[:, None, None]).reshape(-1, 3)
+    v_tris = (vt[None] + 4 + n_b * nbv + (np.arange(n_v) * nvv)[:, None, None]).reshape(-1, 3)
+    tris = np.concatenate([g_t, b_tris, v_tris]).astype(np.int32)
+    tri_face = np.concatenate([[0, 0], (bf[None] + 1 + 6 * np.arange(n_b)[:, None]).ravel(),
+                               (vf[None] + 1 + 6 * n_b + 6 * np.arange(n_v)[:, None]).ravel()]).astype(np.int32)
+    face_material = np.concatenate([[1], np.zeros(6 * n_b), np.full(6 * n_v, 2)]).astype(np.int32)
+    face_object = np.concatenate([[-1], np.full(6 * n_b, -1), np.repeat(np.arange(n_v), 6)]).astype(np.int32)
+    v0 = 4 + n_b * nbv
+    obj_range = np.stack([v0 + np.arange(n_v) * nvv, v0 + (np.arange(n_v) + 1) * nvv], 1).astype(np.int64)
+    # transmitters: 2 m masts 0.5 m inside a roof corner of random blocks
+    txs = []
+    for k in range(n_tx):
+        i, j = rng.integers(0, G, size=2)
+        txs.append((origin(i) + BLOCK - 0.5, origin(j) + BLOCK - 0.5, heights[i, j] + 2.0))
+    centres = np.array([centre(k) for k in range(G + 1)])
+    rx = []
+    while len(rx) < n_rx:
+        street = int(rng.integers(0, 2 * (G + 1)))
+        side = 1.0 if rng.integers(0, 2) == 1 else -1.0
+        off = rng.uniform(4.5, 7.0)
+        along = rng.uniform(-half + 2.5, half - 2.5)
+        if np.any(np.abs(along - centres) < STREET / 2 + 0.5):
+            continue
+        c = centres[street % (G + 1)]
+        rx.append((along, c + side * off, 1.5) if street <= G else (c + side * off, along, 1.5))
+    dt = 0.1
+
+    def transforms(frame: int) -> np.ndarray:
+        xf = identity_transforms(n_v)
+        for v, (axis, dirn, u, speed) in enumerate(veh):
+            p_ = u + dirn * speed * frame * dt
+            p_ = -half + np.mod(p_ + half, extent)
+            xf[v, axis, 3] = np.float32(p_ - u)
+        return xf
+
+    return Scene(name="ragged_city", vertices=verts, tris=tris, tri_face=tri_face, face_material=face_material,
+                 face_object=face_object, materials=np.array([CONCRETE, GROUND, METAL], np.float64),
+                 object_vertex_range=obj_range, tx=np.array(txs, np.float32), rx=np.array(rx, np.float32),
+                 rx_radius=0.5, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=list(freqs_hz),
+                 n_frames=n_frames, dt=dt, transforms_fn=transforms)
+
+
+def batched_workload(n_scenes: int = 64, seed: int = 3, tri_range=(10_000, 500_000), budget_range=(1 << 18, 1 << 22),
+                     rx_range=(64, 1024), tx_range=(1, 8), k_range=(2, 6), bands=(28e9, 60e9)):
+    """Ragged batch of independent cities: triangle counts and ray budgets
+    log-uniform over their ranges, 1-8 transmitters (the budget is split
+    over them), 2-6 reflections, 64-1024 receivers and one band (28 or 60 GHz)
+    per scene, all from `seed`."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_scenes):
+        tris = int(np.exp(rng.uniform(np.log(tri_range[0]), np.log(tri_range[1]))))
+        budget = int(np.exp(rng.uniform(np.log(budget_range[0]), np.log(budget_range[1]))))
+        n_tx = int(rng.integers(tx_range[0], tx_range[1] + 1))
+        n_rx = int(np.exp(rng.uniform(np.log(rx_range[0]), np.log(rx_range[1]))))
+        K = int(rng.integers(k_range[0], k_range[1] + 1))
+        band = float(bands[int(rng.integers(0, len(bands)))])
+        out.append(ragged_city(seed * 1000 + k, tris, n_tx=n_tx, n_rx=n_rx, n_rays=max(budget // n_tx, 1),
+                               max_reflections=K, freqs_hz=(band,)))
+    return out
+
+
 def random_sphere_dirs(n: int, seed: int) -> np.ndarray:
     """n random directions, uniform on the unit sphere (the paper's 'random sphere of rays')."""
     rng = np.random.default_rng(seed)

@@ -82,3 +82,53 @@ def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captu
     st = compare_frame(ctx, scene, ofr, out, o_dirs.shape[0], check_captures=check_captures,
                        check_paths=check_paths)
     return st, out, ofr
+
+
+def check_full_size_sampled(ctx, O, s, frame, stride=16, min_keys=10):
+    """The context's last frame of scene `s` (its Fibonacci rays) against the
+    oracle on every `stride`-th ray of every transmitter: per-ray hits, lengths and captures, then
+    every key the sampled rays' certain captures give, refined by the oracle
+    and compared with the GPU's path (validity, length, delay, directions,
+    field).  The GPU's powers are the coherent and incoherent sums of its own
+    valid paths in key order."""
+    g_tri, g_t, g_len = ctx.trace_log()
+    g_dirs = ctx.ray_dirs()
+    o_dirs = O.fibonacci(s.n_rays)
+    assert np.array_equal(g_dirs, o_dirs)
+    ids = np.arange(0, s.n_rays, stride, dtype=np.int64)
+    osc = O.OracleScene(s, s.transforms(frame))
+    otr = O.trace(osc, s.tx, s.rx, s.rx_radius, o_dirs, s.max_reflections, ray_ids=ids)
+    st = parity.compare_trace(g_tri[:, ids], g_t[:, ids], g_len[:, ids], otr, s.tri_face, radius=radius_of(s))
+    log("  sampled trace", st)
+    g_caps = ctx.captures()
+    sel = (g_caps[:, 0] >= 0) & np.isin(g_caps[:, 0] % s.n_rays, ids)
+    pos = {int(r): i for i, r in enumerate(ids)}
+    parity.compare_captures(g_caps[sel], otr, pos, s.n_rays)
+    # oracle-derived keys: certain captures of the sampled rays, refined by the oracle
+    hit = otr.caps[otr.cap_flags == parity.CAP_HIT][:, 1:]
+    keys = np.unique(np.concatenate([hit, O.los_keys(s.tx.shape[0], s.rx.shape[0], s.max_reflections)]), axis=0)
+    gp = ctx.paths()
+    gk = {tuple(int(x) for x in k): i for i, k in enumerate(gp["keys"])}
+    op = O.refine(osc, s.tx, s.rx, keys, s.max_reflections, s.freqs_hz, s.tx_power_w)
+    checked = 0
+    for j, k in enumerate(keys):
+        i = gk.get(tuple(int(x) for x in k))
+        assert i is not None, "oracle key %s not found on the GPU" % (k,)
+        if op.marginal[j]:
+            continue
+        bad = parity.compare_path_attrs(gp, i, op, j)
+        assert not bad, (k, bad)
+        checked += int(op.valid[j])
+    log("  oracle-derived valid paths checked", checked, "of", len(keys), "keys")
+    assert len(keys) >= min_keys and checked >= min_keys
+    # powers: sums of the GPU's own valid paths in key order
+    pc, pi = ctx.received_power()
+    nf, ntx = len(s.freqs_hz), s.tx.shape[0]
+    acc = np.zeros((nf, ntx, s.rx.shape[0], 3), complex)
+    inc = np.zeros((nf, ntx, s.rx.shape[0]))
+    for i, k in enumerate(gp["keys"]):
+        if gp["valid"][i]:
+            acc[:, k[0], k[1]] += gp["amp"][i]
+            inc[:, k[0], k[1]] += np.sum(np.abs(gp["amp"][i]) ** 2, axis=-1)
+    np.testing.assert_allclose(pc, np.sum(np.abs(acc) ** 2, axis=-1), rtol=1e-9, atol=0)
+    np.testing.assert_allclose(pi, inc, rtol=1e-9, atol=0)

@@ -12,8 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2112_07115_amd import dcem, scenes
-from tests.gpu_frames import assert_comparable, compare_frame, log
-from tests.test_gpu_parity import check_full_size_sampled
+from tests.gpu_frames import assert_comparable, check_full_size_sampled, compare_frame, log
 
 pytestmark = pytest.mark.gpu
 

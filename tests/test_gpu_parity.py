@@ -13,7 +13,7 @@ import pytest
 from paper_2112_07115_amd import dcem, scenes
 from tests import parity
 from tests.bvh_check import check_bvh
-from tests.gpu_frames import assert_comparable, log, radius_of, run_pair
+from tests.gpu_frames import assert_comparable, check_full_size_sampled, log, radius_of, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -97,55 +97,6 @@ def test_urban_full_size_frame0(ctx, O):
     assert st["rays_fully_certain"] > 0.99 * st["rays"]
     assert_comparable(st)
     assert ofr.paths.valid.sum() > 100
-
-
-def check_full_size_sampled(ctx, O, s, frame, stride=16):
-    """The context's last frame of scene `s` (2^20 Fibonacci rays) against the
-    oracle on every `stride`-th ray: per-ray hits, lengths and captures, then
-    every key the sampled rays' certain captures give, refined by the oracle
-    and compared with the GPU's path (validity, length, delay, directions,
-    field).  The GPU's powers are the coherent and incoherent sums of its own
-    valid paths in key order."""
-    g_tri, g_t, g_len = ctx.trace_log()
-    g_dirs = ctx.ray_dirs()
-    o_dirs = O.fibonacci(s.n_rays)
-    assert np.array_equal(g_dirs, o_dirs)
-    ids = np.arange(0, s.n_rays, stride, dtype=np.int64)
-    osc = O.OracleScene(s, s.transforms(frame))
-    otr = O.trace(osc, s.tx, s.rx, s.rx_radius, o_dirs, s.max_reflections, ray_ids=ids)
-    st = parity.compare_trace(g_tri[:, ids], g_t[:, ids], g_len[:, ids], otr, s.tri_face, radius=radius_of(s))
-    log("  sampled trace", st)
-    g_caps = ctx.captures()
-    sel = np.isin(g_caps[:, 0], ids)
-    pos = {int(r): i for i, r in enumerate(ids)}
-    parity.compare_captures(g_caps[sel], otr, pos, s.n_rays)
-    # oracle-derived keys: certain captures of the sampled rays, refined by the oracle
-    hit = otr.caps[otr.cap_flags == parity.CAP_HIT][:, 1:]
-    keys = np.unique(hit, axis=0)
-    gp = ctx.paths()
-    gk = {tuple(int(x) for x in k): i for i, k in enumerate(gp["keys"])}
-    op = O.refine(osc, s.tx, s.rx, keys, s.max_reflections, s.freqs_hz, s.tx_power_w)
-    checked = 0
-    for j, k in enumerate(keys):
-        i = gk.get(tuple(int(x) for x in k))
-        assert i is not None, "oracle key %s not found on the GPU" % (k,)
-        if op.marginal[j]:
-            continue
-        bad = parity.compare_path_attrs(gp, i, op, j)
-        assert not bad, (k, bad)
-        checked += int(op.valid[j])
-    log("  oracle-derived valid paths checked", checked, "of", len(keys), "keys")
-    assert len(keys) >= 10 and checked >= 10
-    # powers: sums of the GPU's own valid paths in key order
-    pc, pi = ctx.received_power()
-    acc = np.zeros((1, 1, s.rx.shape[0], 3), complex)
-    inc = np.zeros((1, 1, s.rx.shape[0]))
-    for i, k in enumerate(gp["keys"]):
-        if gp["valid"][i]:
-            acc[:, k[0], k[1]] += gp["amp"][i]
-            inc[:, k[0], k[1]] += np.sum(np.abs(gp["amp"][i]) ** 2, axis=-1)
-    np.testing.assert_allclose(pc, np.sum(np.abs(acc) ** 2, axis=-1), rtol=1e-9, atol=0)
-    np.testing.assert_allclose(pi, inc, rtol=1e-9, atol=0)
 
 
 def test_urban_full_size_sampled(ctx, O):
