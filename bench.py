@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["both", "coherent", "full"], default="both")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batched workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -106,6 +107,80 @@ def gradient_timing(scene, n_rays, calls=20):
             "outputs": "dP/d eps_r and dP/d sigma of %d materials, dP/dP_t and dP/dw of the 16 transmit "
                        "pattern weights for %d receivers, frame 1"
                        % (scene.materials.shape[0], scene.rx.shape[0])}
+
+
+def batched_bench(torch, steps=3, n_scenes=64):
+    """The ragged batch workload: 64 independent cities (10k-500k triangles,
+    1-8 transmitters, 256k-4M rays, 2-6 reflections, 64-1024 receivers, 28 or
+    60 GHz), one frame of each per step.  Timed three ways, each step from the
+    object transforms to every scene's powers read back: one batched frame
+    (one persistent trace launch for all scenes, shape from the autotuner),
+    the same captured as one HIP graph, and the 64 scenes traced one after
+    the other with their own launches."""
+    from paper_2112_07115_amd import dcem, scenes
+    ws = scenes.batched_workload(n_scenes, seed=3)
+    stream = torch.cuda.Stream()
+    out = {"scenes": n_scenes, "triangles": int(sum(s.n_tris for s in ws)),
+           "rays_per_frame": int(sum(s.n_rays * s.tx.shape[0] for s in ws))}
+    with torch.cuda.stream(stream):
+        ctxs = [dcem.Context(0, stream=stream.cuda_stream) for _ in ws]
+        xfs = []
+        for c, s in zip(ctxs, ws):
+            c.scene_upload(s)
+            xfs.append(torch.tensor(np.stack([s.transforms(f) for f in range(s.n_frames)]), device="cuda"))
+        frames = [dcem.scene_frame_args(s) for s in ws]
+        batch = dcem.Batch(ctxs)
+
+        def place(f):
+            for c, s, x in zip(ctxs, ws, xfs):
+                c.set_object_transforms(x[f % s.n_frames])
+                c.refit_bvh()
+
+        def read():
+            for c in ctxs:
+                c.received_power()
+
+        place(0)
+        t0 = time.perf_counter()
+        out["tuning"] = batch.tune(frames, repeats=1)
+        out["tuning"]["s"] = time.perf_counter() - t0
+        read()
+
+        def timed(step_fn):
+            step_fn(1)   # warm-up (buffers, graph instantiation)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for f in range(2, 2 + steps):
+                step_fn(f)
+            stream.synchronize()
+            return (time.perf_counter() - t0) / steps
+
+        def batched(f):
+            place(f)
+            batch.trace(frames)
+            read()
+
+        def single(f):
+            place(f)
+            for c, fa in zip(ctxs, frames):
+                c.trace_frame(**fa)
+            read()
+
+        t_b = timed(batched)
+        batch.set_graph(True)
+        t_g = timed(batched)
+        graph_frames = batch.info()["graph_frames"]
+        batch.set_graph(False)
+        t_s = timed(single)
+        batch.close()
+        for c in ctxs:
+            c.close()
+    n = out["rays_per_frame"]
+    out.update({"steps": steps, "ms_per_frame_batched": t_b * 1e3, "ms_per_frame_batched_graph": t_g * 1e3,
+                "graph_frames": graph_frames, "ms_per_frame_single": t_s * 1e3,
+                "mrays_per_s_batched": n / t_b / 1e6, "mrays_per_s_batched_graph": n / t_g / 1e6,
+                "mrays_per_s_single": n / t_s / 1e6, "batched_speedup": t_s / t_b})
+    return out
 
 
 def cpu_info():
@@ -303,6 +378,8 @@ def main():
     if "full" in res and main_mode != "full":
         out["roofline_full_trace"] = roofline(res["full"][2], "full")
     out["power_gradients"] = gradient_timing(scene, n)
+    if not args.no_batch and args.mode == "both":
+        out["batched"] = batched_bench(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out))
