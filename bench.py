@@ -183,6 +183,61 @@ def batched_bench(torch, steps=3, n_scenes=64):
     return out
 
 
+def large_bench(torch, frames=6):
+    """The large dynamic workload: a 6 km highway corridor beside a 16x16
+    block city (2.04M triangles), 200 vehicles at 15-35 m/s carrying 4096
+    receivers, 4 roadside transmitters x 4M Fibonacci rays (16.8M rays per
+    frame), 6 reflections, 28 and 60 GHz from one trace.  Coherent frames
+    (refit, revalidation, re-capture of the kept segments at the moved
+    receivers, re-trace of the invalidated rays) against full frames
+    (rebuild, trace every ray); both equal bitwise.  Frame 0 is the
+    first full trace of each context and is not timed.  Also the power
+    gradients of one frame (8 derivatives per receiver and band: the 3
+    materials' eps_r and sigma, P_t; plus 16 pattern weights)."""
+    from paper_2112_07115_amd import dcem, scenes
+    s = scenes.highway_city()
+    out = {"triangles": s.n_tris, "vehicles": s.n_objects, "receivers": int(s.rx.shape[0]), "tx": int(s.tx.shape[0]),
+           "rays_per_frame": int(s.n_rays * s.tx.shape[0]), "max_reflections": s.max_reflections,
+           "bands_ghz": [f / 1e9 for f in s.freqs_hz]}
+    res = {}
+    for mode in ("coherent", "full"):
+        ctx = dcem.Context(0)
+        ctx.set_capture_capacity(1 << 24)
+        ctx.scene_upload(s)
+        last = None
+        dcem.trace_scene_frame(ctx, s, frame=0, mode=dcem.MODE_COHERENT if mode == "coherent" else dcem.MODE_FULL,
+                               rebuild=mode == "full")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        traced = 0
+        for f in range(1, frames + 1):
+            last = dcem.trace_scene_frame(ctx, s, frame=f, rebuild=mode == "full",
+                                          mode=dcem.MODE_COHERENT if mode == "coherent" else dcem.MODE_FULL)
+            traced += ctx.stats()["rays_traced"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / frames
+        st = ctx.stats()
+        res[mode] = {"ms_per_frame": dt * 1e3, "frames_per_s": 1.0 / dt,
+                     "mrays_per_s": out["rays_per_frame"] / dt / 1e6,
+                     "rays_traced_fraction": traced / (frames * out["rays_per_frame"]),
+                     "captures": st["captures"], "valid_paths": st["valid_paths"]}
+        if mode == "coherent":
+            g0 = time.perf_counter()
+            for _ in range(5):
+                ctx.power_gradients()
+            gdt = (time.perf_counter() - g0) / 5
+            res["power_gradients"] = {"ms_per_call": gdt * 1e3, "valid_paths": st["valid_paths"],
+                                      "paths_per_s": st["valid_paths"] / gdt,
+                                      "receiver_bands_per_s": out["receivers"] * out["tx"] * len(s.freqs_hz) / gdt}
+            coh_power = last.p_coh.copy()
+        else:
+            res["coherent_vs_full_bitwise_equal"] = bool(np.array_equal(coh_power, last.p_coh))
+        ctx.close()
+    out.update(res)
+    out["coherent_speedup"] = res["full"]["ms_per_frame"] / res["coherent"]["ms_per_frame"]
+    return out
+
+
 def cpu_info():
     model = None
     try:
@@ -380,6 +435,7 @@ def main():
     out["power_gradients"] = gradient_timing(scene, n)
     if not args.no_batch and args.mode == "both":
         out["batched"] = batched_bench(torch)
+        out["large_dynamic"] = large_bench(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out))

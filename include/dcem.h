@@ -121,9 +121,13 @@ typedef struct dcem_scene_desc {
  *  freqs_hz [n_freqs] FP64, host memory.  tx_power_w: transmit power;
  *  atten_db_per_km: Eq. (3)'s atmospheric term as a specific attenuation.
  *  mode: DCEM_MODE_FULL or DCEM_MODE_COHERENT.  COHERENT reuses the cached
- *  rays of the previous frame traced with the same transmitters, receivers,
- *  rays and max_reflections (falls back to FULL otherwise; ray_dirs given in
- *  device memory are re-read every frame and always count as changed).
+ *  rays of the previous frame traced with the same transmitters, rays,
+ *  max_reflections, receiver count and capture radius (falls back to FULL
+ *  otherwise; ray_dirs given in device memory are re-read every frame and
+ *  always count as changed).  Receivers may move between coherent frames
+ *  (vehicle-mounted receivers): the captures of every reused segment are then
+ *  taken again against the new positions from the cached segments, so the
+ *  frame still equals a full re-trace.
  *  los_always: 1 adds the direct path of every (tx, rx) pair as a candidate
  *  (direct rays are their own mechanism, Sec. III); 0 keeps only captured ones.
  *  keep_cache: 1 stores the per-ray segments needed by the next COHERENT

@@ -395,10 +395,12 @@ def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Opt
         dirs = fibonacci(scene.n_rays)
     xf = scene.transforms(frame_index) if scene.object_vertex_range.shape[0] else None
     osc = OracleScene(scene, xf)
-    tr = trace(osc, scene.tx, scene.rx, scene.rx_radius, dirs, K, nthreads=nthreads)
-    ntx, nrx = scene.tx.shape[0], scene.rx.shape[0]
+    # receivers of this frame (vehicle-mounted receivers move with their vehicles)
+    rx = scene.rx_at(frame_index) if hasattr(scene, "rx_at") else scene.rx
+    tr = trace(osc, scene.tx, rx, scene.rx_radius, dirs, K, nthreads=nthreads)
+    ntx, nrx = scene.tx.shape[0], rx.shape[0]
     keys, certain, possible = candidates(tr, ntx, nrx, K, los_always)
-    paths = refine(osc, scene.tx, scene.rx, keys, K, freqs, tx_power_w, atten_db_per_km,
+    paths = refine(osc, scene.tx, rx, keys, K, freqs, tx_power_w, atten_db_per_km,
                    nthreads=nthreads, pattern=pattern)
     p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))
     return FrameResult(tr, keys, certain, possible, paths, p_coh, p_inc)

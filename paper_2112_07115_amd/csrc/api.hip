@@ -714,6 +714,7 @@ struct FramePlan {
   bool small = false;       // one-workgroup candidate de-duplication
   bool ahead = false;       // the frame's start and revalidation are already enqueued
   bool los = true;
+  bool recapture = false;   // coherent frame whose receivers moved: kept segments captured again
   int64_t n_work = 0;       // n_tx * n_rays
   int64_t expected = 0;     // work items the trace is sized for
   uint32_t n_prev = 0;      // captures of the previous frame (kept by a coherent frame)
@@ -774,13 +775,19 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
     for (float v : dirh) if (!std::isfinite(v)) return fail(c, DCEM_E_INVALID_ARG, "non-finite ray direction");
   }
   TraceConfig& cfg = c->cfg;
-  const bool same = cfg.n_tx == p->n_tx && cfg.n_rx == p->n_rx && cfg.K == p->max_reflections &&
-                    cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius && cfg.tx == txh && cfg.rx == rxh &&
-                    cfg.dirs_fib == fib && (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
-  const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same;
+  // the cached rays stay valid while the transmitters, the rays and the
+  // bounce limit stay; receivers may move (their captures are then taken
+  // again from the cached segments)
+  const bool same_geom = cfg.n_tx == p->n_tx && cfg.n_rx == p->n_rx && cfg.K == p->max_reflections &&
+                         cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius && cfg.tx == txh &&
+                         cfg.dirs_fib == fib && (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
+  const bool rx_moved = cfg.rx != rxh;
+  const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same_geom;
   const bool keep_cache = p->keep_cache != 0 || p->mode == DCEM_MODE_COHERENT;
+  plan.recapture = coherent && rx_moved;
   // -- device inputs
-  const bool need_dirs = !same || !c->has_frame;
+  const bool need_dirs = !same_geom || !c->has_frame;
+  const bool need_rx = need_dirs || rx_moved;
   cfg.n_tx = p->n_tx;
   cfg.n_rx = p->n_rx;
   cfg.K = p->max_reflections;
@@ -804,8 +811,8 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
     c->mat_pending = false;
   }
   c->record_log = p->record_trace_log != 0;
-  if (need_dirs) {   // transmitters, receivers or rays changed
-    HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");
+  if (need_dirs) HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");   // transmitters or rays changed
+  if (need_rx) {
     HIP_TRY(upload(c->rx_pos, rxh, c->stream), "upload rx");
     std::vector<Node> rt = build_rx_tree(rxh, p->rx_radius);
     c->n_rx_nodes = (int32_t)rt.size();
@@ -814,7 +821,7 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   }
   {
     std::vector<double> fv(p->freqs_hz, p->freqs_hz + p->n_freqs);
-    if (fv != c->freqs_host || need_dirs) {
+    if (fv != c->freqs_host || need_dirs || c->freqs_host.empty()) {
       HIP_TRY(upload(c->freqs, fv, c->stream), "upload freqs");
       c->freqs_host = fv;
     }
@@ -852,10 +859,10 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   // counts of the previous frame (read above): its capture list (reused by a
   // coherent frame), its re-trace count (sizes the persistent grid) and its
   // capture count (picks the de-duplication path)
-  plan.n_prev = (uint32_t)c->n_caps_host;
+  plan.n_prev = plan.recapture ? 0u : (uint32_t)c->n_caps_host;   // moved receivers: captures taken again
   plan.n_work = n_work;
   plan.expected = coherent ? ((c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work) : n_work;
-  plan.small = c->has_frame && same && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
+  plan.small = c->has_frame && same_geom && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
   plan.coherent = coherent;
   plan.keep_cache = keep_cache;
   plan.los = p->los_always != 0;
@@ -897,6 +904,7 @@ dcem_status frame_front(dcem_ctx* c, const FramePlan& plan) {
 // The frame's own closest-hit launch.
 dcem_status frame_trace(dcem_ctx* c, const FramePlan& plan) {
   ev_record(c, 8);
+  if (plan.recapture && plan.n_work > 0) launch_recapture(c);
   const int traversal =
       plan.n_work > 0 ? launch_trace(c, !plan.coherent, plan.keep_cache, plan.expected, plan.n_prev) : 0;
   if (traversal < 0) return fail(c, DCEM_E_OUT_OF_MEMORY, "alloc traversal stack");

@@ -313,6 +313,9 @@ void launch_fibonacci(dcem_ctx* c);
 // space could not be allocated (nothing launched).
 int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps);
 void launch_coherence(dcem_ctx* c);
+// Coherent frame with moved receivers: captures of the kept segments of every
+// cached ray against the current receivers (after the revalidation pass).
+void launch_recapture(dcem_ctx* c);
 // The pending refit of the 4-wide tree and the revalidation pass in one launch.
 void launch_refit_coherence(dcem_ctx* c, bool begin);
 // Clear the frame counters and seed the capture list with the LoS candidates.

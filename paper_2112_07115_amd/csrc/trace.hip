@@ -345,6 +345,58 @@ __device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const floa
   setup_ray(r);
 }
 
+// Captures of one segment [o, o + tend d] (tend infinite on a miss; th its
+// hit distance): receivers whose padded box the segment meets, by the
+// receiver tree, then the exact closest-approach test; records appended to
+// the frame's capture list.
+__device__ void capture_segment(const TraceArgs& a, const Ray& r, bool hit, float th, float tend, float dd,
+                                uint32_t work, uint32_t txi, int k, ThreadStack& stack, bool& overflow,
+                                bool& cap_over) {
+  const float za = r.o.z;
+  const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
+  if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+    int node = 0, sp = 0;
+    for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
+      const Node nd = a.rx_nodes[node];
+      float t0, t1;
+      bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, tend, t0);
+      bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, tend, t1);
+      const int c0 = nd.c.x, c1 = nd.c.y;
+      for (int side = 0; side < 2; ++side) {
+        const int cc = side ? c1 : c0;
+        const bool hh = side ? h1 : h0;
+        if (!(hh && cc < 0) || (side == 1 && c1 == c0)) continue;   // a lone sphere fills both slots
+        const int c = ~cc;
+        if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
+          const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
+          if (slot < a.cap_capacity) {
+            Capture cp;
+            cp.work = work;
+            cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
+            a.caps[slot] = cp;
+          } else {
+            cap_over = true;
+          }
+        }
+      }
+      h0 = h0 && c0 >= 0;
+      h1 = h1 && c1 >= 0;
+      if (h0 && h1) {
+        if (sp < stack.cap) stack.put(sp++, c1);
+        else overflow = true;
+        node = c0;
+      } else if (h0) {
+        node = c0;
+      } else if (h1) {
+        node = c1;
+      } else {
+        if (sp == 0) break;
+        node = stack.get(--sp);
+      }
+    }
+  }
+}
+
 // Per-thread tracing of one work item (a ray, from its first segment or, in
 // work-list mode, from its restart segment): closest hits, captures,
 // reflections, the per-bounce face log and segment cache.
@@ -402,50 +454,7 @@ __device__ void trace_item(const TraceArgs& a, uint32_t wi, const Node4* top, in
       a.log_t[li] = hit ? h.t : INFINITY;
       a.log_len[li] = hit ? L_hit : INFINITY;
     }
-    // capture: spheres whose padded box the segment meets, then the exact test
-    const float za = r.o.z;
-    const float zb = hit ? __fmaf_rn(h.t, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
-    if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
-      int node = 0, sp = 0;
-      for (int guard = 2 * a.n_rx_nodes + 2; guard > 0; --guard) {
-        const Node nd = a.rx_nodes[node];
-        float t0, t1;
-        bool h0 = slab(r, nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, tend, t0);
-        bool h1 = slab(r, nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, tend, t1);
-        const int c0 = nd.c.x, c1 = nd.c.y;
-        for (int side = 0; side < 2; ++side) {
-          const int cc = side ? c1 : c0;
-          const bool hh = side ? h1 : h0;
-          if (!(hh && cc < 0) || (side == 1 && c1 == c0)) continue;   // a lone sphere fills both slots
-          const int c = ~cc;
-          if (captured(r, tend, dd, a.rx[3 * c], a.rx[3 * c + 1], a.rx[3 * c + 2], a.r2)) {
-            const uint32_t slot = atomicAdd(&a.counters[kCntCaptures], 1u);
-            if (slot < a.cap_capacity) {
-              Capture cp;
-              cp.work = work;
-              cp.pair_order = ((txi * (uint32_t)a.n_rx + (uint32_t)c) << 4) | (uint32_t)k;
-              a.caps[slot] = cp;
-            } else {
-              cap_over = true;
-            }
-          }
-        }
-        h0 = h0 && c0 >= 0;
-        h1 = h1 && c1 >= 0;
-        if (h0 && h1) {
-          if (sp < stack.cap) stack.put(sp++, c1);
-          else overflow = true;
-          node = c0;
-        } else if (h0) {
-          node = c0;
-        } else if (h1) {
-          node = c1;
-        } else {
-          if (sp == 0) break;
-          node = stack.get(--sp);
-        }
-      }
-    }
+    capture_segment(a, r, hit, h.t, tend, dd, work, txi, k, stack, overflow, cap_over);
     if (!hit || k == a.K) { ++k; break; }
     // specular reflection off the hit triangle's plane
     L = L_hit;
@@ -510,6 +519,37 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     if (wi < n_work) trace_item(a, wi, top, n_top, n4, stack, ic);
   }
   flush_counts(a, ic);
+}
+
+// Coherent frames whose receivers moved: the captures of every kept segment
+// (each segment before its ray's first re-traced one, all segments of a
+// reused ray) against the receivers' current positions, from the cached
+// segment origins, directions and ends, with the arithmetic of the trace
+// kernels (a re-trace would capture exactly these).  The re-trace that
+// follows captures its own segments.
+__global__ __launch_bounds__(kTraceBlock) void k_recapture(TraceArgs a) {
+  __shared__ int stack_mem[kStackLds * kTraceBlock];
+  ThreadStack stack{stack_mem + threadIdx.x, a.stack_spill + blockIdx.x * (size_t)kTraceBlock + threadIdx.x,
+                    (size_t)gridDim.x * kTraceBlock, a.stack_thread};
+  bool overflow = false, cap_over = false;
+  const uint32_t n_work = (uint32_t)a.n_work;
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n_work; w += gridDim.x * blockDim.x) {
+    const int nseg = (int)(a.ray_state[w] & 0x0fu);
+    const int stop = min(nseg, (int)a.restart[w]);
+    const uint32_t txi = (uint32_t)(w / (uint64_t)a.n_rays);
+    for (int k = 0; k < stop; ++k) {
+      const float4 so = a.seg_o[(size_t)k * a.n_work + w];
+      const float4 sd = a.seg_d[(size_t)k * a.n_work + w];
+      Ray r;
+      r.o = make_float3(so.x, so.y, so.z);
+      r.d = make_float3(sd.x, sd.y, sd.z);
+      setup_ray(r);
+      const bool hit = so.w < INFINITY;
+      capture_segment(a, r, hit, so.w, so.w, dot_dd(r), w, txi, k, stack, overflow, cap_over);
+    }
+  }
+  if (overflow) atomicOr(a.err, DCEM_ERR_STACK);
+  if (cap_over) atomicOr(a.err, DCEM_ERR_CAPTURES);
 }
 
 // Full traces of several scenes in one persistent launch.  args[j] describes
@@ -1382,6 +1422,14 @@ hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, in
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+void launch_recapture(dcem_ctx* c) {
+  TraceArgs a = trace_args(c, false, true, 0u);
+  a.stack_spill = ptr<int>(c->stack_spill);
+  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(trace_grid(c), (n_work + kTraceBlock - 1) / kTraceBlock));
+  hipLaunchKernelGGL(k_recapture, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
 }
 
 hipError_t prepare_trace(dcem_ctx* c) {

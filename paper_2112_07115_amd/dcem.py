@@ -496,7 +496,8 @@ class Batch:
 
 def scene_frame_args(scene, frame: int = 0, mode: int = MODE_FULL, **kw) -> dict:
     """Context.trace_frame keyword arguments of one frame of a scene."""
-    args = dict(tx=scene.tx, rx=scene.rx, rx_radius=scene.rx_radius, n_rays=scene.n_rays,
+    args = dict(tx=scene.tx, rx=scene.rx_at(frame) if hasattr(scene, "rx_at") else scene.rx,
+                rx_radius=scene.rx_radius, n_rays=scene.n_rays,
                 max_reflections=scene.max_reflections, freqs_hz=scene.freqs_hz, tx_power_w=scene.tx_power_w,
                 mode=mode)
     args.update(kw)
@@ -520,7 +521,8 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
     n = scene.n_rays if n_rays is None else n_rays
     if ray_dirs is not None:
         n = ray_dirs.shape[0]
-    ctx.trace_frame(scene.tx, scene.rx, scene.rx_radius, n, ray_dirs=ray_dirs,
+    rx = scene.rx_at(frame) if hasattr(scene, "rx_at") else scene.rx
+    ctx.trace_frame(scene.tx, rx, scene.rx_radius, n, ray_dirs=ray_dirs,
                     max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
                     tx_power_w=scene.tx_power_w, atten_db_per_km=atten_db_per_km, mode=mode,
                     los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log)

@@ -49,6 +49,8 @@ class Scene:
     dt: float = 0.1
     # frame -> f32 [No, 3, 4] object-to-world transforms relative to the upload pose
     transforms_fn: Optional[Callable[[int], np.ndarray]] = None
+    # frame -> f32 [Nrx, 3] receiver positions (moving receivers); None: rx at every frame
+    rx_fn: Optional[Callable[[int], np.ndarray]] = None
 
     @property
     def n_tris(self) -> int:
@@ -66,6 +68,10 @@ class Scene:
         if self.transforms_fn is None or self.n_objects == 0:
             return identity_transforms(self.n_objects)
         return self.transforms_fn(frame)
+
+    def rx_at(self, frame: int) -> np.ndarray:
+        """Receiver positions at a frame (vehicle-mounted receivers move)."""
+        return self.rx if self.rx_fn is None else self.rx_fn(frame)
 
 
 def identity_transforms(n: int) -> np.ndarray:
@@ -721,6 +727,158 @@ def ragged_city(seed: int, target_tris: int, n_tx: int = 1, n_rx: int = 256, n_r
                  object_vertex_range=obj_range, tx=np.array(txs, np.float32), rx=np.array(rx, np.float32),
                  rx_radius=0.5, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=list(freqs_hz),
                  n_frames=n_frames, dt=dt, transforms_fn=transforms)
+
+
+def highway_city(seed: int = 5, grid_blocks: int = 16, facade_cells: int = 19, corridor_m: float = 6000.0,
+                 warehouses: int = 60, n_vehicles: int = 200, n_rx: int = 4096, n_tx: int = 4,
+                 n_rays: int = 1 << 22, max_reflections: int = 6, freqs_hz=(28e9, 60e9),
+                 n_frames: int = 300) -> Scene:
+    """Large dynamic scene: a highway corridor beside a city grid, with
+    receivers mounted on the moving vehicles.
+
+    City: grid_blocks^2 blocks of 40 m with 15 m streets centred on the
+    origin, concrete buildings of height U(10, 60) m, facades tessellated
+    facade_cells x 2 facade_cells per side.  Corridor: a straight highway of
+    corridor_m along x, 60 m south of the grid, four lanes (centres +-2 and
+    +-6 m), 4 m concrete noise barriers 12 m either side of the centre line
+    (4 m x 2 m cells), and `warehouses` 50 x 25 m buildings (height U(8, 16) m)
+    behind each barrier.  n_vehicles metal vehicles (4.5 x 1.8 x 1.5 m, 512
+    triangles), 60% on the highway lanes and 40% on the city streets, at
+    U(15, 35) m/s, wrapping at the ends.  n_rx receivers on the vehicle roofs
+    (0.2 m above, spread over each roof), moving with them.  n_tx roadside
+    transmitters on 10 m poles 9 m north of the centre line, evenly along the
+    corridor.  With the defaults about 2M triangles."""
+    rng = np.random.default_rng(seed)
+    G = grid_blocks
+    extent = G * BLOCK + (G + 1) * STREET
+    half = extent / 2.0
+    origin = lambda i: -half + STREET + i * (BLOCK + STREET)
+    centre = lambda k: -half + STREET / 2.0 + k * (BLOCK + STREET)
+    yc = -(half + 60.0)   # corridor centre line
+    Lc = corridor_m
+    parts_v, parts_t, parts_f, mats, objs = [], [], [], [], []
+    nv = 0
+    nfaces = 0
+
+    def add_boxes(lo, size, cells, material, obj_ids=None):
+        nonlocal nv, nfaces
+        tv, tt, tf = _box_template(cells)
+        n = lo.shape[0]
+        verts = lo[:, None, :] + size[:, None, :] * tv[None]
+        parts_v.append(verts.reshape(-1, 3))
+        parts_t.append((tt[None] + nv + (np.arange(n) * tv.shape[0])[:, None, None]).reshape(-1, 3))
+        parts_f.append((tf[None] + nfaces + 6 * np.arange(n)[:, None]).ravel())
+        mats.append(np.full(6 * n, material))
+        objs.append(np.full(6 * n, -1) if obj_ids is None else np.repeat(obj_ids, 6))
+        first = nv
+        nv += n * tv.shape[0]
+        nfaces += 6 * n
+        return first, tv.shape[0]
+
+    # ground (one face)
+    x0, x1 = -Lc / 2 - 50.0, Lc / 2 + 50.0
+    y0, y1 = yc - 100.0, half + 20.0
+    parts_v.append(np.array([[x0, y0, 0.0], [x1, y0, 0.0], [x1, y1, 0.0], [x0, y1, 0.0]]))
+    parts_t.append(np.array([[0, 1, 2], [0, 2, 3]]))
+    parts_f.append(np.array([0, 0]))
+    mats.append(np.array([1]))
+    objs.append(np.array([-1]))
+    nv, nfaces = 4, 1
+    # city buildings
+    heights = rng.uniform(10.0, 60.0, size=(G, G))
+    ii, jj = np.meshgrid(np.arange(G), np.arange(G), indexing="ij")
+    lo = np.stack([origin(ii.ravel()), origin(jj.ravel()), np.zeros(G * G)], 1)
+    size = np.stack([np.full(G * G, BLOCK), np.full(G * G, BLOCK), heights.ravel()], 1)
+    add_boxes(lo, size, (facade_cells, facade_cells, 2 * facade_cells), 0)
+    # noise barriers: thin boxes 0.3 m thick, 4 m tall
+    n_seg = max(1, int(round(Lc / 200.0)))
+    seg_len = Lc / n_seg
+    bx = -Lc / 2 + seg_len * np.arange(n_seg)
+    for side in (-1.0, 1.0):
+        lo = np.stack([bx, np.full(n_seg, yc + side * 12.0 - 0.15), np.zeros(n_seg)], 1)
+        size = np.stack([np.full(n_seg, seg_len), np.full(n_seg, 0.3), np.full(n_seg, 4.0)], 1)
+        add_boxes(lo, size, (int(seg_len / 4.0), 1, 2), 0)
+    # warehouses behind the barriers
+    if warehouses > 0:
+        wx = -Lc / 2 + (np.arange(warehouses) + 0.5) * (Lc / warehouses) - 25.0
+        for side in (-1.0, 1.0):
+            y_lo = yc + side * 25.0 - (25.0 if side < 0 else 0.0)
+            lo = np.stack([wx, np.full(warehouses, y_lo), np.zeros(warehouses)], 1)
+            size = np.stack([np.full(warehouses, 50.0), np.full(warehouses, 25.0), rng.uniform(8.0, 16.0, warehouses)], 1)
+            add_boxes(lo, size, (10, 5, 4), 0)
+    # vehicles
+    L, W, H = VEHICLE
+    veh = []   # (axis, dir, u, speed, lo_xyz, size_xyz, lane period start, period)
+    n_hw = int(round(0.6 * n_vehicles))
+    lanes = [(-6.0, -1.0), (-2.0, -1.0), (2.0, 1.0), (6.0, 1.0)]
+    v_lo, v_size = [], []
+    for v in range(n_vehicles):
+        speed = rng.uniform(15.0, 35.0)
+        if v < n_hw:
+            off, dirn = lanes[int(rng.integers(0, 4))]
+            u = rng.uniform(-Lc / 2, Lc / 2)
+            veh.append((0, dirn, u, speed, -Lc / 2, Lc))
+            v_lo.append((u - L / 2, yc + off - W / 2, VEHICLE_CLEARANCE))
+            v_size.append((L, W, H))
+        else:
+            street = int(rng.integers(0, 2 * (G + 1)))
+            lane = int(rng.integers(0, 2))
+            u = rng.uniform(-half, half)
+            c = centre(street % (G + 1))
+            if street <= G:
+                lane_c, dirn = (c - LANE_OFFSET, 1.0) if lane == 0 else (c + LANE_OFFSET, -1.0)
+                veh.append((0, dirn, u, speed, -half, extent))
+                v_lo.append((u - L / 2, lane_c - W / 2, VEHICLE_CLEARANCE))
+                v_size.append((L, W, H))
+            else:
+                lane_c, dirn = (c + LANE_OFFSET, 1.0) if lane == 0 else (c - LANE_OFFSET, -1.0)
+                veh.append((1, dirn, u, speed, -half, extent))
+                v_lo.append((lane_c - W / 2, u - L / 2, VEHICLE_CLEARANCE))
+                v_size.append((W, L, H))
+    v_lo, v_size = np.asarray(v_lo), np.asarray(v_size)
+    v_first, v_nv = add_boxes(v_lo, v_size, (12, 5, 4), 2, obj_ids=np.arange(n_vehicles))
+    verts = np.concatenate(parts_v).astype(np.float32)
+    tris = np.concatenate(parts_t).astype(np.int32)
+    tri_face = np.concatenate(parts_f).astype(np.int32)
+    face_material = np.concatenate(mats).astype(np.int32)
+    face_object = np.concatenate(objs).astype(np.int32)
+    obj_range = np.stack([v_first + np.arange(n_vehicles) * v_nv, v_first + (np.arange(n_vehicles) + 1) * v_nv],
+                         1).astype(np.int64)
+    # receivers on the roofs: vehicle of each receiver and its roof position
+    rv = np.arange(n_rx) % n_vehicles
+    slot = np.arange(n_rx) // n_vehicles
+    per = np.bincount(rv, minlength=n_vehicles)
+    rx0 = np.zeros((n_rx, 3))
+    for r in range(n_rx):
+        v, k, m = rv[r], slot[r], max(per[rv[r]], 1)
+        f = (k + 0.5) / m
+        rx0[r] = (v_lo[v, 0] + v_size[v, 0] * (0.1 + 0.8 * f if veh[v][0] == 0 else 0.5),
+                  v_lo[v, 1] + v_size[v, 1] * (0.1 + 0.8 * f if veh[v][0] == 1 else 0.5),
+                  VEHICLE_CLEARANCE + H + 0.2)
+    txs = [(-Lc / 2 + (k + 0.5) * Lc / n_tx, yc + 9.0, 10.0) for k in range(n_tx)]
+    dt = 0.1
+
+    def shifts(frame: int) -> np.ndarray:
+        out = np.zeros((n_vehicles, 3))
+        for v, (axis, dirn, u, speed, start, period) in enumerate(veh):
+            p_ = u + dirn * speed * frame * dt
+            p_ = start + np.mod(p_ - start, period)
+            out[v, axis] = np.float32(p_ - u)
+        return out
+
+    def transforms(frame: int) -> np.ndarray:
+        xf = identity_transforms(n_vehicles)
+        xf[:, :, 3] = shifts(frame).astype(np.float32)
+        return xf
+
+    def rx_fn(frame: int) -> np.ndarray:
+        return (rx0 + shifts(frame)[rv]).astype(np.float32)
+
+    return Scene(name="highway_city", vertices=verts, tris=tris, tri_face=tri_face, face_material=face_material,
+                 face_object=face_object, materials=np.array([CONCRETE, GROUND, METAL], np.float64),
+                 object_vertex_range=obj_range, tx=np.array(txs, np.float32), rx=rx_fn(0), rx_radius=0.5,
+                 n_rays=n_rays, max_reflections=max_reflections, freqs_hz=list(freqs_hz), n_frames=n_frames,
+                 dt=dt, transforms_fn=transforms, rx_fn=rx_fn)
 
 
 def batched_workload(n_scenes: int = 64, seed: int = 3, tri_range=(10_000, 500_000), budget_range=(1 << 18, 1 << 22),
