@@ -362,6 +362,7 @@ __global__ void k_cross_parent(const Node* __restrict__ nodes, const int32_t* __
 }
 
 __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) { refit_block(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kRefitBlock) void k_refit_cross(RefitArgs a, int n_rb) { refit_cross_block(a, n_rb); }
 
 
 
@@ -696,6 +697,7 @@ RefitArgs make_refit_args(dcem_ctx* c, bool wide, double* sah_out) {
   a.face_ref_tri = ptr<int32_t>(c->face_ref_tri);
   a.nf = c->nf;
   a.plane = ptr<double4>(c->face_plane);
+  a.cross_kernel = c->nt > kCrossKernelLeaves;
   return a;
 }
 
@@ -703,8 +705,13 @@ int refit_blocks(const dcem_ctx* c) { return (int)((c->nt + kRefitBlock - 1) / k
 
 void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
   if (c->nt == 0) return;
-  hipLaunchKernelGGL(k_refit, dim3((unsigned)refit_blocks(c)), dim3(kRefitBlock), 0, c->stream,
-                     make_refit_args(c, wide, sah_out));
+  const RefitArgs a = make_refit_args(c, wide, sah_out);
+  hipLaunchKernelGGL(k_refit, dim3((unsigned)refit_blocks(c)), dim3(kRefitBlock), 0, c->stream, a);
+  if (a.cross_kernel) launch_refit_cross(c, a, refit_blocks(c));
+}
+
+void launch_refit_cross(dcem_ctx* c, const RefitArgs& a, int n_rb) {
+  hipLaunchKernelGGL(k_refit_cross, dim3(1), dim3(kRefitBlock), 0, c->stream, a, n_rb);
 }
 
 

@@ -37,13 +37,23 @@ struct RefitArgs {
   const int32_t* face_ref_tri;
   int nf;
   double4* plane;             // per face: unit normal and offset
+  bool cross_kernel;          // the cross nodes and the SAH sum are finished by k_refit_cross (large trees)
 };
+
+// Trees with more leaves than this finish their cross nodes in a launch of
+// their own (one block; cross nodes beyond the LDS capacity climb through
+// device memory with workgroup-scope arrivals) instead of in the refit's last
+// block, which would otherwise fall back to device-scope arrivals.
+constexpr int64_t kCrossKernelLeaves = 512 * 1024;
 
 // Arguments of a refit of the current tree (`wide`: also the 4-wide tree in
 // place), its SAH ratio written to sah_out.
 RefitArgs make_refit_args(dcem_ctx* c, bool wide, double* sah_out);
 // Refit blocks of the current tree.
 int refit_blocks(const dcem_ctx* c);
+// The cross-node pass of a large tree's refit (a.cross_kernel), after the
+// launch that ran its block pass.
+void launch_refit_cross(dcem_ctx* c, const RefitArgs& a, int n_rb);
 
 namespace {
 
@@ -190,6 +200,53 @@ __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t 
   }
 }
 
+__device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
+  float* f = reinterpret_cast<float*>(nd);
+  const int base = slot * 6;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Cross nodes finished by one block in device memory: every slot the block
+// pass listed climbs through the cross nodes above it; the second arrival at
+// a node (workgroup-scope counter: one block does all of this) forms the union
+// and writes it into the parent's slot.  Arrival counters are reset for the
+// next refit.
+__device__ __forceinline__ void climb_cross_global(const RefitArgs& a) {
+  const uint32_t n_ent = a.info[3];
+  __syncthreads();
+  if (threadIdx.x == 0) a.info[3] = 0;   // ready for the next refit
+  for (uint32_t e = threadIdx.x; e < n_ent; e += blockDim.x) {
+    int p2 = (int)a.entries[e];
+    float lo[3], hi[3];
+    load_slot_wg(&a.nodes[p2 >> 1], p2 & 1, lo, hi);
+    for (int guard = a.n_internal + 1; guard > 0; --guard) {
+      const int node = p2 >> 1, slot = p2 & 1;
+      const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      a.cnt[node] = 0;
+      float slo[3], shi[3];
+      load_slot_wg(&a.nodes[node], slot ^ 1, slo, shi);
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fminf(lo[k], slo[k]);
+        hi[k] = fmaxf(hi[k], shi[k]);
+      }
+      const int pp = a.nodes[node].c.z;
+      if (pp < 0) {
+        for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
+        break;
+      }
+      put_child_box(a, pp, a.wide ? a.slot4[pp] : -1, lo, hi);
+      p2 = pp;
+    }
+  }
+}
+
+__device__ __forceinline__ void refit_tail(const RefitArgs& a, int n_rb, bool lds, uint32_t n_cross,
+                                           float (*lbox)[12], int2* lkid, double* red);
+
 // Bottom-up refit over a fixed topology, in two passes of one kernel.
 // Block pass: one thread per leaf writes its padded box into its parent's
 // slot; the second thread to arrive at a node forms the union and climbs on.
@@ -227,7 +284,7 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
   const int b0 = rb * kRefitBlock;
   const int tid = threadIdx.x;
   const uint32_t n_cross = a.info[2];
-  const bool two_phase = n_cross <= (uint32_t)kMaxCross;
+  const bool two_phase = a.cross_kernel || n_cross <= (uint32_t)kMaxCross;   // cross slots listed
   {
     const int node = b0 + tid;
     lcnt[tid] = 0;
@@ -310,6 +367,10 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
       if (lkid[tid].y >= 0) ar += box_area(lbox[tid] + 6, lbox[tid] + 9);
     }
     ar = block_sum(ar, red);
+    if (a.cross_kernel) {   // k_refit_cross finishes, after this launch
+      if (tid == 0) a.part[rb] = ar;
+      return;
+    }
     if (tid == 0) {
       __hip_atomic_store(&a.part[rb], ar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)n_rb - 1;
@@ -321,6 +382,37 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
   if (tid == 0) a.info[4] = 0;   // ready for the next refit
   if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
   __syncthreads();
+  refit_tail(a, n_rb, two_phase, n_cross, lbox, lkid, red);
+}
+
+// The cross nodes and the SAH ratio of a large tree, after the refit's block
+// pass (one block of kRefitBlock threads).
+__device__ __forceinline__ void refit_cross_block(const RefitArgs& a, int n_rb) {
+  __shared__ float lbox[kRefitBlock][12];
+  __shared__ uint32_t lcnt[kRefitBlock];
+  __shared__ int32_t lpar[kRefitBlock];
+  __shared__ int32_t lnode[kRefitBlock];
+  __shared__ int2 lslot4[kRefitBlock];
+  __shared__ int2 lkid[kRefitBlock];
+  __shared__ double red[kRefitBlock / kWave];
+  const uint32_t n_cross = a.info[2];
+  const bool lds = n_cross <= (uint32_t)kMaxCross;
+  if (lds) {
+    if (n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
+  } else {
+    climb_cross_global(a);
+  }
+  __syncthreads();
+  refit_tail(a, n_rb, lds, n_cross, lbox, lkid, red);
+}
+
+// SAH ratio of a refitted tree: areas of the cross nodes' internal children
+// (from LDS when `lds`, else from the binary nodes) plus the blocks' sums,
+// over the root's area; written by thread 0.
+__device__ __forceinline__ void refit_tail(const RefitArgs& a, int n_rb, bool lds, uint32_t n_cross,
+                                           float (*lbox)[12], int2* lkid, double* red) {
+  const int tid = threadIdx.x;
+  const bool two_phase = lds;
   // areas of the cross nodes' internal children (in LDS after the two-phase
   // pass, else in the binary nodes), plus the blocks' sums
   double ar = 0.0;

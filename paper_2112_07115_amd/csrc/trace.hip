@@ -1498,9 +1498,11 @@ void launch_refit_coherence(dcem_ctx* c, bool begin) {
   const int cb = (int)std::max<int64_t>(
       std::min<int64_t>((ca.n_work + kRefitBlock - 1) / kRefitBlock, std::max(cu_count(c) - n_rb, 1)),
       (ca.n_work + ca.list_cap - 1) / ca.list_cap);
+  const RefitArgs ra = make_refit_args(c, true, c->sah_dev + 1);
   hipLaunchKernelGGL(k_refit_coherence, dim3(n_rb + std::max(cb, 1)), dim3(kRefitBlock),
-                     coherence_lds(c, ca.list_cap), c->stream, make_refit_args(c, true, c->sah_dev + 1), ca, n_rb,
-                     frame_begin_args(c, c->last_los), begin ? 1 : 0);
+                     coherence_lds(c, ca.list_cap), c->stream, ra, ca, n_rb, frame_begin_args(c, c->last_los),
+                     begin ? 1 : 0);
+  if (ra.cross_kernel) launch_refit_cross(c, ra, n_rb);
 }
 
 hipError_t build_ray_order(dcem_ctx* c) {

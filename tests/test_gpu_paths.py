@@ -114,6 +114,45 @@ def test_large_scene_refit_equals_rebuild():
     b.close()
 
 
+def test_very_large_scene_refit_cross_pass():
+    """More than 512k triangles: the refit's cross nodes are finished by a
+    launch of their own, beyond the LDS capacity through device memory.  The
+    refitted boxes are exact unions, the coherent launch's refit equals the
+    plain one, and hits equal those of a rebuilt tree."""
+    s = scenes.box_field(52000, 400)
+    log("box field", s.n_tris, "triangles")
+    assert s.n_tris > 524288
+    a, b = dcem.Context(0), dcem.Context(0)
+    a.scene_upload(s)
+    b.scene_upload(s)
+    a.refit_bvh(force_rebuild=True)
+    child, box, leaf = a.bvh()
+    lo, hi = leaf_ranges(child)
+    n_cross = int(np.sum(lo // REFIT_BLOCK != hi // REFIT_BLOCK))
+    log("nodes spanning refit blocks", n_cross)
+    assert n_cross > LAST_BLOCK_NODES
+    pad = 4e-6 * (2.0 * float(np.abs(s.vertices).max()) + 1.0)
+    dirs = scenes.random_sphere_dirs(1 << 16, seed=12)
+    for frame in [1, 2, 3]:
+        xf = s.transforms(frame)
+        a.set_object_transforms(xf)
+        rebuilt, ratio = a.refit_bvh(threshold=float("inf"))
+        assert not rebuilt
+        b.set_object_transforms(xf)
+        b.refit_bvh(force_rebuild=True)
+        # coherent frames run the refit inside the revalidation launch
+        a.trace_frame(s.tx, s.rx, s.rx_radius, dirs.shape[0], ray_dirs=dirs, max_reflections=s.max_reflections,
+                      record_trace_log=True, mode=dcem.MODE_COHERENT)
+        b.trace_frame(s.tx, s.rx, s.rx_radius, dirs.shape[0], ray_dirs=dirs, max_reflections=s.max_reflections,
+                      record_trace_log=True)
+        assert_same(outputs(a), outputs(b))
+        child, box, leaf = a.bvh()
+        assert exact_boxes(child, box, leaf, a.vertices(), s.tris, pad)
+        log("frame", frame, "refit == rebuild, SAH ratio", a.stats()["sah_ratio"])
+    a.close()
+    b.close()
+
+
 def test_upload_build_keeps_objects_in_own_subtrees():
     """The build at upload gives every moving object (and the static geometry)
     a subtree of its own, and every face one inside it: a node whose leaf
