@@ -14,9 +14,11 @@
  * are revalidated and only invalidated rays are traced again ("Propagation
  * path caching").
  *
- * Rays are shot forward from the transmitters and captured at receiver
- * spheres (the paper traces backward from the receiver; the set of geometric
- * paths is the same by reciprocity).
+ * Rays are shot from the transmitters and captured at receiver spheres, or
+ * (trace_from_rx) cast from the receivers and captured at transmitter
+ * spheres, the paper's backward tracing (Sec. III, "Backward ray tracing");
+ * both directions yield the same candidates, keyed from the transmitter, so
+ * everything after the trace is the same.
  *
  * Units: metres, hertz, watts, siemens per metre.  Right-handed, z up.
  * Geometry is FP32; path lengths, phases and fields are FP64.
@@ -134,6 +136,15 @@ typedef struct dcem_scene_desc {
  *  frame (COHERENT implies it).
  *  record_trace_log: 1 stores per (tx, ray, bounce) the hit triangle, its
  *  distance and the cumulative path length (see dcem_get_trace_log).
+ *  trace_from_rx: 1 casts the n_rays rays from every receiver and captures
+ *  them at spheres of radius rx_radius around the transmitters (backward
+ *  tracing, Sec. III: the ray count no longer grows with the number of
+ *  sources); every record is turned into the path's key from the transmitter
+ *  (faces in reverse order of the trace), refined and accumulated as in a
+ *  forward frame.  0 shoots from the transmitters.  Coherent frames reuse the
+ *  rays of a previous frame traced in the same direction; in a backward frame
+ *  the transmitters are the capture spheres and may move between coherent
+ *  frames, while moved receivers re-trace.
  *  Antennas are ideal and omnidirectional (Sec. III); the transmitter is
  *  vertically polarised (theta-hat of the departure direction) and the
  *  receiver is polarisation-agnostic. */
@@ -155,11 +166,12 @@ typedef struct dcem_trace_params {
   int32_t keep_cache;
   int32_t record_trace_log;
   int32_t mem_kind;
+  int32_t trace_from_rx;
 } dcem_trace_params;
 
 /* Counters and timings of the last dcem_refit_bvh + dcem_trace_frame. */
 typedef struct dcem_frame_stats {
-  int64_t rays_total;        /* n_tx * n_rays */
+  int64_t rays_total;        /* n_tx * n_rays (n_rx * n_rays when tracing from the receivers) */
   int64_t rays_traced;       /* rays actually traced this frame */
   int64_t rays_reused;       /* rays whose cached result was reused */
   int64_t segments;          /* closest-hit queries executed */
@@ -343,20 +355,26 @@ dcem_status dcem_power_gradients_noalloc(dcem_ctx* ctx, double* d_eps_r, double*
  * towards the last path point), amp [cap][n_freqs][3][2] complex field vector
  * (re, im) whose squared norm is the path's received power, first_ray [cap]
  * (lowest ray index tx * n_rays + i that captured it, -1 for a direct path
- * added by los_always).  Any output pointer may be NULL.  n_out receives the
+ * added by los_always; in a frame traced from the receivers, rx * n_rays + i
+ * of the lowest receiver ray).  Any output pointer may be NULL.  n_out receives the
  * number of paths; at most cap are written. */
 dcem_status dcem_get_paths(dcem_ctx* ctx, int64_t cap, int32_t* keys, uint8_t* valid, double* length,
                            double* tau, double* aod, double* aoa, double* amp, int32_t* first_ray,
                            int64_t* n_out);
 
-/* Per (tx, ray, bounce) log of the last frame ([n_tx][n_rays][K+1], host):
+/* Per (source, ray, bounce) log of the last frame ([n_src][n_rays][K+1],
+ * host; the sources are the transmitters, or the receivers when tracing
+ * backward):
  * tri = hit triangle (-1 miss, -2 not reached), t = hit distance along the
  * (unnormalised) direction, length = cumulative path length at the hit.
  * Requires record_trace_log = 1.  Any pointer may be NULL. */
 dcem_status dcem_get_trace_log(dcem_ctx* ctx, int32_t* tri, float* t, float* length);
 
 /* Raw capture records of the last frame (host): rows [cap][4 + K] =
- * (ray, tx, rx, order, faces... padded -1), in key order then ray order. */
+ * (ray, source, target, order, faces... padded -1) in the trace's direction:
+ * (ray, tx, rx, order, faces from the transmitter), or when tracing from the
+ * receivers (ray, rx, tx, order, faces from the receiver); sorted by
+ * (source, target, order, faces), then ray. */
 dcem_status dcem_get_captures(dcem_ctx* ctx, int64_t cap, int32_t* rows, int64_t* n_out);
 
 /* Current BVH (host): n_internal nodes; child [n][2] (>= 0 internal node,

@@ -14,8 +14,13 @@ does not import the package either.
 
 Functions and the passages they follow:
   fibonacci          ray sphere (step 1 of the frame algorithm)
-  trace              bounces + capture spheres (steps 1-2, forward direction)
-  candidates         de-duplicated (tx, rx, order, faces) keys (step 2's tables)
+  trace              bounces + capture spheres (steps 1-2); rays start at the
+                     sources and are captured at spheres around the targets
+  candidates         de-duplicated (tx, rx, order, faces) keys (step 2's tables);
+                     records traced backward from the receivers (Sec. III,
+                     "Backward ray tracing": sources = receivers, targets =
+                     transmitters) are turned into the path's key from the
+                     transmitter: pair swapped, faces in reverse order
   refine             image method, validity, field per path (steps 3, 4, 6;
                      Eq. (3) with n = 2 for the free-space magnitude)
   received_power     phase-coherent sum per receiver ("phase calculation")
@@ -190,8 +195,28 @@ def los_keys(ntx: int, nrx: int, K: int) -> np.ndarray:
     return keys
 
 
-def candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = True):
+def path_rows(rows: np.ndarray, K: int, backward: bool) -> np.ndarray:
+    """Capture rows (src, tgt, order, faces in traced order) as path keys
+    (tx, rx, order, faces from the transmitter).  Forward rows are keys
+    already; a row traced from a receiver names (rx, tx) and lists the faces
+    from the receiver's end, so the pair is swapped and the first `order`
+    faces are reversed."""
+    rows = np.asarray(rows, dtype=np.int32).reshape(-1, 3 + K)
+    if not backward:
+        return rows
+    out = rows.copy()
+    out[:, 0], out[:, 1] = rows[:, 1], rows[:, 0]
+    for o in range(2, K + 1):
+        sel = rows[:, 2] == o
+        out[sel, 3:3 + o] = rows[sel, 3:3 + o][:, ::-1]
+    return out
+
+
+def candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = True,
+               backward: bool = False):
     """Unique keys from exact captures, sorted by (tx, rx, order, f1..fK).
+    ntx, nrx: the paths' transmitters and receivers; backward: tr was traced
+    from the receivers (its rows name (rx, tx) and faces from the receiver).
 
     Returns (keys, certain, possible):
       keys      the oracle's own candidate set (captures with distance <= r)
@@ -201,7 +226,7 @@ def candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = T
                 uncertain ones included); an FP32 tracer can only find keys
                 outside this set on rays whose path the oracle marks uncertain
     """
-    rows = tr.caps[:, 1:]
+    rows = path_rows(tr.caps[:, 1:], K, backward)
     hit = (tr.cap_flags & CAP_HIT) != 0
     sure = tr.cap_flags == CAP_HIT
     parts = [rows[hit]]
@@ -386,8 +411,12 @@ class FrameResult:
 
 def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Optional[int] = None,
           freqs=None, tx_power_w: Optional[float] = None, atten_db_per_km: float = 0.0,
-          los_always: bool = True, nthreads: Optional[int] = None, pattern=None) -> FrameResult:
-    """One frame, from scratch: the oracle keeps nothing between frames."""
+          los_always: bool = True, nthreads: Optional[int] = None, pattern=None,
+          backward: bool = False) -> FrameResult:
+    """One frame, from scratch: the oracle keeps nothing between frames.
+    backward: rays cast from the receivers and captured at spheres around the
+    transmitters (Sec. III, "Backward ray tracing"); the trace result is then
+    per receiver."""
     K = scene.max_reflections if K is None else K
     freqs = scene.freqs_hz if freqs is None else freqs
     tx_power_w = scene.tx_power_w if tx_power_w is None else tx_power_w
@@ -397,9 +426,10 @@ def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Opt
     osc = OracleScene(scene, xf)
     # receivers of this frame (vehicle-mounted receivers move with their vehicles)
     rx = scene.rx_at(frame_index) if hasattr(scene, "rx_at") else scene.rx
-    tr = trace(osc, scene.tx, rx, scene.rx_radius, dirs, K, nthreads=nthreads)
+    src, tgt = (rx, scene.tx) if backward else (scene.tx, rx)
+    tr = trace(osc, src, tgt, scene.rx_radius, dirs, K, nthreads=nthreads)
     ntx, nrx = scene.tx.shape[0], rx.shape[0]
-    keys, certain, possible = candidates(tr, ntx, nrx, K, los_always)
+    keys, certain, possible = candidates(tr, ntx, nrx, K, los_always, backward)
     paths = refine(osc, scene.tx, rx, keys, K, freqs, tx_power_w, atten_db_per_km,
                    nthreads=nthreads, pattern=pattern)
     p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))

@@ -741,8 +741,12 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   if (!(p->tx_power_w >= 0.0) || !std::isfinite(p->tx_power_w)) return fail(c, DCEM_E_INVALID_ARG, "bad tx_power_w");
   if (!std::isfinite(p->atten_db_per_km)) return fail(c, DCEM_E_INVALID_ARG, "bad atten_db_per_km");
   if (p->mode != DCEM_MODE_FULL && p->mode != DCEM_MODE_COHERENT) return fail(c, DCEM_E_INVALID_ARG, "bad mode");
-  const int64_t n_work = (int64_t)p->n_tx * p->n_rays;
-  if (n_work >= (int64_t(1) << 31) - 1) return fail(c, DCEM_E_UNSUPPORTED, "n_tx * n_rays must be < 2^31 - 1");
+  if (p->trace_from_rx != 0 && p->trace_from_rx != 1) return fail(c, DCEM_E_INVALID_ARG, "trace_from_rx must be 0 or 1");
+  const bool backward = p->trace_from_rx == 1;
+  const int32_t n_src = backward ? p->n_rx : p->n_tx, n_tgt = backward ? p->n_tx : p->n_rx;
+  const int64_t n_work = (int64_t)n_src * p->n_rays;
+  if (n_work >= (int64_t(1) << 31) - 1)
+    return fail(c, DCEM_E_UNSUPPORTED, "rays per frame (sources x n_rays) must be < 2^31 - 1");
   if ((int64_t)p->n_tx * p->n_rx >= (int64_t(1) << 27)) return fail(c, DCEM_E_UNSUPPORTED, "too many tx x rx pairs");
   {
     int bt = 0, br = 0, bf = 0;
@@ -775,31 +779,40 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
     for (float v : dirh) if (!std::isfinite(v)) return fail(c, DCEM_E_INVALID_ARG, "non-finite ray direction");
   }
   TraceConfig& cfg = c->cfg;
-  // the cached rays stay valid while the transmitters, the rays and the
-  // bounce limit stay; receivers may move (their captures are then taken
-  // again from the cached segments)
-  const bool same_geom = cfg.n_tx == p->n_tx && cfg.n_rx == p->n_rx && cfg.K == p->max_reflections &&
-                         cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius && cfg.tx == txh &&
-                         cfg.dirs_fib == fib && (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
-  const bool rx_moved = cfg.rx != rxh;
+  // the trace's sources and targets (the receivers and transmitters when
+  // tracing backward)
+  std::vector<float>& srch = backward ? rxh : txh;
+  std::vector<float>& tgth = backward ? txh : rxh;
+  // the cached rays stay valid while the sources, the rays and the bounce
+  // limit stay; targets may move (their captures are then taken again from
+  // the cached segments)
+  const bool same_geom = cfg.n_src == n_src && cfg.n_tgt == n_tgt && cfg.backward == backward &&
+                         cfg.K == p->max_reflections && cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius &&
+                         cfg.src == srch && cfg.dirs_fib == fib &&
+                         (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
+  const bool rx_moved = cfg.tgt != tgth;
   const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same_geom;
   const bool keep_cache = p->keep_cache != 0 || p->mode == DCEM_MODE_COHERENT;
   plan.recapture = coherent && rx_moved;
   // -- device inputs
   const bool need_dirs = !same_geom || !c->has_frame;
   const bool need_rx = need_dirs || rx_moved;
-  cfg.n_tx = p->n_tx;
-  cfg.n_rx = p->n_rx;
+  cfg.n_src = n_src;
+  cfg.n_tgt = n_tgt;
+  cfg.backward = backward;
   cfg.K = p->max_reflections;
   cfg.n_rays = p->n_rays;
   cfg.rx_radius = p->rx_radius;
-  cfg.tx = txh;
-  cfg.rx = rxh;
+  cfg.src = srch;
+  cfg.tgt = tgth;
   cfg.dirs_fib = fib;
   cfg.dirs_ptr = p->ray_dirs;
   cfg.dirs_host = dirh;
   c->n_tx = p->n_tx;
   c->n_rx = p->n_rx;
+  c->n_src = n_src;
+  c->n_tgt = n_tgt;
+  c->backward = backward;
   c->n_rays = p->n_rays;
   c->K = p->max_reflections;
   c->n_freqs = p->n_freqs;
@@ -811,13 +824,13 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
     c->mat_pending = false;
   }
   c->record_log = p->record_trace_log != 0;
-  if (need_dirs) HIP_TRY(upload(c->tx_pos, txh, c->stream), "upload tx");   // transmitters or rays changed
+  if (need_dirs) HIP_TRY(upload(c->src_pos, srch, c->stream), "upload sources");   // sources or rays changed
   if (need_rx) {
-    HIP_TRY(upload(c->rx_pos, rxh, c->stream), "upload rx");
-    std::vector<Node> rt = build_rx_tree(rxh, p->rx_radius);
+    HIP_TRY(upload(c->tgt_pos, tgth, c->stream), "upload targets");
+    std::vector<Node> rt = build_rx_tree(tgth, p->rx_radius);
     c->n_rx_nodes = (int32_t)rt.size();
-    HIP_TRY(upload(c->rx_nodes, rt, c->stream), "upload receiver tree");
-    HIP_TRY(upload_rx_columns(c, rxh), "upload receiver columns");
+    HIP_TRY(upload(c->rx_nodes, rt, c->stream), "upload capture-sphere tree");
+    HIP_TRY(upload_rx_columns(c, tgth), "upload capture-sphere columns");
   }
   {
     std::vector<double> fv(p->freqs_hz, p->freqs_hz + p->n_freqs);
@@ -1189,7 +1202,7 @@ dcem_status dcem_get_trace_log(dcem_ctx* c, int32_t* tri, float* t, float* lengt
   HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
-  const size_t n = (size_t)c->n_tx * c->n_rays * (c->K + 1);
+  const size_t n = (size_t)c->n_src * c->n_rays * (c->K + 1);
   if (tri) HIP_TRY(hipMemcpy(tri, c->log_tri.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
   if (t) HIP_TRY(hipMemcpy(t, c->log_t.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
   if (length) HIP_TRY(hipMemcpy(length, c->log_len.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
@@ -1211,7 +1224,7 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   std::vector<Capture> cp(nc);
   const int list = c->frame_begun ? c->cur_caps ^ 1 : c->cur_caps;   // the last traced frame's
   HIP_TRY(hipMemcpy(cp.data(), c->caps[list].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
-  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
   // records and the face log are indexed by traversal position; rows name the ray
   std::vector<uint32_t> order((size_t)std::max<int64_t>(c->n_rays, 1));
   if (c->n_rays > 0)
@@ -1230,8 +1243,8 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
     std::vector<int32_t> r(4 + K, -1);
     const uint32_t pair = x.pair_order >> 4, order = x.pair_order & 15u;
     r[0] = x.work == kNoRay ? -1 : ray_of(x.work);
-    r[1] = (int32_t)(pair / c->n_rx);
-    r[2] = (int32_t)(pair % c->n_rx);
+    r[1] = (int32_t)(pair / c->n_tgt);
+    r[2] = (int32_t)(pair % c->n_tgt);
     r[3] = (int32_t)order;
     for (uint32_t j = 0; j < order; ++j) r[4 + j] = flog[(size_t)j * n_work + x.work];
     out.push_back(std::move(r));

@@ -74,8 +74,9 @@ struct __align__(16) Leaf {
   float4 v0, v1, v2;
 };
 
-// Packed capture record: ray work item (tx * n_rays + ray) and
-// (tx * n_rx + rx) << 4 | order.
+// Packed capture record: ray work item (src * n_rays + position) and
+// (src * n_tgt + tgt) << 4 | order, in the trace's direction (source and
+// target are the transmitter and receiver, swapped in a backward frame).
 struct Capture {
   uint32_t work;
   uint32_t pair_order;
@@ -93,11 +94,15 @@ struct TxPattern {
   int on;
 };
 
+// The trace side of a frame: rays start at the sources and are captured by
+// spheres around the targets (forward: transmitters and receivers; a backward
+// frame swaps them).
 struct TraceConfig {
-  int32_t n_tx = 0, n_rx = 0, K = -1;
+  int32_t n_src = 0, n_tgt = 0, K = -1;
+  bool backward = false;
   int64_t n_rays = 0;
   float rx_radius = 0.f;
-  std::vector<float> tx, rx;
+  std::vector<float> src, tgt;
   bool dirs_fib = true;
   const void* dirs_ptr = nullptr;
   std::vector<float> dirs_host;
@@ -181,8 +186,13 @@ struct dcem_ctx {
   dcem::TraceConfig cfg;
   bool cache_valid = false;
   bool geometry_moved = true;   // transforms changed since the cached frame
-  dcem::DevBuf dirs, ray_order, tx_pos, rx_pos, freqs, rx_nodes;
-  // receivers ordered by x column: [n_rx] float4 (x, y, z, receiver index
+  // ray origins and capture-sphere centres of the trace (transmitters and
+  // receivers; receivers and transmitters in a backward frame)
+  int32_t n_src = 0, n_tgt = 0;
+  bool backward = false;
+  // rx_nodes, rx_cols: the capture spheres (the targets) as a tree and by x column
+  dcem::DevBuf dirs, ray_order, src_pos, tgt_pos, freqs, rx_nodes;
+  // targets ordered by x column: [n_tgt] float4 (x, y, z, target index
   // bits), then kRxCols + 1 int32 column starts; column of x:
   // clamp(floor((x - rx_col_x0) * rx_col_scale), 0, kRxCols - 1)
   dcem::DevBuf rx_cols;
@@ -219,6 +229,7 @@ struct dcem_ctx {
   bool refit_pending_timing = false;
 
   // -- candidates / paths
+  // n_tx, n_rx: the paths' transmitters and receivers (either direction)
   int32_t key_words = 0, K = 0, n_freqs = 0, n_tx = 0, n_rx = 0;
   int64_t n_rays = 0;
   int bits_tx = 0, bits_rx = 0, bits_face = 0;
@@ -250,7 +261,7 @@ struct dcem_ctx {
             &face_tri_off, &face_tris, &face_ref_tri, &xf, &obj_box, &face_plane, &tri_slot, &face_slots,
             &nodes, &leaf_slot, &leaf_tri, &leaf_parent, &refit_cnt, &morton, &sort_tmp, &sah_part, &scene_box,
             &node_range, &nodes4, &bvh2_of4, &map4, &depth_key, &slot4, &cross, &tree_info, &tri4, &face_build,
-            &dirs, &ray_order, &tx_pos, &rx_pos, &freqs, &rx_nodes, &rx_cols, &grad_buf, &face_log, &ray_state,
+            &dirs, &ray_order, &src_pos, &tgt_pos, &freqs, &rx_nodes, &rx_cols, &grad_buf, &face_log, &ray_state,
             &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag, &stack_spill,
             &frame_block, &cand_keys, &cand_perm, &cand_tmp, &uniq_idx, &first_ray, &path_valid, &path_len,
             &path_tau, &path_aod, &path_aoa, &path_amp, &pair_range, &path_order, &path_faces, &path_pts,

@@ -23,8 +23,10 @@ struct KeyLayout {
   int W;       // 32-bit words per key
   int bits;    // significant bits
   int bt, br, bf, K;
-  int n_rx;
-  const uint32_t* ray_order;   // traversal position -> ray within its transmitter's block
+  int n_rx;                    // receivers of the paths
+  int n_tgt;                   // capture spheres of the trace (pairs of a record: src * n_tgt + tgt)
+  bool backward;               // records traced from the receivers: (src, tgt) = (rx, tx), faces reversed
+  const uint32_t* ray_order;   // traversal position -> ray within its source's block
   int64_t n_rays;
 };
 
@@ -52,15 +54,22 @@ __device__ inline void put_bits(uint32_t* w, int W, int pos, int nbits, uint32_t
 }
 
 // Sort key of a capture: (tx, rx, order, f1..fK) packed most significant
-// first, faces read from the per-bounce face log of the capturing ray.
-__device__ inline void capture_key(const Capture& c, const int32_t* __restrict__ face_log, int64_t n_work,
-                                   const KeyLayout& L, uint32_t* w) {
-  const uint32_t pair = c.pair_order >> 4, order = c.pair_order & 15u;
-  const uint32_t tx = pair / (uint32_t)L.n_rx, rx = pair - tx * (uint32_t)L.n_rx;
+// first, faces read from the per-bounce face log of the capturing ray.  A
+// record traced from a receiver names (rx, tx) and meets the faces in reverse
+// path order; its key is the path's, from the transmitter.  Returns the
+// path's pair tx * n_rx + rx.
+__device__ inline uint32_t capture_key(const Capture& c, const int32_t* __restrict__ face_log, int64_t n_work,
+                                       const KeyLayout& L, uint32_t* w) {
+  const uint32_t tpair = c.pair_order >> 4, order = c.pair_order & 15u;
+  const uint32_t src = tpair / (uint32_t)L.n_tgt, tgt = tpair - src * (uint32_t)L.n_tgt;
+  const uint32_t tx = L.backward ? tgt : src, rx = L.backward ? src : tgt;
   for (int k = 0; k < 8; ++k) w[k] = 0;
   for (int j = 0; j < L.K; ++j) {
     uint32_t f = 0;
-    if ((uint32_t)j < order) f = (uint32_t)face_log[(size_t)j * n_work + c.work];
+    if ((uint32_t)j < order) {
+      const uint32_t bounce = L.backward ? order - 1u - (uint32_t)j : (uint32_t)j;
+      f = (uint32_t)face_log[(size_t)bounce * n_work + c.work];
+    }
     put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
   }
   int pos = L.K * L.bf;
@@ -69,6 +78,7 @@ __device__ inline void capture_key(const Capture& c, const int32_t* __restrict__
   put_bits(w, L.W, pos, L.br, rx);
   pos += L.br;
   put_bits(w, L.W, pos, L.bt, tx);
+  return tx * (uint32_t)L.n_rx + rx;
 }
 
 __global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log,
@@ -203,10 +213,10 @@ __global__ __launch_bounds__(kCandBlock) void k_small_candidates(
     if (i < n) {
       const Capture c = cr[q];
       uint32_t w[8];
-      capture_key(c, face_log, n_work, L, w);
+      const uint32_t pair = capture_key(c, face_log, n_work, L, w);
       for (int k = 0; k < L.W; ++k) keys_out[k * (int64_t)kSmallN + i] = w[k];
       for (int k = 0; k < kSmallW; ++k) kk[k][i] = k < L.W ? w[k] : 0u;
-      cpair[i] = c.pair_order >> 4;
+      cpair[i] = pair;
       work[q] = ray_of(c.work, L);
     }
   }
@@ -1068,6 +1078,8 @@ KeyLayout key_layout(const dcem_ctx* c) {
   L.bf = std::max(1, bits_for(c->nf));
   L.K = c->K;
   L.n_rx = c->n_rx;
+  L.n_tgt = c->n_tgt;
+  L.backward = c->backward;
   L.ray_order = static_cast<const uint32_t*>(c->ray_order.p);
   L.n_rays = std::max<int64_t>(c->n_rays, 1);
   L.bits = L.bt + L.br + 4 + L.K * L.bf;
@@ -1120,7 +1132,7 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   c->bits_tx = L.bt;
   c->bits_rx = L.br;
   c->bits_face = L.bf;
-  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
   if (small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
@@ -1181,8 +1193,8 @@ void launch_refine(dcem_ctx* c) {
   a.K = c->K;
   a.n_rx = c->n_rx;
   a.n_unique = c->cnt_dev + kCntUnique;
-  a.tx = ptr<float>(c->tx_pos);
-  a.rx = ptr<float>(c->rx_pos);
+  a.tx = ptr<float>(c->backward ? c->tgt_pos : c->src_pos);
+  a.rx = ptr<float>(c->backward ? c->src_pos : c->tgt_pos);
   a.plane = ptr<double4>(c->face_plane);
   a.face_tri_off = ptr<int32_t>(c->face_tri_off);
   a.face_tris = ptr<int32_t>(c->face_tris);

@@ -248,10 +248,13 @@ struct TraceArgs {
   const uint32_t* ray_order;  // traversal position -> ray (directions sorted along a space-filling curve);
                               // per-ray device state is indexed by position: neighbouring directions share
                               // cache lines
+  // ray origins [n_src][3] and capture-sphere centres [n_rx][3]: the
+  // transmitters and receivers, or in a backward frame the receivers and
+  // transmitters (records then name (receiver, transmitter) pairs)
   const float* tx;
-  const float* rx;      // [n_rx][3]
+  const float* rx;
   int n_rx;
-  const Node* rx_nodes; // BVH over the capture spheres (boxes padded), leaves = receiver ids
+  const Node* rx_nodes; // BVH over the capture spheres (boxes padded), leaves = sphere ids
   int n_rx_nodes;
   float r2;
   float rx_zlo, rx_zhi; // z range of all capture spheres
@@ -1303,24 +1306,24 @@ namespace {
 
 // Arguments of a context's trace launch.
 TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_prev_caps) {
-  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.tri4 = ptr<Leaf>(c->tri4);
   a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
   a.dirs = ptr<float>(c->dirs);
   a.ray_order = ptr<uint32_t>(c->ray_order);
-  a.tx = ptr<float>(c->tx_pos);
-  a.rx = ptr<float>(c->rx_pos);
-  a.n_rx = c->n_rx;
+  a.tx = ptr<float>(c->src_pos);
+  a.rx = ptr<float>(c->tgt_pos);
+  a.n_rx = c->n_tgt;
   a.rx_nodes = ptr<Node>(c->rx_nodes);
   a.n_rx_nodes = c->n_rx_nodes;
   a.restart = all_rays ? nullptr : ptr<uint8_t>(c->invalid_flag);
   a.r2 = c->cfg.rx_radius * c->cfg.rx_radius;
   float zlo = FLT_MAX, zhi = -FLT_MAX;
-  for (int i = 0; i < c->n_rx; ++i) {
-    zlo = fminf(zlo, c->cfg.rx[3 * i + 2]);
-    zhi = fmaxf(zhi, c->cfg.rx[3 * i + 2]);
+  for (int i = 0; i < c->n_tgt; ++i) {
+    zlo = fminf(zlo, c->cfg.tgt[3 * i + 2]);
+    zhi = fmaxf(zhi, c->cfg.tgt[3 * i + 2]);
   }
   // widen the culling slab well beyond rounding so it never changes a decision
   const float rr = c->cfg.rx_radius * 1.001f + 1e-3f;
@@ -1427,7 +1430,7 @@ hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, in
 void launch_recapture(dcem_ctx* c) {
   TraceArgs a = trace_args(c, false, true, 0u);
   a.stack_spill = ptr<int>(c->stack_spill);
-  const int64_t n_work = (int64_t)c->n_tx * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(trace_grid(c), (n_work + kTraceBlock - 1) / kTraceBlock));
   hipLaunchKernelGGL(k_recapture, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
 }
@@ -1438,7 +1441,7 @@ hipError_t prepare_trace(dcem_ctx* c) {
 }
 
 FrameBegin frame_begin_args(dcem_ctx* c, bool los) {
-  return FrameBegin{c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), los ? c->n_tx * c->n_rx : 0, c->cap_capacity,
+  return FrameBegin{c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), los ? c->n_src * c->n_tgt : 0, c->cap_capacity,
                     c->err_dev};
 }
 
@@ -1456,8 +1459,8 @@ CohArgs coherence_args(dcem_ctx* c) {
   a.face_object = ptr<int32_t>(c->face_object);
   a.obj_box = ptr<float>(c->obj_box);
   a.n_obj = c->no;
-  a.n_work = (int)((int64_t)c->n_tx * c->n_rays);
-  a.tx = ptr<float>(c->tx_pos);
+  a.n_work = (int)((int64_t)c->n_src * c->n_rays);
+  a.tx = ptr<float>(c->src_pos);
   a.n_rays = c->n_rays;
   a.margin = 1e-3f + c->pad;
   a.restart = ptr<uint8_t>(c->invalid_flag);

@@ -42,7 +42,8 @@ class TraceParams(ctypes.Structure):
     _fields_ = [("tx_pos", _P), ("n_tx", _I32), ("rx_pos", _P), ("n_rx", _I32), ("rx_radius", _F32),
                 ("n_rays", _I64), ("ray_dirs", _P), ("max_reflections", _I32), ("freqs_hz", _P),
                 ("n_freqs", _I32), ("tx_power_w", _F64), ("atten_db_per_km", _F64), ("mode", _I32),
-                ("los_always", _I32), ("keep_cache", _I32), ("record_trace_log", _I32), ("mem_kind", _I32)]
+                ("los_always", _I32), ("keep_cache", _I32), ("record_trace_log", _I32), ("mem_kind", _I32),
+                ("trace_from_rx", _I32)]
 
 
 class FrameStats(ctypes.Structure):
@@ -226,7 +227,7 @@ class Context:
         self._batches = []
         self.K = 0
         self.n_freqs = 1
-        self.n_tx = self.n_rx = 0
+        self.n_tx = self.n_rx = self.n_src = 0
         self.n_rays = 0
 
     def close(self):
@@ -286,7 +287,7 @@ class Context:
     def _params(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None, max_reflections: int = 2,
                 freqs_hz: Sequence[float] = (28e9,), tx_power_w: float = 5.0, atten_db_per_km: float = 0.0,
                 mode: int = MODE_FULL, los_always: bool = True, keep_cache: bool = False,
-                record_trace_log: bool = False):
+                record_trace_log: bool = False, trace_from_rx: bool = False):
         """dcem_trace_params of one frame (arrays kept alive on the context)."""
         dev = ray_dirs is not None and not isinstance(ray_dirs, np.ndarray) and ray_dirs.is_cuda
         if dev:
@@ -299,19 +300,23 @@ class Context:
         p = TraceParams(_addr(txa), int(txa.shape[0]), _addr(rxa), int(rxa.shape[0]), float(rx_radius),
                         int(n_rays), _addr(dirs), int(max_reflections), _addr(fr), int(fr.shape[0]),
                         float(tx_power_w), float(atten_db_per_km), int(mode), int(bool(los_always)),
-                        int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST)
-        shape = (int(max_reflections), int(fr.shape[0]), int(txa.shape[0]), int(rxa.shape[0]), int(n_rays))
+                        int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST,
+                        int(bool(trace_from_rx)))
+        n_tx, n_rx = int(txa.shape[0]), int(rxa.shape[0])
+        shape = (int(max_reflections), int(fr.shape[0]), n_tx, n_rx, int(n_rays), n_rx if trace_from_rx else n_tx)
         return p, shape
 
     def _traced(self, shape):
-        self.K, self.n_freqs, self.n_tx, self.n_rx, self.n_rays = shape
+        # n_src: the rays' origins (the receivers when tracing backward)
+        self.K, self.n_freqs, self.n_tx, self.n_rx, self.n_rays, self.n_src = shape
 
     def trace_frame(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None,
                     max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
                     tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
-                    los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False):
+                    los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False,
+                    trace_from_rx: bool = False):
         p, shape = self._params(tx, rx, rx_radius, n_rays, ray_dirs, max_reflections, freqs_hz, tx_power_w,
-                                atten_db_per_km, mode, los_always, keep_cache, record_trace_log)
+                                atten_db_per_km, mode, los_always, keep_cache, record_trace_log, trace_from_rx)
         self._check(self.lib.dcem_trace_frame(self.handle, ctypes.byref(p)))
         self._traced(shape)
 
@@ -390,7 +395,7 @@ class Context:
         return out
 
     def trace_log(self):
-        shp = (self.n_tx, self.n_rays, self.K + 1)
+        shp = (self.n_src, self.n_rays, self.K + 1)
         tri = np.empty(shp, np.int32)
         t = np.empty(shp, np.float32)
         length = np.empty(shp, np.float32)
@@ -513,7 +518,8 @@ class FrameOutput:
 def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL, ray_dirs=None,
                       n_rays: Optional[int] = None, K: Optional[int] = None, rebuild: bool = False,
                       keep_cache: bool = False, record_trace_log: bool = False, los_always: bool = True,
-                      threshold: float = 1.5, atten_db_per_km: float = 0.0) -> FrameOutput:
+                      threshold: float = 1.5, atten_db_per_km: float = 0.0,
+                      trace_from_rx: bool = False) -> FrameOutput:
     """Convenience: place the scene's objects for `frame`, update the BVH, trace, read power."""
     if scene.object_vertex_range.shape[0]:
         ctx.set_object_transforms(scene.transforms(frame))
@@ -525,6 +531,7 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
     ctx.trace_frame(scene.tx, rx, scene.rx_radius, n, ray_dirs=ray_dirs,
                     max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
                     tx_power_w=scene.tx_power_w, atten_db_per_km=atten_db_per_km, mode=mode,
-                    los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log)
+                    los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log,
+                    trace_from_rx=trace_from_rx)
     pc, pi = ctx.received_power()
     return FrameOutput(pc, pi)

@@ -61,16 +61,18 @@ def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=T
 
 
 def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True,
-             los_always=True, atten_db_per_km=0.0, upload=True):
+             los_always=True, atten_db_per_km=0.0, upload=True, backward=False):
     """Trace one FULL frame on both sides and compare everything; returns
-    (stats, GPU output, oracle FrameResult)."""
+    (stats, GPU output, oracle FrameResult).  backward: rays cast from the
+    receivers on both sides (trace logs and captures are then per receiver)."""
     K = scene.max_reflections if K is None else K
     log("case", scene.name, "frame", frame, "K", K, "rays", n_rays if dirs is None else len(dirs),
-        "atten", atten_db_per_km)
+        "atten", atten_db_per_km, "backward" if backward else "forward")
     if upload:
         ctx.scene_upload(scene)
     out = dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=dirs, n_rays=n_rays, K=K,
-                                 record_trace_log=True, los_always=los_always, atten_db_per_km=atten_db_per_km)
+                                 record_trace_log=True, los_always=los_always, atten_db_per_km=atten_db_per_km,
+                                 trace_from_rx=backward)
     if dirs is None:
         g_dirs = ctx.ray_dirs()
         o_dirs = O.fibonacci(n_rays or scene.n_rays)
@@ -78,7 +80,7 @@ def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captu
     else:
         o_dirs = dirs
     ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K, los_always=los_always,
-                  atten_db_per_km=atten_db_per_km)
+                  atten_db_per_km=atten_db_per_km, backward=backward)
     st = compare_frame(ctx, scene, ofr, out, o_dirs.shape[0], check_captures=check_captures,
                        check_paths=check_paths)
     return st, out, ofr

@@ -55,7 +55,8 @@ MUTATIONS = {
                          "test_oracle_pattern.py"),
 }
 
-# Mistakes planted in the Python half of the oracle (the per-receiver sums).
+# Mistakes planted in the Python half of the oracle (the per-receiver sums,
+# the keys of records traced backward).
 PY_MUTATIONS = {
     # incoherent power as the coherent one (square of the sum over paths)
     "p_inc_square_of_sum": ("return p_coh, p_inc", "return p_coh, p_coh.copy()"),
@@ -65,6 +66,11 @@ PY_MUTATIONS = {
     # coherent sum over only the last path of a receiver
     "p_coh_last_path": ("acc[:, int(paths.keys[i, 0]), int(paths.keys[i, 1])] += paths.amp[i]",
                         "acc[:, int(paths.keys[i, 0]), int(paths.keys[i, 1])] = paths.amp[i]"),
+    # backward records keyed without reversing their faces / swapping the pair
+    "backward_faces_not_reversed": ("out[sel, 3:3 + o] = rows[sel, 3:3 + o][:, ::-1]",
+                                    "out[sel, 3:3 + o] = rows[sel, 3:3 + o]", "test_oracle_variants.py"),
+    "backward_pair_not_swapped": ("out[:, 0], out[:, 1] = rows[:, 1], rows[:, 0]",
+                                  "out[:, 0], out[:, 1] = rows[:, 0], rows[:, 1]", "test_oracle_variants.py"),
 }
 
 
@@ -87,7 +93,7 @@ def test_pins_catch_mutation(name, tmp_path):
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
 
 
-def _run_pins_on_python_copy(tmp_path, old, new):
+def _run_pins_on_python_copy(tmp_path, old, new, suite="test_oracle_pins.py"):
     src = open(PY).read()
     assert src.count(old) == 1, "mutation anchor not found: %r" % old
     mod = tmp_path / "oracle_mutant.py"
@@ -96,7 +102,7 @@ def _run_pins_on_python_copy(tmp_path, old, new):
         '_HERE = %r' % os.path.join(ROOT, "oracle")))
     env = dict(os.environ, DCEM_ORACLE_PY=str(mod))
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           os.path.join(ROOT, "tests", suite)],
                           env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
 
 
