@@ -70,6 +70,10 @@ typedef int32_t dcem_status;
 
 #define DCEM_FORCE_REBUILD 1  /* dcem_refit_bvh flag: rebuild instead of refitting */
 
+/* dcem_trace_params.discovery: which face sequences become candidates */
+#define DCEM_DISCOVER_CAPTURE 0  /* sequences of rays that pass through a capture sphere */
+#define DCEM_DISCOVER_VISITED 1  /* every visited series, tried against every target */
+
 #define DCEM_MAX_REFLECTIONS 10  /* paper, Sec. III: at most 10 reflections */
 #define DCEM_PATTERN_TAPS 16     /* weights of the transmit pattern (dcem_set_tx_pattern) */
 
@@ -136,6 +140,22 @@ typedef struct dcem_scene_desc {
  *  frame (COHERENT implies it).
  *  record_trace_log: 1 stores per (tx, ray, bounce) the hit triangle, its
  *  distance and the cumulative path length (see dcem_get_trace_log).
+ *  discovery: DCEM_DISCOVER_CAPTURE (0) keys a candidate for each capture
+ *  sphere a ray passes through, with the faces it reflected on before.
+ *  DCEM_DISCOVER_VISITED (1) follows the paper's frame algorithm literally
+ *  (Sec. III, steps 2-4): every distinct series of faces the rays reflect on
+ *  (the faces of a ray's first d hits, d = 1..max_reflections, per source) is
+ *  entered in the visited table of its depth and tried against every target
+ *  by the image method, so the path set no longer depends on a ray passing
+ *  close to a receiver; rx_radius is then unused and no capture records are
+ *  made.  The candidates kept are those whose reflection points lie strictly
+ *  inside their segments and inside their faces (checked before the
+ *  occlusion tests of the refinement, with the same arithmetic); their number
+ *  is bounded by the capture capacity (dcem_set_capture_capacity; overflow
+ *  sets DCEM_ERR_CAPTURES) and the series times targets by 2^32
+ *  (DCEM_E_UNSUPPORTED).  los_always keeps its meaning (the empty series).
+ *  Candidate discovery of this mode reads counts back to the host (it is not
+ *  asynchronous).  Coherent frames reuse rays traced in the same mode.
  *  trace_from_rx: 1 casts the n_rays rays from every receiver and captures
  *  them at spheres of radius rx_radius around the transmitters (backward
  *  tracing, Sec. III: the ray count no longer grows with the number of
@@ -167,6 +187,7 @@ typedef struct dcem_trace_params {
   int32_t record_trace_log;
   int32_t mem_kind;
   int32_t trace_from_rx;
+  int32_t discovery;
 } dcem_trace_params;
 
 /* Counters and timings of the last dcem_refit_bvh + dcem_trace_frame. */

@@ -16,6 +16,8 @@ Functions and the passages they follow:
   fibonacci          ray sphere (step 1 of the frame algorithm)
   trace              bounces + capture spheres (steps 1-2); rays start at the
                      sources and are captured at spheres around the targets
+  visited_candidates every distinct series of faces the rays visit, tried
+                     against every target (steps 2-4 without capture spheres)
   candidates         de-duplicated (tx, rx, order, faces) keys (step 2's tables);
                      records traced backward from the receivers (Sec. III,
                      "Backward ray tracing": sources = receivers, targets =
@@ -244,6 +246,58 @@ def candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = T
     return keys, certain, possible
 
 
+def visited_candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: bool = True,
+                       backward: bool = False):
+    """Visited-series discovery (Sec. III, the frame algorithm's steps 2-4):
+    every series of faces a ray reflects on, up to the reflection limit, is
+    entered in the visited table of its depth, and each distinct series is
+    tried against every target (its images checked for a valid path); no
+    capture sphere is involved.  The series of depth d of a ray are the faces
+    of its first d hits (all of them hits).  Traced from the receivers
+    (backward), a series lists the faces from the receiver's end and its key
+    from the transmitter reverses them.  With los_always the empty series of
+    every source gives the direct paths.
+
+    Returns (keys, certain, possible) as candidates() does: keys = every
+    distinct (source, series) times every target, sorted; certain = the series
+    was visited by a ray whose first d hits no FP32 tracer can decide
+    differently; possible = keys."""
+    nsrc = tr.face.shape[0]
+    ntgt = nrx if not backward else ntx
+    unc = (tr.flags & (SEG_TIE | SEG_EDGE)) != 0
+    K1 = tr.flags.shape[-1]
+    fu = np.where(unc.any(axis=-1), unc.argmax(axis=-1), K1)
+    series = {}
+    for d in range(1, K + 1):
+        f = tr.face[:, :, :d]
+        ok = (f >= 0).all(axis=-1)
+        src_i, ray_i = np.nonzero(ok)
+        faces = f[ok]
+        if backward:
+            faces = faces[:, ::-1]
+        sure = fu[src_i, ray_i] >= d
+        for sc, fs, su in zip(src_i.tolist(), faces.tolist(), sure.tolist()):
+            k = (sc, d) + tuple(fs)
+            series[k] = series.get(k, False) or su
+    if los_always:
+        for sc in range(nsrc):
+            series[(sc, 0)] = True
+    rows, cert = [], []
+    for k, su in series.items():
+        src, d, fs = k[0], k[1], list(k[2:])
+        for tg in range(ntgt):
+            tx, rx = (tg, src) if backward else (src, tg)
+            rows.append([tx, rx, d] + fs + [-1] * (K - d))
+            cert.append(su)
+    if not rows:
+        z = np.zeros((0, 3 + K), np.int32)
+        return z, np.zeros(0, bool), z
+    keys = np.array(rows, dtype=np.int32)
+    order = np.lexsort(keys.T[::-1])
+    keys, certain = keys[order], np.array(cert, bool)[order]
+    return keys, certain, keys
+
+
 def _member(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     if len(a) == 0:
         return np.zeros(0, bool)
@@ -412,11 +466,12 @@ class FrameResult:
 def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Optional[int] = None,
           freqs=None, tx_power_w: Optional[float] = None, atten_db_per_km: float = 0.0,
           los_always: bool = True, nthreads: Optional[int] = None, pattern=None,
-          backward: bool = False) -> FrameResult:
+          backward: bool = False, visited: bool = False) -> FrameResult:
     """One frame, from scratch: the oracle keeps nothing between frames.
     backward: rays cast from the receivers and captured at spheres around the
     transmitters (Sec. III, "Backward ray tracing"); the trace result is then
-    per receiver."""
+    per receiver.  visited: candidates by visited-series discovery
+    (visited_candidates) instead of capture spheres."""
     K = scene.max_reflections if K is None else K
     freqs = scene.freqs_hz if freqs is None else freqs
     tx_power_w = scene.tx_power_w if tx_power_w is None else tx_power_w
@@ -429,7 +484,10 @@ def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Opt
     src, tgt = (rx, scene.tx) if backward else (scene.tx, rx)
     tr = trace(osc, src, tgt, scene.rx_radius, dirs, K, nthreads=nthreads)
     ntx, nrx = scene.tx.shape[0], rx.shape[0]
-    keys, certain, possible = candidates(tr, ntx, nrx, K, los_always, backward)
+    if visited:
+        keys, certain, possible = visited_candidates(tr, ntx, nrx, K, los_always, backward)
+    else:
+        keys, certain, possible = candidates(tr, ntx, nrx, K, los_always, backward)
     paths = refine(osc, scene.tx, rx, keys, K, freqs, tx_power_w, atten_db_per_km,
                    nthreads=nthreads, pattern=pattern)
     p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))

@@ -715,6 +715,8 @@ struct FramePlan {
   bool ahead = false;       // the frame's start and revalidation are already enqueued
   bool los = true;
   bool recapture = false;   // coherent frame whose receivers moved: kept segments captured again
+  bool visited = false;     // candidates from the visited series, not from capture spheres
+  bool seed_los = true;     // direct-path records seeded into the capture list at the frame's start
   int64_t n_work = 0;       // n_tx * n_rays
   int64_t expected = 0;     // work items the trace is sized for
   uint32_t n_prev = 0;      // captures of the previous frame (kept by a coherent frame)
@@ -742,6 +744,9 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   if (!std::isfinite(p->atten_db_per_km)) return fail(c, DCEM_E_INVALID_ARG, "bad atten_db_per_km");
   if (p->mode != DCEM_MODE_FULL && p->mode != DCEM_MODE_COHERENT) return fail(c, DCEM_E_INVALID_ARG, "bad mode");
   if (p->trace_from_rx != 0 && p->trace_from_rx != 1) return fail(c, DCEM_E_INVALID_ARG, "trace_from_rx must be 0 or 1");
+  if (p->discovery != DCEM_DISCOVER_CAPTURE && p->discovery != DCEM_DISCOVER_VISITED)
+    return fail(c, DCEM_E_INVALID_ARG, "bad discovery mode");
+  const bool visited = p->discovery == DCEM_DISCOVER_VISITED;
   const bool backward = p->trace_from_rx == 1;
   const int32_t n_src = backward ? p->n_rx : p->n_tx, n_tgt = backward ? p->n_tx : p->n_rx;
   const int64_t n_work = (int64_t)n_src * p->n_rays;
@@ -787,19 +792,21 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   // limit stay; targets may move (their captures are then taken again from
   // the cached segments)
   const bool same_geom = cfg.n_src == n_src && cfg.n_tgt == n_tgt && cfg.backward == backward &&
+                         cfg.visited == visited &&
                          cfg.K == p->max_reflections && cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius &&
                          cfg.src == srch && cfg.dirs_fib == fib &&
                          (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
   const bool rx_moved = cfg.tgt != tgth;
   const bool coherent = p->mode == DCEM_MODE_COHERENT && c->cache_valid && same_geom;
   const bool keep_cache = p->keep_cache != 0 || p->mode == DCEM_MODE_COHERENT;
-  plan.recapture = coherent && rx_moved;
+  plan.recapture = coherent && rx_moved && !visited;   // visited series are tried against the current targets
   // -- device inputs
   const bool need_dirs = !same_geom || !c->has_frame;
   const bool need_rx = need_dirs || rx_moved;
   cfg.n_src = n_src;
   cfg.n_tgt = n_tgt;
   cfg.backward = backward;
+  cfg.visited = visited;
   cfg.K = p->max_reflections;
   cfg.n_rays = p->n_rays;
   cfg.rx_radius = p->rx_radius;
@@ -813,6 +820,7 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   c->n_src = n_src;
   c->n_tgt = n_tgt;
   c->backward = backward;
+  c->visited = visited;
   c->n_rays = p->n_rays;
   c->K = p->max_reflections;
   c->n_freqs = p->n_freqs;
@@ -872,16 +880,21 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   // counts of the previous frame (read above): its capture list (reused by a
   // coherent frame), its re-trace count (sizes the persistent grid) and its
   // capture count (picks the de-duplication path)
-  plan.n_prev = plan.recapture ? 0u : (uint32_t)c->n_caps_host;   // moved receivers: captures taken again
+  // moved receivers: captures taken again; visited series: no captures
+  plan.n_prev = (plan.recapture || visited) ? 0u : (uint32_t)c->n_caps_host;
   plan.n_work = n_work;
   plan.expected = coherent ? ((c->has_frame && c->stats.coherent) ? (int64_t)c->last_cnt[kCntWork] : n_work) : n_work;
-  plan.small = c->has_frame && same_geom && c->n_caps_host <= small_path_capacity() * 3 / 4 && small_path_fits(c);
+  plan.small = !visited && c->has_frame && same_geom && c->n_caps_host <= small_path_capacity() * 3 / 4 &&
+               small_path_fits(c);
+  plan.visited = visited;
   plan.coherent = coherent;
   plan.keep_cache = keep_cache;
   plan.los = p->los_always != 0;
+  plan.seed_los = plan.los && !visited;   // visited discovery: the empty series gives the direct paths
   // a revalidation enqueued ahead (go_ahead) serves a coherent frame with the
   // same configuration, as long as the result block stayed in place
-  plan.ahead = c->revalidated_ahead && coherent && plan.los == c->last_los && c->frame_block.p == block_before;
+  plan.ahead =
+      c->revalidated_ahead && coherent && plan.seed_los == c->last_los && c->frame_block.p == block_before;
   if (plan.small) HIP_TRY(prepare_small_candidates(c), "alloc candidates");
   HIP_TRY(prepare_trace(c), "alloc traversal stack");
   return DCEM_OK;
@@ -893,7 +906,7 @@ dcem_status frame_front(dcem_ctx* c, const FramePlan& plan) {
   if (!plan.ahead) {
     ev_record(c, 0);
     if (!c->frame_begun) c->cur_caps ^= 1;
-    launch_frame_begin(c, plan.los);
+    launch_frame_begin(c, plan.seed_los);
     if (plan.coherent && c->refit_pending) {
       // the revalidation does not read the tree: one launch with the refit
       c->refit_pending = false;
@@ -909,7 +922,7 @@ dcem_status frame_front(dcem_ctx* c, const FramePlan& plan) {
   }
   c->frame_begun = false;
   c->revalidated_ahead = false;
-  c->last_los = plan.los;
+  c->last_los = plan.seed_los;
   HIP_TRY(hipGetLastError(), "frame start");
   return DCEM_OK;
 }
@@ -930,7 +943,13 @@ dcem_status frame_trace(dcem_ctx* c, const FramePlan& plan) {
 // Device part after the trace: candidates, refinement, reduction, and the
 // copy of the frame block to pinned host memory behind them.
 dcem_status frame_back(dcem_ctx* c, const FramePlan& plan) {
-  HIP_TRY(build_candidates(c, plan.small), "candidates");
+  if (plan.visited) {
+    bool too_many = false;
+    HIP_TRY(build_visited_candidates(c, plan.los, too_many), "visited-series candidates");
+    if (too_many) return fail(c, DCEM_E_UNSUPPORTED, "visited series x targets must be < 2^32");
+  } else {
+    HIP_TRY(build_candidates(c, plan.small), "candidates");
+  }
   ev_record(c, 3);
   HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");
   launch_refine(c);
@@ -1048,7 +1067,7 @@ dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, 
     double* g = ptr<double>(c->grad_buf);
     // the frame's unique candidates (its path arrays stay until the next
     // frame's trace, also when that frame has begun)
-    const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
+    const uint32_t nu = c->last_cnt[kCntUnique];
     launch_power_grad(c, nu, want_mat ? g : nullptr, g + ng, d_pattern ? g + 2 * ng : nullptr);
     HIP_TRY(hipGetLastError(), "gradient kernel");
     // one transfer into pinned memory, then host copies into the caller's arrays
@@ -1095,7 +1114,7 @@ dcem_status dcem_power_gradients_noalloc(dcem_ctx* c, double* d_eps_r, double* d
   const bool want_mat = (d_eps_r || d_sigma) && ng > 0;
   if (want_mat || d_pattern) {
     double* g = c->scratch;   // the array's address on this device, never its host-side name
-    const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
+    const uint32_t nu = c->last_cnt[kCntUnique];
     launch_power_grad(c, nu, want_mat ? g : nullptr, g + ng, d_pattern ? g + 2 * ng : nullptr);
     HIP_TRY(hipGetLastError(), "gradient kernel");
     // straight into the caller's arrays (no pinned staging)
@@ -1145,7 +1164,7 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
-  const uint32_t nu = c->n_caps_host > 0 ? c->last_cnt[kCntUnique] : 0;
+  const uint32_t nu = c->last_cnt[kCntUnique];   // cleared at each frame's start
   if (n_out) *n_out = nu;
   const int64_t n = std::min<int64_t>(nu, cap);
   if (n == 0) return DCEM_OK;
@@ -1161,33 +1180,21 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
   HIP_TRY(get(amp, c->path_amp, 48 * n * (size_t)c->n_freqs), "copy amp");
   HIP_TRY(get(first_ray, c->first_ray, 4 * n), "copy first ray");
   if (keys) {
-    const int64_t nc = c->n_caps_host, ks = c->key_stride;
-    const int W = c->key_words;
-    std::vector<uint32_t> kw((size_t)W * ks), perm(nc), pos(nu + 1);
-    HIP_TRY(hipMemcpy(kw.data(), c->cand_keys.p, 4 * kw.size(), hipMemcpyDeviceToHost), "copy keys");
-    HIP_TRY(hipMemcpy(perm.data(), c->cand_perm.p, 4 * perm.size(), hipMemcpyDeviceToHost), "copy perm");
-    HIP_TRY(hipMemcpy(pos.data(), c->uniq_idx.p, 4 * pos.size(), hipMemcpyDeviceToHost), "copy heads");
-    auto bits = [&](uint32_t idx, int at, int nb) {
-      uint32_t v = 0;
-      for (int b = 0; b < nb; ++b) {
-        const int q = at + b;
-        const uint32_t word = kw[(size_t)(W - 1 - q / 32) * ks + idx];
-        v |= ((word >> (q % 32)) & 1u) << b;
-      }
-      return v;
-    };
-    const int K = c->K, bf = c->bits_face;
+    // the decoded candidates (pair, order, faces) the de-duplication or the
+    // visited-series expansion wrote, in key order
+    std::vector<int32_t> pair((size_t)n), faces((size_t)n * std::max(c->K, 1));
+    std::vector<uint8_t> order((size_t)n);
+    HIP_TRY(hipMemcpy(pair.data(), c->pair_range.p, 4 * (size_t)n, hipMemcpyDeviceToHost), "copy pairs");
+    HIP_TRY(hipMemcpy(order.data(), c->path_order.p, (size_t)n, hipMemcpyDeviceToHost), "copy orders");
+    if (c->K > 0)
+      HIP_TRY(hipMemcpy(faces.data(), c->path_faces.p, 4 * (size_t)n * c->K, hipMemcpyDeviceToHost), "copy faces");
+    const int K = c->K;
     for (int64_t u = 0; u < n; ++u) {
-      const uint32_t idx = perm[pos[u]];
       int32_t* row = keys + u * (3 + K);
-      int at = K * bf;
-      const int order = (int)bits(idx, at, 4);
-      at += 4;
-      row[1] = (int32_t)bits(idx, at, c->bits_rx);
-      at += c->bits_rx;
-      row[0] = (int32_t)bits(idx, at, c->bits_tx);
-      row[2] = order;
-      for (int j = 0; j < K; ++j) row[3 + j] = j < order ? (int32_t)bits(idx, (K - 1 - j) * bf, bf) : -1;
+      row[0] = pair[u] / c->n_rx;
+      row[1] = pair[u] % c->n_rx;
+      row[2] = order[u];
+      for (int j = 0; j < K; ++j) row[3 + j] = j < order[u] ? faces[(size_t)u * K + j] : -1;
     }
   }
   return DCEM_OK;

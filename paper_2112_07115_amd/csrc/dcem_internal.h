@@ -100,6 +100,7 @@ struct TxPattern {
 struct TraceConfig {
   int32_t n_src = 0, n_tgt = 0, K = -1;
   bool backward = false;
+  bool visited = false;   // candidates by visited-series discovery
   int64_t n_rays = 0;
   float rx_radius = 0.f;
   std::vector<float> src, tgt;
@@ -240,6 +241,10 @@ struct dcem_ctx {
   int64_t path_cap = 0;          // bound on the number of unique paths of the frame
   bool small_path = false;       // candidates de-duplicated without a host round trip
   dcem::DevBuf sort_hist;
+  // visited-series discovery: the sorted unique series (source, order, faces,
+  // lowest ray) with per-source starts, and the expansion's survivor masks
+  bool visited = false;
+  dcem::DevBuf series_buf, expand_buf;
   int64_t n_caps_host = 0;
   double sqrt_pt = 0.0, atten_db_per_km = 0.0;
   // transmit pattern: the weights of the next traced frame, and those the
@@ -265,7 +270,7 @@ struct dcem_ctx {
             &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag, &stack_spill,
             &frame_block, &cand_keys, &cand_perm, &cand_tmp, &uniq_idx, &first_ray, &path_valid, &path_len,
             &path_tau, &path_aod, &path_aoa, &path_amp, &pair_range, &path_order, &path_faces, &path_pts,
-            &sort_hist};
+            &sort_hist, &series_buf, &expand_buf};
   }
 };
 
@@ -355,6 +360,11 @@ size_t batch_table_bytes(int n);
 
 // ---- candidates, refinement and accumulation (refine.hip)
 hipError_t build_candidates(dcem_ctx* c, bool small);
+// Visited-series discovery: every distinct series of faces the frame's rays
+// reflect on (per source, up to K), tried against every target; the
+// candidates whose image-method points lie inside their segments and faces
+// become the frame's paths (host round trips for the counts).
+hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many);
 // Buffers of the one-workgroup de-duplication path and of its paths.
 hipError_t prepare_small_candidates(dcem_ctx* c);
 bool small_path_fits(const dcem_ctx* c);

@@ -642,6 +642,39 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
   return false;
 }
 
+// Image-method geometry of a candidate (Sec. III step 3): img [3 (order + 1)]
+// receives the images of T through the planes pl[0..order) in turn, pts
+// [3 (order + 2)] the transmitter, the reflection points walked back from R
+// towards the images, and R; d the distance from R to the last image (the
+// path length).  False when a walk is parallel to its plane or a reflection
+// point falls outside its open segment (then the points past it are not
+// set).  The refinement and the visited-series expansion share it, so both
+// take the same decisions.
+__device__ inline bool image_points(D3 T, D3 R, const double4* pl, int order, double* img, double* pts, double& d) {
+  D3 im = T;
+  img[0] = im.x; img[1] = im.y; img[2] = im.z;
+  for (int j = 1; j <= order; ++j) {
+    const D3 n = {pl[j - 1].x, pl[j - 1].y, pl[j - 1].z};
+    im = im - (2.0 * (dot(im, n) - pl[j - 1].w)) * n;
+    img[3 * j] = im.x; img[3 * j + 1] = im.y; img[3 * j + 2] = im.z;
+  }
+  pts[0] = T.x; pts[1] = T.y; pts[2] = T.z;
+  pts[3 * (order + 1)] = R.x; pts[3 * (order + 1) + 1] = R.y; pts[3 * (order + 1) + 2] = R.z;
+  d = len(R - im);
+  D3 Q = R;
+  for (int j = order; j >= 1; --j) {
+    const D3 n = {pl[j - 1].x, pl[j - 1].y, pl[j - 1].z};
+    const D3 D = D3{img[3 * j], img[3 * j + 1], img[3 * j + 2]} - Q;
+    const double den = dot(D, n);
+    if (den == 0.0) return false;
+    const double s = (pl[j - 1].w - dot(Q, n)) / den;
+    if (!(s > 0.0 && s < 1.0)) return false;
+    Q = Q + s * D;
+    pts[3 * j] = Q.x; pts[3 * j + 1] = Q.y; pts[3 * j + 2] = Q.z;
+  }
+  return true;
+}
+
 // Refinement of one unique candidate u by one block of K + 1 wavefronts.
 //  1. Geometry (thread 0; first ray over the candidate's captures on wave 0):
 //     decode the key, image sources through the face planes and reflection
@@ -690,36 +723,9 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
     if (lane == 0) {
       const int tx = pair / a.n_rx, rx = pair - tx * a.n_rx;
       const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
-      // images of the transmitter through the face planes in turn (Sec. III)
-      D3 im = T;
-      simg[0] = im.x; simg[1] = im.y; simg[2] = im.z;
-      for (int j = 1; j <= order0; ++j) {
-        const double4 pl = spl[j - 1];
-        const D3 n = {pl.x, pl.y, pl.z};
-        im = im - (2.0 * (dot(im, n) - pl.w)) * n;
-        simg[3 * j] = im.x; simg[3 * j + 1] = im.y; simg[3 * j + 2] = im.z;
-      }
-      // reflection points walked back from the receiver
+      const bool ok = image_points(T, R, spl, order0, simg, sP, sd);
       double* P = a.pts + (size_t)u * (K + 2) * 3;
-      bool ok = true;
-      D3 Q = R;
-      for (int j = order0; j >= 1; --j) {
-        const double4 pl = spl[j - 1];
-        const D3 n = {pl.x, pl.y, pl.z};
-        const D3 D = D3{simg[3 * j], simg[3 * j + 1], simg[3 * j + 2]} - Q;
-        const double den = dot(D, n);
-        if (den == 0.0) { ok = false; break; }
-        const double s = (pl.w - dot(Q, n)) / den;
-        if (!(s > 0.0 && s < 1.0)) { ok = false; break; }
-        Q = Q + s * D;
-        P[3 * j] = Q.x; P[3 * j + 1] = Q.y; P[3 * j + 2] = Q.z;
-        sP[3 * j] = Q.x; sP[3 * j + 1] = Q.y; sP[3 * j + 2] = Q.z;
-      }
-      P[0] = T.x; P[1] = T.y; P[2] = T.z;
-      P[3 * (order0 + 1)] = R.x; P[3 * (order0 + 1) + 1] = R.y; P[3 * (order0 + 1) + 2] = R.z;
-      sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
-      sP[3 * (order0 + 1)] = R.x; sP[3 * (order0 + 1) + 1] = R.y; sP[3 * (order0 + 1) + 2] = R.z;
-      sd = len(R - im);
+      for (int j = 0; j < 3 * (order0 + 2); ++j) P[j] = sP[j];
       a.length[u] = sd;
       sorder = order0;
       sok = ok ? 1 : 0;
@@ -820,6 +826,208 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       for (int k = 0; k < 6; ++k) a.amp[((size_t)u * a.n_freqs + fi) * 6 + k] = 0.0;
 }
 
+
+// ---- Visited-series discovery (Sec. III, the frame algorithm's steps 2-4:
+// each new series of faces a ray visits is entered in the visited table of its
+// depth and generates images, which are checked for a valid path; no capture
+// sphere decides which series are tried).
+//
+// 1. Items: for every ray, the series of its first d hits for d = 1..(its
+//    leading hits, at most K), plus the empty series of every source (the
+//    direct paths).  Item key: words 0..W-1 hold (source, order, faces in path
+//    order) in a candidate key's layout without the receiver field; word W
+//    holds the item's ray id (kNoRay for an empty series), so after one sort
+//    the head of each run of equal series carries the lowest ray visiting it.
+// 2. Sort, run heads, compaction: the unique series, sorted, and per source
+//    the start of its series.
+// 3. Expansion: candidate u of the S x n_tgt (series, target) pairs, numbered
+//    in the order of its path key (forward: source-major, then target, then
+//    series; backward: target-major, then series), survives when its
+//    image-method points lie strictly inside their segments and inside their
+//    faces (the refinement's first checks, with the same code); survivors are
+//    compacted in order into the decoded-candidate arrays.
+__global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict__ face_log, int64_t n_work,
+                                                      int n_src, int los, KeyLayout S, uint32_t* __restrict__ keys,
+                                                      int64_t stride, uint32_t* __restrict__ count, uint32_t cap) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  int depth = 0;   // leading hits of ray position i, at most K
+  if (i < (uint64_t)n_work)
+    while (depth < S.K && face_log[(size_t)depth * n_work + i] >= 0) ++depth;
+  const bool empty_series = los && i < (uint32_t)n_src;
+  const int n_items = depth + (empty_series ? 1 : 0);
+  int incl = n_items;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  const int total = __shfl(incl, kWave - 1);
+  uint32_t base = 0;
+  if (lane == kWave - 1 && total > 0) base = atomicAdd(count, (uint32_t)total);
+  base = __shfl(base, kWave - 1);
+  uint32_t slot = base + (uint32_t)(incl - n_items);
+  if (depth > 0) {
+    const uint32_t src = (uint32_t)(i / (uint64_t)S.n_rays);
+    const uint32_t rid = ray_of(i, S);
+    for (int d = 1; d <= depth; ++d, ++slot) {
+      if (slot >= cap) continue;   // the host sizes cap for every item
+      uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < d; ++j) {
+        const int bounce = S.backward ? d - 1 - j : j;
+        put_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf, (uint32_t)face_log[(size_t)bounce * n_work + i]);
+      }
+      put_bits(w, S.W, S.K * S.bf, 4, (uint32_t)d);
+      put_bits(w, S.W, S.K * S.bf + 4, S.bt, src);
+      for (int k = 0; k < S.W; ++k) keys[k * stride + slot] = w[k];
+      keys[S.W * stride + slot] = rid;
+    }
+  }
+  if (empty_series && slot < cap) {
+    uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    put_bits(w, S.W, S.K * S.bf + 4, S.bt, i);
+    for (int k = 0; k < S.W; ++k) keys[k * stride + slot] = w[k];
+    keys[S.W * stride + slot] = kNoRay;
+  }
+}
+
+// The unique series: per unique run s (heads in uniq_pos), its source, order,
+// faces [K] (path order, -1 past the order) and lowest ray id (-1: the empty
+// series).
+struct SeriesOut {
+  int32_t* src;
+  int32_t* order;
+  int32_t* first;
+  int32_t* faces;
+};
+
+__global__ __launch_bounds__(256) void k_series_info(const uint32_t* __restrict__ keys, int64_t stride, KeyLayout S,
+                                                     const uint32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ uniq_pos,
+                                                     const uint32_t* __restrict__ n_series, SeriesOut o) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *n_series) return;
+  const uint32_t idx = perm[uniq_pos[s]];
+  uint32_t w[8];
+  for (int k = 0; k < S.W; ++k) w[k] = keys[k * stride + idx];
+  const uint32_t order = key_bits(w, S.W, S.K * S.bf, 4);
+  o.src[s] = (int32_t)key_bits(w, S.W, S.K * S.bf + 4, S.bt);
+  o.order[s] = (int32_t)order;
+  const uint32_t rid = keys[S.W * stride + idx];
+  o.first[s] = rid == kNoRay ? -1 : (int32_t)rid;
+  for (int j = 0; j < S.K; ++j)
+    o.faces[(size_t)s * S.K + j] = (uint32_t)j < order ? (int32_t)key_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf) : -1;
+}
+
+// start[src] = first unique series of source src (lower bound), start[n_src] = S.
+__global__ __launch_bounds__(256) void k_series_starts(const int32_t* __restrict__ ser_src,
+                                                       const uint32_t* __restrict__ n_series, int n_src,
+                                                       uint32_t* __restrict__ start) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > n_src) return;
+  uint32_t lo = 0, hi = *n_series;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ser_src[mid] < q) lo = mid + 1;
+    else hi = mid;
+  }
+  start[q] = lo;
+}
+
+struct ExpandArgs {
+  SeriesOut ser;
+  const uint32_t* start;   // [n_src + 1]
+  uint32_t n_series;
+  uint64_t n_cand;         // n_series * n_tgt
+  int n_src, n_tgt, n_rx, K;
+  bool backward;
+  const float* src_pos;
+  const float* tgt_pos;
+  RefineArgs ra;           // faces: planes, triangles (in_face)
+  uint64_t* mask;          // [ceil(n_cand / 64)] survivors, one bit per candidate
+  uint32_t* block_cnt;     // survivors per block, then (scanned) their offsets
+  uint32_t capacity;       // decoded-candidate entries available
+  uint32_t* err;           // DCEM_ERR_CAPTURES when survivors exceed the capacity
+  UniqueOut out;
+};
+
+// (series, target) of candidate u, in path-key order.
+__device__ inline void expand_index(const ExpandArgs& e, uint64_t u, uint32_t& s, uint32_t& tgt) {
+  if (e.backward) {
+    tgt = (uint32_t)(u / e.n_series);
+    s = (uint32_t)(u - (uint64_t)tgt * e.n_series);
+    return;
+  }
+  // the source whose block [start * n_tgt, start' * n_tgt) holds u
+  int lo = 0, hi = e.n_src - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint64_t)e.start[mid] * e.n_tgt <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint64_t local = u - (uint64_t)e.start[lo] * e.n_tgt;
+  const uint32_t cnt = e.start[lo + 1] - e.start[lo];
+  tgt = (uint32_t)(local / cnt);
+  s = e.start[lo] + (uint32_t)(local - (uint64_t)tgt * cnt);
+}
+
+// write = 0: survivor mask and per-block counts; write = 1: the survivors'
+// decoded candidates at the scanned block offsets.
+__global__ __launch_bounds__(256) void k_expand(ExpandArgs e, int write) {
+  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  __shared__ uint32_t wcnt[256 / kWave];
+  bool keep = false;
+  uint32_t s = 0, tgt = 0;
+  if (u < e.n_cand) {
+    if (write) {
+      keep = (e.mask[u / kWave] >> lane) & 1ull;
+      if (keep) expand_index(e, u, s, tgt);
+    } else {
+      expand_index(e, u, s, tgt);
+      const int order = e.ser.order[s];
+      const uint32_t src = (uint32_t)e.ser.src[s];
+      const uint32_t txi = e.backward ? tgt : src, rxi = e.backward ? src : tgt;
+      const D3 T = fvec(e.backward ? e.tgt_pos : e.src_pos, (int)txi);
+      const D3 R = fvec(e.backward ? e.src_pos : e.tgt_pos, (int)rxi);
+      double4 pl[kMaxK];
+      for (int j = 0; j < order; ++j) pl[j] = e.ra.plane[e.ser.faces[(size_t)s * e.K + j]];
+      double img[3 * (kMaxK + 1)], pts[3 * (kMaxK + 2)], d;
+      keep = image_points(T, R, pl, order, img, pts, d);
+      for (int j = 1; j <= order && keep; ++j)
+        keep = in_face(e.ra, e.ser.faces[(size_t)s * e.K + j - 1], D3{pts[3 * j], pts[3 * j + 1], pts[3 * j + 2]},
+                       D3{pl[j - 1].x, pl[j - 1].y, pl[j - 1].z});
+    }
+  }
+  const uint64_t m = __ballot(keep);
+  if (!write) {
+    if (lane == 0 && u < e.n_cand) e.mask[u / kWave] = m;
+    if (lane == 0) wcnt[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int v = 0; v < 256 / kWave; ++v) t += wcnt[v];
+      e.block_cnt[blockIdx.x] = t;
+    }
+    return;
+  }
+  if (lane == 0) wcnt[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t pos = e.block_cnt[blockIdx.x];
+  for (int v = 0; v < wave; ++v) pos += wcnt[v];
+  pos += (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  if (!keep) return;
+  if (pos >= e.capacity) {
+    atomicOr(e.err, DCEM_ERR_CAPTURES);
+    return;
+  }
+  const int order = e.ser.order[s];
+  const uint32_t src = (uint32_t)e.ser.src[s];
+  const uint32_t txi = e.backward ? tgt : src, rxi = e.backward ? src : tgt;
+  e.out.pair[pos] = (int32_t)(txi * (uint32_t)e.n_rx + rxi);
+  e.out.order[pos] = (uint8_t)order;
+  for (int j = 0; j < e.K; ++j) e.out.faces[(size_t)pos * e.K + j] = e.ser.faces[(size_t)s * e.K + j];
+  e.out.first_ray[pos] = e.ser.first[s];
+}
 
 // One wavefront per (tx, rx): sum the valid paths of that pair (contiguous in
 // key order) with a fixed lane assignment and butterfly, so the result is
@@ -1183,6 +1391,119 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   hipLaunchKernelGGL(k_unique_info, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L, perm,
                      ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique, ptr<Capture>(c->caps[c->cur_caps]),
                      unique_out(c));
+  return hipGetLastError();
+}
+
+hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
+  hipError_t e;
+  too_many = false;
+  c->small_path = false;
+  c->path_cap = 0;
+  // the series key: a candidate key's layout with the source in the
+  // transmitter field and no receiver field, then the ray id word
+  KeyLayout S = key_layout(c);
+  S.bt = bits_for(c->n_src);
+  S.br = 0;
+  S.bits = S.bt + 4 + S.K * S.bf;
+  S.W = (S.bits + 31) / 32;
+  const int Wt = S.W + 1;
+  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t cap = (los ? c->n_src : 0) + n_work * c->K;
+  if (cap == 0) return hipSuccess;   // no series: no candidates (the unique counter was cleared)
+  if (cap >= ((int64_t)1 << 32) - 1) {
+    too_many = true;
+    return hipSuccess;
+  }
+  const int nb = (int)((cap + 255) / 256);
+  if ((e = ensure(c->cand_keys, sizeof(uint32_t) * Wt * cap)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_perm, sizeof(uint32_t) * 2 * cap)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_tmp, cap + 16 + sizeof(uint32_t) * (nb + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (cap + 1))) != hipSuccess) return e;
+  // series_buf: [0] item count, [1] series count (256 B), then the series
+  // arrays (source, order, lowest ray, faces [K]) and the per-source starts
+  const size_t K = (size_t)std::max(c->K, 1);
+  const size_t ser_bytes = 256 + sizeof(int32_t) * (size_t)cap * (3 + K) + sizeof(uint32_t) * ((size_t)c->n_src + 1);
+  if ((e = ensure(c->series_buf, ser_bytes)) != hipSuccess) return e;
+  uint32_t* sc = ptr<uint32_t>(c->series_buf);
+  SeriesOut so;
+  so.src = reinterpret_cast<int32_t*>(ptr<char>(c->series_buf) + 256);
+  so.order = so.src + cap;
+  so.first = so.order + cap;
+  so.faces = so.first + cap;
+  uint32_t* start = reinterpret_cast<uint32_t*>(so.faces + (size_t)cap * K);
+  uint32_t* keys = ptr<uint32_t>(c->cand_keys);
+  uint32_t* perm = ptr<uint32_t>(c->cand_perm);
+  uint8_t* head = ptr<uint8_t>(c->cand_tmp);
+  uint32_t* bcnt = reinterpret_cast<uint32_t*>(ptr<uint8_t>(c->cand_tmp) + ((cap + 15) / 16) * 16);
+  fill_u32(sc, 0u, 2, c->stream);
+  const int64_t n_thr = std::max<int64_t>(n_work, c->n_src);
+  hipLaunchKernelGGL(k_series_items, dim3((unsigned)((n_thr + 255) / 256)), dim3(256), 0, c->stream,
+                     ptr<int32_t>(c->face_log), n_work, c->n_src, los ? 1 : 0, S, keys, cap, sc, (uint32_t)cap);
+  uint32_t n_items = 0;
+  if ((e = hipMemcpyAsync(&n_items, sc, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (n_items == 0) return hipSuccess;
+  n_items = std::min<uint32_t>(n_items, (uint32_t)cap);
+  if ((e = radix_sort_perm(c, keys, Wt, 32 + S.bits, sc, cap, perm, perm + cap, c->stream)) != hipSuccess) return e;
+  const int nbi = (int)((n_items + 255) / 256);
+  hipLaunchKernelGGL(k_heads, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S.W, perm, n_items, head, bcnt);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nbi, sc + 1);
+  hipLaunchKernelGGL(k_compact, dim3(nbi), dim3(256), 0, c->stream, head, bcnt, n_items, sc + 1,
+                     ptr<uint32_t>(c->uniq_idx));
+  hipLaunchKernelGGL(k_series_info, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S, perm,
+                     ptr<uint32_t>(c->uniq_idx), sc + 1, so);
+  hipLaunchKernelGGL(k_series_starts, dim3((c->n_src + 1 + 255) / 256), dim3(256), 0, c->stream, so.src, sc + 1,
+                     c->n_src, start);
+  uint32_t n_series = 0;
+  if ((e = hipMemcpyAsync(&n_series, sc + 1, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  const uint64_t n_cand = (uint64_t)n_series * (uint64_t)c->n_tgt;
+  if (n_cand == 0) return hipSuccess;
+  if (n_cand >= ((uint64_t)1 << 32) - 256) {
+    too_many = true;
+    return hipSuccess;
+  }
+  const uint32_t nbe = (uint32_t)((n_cand + 255) / 256);
+  const size_t mask_words = (size_t)nbe * 4;
+  if ((e = ensure(c->expand_buf, sizeof(uint64_t) * mask_words + sizeof(uint32_t) * ((size_t)nbe + 8))) != hipSuccess)
+    return e;
+  ExpandArgs x;
+  x.ser = so;
+  x.start = start;
+  x.n_series = n_series;
+  x.n_cand = n_cand;
+  x.n_src = c->n_src;
+  x.n_tgt = c->n_tgt;
+  x.n_rx = c->n_rx;
+  x.K = c->K;
+  x.backward = c->backward;
+  x.src_pos = ptr<float>(c->src_pos);
+  x.tgt_pos = ptr<float>(c->tgt_pos);
+  x.ra = RefineArgs{};
+  x.ra.plane = ptr<double4>(c->face_plane);
+  x.ra.face_tri_off = ptr<int32_t>(c->face_tri_off);
+  x.ra.face_tris = ptr<int32_t>(c->face_tris);
+  x.ra.face_slots = ptr<int32_t>(c->face_slots);
+  x.ra.tri4 = ptr<Leaf>(c->tri4);
+  x.mask = ptr<uint64_t>(c->expand_buf);
+  x.block_cnt = reinterpret_cast<uint32_t*>(x.mask + mask_words);
+  x.capacity = 0;
+  x.err = c->err_dev;
+  x.out = unique_out(c);
+  hipLaunchKernelGGL(k_expand, dim3(nbe), dim3(256), 0, c->stream, x, 0);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, x.block_cnt, (int)nbe,
+                     c->cnt_dev + kCntUnique);
+  uint32_t n_keep = 0;
+  if ((e = hipMemcpyAsync(&n_keep, c->cnt_dev + kCntUnique, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  const uint32_t capacity = (uint32_t)std::min<int64_t>(n_keep, c->cap_capacity);
+  if (n_keep > capacity) fill_u32(c->cnt_dev + kCntUnique, capacity, 1, c->stream);
+  c->path_cap = capacity;
+  if ((e = ensure_paths(c, c->path_cap)) != hipSuccess) return e;
+  x.capacity = capacity;
+  x.out = unique_out(c);
+  if (n_keep > 0) hipLaunchKernelGGL(k_expand, dim3(nbe), dim3(256), 0, c->stream, x, 1);
   return hipGetLastError();
 }
 

@@ -254,6 +254,7 @@ struct TraceArgs {
   const float* tx;
   const float* rx;
   int n_rx;
+  int capture;          // 0: no capture tests (candidates come from the visited series)
   const Node* rx_nodes; // BVH over the capture spheres (boxes padded), leaves = sphere ids
   int n_rx_nodes;
   float r2;
@@ -355,6 +356,7 @@ __device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const floa
 __device__ void capture_segment(const TraceArgs& a, const Ray& r, bool hit, float th, float tend, float dd,
                                 uint32_t work, uint32_t txi, int k, ThreadStack& stack, bool& overflow,
                                 bool& cap_over) {
+  if (!a.capture) return;
   const float za = r.o.z;
   const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
   if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     // capture: the group's lanes share the receivers
     const float za = r.o.z;
     const float zb = hit ? __fmaf_rn(th, r.d.z, r.o.z) : (r.d.z > 0 ? INFINITY : (r.d.z < 0 ? -INFINITY : r.o.z));
-    if (fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
+    if (a.capture && fmaxf(za, zb) >= a.rx_zlo && fminf(za, zb) <= a.rx_zhi) {
       // cull by the xy bounds of the segment's part inside the receivers' z
       // band: a sphere the segment meets has its centre within a radius of
       // that part (rx_cull adds slack far above the rounding here)
@@ -1316,6 +1318,7 @@ TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_pre
   a.tx = ptr<float>(c->src_pos);
   a.rx = ptr<float>(c->tgt_pos);
   a.n_rx = c->n_tgt;
+  a.capture = c->visited ? 0 : 1;
   a.rx_nodes = ptr<Node>(c->rx_nodes);
   a.n_rx_nodes = c->n_rx_nodes;
   a.restart = all_rays ? nullptr : ptr<uint8_t>(c->invalid_flag);

@@ -25,6 +25,7 @@ E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED = -
 MEM_HOST, MEM_DEVICE = 0, 1
 MODE_FULL, MODE_COHERENT = 0, 1
 FORCE_REBUILD = 1
+DISCOVER_CAPTURE, DISCOVER_VISITED = 0, 1
 MAX_REFLECTIONS = 10
 PATTERN_TAPS = 16
 
@@ -43,7 +44,7 @@ class TraceParams(ctypes.Structure):
                 ("n_rays", _I64), ("ray_dirs", _P), ("max_reflections", _I32), ("freqs_hz", _P),
                 ("n_freqs", _I32), ("tx_power_w", _F64), ("atten_db_per_km", _F64), ("mode", _I32),
                 ("los_always", _I32), ("keep_cache", _I32), ("record_trace_log", _I32), ("mem_kind", _I32),
-                ("trace_from_rx", _I32)]
+                ("trace_from_rx", _I32), ("discovery", _I32)]
 
 
 class FrameStats(ctypes.Structure):
@@ -287,7 +288,7 @@ class Context:
     def _params(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None, max_reflections: int = 2,
                 freqs_hz: Sequence[float] = (28e9,), tx_power_w: float = 5.0, atten_db_per_km: float = 0.0,
                 mode: int = MODE_FULL, los_always: bool = True, keep_cache: bool = False,
-                record_trace_log: bool = False, trace_from_rx: bool = False):
+                record_trace_log: bool = False, trace_from_rx: bool = False, discovery: int = 0):
         """dcem_trace_params of one frame (arrays kept alive on the context)."""
         dev = ray_dirs is not None and not isinstance(ray_dirs, np.ndarray) and ray_dirs.is_cuda
         if dev:
@@ -301,7 +302,7 @@ class Context:
                         int(n_rays), _addr(dirs), int(max_reflections), _addr(fr), int(fr.shape[0]),
                         float(tx_power_w), float(atten_db_per_km), int(mode), int(bool(los_always)),
                         int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST,
-                        int(bool(trace_from_rx)))
+                        int(bool(trace_from_rx)), int(discovery))
         n_tx, n_rx = int(txa.shape[0]), int(rxa.shape[0])
         shape = (int(max_reflections), int(fr.shape[0]), n_tx, n_rx, int(n_rays), n_rx if trace_from_rx else n_tx)
         return p, shape
@@ -314,9 +315,10 @@ class Context:
                     max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
                     tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
                     los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False,
-                    trace_from_rx: bool = False):
+                    trace_from_rx: bool = False, discovery: int = 0):
         p, shape = self._params(tx, rx, rx_radius, n_rays, ray_dirs, max_reflections, freqs_hz, tx_power_w,
-                                atten_db_per_km, mode, los_always, keep_cache, record_trace_log, trace_from_rx)
+                                atten_db_per_km, mode, los_always, keep_cache, record_trace_log, trace_from_rx,
+                                discovery)
         self._check(self.lib.dcem_trace_frame(self.handle, ctypes.byref(p)))
         self._traced(shape)
 
@@ -519,7 +521,7 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
                       n_rays: Optional[int] = None, K: Optional[int] = None, rebuild: bool = False,
                       keep_cache: bool = False, record_trace_log: bool = False, los_always: bool = True,
                       threshold: float = 1.5, atten_db_per_km: float = 0.0,
-                      trace_from_rx: bool = False) -> FrameOutput:
+                      trace_from_rx: bool = False, discovery: int = 0) -> FrameOutput:
     """Convenience: place the scene's objects for `frame`, update the BVH, trace, read power."""
     if scene.object_vertex_range.shape[0]:
         ctx.set_object_transforms(scene.transforms(frame))
@@ -532,6 +534,6 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
                     max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
                     tx_power_w=scene.tx_power_w, atten_db_per_km=atten_db_per_km, mode=mode,
                     los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log,
-                    trace_from_rx=trace_from_rx)
+                    trace_from_rx=trace_from_rx, discovery=discovery)
     pc, pi = ctx.received_power()
     return FrameOutput(pc, pi)

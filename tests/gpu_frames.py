@@ -32,22 +32,28 @@ def radius_of(scene):
     return float(np.linalg.norm(pts, axis=1).max())
 
 
-def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=True, check_paths=True):
+def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=True, check_paths=True,
+                  visited=False):
     """Compare the context's last frame with the oracle's FrameResult `ofr`
-    (traced over the same n_rays directions).  Returns a dict of statistics."""
+    (traced over the same n_rays directions).  visited: the frame's candidates
+    came from visited-series discovery (no capture records; keys compared by
+    parity.compare_visited).  Returns a dict of statistics."""
     st = {}
     if check_log:
         g_tri, g_t, g_len = ctx.trace_log()
         st = parity.compare_trace(g_tri, g_t, g_len, ofr.trace, scene.tri_face, radius=radius_of(scene))
         log("  trace", st)
-    if check_captures:
+    if check_captures and not visited:
         g_caps = ctx.captures()
         g_caps = g_caps[g_caps[:, 0] >= 0]
         cs = parity.compare_captures(g_caps, ofr.trace, np.arange(n_rays), n_rays)
         log("  captures", cs)
     if check_paths:
         gp = ctx.paths()
-        comparable, n_common = parity.compare_paths(gp, ofr, n_rays)
+        if visited:
+            comparable, n_common = parity.compare_visited(gp, ofr, n_rays)
+        else:
+            comparable, n_common = parity.compare_paths(gp, ofr, n_rays)
         worst = parity.compare_power(out.p_coh, ofr.p_coh, comparable)
         worst_inc = parity.compare_power(out.p_inc, ofr.p_inc, comparable)
         log("  paths: gpu %d oracle %d common %d valid %d; comparable rx %d/%d; worst %.2e dB (P_inc %.2e dB)" %
@@ -61,18 +67,18 @@ def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=T
 
 
 def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captures=True, check_paths=True,
-             los_always=True, atten_db_per_km=0.0, upload=True, backward=False):
+             los_always=True, atten_db_per_km=0.0, upload=True, backward=False, visited=False):
     """Trace one FULL frame on both sides and compare everything; returns
     (stats, GPU output, oracle FrameResult).  backward: rays cast from the
     receivers on both sides (trace logs and captures are then per receiver)."""
     K = scene.max_reflections if K is None else K
     log("case", scene.name, "frame", frame, "K", K, "rays", n_rays if dirs is None else len(dirs),
-        "atten", atten_db_per_km, "backward" if backward else "forward")
+        "atten", atten_db_per_km, "backward" if backward else "forward", "visited" if visited else "capture")
     if upload:
         ctx.scene_upload(scene)
     out = dcem.trace_scene_frame(ctx, scene, frame=frame, ray_dirs=dirs, n_rays=n_rays, K=K,
                                  record_trace_log=True, los_always=los_always, atten_db_per_km=atten_db_per_km,
-                                 trace_from_rx=backward)
+                                 trace_from_rx=backward, discovery=dcem.DISCOVER_VISITED if visited else 0)
     if dirs is None:
         g_dirs = ctx.ray_dirs()
         o_dirs = O.fibonacci(n_rays or scene.n_rays)
@@ -80,9 +86,9 @@ def run_pair(ctx, O, scene, frame=0, dirs=None, K=None, n_rays=None, check_captu
     else:
         o_dirs = dirs
     ofr = O.frame(scene, frame_index=frame, dirs=o_dirs, K=K, los_always=los_always,
-                  atten_db_per_km=atten_db_per_km, backward=backward)
+                  atten_db_per_km=atten_db_per_km, backward=backward, visited=visited)
     st = compare_frame(ctx, scene, ofr, out, o_dirs.shape[0], check_captures=check_captures,
-                       check_paths=check_paths)
+                       check_paths=check_paths, visited=visited)
     return st, out, ofr
 
 

@@ -209,3 +209,53 @@ def compare_power(g_pc, o_pc, comparable, tol_db=0.01):
     assert worst <= tol_db, "power differs by %.4g dB on a comparable receiver" % worst
     assert not np.isnan(g_pc).any(), "NaN power on the GPU"
     return worst
+
+
+def compare_visited(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6):
+    """Candidates of visited-series discovery against the oracle's.
+
+    The oracle refines every (series, target) pair; the GPU keeps those whose
+    image-method points lie inside their segments and faces, then validates
+    them.  Checked: every GPU key is one of the oracle's or comes from a ray
+    whose first `order` hits the oracle marks uncertain; every certain, valid,
+    non-marginal oracle path is on the GPU; keys on both sides agree on
+    validity and attributes (marginal ones excepted).  Returns the (tx, rx)
+    pairs whose power is comparable: a pair is excluded when one of its keys is
+    marginal, or uncertain and valid on either side."""
+    gk = {tuple(int(x) for x in k): i for i, k in enumerate(gp["keys"])}
+    ok_ = {tuple(int(x) for x in k): i for i, k in enumerate(ofr.keys)}
+    fu = first_uncertain(ofr.trace.flags)
+    unexplained = []
+    for k, i in gk.items():
+        if k in ok_:
+            continue
+        fr = int(gp["first_ray"][i])
+        if fr < 0 or k[2] < fu[fr // n_rays, fr % n_rays]:
+            unexplained.append(k)
+    assert not unexplained, "GPU keys the oracle cannot explain: %s" % unexplained[:10]
+    missing = [k for k, j in ok_.items()
+               if ofr.certain[j] and ofr.paths.valid[j] and not ofr.paths.marginal[j] and k not in gk]
+    assert not missing, "certain valid oracle paths missing on the GPU: %s" % sorted(missing)[:10]
+    bad = []
+    n_common = 0
+    for k, i in gk.items():
+        j = ok_.get(k)
+        if j is None or ofr.paths.marginal[j]:
+            continue
+        n_common += 1
+        for b in compare_path_attrs(gp, i, ofr.paths, j, eps_len=eps_len, eps_amp=eps_amp):
+            bad.append((k,) + b)
+    assert not bad, "path mismatches: %s" % bad[:5]
+    ntx, nrx = ofr.p_coh.shape[1], ofr.p_coh.shape[2]
+    comparable = np.ones((ntx, nrx), bool)
+    for k, j in ok_.items():
+        if ofr.paths.marginal[j]:
+            comparable[k[0], k[1]] = False
+        elif not ofr.certain[j]:
+            i = gk.get(k)
+            if ofr.paths.valid[j] or (i is not None and gp["valid"][i]):
+                comparable[k[0], k[1]] = False
+    for k, i in gk.items():
+        if k not in ok_ and gp["valid"][i]:
+            comparable[k[0], k[1]] = False
+    return comparable, n_common

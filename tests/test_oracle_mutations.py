@@ -71,6 +71,9 @@ PY_MUTATIONS = {
                                     "out[sel, 3:3 + o] = rows[sel, 3:3 + o]", "test_oracle_variants.py"),
     "backward_pair_not_swapped": ("out[:, 0], out[:, 1] = rows[:, 1], rows[:, 0]",
                                   "out[:, 0], out[:, 1] = rows[:, 0], rows[:, 1]", "test_oracle_variants.py"),
+    # visited series that skip a ray's first hit, or keep the receiver's face order
+    "visited_series_offset": ("f = tr.face[:, :, :d]", "f = tr.face[:, :, 1:d + 1]", "test_oracle_variants.py"),
+    "visited_backward_not_reversed": ("faces = faces[:, ::-1]", "faces = faces[:, ::1]", "test_oracle_variants.py"),
 }
 
 

@@ -1,5 +1,5 @@
 """Pins of the oracle's paper variants (Sec. III): backward tracing from the
-receivers.
+receivers and visited-series discovery.
 
 Expected values come from brute force: every face sequence up to the
 reflection limit is refined by the image method (the exhaustive enumeration of
@@ -62,3 +62,53 @@ def test_backward_records_name_receiver_then_transmitter(oracle_mod):
     assert sorted(map(tuple, hit[:, :4].tolist())) == [(0, 0, 0, 0), (1, 0, 1, 0)]
     keys, _, _ = oracle_mod.candidates(tr, 2, 1, 1, los_always=False, backward=True)
     assert keys.tolist() == [[0, 0, 0, -1], [1, 0, 0, -1]]
+
+
+def test_visited_series_find_every_static_toy_path(oracle_mod):
+    """Visited-series discovery with only 1024 rays finds every valid path of
+    the exhaustive enumeration (37 up to two reflections), where capture
+    spheres of 0.5 m find a third of them."""
+    s = scenes.static_toy()
+    want = _enumerated(oracle_mod, s, 2)
+    assert len(want) == 37
+    dirs = oracle_mod.fibonacci(1024)
+    vis = oracle_mod.frame(s, dirs=dirs, K=2, visited=True)
+    cap = oracle_mod.frame(s, dirs=dirs, K=2)
+    got_v = _valid_set(vis.keys, vis.paths.valid)
+    got_c = _valid_set(cap.keys, cap.paths.valid)
+    assert got_v == want
+    assert got_c < got_v and len(got_c) < 20
+
+
+def test_visited_series_contain_capture_candidates(oracle_mod):
+    """A capturing ray visited its candidate's series: with the same rays,
+    every capture-discovered key is also a visited-series key."""
+    s = scenes.dynamic_urban()
+    dirs = scenes.random_sphere_dirs(2048, seed=41)
+    vis = oracle_mod.frame(s, dirs=dirs, visited=True)
+    cap = oracle_mod.frame(s, dirs=dirs)
+    kv = {tuple(k) for k in vis.keys.tolist()}
+    kc = {tuple(k) for k in cap.keys.tolist()}
+    assert kc <= kv
+    assert _valid_set(cap.keys, cap.paths.valid) <= _valid_set(vis.keys, vis.paths.valid)
+    # each key is a series of the source's rays tried against every receiver
+    assert len(vis.keys) % s.rx.shape[0] == 0
+
+
+def test_backward_visited_series_find_every_corner_path(oracle_mod):
+    """From the receivers, 2000 rays (the paper's shooting-ray count) and
+    visited series find every valid corner path, two-bounce orders included."""
+    sc = _corner([[3.0, 5.0, 1.0], [12.0, 7.0, 2.0]], [[8.0, 2.0, 1.5], [5.0, 11.0, 1.2], [9.0, 9.0, 2.5]])
+    want = _enumerated(oracle_mod, sc, 2)
+    dirs = oracle_mod.fibonacci(2000)
+    bwd = oracle_mod.frame(sc, dirs=dirs, backward=True, visited=True)
+    assert _valid_set(bwd.keys, bwd.paths.valid) == want
+
+
+def test_backward_visited_series_find_every_static_toy_path(oracle_mod):
+    """1024 rays from each receiver: the receivers' visited series, reversed
+    into keys from the transmitter, give every enumerated valid path."""
+    s = scenes.static_toy()
+    want = _enumerated(oracle_mod, s, 2)
+    fr = oracle_mod.frame(s, dirs=oracle_mod.fibonacci(1024), K=2, backward=True, visited=True)
+    assert _valid_set(fr.keys, fr.paths.valid) == want
