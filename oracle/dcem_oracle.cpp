@@ -100,6 +100,9 @@ struct Face {
 
 struct Material {
     double eps_r, sigma, const_gamma;
+    // penetration loss of a transmission through a face of this material, dB
+    // (Table II); +inf: the material is opaque
+    double pen_db = std::numeric_limits<double>::infinity();
 };
 
 struct Scene {
@@ -225,7 +228,13 @@ struct TraceArgs {
     const float* dirs;
     const int64_t* ray_ids;
     int64_t nsel;
-    int32_t K;
+    int32_t K;          // interactions at most (segments 0..K)
+    int32_t max_refl;   // reflections at most
+    // branch b of a ray transmits at the interactions in sets[b] (bit j:
+    // interaction j) and reflects at the others
+    const uint32_t* sets;
+    int32_t n_branch;
+    int64_t n_dirs;     // rays in `dirs` (capture rows name ray b * n_dirs + id)
     double t_min;
     double eps_rel;
     double radius;   // bounding radius of geometry, transmitters and receivers
@@ -236,13 +245,22 @@ struct TraceArgs {
     int32_t* out_flags;
 };
 
-// Trace one ray from one transmitter; per bounce write the closest hit and the
-// uncertainty flags, and append captures.
-void trace_one(const TraceArgs& A, int32_t txi, int64_t sel, std::vector<Capture>& caps) {
+// Trace one branch of one ray from one source; per segment write the closest
+// hit and the uncertainty flags, and append captures.  The branch goes
+// straight on through the faces of the interactions in its set (a penetrable
+// face; it ends at an opaque one) and reflects at the others (it ends where
+// it would reflect a (max_refl + 1)-th time).  Its segments up to its last
+// transmission are those of the branch without that transmission, so it
+// reports captures only after it.
+void trace_one(const TraceArgs& A, int32_t txi, int32_t b, int64_t sel, std::vector<Capture>& caps) {
     const Scene& sc = *A.sc;
     const int64_t rid = A.ray_ids ? A.ray_ids[sel] : sel;
     const int K = A.K;
-    const int64_t slot = ((int64_t)txi * A.nsel + sel) * (K + 1);
+    const uint32_t tset = A.sets[b];
+    int last_t = -1;
+    for (int j = 0; j < 32; ++j)
+        if ((tset >> j) & 1u) last_t = j;
+    const int64_t slot = (((int64_t)txi * A.n_branch + b) * A.nsel + sel) * (K + 1);
     for (int k = 0; k <= K; ++k) {
         A.out_tri[slot + k] = -2;   // not traced
         A.out_face[slot + k] = -1;
@@ -315,7 +333,7 @@ void trace_one(const TraceArgs& A, int32_t txi, int64_t sel, std::vector<Capture
         if (flags & (SEG_TIE | SEG_EDGE)) uncertain = true;
 
         // --- capture: closest approach of the segment [o, o + tb d] to each sphere centre
-        for (int c = 0; c < A.nrx; ++c) {
+        for (int c = 0; c < A.nrx && k > last_t; ++c) {
             V3 ctr{A.rx[3 * c], A.rx[3 * c + 1], A.rx[3 * c + 2]};
             double s = dot(ctr - o, d) / dot(d, d);
             s = std::max(0.0, std::min(s, tb));
@@ -323,7 +341,7 @@ void trace_one(const TraceArgs& A, int32_t txi, int64_t sel, std::vector<Capture
             const double eps = A.eps_rel * (k + 1) * (A.radius + L + s * dlen);
             if (dist > A.r + eps) continue;
             Capture cp;
-            cp.ray = rid;
+            cp.ray = b * A.n_dirs + rid;
             cp.tx = txi;
             cp.rx = c;
             cp.order = k;
@@ -333,6 +351,19 @@ void trace_one(const TraceArgs& A, int32_t txi, int64_t sel, std::vector<Capture
             caps.push_back(std::move(cp));
         }
         if (best < 0 || k == K) break;
+        if ((tset >> k) & 1u) {
+            // --- transmission: straight on through a penetrable face,
+            //     recorded as -2 - face
+            if (!std::isfinite(sc.mats[sc.faces[bface].material].pen_db)) break;
+            seq.push_back(-2 - bface);
+            L += tb * dlen;
+            o = hit;
+            excl = bface;
+            continue;
+        }
+        int refl = 0;
+        for (int j = 0; j < k; ++j) refl += ((tset >> j) & 1u) ? 0 : 1;
+        if (refl == A.max_refl) break;
         // --- specular reflection off the hit face (the segment ends at the hit point)
         seq.push_back(bface);
         L += tb * dlen;
@@ -406,22 +437,33 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
     PathOut out;
     out.amp.assign(nfreq, CV3{});
     out.damp.assign((size_t)nfreq * n_grad, CV3{});
-    // image chain I_0 = T, I_j = mirror of I_{j-1} in the plane of face j
+    // interaction j: face fid[j - 1], a transmission when listed as -2 - face
+    std::vector<int> fid(order);
+    std::vector<bool> trans(order);
+    for (int j = 0; j < order; ++j) {
+        trans[j] = faces[j] <= -2;
+        fid[j] = trans[j] ? -2 - faces[j] : faces[j];
+        if (fid[j] < 0 || fid[j] >= (int)sc.faces.size()) return out;   // not a face: no path
+        // no path goes through an opaque face
+        if (trans[j] && !std::isfinite(sc.mats[sc.faces[fid[j]].material].pen_db)) return out;
+    }
+    // image chain I_0 = T, I_j = mirror of I_{j-1} in the plane of face j (a
+    // transmission goes straight on: I_j = I_{j-1})
     std::vector<V3> img(order + 1);
     img[0] = T;
     for (int j = 1; j <= order; ++j) {
-        const Face& f = sc.faces[faces[j - 1]];
-        img[j] = img[j - 1] - (2.0 * dot(img[j - 1] - f.p, f.n)) * f.n;
+        const Face& f = sc.faces[fid[j - 1]];
+        img[j] = trans[j - 1] ? img[j - 1] : img[j - 1] - (2.0 * dot(img[j - 1] - f.p, f.n)) * f.n;
     }
     const double length = norm(R - img[order]);
     const double eps = eps_rel * (std::max(sc.radius, std::max(norm(T), norm(R))) + length);
-    // reflection points, walking back from the receiver
+    // interaction points, walking back from the receiver
     std::vector<V3> pts(order + 2);
     pts[0] = T;
     pts[order + 1] = R;
     V3 Q = R;
     for (int j = order; j >= 1; --j) {
-        const Face& f = sc.faces[faces[j - 1]];
+        const Face& f = sc.faces[fid[j - 1]];
         V3 D = img[j] - Q;
         double den = dot(D, f.n);
         if (den == 0.0) return out;
@@ -445,8 +487,8 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
     }
     // every sub-segment unoccluded (faces at its endpoints excluded)
     for (int j = 0; j <= order; ++j) {
-        int fa = j >= 1 ? faces[j - 1] : -1;
-        int fb = j + 1 <= order ? faces[j] : -1;
+        int fa = j >= 1 ? fid[j - 1] : -1;
+        int fb = j + 1 <= order ? fid[j] : -1;
         bool marg = false;
         if (occluded(sc, pts[j], pts[j + 1], fa, fb, t_min, eps, marg)) {
             if (marg) out.marginal = true;
@@ -470,7 +512,15 @@ PathOut refine_one(const Scene& sc, V3 T, V3 R, const int32_t* faces, int order,
         // forward-mode derivatives of E, one per material (its eps_c)
         std::vector<CV3> dE(n_grad, CV3{});
         for (int j = 1; j <= order; ++j) {
-            const Face& fc = sc.faces[faces[j - 1]];
+            const Face& fc = sc.faces[fid[j - 1]];
+            if (trans[j - 1]) {
+                // transmission: the field (and its derivatives) times the
+                // amplitude factor of the material's penetration loss
+                const double tf = std::pow(10.0, -sc.mats[fc.material].pen_db / 20.0);
+                E = CV3{tf * E.x, tf * E.y, tf * E.z};
+                for (int m = 0; m < n_grad; ++m) dE[m] = CV3{tf * dE[m].x, tf * dE[m].y, tf * dE[m].z};
+                continue;
+            }
             V3 ki = unit(pts[j] - pts[j - 1]);
             V3 kr = unit(pts[j + 1] - pts[j]);
             V3 n = fc.n;
@@ -637,7 +687,7 @@ void oracle_fibonacci(int64_t n, float* out) {
 }
 
 // Trace rays (all, or the subset ray_ids[0..nsel)) from every transmitter.
-// Per (tx, ray, bounce) outputs, shape [ntx][nsel][K+1]:
+// Per (source, branch, ray, segment) outputs, shape [ntx][n_branch][nsel][K+1]:
 //   tri (-1 miss, -2 not traced), face, t (parametric), len (path length at
 //   the hit), flags (SEG_*).
 // Captures are written to cap_rows [capacity][4 + K] = (ray, tx, rx, order,
@@ -645,19 +695,21 @@ void oracle_fibonacci(int64_t n, float* out) {
 // (tx, ray, bounce, rx).  Returns the number of captures; if it exceeds
 // `capacity`, only the first `capacity` are written.
 int64_t oracle_trace(const void* scene, const float* tx, int32_t ntx, const float* rx, int32_t nrx, double r,
-                     const float* dirs, const int64_t* ray_ids, int64_t nsel, int32_t K, double t_min,
-                     double eps_rel, int32_t nthreads, int32_t* out_tri, int32_t* out_face, double* out_t,
-                     double* out_len, int32_t* out_flags, int32_t* cap_rows, int32_t* cap_flags,
-                     int64_t capacity) {
+                     const float* dirs, int64_t n_dirs, const int64_t* ray_ids, int64_t nsel, int32_t K,
+                     int32_t max_refl, const uint32_t* sets, int32_t n_branch, double t_min, double eps_rel,
+                     int32_t nthreads, int32_t* out_tri, int32_t* out_face, double* out_t, double* out_len,
+                     int32_t* out_flags, int32_t* cap_rows, int32_t* cap_flags, int64_t capacity) {
     const Scene* sc = static_cast<const Scene*>(scene);
     double radius = sc->radius;
     for (int i = 0; i < ntx; ++i) radius = std::max(radius, norm(V3{tx[3 * i], tx[3 * i + 1], tx[3 * i + 2]}));
     for (int i = 0; i < nrx; ++i) radius = std::max(radius, norm(V3{rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]}));
-    TraceArgs A{sc, tx, ntx, rx, nrx, r, dirs, ray_ids, nsel, K, t_min, eps_rel, radius,
-                out_tri, out_face, out_t, out_len, out_flags};
-    const int64_t n = (int64_t)ntx * nsel;
+    TraceArgs A{sc, tx, ntx, rx, nrx, r, dirs, ray_ids, nsel, K, max_refl, sets, n_branch, n_dirs, t_min, eps_rel,
+                radius, out_tri, out_face, out_t, out_len, out_flags};
+    const int64_t n = (int64_t)ntx * n_branch * nsel;
     std::vector<std::vector<Capture>> per(n);
-    parallel_for(n, nthreads, [&](int64_t i, int) { trace_one(A, (int32_t)(i / nsel), i % nsel, per[i]); });
+    parallel_for(n, nthreads, [&](int64_t i, int) {
+        trace_one(A, (int32_t)(i / (n_branch * nsel)), (int32_t)((i / nsel) % n_branch), i % nsel, per[i]);
+    });
     int64_t cnt = 0;
     const int w = 4 + K;
     for (auto& v : per) {
@@ -678,7 +730,7 @@ int64_t oracle_trace(const void* scene, const float* tx, int32_t ntx, const floa
 }
 
 // Refine candidate paths keys [n][3 + K] = (tx, rx, order, faces... padded
-// -1).  Outputs per path: valid, marginal (validity within eps of flipping),
+// -1; a transmission through face f as -2 - f).  Outputs per path: valid, marginal (validity within eps of flipping),
 // length, tau, aod[3], aoa[3], amp [n][nfreq][3][2] (re, im).  pattern:
 // the 16 transmit pattern weights, or null for the isotropic antenna.
 void oracle_refine(const void* scene, const float* tx, const float* rx, const int32_t* keys, int64_t n,
@@ -735,6 +787,12 @@ void oracle_refine_grad(const void* scene, const float* tx, const float* rx, con
                 a[4] = e.z.real(); a[5] = e.z.imag();
             }
     });
+}
+
+// Penetration loss per material in dB (+inf: opaque), n = the scene's materials.
+void oracle_scene_set_penetration(void* scene, const double* loss_db, int32_t n) {
+    Scene& sc = *static_cast<Scene*>(scene);
+    for (int m = 0; m < n && m < (int)sc.mats.size(); ++m) sc.mats[m].pen_db = loss_db[m];
 }
 
 // Transmit pattern gain of a departure direction (for unit pins).

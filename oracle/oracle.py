@@ -38,6 +38,7 @@ Functions and the passages they follow:
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 import subprocess
 from dataclasses import dataclass
@@ -87,8 +88,9 @@ def _load():
         lib.oracle_scene_radius.argtypes = [P, P]
         lib.oracle_fibonacci.argtypes = [I64, P]
         lib.oracle_trace.restype = I64
-        lib.oracle_trace.argtypes = [P, P, I32, P, I32, F64, P, P, I64, I32, F64, F64, I32,
+        lib.oracle_trace.argtypes = [P, P, I32, P, I32, F64, P, I64, P, I64, I32, I32, P, I32, F64, F64, I32,
                                      P, P, P, P, P, P, P, I64]
+        lib.oracle_scene_set_penetration.argtypes = [P, P, I32]
         lib.oracle_refine.argtypes = [P, P, P, P, I64, I32, P, I32, F64, F64, F64, F64, I32,
                                       P, P, P, P, P, P, P, P]
         lib.oracle_fresnel.argtypes = [F64, F64, F64, F64, F64, P]
@@ -127,6 +129,12 @@ class OracleScene:
         self.handle = lib.oracle_scene_new(
             _ptr(V), V.shape[0], _ptr(T), _ptr(TF), T.shape[0], _ptr(FM), _ptr(FO), FM.shape[0],
             _ptr(M), M.shape[0], _ptr(OR), OR.shape[0], _ptr(xfa))
+        # penetration loss per material in dB (+inf opaque; Table II)
+        pen = getattr(scene, "penetration_db", None)
+        if pen is not None:
+            pa = np.ascontiguousarray(pen, dtype=np.float64).reshape(-1)
+            self._keep.append(pa)
+            lib.oracle_scene_set_penetration(self.handle, _ptr(pa), pa.shape[0])
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -149,42 +157,68 @@ def fresnel(eps_r: float, sigma: float, freq: float, cos_theta: float,
 
 @dataclass
 class TraceResult:
-    tri: np.ndarray        # i32 [ntx, nsel, K+1]  (-1 miss, -2 not traced)
-    face: np.ndarray       # i32 [ntx, nsel, K+1]
-    t: np.ndarray          # f64 [ntx, nsel, K+1]
-    length: np.ndarray     # f64 [ntx, nsel, K+1]
-    flags: np.ndarray      # i32 [ntx, nsel, K+1]  SEG_*
+    # per (source, branch * nsel + ray, segment); K = interactions at most
+    tri: np.ndarray        # i32 [ntx, nb * nsel, K+1]  (-1 miss, -2 not traced)
+    face: np.ndarray       # i32 [ntx, nb * nsel, K+1]
+    t: np.ndarray          # f64 [ntx, nb * nsel, K+1]
+    length: np.ndarray     # f64 [ntx, nb * nsel, K+1]
+    flags: np.ndarray      # i32 [ntx, nb * nsel, K+1]  SEG_*
     caps: np.ndarray       # i32 [ncap, 4 + K]     (ray, tx, rx, order, faces...)
     cap_flags: np.ndarray  # i32 [ncap]            CAP_*
+    sets: tuple = (0,)     # transmitting interactions of each branch (bit j: interaction j)
+
+
+def branch_sets(slots: int, max_t: int) -> list:
+    """The branches of a ray that may transmit at up to max_t of its first
+    `slots` interactions: every such set of interaction indices as a bit mask,
+    by size and then lexicographically (branch 0: the ray that only reflects;
+    Sec. III, "Reflected and transmitted rays")."""
+    out = [0]
+    for t in range(1, max_t + 1):
+        for combo in itertools.combinations(range(slots), t):
+            out.append(sum(1 << j for j in combo))
+    return out
 
 
 def trace(osc: OracleScene, tx, rx, radius: float, dirs: np.ndarray, K: int,
           ray_ids: Optional[np.ndarray] = None, t_min: float = T_MIN,
-          eps_rel: float = EPS_TRACE, nthreads: Optional[int] = None) -> TraceResult:
+          eps_rel: float = EPS_TRACE, nthreads: Optional[int] = None,
+          max_transmissions: int = 0) -> TraceResult:
+    """Rays from every source (tx), captured at spheres around the targets
+    (rx).  K: reflections at most; with max_transmissions > 0 every ray is
+    traced once per branch (branch_sets) and paths hold up to K +
+    max_transmissions interactions, a transmission through face f recorded as
+    -2 - f; capture rows name ray b * len(dirs) + id for branch b."""
     lib = _load()
+    max_refl = K
+    K = max_refl + max_transmissions
+    sets = np.array(branch_sets(K, max_transmissions), dtype=np.uint32)
+    nb = sets.shape[0]
     tx = np.ascontiguousarray(tx, dtype=np.float32).reshape(-1, 3)
     rx = np.ascontiguousarray(rx, dtype=np.float32).reshape(-1, 3)
     dirs = np.ascontiguousarray(dirs, dtype=np.float32).reshape(-1, 3)
     ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, dtype=np.int64)
     nsel = dirs.shape[0] if ids is None else ids.shape[0]
     ntx = tx.shape[0]
-    shp = (ntx, nsel, K + 1)
+    shp = (ntx, nb * nsel, K + 1)
     tri = np.empty(shp, np.int32)
     face = np.empty(shp, np.int32)
     t = np.empty(shp, np.float64)
     length = np.empty(shp, np.float64)
     flags = np.empty(shp, np.int32)
-    cap = max(1024, 4 * ntx * nsel)
+    cap = max(1024, 4 * ntx * nb * nsel)
     nthreads = nthreads or default_threads()
     while True:
         rows = np.empty((cap, 4 + K), np.int32)
         cflags = np.empty(cap, np.int32)
         n = lib.oracle_trace(osc.handle, _ptr(tx), ntx, _ptr(rx), rx.shape[0], float(radius),
-                             _ptr(dirs), _ptr(ids), nsel, K, t_min, eps_rel, nthreads,
+                             _ptr(dirs), dirs.shape[0], _ptr(ids), nsel, K, max_refl, _ptr(sets), nb,
+                             t_min, eps_rel, nthreads,
                              _ptr(tri), _ptr(face), _ptr(t), _ptr(length), _ptr(flags),
                              _ptr(rows), _ptr(cflags), cap)
         if n <= cap:
-            return TraceResult(tri, face, t, length, flags, rows[:n].copy(), cflags[:n].copy())
+            return TraceResult(tri, face, t, length, flags, rows[:n].copy(), cflags[:n].copy(),
+                               tuple(int(x) for x in sets))
         cap = int(n)
 
 
@@ -267,15 +301,26 @@ def visited_candidates(tr: TraceResult, ntx: int, nrx: int, K: int, los_always: 
     unc = (tr.flags & (SEG_TIE | SEG_EDGE)) != 0
     K1 = tr.flags.shape[-1]
     fu = np.where(unc.any(axis=-1), unc.argmax(axis=-1), K1)
+    # interactions each traced branch performed: its segments but the last
+    n_int = (tr.tri != -2).sum(axis=-1) - 1
+    nb = len(tr.sets)
+    nsel = tr.face.shape[1] // nb
+    # per row: its branch's transmitting interactions, and the first depth
+    # that branch adds (shorter series are those of the branch without its
+    # last transmission)
+    tset = np.repeat(np.array(tr.sets, dtype=np.int64), nsel)[None, :]
+    d0 = np.array([1 + max([j for j in range(32) if (s >> j) & 1] or [-1]) for s in tr.sets])
+    d0 = np.repeat(d0, nsel)[None, :]
     series = {}
     for d in range(1, K + 1):
-        f = tr.face[:, :, :d]
-        ok = (f >= 0).all(axis=-1)
-        src_i, ray_i = np.nonzero(ok)
-        faces = f[ok]
+        ok = (n_int >= d) & (d0 <= d)
+        src_i, row_i = np.nonzero(ok)
+        faces = tr.face[src_i, row_i, :d].astype(np.int64)
+        tbits = (tset[0, row_i][:, None] >> np.arange(d)[None, :]) & 1
+        faces = np.where(tbits == 1, -2 - faces, faces)
         if backward:
             faces = faces[:, ::-1]
-        sure = fu[src_i, ray_i] >= d
+        sure = fu[src_i, row_i] >= d
         for sc, fs, su in zip(src_i.tolist(), faces.tolist(), sure.tolist()):
             k = (sc, d) + tuple(fs)
             series[k] = series.get(k, False) or su
@@ -466,13 +511,15 @@ class FrameResult:
 def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Optional[int] = None,
           freqs=None, tx_power_w: Optional[float] = None, atten_db_per_km: float = 0.0,
           los_always: bool = True, nthreads: Optional[int] = None, pattern=None,
-          backward: bool = False, visited: bool = False) -> FrameResult:
+          backward: bool = False, visited: bool = False,
+          max_transmissions: Optional[int] = None) -> FrameResult:
     """One frame, from scratch: the oracle keeps nothing between frames.
     backward: rays cast from the receivers and captured at spheres around the
     transmitters (Sec. III, "Backward ray tracing"); the trace result is then
     per receiver.  visited: candidates by visited-series discovery
     (visited_candidates) instead of capture spheres."""
     K = scene.max_reflections if K is None else K
+    T = getattr(scene, "max_transmissions", 0) if max_transmissions is None else max_transmissions
     freqs = scene.freqs_hz if freqs is None else freqs
     tx_power_w = scene.tx_power_w if tx_power_w is None else tx_power_w
     if dirs is None:
@@ -482,26 +529,40 @@ def frame(scene, frame_index: int = 0, dirs: Optional[np.ndarray] = None, K: Opt
     # receivers of this frame (vehicle-mounted receivers move with their vehicles)
     rx = scene.rx_at(frame_index) if hasattr(scene, "rx_at") else scene.rx
     src, tgt = (rx, scene.tx) if backward else (scene.tx, rx)
-    tr = trace(osc, src, tgt, scene.rx_radius, dirs, K, nthreads=nthreads)
+    tr = trace(osc, src, tgt, scene.rx_radius, dirs, K, nthreads=nthreads, max_transmissions=T)
     ntx, nrx = scene.tx.shape[0], rx.shape[0]
+    slots = K + T   # interactions per path at most: the key's face entries
     if visited:
-        keys, certain, possible = visited_candidates(tr, ntx, nrx, K, los_always, backward)
+        keys, certain, possible = visited_candidates(tr, ntx, nrx, slots, los_always, backward)
     else:
-        keys, certain, possible = candidates(tr, ntx, nrx, K, los_always, backward)
-    paths = refine(osc, scene.tx, rx, keys, K, freqs, tx_power_w, atten_db_per_km,
+        keys, certain, possible = candidates(tr, ntx, nrx, slots, los_always, backward)
+    paths = refine(osc, scene.tx, rx, keys, slots, freqs, tx_power_w, atten_db_per_km,
                    nthreads=nthreads, pattern=pattern)
     p_coh, p_inc = received_power(paths, ntx, nrx, len(freqs))
     return FrameResult(tr, keys, certain, possible, paths, p_coh, p_inc)
 
 
-def enumerate_keys(n_faces: int, ntx: int, nrx: int, K: int) -> np.ndarray:
-    """Every face sequence of length 0..K without immediate repeats, for every (tx, rx)."""
-    seqs = [[]]
+def enumerate_keys(n_faces: int, ntx: int, nrx: int, K: int, T: int = 0) -> np.ndarray:
+    """Every interaction sequence with at most K reflections and T
+    transmissions (a transmission through face f written -2 - f) and no face
+    met twice in a row, for every (tx, rx); keys [n][3 + K + T]."""
+    width = K + T
+    seqs = [([], 0, 0)]   # (entries, reflections, transmissions)
     out = []
-    for order in range(K + 1):
-        for s in seqs:
+    for order in range(width + 1):
+        for s, _, _ in seqs:
             for t in range(ntx):
                 for r in range(nrx):
-                    out.append([t, r, order] + s + [-1] * (K - order))
-        seqs = [s + [f] for s in seqs for f in range(n_faces) if not s or s[-1] != f]
-    return np.array(out, dtype=np.int32).reshape(-1, 3 + K)
+                    out.append([t, r, order] + s + [-1] * (width - order))
+        nxt = []
+        for s, nr, nt in seqs:
+            last = None if not s else (s[-1] if s[-1] >= 0 else -2 - s[-1])
+            for f in range(n_faces):
+                if f == last:
+                    continue
+                if nr < K:
+                    nxt.append((s + [f], nr + 1, nt))
+                if nt < T:
+                    nxt.append((s + [-2 - f], nr, nt + 1))
+        seqs = nxt
+    return np.array(out, dtype=np.int32).reshape(-1, 3 + width)

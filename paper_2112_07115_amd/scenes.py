@@ -24,6 +24,13 @@ import numpy as np
 
 # material rows: (eps_r, sigma [S/m], const_gamma); const_gamma = NaN selects Fresnel
 CONCRETE = (5.31, 0.48, float("nan"))
+# Table II's materials as constant-magnitude reflectors, with their
+# penetration losses (dB; inf: not penetrable)
+WALL_OUTDOOR = (5.31, 0.48, 0.8)
+WALL_INDOOR = (5.31, 0.48, 0.7)
+GLASS_INDOOR = (6.27, 0.0, 0.74)
+PEN_WALL_INDOOR_DB = 20.0
+PEN_GLASS_INDOOR_DB = 5.0
 GROUND = (15.0, 0.035, float("nan"))
 METAL = (1.0, 1.0e7, float("nan"))
 
@@ -51,6 +58,10 @@ class Scene:
     transforms_fn: Optional[Callable[[int], np.ndarray]] = None
     # frame -> f32 [Nrx, 3] receiver positions (moving receivers); None: rx at every frame
     rx_fn: Optional[Callable[[int], np.ndarray]] = None
+    # penetration loss per material in dB (+inf: opaque; Table II), and the
+    # transmissions a path may have (0: no penetration, the outdoor setting)
+    penetration_db: Optional[np.ndarray] = None
+    max_transmissions: int = 0
 
     @property
     def n_tris(self) -> int:
@@ -417,6 +428,89 @@ def parallel_walls(tx, rx, x0: float = -10.0, x1: float = 10.0, half: float = 50
         mb.add_polygon_face([[x, -half, -half], [x, half, -half], [x, half, half], [x, -half, half]],
                             [[0, 1, 2], [0, 2, 3]], material=0)
     return mb.finish("parallel_walls", [material], tx, rx, **kw)
+
+
+def slabs(tx, rx, walls, materials, penetration_db, half: float = 60.0, max_transmissions: int = 2,
+          **kw) -> Scene:
+    """Parallel planar walls x = x_i (one face each, |y|, |z| <= half) of the
+    given materials, for closed-form transmission checks."""
+    mb = _MeshBuilder()
+    for x, m in walls:
+        mb.add_polygon_face([[x, -half, -half], [x, half, -half], [x, half, half], [x, -half, half]],
+                            [[0, 1, 2], [0, 2, 3]], m)
+    return mb.finish("slabs", materials, tx, rx, penetration_db=np.asarray(penetration_db, np.float64),
+                     max_transmissions=max_transmissions, **kw)
+
+
+def _wall_cells(mb, axis: int, pos: float, span, zs, kind, mats) -> None:
+    """A vertical wall in the plane x = pos (axis 0) or y = pos (axis 1), cut
+    into cells along `span` (breakpoints along the other horizontal axis) and
+    `zs` (heights); kind(i, j) gives cell (i, j)'s material key, None for an
+    opening.  Cells of one material form one face."""
+    groups = {}
+    for i in range(len(span) - 1):
+        for j in range(len(zs) - 1):
+            k = kind(i, j)
+            if k is None:
+                continue
+            groups.setdefault(k, []).append((span[i], span[i + 1], zs[j], zs[j + 1]))
+    for k, cells in groups.items():
+        pts, tris = [], []
+        for (a0, a1, z0, z1) in cells:
+            q = [(a0, z0), (a1, z0), (a1, z1), (a0, z1)]
+            base = len(pts)
+            for (a, z) in q:
+                pts.append([pos, a, z] if axis == 0 else [a, pos, z])
+            tris += [[base, base + 1, base + 2], [base, base + 2, base + 3]]
+        mb.add_polygon_face(pts, tris, mats[k])
+
+
+def indoor_office(n_rays: int = 1 << 18, max_reflections: int = 2, max_transmissions: int = 2,
+                  rx_step: float = 1.0) -> Scene:
+    """An office floor (Sec. III's indoor setting: walls, doors and windows of
+    Table II's materials, a 2 m high transmitter, 30 GHz, 0.5 W).
+
+    24 m x 14 m x 3 m: concrete floor and ceiling and outdoor walls (opaque), a
+    corridor between y = 6 and y = 8 whose walls (indoor walls, 20 dB) have a
+    door opening and a glass window (5 dB) per room, and partitions at x = 6,
+    12 and 18 with a glass window each.  Receivers on a rx_step grid at
+    1.5 m; the transmitter in the corridor.  Constant-magnitude reflection
+    coefficients of Table II (0.8, 0.7, 0.74) for the walls and the glass."""
+    mb = _MeshBuilder()
+    mats = {"concrete": 0, "outdoor": 1, "wall": 2, "glass": 3}
+    W, D, H = 24.0, 14.0, 3.0
+    mb.add_polygon_face([[0, 0, 0], [W, 0, 0], [W, D, 0], [0, D, 0]], [[0, 1, 2], [0, 2, 3]], mats["concrete"])
+    mb.add_polygon_face([[0, 0, H], [W, 0, H], [W, D, H], [0, D, H]], [[0, 1, 2], [0, 2, 3]], mats["concrete"])
+    for axis, pos, length in ((0, 0.0, D), (0, W, D), (1, 0.0, W), (1, D, W)):
+        _wall_cells(mb, axis, pos, [0.0, length], [0.0, H], lambda i, j: "outdoor", mats)
+    # corridor walls: per 6 m room a door (x in [2.5, 3.5], below 2.1 m) and
+    # a window (x in [4.0, 5.5], 1.0 to 2.2 m)
+    xs = sorted({0.0, W} | {r * 6.0 + o for r in range(4) for o in (2.5, 3.5, 4.0, 5.5)})
+    zs = [0.0, 1.0, 2.1, 2.2, H]
+
+    def corridor_kind(i, j):
+        x0 = xs[i] % 6.0
+        if abs(x0 - 2.5) < 1e-9 and zs[j] < 2.1:
+            return None
+        if abs(x0 - 4.0) < 1e-9 and 1.0 <= zs[j] < 2.2:
+            return "glass"
+        return "wall"
+    for y in (6.0, 8.0):
+        _wall_cells(mb, 1, y, xs, zs, corridor_kind, mats)
+    # partitions with a window (y in [2, 4] / [10, 12], 1.0 to 2.2 m)
+    for x in (6.0, 12.0, 18.0):
+        for (y0, y1) in ((0.0, 6.0), (8.0, 14.0)):
+            ys = [y0, y0 + 2.0, y0 + 4.0, y1]
+            _wall_cells(mb, 0, x, ys, zs, lambda i, j: "glass" if i == 1 and 1.0 <= zs[j] < 2.2 else "wall", mats)
+    gx = np.arange(rx_step / 2, W, rx_step)
+    gy = np.arange(rx_step / 2, D, rx_step)
+    rx = np.array([[x, y, 1.5] for y in gy for x in gx], np.float32)
+    tx = np.array([[3.0, 7.0, 2.0]], np.float32)
+    inf = float("inf")
+    return mb.finish("indoor_office", [CONCRETE, WALL_OUTDOOR, WALL_INDOOR, GLASS_INDOOR], tx, rx,
+                     rx_radius=0.25, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=[30e9],
+                     tx_power_w=0.5, penetration_db=np.array([inf, inf, PEN_WALL_INDOOR_DB, PEN_GLASS_INDOOR_DB]),
+                     max_transmissions=max_transmissions)
 
 
 def box_field(n_static: int, n_moving: int, half: float = 200.0, seed: int = 5, n_frames: int = 4,

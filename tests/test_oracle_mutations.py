@@ -25,7 +25,18 @@ MUTATIONS = {
     "phase_sign": ("std::polar(mag, -k0 * length)", "std::polar(mag, k0 * length)"),
     "basis_order": ("V3 p_out = cross(sv, kr);", "V3 p_out = cross(kr, sv);"),
     "reflect_factor": ("d = d - (2.0 * dot(d, n)) * n;", "d = d - dot(d, n) * n;"),
-    "image_factor": ("img[j] = img[j - 1] - (2.0 *", "img[j] = img[j - 1] - (1.0 *"),
+    "image_factor": ("img[j - 1] - (2.0 * dot(img[j - 1] - f.p, f.n))", "img[j - 1] - (1.0 * dot(img[j - 1] - f.p, f.n))"),
+    # transmissions (caught by the variant pins)
+    "transmission_power_factor": ("-sc.mats[fc.material].pen_db / 20.0", "-sc.mats[fc.material].pen_db / 10.0",
+                                  "test_oracle_variants.py"),
+    "transmission_mirrors": ("img[j] = trans[j - 1] ? img[j - 1] :", "img[j] = false ? img[j - 1] :",
+                             "test_oracle_variants.py"),
+    "reflection_limit_with_branches": ("if (refl == A.max_refl) break;", "if (refl > A.max_refl) break;",
+                                       "test_oracle_variants.py"),
+    "opaque_face_transmits": ("if (!std::isfinite(sc.mats[sc.faces[bface].material].pen_db)) break;", "",
+                              "test_oracle_variants.py"),
+    "refine_accepts_opaque": ("if (trans[j] && !std::isfinite(sc.mats[sc.faces[fid[j]].material].pen_db)) return out;",
+                              "", "test_oracle_variants.py"),
     "tie_break": ("if (t < tb) { tb = t;", "if (t <= tb) { tb = t;"),
     "capture_clamp": ("s = std::max(0.0, std::min(s, tb));", "s = std::max(0.0, s);"),
     "theta_hat_sign": ("V3{u.z * u.x / rho, u.z * u.y / rho, -rho}",
@@ -72,7 +83,11 @@ PY_MUTATIONS = {
     "backward_pair_not_swapped": ("out[:, 0], out[:, 1] = rows[:, 1], rows[:, 0]",
                                   "out[:, 0], out[:, 1] = rows[:, 0], rows[:, 1]", "test_oracle_variants.py"),
     # visited series that skip a ray's first hit, or keep the receiver's face order
-    "visited_series_offset": ("f = tr.face[:, :, :d]", "f = tr.face[:, :, 1:d + 1]", "test_oracle_variants.py"),
+    "visited_series_offset": ("faces = tr.face[src_i, row_i, :d]", "faces = tr.face[src_i, row_i, 1:d + 1]",
+                              "test_oracle_variants.py"),
+    # visited series of a branch that repeat its parent's, or skip its transmission flags
+    "visited_branch_flags": ("faces = np.where(tbits == 1, -2 - faces, faces)", "faces = faces + 0 * tbits",
+                             "test_oracle_variants.py"),
     "visited_backward_not_reversed": ("faces = faces[:, ::-1]", "faces = faces[:, ::1]", "test_oracle_variants.py"),
 }
 
