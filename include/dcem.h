@@ -74,7 +74,8 @@ typedef int32_t dcem_status;
 #define DCEM_DISCOVER_CAPTURE 0  /* sequences of rays that pass through a capture sphere */
 #define DCEM_DISCOVER_VISITED 1  /* every visited series, tried against every target */
 
-#define DCEM_MAX_REFLECTIONS 10  /* paper, Sec. III: at most 10 reflections */
+#define DCEM_MAX_REFLECTIONS 10  /* paper, Sec. III: at most 10 reflections and transmissions */
+#define DCEM_MAX_TRANSMISSIONS 2 /* transmissions per path (dcem_trace_params.max_transmissions) */
 #define DCEM_PATTERN_TAPS 16     /* weights of the transmit pattern (dcem_set_tx_pattern) */
 
 /* bits of the device error word (reported as DCEM_E_CAPACITY / DCEM_E_INVALID_ARG) */
@@ -156,6 +157,22 @@ typedef struct dcem_scene_desc {
  *  (DCEM_E_UNSUPPORTED).  los_always keeps its meaning (the empty series).
  *  Candidate discovery of this mode reads counts back to the host (it is not
  *  asynchronous).  Coherent frames reuse rays traced in the same mode.
+ *  max_transmissions: 0..DCEM_MAX_TRANSMISSIONS, with max_reflections +
+ *  max_transmissions <= DCEM_MAX_REFLECTIONS (Sec. III, "Reflected and
+ *  transmitted rays": at most 10 interactions).  A ray that meets a face whose
+ *  material has a finite penetration loss (dcem_set_penetration_loss) splits
+ *  into the reflected ray and the ray that goes straight on through the face;
+ *  each ray is traced once per branch, a branch being the set of its first
+ *  max_reflections + max_transmissions interactions that transmit (at most
+ *  max_transmissions of them; n_branch = sum over t <= max_transmissions of
+ *  C(max_reflections + max_transmissions, t), branch 0 only reflects; a
+ *  branch ends where it would transmit through an opaque face or reflect a
+ *  (max_reflections + 1)-th time).  Paths are then sequences of interactions,
+ *  each a reflection or a transmission, at most max_reflections of the first
+ *  and max_transmissions of the second; a transmission scales the field by
+ *  the face's penetration loss and leaves its direction and polarisation
+ *  unchanged.  0 (the paper's outdoor setting: no penetration) traces one
+ *  branch.  Work items per frame: sources x n_branch x n_rays (< 2^31 - 1).
  *  trace_from_rx: 1 casts the n_rays rays from every receiver and captures
  *  them at spheres of radius rx_radius around the transmitters (backward
  *  tracing, Sec. III: the ray count no longer grows with the number of
@@ -188,11 +205,13 @@ typedef struct dcem_trace_params {
   int32_t mem_kind;
   int32_t trace_from_rx;
   int32_t discovery;
+  int32_t max_transmissions;
 } dcem_trace_params;
 
 /* Counters and timings of the last dcem_refit_bvh + dcem_trace_frame. */
 typedef struct dcem_frame_stats {
-  int64_t rays_total;        /* n_tx * n_rays (n_rx * n_rays when tracing from the receivers) */
+  int64_t rays_total;        /* work items: sources (n_tx, or n_rx when tracing from the receivers)
+                                x transmission branches x n_rays */
   int64_t rays_traced;       /* rays actually traced this frame */
   int64_t rays_reused;       /* rays whose cached result was reused */
   int64_t segments;          /* closest-hit queries executed */
@@ -322,6 +341,19 @@ dcem_status dcem_set_tx_pattern(dcem_ctx* ctx, const double* weights, int32_t n_
  * or an invalid row. */
 dcem_status dcem_set_materials(dcem_ctx* ctx, const double* materials, int32_t n_materials);
 
+/* Penetration loss of each material in dB (Table II: indoor wall 20 dB,
+ * glass 5 dB), the field factor of a transmission through a face of that
+ * material being 10^(-loss/20) at any incidence; +inf (the default after
+ * every scene upload) makes the material opaque.  Paths transmit only when a
+ * frame's max_transmissions > 0.  loss_db: host, n_materials values >= 0 or
+ * +inf, copied; applies to the frames traced after the call (the ray cache
+ * is dropped).  The Table II thickness does not enter: a plane-parallel slab
+ * leaves a ray's direction unchanged, and the lateral offset it causes (at
+ * most the thickness times tan theta) is neglected with it.
+ * Errors: DCEM_E_STATE without a scene; DCEM_E_INVALID_ARG for another count
+ * or a negative or NaN loss. */
+dcem_status dcem_set_penetration_loss(dcem_ctx* ctx, const double* loss_db, int32_t n_materials);
+
 /* Derivatives of the last frame's coherent received power p_coh (see
  * dcem_received_power) along its fixed set of valid paths: the path geometry
  * is held, and the field of each path (Sec. III, Eq. (3) with the Fresnel
@@ -370,29 +402,35 @@ dcem_status dcem_power_gradients_noalloc(dcem_ctx* ctx, double* d_eps_r, double*
                                          double* d_pattern);
 
 /* Paths of the last frame in key order (tx, rx, order, faces), host memory.
- * keys [cap][3 + K] int32 (faces padded with -1, K = max_reflections),
+ * keys [cap][3 + K] int32, K = max_reflections + max_transmissions: order =
+ * the number of interactions, then one entry per interaction from the
+ * transmitter: the face index f for a reflection, -2 - f for a transmission
+ * through face f, -1 past the order.
  * valid [cap], length [cap] (m), tau [cap] (s), aod/aoa [cap][3] unit vectors
  * (departure direction at the transmitter; direction from the receiver
  * towards the last path point), amp [cap][n_freqs][3][2] complex field vector
  * (re, im) whose squared norm is the path's received power, first_ray [cap]
- * (lowest ray index tx * n_rays + i that captured it, -1 for a direct path
- * added by los_always; in a frame traced from the receivers, rx * n_rays + i
- * of the lowest receiver ray).  Any output pointer may be NULL.  n_out receives the
- * number of paths; at most cap are written. */
+ * (lowest ray index (source * n_branch + branch) * n_rays + i that found it,
+ * the source being the transmitter, or the receiver when tracing backward; -1
+ * for a direct path added by los_always).  Any output pointer may be NULL.
+ * n_out receives the number of paths; at most cap are written. */
 dcem_status dcem_get_paths(dcem_ctx* ctx, int64_t cap, int32_t* keys, uint8_t* valid, double* length,
                            double* tau, double* aod, double* aoa, double* amp, int32_t* first_ray,
                            int64_t* n_out);
 
-/* Per (source, ray, bounce) log of the last frame ([n_src][n_rays][K+1],
- * host; the sources are the transmitters, or the receivers when tracing
- * backward):
+/* Per (source, ray, segment) log of the last frame ([n_src][n_branch *
+ * n_rays][K+1], host, K = max_reflections + max_transmissions, rays of branch
+ * b at b * n_rays + i; the sources are the transmitters, or the receivers
+ * when tracing backward):
  * tri = hit triangle (-1 miss, -2 not reached), t = hit distance along the
  * (unnormalised) direction, length = cumulative path length at the hit.
  * Requires record_trace_log = 1.  Any pointer may be NULL. */
 dcem_status dcem_get_trace_log(dcem_ctx* ctx, int32_t* tri, float* t, float* length);
 
 /* Raw capture records of the last frame (host): rows [cap][4 + K] =
- * (ray, source, target, order, faces... padded -1) in the trace's direction:
+ * (ray, source, target, order, faces... padded -1) in the trace's direction
+ * (ray = (source * n_branch + branch) * n_rays + i; a transmission through
+ * face f is -2 - f):
  * (ray, tx, rx, order, faces from the transmitter), or when tracing from the
  * receivers (ray, rx, tx, order, faces from the receiver); sorted by
  * (source, target, order, faces), then ray. */

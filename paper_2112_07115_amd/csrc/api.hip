@@ -587,6 +587,10 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   c->nf = nf;
   c->nm = s->n_materials;
   c->mat_pending = false;
+  // every material opaque until dcem_set_penetration_loss says otherwise
+  c->pen_next.assign((size_t)s->n_materials, std::numeric_limits<double>::infinity());
+  c->pen_pending = true;
+  c->h_face_material = FM;
   c->no = s->n_objects;
   c->pad = (float)(4e-6 * (2.0 * R + 1.0));
   c->h_face_object = FO;
@@ -707,6 +711,29 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
 
 namespace {
 
+// The branches of a ray when up to max_t of its first `slots` interactions
+// may transmit: every set of at most max_t interaction indices, as a bit mask
+// (bit j: interaction j transmits), by size, then lexicographically (the
+// empty set first: the ray that only reflects).
+std::vector<uint32_t> branch_sets(int slots, int max_t) {
+  std::vector<uint32_t> out{0u};
+  for (int t = 1; t <= max_t; ++t) {
+    std::vector<int> idx(t);
+    for (int j = 0; j < t; ++j) idx[j] = j;
+    while (true) {
+      uint32_t m = 0;
+      for (int j : idx) m |= 1u << j;
+      out.push_back(m);
+      int j = t - 1;
+      while (j >= 0 && idx[j] == slots - t + j) --j;
+      if (j < 0) break;
+      ++idx[j];
+      for (int q = j + 1; q < t; ++q) idx[q] = idx[q - 1] + 1;
+    }
+  }
+  return out;
+}
+
 // What the device part of a frame does, decided by its host part.
 struct FramePlan {
   bool coherent = false;    // reuse the cached rays, re-trace the listed ones
@@ -747,18 +774,25 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   if (p->discovery != DCEM_DISCOVER_CAPTURE && p->discovery != DCEM_DISCOVER_VISITED)
     return fail(c, DCEM_E_INVALID_ARG, "bad discovery mode");
   const bool visited = p->discovery == DCEM_DISCOVER_VISITED;
+  if (p->max_transmissions < 0 || p->max_transmissions > DCEM_MAX_TRANSMISSIONS)
+    return fail(c, DCEM_E_INVALID_ARG, "max_transmissions must be in [0, %d]", DCEM_MAX_TRANSMISSIONS);
+  if (p->max_reflections + p->max_transmissions > DCEM_MAX_REFLECTIONS)
+    return fail(c, DCEM_E_INVALID_ARG, "max_reflections + max_transmissions must be <= %d", DCEM_MAX_REFLECTIONS);
+  const int32_t slots = p->max_reflections + p->max_transmissions;   // interactions per path at most
+  const std::vector<uint32_t> bsets = branch_sets(slots, p->max_transmissions);
+  const int32_t n_branch = (int32_t)bsets.size();
   const bool backward = p->trace_from_rx == 1;
   const int32_t n_src = backward ? p->n_rx : p->n_tx, n_tgt = backward ? p->n_tx : p->n_rx;
-  const int64_t n_work = (int64_t)n_src * p->n_rays;
+  const int64_t n_work = (int64_t)n_src * n_branch * p->n_rays;
   if (n_work >= (int64_t(1) << 31) - 1)
-    return fail(c, DCEM_E_UNSUPPORTED, "rays per frame (sources x n_rays) must be < 2^31 - 1");
+    return fail(c, DCEM_E_UNSUPPORTED, "work items per frame (sources x branches x n_rays) must be < 2^31 - 1");
   if ((int64_t)p->n_tx * p->n_rx >= (int64_t(1) << 27)) return fail(c, DCEM_E_UNSUPPORTED, "too many tx x rx pairs");
   {
     int bt = 0, br = 0, bf = 0;
     while ((int64_t(1) << bt) < p->n_tx) ++bt;
     while ((int64_t(1) << br) < p->n_rx) ++br;
     while ((int64_t(1) << bf) < c->nf) ++bf;
-    if (bt + br + 4 + p->max_reflections * std::max(bf, 1) > 256)
+    if (bt + br + 4 + slots * (std::max(bf, 1) + (p->max_transmissions > 0 ? 1 : 0)) > 256)
       return fail(c, DCEM_E_UNSUPPORTED, "candidate key exceeds 256 bits");
   }
   HIP_TRY(hipSetDevice(c->device), "set device");
@@ -793,7 +827,8 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   // the cached segments)
   const bool same_geom = cfg.n_src == n_src && cfg.n_tgt == n_tgt && cfg.backward == backward &&
                          cfg.visited == visited &&
-                         cfg.K == p->max_reflections && cfg.n_rays == p->n_rays && cfg.rx_radius == p->rx_radius &&
+                         cfg.K == p->max_reflections && cfg.T == p->max_transmissions && cfg.n_rays == p->n_rays &&
+                         cfg.rx_radius == p->rx_radius && !c->pen_pending &&
                          cfg.src == srch && cfg.dirs_fib == fib &&
                          (fib || (p->mem_kind == DCEM_MEM_HOST && cfg.dirs_host == dirh));
   const bool rx_moved = cfg.tgt != tgth;
@@ -808,6 +843,7 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   cfg.backward = backward;
   cfg.visited = visited;
   cfg.K = p->max_reflections;
+  cfg.T = p->max_transmissions;
   cfg.n_rays = p->n_rays;
   cfg.rx_radius = p->rx_radius;
   cfg.src = srch;
@@ -822,7 +858,10 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   c->backward = backward;
   c->visited = visited;
   c->n_rays = p->n_rays;
-  c->K = p->max_reflections;
+  c->K = slots;
+  c->max_refl = p->max_reflections;
+  c->max_trans = p->max_transmissions;
+  c->n_branch = n_branch;
   c->n_freqs = p->n_freqs;
   c->sqrt_pt = std::sqrt(p->tx_power_w);
   c->atten_db_per_km = p->atten_db_per_km;
@@ -859,7 +898,18 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
     }
     HIP_TRY(build_ray_order(c), "ray order");
   }
-  const size_t nw = (size_t)std::max<int64_t>(n_work, 1), K1 = (size_t)p->max_reflections + 1;
+  if (need_dirs) HIP_TRY(upload(c->branch_set, bsets, c->stream), "upload branches");
+  if (c->pen_pending || c->face_pen.p == nullptr) {
+    // per-face flags and per-material factors of the penetration losses
+    std::vector<uint8_t> fp((size_t)std::max(c->nf, 1), 0);
+    std::vector<double> mp((size_t)std::max(c->nm, 1), 0.0);
+    for (int m = 0; m < c->nm; ++m) mp[m] = std::isfinite(c->pen_next[m]) ? std::pow(10.0, -c->pen_next[m] / 20.0) : 0.0;
+    for (int f = 0; f < c->nf; ++f) fp[f] = std::isfinite(c->pen_next[c->h_face_material[f]]) ? 1 : 0;
+    HIP_TRY(upload(c->face_pen, fp, c->stream), "upload penetration flags");
+    HIP_TRY(upload(c->mat_pen, mp, c->stream), "upload penetration losses");
+    c->pen_pending = false;
+  }
+  const size_t nw = (size_t)std::max<int64_t>(n_work, 1), K1 = (size_t)slots + 1;
   HIP_TRY(ensure(c->face_log, sizeof(int32_t) * K1 * nw), "alloc face log");
   HIP_TRY(ensure(c->ray_state, nw), "alloc ray state");
   if (keep_cache) {
@@ -1044,6 +1094,19 @@ dcem_status dcem_set_materials(dcem_ctx* c, const double* materials, int32_t n_m
   return DCEM_OK;
 }
 
+dcem_status dcem_set_penetration_loss(dcem_ctx* c, const double* loss_db, int32_t n_materials) {
+  if (!c) return DCEM_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->has_scene) return fail(c, DCEM_E_STATE, "no scene uploaded");
+  if (n_materials != c->nm) return fail(c, DCEM_E_INVALID_ARG, "the scene has %d materials", c->nm);
+  if (n_materials > 0 && !loss_db) return fail(c, DCEM_E_INVALID_ARG, "null losses");
+  for (int m = 0; m < n_materials; ++m)
+    if (!(loss_db[m] >= 0.0)) return fail(c, DCEM_E_INVALID_ARG, "material %d: loss must be >= 0 dB or +inf", m);
+  c->pen_next.assign(loss_db, loss_db + n_materials);
+  c->pen_pending = true;
+  return DCEM_OK;
+}
+
 dcem_status dcem_power_gradients(dcem_ctx* c, double* d_eps_r, double* d_sigma, double* d_tx_power,
                                  double* d_pattern) {
   if (!c) return DCEM_E_INVALID_ARG;
@@ -1194,7 +1257,11 @@ dcem_status dcem_get_paths(dcem_ctx* c, int64_t cap, int32_t* keys, uint8_t* val
       row[0] = pair[u] / c->n_rx;
       row[1] = pair[u] % c->n_rx;
       row[2] = order[u];
-      for (int j = 0; j < K; ++j) row[3 + j] = j < order[u] ? faces[(size_t)u * K + j] : -1;
+      for (int j = 0; j < K; ++j) {
+        const int32_t fe = faces[(size_t)u * K + j];
+        // a transmission through face f is reported as -2 - f
+        row[3 + j] = j >= order[u] ? -1 : ((fe & kTransmit) ? -2 - (fe & kFaceMask) : fe);
+      }
     }
   }
   return DCEM_OK;
@@ -1209,7 +1276,7 @@ dcem_status dcem_get_trace_log(dcem_ctx* c, int32_t* tri, float* t, float* lengt
   HIP_TRY(flush_refit(c), "refit");
   dcem_status st = check_device_error(c);
   if (st != DCEM_OK) return st;
-  const size_t n = (size_t)c->n_src * c->n_rays * (c->K + 1);
+  const size_t n = (size_t)c->n_src * c->n_branch * c->n_rays * (c->K + 1);
   if (tri) HIP_TRY(hipMemcpy(tri, c->log_tri.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
   if (t) HIP_TRY(hipMemcpy(t, c->log_t.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
   if (length) HIP_TRY(hipMemcpy(length, c->log_len.p, 4 * n, hipMemcpyDeviceToHost), "copy log");
@@ -1231,15 +1298,18 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
   std::vector<Capture> cp(nc);
   const int list = c->frame_begun ? c->cur_caps ^ 1 : c->cur_caps;   // the last traced frame's
   HIP_TRY(hipMemcpy(cp.data(), c->caps[list].p, sizeof(Capture) * nc, hipMemcpyDeviceToHost), "copy caps");
-  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_branch * c->n_rays;
   // records and the face log are indexed by traversal position; rows name the ray
   std::vector<uint32_t> order((size_t)std::max<int64_t>(c->n_rays, 1));
   if (c->n_rays > 0)
     HIP_TRY(hipMemcpy(order.data(), c->ray_order.p, 4 * (size_t)c->n_rays, hipMemcpyDeviceToHost), "copy order");
+  // the ray column: (source * n_branch + branch) * n_rays + ray (branch 0 only reflects)
   auto ray_of = [&](uint32_t p) -> int32_t {
-    const int64_t tx = p / c->n_rays;
-    return (int32_t)(tx * c->n_rays + order[(size_t)(p - tx * c->n_rays)]);
+    const int64_t vs = p / c->n_rays;
+    return (int32_t)(vs * c->n_rays + order[(size_t)(p - vs * c->n_rays)]);
   };
+  std::vector<uint32_t> bsets((size_t)c->n_branch);
+  HIP_TRY(hipMemcpy(bsets.data(), c->branch_set.p, 4 * bsets.size(), hipMemcpyDeviceToHost), "copy branches");
   const int K = c->K;
   std::vector<int32_t> flog((size_t)(K + 1) * std::max<int64_t>(n_work, 1));
   if (n_work > 0)
@@ -1253,7 +1323,11 @@ dcem_status dcem_get_captures(dcem_ctx* c, int64_t cap, int32_t* rows, int64_t* 
     r[1] = (int32_t)(pair / c->n_tgt);
     r[2] = (int32_t)(pair % c->n_tgt);
     r[3] = (int32_t)order;
-    for (uint32_t j = 0; j < order; ++j) r[4 + j] = flog[(size_t)j * n_work + x.work];
+    const uint32_t tset = x.work == kNoRay ? 0u : bsets[(x.work / c->n_rays) % c->n_branch];
+    for (uint32_t j = 0; j < order; ++j) {
+      const int32_t f = flog[(size_t)j * n_work + x.work];
+      r[4 + j] = ((tset >> j) & 1u) ? -2 - f : f;
+    }
     out.push_back(std::move(r));
   }
   std::sort(out.begin(), out.end(), [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {

@@ -20,6 +20,8 @@ constexpr int kStackSize = kStackLds + kStackSpill;
 constexpr int kTopNodes = 21;            // 4-wide nodes of the top three levels, kept in LDS
 constexpr int kTraceBlock = 128;         // threads per trace block
 constexpr uint32_t kNoRay = 0xffffffffu;
+constexpr int32_t kTransmit = 1 << 30;   // decoded face entry: the interaction transmits through the face
+constexpr int32_t kFaceMask = kTransmit - 1;
 
 // BVH2 internal node, 64 bytes: both child boxes plus links.
 //   b0 = (lo0.x, lo0.y, lo0.z, hi0.x)   b1 = (hi0.y, hi0.z, lo1.x, lo1.y)
@@ -98,7 +100,7 @@ struct TxPattern {
 // spheres around the targets (forward: transmitters and receivers; a backward
 // frame swaps them).
 struct TraceConfig {
-  int32_t n_src = 0, n_tgt = 0, K = -1;
+  int32_t n_src = 0, n_tgt = 0, K = -1, T = 0;
   bool backward = false;
   bool visited = false;   // candidates by visited-series discovery
   int64_t n_rays = 0;
@@ -164,7 +166,13 @@ struct dcem_ctx {
   // array (set by each build), so the refinement's face test reads the
   // vertices the tree holds (the refit's, not a later transform's)
   dcem::DevBuf tri_slot, face_slots;
-  std::vector<int32_t> h_face_object;
+  std::vector<int32_t> h_face_object, h_face_material;
+  // penetration loss per material in dB (+inf: opaque), for the next traced
+  // frame (dcem_set_penetration_loss); uploaded as per-face flags and
+  // per-material amplitude factors
+  std::vector<double> pen_next;
+  bool pen_pending = false;
+  dcem::DevBuf face_pen, mat_pen;   // uint8 [n_faces] 1 = penetrable; double [n_materials] 10^(-dB/20)
 
   // -- BVH
   bool has_bvh = false;
@@ -230,8 +238,14 @@ struct dcem_ctx {
   bool refit_pending_timing = false;
 
   // -- candidates / paths
-  // n_tx, n_rx: the paths' transmitters and receivers (either direction)
+  // n_tx, n_rx: the paths' transmitters and receivers (either direction).
+  // K: interactions per path at most (max_reflections + max_transmissions),
+  // the length of every face sequence; max_refl, max_trans: the two limits.
+  // A ray is traced once per branch (n_branch; branch_set holds each
+  // branch's set of interaction indices that transmit, bit j = interaction j).
   int32_t key_words = 0, K = 0, n_freqs = 0, n_tx = 0, n_rx = 0;
+  int32_t max_refl = 0, max_trans = 0, n_branch = 1;
+  dcem::DevBuf branch_set;
   int64_t n_rays = 0;
   int bits_tx = 0, bits_rx = 0, bits_face = 0;
   dcem::DevBuf cand_keys, cand_perm, cand_tmp, uniq_idx, first_ray;
@@ -270,7 +284,7 @@ struct dcem_ctx {
             &seg_o, &seg_d, &log_tri, &log_t, &log_len, &caps[0], &caps[1], &work_list, &invalid_flag, &stack_spill,
             &frame_block, &cand_keys, &cand_perm, &cand_tmp, &uniq_idx, &first_ray, &path_valid, &path_len,
             &path_tau, &path_aod, &path_aoa, &path_amp, &pair_range, &path_order, &path_faces, &path_pts,
-            &sort_hist, &series_buf, &expand_buf};
+            &sort_hist, &series_buf, &expand_buf, &face_pen, &mat_pen, &branch_set};
   }
 };
 

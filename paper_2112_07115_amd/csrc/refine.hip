@@ -22,7 +22,10 @@ constexpr int kMaxK = DCEM_MAX_REFLECTIONS;
 struct KeyLayout {
   int W;       // 32-bit words per key
   int bits;    // significant bits
-  int bt, br, bf, K;
+  int bt, br, bf, K;           // bf: bits per interaction field (face << tb | transmits)
+  int tb;                      // 1 when interactions may transmit (the field's low bit), else 0
+  int n_branch;                // branches per ray (work item (src * n_branch + b) * n_rays + position)
+  const uint32_t* branch_set;  // transmitting interactions of each branch (bit j: interaction j)
   int n_rx;                    // receivers of the paths
   int n_tgt;                   // capture spheres of the trace (pairs of a record: src * n_tgt + tgt)
   bool backward;               // records traced from the receivers: (src, tgt) = (rx, tx), faces reversed
@@ -63,12 +66,13 @@ __device__ inline uint32_t capture_key(const Capture& c, const int32_t* __restri
   const uint32_t tpair = c.pair_order >> 4, order = c.pair_order & 15u;
   const uint32_t src = tpair / (uint32_t)L.n_tgt, tgt = tpair - src * (uint32_t)L.n_tgt;
   const uint32_t tx = L.backward ? tgt : src, rx = L.backward ? src : tgt;
+  const uint32_t tset = order > 0 ? L.branch_set[(c.work / (uint64_t)L.n_rays) % (uint32_t)L.n_branch] : 0u;
   for (int k = 0; k < 8; ++k) w[k] = 0;
   for (int j = 0; j < L.K; ++j) {
     uint32_t f = 0;
     if ((uint32_t)j < order) {
       const uint32_t bounce = L.backward ? order - 1u - (uint32_t)j : (uint32_t)j;
-      f = (uint32_t)face_log[(size_t)bounce * n_work + c.work];
+      f = ((uint32_t)face_log[(size_t)bounce * n_work + c.work] << L.tb) | ((tset >> bounce) & (uint32_t)L.tb);
     }
     put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
   }
@@ -149,6 +153,12 @@ __device__ inline uint32_t key_bits(const uint32_t* w, int W, int pos, int nbits
   return v;
 }
 
+// Decoded face entry of an interaction field: the face, with kTransmit when
+// the interaction transmits.
+__device__ inline int32_t field_face(uint32_t field, int tb) {
+  return (int32_t)(field >> tb) | ((field & (uint32_t)tb) ? kTransmit : 0);
+}
+
 __device__ inline void write_unique(const UniqueOut& o, const KeyLayout& L, uint32_t u, const uint32_t* w,
                                     uint32_t first_work) {
   int pos = L.K * L.bf;
@@ -160,7 +170,7 @@ __device__ inline void write_unique(const UniqueOut& o, const KeyLayout& L, uint
   o.pair[u] = (int32_t)(tx * (uint32_t)L.n_rx + rx);
   o.order[u] = (uint8_t)order;
   for (int j = 0; j < L.K; ++j)
-    o.faces[(size_t)u * L.K + j] = (uint32_t)j < order ? (int32_t)key_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf) : -1;
+    o.faces[(size_t)u * L.K + j] = (uint32_t)j < order ? field_face(key_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf), L.tb) : -1;
   o.first_ray[u] = first_work == kNoRay ? -1 : (int32_t)first_work;
 }
 
@@ -509,6 +519,7 @@ struct RefineArgs {
   const int32_t* face_slots;   // slot triangle of each face_tris entry
   const int32_t* face_material;
   const double* materials;
+  const double* mat_pen;    // per material: field factor of a transmission, 10^(-loss dB / 20)
   const Node4* nodes4;
   const Leaf* tri4;         // leaf triangles in slot order
   const uint32_t* n4_dev;   // null: empty scene; [1] root leaf-slot mask
@@ -643,19 +654,21 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
 }
 
 // Image-method geometry of a candidate (Sec. III step 3): img [3 (order + 1)]
-// receives the images of T through the planes pl[0..order) in turn, pts
-// [3 (order + 2)] the transmitter, the reflection points walked back from R
-// towards the images, and R; d the distance from R to the last image (the
-// path length).  False when a walk is parallel to its plane or a reflection
-// point falls outside its open segment (then the points past it are not
-// set).  The refinement and the visited-series expansion share it, so both
-// take the same decisions.
-__device__ inline bool image_points(D3 T, D3 R, const double4* pl, int order, double* img, double* pts, double& d) {
+// receives the images of T through the planes pl[0..order) in turn (an
+// interaction j that transmits, bit j - 1 of tmask, leaves the image where it
+// is: the ray goes straight on), pts [3 (order + 2)] the transmitter, the
+// interaction points walked back from R towards the images (each on its
+// plane), and R; d the distance from R to the last image (the path length).
+// False when a walk is parallel to its plane or a point falls outside its
+// open segment (then the points past it are not set).  The refinement and
+// the visited-series expansion share it, so both take the same decisions.
+__device__ inline bool image_points(D3 T, D3 R, const double4* pl, int order, uint32_t tmask, double* img, double* pts,
+                                    double& d) {
   D3 im = T;
   img[0] = im.x; img[1] = im.y; img[2] = im.z;
   for (int j = 1; j <= order; ++j) {
     const D3 n = {pl[j - 1].x, pl[j - 1].y, pl[j - 1].z};
-    im = im - (2.0 * (dot(im, n) - pl[j - 1].w)) * n;
+    if (!((tmask >> (j - 1)) & 1u)) im = im - (2.0 * (dot(im, n) - pl[j - 1].w)) * n;
     img[3 * j] = im.x; img[3 * j + 1] = im.y; img[3 * j + 2] = im.z;
   }
   pts[0] = T.x; pts[1] = T.y; pts[2] = T.z;
@@ -673,6 +686,14 @@ __device__ inline bool image_points(D3 T, D3 R, const double4* pl, int order, do
     pts[3 * j] = Q.x; pts[3 * j + 1] = Q.y; pts[3 * j + 2] = Q.z;
   }
   return true;
+}
+
+// Does the candidate transmit through a face whose material is opaque (a
+// zero transmission factor)?  No path does.
+__device__ inline bool through_opaque(const RefineArgs& a, const int* faces, int order, uint32_t tmask) {
+  for (int j = 0; j < order; ++j)
+    if (((tmask >> j) & 1u) && a.mat_pen[a.face_material[faces[j]]] == 0.0) return true;
+  return false;
 }
 
 // Refinement of one unique candidate u by one block of K + 1 wavefronts.
@@ -693,7 +714,8 @@ constexpr int kRefineMaxThreads = kWave * (kMaxK + 2);
 
 __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ double sP[(kMaxK + 2) * 3];      // transmitter, reflection points, receiver
-  __shared__ int sfaces[kMaxK];
+  __shared__ int sfaces[kMaxK];              // face ids (transmission flag cleared)
+  __shared__ uint32_t stmask;                 // bit j - 1: interaction j transmits
   __shared__ int sorder, sok, sfail;
   __shared__ double sd;
   __shared__ double4 spl[kMaxK];              // planes of the faces
@@ -715,15 +737,18 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   // ---- 1. geometry: lane j takes face j and loads its plane, lane 0 then
   // runs the image method on LDS copies
   if (w == 0) {
+    const uint64_t tm = __ballot(lane < order0 && (face & kTransmit));
     if (lane < order0) {
-      sfaces[lane] = face;
-      spl[lane] = a.plane[face];
+      sfaces[lane] = face & kFaceMask;
+      spl[lane] = a.plane[face & kFaceMask];
     }
     wave_sync();
     if (lane == 0) {
       const int tx = pair / a.n_rx, rx = pair - tx * a.n_rx;
       const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
-      const bool ok = image_points(T, R, spl, order0, simg, sP, sd);
+      stmask = (uint32_t)tm;
+      bool ok = image_points(T, R, spl, order0, (uint32_t)tm, simg, sP, sd);
+      ok = ok && !through_opaque(a, sfaces, order0, (uint32_t)tm);
       double* P = a.pts + (size_t)u * (K + 2) * 3;
       for (int j = 0; j < 3 * (order0 + 2); ++j) P[j] = sP[j];
       a.length[u] = sd;
@@ -770,6 +795,13 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       double* out = a.amp + ((size_t)u * a.n_freqs + fi) * 6;
       Cx E[3] = {{e0.x, 0}, {e0.y, 0}, {e0.z, 0}};
       for (int j = 1; j <= order; ++j) {
+        if ((stmask >> (j - 1)) & 1u) {
+          // transmission: the penetration loss of the face's material
+          // (Table II), polarisation and direction unchanged
+          const double tf = a.mat_pen[a.face_material[sfaces[j - 1]]];
+          for (int c = 0; c < 3; ++c) E[c] = cscl(tf, E[c]);
+          continue;
+        }
         const double4 pl = spl[j - 1];
         const D3 n = {pl.x, pl.y, pl.z};
         const D3 ki = normed(pt(j) - pt(j - 1));
@@ -846,16 +878,24 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
 //    image-method points lie strictly inside their segments and inside their
 //    faces (the refinement's first checks, with the same code); survivors are
 //    compacted in order into the decoded-candidate arrays.
-__global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict__ face_log, int64_t n_work,
+__global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict__ face_log,
+                                                      const uint8_t* __restrict__ ray_state, int64_t n_work,
                                                       int n_src, int los, KeyLayout S, uint32_t* __restrict__ keys,
                                                       int64_t stride, uint32_t* __restrict__ count, uint32_t cap) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  int depth = 0;   // leading hits of ray position i, at most K
-  if (i < (uint64_t)n_work)
-    while (depth < S.K && face_log[(size_t)depth * n_work + i] >= 0) ++depth;
+  // the series of work item i: its interactions d = d0..depth (a branch
+  // adds those through its last transmission; shorter ones are its parent's)
+  int d0 = 1, depth = 0;
+  uint32_t tset = 0;
+  if (i < (uint64_t)n_work) {
+    depth = (int)(ray_state[i] & 0x0fu) - 1;   // interactions performed: segments - 1
+    tset = S.branch_set[(i / (uint64_t)S.n_rays) % (uint32_t)S.n_branch];
+    if (tset) d0 = 32 - __builtin_clz(tset);   // last transmission + 1
+  }
+  const int n_new = depth >= d0 ? depth - d0 + 1 : 0;
   const bool empty_series = los && i < (uint32_t)n_src;
-  const int n_items = depth + (empty_series ? 1 : 0);
+  const int n_items = n_new + (empty_series ? 1 : 0);
   int incl = n_items;
   for (int off = 1; off < kWave; off <<= 1) {
     const int v = __shfl_up(incl, off);
@@ -866,15 +906,17 @@ __global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict_
   if (lane == kWave - 1 && total > 0) base = atomicAdd(count, (uint32_t)total);
   base = __shfl(base, kWave - 1);
   uint32_t slot = base + (uint32_t)(incl - n_items);
-  if (depth > 0) {
-    const uint32_t src = (uint32_t)(i / (uint64_t)S.n_rays);
+  if (n_new > 0) {
+    const uint32_t src = (uint32_t)(i / ((uint64_t)S.n_rays * S.n_branch));
     const uint32_t rid = ray_of(i, S);
-    for (int d = 1; d <= depth; ++d, ++slot) {
+    for (int d = d0; d <= depth; ++d, ++slot) {
       if (slot >= cap) continue;   // the host sizes cap for every item
       uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int j = 0; j < d; ++j) {
         const int bounce = S.backward ? d - 1 - j : j;
-        put_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf, (uint32_t)face_log[(size_t)bounce * n_work + i]);
+        const uint32_t f = ((uint32_t)face_log[(size_t)bounce * n_work + i] << S.tb) |
+                           ((tset >> bounce) & (uint32_t)S.tb);
+        put_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf, f);
       }
       put_bits(w, S.W, S.K * S.bf, 4, (uint32_t)d);
       put_bits(w, S.W, S.K * S.bf + 4, S.bt, src);
@@ -915,7 +957,7 @@ __global__ __launch_bounds__(256) void k_series_info(const uint32_t* __restrict_
   const uint32_t rid = keys[S.W * stride + idx];
   o.first[s] = rid == kNoRay ? -1 : (int32_t)rid;
   for (int j = 0; j < S.K; ++j)
-    o.faces[(size_t)s * S.K + j] = (uint32_t)j < order ? (int32_t)key_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf) : -1;
+    o.faces[(size_t)s * S.K + j] = (uint32_t)j < order ? field_face(key_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf), S.tb) : -1;
 }
 
 // start[src] = first unique series of source src (lower bound), start[n_src] = S.
@@ -990,12 +1032,19 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs e, int write) {
       const D3 T = fvec(e.backward ? e.tgt_pos : e.src_pos, (int)txi);
       const D3 R = fvec(e.backward ? e.src_pos : e.tgt_pos, (int)rxi);
       double4 pl[kMaxK];
-      for (int j = 0; j < order; ++j) pl[j] = e.ra.plane[e.ser.faces[(size_t)s * e.K + j]];
+      int fid[kMaxK];
+      uint32_t tmask = 0;
+      for (int j = 0; j < order; ++j) {
+        const int32_t fe = e.ser.faces[(size_t)s * e.K + j];
+        fid[j] = fe & kFaceMask;
+        pl[j] = e.ra.plane[fid[j]];
+        if (fe & kTransmit) tmask |= 1u << j;
+      }
       double img[3 * (kMaxK + 1)], pts[3 * (kMaxK + 2)], d;
-      keep = image_points(T, R, pl, order, img, pts, d);
+      keep = image_points(T, R, pl, order, tmask, img, pts, d) && !through_opaque(e.ra, fid, order, tmask);
       for (int j = 1; j <= order && keep; ++j)
-        keep = in_face(e.ra, e.ser.faces[(size_t)s * e.K + j - 1], D3{pts[3 * j], pts[3 * j + 1], pts[3 * j + 2]},
-                       D3{pl[j - 1].x, pl[j - 1].y, pl[j - 1].z});
+        keep = in_face(e.ra, e.ser.faces[(size_t)s * e.K + j - 1] & kFaceMask,
+                       D3{pts[3 * j], pts[3 * j + 1], pts[3 * j + 2]}, D3{pl[j - 1].x, pl[j - 1].y, pl[j - 1].z});
     }
   }
   const uint64_t m = __ballot(keep);
@@ -1107,7 +1156,8 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
                                                     const double* __restrict__ length, uint32_t n_unique, int K,
                                                     int n_pairs, const double* __restrict__ freqs, int n_freqs,
                                                     const int32_t* __restrict__ face_material,
-                                                    const double* __restrict__ materials, int n_mat, double sqrt_pt,
+                                                    const double* __restrict__ materials,
+                                                    const double* __restrict__ mat_pen, int n_mat, double sqrt_pt,
                                                     double atten_db_per_km, TxPattern pat, double* __restrict__ g_eps,
                                                     double* __restrict__ g_sig, double* __restrict__ g_pat) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1149,7 +1199,18 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
     E[2] = {e0.z, 0};
     for (int c = 0; c < 3; ++c) dE[c] = {0, 0};
     for (int j = 1; j <= ord; ++j) {
-      const int mat = face_material[faces[(size_t)u * K + j - 1]];
+      const int32_t fe = faces[(size_t)u * K + j - 1];
+      const int mat = face_material[fe & kFaceMask];
+      if (fe & kTransmit) {
+        // a transmission scales the field (and its derivatives) by its loss,
+        // which no material parameter here changes
+        const double tf = mat_pen[mat];
+        for (int c = 0; c < 3; ++c) {
+          E[c] = cscl(tf, E[c]);
+          dE[c] = cscl(tf, dE[c]);
+        }
+        continue;
+      }
       const D3 ki = normed(pt(j) - pt(j - 1));
       const D3 kr = normed(pt(j + 1) - pt(j));
       const D3 dk = kr - ki;   // along the normal (zero only at grazing incidence)
@@ -1226,7 +1287,10 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
         bool act = valid[u] != 0;
         if (act && m >= 0) {
           bool uses = false;
-          for (int j = 0; j < order[u]; ++j) uses = uses || face_material[faces[(size_t)u * K + j]] == m;
+          for (int j = 0; j < order[u]; ++j) {
+            const int32_t fe = faces[(size_t)u * K + j];
+            uses = uses || (!(fe & kTransmit) && face_material[fe & kFaceMask] == m);
+          }
           act = uses;
         }
         if (act) {
@@ -1283,8 +1347,11 @@ KeyLayout key_layout(const dcem_ctx* c) {
   KeyLayout L;
   L.bt = bits_for(c->n_tx);
   L.br = bits_for(c->n_rx);
-  L.bf = std::max(1, bits_for(c->nf));
+  L.tb = c->max_trans > 0 ? 1 : 0;
+  L.bf = std::max(1, bits_for(c->nf)) + L.tb;
   L.K = c->K;
+  L.n_branch = c->n_branch;
+  L.branch_set = static_cast<const uint32_t*>(c->branch_set.p);
   L.n_rx = c->n_rx;
   L.n_tgt = c->n_tgt;
   L.backward = c->backward;
@@ -1340,7 +1407,7 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
   c->bits_tx = L.bt;
   c->bits_rx = L.br;
   c->bits_face = L.bf;
-  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_branch * c->n_rays;
   if (small) {
     if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
     if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
@@ -1407,7 +1474,7 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   S.bits = S.bt + 4 + S.K * S.bf;
   S.W = (S.bits + 31) / 32;
   const int Wt = S.W + 1;
-  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_branch * c->n_rays;
   const int64_t cap = (los ? c->n_src : 0) + n_work * c->K;
   if (cap == 0) return hipSuccess;   // no series: no candidates (the unique counter was cleared)
   if (cap >= ((int64_t)1 << 32) - 1) {
@@ -1438,7 +1505,8 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   fill_u32(sc, 0u, 2, c->stream);
   const int64_t n_thr = std::max<int64_t>(n_work, c->n_src);
   hipLaunchKernelGGL(k_series_items, dim3((unsigned)((n_thr + 255) / 256)), dim3(256), 0, c->stream,
-                     ptr<int32_t>(c->face_log), n_work, c->n_src, los ? 1 : 0, S, keys, cap, sc, (uint32_t)cap);
+                     ptr<int32_t>(c->face_log), ptr<uint8_t>(c->ray_state), n_work, c->n_src, los ? 1 : 0, S, keys,
+                     cap, sc, (uint32_t)cap);
   uint32_t n_items = 0;
   if ((e = hipMemcpyAsync(&n_items, sc, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
@@ -1485,6 +1553,8 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   x.ra.face_tris = ptr<int32_t>(c->face_tris);
   x.ra.face_slots = ptr<int32_t>(c->face_slots);
   x.ra.tri4 = ptr<Leaf>(c->tri4);
+  x.ra.face_material = ptr<int32_t>(c->face_material);
+  x.ra.mat_pen = ptr<double>(c->mat_pen);
   x.mask = ptr<uint64_t>(c->expand_buf);
   x.block_cnt = reinterpret_cast<uint32_t*>(x.mask + mask_words);
   x.capacity = 0;
@@ -1522,6 +1592,7 @@ void launch_refine(dcem_ctx* c) {
   a.face_slots = ptr<int32_t>(c->face_slots);
   a.face_material = ptr<int32_t>(c->face_material);
   a.materials = ptr<double>(c->materials);
+  a.mat_pen = ptr<double>(c->mat_pen);
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.tri4 = ptr<Leaf>(c->tri4);
   a.n4_dev = c->nt > 0 ? ptr<uint32_t>(c->tree_info) : nullptr;
@@ -1552,7 +1623,8 @@ void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_
                      ptr<int32_t>(c->pair_range), ptr<uint8_t>(c->path_valid), ptr<double>(c->path_amp),
                      ptr<double>(c->path_pts), ptr<uint8_t>(c->path_order), ptr<int32_t>(c->path_faces),
                      ptr<double>(c->path_len), n_unique, c->K, n_pairs, ptr<double>(c->freqs),
-                     c->n_freqs, ptr<int32_t>(c->face_material), ptr<double>(c->materials), c->nm, c->sqrt_pt,
+                     c->n_freqs, ptr<int32_t>(c->face_material), ptr<double>(c->materials), ptr<double>(c->mat_pen),
+                     c->nm, c->sqrt_pt,
                      c->atten_db_per_km, c->pattern_frame, g_eps, g_sig, g_pat);
 }
 

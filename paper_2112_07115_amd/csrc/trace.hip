@@ -263,10 +263,20 @@ struct TraceArgs {
   const float4* rx_cols;      // receivers by x column, then the column starts (see dcem_ctx::rx_cols)
   float rx_col_x0, rx_col_scale;
   const uint8_t* restart;     // work-list mode: first segment to trace again
-  int64_t n_rays;
+  int64_t n_rays;             // rays per source and branch
   int n_work;
   const uint32_t* work_list;  // null: all work items
-  int K;
+  int K;                      // interactions at most (segments 0..K)
+  // Transmission (the "Reflected and transmitted rays" item of Sec. III):
+  // each ray is traced once per branch; branch b transmits at the
+  // interactions in branch_set[b] (bit j: interaction j) and reflects at the
+  // others, at most max_refl times.  Work item (src, b, position) is
+  // (src * n_branch + b) * n_rays + position.  A branch stops where it would
+  // transmit through a face that is not penetrable (face_pen[face] == 0).
+  int max_refl;
+  int n_branch;
+  const uint32_t* branch_set;
+  const uint8_t* face_pen;
   const int32_t* face_object;
   uint32_t* counters;
   int32_t* face_log;          // [K+1][n_work]
@@ -349,6 +359,13 @@ __device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const floa
   setup_ray(r);
 }
 
+// Continue straight on from the hit at parameter t (transmission), with the
+// origin computed as a reflection computes it.
+__device__ inline void transmit_ray(Ray& r, float t) {
+  r.o = make_float3(__fmaf_rn(t, r.d.x, r.o.x), __fmaf_rn(t, r.d.y, r.o.y), __fmaf_rn(t, r.d.z, r.o.z));
+  setup_ray(r);
+}
+
 // Captures of one segment [o, o + tend d] (tend infinite on a miss; th its
 // hit distance): receivers whose padded box the segment meets, by the
 // receiver tree, then the exact closest-approach test; records appended to
@@ -420,9 +437,14 @@ __device__ void trace_item(const TraceArgs& a, uint32_t wi, const Node4* top, in
   // work: the ray's traversal position (its index in the face log, the
   // caches and the capture records); rid: its ray id (the parity log)
   const uint32_t work = a.work_list ? a.work_list[wi] : wi;
-  const uint32_t txi = (uint32_t)(work / (uint64_t)a.n_rays);
-  const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
-  const uint32_t rid = txi * (uint32_t)a.n_rays + ray;
+  const uint32_t vsrc = (uint32_t)(work / (uint64_t)a.n_rays);   // src * n_branch + branch
+  const uint32_t ray = a.ray_order[work - (uint64_t)vsrc * a.n_rays];
+  const uint32_t rid = vsrc * (uint32_t)a.n_rays + ray;
+  const uint32_t txi = vsrc / (uint32_t)a.n_branch;
+  // the branch's transmitting interactions; segments up to its last one are
+  // those of the branch without it, which records their captures
+  const uint32_t tset = a.branch_set[vsrc - txi * (uint32_t)a.n_branch];
+  const int last_t = tset ? 31 - __builtin_clz(tset) : -1;
   int k = a.restart ? (int)a.restart[work] : 0;
   Ray r;
   int excl = -1;
@@ -459,11 +481,20 @@ __device__ void trace_item(const TraceArgs& a, uint32_t wi, const Node4* top, in
       a.log_t[li] = hit ? h.t : INFINITY;
       a.log_len[li] = hit ? L_hit : INFINITY;
     }
-    capture_segment(a, r, hit, h.t, tend, dd, work, txi, k, stack, overflow, cap_over);
+    if (k > last_t) capture_segment(a, r, hit, h.t, tend, dd, work, txi, k, stack, overflow, cap_over);
     if (!hit || k == a.K) { ++k; break; }
-    // specular reflection off the hit triangle's plane
-    L = L_hit;
-    reflect_ray(r, h.t, a.tri4[h.leaf].v0, a.tri4[h.leaf].v1, a.tri4[h.leaf].v2);
+    if ((tset >> k) & 1u) {
+      // transmission: straight on through a penetrable face
+      if (!a.face_pen[h.face]) { ++k; break; }
+      L = L_hit;
+      transmit_ray(r, h.t);
+    } else {
+      // specular reflection off the hit triangle's plane, unless the branch
+      // has reflected max_refl times
+      if (k - __popc(tset & ((1u << k) - 1u)) == a.max_refl) { ++k; break; }
+      L = L_hit;
+      reflect_ray(r, h.t, a.tri4[h.leaf].v0, a.tri4[h.leaf].v1, a.tri4[h.leaf].v2);
+    }
     excl = h.face;
   }
   // mark the remaining bounces as not reached
@@ -541,8 +572,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_recapture(TraceArgs a) {
   for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n_work; w += gridDim.x * blockDim.x) {
     const int nseg = (int)(a.ray_state[w] & 0x0fu);
     const int stop = min(nseg, (int)a.restart[w]);
-    const uint32_t txi = (uint32_t)(w / (uint64_t)a.n_rays);
-    for (int k = 0; k < stop; ++k) {
+    const uint32_t vsrc = (uint32_t)(w / (uint64_t)a.n_rays);
+    const uint32_t txi = vsrc / (uint32_t)a.n_branch;
+    const uint32_t tset = a.branch_set[vsrc - txi * (uint32_t)a.n_branch];
+    // a branch records the captures of its segments after its last transmission
+    for (int k = tset ? 32 - __builtin_clz(tset) : 0; k < stop; ++k) {
       const float4 so = a.seg_o[(size_t)k * a.n_work + w];
       const float4 sd = a.seg_d[(size_t)k * a.n_work + w];
       Ray r;
@@ -1308,7 +1342,7 @@ namespace {
 
 // Arguments of a context's trace launch.
 TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_prev_caps) {
-  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_branch * c->n_rays;
   TraceArgs a;
   a.nodes4 = ptr<Node4>(c->nodes4);
   a.tri4 = ptr<Leaf>(c->tri4);
@@ -1340,6 +1374,10 @@ TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_pre
   a.n_work = (int)n_work;
   a.work_list = all_rays ? nullptr : ptr<uint32_t>(c->work_list);
   a.K = c->K;
+  a.max_refl = c->max_refl;
+  a.n_branch = c->n_branch;
+  a.branch_set = ptr<uint32_t>(c->branch_set);
+  a.face_pen = ptr<uint8_t>(c->face_pen);
   a.face_object = ptr<int32_t>(c->face_object);
   a.counters = c->cnt_dev;
   a.face_log = ptr<int32_t>(c->face_log);
@@ -1364,7 +1402,7 @@ TraceArgs trace_args(dcem_ctx* c, bool all_rays, bool keep_cache, uint32_t n_pre
 
 int launch_trace(dcem_ctx* c, bool all_rays, bool keep_cache, int64_t expected, uint32_t n_prev_caps) {
   TraceArgs a = trace_args(c, all_rays, keep_cache, n_prev_caps);
-  if (!all_rays && expected <= kWaveTraceMax) {
+  if (!all_rays && expected <= kWaveTraceMax && c->n_branch == 1) {
     // short re-trace list: one wavefront per ray
     const int64_t want = (expected + expected / 4 + kWaves * kGroups - 1) / (kWaves * kGroups) + 1;
     const int grid = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)cu_count(c) * 8, want));
@@ -1433,7 +1471,7 @@ hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, in
 void launch_recapture(dcem_ctx* c) {
   TraceArgs a = trace_args(c, false, true, 0u);
   a.stack_spill = ptr<int>(c->stack_spill);
-  const int64_t n_work = (int64_t)c->n_src * c->n_rays;
+  const int64_t n_work = (int64_t)c->n_src * c->n_branch * c->n_rays;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(trace_grid(c), (n_work + kTraceBlock - 1) / kTraceBlock));
   hipLaunchKernelGGL(k_recapture, dim3(grid), dim3(kTraceBlock), 0, c->stream, a);
 }
@@ -1462,9 +1500,9 @@ CohArgs coherence_args(dcem_ctx* c) {
   a.face_object = ptr<int32_t>(c->face_object);
   a.obj_box = ptr<float>(c->obj_box);
   a.n_obj = c->no;
-  a.n_work = (int)((int64_t)c->n_src * c->n_rays);
+  a.n_work = (int)((int64_t)c->n_src * c->n_branch * c->n_rays);
   a.tx = ptr<float>(c->src_pos);
-  a.n_rays = c->n_rays;
+  a.n_rays = c->n_rays * c->n_branch;   // work items per source (the segment-0 origin)
   a.margin = 1e-3f + c->pad;
   a.restart = ptr<uint8_t>(c->invalid_flag);
   a.list = ptr<uint32_t>(c->work_list);

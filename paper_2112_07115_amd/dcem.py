@@ -44,7 +44,7 @@ class TraceParams(ctypes.Structure):
                 ("n_rays", _I64), ("ray_dirs", _P), ("max_reflections", _I32), ("freqs_hz", _P),
                 ("n_freqs", _I32), ("tx_power_w", _F64), ("atten_db_per_km", _F64), ("mode", _I32),
                 ("los_always", _I32), ("keep_cache", _I32), ("record_trace_log", _I32), ("mem_kind", _I32),
-                ("trace_from_rx", _I32), ("discovery", _I32)]
+                ("trace_from_rx", _I32), ("discovery", _I32), ("max_transmissions", _I32)]
 
 
 class FrameStats(ctypes.Structure):
@@ -119,6 +119,7 @@ SIGNATURES = [
     ("dcem_received_power", _I32, [_P, _P, _P, _I32]),
     ("dcem_set_tx_pattern", _I32, [_P, _P, _I32]),
     ("dcem_set_materials", _I32, [_P, _P, _I32]),
+    ("dcem_set_penetration_loss", _I32, [_P, _P, _I32]),
     ("dcem_power_gradients", _I32, [_P, _P, _P, _P, _P]),
     ("dcem_power_gradients_noalloc", _I32, [_P, _P, _P, _P, _P]),
     ("dcem_get_paths", _I32, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
@@ -229,6 +230,7 @@ class Context:
         self.K = 0
         self.n_freqs = 1
         self.n_tx = self.n_rx = self.n_src = 0
+        self.n_branch = 1
         self.n_rays = 0
 
     def close(self):
@@ -268,6 +270,9 @@ class Context:
         d = SceneDesc(_addr(V), V.shape[0], _addr(T), _addr(TF), T.shape[0], _addr(FM), _addr(FO),
                       FM.shape[0], _addr(M), M.shape[0], _addr(OR), OR.shape[0], MEM_HOST)
         self._check(self.lib.dcem_scene_upload(self.handle, ctypes.byref(d)))
+        pen = getattr(scene, "penetration_db", None)   # per material, +inf opaque (Table II losses)
+        if pen is not None:
+            self.set_penetration_loss(pen)
         self.n_vertices = V.shape[0]
         self.n_tris = T.shape[0]
         self.n_objects = OR.shape[0]
@@ -288,7 +293,8 @@ class Context:
     def _params(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None, max_reflections: int = 2,
                 freqs_hz: Sequence[float] = (28e9,), tx_power_w: float = 5.0, atten_db_per_km: float = 0.0,
                 mode: int = MODE_FULL, los_always: bool = True, keep_cache: bool = False,
-                record_trace_log: bool = False, trace_from_rx: bool = False, discovery: int = 0):
+                record_trace_log: bool = False, trace_from_rx: bool = False, discovery: int = 0,
+                max_transmissions: int = 0):
         """dcem_trace_params of one frame (arrays kept alive on the context)."""
         dev = ray_dirs is not None and not isinstance(ray_dirs, np.ndarray) and ray_dirs.is_cuda
         if dev:
@@ -302,23 +308,25 @@ class Context:
                         int(n_rays), _addr(dirs), int(max_reflections), _addr(fr), int(fr.shape[0]),
                         float(tx_power_w), float(atten_db_per_km), int(mode), int(bool(los_always)),
                         int(bool(keep_cache)), int(bool(record_trace_log)), MEM_DEVICE if dev else MEM_HOST,
-                        int(bool(trace_from_rx)), int(discovery))
+                        int(bool(trace_from_rx)), int(discovery), int(max_transmissions))
         n_tx, n_rx = int(txa.shape[0]), int(rxa.shape[0])
-        shape = (int(max_reflections), int(fr.shape[0]), n_tx, n_rx, int(n_rays), n_rx if trace_from_rx else n_tx)
+        shape = (int(max_reflections) + int(max_transmissions), int(fr.shape[0]), n_tx, n_rx, int(n_rays),
+                 n_rx if trace_from_rx else n_tx, n_branches(int(max_reflections), int(max_transmissions)))
         return p, shape
 
     def _traced(self, shape):
-        # n_src: the rays' origins (the receivers when tracing backward)
-        self.K, self.n_freqs, self.n_tx, self.n_rx, self.n_rays, self.n_src = shape
+        # K: interactions per path at most; n_src: the rays' origins (the
+        # receivers when tracing backward); n_branch: traces per ray
+        self.K, self.n_freqs, self.n_tx, self.n_rx, self.n_rays, self.n_src, self.n_branch = shape
 
     def trace_frame(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None,
                     max_reflections: int = 2, freqs_hz: Sequence[float] = (28e9,),
                     tx_power_w: float = 5.0, atten_db_per_km: float = 0.0, mode: int = MODE_FULL,
                     los_always: bool = True, keep_cache: bool = False, record_trace_log: bool = False,
-                    trace_from_rx: bool = False, discovery: int = 0):
+                    trace_from_rx: bool = False, discovery: int = 0, max_transmissions: int = 0):
         p, shape = self._params(tx, rx, rx_radius, n_rays, ray_dirs, max_reflections, freqs_hz, tx_power_w,
                                 atten_db_per_km, mode, los_always, keep_cache, record_trace_log, trace_from_rx,
-                                discovery)
+                                discovery, max_transmissions)
         self._check(self.lib.dcem_trace_frame(self.handle, ctypes.byref(p)))
         self._traced(shape)
 
@@ -341,6 +349,11 @@ class Context:
             return
         w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
         self._check(self.lib.dcem_set_tx_pattern(self.handle, _addr(w), int(w.shape[0])))
+
+    def set_penetration_loss(self, loss_db):
+        """Penetration loss in dB per material (+inf: opaque) for the next frames."""
+        v = _host(loss_db, np.float64).reshape(-1)
+        self._check(self.lib.dcem_set_penetration_loss(self.handle, _addr(v), int(v.shape[0])))
 
     def set_materials(self, materials):
         """New material table [n_materials, 3] (eps_r, sigma, const_gamma) for
@@ -397,7 +410,7 @@ class Context:
         return out
 
     def trace_log(self):
-        shp = (self.n_src, self.n_rays, self.K + 1)
+        shp = (self.n_src, self.n_branch * self.n_rays, self.K + 1)
         tri = np.empty(shp, np.int32)
         t = np.empty(shp, np.float32)
         length = np.empty(shp, np.float32)
@@ -501,12 +514,20 @@ class Batch:
         return out.as_dict()
 
 
+def n_branches(max_reflections: int, max_transmissions: int) -> int:
+    """Traces per ray: sets of at most max_transmissions of the first
+    max_reflections + max_transmissions interactions (dcem_trace_params)."""
+    from math import comb
+    slots = max_reflections + max_transmissions
+    return sum(comb(slots, t) for t in range(max_transmissions + 1))
+
+
 def scene_frame_args(scene, frame: int = 0, mode: int = MODE_FULL, **kw) -> dict:
     """Context.trace_frame keyword arguments of one frame of a scene."""
     args = dict(tx=scene.tx, rx=scene.rx_at(frame) if hasattr(scene, "rx_at") else scene.rx,
                 rx_radius=scene.rx_radius, n_rays=scene.n_rays,
                 max_reflections=scene.max_reflections, freqs_hz=scene.freqs_hz, tx_power_w=scene.tx_power_w,
-                mode=mode)
+                mode=mode, max_transmissions=getattr(scene, "max_transmissions", 0))
     args.update(kw)
     return args
 
@@ -521,7 +542,8 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
                       n_rays: Optional[int] = None, K: Optional[int] = None, rebuild: bool = False,
                       keep_cache: bool = False, record_trace_log: bool = False, los_always: bool = True,
                       threshold: float = 1.5, atten_db_per_km: float = 0.0,
-                      trace_from_rx: bool = False, discovery: int = 0) -> FrameOutput:
+                      trace_from_rx: bool = False, discovery: int = 0,
+                      max_transmissions: Optional[int] = None) -> FrameOutput:
     """Convenience: place the scene's objects for `frame`, update the BVH, trace, read power."""
     if scene.object_vertex_range.shape[0]:
         ctx.set_object_transforms(scene.transforms(frame))
@@ -534,6 +556,8 @@ def trace_scene_frame(ctx: Context, scene, frame: int = 0, mode: int = MODE_FULL
                     max_reflections=scene.max_reflections if K is None else K, freqs_hz=scene.freqs_hz,
                     tx_power_w=scene.tx_power_w, atten_db_per_km=atten_db_per_km, mode=mode,
                     los_always=los_always, keep_cache=keep_cache, record_trace_log=record_trace_log,
-                    trace_from_rx=trace_from_rx, discovery=discovery)
+                    trace_from_rx=trace_from_rx, discovery=discovery,
+                    max_transmissions=getattr(scene, "max_transmissions", 0) if max_transmissions is None
+                    else max_transmissions)
     pc, pi = ctx.received_power()
     return FrameOutput(pc, pi)

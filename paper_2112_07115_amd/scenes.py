@@ -502,13 +502,15 @@ def indoor_office(n_rays: int = 1 << 18, max_reflections: int = 2, max_transmiss
         for (y0, y1) in ((0.0, 6.0), (8.0, 14.0)):
             ys = [y0, y0 + 2.0, y0 + 4.0, y1]
             _wall_cells(mb, 0, x, ys, zs, lambda i, j: "glass" if i == 1 and 1.0 <= zs[j] < 2.2 else "wall", mats)
-    gx = np.arange(rx_step / 2, W, rx_step)
-    gy = np.arange(rx_step / 2, D, rx_step)
+    # receivers and transmitter off the walls' lattice, so that no path meets
+    # a face edge by construction
+    gx = np.arange(rx_step * 0.437, W, rx_step)
+    gy = np.arange(rx_step * 0.383, D, rx_step)
     rx = np.array([[x, y, 1.5] for y in gy for x in gx], np.float32)
-    tx = np.array([[3.0, 7.0, 2.0]], np.float32)
+    tx = np.array([[3.173, 7.061, 2.0]], np.float32)
     inf = float("inf")
     return mb.finish("indoor_office", [CONCRETE, WALL_OUTDOOR, WALL_INDOOR, GLASS_INDOOR], tx, rx,
-                     rx_radius=0.25, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=[30e9],
+                     rx_radius=0.2, n_rays=n_rays, max_reflections=max_reflections, freqs_hz=[30e9],
                      tx_power_w=0.5, penetration_db=np.array([inf, inf, PEN_WALL_INDOOR_DB, PEN_GLASS_INDOOR_DB]),
                      max_transmissions=max_transmissions)
 

@@ -39,6 +39,9 @@ def compare_frame(ctx, scene, ofr, out, n_rays, check_log=True, check_captures=T
     came from visited-series discovery (no capture records; keys compared by
     parity.compare_visited).  Returns a dict of statistics."""
     st = {}
+    # rays are traced once per transmission branch: the logs' rows and the
+    # ray ids run over branch * n_rays + ray
+    n_rays = n_rays * getattr(ctx, "n_branch", 1)
     if check_log:
         g_tri, g_t, g_len = ctx.trace_log()
         st = parity.compare_trace(g_tri, g_t, g_len, ofr.trace, scene.tri_face, radius=radius_of(scene))

@@ -14,8 +14,9 @@ radius).  Everything else must agree exactly:
     ray whose path is uncertain;
   - refined paths (FP64 on both sides): validity, length within 1e-9
     relative, field amplitude within 1e-6 relative;
-  - received power within 0.01 dB for every receiver whose path set is
-    certain on both sides.
+  - received power within 0.01 dB for every receiver none of whose keys is
+    marginal, or uncertain and valid on a side that has it (its power is the
+    same sum of the same valid paths on both sides).
 """
 from __future__ import annotations
 
@@ -182,17 +183,16 @@ def compare_paths(gp: dict, ofr, n_rays: int, eps_len=1e-9, eps_amp=1e-6, tol_db
         for b in compare_path_attrs(gp, i, ofr.paths, j, eps_len=eps_len, eps_amp=eps_amp):
             bad.append((k,) + b)
     assert not bad, "path mismatches: %s" % bad[:5]
-    # per-receiver power
+    # per-receiver power: a receiver's power is the sum over its valid paths,
+    # so it is comparable unless one of its keys is marginal, or uncertain
+    # (either side may or may not have it) and valid on a side that has it
     ntx, nrx = ofr.p_coh.shape[1], ofr.p_coh.shape[2]
     comparable = np.ones((ntx, nrx), bool)
     for k, i in ok_.items():
-        if (not ofr.certain[i]) or ofr.paths.marginal[i]:
+        if ofr.paths.marginal[i] or (not ofr.certain[i] and ofr.paths.valid[i]):
             comparable[k[0], k[1]] = False
-    for k in gk:
-        if k not in cert:
-            comparable[k[0], k[1]] = False
-    for k in poss:
-        if k not in cert:
+    for k, i in gk.items():
+        if k not in cert and gp["valid"][i]:
             comparable[k[0], k[1]] = False
     return comparable, n_common
 
