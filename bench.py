@@ -238,6 +238,50 @@ def large_bench(torch, frames=6):
     return out
 
 
+def variants_bench(torch, frames=4):
+    """The paper's variants of the frame algorithm (Sec. III), each at its
+    workload, full frames timed after one untimed frame (wall clock over the
+    frames, the host round trips of visited-series discovery included):
+      visited_series  dynamic_urban (2^20 Fibonacci rays, K = 4, 256 Rx):
+                      every distinct series of faces the rays visit tried
+                      against every receiver, against capture spheres;
+      backward        the same scene traced from the 256 receivers (4096
+                      rays each, 2^20 in all), visited series;
+      transmission    the indoor office (396 triangles, 336 Rx, 30 GHz),
+                      2^18 rays, K = 2 reflections and 2 transmissions
+                      through walls (20 dB) and glass (5 dB): 11 branches
+                      per ray, visited series and capture spheres."""
+    from paper_2112_07115_amd import dcem, scenes
+
+    def timed(s, label, **kw):
+        ctx = dcem.Context(0)
+        ctx.set_capture_capacity(1 << 24)
+        ctx.scene_upload(s)
+        dcem.trace_scene_frame(ctx, s, frame=0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(1, frames + 1):
+            dcem.trace_scene_frame(ctx, s, frame=f if s.n_frames > 1 else 0, **kw)
+            ctx.received_power()
+        dt = (time.perf_counter() - t0) / frames
+        st = ctx.stats()
+        ctx.close()
+        work = st["rays_total"]
+        return {"case": label, "ms_per_frame": dt * 1e3, "work_items_per_frame": int(work),
+                "mrays_per_s": work / dt / 1e6, "candidates": int(st["unique_candidates"]),
+                "valid_paths": int(st["valid_paths"])}
+
+    urban = scenes.dynamic_urban()
+    office = scenes.indoor_office()
+    out = {"visited_series": [timed(urban, "capture spheres"),
+                              timed(urban, "visited series", discovery=dcem.DISCOVER_VISITED)],
+           "backward": [timed(urban, "from the receivers, visited series", trace_from_rx=True,
+                              discovery=dcem.DISCOVER_VISITED, n_rays=4096)],
+           "transmission": [timed(office, "visited series", discovery=dcem.DISCOVER_VISITED),
+                            timed(office, "capture spheres")]}
+    return out
+
+
 def cpu_info():
     model = None
     try:
@@ -436,6 +480,7 @@ def main():
     if not args.no_batch and args.mode == "both":
         out["batched"] = batched_bench(torch)
         out["large_dynamic"] = large_bench(torch)
+        out["variants"] = variants_bench(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out))

@@ -68,7 +68,13 @@ typedef int32_t dcem_status;
 #define DCEM_MODE_FULL 0      /* trace every ray */
 #define DCEM_MODE_COHERENT 1  /* reuse the previous frame's rays; retrace invalidated ones */
 
-#define DCEM_FORCE_REBUILD 1  /* dcem_refit_bvh flag: rebuild instead of refitting */
+#define DCEM_FORCE_REBUILD 1     /* dcem_refit_bvh flag: rebuild the whole tree instead of refitting */
+#define DCEM_REBUILD_SUBTREES 2  /* dcem_refit_bvh flag: rebuild the tree above the objects' subtrees */
+
+/* dcem_refit_bvh's decision (rebuilt, dcem_frame_stats.rebuilt) */
+#define DCEM_REFITTED 0
+#define DCEM_REBUILT_FULL 1      /* the whole tree was built again */
+#define DCEM_REBUILT_SUBTREES 2  /* only the tree above the objects' subtrees was built again */
 
 /* dcem_trace_params.discovery: which face sequences become candidates */
 #define DCEM_DISCOVER_CAPTURE 0  /* sequences of rays that pass through a capture sphere */
@@ -221,7 +227,7 @@ typedef struct dcem_frame_stats {
   int64_t nodes_visited;     /* 4-wide BVH nodes the closest-hit traversal fetched from device memory
                                 (the per-thread traversal keeps the top three levels in LDS) */
   int64_t tri_tests;         /* ray-triangle tests of the closest-hit traversal */
-  int32_t rebuilt;           /* last dcem_refit_bvh rebuilt the tree */
+  int32_t rebuilt;           /* last dcem_refit_bvh: DCEM_REFITTED, DCEM_REBUILT_FULL or DCEM_REBUILT_SUBTREES */
   int32_t coherent;          /* this frame reused the cache */
   double sah_ratio;          /* SAH cost of the tree relative to its last build */
   /* stage times (dcem_set_timing): the refit or rebuild, then the trace's
@@ -289,7 +295,14 @@ dcem_status dcem_set_object_transforms(dcem_ctx* ctx, const float* xf, int32_t n
  * the SAH surface-area sum relative to the last build, and rebuild instead
  * when the quality measured after the previous refit exceeds
  * rebuild_threshold (<= 0 selects 1.5; +inf never rebuilds) or when flags
- * has DCEM_FORCE_REBUILD.  The decision lags by one refit so that no host
+ * has DCEM_FORCE_REBUILD or DCEM_REBUILD_SUBTREES.  A rebuild the quality
+ * test asks for first rebuilds only subtrees (paper: "it is possible to just
+ * rebuild subtrees in some cases"): the static geometry and each moving
+ * object keep their own subtrees, which rigid motion does not degrade, and
+ * only the tree above them is built again from the objects' current
+ * positions (DCEM_REBUILT_SUBTREES); once the tree that leaves has a SAH sum
+ * above rebuild_threshold times that of the last full build, the next
+ * rebuild is a full one (DCEM_REBUILT_FULL).  The decision lags by one refit so that no host
  * round trip is needed: the ratio of a refit is read back by the next
  * synchronising call.  rebuilt / sah_ratio (nullable, host) receive the
  * decision and the ratio it was based on (1.0 right after a rebuild).

@@ -277,7 +277,7 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
   c->list_clear = false;   // the new block's counters start undefined
   // keep the head (SAH values of the current tree) across a reallocation
-  double sah_keep[2] = {1.0, 1.0};
+  double sah_keep[3] = {1.0, 1.0, 1.0};
   const bool had = c->frame_block.p != nullptr;
   hipError_t e;
   if (had) {
@@ -369,9 +369,10 @@ dcem_status sync_frame(dcem_ctx* c) {
   std::memcpy(c->last_cnt, hb, sizeof(uint32_t) * kCntSlots);
   uint32_t err = 0;
   std::memcpy(&err, hb + 128, 4);
-  double sah[2];
+  double sah[3];
   std::memcpy(sah, hb + 256, sizeof sah);
   if (c->refit_since_build && sah[0] > 0) c->pending_ratio = sah[1] / sah[0];
+  c->subtree_ratio = sah[2] > 0 ? sah[0] / sah[2] : 1.0;
   c->sah_last = c->pending_ratio;
   if (c->has_frame) {
     c->n_caps_host = std::min<int64_t>(c->last_cnt[kCntCaptures], c->cap_capacity);
@@ -675,7 +676,13 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
   // the last synchronisation), so no host round trip is needed here
   const double measured = c->pending_ratio;
   int32_t rb = 0;
-  if ((flags & DCEM_FORCE_REBUILD) || measured > threshold) {
+  // a quality-driven rebuild first rebuilds only the tree above the groups
+  // (static geometry, each moving object), whose subtrees moved rigidly;
+  // once the tree that leaves is itself worse than the threshold relative to
+  // the last full build, the whole tree is rebuilt
+  const bool subtrees = (flags & DCEM_REBUILD_SUBTREES) ||
+                        (!(flags & DCEM_FORCE_REBUILD) && c->keys_grouped && c->subtree_ratio <= threshold);
+  if ((flags & (DCEM_FORCE_REBUILD | DCEM_REBUILD_SUBTREES)) || measured > threshold) {
     // a frame whose results are still unread may have to redo its candidates
     // (more captures than the device path holds), which reads the tree it
     // was traced with: finish it before the tree is rebuilt
@@ -687,8 +694,13 @@ dcem_status dcem_refit_bvh(dcem_ctx* c, int32_t flags, double threshold, int32_t
     ev_record(c, 6);
     // a forced rebuild serves the frame at hand; one the quality test asks
     // for keeps the objects apart for the refits that follow
-    HIP_TRY(build_lbvh(c, !(flags & DCEM_FORCE_REBUILD)), "rebuild BVH");
-    rb = 1;
+    if (subtrees && !(flags & DCEM_FORCE_REBUILD) && c->keys_grouped) {
+      HIP_TRY(rebuild_subtrees(c), "rebuild BVH subtrees");
+      rb = DCEM_REBUILT_SUBTREES;
+    } else {
+      HIP_TRY(build_lbvh(c, !(flags & DCEM_FORCE_REBUILD)), "rebuild BVH");
+      rb = DCEM_REBUILT_FULL;
+    }
     ev_record(c, 7);
   } else {
     // enqueued by the next call that needs the tree (a coherent trace runs

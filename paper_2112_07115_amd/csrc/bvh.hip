@@ -514,6 +514,50 @@ __global__ void k_face_slots(const int32_t* __restrict__ face_tris, const int32_
   if (k < n) face_slots[k] = tri_slot[face_tris[k]];
 }
 
+__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+// Replace the group prefix of every triangle's stored key (the group's
+// spatial rank) and keep the rest (the face rank and the Morton code inside
+// the group), so the keys order the groups by their current centres while
+// each group's triangles keep their order.
+__global__ void k_regroup_keys(const int32_t* __restrict__ tri_face, const int32_t* __restrict__ face_object,
+                               const int32_t* __restrict__ orank, int rank_bits, int low_bits, int64_t nt,
+                               uint32_t* __restrict__ key_hi, uint32_t* __restrict__ key_lo) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const uint64_t low = (((uint64_t)key_hi[i] << 32) | key_lo[i]) & ((1ull << low_bits) - 1ull);
+  const uint64_t key = ((uint64_t)group_prefix(face_object, orank, rank_bits, tri_face[i]) << low_bits) | low;
+  key_hi[i] = (uint32_t)(key >> 32);
+  key_lo[i] = (uint32_t)key;
+}
+
+hipError_t tree_from_keys(dcem_ctx* c, int key_words, int key_bits);
+
+hipError_t rebuild_subtrees(dcem_ctx* c) {
+  if (!c->keys_grouped || c->nt < 2) return build_lbvh(c, true);
+  const int64_t nt = c->nt;
+  const int no = c->no;
+  const int key_words = c->key_words_built;
+  uint32_t* code = ptr<uint32_t>(c->morton);
+  uint32_t* key_hi = code;
+  uint32_t* key_lo = code + (size_t)nt;
+  uint32_t* nbox = code + (key_words + 2) * (size_t)nt;   // the last full build's centroid bounds
+  uint32_t* ocode = nbox + 8;
+  int32_t* orank = reinterpret_cast<int32_t*>(ocode + no);
+  c->refit_since_build = false;
+  c->pending_ratio = 1.0;
+  hipLaunchKernelGGL(k_object_codes, dim3((no + 255) / 256), dim3(256), 0, c->stream, ptr<float>(c->obj_box), no,
+                     nbox, ocode);
+  hipLaunchKernelGGL(k_object_rank, dim3((no + 255) / 256), dim3(256), 0, c->stream, ocode, no, orank);
+  const int low_bits = c->key_face_bits + 30;
+  hipLaunchKernelGGL(k_regroup_keys, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                     ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_object), orank, c->key_rank_bits, low_bits, nt,
+                     key_hi, key_lo);
+  return tree_from_keys(c, key_words, c->key_rank_bits + 1 + low_bits);
+}
+
 hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
   const int64_t nt = c->nt;
   hipError_t e;
@@ -601,6 +645,29 @@ hipError_t build_lbvh(dcem_ctx* c, bool separate_objects) {
                      ptr<int32_t>(c->tris), nt, nbox, ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_object),
                      orank, rank_bits, frank, fbits, fbox, ptr<float>(c->obj_box), key_hi, key_lo);
   const int key_bits = key_words == 2 ? prefix_bits + fbits + 30 : 30;
+  // what a subtree rebuild needs of these keys
+  c->keys_grouped = objects;
+  c->key_words_built = key_words;
+  c->key_rank_bits = rank_bits;
+  c->key_face_bits = fbits;
+  if ((e = tree_from_keys(c, key_words, key_bits)) != hipSuccess) return e;
+  // the SAH of a full build: the reference of later subtree rebuilds
+  hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, c->stream, c->sah_dev + 0, c->sah_dev + 2);
+  return hipGetLastError();
+}
+
+// The binary tree of the sorted keys (code [key_words][nt] per triangle,
+// key_bits significant), its refit, the 4-wide tree and the face slots.
+hipError_t tree_from_keys(dcem_ctx* c, int key_words, int key_bits) {
+  const int64_t nt = c->nt;
+  const int ni = c->n_internal;
+  hipError_t e;
+  uint32_t* code = ptr<uint32_t>(c->morton);   // [key_words][nt]
+  uint32_t* key_hi = key_words == 2 ? code : nullptr;
+  uint32_t* key_lo = code + (key_words - 1) * (size_t)nt;
+  uint32_t* perm = code + key_words * (size_t)nt;
+  uint32_t* perm_tmp = perm + nt;
+  uint32_t* nbox = perm_tmp + nt;
   if ((e = radix_sort_perm(c, code, key_words, key_bits, nbox + 6, nt, perm, perm_tmp, c->stream)) != hipSuccess)
     return e;
   fill_u32(ptr<uint32_t>(c->refit_cnt), 0u, (size_t)ni, c->stream);

@@ -190,6 +190,10 @@ struct dcem_ctx {
   dcem::DevBuf tri4;                                 // leaf triangles in slot order (Leaf [n4][4])
   dcem::DevBuf face_build;                           // build scratch: face boxes, keys, order and ranks
   int face_bits = 0;                                 // bits of a face's rank among its group's faces
+  // the last full build's keys (in `morton`): grouped by object, and their layout
+  bool keys_grouped = false;
+  int key_words_built = 1, key_rank_bits = 0, key_face_bits = 0;
+  double subtree_ratio = 1.0;                        // SAH of the last build relative to the last full build
 
   // -- rays and cache
   dcem::TraceConfig cfg;
@@ -228,7 +232,7 @@ struct dcem_ctx {
   int64_t n_pow_cap = 0;
   uint32_t* cnt_dev = nullptr;
   uint32_t* err_dev = nullptr;
-  double* sah_dev = nullptr;     // [0] SAH sum ratio of the last build, [1] of the last refit
+  double* sah_dev = nullptr;     // SAH sums: [0] of the last build, [1] of the last refit, [2] of the last full build
   double* pcoh_dev = nullptr;
   double* pinc_dev = nullptr;
   uint32_t last_cnt[32] = {};    // counters as of the last synchronisation
@@ -323,6 +327,12 @@ void launch_xform(dcem_ctx* c, const float* xf);
 // (and the static geometry) in a subtree of its own, for a tree that will be
 // refitted; otherwise one Morton order over all triangles.
 hipError_t build_lbvh(dcem_ctx* c, bool separate_objects);
+// Rebuild the part of the tree above the groups (the static geometry and each
+// moving object): the groups are ordered again by their current centres and
+// every group's subtree keeps its structure (its triangles keep their keys
+// below the group prefix).  Needs a last full build with separated objects,
+// else does one.
+hipError_t rebuild_subtrees(dcem_ctx* c);
 // Refit the binary tree (`wide`: and the 4-wide tree in place, no collapse
 // needed), write the SAH ratio to sah_out and the face planes.
 void launch_refit(dcem_ctx* c, bool wide, double* sah_out);

@@ -26,6 +26,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 MODE_FULL, MODE_COHERENT = 0, 1
 FORCE_REBUILD = 1
 DISCOVER_CAPTURE, DISCOVER_VISITED = 0, 1
+REBUILD_SUBTREES = 2
+REFITTED, REBUILT_FULL, REBUILT_SUBTREES = 0, 1, 2
 MAX_REFLECTIONS = 10
 PATTERN_TAPS = 16
 
@@ -283,12 +285,15 @@ class Context:
         n = int(a.shape[0])
         self._check(self.lib.dcem_set_object_transforms(self.handle, _addr(a), n, _kind(a)))
 
-    def refit_bvh(self, force_rebuild: bool = False, threshold: float = 1.5):
+    def refit_bvh(self, force_rebuild: bool = False, threshold: float = 1.5, subtrees: bool = False):
+        """Refit (or rebuild) the tree for the current vertices; returns
+        (decision, SAH ratio): REFITTED, REBUILT_FULL or REBUILT_SUBTREES."""
         rb = _I32(0)
         ratio = _F64(0.0)
-        self._check(self.lib.dcem_refit_bvh(self.handle, FORCE_REBUILD if force_rebuild else 0,
-                                            float(threshold), ctypes.byref(rb), ctypes.byref(ratio)))
-        return bool(rb.value), float(ratio.value)
+        flags = (FORCE_REBUILD if force_rebuild else 0) | (REBUILD_SUBTREES if subtrees else 0)
+        self._check(self.lib.dcem_refit_bvh(self.handle, flags, float(threshold), ctypes.byref(rb),
+                                            ctypes.byref(ratio)))
+        return int(rb.value), float(ratio.value)
 
     def _params(self, tx, rx, rx_radius: float, n_rays: int, ray_dirs=None, max_reflections: int = 2,
                 freqs_hz: Sequence[float] = (28e9,), tx_power_w: float = 5.0, atten_db_per_km: float = 0.0,
