@@ -756,6 +756,7 @@ struct FramePlan {
   bool recapture = false;   // coherent frame whose receivers moved: kept segments captured again
   bool visited = false;     // candidates from the visited series, not from capture spheres
   bool seed_los = true;     // direct-path records seeded into the capture list at the frame's start
+  int64_t hint = 0;         // > 0: sort-based candidates sized for this many captures, counts read on the device
   int64_t n_work = 0;       // n_tx * n_rays
   int64_t expected = 0;     // work items the trace is sized for
   uint32_t n_prev = 0;      // captures of the previous frame (kept by a coherent frame)
@@ -949,6 +950,11 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   plan.small = !visited && c->has_frame && same_geom && c->n_caps_host <= small_path_capacity() * 3 / 4 &&
                small_path_fits(c);
   plan.visited = visited;
+  // more captures than the one workgroup holds: the sort-based path, sized
+  // from the last frame's count with room to grow, so the frame needs no
+  // host round trip (a larger count is redone exactly when read)
+  if (!plan.small && !visited && c->has_frame && same_geom)
+    plan.hint = std::min<int64_t>(c->cap_capacity, 2 * c->n_caps_host + 4096);
   plan.coherent = coherent;
   plan.keep_cache = keep_cache;
   plan.los = p->los_always != 0;
@@ -958,6 +964,7 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   plan.ahead =
       c->revalidated_ahead && coherent && plan.seed_los == c->last_los && c->frame_block.p == block_before;
   if (plan.small) HIP_TRY(prepare_small_candidates(c), "alloc candidates");
+  if (plan.hint > 0) HIP_TRY(prepare_sorted_candidates(c, plan.hint), "alloc candidates");
   HIP_TRY(prepare_trace(c), "alloc traversal stack");
   return DCEM_OK;
 }
@@ -1010,7 +1017,7 @@ dcem_status frame_back(dcem_ctx* c, const FramePlan& plan) {
     HIP_TRY(build_visited_candidates(c, plan.los, too_many), "visited-series candidates");
     if (too_many) return fail(c, DCEM_E_UNSUPPORTED, "visited series x targets must be < 2^32");
   } else {
-    HIP_TRY(build_candidates(c, plan.small), "candidates");
+    HIP_TRY(build_candidates(c, plan.small, plan.hint), "candidates");
   }
   ev_record(c, 3);
   HIP_TRY(ensure_paths(c, c->path_cap), "alloc paths");
@@ -1470,7 +1477,7 @@ dcem_status batch_frame(dcem_batch* b, const dcem_trace_params* params, const dc
       full_cache.push_back(plan[j].keep_cache ? 1 : 0);
     }
     // device-side decisions only (no host round trip, no timing events)
-    capturable = capturable && plan[j].small && !cj->timing;
+    capturable = capturable && (plan[j].small || plan[j].hint > 0) && !cj->timing;
   }
   if (capturable) HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed), "begin capture");
   dcem_status st = DCEM_OK;

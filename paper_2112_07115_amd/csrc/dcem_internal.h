@@ -344,6 +344,9 @@ void launch_collapse(dcem_ctx* c);
 // The item count is min(*n_dev, n_max), read on the device.
 hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, const uint32_t* n_dev,
                            int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s);
+// The sort's histogram space for up to n_max items (sized before a frame that
+// a graph may capture).
+hipError_t prepare_sort(dcem_ctx* c, int64_t n_max);
 
 // ---- trace (trace.hip)
 void launch_fibonacci(dcem_ctx* c);
@@ -383,7 +386,9 @@ hipError_t launch_trace_batch(dcem_ctx* const* cs, const uint8_t* keep_cache, in
 size_t batch_table_bytes(int n);
 
 // ---- candidates, refinement and accumulation (refine.hip)
-hipError_t build_candidates(dcem_ctx* c, bool small);
+hipError_t build_candidates(dcem_ctx* c, bool small, int64_t hint = 0);
+// Buffers of the sort-based de-duplication sized for n captures.
+hipError_t prepare_sorted_candidates(dcem_ctx* c, int64_t n);
 // Visited-series discovery: every distinct series of faces the frame's rays
 // reflect on (per source, up to K), tried against every target; the
 // candidates whose image-method points lie inside their segments and faces

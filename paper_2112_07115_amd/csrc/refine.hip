@@ -85,10 +85,12 @@ __device__ inline uint32_t capture_key(const Capture& c, const int32_t* __restri
   return tx * (uint32_t)L.n_rx + rx;
 }
 
-__global__ void k_keys(const Capture* __restrict__ caps, uint32_t n, const int32_t* __restrict__ face_log,
-                       int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys, int64_t stride) {
+// Item counts of the sort-based path are read on the device: min(*n_dev, n_max).
+__global__ void k_keys(const Capture* __restrict__ caps, const uint32_t* __restrict__ n_dev, uint32_t n_max,
+                       const int32_t* __restrict__ face_log, int64_t n_work, KeyLayout L, uint32_t* __restrict__ keys,
+                       int64_t stride) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= min(*n_dev, n_max)) return;
   uint32_t w[8];
   capture_key(caps[i], face_log, n_work, L, w);
   for (int k = 0; k < L.W; ++k) keys[k * stride + i] = w[k];
@@ -335,9 +337,11 @@ void launch_small_dedupe(dcem_ctx* c, const KeyLayout& L, int64_t n_work) {
 }
 
 __global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
-                                               const uint32_t* __restrict__ perm, uint32_t n,
-                                               uint8_t* __restrict__ head, uint32_t* __restrict__ block_cnt) {
+                                               const uint32_t* __restrict__ perm, const uint32_t* __restrict__ n_dev,
+                                               uint32_t n_max, uint8_t* __restrict__ head,
+                                               uint32_t* __restrict__ block_cnt) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = min(*n_dev, n_max);
   bool h = false;
   if (i < n) {
     h = i == 0;
@@ -378,10 +382,12 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint32_t* __restrict__ v, i
 }
 
 __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ head,
-                                                 const uint32_t* __restrict__ block_off, uint32_t n,
+                                                 const uint32_t* __restrict__ block_off,
+                                                 const uint32_t* __restrict__ n_dev, uint32_t n_max,
                                                  const uint32_t* __restrict__ n_unique,
                                                  uint32_t* __restrict__ uniq_pos) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = min(*n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool h = i < n && head[i];
   const uint64_t m = __ballot(h);
@@ -653,37 +659,46 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
   return false;
 }
 
-// Image-method geometry of a candidate (Sec. III step 3): img [3 (order + 1)]
-// receives the images of T through the planes pl[0..order) in turn (an
-// interaction j that transmits, bit j - 1 of tmask, leaves the image where it
-// is: the ray goes straight on), pts [3 (order + 2)] the transmitter, the
-// interaction points walked back from R towards the images (each on its
-// plane), and R; d the distance from R to the last image (the path length).
-// False when a walk is parallel to its plane or a point falls outside its
-// open segment (then the points past it are not set).  The refinement and
-// the visited-series expansion share it, so both take the same decisions.
-__device__ inline bool image_points(D3 T, D3 R, const double4* pl, int order, uint32_t tmask, double* img, double* pts,
-                                    double& d) {
-  D3 im = T;
-  img[0] = im.x; img[1] = im.y; img[2] = im.z;
-  for (int j = 1; j <= order; ++j) {
-    const D3 n = {pl[j - 1].x, pl[j - 1].y, pl[j - 1].z};
-    if (!((tmask >> (j - 1)) & 1u)) im = im - (2.0 * (dot(im, n) - pl[j - 1].w)) * n;
-    img[3 * j] = im.x; img[3 * j + 1] = im.y; img[3 * j + 2] = im.z;
-  }
-  pts[0] = T.x; pts[1] = T.y; pts[2] = T.z;
-  pts[3 * (order + 1)] = R.x; pts[3 * (order + 1) + 1] = R.y; pts[3 * (order + 1) + 2] = R.z;
-  d = len(R - im);
+// Image-method geometry of a candidate (Sec. III step 3): the images of T
+// through the planes of interactions 1..j in turn (an interaction that
+// transmits, bit j - 1 of tmask, leaves the image where it is: the ray goes
+// straight on), then the interaction points walked back from R towards the
+// images, each on its plane.  plane(j) gives interaction j + 1's plane;
+// visit(j, P) receives point j (j = order..1) and may stop the walk by
+// returning false; d receives the distance from R to the last image (the path
+// length).  False when a walk is parallel to its plane, a point falls outside
+// its open segment, or visit stops.  An image is recomputed from T when the
+// walk needs it (no arrays), with contraction off, so the refinement and the
+// visited-series expansion, which share this code, take the same decisions.
+template <class Plane, class Visit>
+__device__ inline bool image_walk(D3 T, D3 R, int order, uint32_t tmask, Plane plane, Visit visit, double& d) {
+#pragma clang fp contract(off)
+  auto image = [&](int j) {
+    D3 im = T;
+    for (int q = 1; q <= j; ++q) {
+      if ((tmask >> (q - 1)) & 1u) continue;
+      const double4 pl = plane(q - 1);
+      const D3 n = {pl.x, pl.y, pl.z};
+      const double h = 2.0 * ((im.x * n.x + im.y * n.y + im.z * n.z) - pl.w);
+      im = D3{im.x - h * n.x, im.y - h * n.y, im.z - h * n.z};
+    }
+    return im;
+  };
+  const D3 last = image(order);
+  const D3 rl = {R.x - last.x, R.y - last.y, R.z - last.z};
+  d = sqrt(rl.x * rl.x + rl.y * rl.y + rl.z * rl.z);
   D3 Q = R;
   for (int j = order; j >= 1; --j) {
-    const D3 n = {pl[j - 1].x, pl[j - 1].y, pl[j - 1].z};
-    const D3 D = D3{img[3 * j], img[3 * j + 1], img[3 * j + 2]} - Q;
-    const double den = dot(D, n);
+    const double4 pl = plane(j - 1);
+    const D3 n = {pl.x, pl.y, pl.z};
+    const D3 im = j == order ? last : image(j);
+    const D3 D = {im.x - Q.x, im.y - Q.y, im.z - Q.z};
+    const double den = D.x * n.x + D.y * n.y + D.z * n.z;
     if (den == 0.0) return false;
-    const double s = (pl[j - 1].w - dot(Q, n)) / den;
+    const double s = (pl.w - (Q.x * n.x + Q.y * n.y + Q.z * n.z)) / den;
     if (!(s > 0.0 && s < 1.0)) return false;
-    Q = Q + s * D;
-    pts[3 * j] = Q.x; pts[3 * j + 1] = Q.y; pts[3 * j + 2] = Q.z;
+    Q = D3{Q.x + s * D.x, Q.y + s * D.y, Q.z + s * D.z};
+    if (!visit(j, Q)) return false;
   }
   return true;
 }
@@ -719,7 +734,6 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ int sorder, sok, sfail;
   __shared__ double sd;
   __shared__ double4 spl[kMaxK];              // planes of the faces
-  __shared__ double simg[(kMaxK + 1) * 3];    // transmitter images
   __shared__ uint32_t stk[kMaxK + 1][kCheckStack];
   const uint32_t u = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
@@ -747,7 +761,15 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       const int tx = pair / a.n_rx, rx = pair - tx * a.n_rx;
       const D3 T = fvec(a.tx, tx), R = fvec(a.rx, rx);
       stmask = (uint32_t)tm;
-      bool ok = image_points(T, R, spl, order0, (uint32_t)tm, simg, sP, sd);
+      sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
+      sP[3 * (order0 + 1)] = R.x; sP[3 * (order0 + 1) + 1] = R.y; sP[3 * (order0 + 1) + 2] = R.z;
+      bool ok = image_walk(
+          T, R, order0, (uint32_t)tm, [&](int j) { return spl[j]; },
+          [&](int j, D3 q) {
+            sP[3 * j] = q.x; sP[3 * j + 1] = q.y; sP[3 * j + 2] = q.z;
+            return true;
+          },
+          sd);
       ok = ok && !through_opaque(a, sfaces, order0, (uint32_t)tm);
       double* P = a.pts + (size_t)u * (K + 2) * 3;
       for (int j = 0; j < 3 * (order0 + 2); ++j) P[j] = sP[j];
@@ -896,16 +918,27 @@ __global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict_
   const int n_new = depth >= d0 ? depth - d0 + 1 : 0;
   const bool empty_series = los && i < (uint32_t)n_src;
   const int n_items = n_new + (empty_series ? 1 : 0);
+  // one append per block: wave scans, then the wave totals in LDS
+  __shared__ uint32_t wsum[256 / kWave], bbase;
+  const int wave = threadIdx.x / kWave;
   int incl = n_items;
   for (int off = 1; off < kWave; off <<= 1) {
     const int v = __shfl_up(incl, off);
     if (lane >= off) incl += v;
   }
-  const int total = __shfl(incl, kWave - 1);
-  uint32_t base = 0;
-  if (lane == kWave - 1 && total > 0) base = atomicAdd(count, (uint32_t)total);
-  base = __shfl(base, kWave - 1);
-  uint32_t slot = base + (uint32_t)(incl - n_items);
+  if (lane == kWave - 1) wsum[wave] = (uint32_t)incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int v = 0; v < 256 / kWave; ++v) {
+      const uint32_t x = wsum[v];
+      wsum[v] = t;
+      t += x;
+    }
+    bbase = t > 0 ? atomicAdd(count, t) : 0u;
+  }
+  __syncthreads();
+  uint32_t slot = bbase + wsum[wave] + (uint32_t)(incl - n_items);
   if (n_new > 0) {
     const uint32_t src = (uint32_t)(i / ((uint64_t)S.n_rays * S.n_branch));
     const uint32_t rid = ray_of(i, S);
@@ -975,6 +1008,57 @@ __global__ __launch_bounds__(256) void k_series_starts(const int32_t* __restrict
   start[q] = lo;
 }
 
+// Bounds of each face's vertices (as the tree holds them), for the
+// expansion's pre-test of its in-face checks: [nf][6] lo xyz, hi xyz as
+// order-preserving integer bits (min and max by integer atomics), one thread
+// per face triangle; box must hold 0xffffffff in the lo words and 0 in the hi
+// words.
+__device__ inline uint32_t ordered_u32(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float from_ordered_u32(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ __launch_bounds__(256) void k_face_boxes(const int32_t* __restrict__ face_tris,
+                                                    const int32_t* __restrict__ tri_face,
+                                                    const int32_t* __restrict__ face_slots,
+                                                    const Leaf* __restrict__ tri4, int64_t nt, uint32_t* __restrict__ box) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  const int f = tri_face[face_tris[k]];
+  const Leaf L = tri4[face_slots[k]];
+  const float4 v[3] = {L.v0, L.v1, L.v2};
+  for (int q = 0; q < 3; ++q) {
+    atomicMin(&box[6 * f + 0], ordered_u32(v[q].x));
+    atomicMin(&box[6 * f + 1], ordered_u32(v[q].y));
+    atomicMin(&box[6 * f + 2], ordered_u32(v[q].z));
+    atomicMax(&box[6 * f + 3], ordered_u32(v[q].x));
+    atomicMax(&box[6 * f + 4], ordered_u32(v[q].y));
+    atomicMax(&box[6 * f + 5], ordered_u32(v[q].z));
+  }
+}
+
+__global__ void k_face_box_init(uint32_t* __restrict__ box, int nf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 6 * nf) box[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
+}
+
+// May p lie in face f?  The two coordinates in_face keeps (the normal's
+// dominant axis dropped) against the face's bounds: a point in_face accepts
+// always passes (it lies in a triangle's projection, inside the bounds of its
+// vertices), so this only skips checks that would fail.
+__device__ inline bool in_face_bounds(const uint32_t* __restrict__ box, int f, D3 p, D3 n) {
+  const double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
+  const int drop = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  const uint32_t* b = box + 6 * f;
+  auto inside = [&](double u, int a) {
+    return u >= (double)from_ordered_u32(b[a]) && u <= (double)from_ordered_u32(b[3 + a]);
+  };
+  return (drop == 0 || inside(p.x, 0)) && (drop == 1 || inside(p.y, 1)) && (drop == 2 || inside(p.z, 2));
+}
+
 struct ExpandArgs {
   SeriesOut ser;
   const uint32_t* start;   // [n_src + 1]
@@ -985,6 +1069,7 @@ struct ExpandArgs {
   const float* src_pos;
   const float* tgt_pos;
   RefineArgs ra;           // faces: planes, triangles (in_face)
+  const uint32_t* face_box;   // [nf][6] face bounds as ordered bits (k_face_boxes)
   uint64_t* mask;          // [ceil(n_cand / 64)] survivors, one bit per candidate
   uint32_t* block_cnt;     // survivors per block, then (scanned) their offsets
   uint32_t capacity;       // decoded-candidate entries available
@@ -1031,20 +1116,27 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs e, int write) {
       const uint32_t txi = e.backward ? tgt : src, rxi = e.backward ? src : tgt;
       const D3 T = fvec(e.backward ? e.tgt_pos : e.src_pos, (int)txi);
       const D3 R = fvec(e.backward ? e.src_pos : e.tgt_pos, (int)rxi);
-      double4 pl[kMaxK];
-      int fid[kMaxK];
+      const int32_t* fs = e.ser.faces + (size_t)s * e.K;
       uint32_t tmask = 0;
+      bool opaque = false;
       for (int j = 0; j < order; ++j) {
-        const int32_t fe = e.ser.faces[(size_t)s * e.K + j];
-        fid[j] = fe & kFaceMask;
-        pl[j] = e.ra.plane[fid[j]];
-        if (fe & kTransmit) tmask |= 1u << j;
+        const int32_t fe = fs[j];
+        if (fe & kTransmit) {
+          tmask |= 1u << j;
+          opaque = opaque || e.ra.mat_pen[e.ra.face_material[fe & kFaceMask]] == 0.0;
+        }
       }
-      double img[3 * (kMaxK + 1)], pts[3 * (kMaxK + 2)], d;
-      keep = image_points(T, R, pl, order, tmask, img, pts, d) && !through_opaque(e.ra, fid, order, tmask);
-      for (int j = 1; j <= order && keep; ++j)
-        keep = in_face(e.ra, e.ser.faces[(size_t)s * e.K + j - 1] & kFaceMask,
-                       D3{pts[3 * j], pts[3 * j + 1], pts[3 * j + 2]}, D3{pl[j - 1].x, pl[j - 1].y, pl[j - 1].z});
+      double d;
+      // each point is tested against its face as soon as the walk reaches it
+      keep = !opaque && image_walk(
+                            T, R, order, tmask, [&](int j) { return e.ra.plane[fs[j] & kFaceMask]; },
+                            [&](int j, D3 q) {
+                              const int f = fs[j - 1] & kFaceMask;
+                              const double4 pl = e.ra.plane[f];
+                              const D3 n = {pl.x, pl.y, pl.z};
+                              return in_face_bounds(e.face_box, f, q, n) && in_face(e.ra, f, q, n);
+                            },
+                            d);
     }
   }
   const uint64_t m = __ballot(keep);
@@ -1393,11 +1485,43 @@ hipError_t prepare_small_candidates(dcem_ctx* c) {
   return ensure_paths(c, kSmallN);
 }
 
+// Buffers of the sort-based de-duplication for n captures (keys, permutation,
+// run heads and block counts, unique positions, paths, the sort's histograms).
+hipError_t prepare_sorted_candidates(dcem_ctx* c, int64_t n) {
+  hipError_t e;
+  n = std::max<int64_t>(n, 1);
+  const KeyLayout L = key_layout(c);
+  const int64_t nb = (n + 255) / 256;
+  if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * n)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_perm, sizeof(uint32_t) * 2 * n)) != hipSuccess) return e;
+  if ((e = ensure(c->cand_tmp, n + 16 + sizeof(uint32_t) * (nb + 8))) != hipSuccess) return e;
+  if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (n + 1))) != hipSuccess) return e;
+  if ((e = ensure_paths(c, n)) != hipSuccess) return e;
+  return prepare_sort(c, n);
+}
+
+namespace {
+
+// Size-hinted path: more captures than the buffers were sized for leave the
+// frame's candidates to the host's exact redo (as the one-workgroup path does).
+__global__ void k_fit_check(const uint32_t* __restrict__ n_caps, uint32_t n_max, uint32_t* __restrict__ n_unique,
+                            uint32_t* __restrict__ fallback) {
+  if (threadIdx.x == 0 && *n_caps > n_max) {
+    *fallback = 1;
+    *n_unique = 0;
+  }
+}
+
+}  // namespace
+
 // Candidate keys, sort and unique.  `small`: one workgroup de-duplicates up to
 // kSmallN captures whose count it reads on the device (no host round trip; a
 // larger count raises the fallback counter and the host redoes the frame's
-// candidates exactly).  Otherwise the capture count is read back first.
-hipError_t build_candidates(dcem_ctx* c, bool small) {
+// candidates exactly).  `hint` > 0: the sort-based path with every size taken
+// from `hint` and the capture count read on the device (no host round trip;
+// more captures than `hint` fall back the same way).  Otherwise the capture
+// count is read back first.
+hipError_t build_candidates(dcem_ctx* c, bool small, int64_t hint) {
   hipError_t e;
   // the de-duplication writes each unique candidate's decoded record into
   // the path arrays
@@ -1420,44 +1544,53 @@ hipError_t build_candidates(dcem_ctx* c, bool small) {
     return hipGetLastError();
   }
   c->small_path = false;
-  uint32_t n_caps = 0;
-  if ((e = hipMemcpyAsync(&n_caps, cnt + kCntCaptures, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-  if (n_caps > c->cap_capacity) n_caps = (uint32_t)c->cap_capacity;
-  c->n_caps_host = n_caps;
-  const int64_t n = std::max<int64_t>(n_caps, 1);
-  c->path_cap = n_caps;
-  if ((e = ensure_paths(c, n)) != hipSuccess) return e;
-  if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
-    if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
-    if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
-    if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
-    c->key_stride = kSmallN;
-    launch_small_dedupe(c, L, n_work);
-    return hipGetLastError();
+  const bool device_count = hint > 0;
+  uint32_t n_max = 0;
+  if (device_count) {
+    n_max = (uint32_t)std::min<int64_t>(hint, c->cap_capacity);
+  } else {
+    uint32_t n_caps = 0;
+    if ((e = hipMemcpyAsync(&n_caps, cnt + kCntCaptures, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    if (n_caps > c->cap_capacity) n_caps = (uint32_t)c->cap_capacity;
+    c->n_caps_host = n_caps;
+    if (n_caps <= (uint32_t)kSmallN && L.W <= kSmallW) {
+      c->path_cap = n_caps;
+      if ((e = ensure_paths(c, std::max<int64_t>(n_caps, 1))) != hipSuccess) return e;
+      if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * kSmallN)) != hipSuccess) return e;
+      if ((e = ensure(c->cand_perm, sizeof(uint32_t) * kSmallN)) != hipSuccess) return e;
+      if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (kSmallN + 1))) != hipSuccess) return e;
+      c->key_stride = kSmallN;
+      launch_small_dedupe(c, L, n_work);
+      return hipGetLastError();
+    }
+    n_max = n_caps;
   }
+  const int64_t n = std::max<int64_t>(n_max, 1);
+  c->path_cap = n_max;
   c->key_stride = n;
-  if ((e = ensure(c->cand_keys, sizeof(uint32_t) * L.W * n)) != hipSuccess) return e;
-  if ((e = ensure(c->cand_perm, sizeof(uint32_t) * 2 * n)) != hipSuccess) return e;
+  if ((e = prepare_sorted_candidates(c, n)) != hipSuccess) return e;
+  if (n_max == 0) return hipSuccess;   // the unique counter was cleared at frame start
   const int nb = (int)((n + 255) / 256);
-  if ((e = ensure(c->cand_tmp, n + 16 + sizeof(uint32_t) * (nb + 8))) != hipSuccess) return e;
-  if ((e = ensure(c->uniq_idx, sizeof(uint32_t) * (n + 1))) != hipSuccess) return e;
   uint32_t* keys = ptr<uint32_t>(c->cand_keys);
   uint32_t* perm = ptr<uint32_t>(c->cand_perm);
   uint8_t* head = ptr<uint8_t>(c->cand_tmp);
   uint32_t* bcnt = reinterpret_cast<uint32_t*>(ptr<uint8_t>(c->cand_tmp) + ((n + 15) / 16) * 16);
-  if (n_caps == 0) return hipSuccess;   // the unique counter was cleared at frame start
-  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_caps,
+  const uint32_t* n_dev = cnt + kCntCaptures;
+  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_dev, n_max,
                      ptr<int32_t>(c->face_log), n_work, L, keys, (int64_t)n);
-  if ((e = radix_sort_perm(c, keys, L.W, L.bits, cnt + kCntCaptures, n, perm, perm + n, c->stream)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_caps, head, bcnt);
+  if ((e = radix_sort_perm(c, keys, L.W, L.bits, n_dev, n, perm, perm + n, c->stream)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_dev, n_max, head, bcnt);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nb, cnt + kCntUnique);
-  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_caps, cnt + kCntUnique,
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_dev, n_max, cnt + kCntUnique,
                      ptr<uint32_t>(c->uniq_idx));
   hipLaunchKernelGGL(k_unique_info, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L, perm,
                      ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique, ptr<Capture>(c->caps[c->cur_caps]),
                      unique_out(c));
+  if (device_count)
+    hipLaunchKernelGGL(k_fit_check, dim3(1), dim3(64), 0, c->stream, n_dev, n_max, cnt + kCntUnique,
+                       cnt + kCntFallback);
   return hipGetLastError();
 }
 
@@ -1514,9 +1647,10 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   n_items = std::min<uint32_t>(n_items, (uint32_t)cap);
   if ((e = radix_sort_perm(c, keys, Wt, 32 + S.bits, sc, cap, perm, perm + cap, c->stream)) != hipSuccess) return e;
   const int nbi = (int)((n_items + 255) / 256);
-  hipLaunchKernelGGL(k_heads, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S.W, perm, n_items, head, bcnt);
+  hipLaunchKernelGGL(k_heads, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S.W, perm, sc, n_items, head,
+                     bcnt);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nbi, sc + 1);
-  hipLaunchKernelGGL(k_compact, dim3(nbi), dim3(256), 0, c->stream, head, bcnt, n_items, sc + 1,
+  hipLaunchKernelGGL(k_compact, dim3(nbi), dim3(256), 0, c->stream, head, bcnt, sc, n_items, sc + 1,
                      ptr<uint32_t>(c->uniq_idx));
   hipLaunchKernelGGL(k_series_info, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S, perm,
                      ptr<uint32_t>(c->uniq_idx), sc + 1, so);
@@ -1533,7 +1667,9 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   }
   const uint32_t nbe = (uint32_t)((n_cand + 255) / 256);
   const size_t mask_words = (size_t)nbe * 4;
-  if ((e = ensure(c->expand_buf, sizeof(uint64_t) * mask_words + sizeof(uint32_t) * ((size_t)nbe + 8))) != hipSuccess)
+  const size_t box_floats = 6 * (size_t)std::max(c->nf, 1);
+  if ((e = ensure(c->expand_buf, sizeof(uint64_t) * mask_words + sizeof(uint32_t) * ((size_t)nbe + 8) +
+                                     sizeof(float) * box_floats)) != hipSuccess)
     return e;
   ExpandArgs x;
   x.ser = so;
@@ -1557,6 +1693,14 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   x.ra.mat_pen = ptr<double>(c->mat_pen);
   x.mask = ptr<uint64_t>(c->expand_buf);
   x.block_cnt = reinterpret_cast<uint32_t*>(x.mask + mask_words);
+  uint32_t* fbox = x.block_cnt + nbe + 8;
+  x.face_box = fbox;
+  if (c->nf > 0 && c->nt > 0) {
+    hipLaunchKernelGGL(k_face_box_init, dim3((6 * c->nf + 255) / 256), dim3(256), 0, c->stream, fbox, c->nf);
+    hipLaunchKernelGGL(k_face_boxes, dim3((unsigned)((c->nt + 255) / 256)), dim3(256), 0, c->stream,
+                       ptr<int32_t>(c->face_tris), ptr<int32_t>(c->tri_face), ptr<int32_t>(c->face_slots),
+                       ptr<Leaf>(c->tri4), c->nt, fbox);
+  }
   x.capacity = 0;
   x.err = c->err_dev;
   x.out = unique_out(c);

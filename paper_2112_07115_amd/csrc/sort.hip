@@ -15,6 +15,7 @@ constexpr int kThreads = 256;
 constexpr int kRounds = 8;
 constexpr int kTile = kThreads * kRounds;
 constexpr int kWaves = kThreads / kWave;
+constexpr int kSmallScan = 1 << 16;   // histogram entries the one-block scan takes alone
 
 __device__ inline uint32_t digit_of(const uint32_t* __restrict__ keys, int64_t stride, int word, int shift,
                                     uint32_t idx) {
@@ -68,6 +69,54 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ hist, int 
   }
 }
 
+// Larger histograms: a three-kernel scan.  Block g owns the contiguous
+// segment [g * seg, (g + 1) * seg) of hist: k_scan_sums reduces it into
+// sums[g], k_scan (one block) scans the sums, and k_scan_down scans the
+// segment again, 256 coalesced entries at a time, from its block's offset.
+constexpr int kScanBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_scan_sums(const uint32_t* __restrict__ hist, int total, int seg,
+                                                       uint32_t* __restrict__ sums) {
+  __shared__ uint32_t ws[kWaves];
+  const int b = blockIdx.x * seg, e = min(total, b + seg);
+  uint32_t s = 0;
+  for (int i = b + (int)threadIdx.x; i < e; i += kThreads) s += hist[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kWaves; ++w) t += ws[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(uint32_t* __restrict__ hist, int total, int seg,
+                                                       const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t ws[kWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int b = blockIdx.x * seg, e = min(total, b + seg);
+  uint32_t run = offs[blockIdx.x];
+  for (int c = b; c < e; c += kThreads) {
+    const int i = c + (int)threadIdx.x;
+    const uint32_t v = i < e ? hist[i] : 0u;
+    uint32_t incl = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    if (lane == kWave - 1) ws[wave] = incl;
+    __syncthreads();
+    uint32_t before = run;
+    for (int w = 0; w < wave; ++w) before += ws[w];
+    uint32_t chunk = 0;
+    for (int w = 0; w < kWaves; ++w) chunk += ws[w];
+    if (i < e) hist[i] = before + incl - v;
+    run += chunk;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ keys, int64_t stride, int word,
                                                       int shift, const uint32_t* __restrict__ src,
                                                       uint32_t* __restrict__ dst, const uint32_t* __restrict__ n_dev,
@@ -116,13 +165,23 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
 
 }  // namespace
 
+hipError_t prepare_sort(dcem_ctx* c, int64_t n_max) {
+  const int64_t n_tiles = std::max<int64_t>((n_max + kTile - 1) / kTile, 1);
+  return ensure(c->sort_hist, sizeof(uint32_t) * (256 * (size_t)n_tiles + kScanBlocks));
+}
+
 hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, const uint32_t* n_dev,
                            int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   const int n_tiles = (int)((n_max + kTile - 1) / kTile);
-  hipError_t e = ensure(c->sort_hist, sizeof(uint32_t) * 256 * (size_t)n_tiles);
+  const int total = 256 * n_tiles;
+  // histograms of more entries than the one-block scan handles quickly are
+  // scanned by kScanBlocks blocks (their sums after the histogram)
+  const int seg = (total + kScanBlocks - 1) / kScanBlocks;
+  hipError_t e = ensure(c->sort_hist, sizeof(uint32_t) * ((size_t)total + kScanBlocks));
   if (e != hipSuccess) return e;
   uint32_t* hist = ptr<uint32_t>(c->sort_hist);
+  uint32_t* sums = hist + total;
   const int passes = (bits + 7) / 8;
   const uint32_t* src = nullptr;
   for (int p = 0; p < passes; ++p) {
@@ -132,7 +191,13 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
     uint32_t* dst = ((passes - 1 - p) % 2 == 0) ? perm : perm_tmp;
     hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kThreads), 0, s, keys, n_max, word, shift, src, n_dev,
                        (uint32_t)n_max, hist, n_tiles);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, 256 * n_tiles);
+    if (total <= kSmallScan) {
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, total);
+    } else {
+      hipLaunchKernelGGL(k_scan_sums, dim3(kScanBlocks), dim3(kThreads), 0, s, hist, total, seg, sums);
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sums, kScanBlocks);
+      hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kThreads), 0, s, hist, total, seg, sums);
+    }
     hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kThreads), 0, s, keys, n_max, word, shift, src, dst, n_dev,
                        (uint32_t)n_max, hist, n_tiles);
     src = dst;

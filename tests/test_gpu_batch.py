@@ -125,3 +125,22 @@ def test_batch_scenes_against_oracle_sampled(O):
         log("scene", s.n_tris, "tris", s.tx.shape[0], "tx", s.n_rays, "rays K", s.max_reflections)
         check_full_size_sampled(c, O, s, 2, stride=max(1, s.n_rays // 16384), min_keys=3)
     batch.close()
+
+
+def test_batch_of_large_capture_lists_as_one_graph():
+    """Scenes with more captures than the one-workgroup path holds: after the
+    first frame their candidates take the sort-based path sized from the last
+    frame's count, with every count read on the device, so the whole batch is
+    captured as one graph too."""
+    import torch
+    stream = torch.cuda.Stream()
+    ws = small_batch(4, seed=16, budget_range=(1 << 20, 1 << 21), rx_range=(768, 1024))
+    with torch.cuda.stream(stream):
+        batch, b, s = run_batched_and_single(ws, [0, 1, 2, 3], graph=True, stream=stream.cuda_stream)
+        info = batch.info()
+        caps = [c.stats()["captures"] for c in b]
+        log("captures per scene", caps, info)
+        assert max(caps) > 2048
+        assert info["graph_frames"] >= 2, info
+        batch.close()
+    torch.cuda.synchronize()
