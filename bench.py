@@ -51,9 +51,10 @@ def run_mode(scene, mode, warmup, steps, n_rays, torch, instrumented):
     coherent = mode == "coherent"
     # per-frame object transforms, resident on the GPU before timing starts
     xfs = torch.tensor(np.stack([scene.transforms(f) for f in range(nf)]), device="cuda")
+    xf_views = [xfs[f] for f in range(nf)]   # one device view per frame, made before timing
 
     def geometry(f):
-        ctx.set_object_transforms(xfs[f % nf])
+        ctx.set_object_transforms(xf_views[f % nf])
         ctx.refit_bvh(force_rebuild=not coherent)
 
     def frame(f):

@@ -309,8 +309,22 @@ dcem_status finish_candidates(dcem_ctx* c);
 
 // Begin the next frame and enqueue its revalidation with the pending refit,
 // once nothing of the last frame remains to be read back (see frame_begun).
+// While the last frame's results are still on their way, the launches go
+// ahead at once, each guarded on the device by that frame's fallback flag:
+// a frame whose candidates must be redone (on the tree it was traced with)
+// turns them into no-ops, and sync_frame restores the host state.  (Not with
+// stage timings on: the events would be recorded over before they are read.)
 void go_ahead(dcem_ctx* c) {
-  if (!c->refit_pending || c->revalidated_ahead || !c->has_frame || !c->cache_valid || !c->counts_current) return;
+  if (!c->refit_pending || c->revalidated_ahead || !c->has_frame || !c->cache_valid) return;
+  const bool early = !c->counts_current;
+  if (early && (!c->copy_pending || c->timing)) return;
+  const uint32_t* skip = early ? c->cnt_dev + kCntFallback : nullptr;
+  if (early && !c->early_ahead) {
+    c->early_ahead = true;
+    c->early_caps = c->cur_caps;
+    c->early_begun = c->frame_begun;
+    c->early_list_clear = c->list_clear;
+  }
   if (!c->frame_begun) {
     c->cur_caps ^= 1;
     c->frame_begun = true;
@@ -320,10 +334,10 @@ void go_ahead(dcem_ctx* c) {
   // earlier early start of this frame appended to it
   const bool fresh = c->list_clear;
   ev_record(c, 0);
-  if (!fresh) launch_frame_begin(c, c->last_los);
+  if (!fresh) launch_frame_begin(c, c->last_los, skip);
   c->refit_pending = false;
   ev_record(c, 6);
-  launch_refit_coherence(c, fresh);
+  launch_refit_coherence(c, fresh, skip);
   c->list_clear = false;
   ev_record(c, 7);
   ev_record(c, 1);
@@ -377,6 +391,21 @@ dcem_status sync_frame(dcem_ctx* c) {
   if (c->has_frame) {
     c->n_caps_host = std::min<int64_t>(c->last_cnt[kCntCaptures], c->cap_capacity);
     c->counts_current = true;
+    if (c->early_ahead) {
+      c->early_ahead = false;
+      if (c->last_cnt[kCntFallback]) {
+        // the launches that went ahead did nothing: the refit is pending again
+        c->cur_caps = c->early_caps;
+        c->frame_begun = c->early_begun;
+        c->list_clear = c->early_list_clear;
+        c->revalidated_ahead = false;
+        c->refit_pending = true;
+      } else if (err) {
+        // they ran, but an error they raised would be cleared with this
+        // frame's: the next frame starts over from its lists
+        c->revalidated_ahead = false;
+      }
+    }
     if (c->last_cnt[kCntFallback] && !err) {
       // more captures than the small path holds: redo the candidates exactly
       const uint32_t zero = 0;
@@ -518,6 +547,7 @@ dcem_status dcem_scene_upload(dcem_ctx* c, const dcem_scene_desc* s) {
   c->refit_pending = false;   // the new scene is built from scratch
   c->frame_begun = false;
   c->revalidated_ahead = false;
+  c->early_ahead = false;
   std::vector<float> V;
   std::vector<int32_t> T, TF, FM, FO;
   std::vector<double> M;

@@ -362,7 +362,10 @@ __global__ void k_cross_parent(const Node* __restrict__ nodes, const int32_t* __
 }
 
 __global__ __launch_bounds__(kRefitBlock) void k_refit(RefitArgs a) { refit_block(a, blockIdx.x, gridDim.x); }
-__global__ __launch_bounds__(kRefitBlock) void k_refit_cross(RefitArgs a, int n_rb) { refit_cross_block(a, n_rb); }
+__global__ __launch_bounds__(kRefitBlock) void k_refit_cross(RefitArgs a, int n_rb) {
+  if (a.skip && *a.skip) return;   // uniform: the word does not change during the launch
+  refit_cross_block(a, n_rb);
+}
 
 
 
@@ -737,6 +740,7 @@ RefitArgs make_refit_args(dcem_ctx* c, bool wide, double* sah_out) {
   const int ni = c->n_internal;
   int32_t* cross = ptr<int32_t>(c->cross);
   RefitArgs a;
+  a.skip = nullptr;
   a.V = ptr<float>(c->vertices);
   a.T = ptr<int32_t>(c->tris);
   a.tri_face = ptr<int32_t>(c->tri_face);

@@ -145,6 +145,14 @@ struct dcem_ctx {
   // configuration then starts at the re-trace.
   bool frame_begun = false;
   bool revalidated_ahead = false;
+  // the going-ahead launch was enqueued before the last frame's results were
+  // read, guarded by that frame's fallback flag (it did nothing if that frame
+  // needs its candidates redone)
+  bool early_ahead = false;
+  // host state before the first early launch, restored when it did nothing
+  int early_caps = 0;
+  bool early_begun = false;
+  bool early_list_clear = false;
   bool list_clear = false;   // kCntList of the current frame block is zero (its last frame's reduction ran)
   bool last_los = true;
   hipEvent_t ev_copy = nullptr;   // the last traced frame's results have reached host_block
@@ -359,10 +367,11 @@ void launch_coherence(dcem_ctx* c);
 // Coherent frame with moved receivers: captures of the kept segments of every
 // cached ray against the current receivers (after the revalidation pass).
 void launch_recapture(dcem_ctx* c);
-// The pending refit of the 4-wide tree and the revalidation pass in one launch.
-void launch_refit_coherence(dcem_ctx* c, bool begin);
+// The pending refit of the 4-wide tree and the revalidation pass in one launch
+// (skip, nullable: a device word that, nonzero at launch, cancels the launch).
+void launch_refit_coherence(dcem_ctx* c, bool begin, const uint32_t* skip = nullptr);
 // Clear the frame counters and seed the capture list with the LoS candidates.
-void launch_frame_begin(dcem_ctx* c, bool los);
+void launch_frame_begin(dcem_ctx* c, bool los, const uint32_t* skip = nullptr);
 hipError_t build_ray_order(dcem_ctx* c);
 // Buffers a frame's trace needs (the per-thread stack's spill space), sized
 // before anything of the frame is enqueued.

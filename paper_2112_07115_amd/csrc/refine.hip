@@ -66,7 +66,8 @@ __device__ inline uint32_t capture_key(const Capture& c, const int32_t* __restri
   const uint32_t tpair = c.pair_order >> 4, order = c.pair_order & 15u;
   const uint32_t src = tpair / (uint32_t)L.n_tgt, tgt = tpair - src * (uint32_t)L.n_tgt;
   const uint32_t tx = L.backward ? tgt : src, rx = L.backward ? src : tgt;
-  const uint32_t tset = order > 0 ? L.branch_set[(c.work / (uint64_t)L.n_rays) % (uint32_t)L.n_branch] : 0u;
+  const uint32_t tset =
+      (order > 0 && L.n_branch > 1) ? L.branch_set[(c.work / (uint64_t)L.n_rays) % (uint32_t)L.n_branch] : 0u;
   for (int k = 0; k < 8; ++k) w[k] = 0;
   for (int j = 0; j < L.K; ++j) {
     uint32_t f = 0;
@@ -659,31 +660,29 @@ __device__ bool group_occluded(const RefineArgs& a, D3 p, D3 q, int fa, int fb, 
   return false;
 }
 
-// Image-method geometry of a candidate (Sec. III step 3): the images of T
-// through the planes of interactions 1..j in turn (an interaction that
-// transmits, bit j - 1 of tmask, leaves the image where it is: the ray goes
-// straight on), then the interaction points walked back from R towards the
-// images, each on its plane.  plane(j) gives interaction j + 1's plane;
+// The image of point im in plane pl (unit normal xyz, offset w), with
+// contraction off: the refinement and the visited-series expansion both
+// compute images with this function.
+__device__ inline D3 reflect_image(D3 im, double4 pl) {
+#pragma clang fp contract(off)
+  const double h = 2.0 * ((im.x * pl.x + im.y * pl.y + im.z * pl.z) - pl.w);
+  return D3{im.x - h * pl.x, im.y - h * pl.y, im.z - h * pl.z};
+}
+
+// Image-method geometry of a candidate (Sec. III step 3): image(j) gives the
+// image of T through the planes of interactions 1..j in turn (reflect_image
+// for each reflection; a transmission leaves the image where it is: the ray
+// goes straight on), plane(j) interaction j + 1's plane; the interaction
+// points are walked back from R towards the images, each on its plane, and
 // visit(j, P) receives point j (j = order..1) and may stop the walk by
 // returning false; d receives the distance from R to the last image (the path
 // length).  False when a walk is parallel to its plane, a point falls outside
-// its open segment, or visit stops.  An image is recomputed from T when the
-// walk needs it (no arrays), with contraction off, so the refinement and the
-// visited-series expansion, which share this code, take the same decisions.
-template <class Plane, class Visit>
-__device__ inline bool image_walk(D3 T, D3 R, int order, uint32_t tmask, Plane plane, Visit visit, double& d) {
+// its open segment, or visit stops.  Contraction is off, so the refinement
+// and the visited-series expansion, which share this code, take the same
+// decisions.
+template <class Image, class Plane, class Visit>
+__device__ inline bool image_walk(D3 R, int order, Image image, Plane plane, Visit visit, double& d) {
 #pragma clang fp contract(off)
-  auto image = [&](int j) {
-    D3 im = T;
-    for (int q = 1; q <= j; ++q) {
-      if ((tmask >> (q - 1)) & 1u) continue;
-      const double4 pl = plane(q - 1);
-      const D3 n = {pl.x, pl.y, pl.z};
-      const double h = 2.0 * ((im.x * n.x + im.y * n.y + im.z * n.z) - pl.w);
-      im = D3{im.x - h * n.x, im.y - h * n.y, im.z - h * n.z};
-    }
-    return im;
-  };
   const D3 last = image(order);
   const D3 rl = {R.x - last.x, R.y - last.y, R.z - last.z};
   d = sqrt(rl.x * rl.x + rl.y * rl.y + rl.z * rl.z);
@@ -729,6 +728,7 @@ constexpr int kRefineMaxThreads = kWave * (kMaxK + 2);
 
 __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ double sP[(kMaxK + 2) * 3];      // transmitter, reflection points, receiver
+  __shared__ D3 simg[kMaxK + 1];             // images of the transmitter
   __shared__ int sfaces[kMaxK];              // face ids (transmission flag cleared)
   __shared__ uint32_t stmask;                 // bit j - 1: interaction j transmits
   __shared__ int sorder, sok, sfail;
@@ -763,8 +763,15 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       stmask = (uint32_t)tm;
       sP[0] = T.x; sP[1] = T.y; sP[2] = T.z;
       sP[3 * (order0 + 1)] = R.x; sP[3 * (order0 + 1) + 1] = R.y; sP[3 * (order0 + 1) + 2] = R.z;
+      // the images, forward once (reflect_image), kept in LDS for the walk
+      D3 im = T;
+      simg[0] = im;
+      for (int j = 1; j <= order0; ++j) {
+        if (!((tm >> (j - 1)) & 1ull)) im = reflect_image(im, spl[j - 1]);
+        simg[j] = im;
+      }
       bool ok = image_walk(
-          T, R, order0, (uint32_t)tm, [&](int j) { return spl[j]; },
+          R, order0, [&](int j) { return simg[j]; }, [&](int j) { return spl[j]; },
           [&](int j, D3 q) {
             sP[3 * j] = q.x; sP[3 * j + 1] = q.y; sP[3 * j + 2] = q.z;
             return true;
@@ -1128,8 +1135,17 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs e, int write) {
       }
       double d;
       // each point is tested against its face as soon as the walk reaches it
+      auto plane = [&](int j) { return e.ra.plane[fs[j] & kFaceMask]; };
+      // images recomputed when the walk needs them (no arrays), with the
+      // refinement's reflect_image
+      auto image = [&](int j) {
+        D3 im = T;
+        for (int q = 1; q <= j; ++q)
+          if (!((tmask >> (q - 1)) & 1u)) im = reflect_image(im, plane(q - 1));
+        return im;
+      };
       keep = !opaque && image_walk(
-                            T, R, order, tmask, [&](int j) { return e.ra.plane[fs[j] & kFaceMask]; },
+                            R, order, image, plane,
                             [&](int j, D3 q) {
                               const int f = fs[j - 1] & kFaceMask;
                               const double4 pl = e.ra.plane[f];

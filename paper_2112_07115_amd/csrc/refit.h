@@ -38,6 +38,7 @@ struct RefitArgs {
   int nf;
   double4* plane;             // per face: unit normal and offset
   bool cross_kernel;          // the cross nodes and the SAH sum are finished by k_refit_cross (large trees)
+  const uint32_t* skip;       // nullable: a nonzero word here (read at launch) makes the launch do nothing
 };
 
 // Trees with more leaves than this finish their cross nodes in a launch of

@@ -1018,6 +1018,10 @@ struct FrameBegin {
   int n_los;
   int64_t cap_capacity;
   uint32_t* err;
+  // nullable: a nonzero word here (read at launch; the last frame's candidate
+  // fallback flag) makes the launch do nothing: that frame's candidates must
+  // be redone on the tree it was traced with before the next frame begins
+  const uint32_t* skip;
 };
 
 __device__ inline void frame_begin_part(const FrameBegin& f, int t, int nt, bool keep_list) {
@@ -1035,6 +1039,7 @@ __device__ inline void frame_begin_part(const FrameBegin& f, int t, int nt, bool
 }
 
 __global__ void k_frame_begin(FrameBegin f) {
+  if (f.skip && *f.skip) return;
   frame_begin_part(f, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, false);
 }
 
@@ -1278,6 +1283,10 @@ __global__ __launch_bounds__(kCohBlock) void k_coherence(CohArgs a) { coherence_
 // frame's reduction zeroed).
 __global__ __launch_bounds__(kRefitBlock) void k_refit_coherence(RefitArgs ra, CohArgs ca, int n_rb, FrameBegin fb,
                                                                  int begin) {
+  // with a skip word set (the last frame needs its candidates redone) nothing
+  // runs; the word only turns from nonzero to zero inside this launch (the
+  // frame start clears it) if it was zero already, so every block agrees
+  if (fb.skip && *fb.skip) return;
   if ((int)blockIdx.x < n_rb) {
     refit_block(ra, blockIdx.x, n_rb);
   } else {
@@ -1483,11 +1492,12 @@ hipError_t prepare_trace(dcem_ctx* c) {
 
 FrameBegin frame_begin_args(dcem_ctx* c, bool los) {
   return FrameBegin{c->cnt_dev, ptr<Capture>(c->caps[c->cur_caps]), los ? c->n_src * c->n_tgt : 0, c->cap_capacity,
-                    c->err_dev};
+                    c->err_dev, nullptr};
 }
 
-void launch_frame_begin(dcem_ctx* c, bool los) {
-  const FrameBegin f = frame_begin_args(c, los);
+void launch_frame_begin(dcem_ctx* c, bool los, const uint32_t* skip) {
+  FrameBegin f = frame_begin_args(c, los);
+  f.skip = skip;
   hipLaunchKernelGGL(k_frame_begin, dim3((unsigned)std::max(1, (f.n_los + 255) / 256)), dim3(256), 0, c->stream, f);
 }
 
@@ -1532,7 +1542,7 @@ void launch_coherence(dcem_ctx* c) {
                      a);
 }
 
-void launch_refit_coherence(dcem_ctx* c, bool begin) {
+void launch_refit_coherence(dcem_ctx* c, bool begin, const uint32_t* skip) {
   CohArgs ca = coherence_args(c);
   ca.list_cap = 2 * kCohList;
   const int n_rb = refit_blocks(c);
@@ -1542,10 +1552,12 @@ void launch_refit_coherence(dcem_ctx* c, bool begin) {
   const int cb = (int)std::max<int64_t>(
       std::min<int64_t>((ca.n_work + kRefitBlock - 1) / kRefitBlock, std::max(cu_count(c) - n_rb, 1)),
       (ca.n_work + ca.list_cap - 1) / ca.list_cap);
-  const RefitArgs ra = make_refit_args(c, true, c->sah_dev + 1);
+  RefitArgs ra = make_refit_args(c, true, c->sah_dev + 1);
+  ra.skip = skip;
+  FrameBegin fb = frame_begin_args(c, c->last_los);
+  fb.skip = skip;
   hipLaunchKernelGGL(k_refit_coherence, dim3(n_rb + std::max(cb, 1)), dim3(kRefitBlock),
-                     coherence_lds(c, ca.list_cap), c->stream, ra, ca, n_rb, frame_begin_args(c, c->last_los),
-                     begin ? 1 : 0);
+                     coherence_lds(c, ca.list_cap), c->stream, ra, ca, n_rb, fb, begin ? 1 : 0);
   if (ra.cross_kernel) launch_refit_cross(c, ra, n_rb);
 }
 
