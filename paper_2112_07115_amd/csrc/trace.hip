@@ -39,13 +39,14 @@ __device__ inline void setup_ray(Ray& r) {
   int ky = kx == 2 ? 0 : kx + 1;
   if (comp(r.d, kz) < 0.0f) { int t = kx; kx = ky; ky = t; }
   r.kx = kx; r.ky = ky; r.kz = kz;
-  const float dz = comp(r.d, kz);
-  r.sx = __fdiv_rn(comp(r.d, kx), dz);
-  r.sy = __fdiv_rn(comp(r.d, ky), dz);
-  r.sz = __fdiv_rn(1.0f, dz);
   const float tiny = 1e-30f;
   r.inv = make_float3(__fdiv_rn(1.0f, r.d.x != 0.0f ? r.d.x : tiny), __fdiv_rn(1.0f, r.d.y != 0.0f ? r.d.y : tiny),
                       __fdiv_rn(1.0f, r.d.z != 0.0f ? r.d.z : tiny));
+  // shear constants from the reciprocal of the dominant component (never
+  // zero for a nonzero direction): one division per axis in all
+  r.sz = comp(r.inv, kz);
+  r.sx = comp(r.d, kx) * r.sz;
+  r.sy = comp(r.d, ky) * r.sz;
 }
 
 // Watertight ray-triangle intersection (Woop, Benthin and Wald, JCGT 2013):
@@ -299,7 +300,7 @@ struct TraceArgs {
 // Coherent frames: keep each capture of the previous frame made before its
 // ray's first re-traced segment (those after it are found again by the
 // re-trace).  Appended with one atomic per wavefront; run by every block of
-// the trace kernel before it traces.
+// the trace kernel once its wavefronts have traced their rays.
 __device__ void keep_previous_captures(const TraceArgs& a, bool& cap_over) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -349,10 +350,10 @@ __device__ inline void reflect_ray(Ray& r, float t, const float4& p0, const floa
   const float ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
   const float fx = p2.x - p0.x, fy = p2.y - p0.y, fz = p2.z - p0.z;
   float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-  const float nl = __fsqrt_rn(nx * nx + ny * ny + nz * nz);
-  nx = __fdiv_rn(nx, nl);
-  ny = __fdiv_rn(ny, nl);
-  nz = __fdiv_rn(nz, nl);
+  const float rl = __fdiv_rn(1.0f, __fsqrt_rn(nx * nx + ny * ny + nz * nz));
+  nx = nx * rl;
+  ny = ny * rl;
+  nz = nz * rl;
   const float dn2 = 2.0f * (r.d.x * nx + r.d.y * ny + r.d.z * nz);
   r.o = make_float3(__fmaf_rn(t, r.d.x, r.o.x), __fmaf_rn(t, r.d.y, r.o.y), __fmaf_rn(t, r.d.z, r.o.z));
   r.d = make_float3(r.d.x - dn2 * nx, r.d.y - dn2 * ny, r.d.z - dn2 * nz);
@@ -545,7 +546,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
   const uint32_t n_work = a.work_list ? a.counters[kCntList] : (uint32_t)a.n_work;
   if (a.work_list && blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
   ItemCounts ic;
-  keep_previous_captures(a, ic.cap_over);
   while (true) {
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&a.counters[kCntQueue], (uint32_t)kWave);
@@ -554,6 +554,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     const uint32_t wi = base + lane;
     if (wi < n_work) trace_item(a, wi, top, n_top, n4, stack, ic);
   }
+  keep_previous_captures(a, ic.cap_over);
   flush_counts(a, ic);
 }
 
@@ -746,7 +747,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
-  keep_previous_captures(a, cap_over);
 
   // this group's ray (equal on its lanes)
   bool busy = false;
@@ -936,9 +936,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
         c0 = rx_col[max(rx_column(bx0) - 1, 0)];
         c1 = rx_col[min(rx_column(bx1) + 1, kRxCols - 1) + 1];
       }
-      for (int c = c0 + gl; c < c1; c += kRayLanes) {
-        const float4 q = rx_lds ? rxs[c] : a.rx_cols[c];
-        if (q.x < bx0 || q.x > bx1 || q.y < by0 || q.y > by1) continue;
+      auto test_rx = [&](const float4 q) {
+        if (q.x < bx0 || q.x > bx1 || q.y < by0 || q.y > by1) return;
         if (captured(r, tend, dd, q.x, q.y, q.z, a.r2)) {
           Capture cp;
           cp.work = work;
@@ -952,6 +951,13 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
             else cap_over = true;
           }
         }
+      };
+      // two loops (the condition is uniform): a load that may read either
+      // LDS or device memory would wait for this segment's log stores
+      if (rx_lds) {
+        for (int c = c0 + gl; c < c1; c += kRayLanes) test_rx(rxs[c]);
+      } else {
+        for (int c = c0 + gl; c < c1; c += kRayLanes) test_rx(a.rx_cols[c]);
       }
     }
     ++k;
@@ -984,6 +990,9 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     }
     start_ray(next);
   }
+  // the previous frame's captures that stay (after this wavefront's rays:
+  // off the path of the longest ones)
+  keep_previous_captures(a, cap_over);
   // append the block's staged captures with one atomic
   __syncthreads();
   const uint32_t ns = min(scap_n, (uint32_t)kCapStage);
