@@ -107,20 +107,24 @@ __device__ inline double box_area(const float* lo, const float* hi) {
   return 2.0 * (dx * dy + dy * dz + dz * dx);
 }
 
-// Unit normal n and offset n . a of the plane of face f (FP64, from the
-// face's reference triangle a, b, c: n = (b - a) x (c - a) normalised).
-__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
-                                  double4* __restrict__ plane, int f) {
-  const int ia = T[3 * t], ib = T[3 * t + 1], ic = T[3 * t + 2];
-  const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
-  const double ux = V[3 * ib] - ax, uy = V[3 * ib + 1] - ay, uz = V[3 * ib + 2] - az;
-  const double vx = V[3 * ic] - ax, vy = V[3 * ic + 1] - ay, vz = V[3 * ic + 2] - az;
+// Unit normal n and offset n . a of the plane through a, b, c (FP64:
+// n = (b - a) x (c - a) normalised).
+__device__ inline double4 plane_of(const float3& a, const float3& b, const float3& c) {
+  const double ax = a.x, ay = a.y, az = a.z;
+  const double ux = (double)b.x - ax, uy = (double)b.y - ay, uz = (double)b.z - az;
+  const double vx = (double)c.x - ax, vy = (double)c.y - ay, vz = (double)c.z - az;
   double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
   const double l = sqrt(nx * nx + ny * ny + nz * nz);
   nx /= l;
   ny /= l;
   nz /= l;
-  plane[f] = make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
+  return make_double4(nx, ny, nz, nx * ax + ny * ay + nz * az);
+}
+
+// The plane of face f, from the face's reference triangle t.
+__device__ inline void face_plane(const float* __restrict__ V, const int32_t* __restrict__ T, int t,
+                                  double4* __restrict__ plane, int f) {
+  plane[f] = plane_of(load_v(V, T[3 * t]), load_v(V, T[3 * t + 1]), load_v(V, T[3 * t + 2]));
 }
 
 
@@ -280,26 +284,53 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
   __shared__ int2 lkid[kRefitBlock];     // child entries (>= 0: internal)
   __shared__ double red[kRefitBlock / kWave];
   __shared__ bool last;
-  for (int f = rb * kRefitBlock + threadIdx.x; f < a.nf; f += (unsigned)n_rb * kRefitBlock)
-    face_plane(a.V, a.T, a.face_ref_tri[f], a.plane, f);
   const int b0 = rb * kRefitBlock;
   const int tid = threadIdx.x;
   const uint32_t n_cross = a.info[2];
   const bool two_phase = a.cross_kernel || n_cross <= (uint32_t)kMaxCross;   // cross slots listed
-  {
-    const int node = b0 + tid;
-    lcnt[tid] = 0;
-    const bool ok = node < a.n_internal;
-    lpar[tid] = ok ? a.nodes[node].c.z : -1;
-    lnode[tid] = ok && a.cross_index[node] < 0;   // block-local
-    lkid[tid] = ok ? make_int2(a.nodes[node].c.x, a.nodes[node].c.y) : make_int2(-1, -1);
-    if (a.wide && ok) lslot4[tid] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
+  // Thread tid of the block holds node, leaf and face b0 + tid.  Their three
+  // dependent gathers (index, vertex indices, vertices) are issued together,
+  // so the climb starts three memory round trips after the launch instead of
+  // seven.
+  const int node = b0 + tid, i = b0 + tid, f = b0 + tid;
+  const bool ok = node < a.n_internal, has_leaf = i < a.n, has_face = f < a.nf;
+  const int lt = has_leaf ? a.leaf_tri[i] : 0;
+  const int ls = has_leaf && a.wide ? a.leaf_slot[i] : 0;
+  const int ft = has_face ? a.face_ref_tri[f] : 0;
+  const int4 nc = ok ? a.nodes[node].c : make_int4(-1, -1, -1, 0);
+  const bool local_node = ok && a.cross_index[node] < 0;
+  const int2 s4 = a.wide && ok ? make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]) : make_int2(-1, -1);
+  int lv[3] = {0, 0, 0}, fv[3] = {0, 0, 0}, lface = 0;
+  if (has_leaf) {
+    for (int k = 0; k < 3; ++k) lv[k] = a.T[3 * lt + k];
+    lface = a.tri_face[lt];
   }
+  if (has_face)
+    for (int k = 0; k < 3; ++k) fv[k] = a.T[3 * ft + k];
+  float3 lp[3], fp[3];
+  int lmoving = 0;
+  for (int k = 0; k < 3; ++k) {
+    lp[k] = has_leaf ? load_v(a.V, lv[k]) : make_float3(0.f, 0.f, 0.f);
+    fp[k] = has_face ? load_v(a.V, fv[k]) : make_float3(0.f, 0.f, 0.f);
+  }
+  if (has_leaf) lmoving = a.face_object[lface] >= 0 ? 1 : 0;
+  lcnt[tid] = 0;
+  lpar[tid] = ok ? nc.z : -1;
+  lnode[tid] = local_node;   // block-local
+  lkid[tid] = ok ? make_int2(nc.x, nc.y) : make_int2(-1, -1);
+  if (a.wide && ok) lslot4[tid] = s4;
+  if (has_face) a.plane[f] = plane_of(fp[0], fp[1], fp[2]);
+  // faces beyond one per thread (none when the refit has a thread per
+  // triangle: every face holds a triangle)
+  for (int g = f + n_rb * kRefitBlock; g < a.nf; g += n_rb * kRefitBlock)
+    face_plane(a.V, a.T, a.face_ref_tri[g], a.plane, g);
   __syncthreads();
-  const int i = b0 + tid;
-  if (i < a.n) {
-    const Leaf L = leaf_record(a.V, a.T, a.tri_face, a.face_object, a.leaf_tri[i]);
-    if (a.wide) a.tri4[a.leaf_slot[i]] = L;
+  if (has_leaf) {
+    Leaf L;
+    L.v0 = make_float4(lp[0].x, lp[0].y, lp[0].z, __int_as_float(lt));
+    L.v1 = make_float4(lp[1].x, lp[1].y, lp[1].z, __int_as_float(lface));
+    L.v2 = make_float4(lp[2].x, lp[2].y, lp[2].z, __int_as_float(lmoving));
+    if (a.wide) a.tri4[ls] = L;
     float lo[3] = {fminf(L.v0.x, fminf(L.v1.x, L.v2.x)) - a.pad, fminf(L.v0.y, fminf(L.v1.y, L.v2.y)) - a.pad,
                    fminf(L.v0.z, fminf(L.v1.z, L.v2.z)) - a.pad};
     float hi[3] = {fmaxf(L.v0.x, fmaxf(L.v1.x, L.v2.x)) + a.pad, fmaxf(L.v0.y, fmaxf(L.v1.y, L.v2.y)) + a.pad,

@@ -1154,12 +1154,18 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   // blocks stride over the rays (the grid above is built once per block)
-  for (int base0 = cb * nth; base0 < n_work; base0 += n_cb * nth) {
-    const int i = base0 + threadIdx.x;
+  // each thread checks rays i, i + stride, ...: the next ray's state byte is
+  // loaded while the current ray's segments are, so a ray costs one round trip
+  const int64_t stride = (int64_t)n_cb * nth;
+  uint32_t st_next = (int64_t)cb * nth + threadIdx.x < n_work ? ray_state[cb * nth + threadIdx.x] : 0u;
+  for (int64_t base0 = (int64_t)cb * nth; base0 < n_work; base0 += stride) {
+    const int64_t i = base0 + threadIdx.x;
     int first = 255;
     const uint32_t w = (uint32_t)i;
+    const uint32_t st_cur = st_next;
+    if (i + stride < n_work) st_next = ray_state[i + stride];
     if (i < n_work) {
-      const uint32_t st = ray_state[w];
+      const uint32_t st = st_cur;
       const int nseg = (int)(st & 0x0fu);
       const bool moving_hit = (st & 0x80u) != 0;
       // does the cached segment (o, d) meet a moving object's box now?
