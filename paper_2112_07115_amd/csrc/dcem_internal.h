@@ -348,10 +348,13 @@ void launch_collapse(dcem_ctx* c);
 
 // ---- radix sort (sort.hip)
 // Stable LSD sort of n items by `bits` low bits of a multi-word key stored
-// word-major ([W][n], word W-1 least significant), producing a permutation.
-// The item count is min(*n_dev, n_max), read on the device.
+// word-major ([W][stride], word W-1 least significant; stride -1: n_max),
+// producing a permutation.  The item count is min(*n_dev, n_max), read on the
+// device.  Only the low `low_bits` bits of word W-1 are sorted on (the others
+// are zero in every key).
 hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, const uint32_t* n_dev,
-                           int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s);
+                           int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s, int64_t stride = -1,
+                           int low_bits = 32);
 // The sort's histogram space for up to n_max items (sized before a frame that
 // a graph may capture).
 hipError_t prepare_sort(dcem_ctx* c, int64_t n_max);

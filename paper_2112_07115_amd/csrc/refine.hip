@@ -916,15 +916,52 @@ __global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict_
   // the series of work item i: its interactions d = d0..depth (a branch
   // adds those through its last transmission; shorter ones are its parent's)
   int d0 = 1, depth = 0;
-  uint32_t tset = 0;
+  uint32_t tset = 0, src = 0;
   if (i < (uint64_t)n_work) {
     depth = (int)(ray_state[i] & 0x0fu) - 1;   // interactions performed: segments - 1
     tset = S.branch_set[(i / (uint64_t)S.n_rays) % (uint32_t)S.n_branch];
     if (tset) d0 = 32 - __builtin_clz(tset);   // last transmission + 1
+    src = (uint32_t)(i / ((uint64_t)S.n_rays * S.n_branch));
   }
-  const int n_new = depth >= d0 ? depth - d0 + 1 : 0;
+  // interaction fields in bounce order (face, transmit bit)
+  uint32_t fld[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j)
+    fld[j] = j < depth ? ((uint32_t)face_log[(size_t)j * n_work + i] << S.tb) | ((tset >> j) & (uint32_t)S.tb) : 0u;
+  // Neighbouring positions are rays of neighbouring directions and mostly
+  // visit the same series: within a wavefront, a run of consecutive items
+  // with the same series of length d enters it once, with the run's lowest
+  // ray id (the sort below keeps the lowest over all entries, so the result
+  // is the same).
+  const uint32_t rid = i < (uint64_t)n_work ? ray_of(i, S) : kNoRay;
+  const uint32_t psrc = __shfl_up(src, 1);
+  const int pdepth = __shfl_up(depth, 1), pd0 = __shfl_up(d0, 1);
+  uint32_t enter = 0;        // bit d - 1: this item enters its series of length d
+  uint32_t run_min[kMaxK];   // the lowest ray id of that run
+  bool eq = lane > 0 && psrc == src;
+#pragma unroll
+  for (int d = 1; d <= kMaxK; ++d) {
+    run_min[d - 1] = kNoRay;
+    if (d > S.K) continue;   // uniform
+    eq = eq && __shfl_up(fld[d - 1], 1) == fld[d - 1];
+    const bool has = d >= d0 && d <= depth;
+    const bool same = has && eq && d >= pd0 && d <= pdepth;
+    // runs: each starts at an item that does not continue its predecessor's
+    const uint64_t starts = __ballot(!same);
+    const uint64_t above = lane == kWave - 1 ? 0ull : starts & ~((2ull << lane) - 1ull);
+    const int last = above ? __ffsll((unsigned long long)above) - 2 : kWave - 1;   // this lane's run ends here
+    uint32_t m = has ? rid : kNoRay;
+    for (int step = 1; step < kWave; step <<= 1) {   // suffix minimum within the run
+      const uint32_t o = __shfl_down(m, step);
+      if (lane + step <= last) m = min(m, o);
+    }
+    if (has && !same) {
+      enter |= 1u << (d - 1);
+      run_min[d - 1] = m;
+    }
+  }
   const bool empty_series = los && i < (uint32_t)n_src;
-  const int n_items = n_new + (empty_series ? 1 : 0);
+  const int n_items = __popc(enter) + (empty_series ? 1 : 0);
   // one append per block: wave scans, then the wave totals in LDS
   __shared__ uint32_t wsum[256 / kWave], bbase;
   const int wave = threadIdx.x / kWave;
@@ -946,23 +983,18 @@ __global__ __launch_bounds__(256) void k_series_items(const int32_t* __restrict_
   }
   __syncthreads();
   uint32_t slot = bbase + wsum[wave] + (uint32_t)(incl - n_items);
-  if (n_new > 0) {
-    const uint32_t src = (uint32_t)(i / ((uint64_t)S.n_rays * S.n_branch));
-    const uint32_t rid = ray_of(i, S);
-    for (int d = d0; d <= depth; ++d, ++slot) {
-      if (slot >= cap) continue;   // the host sizes cap for every item
+#pragma unroll
+  for (int d = 1; d <= kMaxK; ++d) {
+    if (!((enter >> (d - 1)) & 1u)) continue;
+    if (slot < cap) {   // the host sizes cap for every item
       uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int j = 0; j < d; ++j) {
-        const int bounce = S.backward ? d - 1 - j : j;
-        const uint32_t f = ((uint32_t)face_log[(size_t)bounce * n_work + i] << S.tb) |
-                           ((tset >> bounce) & (uint32_t)S.tb);
-        put_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf, f);
-      }
+      for (int j = 0; j < d; ++j) put_bits(w, S.W, (S.K - 1 - j) * S.bf, S.bf, fld[S.backward ? d - 1 - j : j]);
       put_bits(w, S.W, S.K * S.bf, 4, (uint32_t)d);
       put_bits(w, S.W, S.K * S.bf + 4, S.bt, src);
       for (int k = 0; k < S.W; ++k) keys[k * stride + slot] = w[k];
-      keys[S.W * stride + slot] = rid;
+      keys[S.W * stride + slot] = run_min[d - 1];
     }
+    ++slot;
   }
   if (empty_series && slot < cap) {
     uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1033,17 +1065,44 @@ __global__ __launch_bounds__(256) void k_face_boxes(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ face_slots,
                                                     const Leaf* __restrict__ tri4, int64_t nt, uint32_t* __restrict__ box) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= nt) return;
-  const int f = tri_face[face_tris[k]];
-  const Leaf L = tri4[face_slots[k]];
-  const float4 v[3] = {L.v0, L.v1, L.v2};
-  for (int q = 0; q < 3; ++q) {
-    atomicMin(&box[6 * f + 0], ordered_u32(v[q].x));
-    atomicMin(&box[6 * f + 1], ordered_u32(v[q].y));
-    atomicMin(&box[6 * f + 2], ordered_u32(v[q].z));
-    atomicMax(&box[6 * f + 3], ordered_u32(v[q].x));
-    atomicMax(&box[6 * f + 4], ordered_u32(v[q].y));
-    atomicMax(&box[6 * f + 5], ordered_u32(v[q].z));
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool ok = k < nt;
+  int f = -1;
+  uint32_t b[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};   // ordered bits: lo x y z, hi x y z
+  if (ok) {
+    f = tri_face[face_tris[k]];
+    const Leaf L = tri4[face_slots[k]];
+    const float4 v[3] = {L.v0, L.v1, L.v2};
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t o[3] = {ordered_u32(v[q].x), ordered_u32(v[q].y), ordered_u32(v[q].z)};
+      for (int a = 0; a < 3; ++a) {
+        b[a] = min(b[a], o[a]);
+        b[3 + a] = max(b[3 + a], o[a]);
+      }
+    }
+  }
+  // a face's triangles are consecutive: each run of one face in the
+  // wavefront is reduced first and enters the face's box with one set of
+  // atomics (a face of many triangles would otherwise serialise on them)
+  const bool head = ok && (lane == 0 || __shfl_up(f, 1) != f);
+  const uint64_t starts = __ballot(!ok || head);
+  const uint64_t above = lane == kWave - 1 ? 0ull : starts & ~((2ull << lane) - 1ull);
+  const int last = above ? __ffsll((unsigned long long)above) - 2 : kWave - 1;
+  for (int step = 1; step < kWave; step <<= 1) {
+    uint32_t o[6];
+    for (int a = 0; a < 6; ++a) o[a] = __shfl_down(b[a], step);
+    if (lane + step <= last) {
+      for (int a = 0; a < 3; ++a) {
+        b[a] = min(b[a], o[a]);
+        b[3 + a] = max(b[3 + a], o[3 + a]);
+      }
+    }
+  }
+  if (head) {
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&box[6 * f + a], b[a]);
+      atomicMax(&box[6 * f + 3 + a], b[3 + a]);
+    }
   }
 }
 
@@ -1661,7 +1720,10 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   if (n_items == 0) return hipSuccess;
   n_items = std::min<uint32_t>(n_items, (uint32_t)cap);
-  if ((e = radix_sort_perm(c, keys, Wt, 32 + S.bits, sc, cap, perm, perm + cap, c->stream)) != hipSuccess) return e;
+  // sized by the items there are (read above), on the bits of ray ids there are
+  if ((e = radix_sort_perm(c, keys, Wt, 32 + S.bits, sc, n_items, perm, perm + cap, c->stream, cap,
+                           bits_for(n_work))) != hipSuccess)
+    return e;
   const int nbi = (int)((n_items + 255) / 256);
   hipLaunchKernelGGL(k_heads, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S.W, perm, sc, n_items, head,
                      bcnt);

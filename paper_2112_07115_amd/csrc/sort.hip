@@ -15,7 +15,7 @@ constexpr int kThreads = 256;
 constexpr int kRounds = 8;
 constexpr int kTile = kThreads * kRounds;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kSmallScan = 1 << 16;   // histogram entries the one-block scan takes alone
+constexpr int kSmallScan = 1 << 14;   // histogram entries the one-block scan takes alone
 
 __device__ inline uint32_t digit_of(const uint32_t* __restrict__ keys, int64_t stride, int word, int shift,
                                     uint32_t idx) {
@@ -171,8 +171,10 @@ hipError_t prepare_sort(dcem_ctx* c, int64_t n_max) {
 }
 
 hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, const uint32_t* n_dev,
-                           int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s) {
+                           int64_t n_max, uint32_t* perm, uint32_t* perm_tmp, hipStream_t s, int64_t stride,
+                           int low_bits) {
   if (n_max <= 0) return hipSuccess;
+  if (stride < 0) stride = n_max;
   const int n_tiles = (int)((n_max + kTile - 1) / kTile);
   const int total = 256 * n_tiles;
   // histograms of more entries than the one-block scan handles quickly are
@@ -182,14 +184,19 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
   if (e != hipSuccess) return e;
   uint32_t* hist = ptr<uint32_t>(c->sort_hist);
   uint32_t* sums = hist + total;
-  const int passes = (bits + 7) / 8;
+  // digit passes from the least significant bit, without the digits of word
+  // W-1 above low_bits (zero in every key)
+  auto used = [&](int b) { return b >= 32 || b < low_bits; };
+  int passes = 0;
+  for (int b = 0; b < bits; b += 8) passes += used(b) ? 1 : 0;
   const uint32_t* src = nullptr;
-  for (int p = 0; p < passes; ++p) {
-    const int b = 8 * p;
+  for (int b = 0, p = 0; b < bits; b += 8) {
+    if (!used(b)) continue;
     const int word = W - 1 - b / 32;
     const int shift = b % 32;
     uint32_t* dst = ((passes - 1 - p) % 2 == 0) ? perm : perm_tmp;
-    hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kThreads), 0, s, keys, n_max, word, shift, src, n_dev,
+    ++p;
+    hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kThreads), 0, s, keys, stride, word, shift, src, n_dev,
                        (uint32_t)n_max, hist, n_tiles);
     if (total <= kSmallScan) {
       hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, total);
@@ -198,7 +205,7 @@ hipError_t radix_sort_perm(dcem_ctx* c, const uint32_t* keys, int W, int bits, c
       hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sums, kScanBlocks);
       hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kThreads), 0, s, hist, total, seg, sums);
     }
-    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kThreads), 0, s, keys, n_max, word, shift, src, dst, n_dev,
+    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kThreads), 0, s, keys, stride, word, shift, src, dst, n_dev,
                        (uint32_t)n_max, hist, n_tiles);
     src = dst;
   }
