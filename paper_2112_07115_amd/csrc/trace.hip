@@ -300,11 +300,12 @@ struct TraceArgs {
 // Coherent frames: keep each capture of the previous frame made before its
 // ray's first re-traced segment (those after it are found again by the
 // re-trace).  Appended with one atomic per wavefront; run by every block of
-// the trace kernel once its wavefronts have traced their rays.
-__device__ void keep_previous_captures(const TraceArgs& a, bool& cap_over) {
+// the trace kernel, block b taking the records of position `blk` (b, or the
+// blocks in reverse order when the last blocks of the launch trace nothing).
+__device__ void keep_previous_captures(const TraceArgs& a, bool& cap_over, uint32_t blk) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x - lane); base < a.n_prev; base += stride) {
+  for (uint32_t base = blk * blockDim.x + (threadIdx.x - lane); base < a.n_prev; base += stride) {
     const uint32_t i = base + lane;
     bool keep = false;
     Capture c{};
@@ -554,7 +555,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceArgs a) {
     const uint32_t wi = base + lane;
     if (wi < n_work) trace_item(a, wi, top, n_top, n4, stack, ic);
   }
-  keep_previous_captures(a, ic.cap_over);
+  keep_previous_captures(a, ic.cap_over, blockIdx.x);
   flush_counts(a, ic);
 }
 
@@ -799,6 +800,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     begin_segment();
   };
 
+  // the previous frame's captures that stay, copied by the last blocks of
+  // the launch first (sized for a quarter more rays than listed, they have
+  // none to trace), so the blocks that trace start at once
+  keep_previous_captures(a, cap_over, gridDim.x - 1 - blockIdx.x);
   // first item by position, then from the shared queue
   start_ray((blockIdx.x * kWaves + threadIdx.x / kWave) * kGroups + g);
   const uint32_t n_static = gridDim.x * kWaves * kGroups;
@@ -990,9 +995,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     }
     start_ray(next);
   }
-  // the previous frame's captures that stay (after this wavefront's rays:
-  // off the path of the longest ones)
-  keep_previous_captures(a, cap_over);
   // append the block's staged captures with one atomic
   __syncthreads();
   const uint32_t ns = min(scap_n, (uint32_t)kCapStage);
