@@ -732,19 +732,28 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   const uint64_t below = (1ull << lane) - 1ull;
   uint32_t* se = stk_e[threadIdx.x / kRayLanes];
   float* st = stk_t[threadIdx.x / kRayLanes];
-  const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
+  // the block's receivers, loaded into registers first (stored to LDS below,
+  // once the group's first ray has been loaded alongside)
   const bool rx_lds = a.n_rx <= kWaveRx;
-  if (rx_lds)
-    for (int i = threadIdx.x; i < a.n_rx; i += kWaveBlock) rxs[i] = a.rx_cols[i];
+  float4 rx_pre[kWaveRx / kWaveBlock];
+#pragma unroll
+  for (int q = 0; q < kWaveRx / kWaveBlock; ++q) {
+    const int i = threadIdx.x + q * kWaveBlock;
+    rx_pre[q] = rx_lds && i < a.n_rx ? a.rx_cols[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   const int32_t* col_start = reinterpret_cast<const int32_t*>(a.rx_cols + a.n_rx);
-  for (int i = threadIdx.x; i <= kRxCols; i += kWaveBlock) rx_col[i] = col_start[i];
-  if (threadIdx.x == 0) scap_n = 0;
-  __syncthreads();
+  static_assert(kRxCols < kWaveBlock, "one column start per thread");
+  const int32_t col_pre = threadIdx.x <= kRxCols ? col_start[threadIdx.x] : 0;
+  const int n4 = a.n4_dev ? (int)a.n4_dev[0] : 0;
+  const uint32_t root = n4 > 0 ? a.n4_dev[1] << kNodeBits : 0u;
+  const uint32_t n_work = a.counters[kCntList];
+  // the group's first list entry, read within the list's capacity (used
+  // only when it is in the list)
+  const uint32_t item0 = (blockIdx.x * kWaves + threadIdx.x / kWave) * kGroups + g;
+  const uint32_t work0 = item0 < (uint64_t)a.n_work ? a.work_list[item0] : 0u;
   auto rx_column = [&](float x) {
     return (int)fminf(fmaxf(floorf((x - a.rx_col_x0) * a.rx_col_scale), 0.0f), (float)(kRxCols - 1));
   };
-  const uint32_t root = n4 > 0 ? a.n4_dev[1] << kNodeBits : 0u;
-  const uint32_t n_work = a.counters[kCntList];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntWork] = n_work;
   uint32_t seg_count = 0, node_count = 0, tri_count = 0;
   bool overflow = false, cap_over = false;
@@ -774,10 +783,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
     }
     ax = mask_axes(r);
   };
-  auto start_ray = [&](uint32_t item) {
+  auto start_ray = [&](uint32_t item, bool first) {
     busy = item < n_work;
     if (!busy) return;
-    work = a.work_list[item];
+    work = first ? work0 : a.work_list[item];
     txi = (uint32_t)(work / (uint64_t)a.n_rays);
     const uint32_t ray = a.ray_order[work - (uint64_t)txi * a.n_rays];
     rid = txi * (uint32_t)a.n_rays + ray;
@@ -805,7 +814,15 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
   // none to trace), so the blocks that trace start at once
   keep_previous_captures(a, cap_over, gridDim.x - 1 - blockIdx.x);
   // first item by position, then from the shared queue
-  start_ray((blockIdx.x * kWaves + threadIdx.x / kWave) * kGroups + g);
+  start_ray(item0, true);
+#pragma unroll
+  for (int q = 0; q < kWaveRx / kWaveBlock; ++q) {
+    const int i = threadIdx.x + q * kWaveBlock;
+    if (rx_lds && i < a.n_rx) rxs[i] = rx_pre[q];
+  }
+  if (threadIdx.x <= kRxCols) rx_col[threadIdx.x] = col_pre;
+  if (threadIdx.x == 0) scap_n = 0;
+  __syncthreads();
   const uint32_t n_static = gridDim.x * kWaves * kGroups;
   while (true) {
     wave_sync();
@@ -993,7 +1010,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_trace_wave(TraceArgs a) {
       if (gl == 0) next = n_static + atomicAdd(&a.counters[kCntQueue], 1u);
       next = __shfl(next, leader);
     }
-    start_ray(next);
+    start_ray(next, false);
   }
   // append the block's staged captures with one atomic
   __syncthreads();
