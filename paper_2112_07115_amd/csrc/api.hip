@@ -276,6 +276,10 @@ hipError_t ensure_frame_block(dcem_ctx* c, int64_t n_pow) {
   if (je != hipSuccess) return je;
   const size_t bytes = kBlockHead + 2 * sizeof(double) * (size_t)n_pow;
   c->list_clear = false;   // the new block's counters start undefined
+  // a revalidation enqueued ahead left its list count and the frame's start
+  // in the old block: the frame starts over in the new one (which the
+  // allocator may well place at the old address)
+  c->revalidated_ahead = false;
   // keep the head (SAH values of the current tree) across a reallocation
   double sah_keep[3] = {1.0, 1.0, 1.0};
   const bool had = c->frame_block.p != nullptr;
@@ -968,7 +972,6 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   HIP_TRY(ensure(c->caps[1], sizeof(Capture) * (size_t)c->cap_capacity), "alloc captures");
   HIP_TRY(ensure(c->work_list, sizeof(uint32_t) * nw), "alloc work list");
   HIP_TRY(ensure(c->invalid_flag, nw), "alloc flags");
-  const void* block_before = c->frame_block.p;
   HIP_TRY(ensure_frame_block(c, (int64_t)p->n_freqs * p->n_tx * p->n_rx), "alloc results");
   // counts of the previous frame (read above): its capture list (reused by a
   // coherent frame), its re-trace count (sizes the persistent grid) and its
@@ -990,9 +993,9 @@ dcem_status frame_setup(dcem_ctx* c, const dcem_trace_params* p, FramePlan& plan
   plan.los = p->los_always != 0;
   plan.seed_los = plan.los && !visited;   // visited discovery: the empty series gives the direct paths
   // a revalidation enqueued ahead (go_ahead) serves a coherent frame with the
-  // same configuration, as long as the result block stayed in place
-  plan.ahead =
-      c->revalidated_ahead && coherent && plan.seed_los == c->last_los && c->frame_block.p == block_before;
+  // same configuration, as long as the result block stayed in place (a
+  // reallocation clears revalidated_ahead)
+  plan.ahead = c->revalidated_ahead && coherent && plan.seed_los == c->last_los;
   if (plan.small) HIP_TRY(prepare_small_candidates(c), "alloc candidates");
   if (plan.hint > 0) HIP_TRY(prepare_sorted_candidates(c, plan.hint), "alloc candidates");
   HIP_TRY(prepare_trace(c), "alloc traversal stack");

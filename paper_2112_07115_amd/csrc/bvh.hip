@@ -99,14 +99,28 @@ __global__ void k_centroid_bounds(const float* __restrict__ V, const int32_t* __
     lo[0] = fminf(lo[0], cx); lo[1] = fminf(lo[1], cy); lo[2] = fminf(lo[2], cz);
     hi[0] = fmaxf(hi[0], cx); hi[1] = fmaxf(hi[1], cy); hi[2] = fmaxf(hi[2], cz);
   }
-  // wave reduction, then one atomic per wave
+  // wave reduction, then block reduction, then one set of atomics per block
+  // (device-scope atomics on six addresses: fewer of them contend less)
   for (int a = 0; a < 3; ++a) {
     for (int off = 32; off > 0; off >>= 1) {
       lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
       hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
     }
   }
-  if ((threadIdx.x & 63) == 0) {
+  __shared__ float wred[6][1024 / 64];
+  const int nw = (int)blockDim.x / 64, wv = (int)threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 3; ++a) {
+      wred[a][wv] = lo[a];
+      wred[3 + a][wv] = hi[a];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], wred[a][w]);
+        hi[a] = fmaxf(hi[a], wred[3 + a][w]);
+      }
     for (int a = 0; a < 3; ++a) {
       atomicMin(&box[a], ordered_bits(lo[a]));
       atomicMax(&box[3 + a], ordered_bits(hi[a]));

@@ -1141,16 +1141,33 @@ __device__ __forceinline__ void coherence_block(const CohArgs& args, int cb, int
   if (grid)
     for (int c = threadIdx.x; c < kCohGrid * kCohGrid * words; c += nth) cell[c] = 0ull;
   __syncthreads();
-  for (int b = threadIdx.x; b < n_obj; b += nth) {
-    for (int a = 0; a < 3; ++a) {
-      const float lo = obj_box[6 * b + a], hi = obj_box[6 * b + 3 + a];
-      if (grid) {
-        bl(a, b) = lo;
-        bl(3 + a, b) = hi;
+  // the objects' extent: each wavefront loads its boxes at once and reduces
+  // them before one set of LDS atomics (atomics with lane-varying values on
+  // one address would be serialised over the lanes)
+  const int lane0 = threadIdx.x & (kWave - 1);
+  for (int w0 = threadIdx.x - lane0; w0 < n_obj; w0 += nth) {   // uniform over the wavefront
+    const int b = w0 + lane0;
+    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
+    if (b < n_obj) {
+      float v[6];
+      for (int k = 0; k < 6; ++k) v[k] = obj_box[6 * b + k];
+      if (grid)
+        for (int k = 0; k < 6; ++k) bl(k, b) = v[k];
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = ordered_bits(v[a]);
+        mx[a] = ordered_bits(v[3 + a]);
       }
-      atomicMin(&ext[a], ordered_bits(lo));
-      atomicMax(&ext[3 + a], ordered_bits(hi));
     }
+    for (int off = kWave / 2; off > 0; off >>= 1)
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = min(mn[a], (uint32_t)__shfl_xor((int)mn[a], off));
+        mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], off));
+      }
+    if (lane0 == 0)
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&ext[a], mn[a]);
+        atomicMax(&ext[3 + a], mx[a]);
+      }
   }
   __syncthreads();
   const float gx0 = from_ordered(ext[0]), gy0 = from_ordered(ext[1]);

@@ -212,7 +212,9 @@ class Context:
     """One dcem context: a device, a HIP stream and the scene, BVH and ray cache on it.
 
     allocator: "torch" (default when torch is loaded) takes every device
-    buffer from torch's caching allocator, None uses hipMalloc."""
+    buffer from torch's caching allocator, None uses hipMalloc; any other
+    object supplies its own dcem_allocator as `.desc` (an AllocatorDesc whose
+    callbacks it keeps alive)."""
 
     def __init__(self, device: int = 0, stream=None, allocator="torch"):
         self.lib = load_library()
@@ -220,7 +222,12 @@ class Context:
         if stream is None:
             # follow torch's current stream when torch is in use; else the null stream
             stream = torch.cuda.current_stream(device).cuda_stream if torch is not None else 0
-        self.allocator = TorchAllocator(device) if (allocator == "torch" and torch is not None) else None
+        if isinstance(allocator, str):
+            if allocator != "torch":
+                raise ValueError("allocator: 'torch', None or an object with .desc")
+            self.allocator = TorchAllocator(device) if torch is not None else None
+        else:
+            self.allocator = allocator
         self.handle = _P()
         st = self.lib.dcem_create(ctypes.byref(self.handle), device, _P(stream or None),
                                   ctypes.byref(self.allocator.desc) if self.allocator else None)

@@ -297,3 +297,70 @@ def test_unread_frame_then_coherent_frame_with_more_frequencies():
         assert coh.stats()["coherent"] == 1
     coh.close()
     full.close()
+
+
+class ReusingAllocator:
+    """A dcem_allocator that hands the most recently freed block back for the
+    next request it fits (blocks rounded up to 1 MiB, taken from torch), so a
+    buffer that grows is reallocated at its old address."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch, self.device = torch, device
+        self.free_list, self.cap, self.held = [], {}, []
+
+        def alloc(nbytes, stream, user):
+            n = int(nbytes)
+            for j in range(len(self.free_list) - 1, -1, -1):
+                p = self.free_list[j]
+                if self.cap[p] >= n:
+                    del self.free_list[j]
+                    return p
+            size = (n + (1 << 20) - 1) >> 20 << 20
+            p = self.torch.cuda.caching_allocator_alloc(size, device=self.device, stream=int(stream or 0))
+            self.cap[p] = size
+            self.held.append(p)
+            return p
+
+        def free(p, nbytes, stream, user):
+            if p in self.cap:
+                self.free_list.append(p)
+
+        self._alloc, self._free = dcem._ALLOC_FN(alloc), dcem._FREE_FN(free)
+        self.desc = dcem.AllocatorDesc(self._alloc, self._free, None)
+
+    def release(self):
+        for p in self.held:
+            self.torch.cuda.caching_allocator_delete(p)
+        self.held, self.free_list, self.cap = [], [], {}
+
+
+def test_result_block_regrown_at_the_same_address():
+    """A coherent frame with more frequencies grows the result block; when the
+    allocator returns the old address, a revalidation enqueued ahead into the
+    old block must still be redone (its list count and frame start lived
+    there).  Unread and read previous frames, against full re-traces."""
+    s = scenes.dynamic_urban()
+    n = 1 << 16
+    alloc = ReusingAllocator()
+    coh, full = dcem.Context(0, allocator=alloc), dcem.Context(0)
+    coh.scene_upload(s)
+    full.scene_upload(s)
+    kw = dict(max_reflections=s.max_reflections, tx_power_w=s.tx_power_w, record_trace_log=True)
+    plan = [(0, [28e9], False), (1, [28e9], True), (2, [28e9, 60e9], False), (3, [28e9, 60e9, 73e9], True),
+            (4, [28e9, 60e9, 73e9, 80e9], True), (5, [28e9, 60e9, 73e9, 80e9, 90e9], True)]
+    for frame, freqs, read in plan:
+        log("frame", frame, "freqs", len(freqs), "read" if read else "unread")
+        coh.set_object_transforms(s.transforms(frame))
+        coh.refit_bvh()
+        coh.trace_frame(s.tx, s.rx, s.rx_radius, n, freqs_hz=freqs, mode=dcem.MODE_COHERENT, **kw)
+        if not read:
+            continue   # left unread: the next trace call finishes it first
+        full.set_object_transforms(s.transforms(frame))
+        full.refit_bvh(force_rebuild=True)
+        full.trace_frame(s.tx, s.rx, s.rx_radius, n, freqs_hz=freqs, mode=dcem.MODE_FULL, **kw)
+        assert_same(frame_outputs(full), frame_outputs(coh))
+        assert coh.stats()["coherent"] == 1
+    coh.close()
+    full.close()
+    alloc.release()
