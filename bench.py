@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batched workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--variants-only", choices=["all", "visited_series", "backward", "transmission"],
+                    help="time only the paper's variant workloads (one JSON object; for profiling them)")
     return ap.parse_args()
 
 
@@ -239,7 +241,7 @@ def large_bench(torch, frames=6):
     return out
 
 
-def variants_bench(torch, frames=4):
+def variants_bench(torch, frames=4, only=None):
     """The paper's variants of the frame algorithm (Sec. III), each at its
     workload, full frames timed after one untimed frame (wall clock over the
     frames, the host round trips of visited-series discovery included):
@@ -274,13 +276,13 @@ def variants_bench(torch, frames=4):
 
     urban = scenes.dynamic_urban()
     office = scenes.indoor_office()
-    out = {"visited_series": [timed(urban, "capture spheres"),
-                              timed(urban, "visited series", discovery=dcem.DISCOVER_VISITED)],
-           "backward": [timed(urban, "from the receivers, visited series", trace_from_rx=True,
-                              discovery=dcem.DISCOVER_VISITED, n_rays=4096)],
-           "transmission": [timed(office, "visited series", discovery=dcem.DISCOVER_VISITED),
-                            timed(office, "capture spheres")]}
-    return out
+    cases = {"visited_series": lambda: [timed(urban, "capture spheres"),
+                                        timed(urban, "visited series", discovery=dcem.DISCOVER_VISITED)],
+             "backward": lambda: [timed(urban, "from the receivers, visited series", trace_from_rx=True,
+                                        discovery=dcem.DISCOVER_VISITED, n_rays=4096)],
+             "transmission": lambda: [timed(office, "visited series", discovery=dcem.DISCOVER_VISITED),
+                                      timed(office, "capture spheres")]}
+    return {k: f() for k, f in cases.items() if only in (None, "all", k)}
 
 
 def cpu_info():
@@ -413,6 +415,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_2112_07115_amd import dcem, scenes
+    if args.variants_only:
+        print(json.dumps({"variants": variants_bench(torch, only=args.variants_only)}))
+        return
     scene = scenes.dynamic_urban(n_rays=args.rays)
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
