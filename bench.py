@@ -39,6 +39,8 @@ def parse():
                     help="first run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--variants-only", choices=["all", "visited_series", "backward", "transmission"],
                     help="time only the paper's variant workloads (one JSON object; for profiling them)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="time only the large dynamic workload (one JSON object; for profiling it)")
     return ap.parse_args()
 
 
@@ -417,6 +419,9 @@ def main():
     from paper_2112_07115_amd import dcem, scenes
     if args.variants_only:
         print(json.dumps({"variants": variants_bench(torch, only=args.variants_only)}))
+        return
+    if args.large_only:
+        print(json.dumps({"large_dynamic": large_bench(torch)}))
         return
     scene = scenes.dynamic_urban(n_rays=args.rays)
     if args.copy_probe:

@@ -340,10 +340,11 @@ void launch_small_dedupe(dcem_ctx* c, const KeyLayout& L, int64_t n_work) {
 __global__ __launch_bounds__(256) void k_heads(const uint32_t* __restrict__ keys, int64_t stride, int W,
                                                const uint32_t* __restrict__ perm, const uint32_t* __restrict__ n_dev,
                                                uint32_t n_max, uint8_t* __restrict__ head,
-                                               uint32_t* __restrict__ block_cnt) {
+                                               uint32_t* __restrict__ block_cnt, uint32_t* __restrict__ run_min) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = min(*n_dev, n_max);
   bool h = false;
+  if (run_min && i < n) run_min[i] = kNoRay;   // nullable: per-run lowest ray ids, filled by k_compact
   if (i < n) {
     h = i == 0;
     if (!h) {
@@ -382,15 +383,22 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint32_t* __restrict__ v, i
   if (threadIdx.x == 1023) *total = part[1023];
 }
 
+// Positions of the run heads (uniq_pos), and with run_min (nullable) the
+// lowest ray id of every run: each capture of the sorted list enters its
+// ray into its run's minimum (atomic, so a long run costs no serial walk).
 __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ head,
                                                  const uint32_t* __restrict__ block_off,
                                                  const uint32_t* __restrict__ n_dev, uint32_t n_max,
                                                  const uint32_t* __restrict__ n_unique,
-                                                 uint32_t* __restrict__ uniq_pos) {
+                                                 uint32_t* __restrict__ uniq_pos, uint32_t* __restrict__ run_min,
+                                                 const uint32_t* __restrict__ perm, const Capture* __restrict__ caps,
+                                                 KeyLayout L) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = min(*n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool h = i < n && head[i];
+  uint32_t ray = kNoRay;
+  if (run_min && i < n) ray = ray_of(caps[perm[i]].work, L);   // loaded while the heads are counted
   const uint64_t m = __ballot(h);
   __shared__ uint32_t wc[4];
   if (lane == 0) wc[wave] = (uint32_t)__popcll(m);
@@ -398,21 +406,22 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ hea
   uint32_t off = block_off[blockIdx.x];
   for (int w = 0; w < wave; ++w) off += wc[w];
   if (h) uniq_pos[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  // run index of position i: the heads at or before it, less one
+  if (run_min && i < n) atomicMin(&run_min[off + __popcll(m & ((2ull << lane) - 1ull)) - 1], ray);
   if (i == 0) uniq_pos[*n_unique] = n;
 }
 
 // Decoded candidate of every unique key of the sorted list: its key from the
-// first capture of its run, its lowest ray over the run.
+// first capture of its run, its lowest ray over the run (from k_compact).
 __global__ __launch_bounds__(256) void k_unique_info(const uint32_t* __restrict__ keys, int64_t stride, KeyLayout L,
                                                      const uint32_t* __restrict__ perm,
                                                      const uint32_t* __restrict__ uniq_pos,
                                                      const uint32_t* __restrict__ n_unique,
-                                                     const Capture* __restrict__ caps, UniqueOut out) {
+                                                     const uint32_t* __restrict__ run_min, UniqueOut out) {
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= *n_unique) return;
-  const uint32_t h = uniq_pos[u], e = uniq_pos[u + 1];
-  uint32_t fr = kNoRay;
-  for (uint32_t j = h; j < e; ++j) fr = min(fr, ray_of(caps[perm[j]].work, L));
+  const uint32_t h = uniq_pos[u];
+  const uint32_t fr = run_min[u];
   uint32_t w[8];
   const uint32_t idx = perm[h];
   for (int k = 0; k < L.W; ++k) w[k] = keys[k * stride + idx];
@@ -1656,13 +1665,16 @@ hipError_t build_candidates(dcem_ctx* c, bool small, int64_t hint) {
   hipLaunchKernelGGL(k_keys, dim3(nb), dim3(256), 0, c->stream, ptr<Capture>(c->caps[c->cur_caps]), n_dev, n_max,
                      ptr<int32_t>(c->face_log), n_work, L, keys, (int64_t)n);
   if ((e = radix_sort_perm(c, keys, L.W, L.bits, n_dev, n, perm, perm + n, c->stream)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_dev, n_max, head, bcnt);
+  // the sort's second permutation buffer is free after the sort: the runs'
+  // lowest ray ids
+  uint32_t* run_min = perm + n;
+  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L.W, perm, n_dev, n_max, head, bcnt,
+                     run_min);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nb, cnt + kCntUnique);
   hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, c->stream, head, bcnt, n_dev, n_max, cnt + kCntUnique,
-                     ptr<uint32_t>(c->uniq_idx));
+                     ptr<uint32_t>(c->uniq_idx), run_min, perm, ptr<Capture>(c->caps[c->cur_caps]), L);
   hipLaunchKernelGGL(k_unique_info, dim3(nb), dim3(256), 0, c->stream, keys, (int64_t)n, L, perm,
-                     ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique, ptr<Capture>(c->caps[c->cur_caps]),
-                     unique_out(c));
+                     ptr<uint32_t>(c->uniq_idx), cnt + kCntUnique, run_min, unique_out(c));
   if (device_count)
     hipLaunchKernelGGL(k_fit_check, dim3(1), dim3(64), 0, c->stream, n_dev, n_max, cnt + kCntUnique,
                        cnt + kCntFallback);
@@ -1726,10 +1738,10 @@ hipError_t build_visited_candidates(dcem_ctx* c, bool los, bool& too_many) {
     return e;
   const int nbi = (int)((n_items + 255) / 256);
   hipLaunchKernelGGL(k_heads, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S.W, perm, sc, n_items, head,
-                     bcnt);
+                     bcnt, nullptr);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, c->stream, bcnt, nbi, sc + 1);
   hipLaunchKernelGGL(k_compact, dim3(nbi), dim3(256), 0, c->stream, head, bcnt, sc, n_items, sc + 1,
-                     ptr<uint32_t>(c->uniq_idx));
+                     ptr<uint32_t>(c->uniq_idx), nullptr, nullptr, nullptr, S);
   hipLaunchKernelGGL(k_series_info, dim3(nbi), dim3(256), 0, c->stream, keys, (int64_t)cap, S, perm,
                      ptr<uint32_t>(c->uniq_idx), sc + 1, so);
   hipLaunchKernelGGL(k_series_starts, dim3((c->n_src + 1 + 255) / 256), dim3(256), 0, c->stream, so.src, sc + 1,
