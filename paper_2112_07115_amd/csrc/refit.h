@@ -223,10 +223,21 @@ __device__ __forceinline__ void climb_cross_global(const RefitArgs& a) {
   const uint32_t n_ent = a.info[3];
   __syncthreads();
   if (threadIdx.x == 0) a.info[3] = 0;   // ready for the next refit
-  for (uint32_t e = threadIdx.x; e < n_ent; e += blockDim.x) {
-    int p2 = (int)a.entries[e];
-    float lo[3], hi[3];
-    load_slot_wg(&a.nodes[p2 >> 1], p2 & 1, lo, hi);
+  // a thread's listed slots are loaded ahead: while one climbs, the next
+  // one's box (written by the block pass, never by this climb) and the one
+  // after's slot index are in flight
+  const uint32_t step = blockDim.x;
+  int p2_cur = 0, p2_next = 0;
+  float lo_cur[3] = {0.f, 0.f, 0.f}, hi_cur[3] = {0.f, 0.f, 0.f};
+  if (threadIdx.x < n_ent) p2_cur = (int)a.entries[threadIdx.x];
+  if (threadIdx.x + step < n_ent) p2_next = (int)a.entries[threadIdx.x + step];
+  if (threadIdx.x < n_ent) load_slot_wg(&a.nodes[p2_cur >> 1], p2_cur & 1, lo_cur, hi_cur);
+  for (uint32_t e = threadIdx.x; e < n_ent; e += step) {
+    int p2 = p2_cur;
+    float lo[3] = {lo_cur[0], lo_cur[1], lo_cur[2]}, hi[3] = {hi_cur[0], hi_cur[1], hi_cur[2]};
+    if (e + step < n_ent) load_slot_wg(&a.nodes[p2_next >> 1], p2_next & 1, lo_cur, hi_cur);
+    p2_cur = p2_next;
+    if (e + 2 * step < n_ent) p2_next = (int)a.entries[e + 2 * step];
     for (int guard = a.n_internal + 1; guard > 0; --guard) {
       const int node = p2 >> 1, slot = p2 & 1;
       const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
