@@ -68,12 +68,29 @@ __device__ inline uint32_t capture_key(const Capture& c, const int32_t* __restri
   const uint32_t tx = L.backward ? tgt : src, rx = L.backward ? src : tgt;
   const uint32_t tset =
       (order > 0 && L.n_branch > 1) ? L.branch_set[(c.work / (uint64_t)L.n_rays) % (uint32_t)L.n_branch] : 0u;
+  // the ray's faces in bounce order, loaded together (one round trip)
+  int32_t fl[kMaxK];
+#pragma unroll
+  for (int b = 0; b < kMaxK; ++b) {
+    fl[b] = 0;
+    if (b >= L.K) break;   // uniform
+    if ((uint32_t)b < order) fl[b] = face_log[(size_t)b * n_work + c.work];
+  }
   for (int k = 0; k < 8; ++k) w[k] = 0;
-  for (int j = 0; j < L.K; ++j) {
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    if (j >= L.K) break;   // uniform
     uint32_t f = 0;
     if ((uint32_t)j < order) {
-      const uint32_t bounce = L.backward ? order - 1u - (uint32_t)j : (uint32_t)j;
-      f = ((uint32_t)face_log[(size_t)bounce * n_work + c.work] << L.tb) | ((tset >> bounce) & (uint32_t)L.tb);
+      int bounce = j;
+      int32_t fb = fl[j];
+      if (L.backward) {   // uniform: faces in reverse order, picked without indexing the array
+        bounce = (int)order - 1 - j;
+#pragma unroll
+        for (int b = 0; b < kMaxK; ++b)
+          if (b == bounce) fb = fl[b];
+      }
+      f = ((uint32_t)fb << L.tb) | ((tset >> bounce) & (uint32_t)L.tb);
     }
     put_bits(w, L.W, (L.K - 1 - j) * L.bf, L.bf, f);
   }
