@@ -1271,6 +1271,41 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs e, int write) {
   e.out.first_ray[pos] = e.ser.first[s];
 }
 
+// The run of `key` in the sorted array a[0, n): [start, end) with a[i] == key,
+// by one wavefront (all lanes call it with the same arguments): 64-way splits
+// of both bounds at once, each round one load per lane and bound, so the run
+// is found in log64(n) memory round trips instead of 2 log2(n).
+__device__ inline void wave_run(const int32_t* __restrict__ a, int n, int key, int lane, int& start, int& end) {
+  int lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;   // first index with a[i] >= key, with a[i] > key
+  while (lo0 < hi0 || lo1 < hi1) {          // uniform over the wavefront
+    const int s0 = max((hi0 - lo0 + kWave - 1) / kWave, 1), s1 = max((hi1 - lo1 + kWave - 1) / kWave, 1);
+    const int q0 = lo0 + lane * s0, q1 = lo1 + lane * s1;
+    const bool b0 = q0 < hi0 && a[q0] < key;    // a prefix of the lanes (a is sorted)
+    const bool b1 = q1 < hi1 && a[q1] <= key;
+    const int c0 = __popcll(__ballot(b0)), c1 = __popcll(__ballot(b1));
+    if (lo0 < hi0) {
+      if (c0 == 0) {
+        hi0 = lo0;
+      } else {
+        const int nl = lo0 + (c0 - 1) * s0 + 1;
+        hi0 = min(hi0, lo0 + c0 * s0);
+        lo0 = nl;
+      }
+    }
+    if (lo1 < hi1) {
+      if (c1 == 0) {
+        hi1 = lo1;
+      } else {
+        const int nl = lo1 + (c1 - 1) * s1 + 1;
+        hi1 = min(hi1, lo1 + c1 * s1);
+        lo1 = nl;
+      }
+    }
+  }
+  start = lo0;
+  end = lo1;
+}
+
 // One wavefront per (tx, rx): sum the valid paths of that pair (contiguous in
 // key order) with a fixed lane assignment and butterfly, so the result is
 // bitwise reproducible.
@@ -1288,18 +1323,8 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ pair
   __syncthreads();
   if (wave < n_pairs) {
     const int n = (int)*n_unique;
-    int lo = 0, hi = n;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (pair[mid] < wave) lo = mid + 1; else hi = mid;
-    }
-    const int start = lo;
-    hi = n;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
-    }
-    const int end = lo;
+    int start, end;
+    wave_run(pair, n, wave, lane, start, end);
     uint32_t nv = 0;
     for (int u = start + lane; u < end; u += 64) nv += valid[u] ? 1u : 0u;
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
@@ -1357,18 +1382,8 @@ __global__ __launch_bounds__(256) void k_power_grad(const int32_t* __restrict__ 
   const int lane = threadIdx.x & 63;
   if (wave >= n_pairs) return;   // uniform per wavefront
   const int n = (int)n_unique;
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pair[mid] < wave) lo = mid + 1; else hi = mid;
-  }
-  const int start = lo;
-  hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pair[mid] <= wave) lo = mid + 1; else hi = mid;
-  }
-  const int end = lo;
+  int start, end;
+  wave_run(pair, n, wave, lane, start, end);
   auto butterfly = [](double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
