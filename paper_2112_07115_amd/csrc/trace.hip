@@ -168,6 +168,13 @@ struct ThreadStack {
   }
 };
 
+typedef __attribute__((address_space(3))) const Node4 LdsNode4;      // a node in LDS
+typedef __attribute__((address_space(1))) const Node4 GlobalNode4;   // a node in device memory
+// Node i of an array known to live in LDS / in device memory (address-space
+// casts need C-style casts).
+__device__ inline Node4 node_in_lds(const Node4* a, int i) { return *(const Node4*)((const LdsNode4*)a + i); }
+__device__ inline Node4 node_in_memory(const Node4* a, int i) { return *(const Node4*)((const GlobalNode4*)a + i); }
+
 // Closest hit: lexicographic minimum of (t, triangle id) over all triangles
 // with t > t_min outside face `excl`, by a stack traversal of the 4-wide tree
 // (nearest child first; the top levels are read from LDS).  The result does
@@ -183,7 +190,12 @@ __device__ Hit closest_hit(const Ray& r, const Node4* __restrict__ nodes, const 
   // guarantees termination
   for (int64_t guard = (int64_t)n4 + 2;; --guard) {
     if (guard == 0) { overflow = true; break; }
-    const Node4 nd = node < n_top ? top[node] : nodes[node];
+    // read through address-space-typed pointers, in two branches: a select
+    // of the two pointers would make every node read a generic load that
+    // waits on both the LDS and the memory counters
+    Node4 nd;
+    if (node < n_top) nd = node_in_lds(top, node);
+    else nd = node_in_memory(nodes, node);
     if (node >= n_top) ++n_nodes;   // fetched from memory (the top levels sit in LDS)
     float t[4];
     int c[4];
