@@ -182,7 +182,17 @@ __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t 
     int k = a.cross_index[p2 >> 1], slot = p2 & 1;
     float lo[3], hi[3];
     load_slot_coherent(&a.nodes[p2 >> 1], slot, lo, hi);
+    int kp = lpar[k];
     for (uint32_t guard = n_cross + 1; guard > 0; --guard) {
+      // the parent's links (written before the climb, never by it) are read
+      // while this level's box is stored and the arrival counted
+      int kpp = -1, pnode = 0;
+      int2 ds = make_int2(-1, -1);
+      if (kp >= 0) {
+        kpp = lpar[kp >> 1];
+        pnode = lnode[kp >> 1];
+        if (a.wide) ds = lslot4[kp >> 1];
+      }
       float* bx = lbox[k] + 6 * slot;
       for (int q = 0; q < 3; ++q) { bx[q] = lo[q]; bx[3 + q] = hi[q]; }
       const uint32_t old = lds_arrive(&lcnt[k]);
@@ -192,15 +202,14 @@ __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t 
         lo[q] = fminf(lo[q], sb[q]);
         hi[q] = fmaxf(hi[q], sb[3 + q]);
       }
-      const int kp = lpar[k];
       if (kp < 0) {
         for (int q = 0; q < 3; ++q) { a.root_box[q] = lo[q]; a.root_box[3 + q] = hi[q]; }
         break;
       }
       k = kp >> 1;
       slot = kp & 1;
-      const int2 ds = a.wide ? lslot4[k] : make_int2(-1, -1);
-      put_child_box(a, (lnode[k] << 1) | slot, slot ? ds.y : ds.x, lo, hi);
+      put_child_box(a, (pnode << 1) | slot, slot ? ds.y : ds.x, lo, hi);
+      kp = kpp;
     }
   }
 }
