@@ -372,10 +372,15 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
         if (kTwoPhase) __builtin_amdgcn_s_waitcnt(0x0f70);
         for (int guard = a.n; guard > 0; --guard) {   // depth < n in a sound tree
           const int node = p2 >> 1, slot = p2 & 1;
-          const bool local = node >= b0 && node < b0 + kRefitBlock && lnode[node - b0];
+          // the node's links in LDS (written before the climb, never by it),
+          // read together
+          const bool in_block = node >= b0 && node < b0 + kRefitBlock;
+          const int li = in_block ? node - b0 : 0;
+          const bool local = in_block && lnode[li];
+          const int2 ds = lslot4[li];
+          const int par = lpar[li];
           float slo[3], shi[3];
           if (local) {
-            const int2 ds = lslot4[node - b0];
             put_child_box(a, p2, a.wide ? (slot ? ds.y : ds.x) : -1, lo, hi);
             float* bx = lbox[node - b0] + 6 * slot;
             for (int k = 0; k < 3; ++k) { bx[k] = lo[k]; bx[3 + k] = hi[k]; }
@@ -398,8 +403,8 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
             lo[k] = fminf(lo[k], slo[k]);
             hi[k] = fmaxf(hi[k], shi[k]);
           }
-          if (kTwoPhase) p2 = lpar[node - b0];   // local here
-          else p2 = local ? lpar[node - b0] : a.nodes[node].c.z;
+          if (kTwoPhase) p2 = par;   // local here
+          else p2 = local ? par : a.nodes[node].c.z;
           if (p2 < 0) {
             for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
             break;
