@@ -161,19 +161,37 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
+// The links of cross node k (fixed between builds): its parent entry, its
+// binary node, that node's children and their 4-wide slots.
+struct CrossLinks {
+  int par, node;
+  int2 kid, s4;
+};
+
+__device__ inline CrossLinks cross_links(const RefitArgs& a, uint32_t k) {
+  CrossLinks x;
+  x.par = a.cross_parent[k];
+  x.node = a.cross_list[k];
+  x.kid = make_int2(a.nodes[x.node].c.x, a.nodes[x.node].c.y);
+  x.s4 = a.wide ? make_int2(a.slot4[2 * x.node], a.slot4[2 * x.node + 1]) : make_int2(-1, -1);
+  return x;
+}
+
 // Last-block pass of the refit: finish the cross nodes in LDS, from the slots
-// the block pass listed up to the root.
+// the block pass listed up to the root.  With `have`, pre holds this thread's
+// first cross node's links (loaded ahead).
 __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t n_cross, float (*lbox)[12], uint32_t* lcnt,
-                                   int32_t* lpar, int32_t* lnode, int2* lslot4, int2* lkid) {
+                                   int32_t* lpar, int32_t* lnode, int2* lslot4, int2* lkid, bool have,
+                                   const CrossLinks& pre) {
   const int tid = threadIdx.x;
   const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (uint32_t k = tid; k < n_cross; k += kRefitBlock) {
+    const CrossLinks x = have && k == (uint32_t)tid ? pre : cross_links(a, k);
     lcnt[k] = 0;
-    lpar[k] = a.cross_parent[k];
-    const int node = a.cross_list[k];
-    lnode[k] = node;
-    lkid[k] = make_int2(a.nodes[node].c.x, a.nodes[node].c.y);
-    if (a.wide) lslot4[k] = make_int2(a.slot4[2 * node], a.slot4[2 * node + 1]);
+    lpar[k] = x.par;
+    lnode[k] = x.node;
+    lkid[k] = x.kid;
+    if (a.wide) lslot4[k] = x.s4;
   }
   __syncthreads();
   if (tid == 0) a.info[3] = 0;   // ready for the next refit
@@ -334,6 +352,10 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
     fp[k] = has_face ? load_v(a.V, fv[k]) : make_float3(0.f, 0.f, 0.f);
   }
   if (has_leaf) lmoving = a.face_object[lface] >= 0 ? 1 : 0;
+  // the cross nodes' links, loaded by every block with its own gathers: the
+  // block that finishes last has them at once
+  const bool have_links = two_phase && !a.cross_kernel && (uint32_t)tid < n_cross;
+  const CrossLinks links = have_links ? cross_links(a, tid) : CrossLinks{0, 0, make_int2(-1, -1), make_int2(-1, -1)};
   lcnt[tid] = 0;
   lpar[tid] = ok ? nc.z : -1;
   lnode[tid] = local_node;   // block-local
@@ -437,7 +459,8 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
   if (!last) return;
   // ---- the last block to finish completes the cross nodes and the SAH sum
   if (tid == 0) a.info[4] = 0;   // ready for the next refit
-  if (two_phase && n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
+  if (two_phase && n_cross > 0)
+    finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid, have_links, links);
   __syncthreads();
   refit_tail(a, n_rb, two_phase, n_cross, lbox, lkid, red);
 }
@@ -455,7 +478,7 @@ __device__ __forceinline__ void refit_cross_block(const RefitArgs& a, int n_rb) 
   const uint32_t n_cross = a.info[2];
   const bool lds = n_cross <= (uint32_t)kMaxCross;
   if (lds) {
-    if (n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid);
+    if (n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid, false, CrossLinks{});
   } else {
     climb_cross_global(a);
   }
