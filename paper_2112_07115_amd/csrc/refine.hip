@@ -736,23 +736,29 @@ __device__ inline bool through_opaque(const RefineArgs& a, const int* faces, int
   return false;
 }
 
-// Refinement of one unique candidate u by one block of K + 1 wavefronts.
-//  1. Geometry (thread 0; first ray over the candidate's captures on wave 0):
+// Refinement of one unique candidate u by one block of four wavefronts (one
+// per SIMD, so four blocks share a compute unit; blocks of more wavefronts
+// place two on the same SIMD and only two of them fit).
+//  1. Geometry (wavefront 0: lane j loads face j's plane, lane 0 walks):
 //     decode the key, image sources through the face planes and reflection
 //     points walked back from the receiver, each strictly inside its segment
 //     (Sec. III step 3).
-//  2. Validation (wavefront j, j <= order): sub-segment j must be unoccluded
-//     (every triangle outside its end faces), and wavefront 0 also tests that
-//     each reflection point lies in its face, the face's triangles spread over
-//     the lanes (Sec. III step 4).
-//  3. Field (lane f of wavefront 0 for frequency f): length, delay,
+//  2. Tasks 0..order, validation: sub-segment j must be unoccluded (every
+//     triangle outside its end faces), and for j >= 1 reflection point j must
+//     lie in its face, the face's triangles spread over the lanes (Sec. III
+//     step 4).
+//  3. Task order + 1, the field (lane f for frequency f): length, delay,
 //     directions and the field: theta-hat of the departure direction carried
 //     through each reflection by the Fresnel coefficients, times
 //     sqrt(Pt) lambda / (4 pi d), the specific attenuation and the phase
 //     e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
-constexpr int kRefineMaxThreads = kWave * (kMaxK + 2);
+// Wavefront w starts with task w and takes the next free one from an LDS
+// counter after each; the wavefront that computed the field writes the
+// outputs once every task is done (a path found invalid is zeroed then).
+constexpr int kRefineWaves = 4;
 
-__global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
+__global__ __launch_bounds__(kRefineWaves * kWave) __attribute__((amdgpu_waves_per_eu(4)))
+void k_refine(RefineArgs a) {
   __shared__ double sP[(kMaxK + 2) * 3];      // transmitter, reflection points, receiver
   __shared__ D3 simg[kMaxK + 1];             // images of the transmitter
   __shared__ int sfaces[kMaxK];              // face ids (transmission flag cleared)
@@ -760,7 +766,9 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
   __shared__ int sorder, sok, sfail;
   __shared__ double sd;
   __shared__ double4 spl[kMaxK];              // planes of the faces
-  __shared__ uint32_t stk[kMaxK + 1][kCheckStack];
+  __shared__ uint32_t stk[kRefineWaves][kCheckStack];   // each wavefront's occlusion stack
+  __shared__ int snext;                                   // next free task
+  __shared__ int stask[kMaxK + 2];                        // the tasks in the order they are drawn
   const uint32_t u = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int K = a.K;
@@ -810,36 +818,43 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
       sorder = order0;
       sok = ok ? 1 : 0;
       sfail = 0;
+      // the task order: the sub-segments longest first (an occlusion query's
+      // cost grows with the length it crosses), the field second, so that
+      // wavefront 1 always computes it; tasks 0..3 go to wavefronts 0..3
+      int n_seg = 0;
+      double seg_len[kMaxK + 1];
+      for (int j = 0; j <= order0; ++j) {
+        const double dx = sP[3 * j + 3] - sP[3 * j], dy = sP[3 * j + 4] - sP[3 * j + 1],
+                     dz = sP[3 * j + 5] - sP[3 * j + 2];
+        const double l2 = dx * dx + dy * dy + dz * dz;
+        int i = n_seg++;
+        for (; i > 0 && seg_len[i - 1] < l2; --i) {
+          seg_len[i] = seg_len[i - 1];
+          stask[i + (i >= 1 ? 1 : 0)] = stask[i - 1 + (i - 1 >= 1 ? 1 : 0)];
+        }
+        seg_len[i] = l2;
+        stask[i + (i >= 1 ? 1 : 0)] = j;
+      }
+      stask[1] = order0 + 1;
+      snext = kRefineWaves;
     }
   }
   __syncthreads();
   const int order = sorder;
   bool ok = sok != 0;
-  // ---- 2. validation, one wavefront per sub-segment: wavefront w >= 1 also
-  // checks reflection point w against its face
-  if (ok && w <= order) {
-    const uint64_t all = ~0ull;
-    bool fail = false, fault = false;
-    if (w >= 1) {
-      const int f = sfaces[w - 1];
-      const double4 pl = spl[w - 1];
-      const D3 pt = {sP[3 * w], sP[3 * w + 1], sP[3 * w + 2]};
-      const bool inside = in_face(a, f, pt, D3{pl.x, pl.y, pl.z}, lane, kWave);
-      fail = __ballot(inside) == 0;
-    }
-    const int fa = w >= 1 ? sfaces[w - 1] : -1;
-    const int fb = w + 1 <= order ? sfaces[w] : -1;
-    const D3 p = {sP[3 * w], sP[3 * w + 1], sP[3 * w + 2]};
-    const D3 q = {sP[3 * (w + 1)], sP[3 * (w + 1) + 1], sP[3 * (w + 1) + 2]};
-    if (!fail && group_occluded(a, p, q, fa, fb, stk[w], lane, all, fault)) fail = true;
-    if (fail && lane == 0) sfail = 1;
-    if (fault && lane == 0) atomicOr(a.err, DCEM_ERR_STACK);
-  }
-  // ---- 3. field, one lane per frequency, by wavefront K + 1 while the
-  // others validate (a path found invalid is zeroed after the barrier)
-  const int fw = K + 1;
   auto pt = [&](int j) { return D3{sP[3 * j], sP[3 * j + 1], sP[3 * j + 2]}; };
-  if (w == fw && ok) {
+  // task positions are drawn in increasing order, each once: position 1 is
+  // the field (wavefront 1 first), the others are sub-segments
+  const int n_tasks = ok ? order + 2 : 0;
+  int t = w;   // uniform over the wavefront
+  auto draw = [&]() {
+    int next = 0;
+    if (lane == 0) next = atomicAdd(&snext, 1);
+    t = __shfl(next, 0);
+  };
+  if (t == 1 && n_tasks > 1) {
+    // ---- 3. the field, one lane per frequency (a path found invalid is
+    // zeroed once every task is done)
     const double d = sd;
     const D3 aod = normed(pt(1) - pt(0));
     const double rho = sqrt(aod.x * aod.x + aod.y * aod.y);
@@ -892,9 +907,31 @@ __global__ __launch_bounds__(kRefineMaxThreads) void k_refine(RefineArgs a) {
         out[2 * c + 1] = v.im;
       }
     }
+    draw();
+  }
+  while (t < n_tasks) {
+    // ---- 2. validation of sub-segment j: for j >= 1 also reflection point j
+    // against its face
+    const int j = stask[t];
+    const uint64_t all = ~0ull;
+    bool fail = false, fault = false;
+    if (j >= 1) {
+      const int f = sfaces[j - 1];
+      const double4 pl = spl[j - 1];
+      const bool inside = in_face(a, f, pt(j), D3{pl.x, pl.y, pl.z}, lane, kWave);
+      fail = __ballot(inside) == 0;
+    }
+    const int fa = j >= 1 ? sfaces[j - 1] : -1;
+    const int fb = j + 1 <= order ? sfaces[j] : -1;
+    if (!fail && group_occluded(a, pt(j), pt(j + 1), fa, fb, stk[w], lane, all, fault)) fail = true;
+    if (fail && lane == 0) sfail = 1;
+    if (fault && lane == 0) atomicOr(a.err, DCEM_ERR_STACK);
+    draw();
   }
   __syncthreads();
-  if (w != fw) return;
+  // the outputs, by the wavefront that wrote the field (wavefront 0 when
+  // there was none)
+  if (w != (ok ? 1 : 0)) return;
   ok = ok && sfail == 0;
   D3 aod = {0, 0, 0}, aoa = {0, 0, 0};
   if (ok) {
@@ -1880,7 +1917,7 @@ void launch_refine(dcem_ctx* c) {
   a.pts = ptr<double>(c->path_pts);
   a.counters = c->cnt_dev;
   a.err = c->err_dev;
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kWave * (c->K + 2)), 0, c->stream, a);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(kRefineWaves * kWave), 0, c->stream, a);
 }
 
 void launch_power_grad(dcem_ctx* c, uint32_t n_unique, double* g_eps, double* g_sig, double* g_pat) {
