@@ -796,7 +796,10 @@ void launch_refit(dcem_ctx* c, bool wide, double* sah_out) {
 }
 
 void launch_refit_cross(dcem_ctx* c, const RefitArgs& a, int n_rb) {
-  hipLaunchKernelGGL(k_refit_cross, dim3(1), dim3(kRefitBlock), 0, c->stream, a, n_rb);
+  // about a dozen listed slots per refit block: a thread per slot for up to
+  // 32 per block (more are taken in turn by the same threads)
+  const int blocks = std::min(std::max((n_rb * 32 + kRefitBlock - 1) / kRefitBlock, 1), 512);
+  hipLaunchKernelGGL(k_refit_cross, dim3(blocks), dim3(kRefitBlock), 0, c->stream, a, n_rb);
 }
 
 

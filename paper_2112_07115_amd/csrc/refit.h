@@ -53,7 +53,8 @@ RefitArgs make_refit_args(dcem_ctx* c, bool wide, double* sah_out);
 // Refit blocks of the current tree.
 int refit_blocks(const dcem_ctx* c);
 // The cross-node pass of a large tree's refit (a.cross_kernel), after the
-// launch that ran its block pass.
+// launch that ran its block pass: its listed slots climb on the threads of
+// several blocks, and the last block to finish sums the SAH areas.
 void launch_refit_cross(dcem_ctx* c, const RefitArgs& a, int n_rb);
 
 namespace {
@@ -232,51 +233,42 @@ __device__ __forceinline__ void finish_cross_nodes(const RefitArgs& a, uint32_t 
   }
 }
 
-__device__ inline void load_slot_wg(Node* nd, int slot, float* lo, float* hi) {
-  float* f = reinterpret_cast<float*>(nd);
-  const int base = slot * 6;
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = __hip_atomic_load(f + base + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    hi[a] = __hip_atomic_load(f + base + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-}
-
-// Cross nodes finished by one block in device memory: every slot the block
-// pass listed climbs through the cross nodes above it; the second arrival at
-// a node (workgroup-scope counter: one block does all of this) forms the union
-// and writes it into the parent's slot.  Arrival counters are reset for the
-// next refit.
+// Cross nodes finished in device memory by the blocks of the cross pass:
+// every slot the block pass listed climbs through the cross nodes above it
+// (the slots spread over the launch's threads); the second arrival at a node
+// (device-scope counter) forms the union and writes it into the parent's
+// slot.  Arrival counters are reset for the next refit.
 __device__ __forceinline__ void climb_cross_global(const RefitArgs& a) {
-  const uint32_t n_ent = a.info[3];
-  __syncthreads();
-  if (threadIdx.x == 0) a.info[3] = 0;   // ready for the next refit
+  const uint32_t n_ent = __hip_atomic_load(&a.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // a thread's listed slots are loaded ahead: while one climbs, the next
   // one's box (written by the block pass, never by this climb) and the one
   // after's slot index are in flight
-  const uint32_t step = blockDim.x;
+  const uint32_t step = gridDim.x * blockDim.x;
+  const uint32_t e0 = blockIdx.x * blockDim.x + threadIdx.x;
   int p2_cur = 0, p2_next = 0;
   float lo_cur[3] = {0.f, 0.f, 0.f}, hi_cur[3] = {0.f, 0.f, 0.f};
-  if (threadIdx.x < n_ent) p2_cur = (int)a.entries[threadIdx.x];
-  if (threadIdx.x + step < n_ent) p2_next = (int)a.entries[threadIdx.x + step];
-  if (threadIdx.x < n_ent) load_slot_wg(&a.nodes[p2_cur >> 1], p2_cur & 1, lo_cur, hi_cur);
-  for (uint32_t e = threadIdx.x; e < n_ent; e += step) {
+  if (e0 < n_ent) p2_cur = (int)a.entries[e0];
+  if (e0 + step < n_ent) p2_next = (int)a.entries[e0 + step];
+  if (e0 < n_ent) load_slot_coherent(&a.nodes[p2_cur >> 1], p2_cur & 1, lo_cur, hi_cur);
+  for (uint32_t e = e0; e < n_ent; e += step) {
     int p2 = p2_cur;
     float lo[3] = {lo_cur[0], lo_cur[1], lo_cur[2]}, hi[3] = {hi_cur[0], hi_cur[1], hi_cur[2]};
-    if (e + step < n_ent) load_slot_wg(&a.nodes[p2_next >> 1], p2_next & 1, lo_cur, hi_cur);
+    if (e + step < n_ent) load_slot_coherent(&a.nodes[p2_next >> 1], p2_next & 1, lo_cur, hi_cur);
     p2_cur = p2_next;
     if (e + 2 * step < n_ent) p2_next = (int)a.entries[e + 2 * step];
     for (int guard = a.n_internal + 1; guard > 0; --guard) {
       const int node = p2 >> 1, slot = p2 & 1;
-      const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // the parent link (fixed between builds) is read while the arrival is counted
+      const int pp = a.nodes[node].c.z;
+      const uint32_t old = __hip_atomic_fetch_add(&a.cnt[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
       if (old == 0) break;
       a.cnt[node] = 0;
       float slo[3], shi[3];
-      load_slot_wg(&a.nodes[node], slot ^ 1, slo, shi);
+      load_slot_coherent(&a.nodes[node], slot ^ 1, slo, shi);
       for (int k = 0; k < 3; ++k) {
         lo[k] = fminf(lo[k], slo[k]);
         hi[k] = fmaxf(hi[k], shi[k]);
       }
-      const int pp = a.nodes[node].c.z;
       if (pp < 0) {
         for (int k = 0; k < 3; ++k) { a.root_box[k] = lo[k]; a.root_box[3 + k] = hi[k]; }
         break;
@@ -466,7 +458,8 @@ __device__ __forceinline__ void refit_block(const RefitArgs& a, int rb, int n_rb
 }
 
 // The cross nodes and the SAH ratio of a large tree, after the refit's block
-// pass (one block of kRefitBlock threads).
+// pass: in LDS by block 0 when they fit, else climbed by every block in device
+// memory, the SAH sum then by the last block to finish.
 __device__ __forceinline__ void refit_cross_block(const RefitArgs& a, int n_rb) {
   __shared__ float lbox[kRefitBlock][12];
   __shared__ uint32_t lcnt[kRefitBlock];
@@ -475,12 +468,25 @@ __device__ __forceinline__ void refit_cross_block(const RefitArgs& a, int n_rb) 
   __shared__ int2 lslot4[kRefitBlock];
   __shared__ int2 lkid[kRefitBlock];
   __shared__ double red[kRefitBlock / kWave];
+  __shared__ bool last;
   const uint32_t n_cross = a.info[2];
   const bool lds = n_cross <= (uint32_t)kMaxCross;
   if (lds) {
+    if (blockIdx.x != 0) return;   // uniform
     if (n_cross > 0) finish_cross_nodes(a, n_cross, lbox, lcnt, lpar, lnode, lslot4, lkid, false, CrossLinks{});
   } else {
     climb_cross_global(a);
+    __threadfence();   // this thread's box stores before the block's ticket
+    __syncthreads();
+    if (threadIdx.x == 0)
+      last = __hip_atomic_fetch_add(&a.info[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;   // uniform
+    __threadfence();     // every block's climbs before the sums
+    if (threadIdx.x == 0) {
+      a.info[3] = 0;   // ready for the next refit
+      a.info[4] = 0;
+    }
   }
   __syncthreads();
   refit_tail(a, n_rb, lds, n_cross, lbox, lkid, red);
