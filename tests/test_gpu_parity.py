@@ -73,6 +73,18 @@ def test_many_pairs_small_capture_list(ctx, O):
     assert out.p_coh.shape == (1, 2, rx.shape[0])
 
 
+def test_every_order_up_to_ten_between_parallel_walls(ctx, O):
+    """A street canyon without ground at K = 10: the receiver gets the direct
+    path and two paths of every order 1..10, so the refinement's blocks of four
+    wavefronts run up to twelve tasks (eleven sub-segments and the field)."""
+    s = scenes.parallel_walls([[0, 0, 1.5]], [[3.0, 40.0, 1.5]], n_rays=1 << 16, max_reflections=10,
+                              rx_radius=2.0)
+    st, out, ofr = run_pair(ctx, O, s)
+    p = ctx.paths()
+    orders = p["keys"][p["valid"], 2]
+    assert np.array_equal(np.bincount(orders, minlength=11), [1] + [2] * 10)
+
+
 def test_ragged_ray_counts_and_orders(ctx, O):
     s = scenes.static_toy()
     for n, K in [(1, 2), (63, 0), (65, 3), (1000, 10)]:
