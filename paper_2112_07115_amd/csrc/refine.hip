@@ -743,18 +743,19 @@ __device__ inline bool through_opaque(const RefineArgs& a, const int* faces, int
 //     decode the key, image sources through the face planes and reflection
 //     points walked back from the receiver, each strictly inside its segment
 //     (Sec. III step 3).
-//  2. Tasks 0..order, validation: sub-segment j must be unoccluded (every
-//     triangle outside its end faces), and for j >= 1 reflection point j must
-//     lie in its face, the face's triangles spread over the lanes (Sec. III
-//     step 4).
-//  3. Task order + 1, the field (lane f for frequency f): length, delay,
-//     directions and the field: theta-hat of the departure direction carried
-//     through each reflection by the Fresnel coefficients, times
-//     sqrt(Pt) lambda / (4 pi d), the specific attenuation and the phase
-//     e^{-j k0 d} (Eq. (3) with n = 2, Sec. III step 6).
-// Wavefront w starts with task w and takes the next free one from an LDS
-// counter after each; the wavefront that computed the field writes the
-// outputs once every task is done (a path found invalid is zeroed then).
+//  2. One validation task per sub-segment j = 0..order: the sub-segment must
+//     be unoccluded (every triangle outside its end faces), and for j >= 1
+//     reflection point j must lie in its face, the face's triangles spread
+//     over the lanes (Sec. III step 4).
+//  3. The field task (lane f for frequency f): length, delay, directions and
+//     the field: theta-hat of the departure direction carried through each
+//     reflection by the Fresnel coefficients, times sqrt(Pt) lambda /
+//     (4 pi d), the specific attenuation and the phase e^{-j k0 d} (Eq. (3)
+//     with n = 2, Sec. III step 6).
+// The tasks are drawn in a fixed order from an LDS counter (wavefront w
+// starts with position w): the sub-segments longest first, the field at
+// position 1, so wavefront 1 computes it and then writes the outputs once
+// every task is done (a path found invalid is zeroed then).
 constexpr int kRefineWaves = 4;
 
 __global__ __launch_bounds__(kRefineWaves * kWave) __attribute__((amdgpu_waves_per_eu(4)))
